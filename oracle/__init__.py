@@ -1,0 +1,31 @@
+"""FP64 CPU oracle for multi-scale low-rank decomposition.
+
+TEST INFRASTRUCTURE ONLY. Only the tests, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import or call anything in this package.
+The product path (the HIP library and its Python binding) never touches it, and
+this package never touches the product path: the two share no code, only the
+seeded inputs of the ``synth`` module.
+
+Everything here is plain numpy in float64, written step by step from the paper
+(Ong & Lustig, "Beyond Low Rank + Sparse: Multi-scale Low Rank Matrix
+Decomposition"). A dense SVD from LAPACK (numpy.linalg.svd) serves as the
+library step inside singular value thresholding.
+
+Parity status per function (what independent facts pin it; see tests/):
+  cycle_shift         pinned: SplitMix64 published output for seed 0, and the
+                      block-wise identities of the shifted operator.
+  default_lambda      pinned: the special cases of the boxed lambda formula.
+  svt                 pinned: prox optimality conditions (subdifferential of the
+                      nuclear norm), brute-force 2x2 minimisation, rank-1 and
+                      1xN / Nx1 closed forms.
+  block_svt,          pinned: 1x1 soft-threshold and 1xN group closed forms,
+  cycle_spun_bsvt     rank-1 planted blocks under wrapped shifts.
+  admm                pinned: KKT conditions and a vanishing duality gap at
+                      convergence, scaling / transpose invariances, trivial
+                      ladders, ground-truth recovery on sparse instances.
+"""
+from .msld_oracle import (  # noqa: F401
+    MASK64, splitmix64_mix, cycle_shift, default_lambda, shift, unshift, svt,
+    block_svt, cycle_spun_bsvt, admm, block_nuclear_norm, block_dual_norm,
+    kkt_report, skip_bound_sq,
+)

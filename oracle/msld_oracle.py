@@ -1,0 +1,196 @@
+"""Plain FP64 reference for the ADMM / block-wise SVT iteration (test infrastructure).
+
+Only tests/, __graft_entry__.smoke() and bench.py's cpu_baseline leg may use this
+module. Each function cites the passage of the paper it follows. Notation follows
+the paper: Y is M x N, scale i has m_i x n_i blocks, lambda_i its weight, rho the
+ADMM parameter, X_i / Z_i / U_i the ADMM variables.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+MASK64 = (1 << 64) - 1
+_GAMMA = 0x9E3779B97F4A7C15          # SplitMix64 increment (Steele, Lea & Flood 2014)
+
+
+# --------------------------------------------------------------------------- shifts
+def splitmix64_mix(z: int) -> int:
+    """SplitMix64 output function (Steele, Lea & Flood, OOPSLA 2014; the
+    'variant 13' 64-bit finaliser). Pure 64-bit integer arithmetic."""
+    z &= MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+    return z ^ (z >> 31)
+
+
+def cycle_shift(seed: int, k: int, i: int, m: int, n: int):
+    """Random cycle-spin shift s = (s_r, s_c) of scale i at iteration k
+    (Sec. 9, random cycle spinning: one random shift per Z-update).
+
+    The paper does not say how shifts are drawn. Reading used here: shifts are
+    residues modulo the block size (a shift by a whole block gives the same
+    partition); one independent draw per (k, i), both 0-based, i < 16, from the
+    counter-based SplitMix64 value z = mix(seed + gamma * (16 k + i + 1)) mod 2^64;
+    s_r = (z >> 32) mod m, s_c = (z & 0xffffffff) mod n.
+    """
+    x = (int(seed) + _GAMMA * (16 * int(k) + int(i) + 1)) & MASK64
+    z = splitmix64_mix(x)
+    return (z >> 32) % int(m), (z & 0xFFFFFFFF) % int(n)
+
+
+def shift(A: np.ndarray, s):
+    """Shift_s of Sec. 9 with cyclic wrap: Shift_s(A)[r, c] = A[(r+s_r) mod M, (c+s_c) mod N]."""
+    return np.roll(A, (-int(s[0]), -int(s[1])), axis=(0, 1))
+
+
+def unshift(A: np.ndarray, s):
+    """Shift_{-s}, the inverse of `shift`."""
+    return np.roll(A, (int(s[0]), int(s[1])), axis=(0, 1))
+
+
+# ------------------------------------------------------------------- regularisation
+def default_lambda(M: int, N: int, m: int, n: int) -> float:
+    """Boxed regularisation rule of Sec. 4 (eq:lambda), with constant 1 as in the
+    experiments of Sec. 10 and the natural logarithm:
+    lambda_i = sqrt(m_i) + sqrt(n_i) + sqrt(log(MN / max(m_i, n_i)))."""
+    return math.sqrt(m) + math.sqrt(n) + math.sqrt(math.log(M * N / max(m, n)))
+
+
+# --------------------------------------------------------------------------- SVT
+def svt(B: np.ndarray, tau: float) -> np.ndarray:
+    """Singular value soft-threshold of Sec. 7 (eq:svt): U max(Sigma - tau, 0) V^T.
+    Works on a single matrix (m, n) or a stack (..., m, n)."""
+    U, S, Vt = np.linalg.svd(B, full_matrices=False)
+    S = np.maximum(S - tau, 0.0)
+    return np.matmul(U * S[..., None, :], Vt)
+
+
+def _blocks(A: np.ndarray, m: int, n: int) -> np.ndarray:
+    """All R_b(A) of the contiguous m x n partition (Sec. 2, block reshape operator),
+    stacked as (M/m, N/n, m, n); block (p, q) is A[p m:(p+1) m, q n:(q+1) n]."""
+    M, N = A.shape
+    return A.reshape(M // m, m, N // n, n).transpose(0, 2, 1, 3)
+
+
+def _unblocks(Bk: np.ndarray) -> np.ndarray:
+    """sum_b R_b^T(B_b): embed every block back at its place (adjoint of R_b)."""
+    P, Q, m, n = Bk.shape
+    return Bk.transpose(0, 2, 1, 3).reshape(P * m, Q * n)
+
+
+def block_svt(A: np.ndarray, m: int, n: int, tau: float) -> np.ndarray:
+    """Block-wise SVT of Sec. 7 (eq:bsvt): sum_b R_b^T(SVT_tau(R_b(A))) over the
+    contiguous m x n partition. Blocks are disjoint, so the sum is a placement."""
+    M, N = A.shape
+    if M % m or N % n:
+        raise ValueError("block size must tile the matrix")
+    Bk = _blocks(np.asarray(A, dtype=np.float64), m, n)
+    P, Q = Bk.shape[:2]
+    Zk = svt(Bk.reshape(P * Q, m, n), tau).reshape(P, Q, m, n)
+    return _unblocks(Zk)
+
+
+def cycle_spun_bsvt(A: np.ndarray, m: int, n: int, tau: float, s) -> np.ndarray:
+    """Random cycle spinning of Sec. 9: Shift_{-s}(BSVT_tau(Shift_s(A)))."""
+    return unshift(block_svt(shift(A, s), m, n, tau), s)
+
+
+# --------------------------------------------------------------------------- ADMM
+def admm(Y, ladder, lam=None, rho=1.0, iters=100, cycle_spin=False, seed=0,
+         tol=0.0, check_every=1, history=False):
+    """ADMM of Sec. 7 (eq:admm) for eq:cvx, with the random cycle spinning of Sec. 9.
+
+    Per iteration k, in the paper's order:
+        X_i <- (Z_i - U_i) + (Y - sum_j (Z_j - U_j)) / L
+        Z_i <- Shift_{-s}(BSVT_{lambda_i/rho}(Shift_s(X_i + U_i)))   (s = 0 without spinning)
+        U_i <- U_i - (Z_i - X_i)
+    Readings where the paper is silent: Z_i = U_i = 0 at start; the returned
+    components are Z_i (exactly block-low-rank); primal residual
+    r_k = sqrt(sum_i ||X_i - Z_i||_F^2) / ||Y||_F with the new Z_i; when tol > 0 the
+    loop stops after iteration k if (k+1) % check_every == 0 and r_k <= tol.
+    """
+    Y = np.asarray(Y, dtype=np.float64)
+    M, N = Y.shape
+    ladder = [(int(m), int(n)) for (m, n) in ladder]
+    L = len(ladder)
+    if lam is None:
+        lam = [default_lambda(M, N, m, n) for (m, n) in ladder]
+    lam = [float(x) for x in lam]
+    Z = np.zeros((L, M, N))
+    U = np.zeros((L, M, N))
+    X = np.zeros((L, M, N))
+    ny = np.linalg.norm(Y)
+    ny = ny if ny > 0 else 1.0
+    hist = []
+    r = float("nan")
+    k_done = 0
+    for k in range(int(iters)):
+        S = (Z - U).sum(axis=0)
+        for i in range(L):
+            X[i] = (Z[i] - U[i]) + (Y - S) / L
+        for i, (m, n) in enumerate(ladder):
+            s = cycle_shift(seed, k, i, m, n) if cycle_spin else (0, 0)
+            Z[i] = cycle_spun_bsvt(X[i] + U[i], m, n, lam[i] / rho, s)
+        U = U - (Z - X)
+        r = float(np.sqrt(((X - Z) ** 2).sum()) / ny)
+        k_done = k + 1
+        if history:
+            hist.append(r)
+        if tol > 0 and k_done % int(check_every) == 0 and r <= tol:
+            break
+    return {"Z": Z, "X": X, "U": U, "iters": k_done, "resid": r,
+            "history": hist, "lam": lam}
+
+
+# --------------------------------------------------------------------- diagnostics
+def block_nuclear_norm(A, m, n) -> float:
+    """||A||_(i) of Sec. 3: sum over blocks of the nuclear norm of R_b(A)."""
+    Bk = _blocks(np.asarray(A, dtype=np.float64), m, n)
+    P, Q = Bk.shape[:2]
+    return float(np.linalg.svd(Bk.reshape(P * Q, m, n), compute_uv=False).sum())
+
+
+def block_dual_norm(A, m, n) -> float:
+    """||A||*_(i) of Sec. 3: max over blocks of the largest singular value of R_b(A)."""
+    Bk = _blocks(np.asarray(A, dtype=np.float64), m, n)
+    P, Q = Bk.shape[:2]
+    return float(np.linalg.svd(Bk.reshape(P * Q, m, n), compute_uv=False).max())
+
+
+def kkt_report(Y, ladder, lam, rho, Z, U):
+    """Optimality diagnostics for eq:cvx from an ADMM state (no cycle spinning).
+
+    Dual certificate: at a fixed point all U_i coincide and Q = rho * mean_i U_i
+    satisfies Q in lambda_i * subdifferential of ||Z_i||_(i) (the condition of
+    Thm A.3 with the dual norm of Sec. 3). For any Q with ||Q||*_(i) <= lambda_i,
+    <Q, Y> lower-bounds the optimum (weak duality), so Q is scaled into that set.
+    The primal value is taken at the feasible point Z_i + (Y - sum_j Z_j)/L.
+    """
+    Y = np.asarray(Y, dtype=np.float64)
+    L = len(ladder)
+    Ubar = np.mean(U, axis=0)
+    Q = rho * Ubar
+    ratios = [block_dual_norm(Q, m, n) / lam[i] for i, (m, n) in enumerate(ladder)]
+    Qs = Q / max(1.0, max(ratios))
+    dual = float((Qs * Y).sum())
+    Zf = Z + (Y - Z.sum(axis=0)) / L
+    primal = float(sum(lam[i] * block_nuclear_norm(Zf[i], m, n)
+                       for i, (m, n) in enumerate(ladder)))
+    spread = float(max(np.linalg.norm(U[i] - Ubar) for i in range(L)) /
+                   max(np.linalg.norm(Ubar), 1e-300))
+    return {"primal": primal, "dual": dual,
+            "gap": (primal - dual) / max(abs(primal), 1e-300),
+            "dual_ratio": ratios, "u_spread": spread,
+            "consensus": float(np.linalg.norm(Y - Z.sum(axis=0)) /
+                               max(np.linalg.norm(Y), 1e-300))}
+
+
+def skip_bound_sq(B) -> float:
+    """Square of the upper bound on the largest singular value used to skip SVDs
+    (Sec. 8). The printed formula has an unbound index; reading used here:
+    sigma_max(B)^2 <= max_r sum_k |B_rk| (sum_j |B_jk|), the maximum row sum of
+    |B||B|^T, which bounds the spectral radius of B B^T."""
+    A = np.abs(np.asarray(B, dtype=np.float64))
+    return float((A @ A.sum(axis=0)).max())

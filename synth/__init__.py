@@ -1,0 +1,160 @@
+"""Seeded synthetic inputs for multi-scale low-rank decomposition.
+
+This module is shared by the tests, the benchmark and the oracle harness. It holds
+only random draws and the signal model (Sec. 2: Y is a sum of block-wise low-rank
+components plus optional Gaussian noise); it contains none of the solver's
+arithmetic (no thresholding, no ADMM, no regularisation defaults).
+
+Recipe (one definition used everywhere):
+  * rng = numpy.random.default_rng(seed) (PCG64).
+  * For each scale i in ladder order, with block size m_i x n_i and
+    P_i = (M/m_i)(N/n_i) contiguous blocks in row-major block order:
+      k_i = max(1, round(density * P_i)) distinct block ids drawn by
+      rng.choice(P_i, k_i, replace=False), then sorted;
+      per rank r: u ~ N(0,1)^{k_i x m_i x r}, v ~ N(0,1)^{k_i x n_i x r} (drawn in
+      that order); block = u @ v^T.
+  * noise: sigma * N(0,1)^{M x N}, drawn last, added after the components.
+  * Y = float32(sum of components + noise); components are returned in fp64.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = ["Instance", "make_instance", "full_ladder", "geometric_ladder",
+           "batch_instances", "serving_trace"]
+
+
+@dataclass
+class Instance:
+    Y: np.ndarray                     # (M, N) float32
+    ladder: list                      # [(m_i, n_i)]
+    components: np.ndarray | None     # (L, M, N) float64 ground truth, or None
+    active: list = field(default_factory=list)   # per scale: sorted active block ids
+    seed: int = 0
+    density: float = 0.0
+    rank: int = 1
+    noise: float = 0.0
+
+    @property
+    def shape(self):
+        return self.Y.shape
+
+
+def _check_ladder(M, N, ladder):
+    for (m, n) in ladder:
+        if m <= 0 or n <= 0 or M % m or N % n:
+            raise ValueError(f"block {m}x{n} does not tile {M}x{N}")
+
+
+def make_instance(M, N, ladder, density, rank=1, noise=0.0, seed=0,
+                  keep_components=True, ranks=None) -> Instance:
+    """Draw Y = sum_i X_i + noise following the module recipe.
+
+    `ranks` (optional, per scale) overrides `rank` scale by scale.
+    `keep_components=False` skips storing the (L, M, N) fp64 ground truth, which
+    matters for 8192 x 8192 inputs.
+    """
+    ladder = [(int(m), int(n)) for (m, n) in ladder]
+    _check_ladder(M, N, ladder)
+    rng = np.random.default_rng(seed)
+    L = len(ladder)
+    acc = np.zeros((M, N), dtype=np.float64)
+    comps = np.zeros((L, M, N), dtype=np.float64) if keep_components else None
+    active = []
+    for i, (m, n) in enumerate(ladder):
+        r = int(ranks[i]) if ranks is not None else int(rank)
+        P, Q = M // m, N // n
+        nb = P * Q
+        k = max(1, int(round(density * nb)))
+        ids = np.sort(rng.choice(nb, size=k, replace=False))
+        u = rng.standard_normal((k, m, r))
+        v = rng.standard_normal((k, n, r))
+        blocks = np.matmul(u, np.transpose(v, (0, 2, 1)))      # (k, m, n)
+        tgt = acc if comps is None else comps[i]
+        view = tgt.reshape(P, m, Q, n)                          # view, no copy
+        p, q = ids // Q, ids % Q
+        view[p, :, q, :] += blocks
+        if comps is not None:
+            acc += comps[i]
+        active.append(ids)
+    if noise > 0:
+        acc += noise * rng.standard_normal((M, N))
+    Y = acc.astype(np.float32)
+    return Instance(Y=Y, ladder=ladder, components=comps, active=active,
+                    seed=seed, density=density, rank=rank, noise=noise)
+
+
+def full_ladder(M, N, small):
+    """Ladder of square blocks `small` followed by the full M x N block."""
+    return [(b, b) for b in small] + [(M, N)]
+
+
+def geometric_ladder(M, N, L):
+    """Ratio-4 ladder 1, 4, 16, ... of L-1 square scales, then the full block."""
+    out = []
+    b = 1
+    for _ in range(L - 1):
+        out.append((b, b))
+        b *= 4
+    out.append((M, N))
+    _check_ladder(M, N, out)
+    return out
+
+
+def batch_instances(count, seed=0, density=0.02, noise=0.01):
+    """Independent instances of mixed sizes and ladders (one batched launch).
+
+    Shapes are drawn uniformly from {64^2, 128^2, 256^2, 128x512}; ladders from
+    {1,4,16,full} and {1,8,32,full}; rank-1 block ground truth.
+    Instance j uses data seed (seed * 1_000_003 + j).
+    """
+    shapes = [(64, 64), (128, 128), (256, 256), (128, 512)]
+    smalls = [(1, 4, 16), (1, 8, 32)]
+    rng = np.random.default_rng(seed)
+    si = rng.integers(0, len(shapes), size=count)
+    li = rng.integers(0, len(smalls), size=count)
+    out = []
+    for j in range(count):
+        M, N = shapes[si[j]]
+        lad = full_ladder(M, N, smalls[li[j]])
+        out.append(make_instance(M, N, lad, density, rank=1, noise=noise,
+                                 seed=seed * 1_000_003 + j, keep_components=False))
+    return out
+
+
+def serving_trace(count, rate, seed=0, density=0.02, noise=0.01):
+    """Poisson arrival trace of decomposition requests.
+
+    Returns a list of (arrival_time_s, M, N, ladder, rank, data_seed). Shapes are
+    uniform over {128^2, 512^2, 1024x256, 2048^2}; L uniform over {4, 5, 6} with a
+    ratio-4 ladder ending in the full block (truncated where a block would not
+    tile the matrix); rank 1 or 2 with equal probability.
+    """
+    shapes = [(128, 128), (512, 512), (1024, 256), (2048, 2048)]
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for j in range(count):
+        t += rng.exponential(1.0 / rate)
+        M, N = shapes[rng.integers(0, len(shapes))]
+        L = int(rng.integers(4, 7))
+        lad = []
+        b = 1
+        while len(lad) < L - 1 and b <= min(M, N) // 4 and M % b == 0 and N % b == 0:
+            lad.append((b, b))
+            b *= 4
+        lad.append((M, N))
+        rank = int(rng.integers(1, 3))
+        out.append((t, M, N, lad, rank, seed * 1_000_003 + j))
+    return out
+
+
+def lcm_blocks(ladder):
+    a, b = 1, 1
+    for (m, n) in ladder:
+        a = a * m // math.gcd(a, m)
+        b = b * n // math.gcd(b, n)
+    return a, b

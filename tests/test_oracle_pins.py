@@ -1,0 +1,283 @@
+"""Pins for the FP64 oracle: facts fixed by the paper and by mathematics, independent
+of the oracle's own formulas (closed forms, optimality conditions, brute force,
+published generator outputs, exact invariances of the iteration)."""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.optimize import minimize
+
+import oracle as O
+from synth import make_instance
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden_hex(name):
+    out = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                out.append(int(line, 16))
+    return out
+
+
+# ----------------------------------------------------------------- shift hash (Sec. 9)
+def test_splitmix64_published_outputs():
+    ref = _golden_hex("splitmix64_seed0.txt")
+    state = 0
+    for want in ref:
+        state = (state + 0x9E3779B97F4A7C15) & O.MASK64
+        assert O.splitmix64_mix(state) == want
+
+
+def test_cycle_shift_counter_layout():
+    # seed 0: counter 16k+i+1 = 1..4 for (k=0, i=0..3) gives the published stream.
+    ref = _golden_hex("splitmix64_seed0.txt")
+    for i, z in enumerate(ref):
+        for (m, n) in [(4, 4), (8, 32), (512, 512), (7, 3), (1, 1)]:
+            assert O.cycle_shift(0, 0, i, m, n) == ((z >> 32) % m, (z & 0xFFFFFFFF) % n)
+    # (k=1, i=0) uses counter 17: 17 steps of the same stream
+    state = 0
+    for _ in range(17):
+        state = (state + 0x9E3779B97F4A7C15) & O.MASK64
+    z = O.splitmix64_mix(state)
+    assert O.cycle_shift(0, 1, 0, 64, 64) == ((z >> 32) % 64, (z & 0xFFFFFFFF) % 64)
+
+
+def test_shift_definition_bruteforce():
+    rng = np.random.default_rng(0)
+    A = rng.standard_normal((5, 7))
+    s = (3, 4)
+    S = O.shift(A, s)
+    for r in range(5):
+        for c in range(7):
+            assert S[r, c] == A[(r + 3) % 5, (c + 4) % 7]
+    assert np.array_equal(O.unshift(S, s), A)
+
+
+# ------------------------------------------------------------------ lambda (Sec. 4)
+def test_lambda_special_cases():
+    # full M x N block: sqrt(M) + sqrt(N) + sqrt(log(min(M, N)))
+    assert math.isclose(O.default_lambda(64, 128, 64, 128),
+                        8 + math.sqrt(128) + math.sqrt(math.log(64)), rel_tol=1e-15)
+    # 1 x 1 blocks: 2 + sqrt(log(M N))
+    assert math.isclose(O.default_lambda(512, 512, 1, 1), 2 + math.sqrt(math.log(512 * 512)),
+                        rel_tol=1e-15)
+    # noise-like MN x 1 reshape would give sqrt(MN) + 1 + 0
+    assert math.isclose(O.default_lambda(1, 4096, 1, 4096), 1 + 64 + math.sqrt(math.log(1)),
+                        rel_tol=1e-15)
+
+
+# ------------------------------------------------------------------ SVT (eq:svt)
+def _spec_norm(A):
+    return math.sqrt(max(np.linalg.eigvalsh(A.T @ A).max(), 0.0))
+
+
+def _nuc_norm(A):
+    # eigenvalues of A^T A that are rounding noise around an exact zero are dropped
+    ev = np.linalg.eigvalsh(A.T @ A)
+    ev[ev < 1e-12 * max(ev.max(), 1e-300)] = 0.0
+    return float(np.sqrt(ev).sum())
+
+
+@pytest.mark.parametrize("shape", [(6, 6), (9, 4), (3, 11), (16, 16), (1, 7), (5, 1)])
+@pytest.mark.parametrize("q", [0.1, 0.5, 0.9])
+def test_svt_prox_optimality(shape, q):
+    """Z = prox_{tau ||.||_*}(B) iff G = B - Z satisfies ||G||_2 <= tau and
+    <G, Z> = tau ||Z||_* (subdifferential of the nuclear norm, Sec. 5.1)."""
+    rng = np.random.default_rng(hash((shape, q)) % 2**32)
+    B = rng.standard_normal(shape) * 3
+    sv = np.sqrt(np.clip(np.linalg.eigvalsh(B.T @ B), 0, None))
+    tau = float(np.quantile(sv, q)) + 1e-3
+    Z = O.svt(B, tau)
+    G = B - Z
+    assert _spec_norm(G) <= tau * (1 + 1e-10)
+    assert abs(float((G * Z).sum()) - tau * _nuc_norm(Z)) <= 1e-9 * max(1.0, tau * _nuc_norm(Z))
+
+
+def test_svt_bruteforce_2x2():
+    """Direct minimisation of 0.5||Z - V||^2 + tau ||Z||_* over 2x2 matrices, with the
+    SVD-free identity ||Z||_* = sqrt(||Z||_F^2 + 2 |det Z|)."""
+    rng = np.random.default_rng(7)
+    for trial in range(12):
+        V = rng.standard_normal((2, 2)) * 2
+        tau = float(rng.uniform(0.1, 2.5))
+
+        def f(z):
+            Z = z.reshape(2, 2)
+            nuc = math.sqrt(max((Z * Z).sum() + 2 * abs(np.linalg.det(Z)), 0.0))
+            return 0.5 * ((Z - V) ** 2).sum() + tau * nuc
+
+        best = None
+        for x0 in [np.zeros(4), V.ravel(), 0.5 * V.ravel(), rng.standard_normal(4)]:
+            res = minimize(f, x0, method="Nelder-Mead",
+                           options={"xatol": 1e-12, "fatol": 1e-14, "maxiter": 40000,
+                                    "maxfev": 40000})
+            if best is None or res.fun < best.fun:
+                best = res
+        Z = O.svt(V, tau)
+        assert f(Z.ravel()) <= best.fun + 1e-12
+        assert np.abs(Z.ravel() - best.x).max() < 1e-5
+
+
+def test_svt_rank1_closed_form():
+    rng = np.random.default_rng(3)
+    u, v = rng.standard_normal(7), rng.standard_normal(5)
+    B = np.outer(u, v)
+    sig = np.linalg.norm(u) * np.linalg.norm(v)
+    for tau in [0.1 * sig, 0.7 * sig, 1.3 * sig]:
+        want = max(1 - tau / sig, 0.0) * B
+        assert np.allclose(O.svt(B, tau), want, atol=1e-12 * sig)
+
+
+# ------------------------------------------------------------ BlockSVT (eq:bsvt)
+def test_bsvt_1x1_is_soft_threshold():
+    rng = np.random.default_rng(1)
+    A = rng.standard_normal((12, 10)) * 2
+    tau = 0.8
+    want = np.sign(A) * np.maximum(np.abs(A) - tau, 0)
+    assert np.allclose(O.block_svt(A, 1, 1, tau), want, atol=1e-14)
+    assert np.allclose(O.cycle_spun_bsvt(A, 1, 1, tau, (0, 0)), want, atol=1e-14)
+
+
+@pytest.mark.parametrize("m,n,s", [(1, 10, (3, 0)), (1, 5, (2, 3)), (12, 1, (5, 0)),
+                                   (4, 1, (3, 0))])
+def test_bsvt_group_soft_threshold_with_wrap(m, n, s):
+    """1 x n (and m x 1) blocks: joint soft-threshold v max(1 - tau/||v||, 0) per group,
+    groups taken on the cyclically shifted grid (brute-force index loops)."""
+    rng = np.random.default_rng(2)
+    M, N = 12, 10
+    A = rng.standard_normal((M, N))
+    tau = 1.1
+    want = np.zeros_like(A)
+    for p in range(M // m):
+        for q in range(N // n):
+            idx = [((p * m + s[0] + r) % M, (q * n + s[1] + c) % N)
+                   for r in range(m) for c in range(n)]
+            v = np.array([A[i] for i in idx])
+            g = max(1 - tau / np.linalg.norm(v), 0.0)
+            for (i, val) in zip(idx, v):
+                want[i] = g * val
+    got = O.cycle_spun_bsvt(A, m, n, tau, s)
+    assert np.allclose(got, want, atol=1e-13)
+
+
+def test_bsvt_planted_rank1_blocks_wrapped():
+    """Rank-1 blocks planted on the shifted grid are each scaled by (1 - tau/sigma_b)+,
+    which only holds if gather/scatter wrap exactly as Shift_s prescribes."""
+    rng = np.random.default_rng(4)
+    M, N, m, n, s = 12, 18, 3, 6, (2, 5)
+    A = np.zeros((M, N))
+    want = np.zeros((M, N))
+    tau = 2.0
+    for p in range(M // m):
+        for q in range(N // n):
+            u, v = rng.standard_normal(m), rng.standard_normal(n)
+            sig = np.linalg.norm(u) * np.linalg.norm(v)
+            g = max(1 - tau / sig, 0.0)
+            for r in range(m):
+                for c in range(n):
+                    pos = ((p * m + s[0] + r) % M, (q * n + s[1] + c) % N)
+                    A[pos] = u[r] * v[c]
+                    want[pos] = g * u[r] * v[c]
+    assert np.allclose(O.cycle_spun_bsvt(A, m, n, tau, s), want, atol=1e-12)
+    # the unshifted grid does not see rank-1 blocks: the result must differ
+    assert not np.allclose(O.block_svt(A, m, n, tau), want, atol=1e-6)
+
+
+def test_skip_bound_dominates_sigma_max():
+    rng = np.random.default_rng(5)
+    for shape in [(4, 4), (8, 8), (16, 3), (32, 32), (1, 9)]:
+        for _ in range(20):
+            B = rng.standard_normal(shape) * rng.uniform(0.01, 10)
+            B[rng.random(shape) < 0.5] = 0
+            smax = _spec_norm(B)
+            assert O.skip_bound_sq(B) >= smax ** 2 * (1 - 1e-12)
+
+
+# ------------------------------------------------------------------ ADMM (eq:admm)
+def test_admm_single_scale_converges_to_Y():
+    """L = 1: the only feasible point is X_1 = Y, so Z_1 -> Y."""
+    rng = np.random.default_rng(6)
+    Y = rng.standard_normal((16, 16))
+    out = O.admm(Y, [(4, 4)], rho=1.0, iters=400)
+    assert np.linalg.norm(out["Z"][0] - Y) / np.linalg.norm(Y) < 1e-8
+
+
+def test_admm_exact_rescaling():
+    """eq:cvx is positively homogeneous and the BSVT threshold is lambda/rho, so the
+    iterates for (cY, rho/c) are exactly c times those for (Y, rho) at every K."""
+    inst = make_instance(32, 32, [(1, 1), (4, 4), (8, 8), (32, 32)], 0.05, noise=0.01, seed=3)
+    c = 3.7
+    a = O.admm(inst.Y, inst.ladder, rho=1.0, iters=25, cycle_spin=True, seed=11)
+    b = O.admm(c * inst.Y.astype(np.float64), inst.ladder, rho=1.0 / c, iters=25,
+               cycle_spin=True, seed=11)
+    assert np.abs(b["Z"] - c * a["Z"]).max() <= 1e-10 * np.abs(c * a["Z"]).max()
+    assert np.abs(b["U"] - c * a["U"]).max() <= 1e-10 * max(np.abs(c * a["U"]).max(), 1)
+
+
+def test_admm_transpose_symmetry():
+    inst = make_instance(24, 40, [(1, 1), (2, 4), (6, 8), (24, 40)], 0.1, seed=5)
+    lam = [2.0, 3.0, 5.0, 9.0]
+    a = O.admm(inst.Y, inst.ladder, lam=lam, iters=30)
+    bt = O.admm(inst.Y.T.copy(), [(n, m) for (m, n) in inst.ladder], lam=lam, iters=30)
+    assert np.allclose(bt["Z"], a["Z"].transpose(0, 2, 1), atol=1e-12)
+
+
+def test_admm_grid_shift_equivariance():
+    inst = make_instance(32, 32, [(1, 1), (4, 4), (8, 8)], 0.1, seed=8)
+    a = O.admm(inst.Y, inst.ladder, iters=30)
+    d = (8, 16)
+    b = O.admm(np.roll(inst.Y, d, axis=(0, 1)), inst.ladder, iters=30)
+    assert np.allclose(b["Z"], np.roll(a["Z"], d, axis=(1, 2)), atol=1e-12)
+
+
+def test_admm_kkt_and_duality_gap():
+    """At convergence (no cycle spinning) the ADMM fixed point solves eq:cvx:
+    consensus sum Z_i = Y, all U_i equal, rho*U is dual feasible with the dual norm
+    attained on scales carrying signal, and the primal-dual gap closes."""
+    inst = make_instance(16, 16, [(1, 1), (4, 4), (16, 16)], 0.05, seed=0)
+    Y = inst.Y.astype(np.float64)
+    out = O.admm(Y, inst.ladder, rho=2.0, iters=1500)
+    rep = O.kkt_report(Y, inst.ladder, out["lam"], 2.0, out["Z"], out["U"])
+    assert out["resid"] < 1e-7
+    assert rep["consensus"] < 1e-7
+    assert rep["u_spread"] < 1e-9
+    assert max(rep["dual_ratio"]) <= 1 + 1e-9
+    for i in range(3):
+        if np.abs(out["Z"][i]).max() > 1e-6:
+            assert rep["dual_ratio"][i] > 1 - 1e-6
+    assert abs(rep["gap"]) < 2e-7
+    # early iterates are not optimal: the certificate is not trivially satisfied
+    early = O.admm(Y, inst.ladder, rho=2.0, iters=20)
+    rep0 = O.kkt_report(Y, inst.ladder, early["lam"], 2.0, early["Z"], early["U"])
+    assert rep0["gap"] > 1e-4
+
+
+@pytest.mark.parametrize("ladder,bar", [([(1, 1), (32, 32)], 5),
+                                         ([(1, 1), (4, 4), (32, 32)], 4)])
+def test_admm_recovers_sparse_multiscale_truth(ladder, bar):
+    """Exact recovery on sparse incoherent instances (Thm 5.1; the Sec. 4 remark that
+    the suggested lambda recovers matched models; low rank + sparse is the 2-scale
+    case). Family: 32x32, density 0.01 (10 sparse entries, one rank-1 block per
+    larger scale), no noise, seeds 0..4, stop at r <= 1e-6 (cap 4000). Success =
+    every component within 1e-2 relative of the truth; `bar` successes required."""
+    ok = 0
+    for seed in range(5):
+        inst = make_instance(32, 32, ladder, 0.01, seed=seed)
+        out = O.admm(inst.Y, inst.ladder, rho=1.0, iters=4000, tol=1e-6, check_every=20)
+        errs = [np.linalg.norm(out["Z"][i] - inst.components[i]) /
+                max(np.linalg.norm(inst.components[i]), 1e-12) for i in range(len(ladder))]
+        ok += max(errs) < 1e-2
+    assert ok >= bar
+
+
+def test_admm_tolerance_stop_and_history():
+    inst = make_instance(16, 16, [(1, 1), (4, 4), (16, 16)], 0.1, seed=2)
+    out = O.admm(inst.Y, inst.ladder, iters=500, tol=1e-2, check_every=5, history=True)
+    assert out["iters"] % 5 == 0 and out["resid"] <= 1e-2 and out["iters"] < 500
+    assert len(out["history"]) == out["iters"]
+    assert all(h > 1e-2 for h in out["history"][4:out["iters"] - 1:5])
