@@ -1,0 +1,154 @@
+/*
+ * msld.h -- C ABI of the MI355X (gfx950) multi-scale low-rank decomposition library.
+ *
+ * The library solves the convex multi-scale low-rank decomposition (Ong & Lustig,
+ * "Beyond Low Rank + Sparse: Multi-scale Low Rank Matrix Decomposition", Sec. 3,
+ * eq:cvx):
+ *     minimise  sum_i lambda_i ||X_i||_(i)   subject to  sum_i X_i = Y,
+ * where ||.||_(i) is the sum of nuclear norms of the m_i x n_i blocks of scale i,
+ * with the ADMM iteration of Sec. 7 (eq:admm): a consensus X-update, a block-wise
+ * singular value soft-threshold (eq:svt, eq:bsvt) per scale, and a scaled dual
+ * update, optionally with the random cycle spinning of Sec. 9.
+ *
+ * Conventions for every entry point:
+ *   - Matrices are float32, row-major. "d_" pointers are HIP device pointers on the
+ *     device that is current when the call is made; other pointers are host memory.
+ *   - Work is enqueued on the HIP stream given at msld_create (NULL = legacy default
+ *     stream) and is stream-ordered; a call returns before the GPU work ends unless
+ *     it says otherwise.
+ *   - The caller owns every buffer it passes; the library never frees them. The
+ *     library owns its handle and workspace (allocated in msld_create, released in
+ *     msld_free).
+ *   - Errors: invalid arguments return MSLD_EINVAL before anything is enqueued. A
+ *     failing HIP call returns MSLD_EDEVICE and marks the handle failed: later
+ *     calls on it return MSLD_EDEVICE. No C++ exception crosses this interface.
+ *   - A handle must not be used from two host threads at once; distinct handles
+ *     may run concurrently on distinct streams.
+ */
+#ifndef MSLD_H
+#define MSLD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MSLD_MAX_SCALES 16
+
+typedef enum {
+  MSLD_OK = 0,
+  MSLD_EINVAL = -1,    /* invalid argument or parameter set */
+  MSLD_ENOMEM = -2,    /* device or host allocation failed */
+  MSLD_EDEVICE = -3,   /* a HIP runtime call failed; the handle is now unusable */
+  MSLD_ENUMERIC = -4,  /* the iterate became non-finite (NaN/Inf in Y or overflow) */
+  MSLD_EBUSY = -5      /* reserved for queue-full conditions */
+} msld_status;
+
+/* Problem and solver parameters (Sec. 2 partition, Sec. 4 lambda, Sec. 7 ADMM,
+ * Sec. 9 cycle spinning).
+ *   M, N        : Y is M x N, 1 <= M, N <= 2^20 and M*N < 2^31.
+ *   L           : number of scales, 1 <= L <= MSLD_MAX_SCALES.
+ *   block_m/n[i]: block size of scale i. Must divide M and N (contiguous tiling of
+ *                 the partition of Sec. 2); (M, N) is the single full-size block.
+ *                 Any shape that tiles M x N is accepted; 1 x 1 scales are
+ *                 soft-thresholded inside the consensus pass.
+ *   lambda[i]   : weight of scale i, > 0; a value <= 0 selects the default of the
+ *                 boxed rule eq:lambda, sqrt(m)+sqrt(n)+sqrt(ln(MN/max(m,n))).
+ *   rho         : ADMM parameter, > 0; scale i thresholds at lambda_i / rho.
+ *   max_iters   : iteration count K (tol == 0) or cap (tol > 0), >= 1.
+ *   tol         : 0 runs exactly max_iters iterations; > 0 also stops after
+ *                 iteration k when (k+1) % check_every == 0 and the primal residual
+ *                 r_k = sqrt(sum_i ||X_i - Z_i||_F^2) / ||Y||_F is <= tol.
+ *   check_every : >= 1, residual cadence when tol > 0.
+ *   cycle_spin  : 0 = fixed partition; 1 = random cycle spinning: scale i at
+ *                 iteration k uses shift msld_cycle_shift(shift_seed, k, i, ...).
+ *   shift_seed  : seed of the counter-based shift hash. */
+typedef struct msld_params {
+  int32_t M, N, L;
+  int32_t block_m[MSLD_MAX_SCALES];
+  int32_t block_n[MSLD_MAX_SCALES];
+  float lambda[MSLD_MAX_SCALES];
+  float rho;
+  int32_t max_iters;
+  float tol;
+  int32_t check_every;
+  int32_t cycle_spin;
+  int32_t reserved0;
+  uint64_t shift_seed;
+} msld_params;
+
+/* Outcome of one msld_solve. primal_resid is r_k of the last iteration run
+ * (computed when info is requested). live[i] counts the blocks of scale i that
+ * passed the singular-value bound test and were decomposed, summed over all
+ * iterations; sweeps[i] sums the Jacobi sweeps run on them; rank[i] sums the
+ * output ranks. */
+typedef struct msld_result {
+  int32_t iters;
+  int32_t status;
+  double primal_resid;
+  uint64_t live[MSLD_MAX_SCALES];
+  uint64_t sweeps[MSLD_MAX_SCALES];
+  uint64_t rank[MSLD_MAX_SCALES];
+} msld_result;
+
+typedef struct msld_solver msld_solver; /* opaque */
+
+/* Validate p, plan the kernels of every scale and allocate the workspace on the
+ * current device. hip_stream is a hipStream_t (NULL = default stream). On success
+ * *out holds a new handle; on failure *out is NULL. */
+msld_status msld_create(const msld_params *p, void *hip_stream, msld_solver **out);
+
+/* Run the ADMM of eq:admm on Y (M x N, leading dimension ldY >= N, device) and
+ * write the components Z_1..Z_L to d_Z (L x M x N contiguous, device, caller-owned;
+ * it also serves as the iterate, so it must not alias d_Y). Starts from
+ * Z_i = U_i = 0. If info is non-NULL the call synchronises the stream and fills
+ * *info; with tol > 0 the call always synchronises (it reads the residual back).
+ * Returns MSLD_ENUMERIC when the residual it reads back is not finite. */
+msld_status msld_solve(msld_solver *s, const float *d_Y, int64_t ldY, float *d_Z,
+                       msld_result *info);
+
+/* One block-wise SVT call with scale `scale`'s block shape and an explicit shift
+ * (Sec. 7 eq:bsvt with Sec. 9 Shift): d_Z = Shift_{-s}(BSVT_tau(Shift_s(d_V))),
+ * where Shift_s(A)[r][c] = A[(r+sr) mod M][(c+sc) mod N]. d_V and d_Z are M x N
+ * contiguous device buffers; they may alias. 0 <= sr < block_m, 0 <= sc < block_n.
+ * Uses the handle's workspace, so it must not overlap a msld_solve on the handle. */
+msld_status msld_bsvt(msld_solver *s, int32_t scale, const float *d_V, float *d_Z,
+                      float tau, int32_t sr, int32_t sc);
+
+/* Release the handle and its workspace (waits for the handle's stream). NULL-safe. */
+void msld_free(msld_solver *s);
+
+/* Bytes of device workspace msld_create allocates for p (0 if p is invalid). */
+size_t msld_workspace_bytes(const msld_params *p);
+
+/* Human-readable name of a status code (static string). */
+const char *msld_status_string(int32_t status);
+
+/* Default weight of eq:lambda for an m x n block of an M x N matrix (host). */
+msld_status msld_default_lambda(int32_t M, int32_t N, int32_t m, int32_t n, float *out);
+
+/* Cycle-spin shift of scale i at iteration k (host computation; Sec. 9). The paper
+ * leaves the draw unspecified; the library uses the SplitMix64 output mix
+ * (Steele, Lea & Flood 2014) of seed + 0x9E3779B97F4A7C15 * (16k + i + 1) modulo
+ * 2^64, and takes sr = (z >> 32) mod m, sc = (z mod 2^32) mod n. k >= 0,
+ * 0 <= i < 16. */
+msld_status msld_cycle_shift(uint64_t seed, int32_t k, int32_t i, int32_t m, int32_t n,
+                             int32_t *sr, int32_t *sc);
+
+/* The same shifts computed by device code (the code the kernels run), for
+ * count consecutive iterations k0..k0+count-1 of every scale of the handle's
+ * ladder: out[(k - k0) * L * 2 + i * 2 + {0,1}] = (sr, sc). out is host memory of
+ * 2 * L * count ints; the call synchronises. count >= 1. */
+msld_status msld_device_shifts(msld_solver *s, int32_t k0, int32_t count, int32_t *out);
+
+/* Kernel tier the plan chose for scale i: 0 = 1x1 (fused in the consensus pass),
+ * 1 = register tier (blocks up to 8 x 8), 2 = LDS tier, 3 = HBM panel tier.
+ * Returns -1 for an invalid index. */
+int32_t msld_scale_tier(const msld_solver *s, int32_t scale);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MSLD_H */

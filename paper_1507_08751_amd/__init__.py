@@ -1,0 +1,240 @@
+"""Multi-scale low-rank decomposition on MI355X: Python binding of libmsld.so.
+
+Argument marshalling only: every step of the ADMM / block-wise SVT iteration runs
+in the library's HIP kernels. PyTorch supplies device memory and the stream.
+There is no CPU fallback: without the built library (``python -m
+paper_1507_08751_amd.build``) every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+__all__ = ["load", "Solver", "solve", "bsvt", "cycle_shift", "default_lambda",
+           "MAX_SCALES", "TIERS", "MsldError"]
+
+MAX_SCALES = 16
+TIERS = {0: "1x1", 1: "register", 2: "lds", 3: "panel"}
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmsld.so")
+
+_lib = None
+
+
+class MsldError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = int(status)
+        msg = _lib.msld_status_string(self.status).decode() if _lib else str(status)
+        super().__init__(f"{what}: {msg}" if what else msg)
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int32), ("N", ctypes.c_int32), ("L", ctypes.c_int32),
+                ("block_m", ctypes.c_int32 * MAX_SCALES),
+                ("block_n", ctypes.c_int32 * MAX_SCALES),
+                ("lambda_", ctypes.c_float * MAX_SCALES),
+                ("rho", ctypes.c_float), ("max_iters", ctypes.c_int32),
+                ("tol", ctypes.c_float), ("check_every", ctypes.c_int32),
+                ("cycle_spin", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("shift_seed", ctypes.c_uint64)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("primal_resid", ctypes.c_double),
+                ("live", ctypes.c_uint64 * MAX_SCALES),
+                ("sweeps", ctypes.c_uint64 * MAX_SCALES),
+                ("rank", ctypes.c_uint64 * MAX_SCALES)]
+
+
+EXPORTS = {
+    "msld_create": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_void_p,
+                                   ctypes.POINTER(ctypes.c_void_p)]),
+    "msld_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                  ctypes.c_void_p, ctypes.POINTER(Result)]),
+    "msld_bsvt": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                 ctypes.c_void_p, ctypes.c_float, ctypes.c_int32,
+                                 ctypes.c_int32]),
+    "msld_free": (None, [ctypes.c_void_p]),
+    "msld_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Params)]),
+    "msld_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
+    "msld_default_lambda": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.c_int32, ctypes.POINTER(ctypes.c_float)]),
+    "msld_cycle_shift": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int32)]),
+    "msld_device_shifts": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_int32)]),
+    "msld_scale_tier": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+}
+
+
+def load(path: str | None = None):
+    """Load libmsld.so (built in-tree). Raises if it is missing: there is no fallback."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing; build it with "
+                           "`python -m paper_1507_08751_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in EXPORTS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status, what):
+    if status != 0:
+        raise MsldError(status, what)
+
+
+def default_lambda(M, N, m, n) -> float:
+    lib = load()
+    out = ctypes.c_float()
+    _check(lib.msld_default_lambda(M, N, m, n, ctypes.byref(out)), "msld_default_lambda")
+    return float(out.value)
+
+
+def cycle_shift(seed, k, i, m, n):
+    lib = load()
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib.msld_cycle_shift(seed, k, i, m, n, ctypes.byref(a), ctypes.byref(b)),
+           "msld_cycle_shift")
+    return a.value, b.value
+
+
+def make_params(M, N, ladder, lam=None, rho=1.0, iters=100, tol=0.0, check_every=1,
+                cycle_spin=False, seed=0) -> Params:
+    if len(ladder) < 1 or len(ladder) > MAX_SCALES:
+        raise ValueError("ladder must have 1..16 scales")
+    p = Params()
+    p.M, p.N, p.L = int(M), int(N), len(ladder)
+    for i, (m, n) in enumerate(ladder):
+        p.block_m[i], p.block_n[i] = int(m), int(n)
+        p.lambda_[i] = float(lam[i]) if lam is not None else 0.0
+    p.rho = float(rho)
+    p.max_iters = int(iters)
+    p.tol = float(tol)
+    p.check_every = int(check_every)
+    p.cycle_spin = 1 if cycle_spin else 0
+    p.shift_seed = int(seed) & ((1 << 64) - 1)
+    return p
+
+
+def workspace_bytes(M, N, ladder, **kw) -> int:
+    lib = load()
+    p = make_params(M, N, ladder, **kw)
+    return int(lib.msld_workspace_bytes(ctypes.byref(p)))
+
+
+def _stream_ptr(torch, device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Solver:
+    """One planned decomposition problem (msld_create). Reusable across solves."""
+
+    def __init__(self, M, N, ladder, lam=None, rho=1.0, iters=100, tol=0.0, check_every=1,
+                 cycle_spin=False, seed=0, device=None):
+        import torch
+        self._torch = torch
+        lib = load()
+        self.M, self.N = int(M), int(N)
+        self.ladder = [(int(m), int(n)) for (m, n) in ladder]
+        self.L = len(self.ladder)
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
+            else torch.device(device)
+        self.params = make_params(M, N, ladder, lam, rho, iters, tol, check_every,
+                                  cycle_spin, seed)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            st = lib.msld_create(ctypes.byref(self.params), _stream_ptr(torch, self.device),
+                                 ctypes.byref(h))
+        _check(st, "msld_create")
+        self._h = h
+        self._lib = lib
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.msld_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def tier(self, i) -> int:
+        return int(self._lib.msld_scale_tier(self._h, i))
+
+    def solve(self, Y, out=None, info=True):
+        """Run the ADMM on Y (M x N float32 device tensor); returns (Z [L,M,N], info)."""
+        torch = self._torch
+        if Y.dtype != torch.float32 or not Y.is_cuda or Y.dim() != 2:
+            raise ValueError("Y must be a 2-D float32 device tensor")
+        if tuple(Y.shape) != (self.M, self.N) or Y.stride(1) != 1:
+            raise ValueError("Y has the wrong shape or a non-unit column stride")
+        if out is None:
+            out = torch.empty((self.L, self.M, self.N), dtype=torch.float32, device=Y.device)
+        if out.shape != (self.L, self.M, self.N) or not out.is_contiguous():
+            raise ValueError("out must be a contiguous (L, M, N) float32 tensor")
+        res = Result()
+        with torch.cuda.device(Y.device):
+            st = self._lib.msld_solve(self._h, ctypes.c_void_p(Y.data_ptr()),
+                                      ctypes.c_int64(Y.stride(0)),
+                                      ctypes.c_void_p(out.data_ptr()),
+                                      ctypes.byref(res) if info else None)
+        _check(st, "msld_solve")
+        if not info:
+            return out, None
+        return out, {"iters": res.iters, "primal_resid": res.primal_resid,
+                     "live": list(res.live)[:self.L], "sweeps": list(res.sweeps)[:self.L],
+                     "rank": list(res.rank)[:self.L]}
+
+    def bsvt(self, scale, V, tau, shift=(0, 0), out=None):
+        """Z = Shift_{-s}(BSVT_tau(Shift_s(V))) with scale `scale`'s block shape."""
+        torch = self._torch
+        if V.dtype != torch.float32 or not V.is_cuda or tuple(V.shape) != (self.M, self.N) \
+                or not V.is_contiguous():
+            raise ValueError("V must be a contiguous (M, N) float32 device tensor")
+        if out is None:
+            out = torch.empty_like(V)
+        with torch.cuda.device(V.device):
+            st = self._lib.msld_bsvt(self._h, int(scale), ctypes.c_void_p(V.data_ptr()),
+                                     ctypes.c_void_p(out.data_ptr()), float(tau),
+                                     int(shift[0]), int(shift[1]))
+        _check(st, "msld_bsvt")
+        return out
+
+    def device_shifts(self, k0, count):
+        buf = (ctypes.c_int32 * (2 * self.L * count))()
+        with self._torch.cuda.device(self.device):
+            _check(self._lib.msld_device_shifts(self._h, k0, count, buf), "msld_device_shifts")
+        import numpy as np
+        return np.array(buf, dtype=np.int64).reshape(count, self.L, 2)
+
+
+def solve(Y, ladder, lam=None, rho=1.0, iters=100, tol=0.0, check_every=1,
+          cycle_spin=False, seed=0):
+    """One-shot decomposition: returns (Z [L, M, N] device tensor, info dict)."""
+    s = Solver(Y.shape[0], Y.shape[1], ladder, lam, rho, iters, tol, check_every,
+               cycle_spin, seed, device=Y.device)
+    try:
+        return s.solve(Y)
+    finally:
+        s.close()
+
+
+def bsvt(V, m, n, tau, shift=(0, 0)):
+    """One block-wise SVT call on V with m x n blocks and shift s (Sec. 7 and 9)."""
+    s = Solver(V.shape[0], V.shape[1], [(m, n)], iters=1, device=V.device)
+    try:
+        return s.bsvt(0, V.contiguous(), tau, shift)
+    finally:
+        s.close()

@@ -1,0 +1,1066 @@
+// HIP kernels for the ADMM / block-wise SVT iteration on gfx950 (wave64).
+//
+// State kept in "D form": with D_i = Z_i - U_i the iteration of Sec. 7 (eq:admm),
+//   X_i = (Z_i - U_i) + (Y - sum_j (Z_j - U_j)) / L,  Z_i' = BSVT(X_i + U_i),
+//   U_i' = U_i - (Z_i' - X_i),
+// becomes, with R = (Y - sum_j D_j) / L and V_i = X_i + U_i = Z_i + R:
+//   Z_i' = BSVT_{lambda_i/rho}(V_i),   D_i' = Z_i' - U_i' = 2 Z_i' - V_i,
+// and the primal residual term is X_i - Z_i' = D_i + R - Z_i'.
+// A pass reads R and Z_i and writes Z_i' and D_i'; no U plane is stored.
+#include "msld_internal.h"
+
+namespace msld {
+
+static constexpr float kEps = 5.9604645e-8f;  // 2^-24, unit roundoff of float32
+
+__device__ __forceinline__ int wrap_add(int base, int off, int mod) {
+  int v = base + off;
+  return v >= mod ? v - mod : v;
+}
+
+// ------------------------------------------------------------------ fill
+__global__ void k_fill(float* __restrict__ p, float v, size_t count) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < count; i += stride) p[i] = v;
+}
+
+hipError_t launch_fill(float* p, float v, size_t count, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  size_t blocks = (count + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, st, p, v, count);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------- consensus pass
+// R = (Y - sum_j D_j) / L  (X-update of eq:admm), fused with every 1x1 scale:
+// for 1x1 blocks the block-wise SVT is the entrywise soft-threshold (Sec. 7), so
+// Z_i' = soft(Z_i + R, tau_i) and D_i' = 2 Z_i' - (Z_i + R) are produced here.
+struct OneByOne {
+  int idx[16];
+  float tau[16];
+  int n;
+};
+
+__device__ __forceinline__ float soft(float v, float t) {
+  return v - fminf(fmaxf(v, -t), t);
+}
+
+__global__ void __launch_bounds__(256) k_consensus_v4(
+    const float* __restrict__ Y, int64_t ldY, const float* __restrict__ Dcur,
+    float* __restrict__ Dnext, float* __restrict__ Z, float* __restrict__ R, int M, int N,
+    int L, float invL, OneByOne ob) {
+  const int64_t MN = (int64_t)M * N;
+  const int total4 = (int)(MN >> 2);
+  const int stride = gridDim.x * blockDim.x;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total4; e += stride) {
+    const int flat = e << 2;
+    const int r = flat / N;
+    const int c = flat - r * N;
+    float4 y = *reinterpret_cast<const float4*>(Y + (int64_t)r * ldY + c);
+    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int j = 0; j < L; ++j) {
+      const float4 d = *reinterpret_cast<const float4*>(Dcur + j * MN + flat);
+      s.x += d.x; s.y += d.y; s.z += d.z; s.w += d.w;
+    }
+    float4 rr;
+    rr.x = (y.x - s.x) * invL; rr.y = (y.y - s.y) * invL;
+    rr.z = (y.z - s.z) * invL; rr.w = (y.w - s.w) * invL;
+    for (int t = 0; t < ob.n; ++t) {
+      const int j = ob.idx[t];
+      const float tau = ob.tau[t];
+      float4* zp = reinterpret_cast<float4*>(Z + j * MN + flat);
+      float4 z = *zp;
+      float4 v;
+      v.x = z.x + rr.x; v.y = z.y + rr.y; v.z = z.z + rr.z; v.w = z.w + rr.w;
+      z.x = soft(v.x, tau); z.y = soft(v.y, tau); z.z = soft(v.z, tau); z.w = soft(v.w, tau);
+      *zp = z;
+      float4 d;
+      d.x = 2.f * z.x - v.x; d.y = 2.f * z.y - v.y; d.z = 2.f * z.z - v.z; d.w = 2.f * z.w - v.w;
+      *reinterpret_cast<float4*>(Dnext + j * MN + flat) = d;
+    }
+    *reinterpret_cast<float4*>(R + flat) = rr;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_consensus_s(
+    const float* __restrict__ Y, int64_t ldY, const float* __restrict__ Dcur,
+    float* __restrict__ Dnext, float* __restrict__ Z, float* __restrict__ R, int M, int N,
+    int L, float invL, OneByOne ob) {
+  const int64_t MN = (int64_t)M * N;
+  const int total = (int)MN;
+  const int stride = gridDim.x * blockDim.x;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const int r = e / N;
+    const int c = e - r * N;
+    float s = 0.f;
+    for (int j = 0; j < L; ++j) s += Dcur[j * MN + e];
+    const float rr = (Y[(int64_t)r * ldY + c] - s) * invL;
+    for (int t = 0; t < ob.n; ++t) {
+      const int j = ob.idx[t];
+      const float v = Z[j * MN + e] + rr;
+      const float z = soft(v, ob.tau[t]);
+      Z[j * MN + e] = z;
+      Dnext[j * MN + e] = 2.f * z - v;
+    }
+    R[e] = rr;
+  }
+}
+
+hipError_t launch_consensus(const float* Y, int64_t ldY, const float* Dcur, float* Dnext,
+                            float* Z, float* R, int M, int N, int L, const int* scales1,
+                            const float* taus1, int n1, hipStream_t st) {
+  OneByOne ob;
+  ob.n = n1;
+  for (int t = 0; t < 16; ++t) {
+    ob.idx[t] = t < n1 ? scales1[t] : 0;
+    ob.tau[t] = t < n1 ? taus1[t] : 0.f;
+  }
+  const int64_t MN = (int64_t)M * N;
+  const float invL = 1.0f / (float)L;
+  const bool vec = (N % 4 == 0) && (ldY % 4 == 0) &&
+                   ((reinterpret_cast<uintptr_t>(Y) & 15) == 0);
+  int64_t work = vec ? MN / 4 : MN;
+  int64_t blocks = (work + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  if (blocks < 1) blocks = 1;
+  if (vec)
+    hipLaunchKernelGGL(k_consensus_v4, dim3((unsigned)blocks), dim3(256), 0, st, Y, ldY,
+                       Dcur, Dnext, Z, R, M, N, L, invL, ob);
+  else
+    hipLaunchKernelGGL(k_consensus_s, dim3((unsigned)blocks), dim3(256), 0, st, Y, ldY,
+                       Dcur, Dnext, Z, R, M, N, L, invL, ob);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------- register tier (B <= 8)
+// One lane owns one B x B block: gather (R_b after Shift_s), singular-value bound
+// test (Sec. 8), cyclic one-sided Jacobi SVD in registers, soft-threshold of the
+// singular values (eq:svt) and the rebuild, written back to the same wrapped
+// coordinates (R_b^T then Shift_{-s}).
+template <int B>
+__global__ void __launch_bounds__(256) k_tiny(
+    const float* __restrict__ Zin, const float* __restrict__ R, float* __restrict__ Zout,
+    float* __restrict__ Dout, int M, int N, int Q, int nblk, float tau, float tau2lim,
+    ShiftSpec sh, float jtol, int max_sweeps, unsigned long long* __restrict__ stats) {
+  int sr, sc;
+  resolve_shift(sh, B, B, &sr, &sc);
+  const int stride = gridDim.x * blockDim.x;
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nblk; b += stride) {
+    const int p = b / Q;
+    const int q = b - p * Q;
+    int rows[B], cols[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+      rows[i] = wrap_add(p * B + i, sr, M);
+      cols[i] = wrap_add(q * B + i, sc, N);
+    }
+    float a[B][B];
+#pragma unroll
+    for (int i = 0; i < B; ++i)
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+        const int64_t o = (int64_t)rows[i] * N + cols[j];
+        a[i][j] = Zin[o] + (R ? R[o] : 0.f);
+      }
+    // bound of Sec. 8: max_r sum_k |a_rk| (sum_j |a_jk|), and ||a||_F^2
+    float cs[B];
+    float fro = 0.f;
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      float s = 0.f;
+#pragma unroll
+      for (int i = 0; i < B; ++i) {
+        s += fabsf(a[i][j]);
+        fro += a[i][j] * a[i][j];
+      }
+      cs[j] = s;
+    }
+    float bnd = 0.f;
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+      float s = 0.f;
+#pragma unroll
+      for (int j = 0; j < B; ++j) s += fabsf(a[i][j]) * cs[j];
+      bnd = fmaxf(bnd, s);
+    }
+    if (fminf(bnd, fro) <= tau2lim) {
+#pragma unroll
+      for (int i = 0; i < B; ++i)
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+          const int64_t o = (int64_t)rows[i] * N + cols[j];
+          Zout[o] = 0.f;
+          if (Dout) Dout[o] = -a[i][j];
+        }
+      continue;
+    }
+    float w[B][B];
+#pragma unroll
+    for (int i = 0; i < B; ++i)
+#pragma unroll
+      for (int j = 0; j < B; ++j) w[i][j] = (i == j) ? 1.f : 0.f;
+    int sweeps = 0;
+    for (int swp = 0; swp < max_sweeps; ++swp) {
+      bool rot = false;
+#pragma unroll
+      for (int pp = 0; pp < B - 1; ++pp)
+#pragma unroll
+        for (int qq = pp + 1; qq < B; ++qq) {
+          float al = 0.f, be = 0.f, ga = 0.f;
+#pragma unroll
+          for (int i = 0; i < B; ++i) {
+            al += a[i][pp] * a[i][pp];
+            be += a[i][qq] * a[i][qq];
+            ga += a[i][pp] * a[i][qq];
+          }
+          if (fabsf(ga) > jtol * sqrtf(al) * sqrtf(be)) {
+            rot = true;
+            const float zeta = (be - al) / (2.f * ga);
+            const float t = (fabsf(zeta) > 1e18f)
+                                ? 0.5f / zeta
+                                : copysignf(1.f, zeta) / (fabsf(zeta) + sqrtf(1.f + zeta * zeta));
+            const float c = 1.f / sqrtf(1.f + t * t);
+            const float s = c * t;
+#pragma unroll
+            for (int i = 0; i < B; ++i) {
+              const float x = a[i][pp], y = a[i][qq];
+              a[i][pp] = c * x - s * y;
+              a[i][qq] = s * x + c * y;
+              const float u = w[i][pp], v = w[i][qq];
+              w[i][pp] = c * u - s * v;
+              w[i][qq] = s * u + c * v;
+            }
+          }
+        }
+      ++sweeps;
+      if (!rot) break;
+    }
+    float g[B];
+    int rank = 0;
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      float s2 = 0.f;
+#pragma unroll
+      for (int i = 0; i < B; ++i) s2 += a[i][j] * a[i][j];
+      const float sig = sqrtf(s2);
+      g[j] = sig > tau ? 1.f - tau / sig : 0.f;
+      rank += g[j] > 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < B; ++i)
+#pragma unroll
+      for (int c2 = 0; c2 < B; ++c2) {
+        float z = 0.f;
+#pragma unroll
+        for (int j = 0; j < B; ++j) z += g[j] * a[i][j] * w[c2][j];
+        const int64_t o = (int64_t)rows[i] * N + cols[c2];
+        const float v = Zin[o] + (R ? R[o] : 0.f);
+        Zout[o] = z;
+        if (Dout) Dout[o] = 2.f * z - v;
+      }
+    atomicAdd(&stats[0], 1ull);
+    atomicAdd(&stats[1], (unsigned long long)sweeps);
+    atomicAdd(&stats[2], (unsigned long long)rank);
+  }
+}
+
+__global__ void k_zero_int(int* p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = 0;
+}
+
+// ---------------------------------------------------------------- stream pass
+// For one scale: gather V = Z + R over every (shifted) block, write the result the
+// block would have if its SVT is zero (Z' = 0, D' = -V) and evaluate the bound of
+// Sec. 8 (plus the Frobenius norm, another valid bound on sigma_max). Blocks whose
+// bound exceeds tau enter the live list; the SVD pass later reads their V back
+// from D' = -V and overwrites both outputs.
+// A workgroup handles all m rows of one block row and a strip of `w` columns.
+__global__ void __launch_bounds__(256) k_stream(
+    const float* __restrict__ Zin, const float* __restrict__ R, float* __restrict__ Zout,
+    float* __restrict__ Dout, ScaleGeom g, StreamPlan sp, ShiftSpec sh, float tau2lim,
+    int* __restrict__ live_count, int* __restrict__ live_list, float* __restrict__ rowpart,
+    float* __restrict__ fropart) {
+  extern __shared__ float smem[];
+  const int M = g.M, N = g.N, m = g.m, n = g.n, Q = g.Q;
+  int sr, sc;
+  resolve_shift(sh, m, n, &sr, &sc);
+  const int p = blockIdx.x / sp.spr;
+  const int j = blockIdx.x - p * sp.spr;
+  int col0, w, q0 = 0, nq = 1, part = 0;
+  if (sp.whole) {
+    q0 = j * sp.kb;
+    nq = min(sp.kb, Q - q0);
+    col0 = q0 * n;
+    w = nq * n;
+  } else {
+    q0 = j / sp.spb;
+    part = j - q0 * sp.spb;
+    col0 = q0 * n + part * sp.ws;
+    w = min(sp.ws, n - part * sp.ws);
+  }
+  const int ldt = w + 1;
+  float* tile = smem;                       // m x ldt
+  float* pcs = tile + m * ldt;              // 256 partial column |.| sums
+  float* pcq = pcs + 256;                   // 256 partial column squares
+  float* cs = pcq + 256;                    // w column sums
+  float* cq = cs + sp.ws + 1;               // w column squares
+  unsigned* smax = reinterpret_cast<unsigned*>(cq + sp.ws + 1);  // nq row maxima
+  const int tid = threadIdx.x;
+  const int nel = m * w;
+  for (int e = tid; e < nel; e += 256) {
+    const int r = e / w;
+    const int c = e - r * w;
+    const int gr = wrap_add(p * m + r, sr, M);
+    const int gc = wrap_add(col0 + c, sc, N);
+    const int64_t o = (int64_t)gr * N + gc;
+    const float v = Zin[o] + (R ? R[o] : 0.f);
+    tile[r * ldt + c] = v;
+    Zout[o] = 0.f;
+    Dout[o] = -v;
+  }
+  if (tid < nq) smax[tid] = 0u;
+  __syncthreads();
+  // column sums: rg row groups of w threads
+  const int rg = 256 / w > 0 ? 256 / w : 1;
+  if (w <= 256) {
+    if (tid < rg * w) {
+      const int c = tid % w;
+      const int gq = tid / w;
+      float s = 0.f, s2 = 0.f;
+      for (int r = gq; r < m; r += rg) {
+        const float v = tile[r * ldt + c];
+        s += fabsf(v);
+        s2 += v * v;
+      }
+      pcs[tid] = s;
+      pcq[tid] = s2;
+    }
+    __syncthreads();
+    if (tid < w) {
+      float s = 0.f, s2 = 0.f;
+      for (int gq = 0; gq < rg; ++gq) {
+        s += pcs[gq * w + tid];
+        s2 += pcq[gq * w + tid];
+      }
+      cs[tid] = s;
+      cq[tid] = s2;
+    }
+  } else {
+    for (int c = tid; c < w; c += 256) {
+      float s = 0.f, s2 = 0.f;
+      for (int r = 0; r < m; ++r) {
+        const float v = tile[r * ldt + c];
+        s += fabsf(v);
+        s2 += v * v;
+      }
+      cs[c] = s;
+      cq[c] = s2;
+    }
+  }
+  __syncthreads();
+  // weighted row sums per (row, block segment)
+  const int segw = sp.whole ? n : w;
+  const int npairs = m * nq;
+  for (int e = tid; e < npairs; e += 256) {
+    const int s = e / m;
+    const int r = e - s * m;
+    const float* row = tile + r * ldt + s * segw;
+    const float* csg = cs + s * segw;
+    float acc = 0.f;
+    for (int c = 0; c < segw; ++c) acc += fabsf(row[c]) * csg[c];
+    if (sp.whole) {
+      atomicMax(&smax[s], __float_as_uint(acc));
+    } else {
+      const int64_t blk = (int64_t)p * Q + q0;
+      rowpart[(blk * sp.spb + part) * m + r] = acc;
+    }
+  }
+  __syncthreads();
+  if (sp.whole) {
+    if (tid < nq) {
+      float fro = 0.f;
+      for (int c = 0; c < n; ++c) fro += cq[tid * n + c];
+      const float bnd = __uint_as_float(smax[tid]);
+      if (fminf(bnd, fro) > tau2lim) {
+        const int slot = atomicAdd(live_count, 1);
+        live_list[slot] = p * Q + q0 + tid;
+      }
+    }
+  } else if (tid == 0) {
+    float fro = 0.f;
+    for (int c = 0; c < w; ++c) fro += cq[c];
+    fropart[((int64_t)p * Q + q0) * sp.spb + part] = fro;
+  }
+}
+
+// Completes the bound of blocks split over several strips (fixed summation order).
+__global__ void __launch_bounds__(256) k_bound_reduce(ScaleGeom g, StreamPlan sp,
+                                                      float tau2lim, int* live_count,
+                                                      int* live_list, const float* rowpart,
+                                                      const float* fropart) {
+  __shared__ float red[256];
+  const int blk = blockIdx.x;
+  const int m = g.m;
+  float mx = 0.f;
+  for (int r = threadIdx.x; r < m; r += 256) {
+    float s = 0.f;
+    for (int t = 0; t < sp.spb; ++t) s += rowpart[((int64_t)blk * sp.spb + t) * m + r];
+    mx = fmaxf(mx, s);
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    float fro = 0.f;
+    for (int t = 0; t < sp.spb; ++t) fro += fropart[(int64_t)blk * sp.spb + t];
+    if (fminf(red[0], fro) > tau2lim) {
+      const int slot = atomicAdd(live_count, 1);
+      live_list[slot] = blk;
+    }
+  }
+}
+
+// ------------------------------------------------------ one-sided Jacobi core
+// Parallel (round-robin) ordering: ncols (even) columns, ncols-1 rounds of ncols/2
+// disjoint pairs; over a sweep every pair meets once.
+__device__ __forceinline__ void rr_pair(int round, int k, int ncols, int* a, int* b) {
+  const int n1 = ncols - 1;
+  *a = (k == 0) ? 0 : 1 + (k - 1 + round) % n1;
+  *b = 1 + (ncols - 2 - k + round) % n1;
+}
+
+// Hestenes one-sided Jacobi on the columns of A (column j at A + j*lda, `arows`
+// rows), accumulating the same rotations into W (column j at W + j*ldw, `wrows`
+// rows). Each pair is handled by G consecutive lanes that split the rows; the
+// three inner products are reduced across the G lanes with xor shuffles. Returns
+// the number of sweeps run. All threads of the workgroup must call it.
+template <int G>
+__device__ int jacobi_sweeps(float* A, int lda, int arows, float* W, int ldw, int wrows,
+                             int ncols, int max_sweeps, float tol, int* any_rot) {
+  const int tid = threadIdx.x;
+  const int npairs = ncols >> 1;
+  const int grp = tid / G;
+  const int t = tid - grp * G;
+  const bool act = grp < npairs;
+  int sweeps = 0;
+  *any_rot = 0;
+  for (int sw = 0; sw < max_sweeps; ++sw) {
+    int rotated = 0;
+    for (int rd = 0; rd < ncols - 1; ++rd) {
+      float al = 0.f, be = 0.f, ga = 0.f;
+      int pa = 0, pb = 0;
+      if (act) {
+        rr_pair(rd, grp, ncols, &pa, &pb);
+        const float* ap = A + pa * lda;
+        const float* aq = A + pb * lda;
+        for (int r = t; r < arows; r += G) {
+          const float x = ap[r], y = aq[r];
+          al += x * x;
+          be += y * y;
+          ga += x * y;
+        }
+      }
+#pragma unroll
+      for (int o = G >> 1; o > 0; o >>= 1) {
+        al += __shfl_xor(al, o);
+        be += __shfl_xor(be, o);
+        ga += __shfl_xor(ga, o);
+      }
+      if (act && fabsf(ga) > tol * sqrtf(al) * sqrtf(be)) {
+        rotated = 1;
+        const float zeta = (be - al) / (2.f * ga);
+        const float tt = (fabsf(zeta) > 1e18f)
+                             ? 0.5f / zeta
+                             : copysignf(1.f, zeta) / (fabsf(zeta) + sqrtf(1.f + zeta * zeta));
+        const float c = 1.f / sqrtf(1.f + tt * tt);
+        const float s = c * tt;
+        float* ap = A + pa * lda;
+        float* aq = A + pb * lda;
+        for (int r = t; r < arows; r += G) {
+          const float x = ap[r], y = aq[r];
+          ap[r] = c * x - s * y;
+          aq[r] = s * x + c * y;
+        }
+        float* wp = W + pa * ldw;
+        float* wq = W + pb * ldw;
+        for (int r = t; r < wrows; r += G) {
+          const float x = wp[r], y = wq[r];
+          wp[r] = c * x - s * y;
+          wq[r] = s * x + c * y;
+        }
+      }
+      __syncthreads();
+    }
+    ++sweeps;
+    if (!__syncthreads_or(rotated)) break;
+    *any_rot = 1;
+  }
+  return sweeps;
+}
+
+// ------------------------------------------------------------- LDS tier
+// One workgroup per live block (persistent over the live list). The logical block
+// B (block or its transpose, mb >= nb) and the rotation matrix W live in LDS.
+template <int G>
+__global__ void __launch_bounds__(1024) k_svd_lds(
+    float* __restrict__ Zout, float* __restrict__ Dout, ScaleGeom g, ShiftSpec sh,
+    float tau, float jtol, int max_sweeps, const int* __restrict__ live_count,
+    const int* __restrict__ live_list, unsigned long long* __restrict__ stats) {
+  extern __shared__ float smem[];
+  const int M = g.M, N = g.N, m = g.m, n = g.n, Q = g.Q;
+  const int mb = g.mb, nb = g.nb, trans = g.trans;
+  const int nbp = (nb + 1) & ~1;
+  const int lda = mb | 1;
+  const int ldw = nb | 1;
+  float* A = smem;
+  float* W = A + nbp * lda;
+  float* gain = W + nbp * ldw;
+  int* lcols = reinterpret_cast<int*>(gain + nbp);
+  __shared__ int s_k;
+  int sr, sc;
+  resolve_shift(sh, m, n, &sr, &sc);
+  const int count = *live_count;
+  const int nt = blockDim.x;
+  const int tid = threadIdx.x;
+  for (int it = blockIdx.x; it < count; it += gridDim.x) {
+    const int blk = live_list[it];
+    const int p = blk / Q;
+    const int q = blk - p * Q;
+    // gather V = -D' (written by the stream pass) into logical column-major B
+    for (int e = tid; e < m * n; e += nt) {
+      const int i = e / n;
+      const int j = e - i * n;
+      const int64_t o = (int64_t)wrap_add(p * m + i, sr, M) * N + wrap_add(q * n + j, sc, N);
+      const float v = -Dout[o];
+      if (!trans) A[j * lda + i] = v;
+      else A[i * lda + j] = v;
+    }
+    if (nbp > nb)
+      for (int r = tid; r < mb; r += nt) A[nb * lda + r] = 0.f;
+    for (int e = tid; e < nbp * nb; e += nt) {
+      const int jj = e / nb;
+      const int c = e - jj * nb;
+      W[jj * ldw + c] = (jj == c) ? 1.f : 0.f;
+    }
+    __syncthreads();
+    int any_rot;
+    const int sweeps = jacobi_sweeps<G>(A, lda, mb, W, ldw, nb, nbp, max_sweeps, jtol, &any_rot);
+    // singular values sigma_j = ||B w_j||, gains max(1 - tau/sigma_j, 0)  (eq:svt)
+    for (int jj = tid; jj < nb; jj += nt) {
+      float s2 = 0.f;
+      for (int r = 0; r < mb; ++r) s2 += A[jj * lda + r] * A[jj * lda + r];
+      const float sig = sqrtf(s2);
+      gain[jj] = sig > tau ? 1.f - tau / sig : 0.f;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int k = 0;
+      for (int jj = 0; jj < nb; ++jj)
+        if (gain[jj] > 0.f) lcols[k++] = jj;
+      s_k = k;
+      atomicAdd(&stats[0], 1ull);
+      atomicAdd(&stats[1], (unsigned long long)sweeps);
+      atomicAdd(&stats[2], (unsigned long long)k);
+    }
+    __syncthreads();
+    const int k = s_k;
+    // rebuild B' = sum_j g_j (B w_j) w_j^T and scatter to the wrapped coordinates
+    for (int e = tid; e < m * n; e += nt) {
+      const int i = e / n;
+      const int j = e - i * n;
+      const int r = trans ? j : i;
+      const int c = trans ? i : j;
+      float z = 0.f;
+      for (int t = 0; t < k; ++t) {
+        const int l = lcols[t];
+        z += gain[l] * A[l * lda + r] * W[l * ldw + c];
+      }
+      const int64_t o = (int64_t)wrap_add(p * m + i, sr, M) * N + wrap_add(q * n + j, sc, N);
+      const float v = -Dout[o];
+      Zout[o] = z;
+      Dout[o] = 2.f * z - v;
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ panel tier
+// Blocks too large for LDS: block one-sided Jacobi over column panels of width pw
+// kept in HBM (column-major A, W per live block slot). Each round pairs panels
+// round-robin; a workgroup orthogonalises the 2*pw columns of one panel pair in
+// LDS (one inner sweep) and writes them back.
+__global__ void __launch_bounds__(256) k_panel_load(const float* __restrict__ Dout, ScaleGeom g,
+                                                    ShiftSpec sh, const int* live_count,
+                                                    const int* live_list, float* pA, int nbp) {
+  __shared__ float tile[32][33];
+  const int M = g.M, N = g.N, m = g.m, n = g.n, Q = g.Q, mb = g.mb;
+  int sr, sc;
+  resolve_shift(sh, m, n, &sr, &sc);
+  const int count = *live_count;
+  const int tilesj = (n + 31) / 32;
+  const int ti = blockIdx.x / tilesj;
+  const int tj = blockIdx.x - ti * tilesj;
+  const int i0 = ti * 32, j0 = tj * 32;
+  for (int it = blockIdx.y; it < count; it += gridDim.y) {
+    const int blk = live_list[it];
+    const int p = blk / Q;
+    const int q = blk - p * Q;
+    float* A = pA + (int64_t)it * nbp * mb;
+    for (int e = threadIdx.x; e < 32 * 32; e += 256) {
+      const int ii = e >> 5, jj = e & 31;
+      const int i = i0 + ii, j = j0 + jj;
+      float v = 0.f;
+      if (i < m && j < n) {
+        const int64_t o =
+            (int64_t)wrap_add(p * m + i, sr, M) * N + wrap_add(q * n + j, sc, N);
+        v = -Dout[o];
+      }
+      tile[ii][jj] = v;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 32 * 32; e += 256) {
+      const int a = e >> 5, b = e & 31;
+      if (!g.trans) {
+        // column j0+a of B, rows i0+b
+        const int i = i0 + b, j = j0 + a;
+        if (i < m && j < n) A[(int64_t)j * mb + i] = tile[b][a];
+      } else {
+        // B = block^T: column i0+a of B, rows j0+b
+        const int i = i0 + a, j = j0 + b;
+        if (i < m && j < n) A[(int64_t)i * mb + j] = tile[a][b];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_panel_init(ScaleGeom g, const int* live_count, float* pA, float* pW,
+                             int* pflag, int nbp) {
+  const int count = *live_count;
+  const int mb = g.mb, nb = g.nb;
+  for (int it = blockIdx.y; it < count; it += gridDim.y) {
+    float* A = pA + (int64_t)it * nbp * mb;
+    float* W = pW + (int64_t)it * nbp * nb;
+    const int64_t wn = (int64_t)nbp * nb;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < wn;
+         e += (int64_t)gridDim.x * blockDim.x) {
+      const int jj = (int)(e / nb);
+      const int c = (int)(e - (int64_t)jj * nb);
+      W[e] = (jj == c) ? 1.f : 0.f;
+    }
+    const int64_t pad = (int64_t)(nbp - nb) * mb;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < pad;
+         e += (int64_t)gridDim.x * blockDim.x)
+      A[(int64_t)nb * mb + e] = 0.f;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      pflag[2 * it] = 0;
+      pflag[2 * it + 1] = 0;
+    }
+  }
+}
+
+template <int G>
+__global__ void __launch_bounds__(256) k_panel_round(ScaleGeom g, const int* live_count,
+                                                     float* pA, float* pW, int* pflag, int nbp,
+                                                     int pw, int round, float jtol) {
+  extern __shared__ float smem[];
+  const int mb = g.mb, nb = g.nb;
+  const int npan = nbp / pw;
+  const int lda = mb | 1;
+  const int ldw = nb | 1;
+  float* A = smem;                 // 2pw x lda
+  float* W = A + 2 * pw * lda;     // 2pw x ldw
+  const int count = *live_count;
+  int pa, pb;
+  rr_pair(round, blockIdx.x, npan, &pa, &pb);
+  for (int it = blockIdx.y; it < count; it += gridDim.y) {
+    if (pflag[2 * it + 1]) continue;  // converged: uniform across the workgroup
+    float* gA = pA + (int64_t)it * nbp * mb;
+    float* gW = pW + (int64_t)it * nbp * nb;
+    for (int e = threadIdx.x; e < 2 * pw * mb; e += blockDim.x) {
+      const int jj = e / mb;
+      const int r = e - jj * mb;
+      const int col = (jj < pw) ? pa * pw + jj : pb * pw + (jj - pw);
+      A[jj * lda + r] = gA[(int64_t)col * mb + r];
+    }
+    for (int e = threadIdx.x; e < 2 * pw * nb; e += blockDim.x) {
+      const int jj = e / nb;
+      const int r = e - jj * nb;
+      const int col = (jj < pw) ? pa * pw + jj : pb * pw + (jj - pw);
+      W[jj * ldw + r] = gW[(int64_t)col * nb + r];
+    }
+    __syncthreads();
+    int any_rot;
+    jacobi_sweeps<G>(A, lda, mb, W, ldw, nb, 2 * pw, 1, jtol, &any_rot);
+    if (any_rot && threadIdx.x == 0) atomicOr(&pflag[2 * it], 1);
+    for (int e = threadIdx.x; e < 2 * pw * mb; e += blockDim.x) {
+      const int jj = e / mb;
+      const int r = e - jj * mb;
+      const int col = (jj < pw) ? pa * pw + jj : pb * pw + (jj - pw);
+      gA[(int64_t)col * mb + r] = A[jj * lda + r];
+    }
+    for (int e = threadIdx.x; e < 2 * pw * nb; e += blockDim.x) {
+      const int jj = e / nb;
+      const int r = e - jj * nb;
+      const int col = (jj < pw) ? pa * pw + jj : pb * pw + (jj - pw);
+      gW[(int64_t)col * nb + r] = W[jj * ldw + r];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_panel_sweep_end(const int* live_count, int* pflag,
+                                  unsigned long long* stats) {
+  const int count = *live_count;
+  for (int it = blockIdx.x * blockDim.x + threadIdx.x; it < count;
+       it += gridDim.x * blockDim.x) {
+    if (pflag[2 * it + 1]) continue;
+    atomicAdd(&stats[1], 1ull);                   // one more sweep ran on this block
+    if (!pflag[2 * it]) pflag[2 * it + 1] = 1;   // no pair above tolerance: converged
+    pflag[2 * it] = 0;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_panel_gain(ScaleGeom g, const int* live_count,
+                                                    const float* pA, float* pg, int nbp,
+                                                    float tau, unsigned long long* stats) {
+  __shared__ int s_rank;
+  const int mb = g.mb, nb = g.nb;
+  const int count = *live_count;
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  for (int it = blockIdx.x; it < count; it += gridDim.x) {
+    if (threadIdx.x == 0) s_rank = 0;
+    __syncthreads();
+    const float* A = pA + (int64_t)it * nbp * mb;
+    for (int jj = wv; jj < nb; jj += 4) {
+      float s2 = 0.f;
+      for (int r = lane; r < mb; r += 64) s2 += A[(int64_t)jj * mb + r] * A[(int64_t)jj * mb + r];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o);
+      if (lane == 0) {
+        const float sig = sqrtf(s2);
+        const float gj = sig > tau ? 1.f - tau / sig : 0.f;
+        pg[(int64_t)it * nbp + jj] = gj;
+        if (gj > 0.f) atomicAdd(&s_rank, 1);
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      atomicAdd(&stats[0], 1ull);
+      atomicAdd(&stats[2], (unsigned long long)s_rank);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(256) k_panel_rebuild(float* __restrict__ Zout,
+                                                       float* __restrict__ Dout, ScaleGeom g,
+                                                       ShiftSpec sh, const int* live_count,
+                                                       const int* live_list, const float* pA,
+                                                       const float* pW, const float* pg,
+                                                       int nbp) {
+  __shared__ int lcols[4096];
+  __shared__ float lg[4096];
+  __shared__ int s_k;
+  const int M = g.M, N = g.N, m = g.m, n = g.n, Q = g.Q, mb = g.mb, nb = g.nb;
+  int sr, sc;
+  resolve_shift(sh, m, n, &sr, &sc);
+  const int count = *live_count;
+  const int tilesj = (n + 31) / 32;
+  const int ti = blockIdx.x / tilesj;
+  const int tj = blockIdx.x - ti * tilesj;
+  const int i0 = ti * 32, j0 = tj * 32;
+  for (int it = blockIdx.y; it < count; it += gridDim.y) {
+    const int blk = live_list[it];
+    const int p = blk / Q;
+    const int q = blk - p * Q;
+    const float* A = pA + (int64_t)it * nbp * mb;
+    const float* W = pW + (int64_t)it * nbp * nb;
+    const float* gg = pg + (int64_t)it * nbp;
+    if (threadIdx.x == 0) {
+      int k = 0;
+      for (int l = 0; l < nb && k < 4096; ++l)
+        if (gg[l] > 0.f) {
+          lcols[k] = l;
+          lg[k] = gg[l];
+          ++k;
+        }
+      s_k = k;
+    }
+    __syncthreads();
+    const int k = s_k;
+    for (int e = threadIdx.x; e < 32 * 32; e += 256) {
+      const int ii = e >> 5, jj = e & 31;
+      const int i = i0 + ii, j = j0 + jj;
+      if (i >= m || j >= n) continue;
+      const int r = g.trans ? j : i;
+      const int c = g.trans ? i : j;
+      float z = 0.f;
+      for (int t = 0; t < k; ++t) {
+        const int l = lcols[t];
+        z += lg[t] * A[(int64_t)l * mb + r] * W[(int64_t)l * nb + c];
+      }
+      const int64_t o = (int64_t)wrap_add(p * m + i, sr, M) * N + wrap_add(q * n + j, sc, N);
+      const float v = -Dout[o];
+      Zout[o] = z;
+      Dout[o] = 2.f * z - v;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------- scale dispatcher
+template <int G>
+static hipError_t launch_lds_g(int grid, int threads, size_t lds, float* Zout, float* Dout,
+                               const ScaleGeom& g, const ShiftSpec& sh, float tau, float jtol,
+                               int max_sweeps, ScaleWork& w, hipStream_t st) {
+  hipLaunchKernelGGL(k_svd_lds<G>, dim3(grid), dim3(threads), lds, st, Zout, Dout, g, sh, tau,
+                     jtol, max_sweeps, w.live_count, w.live_list, w.stats);
+  return hipGetLastError();
+}
+
+template <int G>
+static hipError_t launch_round_g(dim3 grid, size_t lds, const ScaleGeom& g, ScaleWork& w,
+                                 int round, float jtol, hipStream_t st) {
+  hipLaunchKernelGGL(k_panel_round<G>, grid, dim3(256), lds, st, g, w.live_count, w.pA, w.pW,
+                     w.pflag, w.nbp, w.pw, round, jtol);
+  return hipGetLastError();
+}
+
+int lds_tier_threads(int nb, int mb, int* G) {
+  const int pairs = (nb + 1) / 2;
+  int gg = 1;
+  while (gg * 2 <= 16 && gg * 2 * 8 <= mb) gg *= 2;
+  while (gg > 1 && pairs * gg > 1024) gg >>= 1;
+  *G = gg;
+  int threads = pairs * gg;
+  threads = ((threads + 63) / 64) * 64;
+  if (threads > 1024) threads = 1024;
+  return threads;
+}
+
+size_t lds_tier_bytes(int mb, int nb) {
+  const int nbp = (nb + 1) & ~1;
+  return (size_t)4 * ((size_t)nbp * (mb | 1) + (size_t)nbp * (nb | 1) + nbp) + 4 * (size_t)nbp;
+}
+
+size_t stream_lds_bytes(int m, const StreamPlan& sp) {
+  return (size_t)4 * ((size_t)m * (sp.ws + 1) + 512 + 2 * (sp.ws + 1) + sp.ws + 1);
+}
+
+hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, ScaleWork& w,
+                        const float* Zin, const float* R, float* Zout, float* Dout, float tau,
+                        const ShiftSpec& sh, float jtol, int max_sweeps, int panel_sweeps,
+                        int num_cus, hipStream_t st) {
+  hipError_t e;
+  const double tl = (double)tau * (double)tau *
+                    (1.0 - 2.0 * (double)(g.m + g.n + 4) * (double)kEps);
+  const float tau2lim = (float)tl;
+  const int nblk = g.P * g.Q;
+  if (tier == TIER_REG) {
+    int blocks = (nblk + 255) / 256;
+    if (blocks > 65535) blocks = 65535;
+    if (g.m == 2)
+      hipLaunchKernelGGL(k_tiny<2>, dim3(blocks), dim3(256), 0, st, Zin, R, Zout, Dout, g.M, g.N,
+                         g.Q, nblk, tau, tau2lim, sh, jtol, max_sweeps, w.stats);
+    else if (g.m == 4)
+      hipLaunchKernelGGL(k_tiny<4>, dim3(blocks), dim3(256), 0, st, Zin, R, Zout, Dout, g.M, g.N,
+                         g.Q, nblk, tau, tau2lim, sh, jtol, max_sweeps, w.stats);
+    else
+      hipLaunchKernelGGL(k_tiny<8>, dim3(blocks), dim3(256), 0, st, Zin, R, Zout, Dout, g.M, g.N,
+                         g.Q, nblk, tau, tau2lim, sh, jtol, max_sweeps, w.stats);
+    return hipGetLastError();
+  }
+  // stream pass: speculative zero-output write + bound + live list
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, w.live_count);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  {
+    const size_t lds = stream_lds_bytes(g.m, sp);
+    hipLaunchKernelGGL(k_stream, dim3(g.P * sp.spr), dim3(256), lds, st, Zin, R, Zout, Dout, g,
+                       sp, sh, tau2lim, w.live_count, w.live_list, w.rowpart, w.fropart);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (!sp.whole) {
+      hipLaunchKernelGGL(k_bound_reduce, dim3(nblk), dim3(256), 0, st, g, sp, tau2lim,
+                         w.live_count, w.live_list, w.rowpart, w.fropart);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  }
+  if (tier == TIER_LDS) {
+    int G = 1;
+    const int threads = lds_tier_threads(g.nb, g.mb, &G);
+    const size_t lds = lds_tier_bytes(g.mb, g.nb);
+    int per_cu = (int)(160 * 1024 / (lds + 1024));
+    if (per_cu < 1) per_cu = 1;
+    if (per_cu > 8) per_cu = 8;
+    int grid = num_cus * per_cu;
+    if (grid > nblk) grid = nblk;
+    switch (G) {
+      case 1: return launch_lds_g<1>(grid, threads, lds, Zout, Dout, g, sh, tau, jtol, max_sweeps, w, st);
+      case 2: return launch_lds_g<2>(grid, threads, lds, Zout, Dout, g, sh, tau, jtol, max_sweeps, w, st);
+      case 4: return launch_lds_g<4>(grid, threads, lds, Zout, Dout, g, sh, tau, jtol, max_sweeps, w, st);
+      case 8: return launch_lds_g<8>(grid, threads, lds, Zout, Dout, g, sh, tau, jtol, max_sweeps, w, st);
+      default: return launch_lds_g<16>(grid, threads, lds, Zout, Dout, g, sh, tau, jtol, max_sweeps, w, st);
+    }
+  }
+  // panel tier
+  const int slots_y = w.slots < 65535 ? w.slots : 65535;
+  {
+    const int tiles = ((g.m + 31) / 32) * ((g.n + 31) / 32);
+    hipLaunchKernelGGL(k_panel_load, dim3(tiles, slots_y), dim3(256), 0, st, Dout, g, sh,
+                       w.live_count, w.live_list, w.pA, w.nbp);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_panel_init, dim3(64, slots_y), dim3(256), 0, st, g, w.live_count, w.pA,
+                       w.pW, w.pflag, w.nbp);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  const int npan = w.nbp / w.pw;
+  const int G = 256 / w.pw;
+  const size_t lds = (size_t)4 * 2 * w.pw * ((g.mb | 1) + (g.nb | 1));
+  for (int sweep = 0; sweep < panel_sweeps; ++sweep) {
+    for (int rd = 0; rd < npan - 1; ++rd) {
+      const dim3 grid(npan / 2, slots_y);
+      switch (G) {
+        case 1: e = launch_round_g<1>(grid, lds, g, w, rd, jtol, st); break;
+        case 2: e = launch_round_g<2>(grid, lds, g, w, rd, jtol, st); break;
+        case 4: e = launch_round_g<4>(grid, lds, g, w, rd, jtol, st); break;
+        case 8: e = launch_round_g<8>(grid, lds, g, w, rd, jtol, st); break;
+        case 16: e = launch_round_g<16>(grid, lds, g, w, rd, jtol, st); break;
+        case 32: e = launch_round_g<32>(grid, lds, g, w, rd, jtol, st); break;
+        default: e = launch_round_g<64>(grid, lds, g, w, rd, jtol, st); break;
+      }
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_panel_sweep_end, dim3((w.slots + 255) / 256), dim3(256), 0, st,
+                       w.live_count, w.pflag, w.stats);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_panel_gain, dim3(slots_y), dim3(256), 0, st, g, w.live_count, w.pA, w.pg,
+                     w.nbp, tau, w.stats);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  {
+    const int tiles = ((g.m + 31) / 32) * ((g.n + 31) / 32);
+    hipLaunchKernelGGL(k_panel_rebuild, dim3(tiles, slots_y), dim3(256), 0, st, Zout, Dout, g,
+                       sh, w.live_count, w.live_list, w.pA, w.pW, w.pg, w.nbp);
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ residual
+// sum_i ||D_i + R - Z_i'||^2 (= sum_i ||X_i - Z_i'||^2) with per-workgroup partials
+// reduced in a fixed order, so the value does not depend on scheduling.
+__global__ void __launch_bounds__(256) k_resid(const float* __restrict__ Dold,
+                                               const float* __restrict__ R,
+                                               const float* __restrict__ Z, int64_t MN, int L,
+                                               double* __restrict__ partial) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < MN; e += stride) {
+    const float r = R[e];
+    float s = 0.f;
+    for (int i = 0; i < L; ++i) {
+      const float d = Dold[i * MN + e] + r - Z[i * MN + e];
+      s += d * d;
+    }
+    acc += (double)s;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) k_sumsq(const float* __restrict__ Y, int64_t ldY, int M,
+                                               int N, double* __restrict__ partial) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  const int64_t MN = (int64_t)M * N;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < MN; e += stride) {
+    const int64_t r = e / N;
+    const int64_t c = e - r * N;
+    const float y = Y[r * ldY + c];
+    acc += (double)y * (double)y;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void k_final_sum(const double* partial, int nparts, double* out) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < nparts; ++i) s += partial[i];
+    out[0] = s;
+  }
+}
+
+hipError_t launch_resid(const float* Dold, const float* R, const float* Z, int M, int N, int L,
+                        double* partial, int nparts, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_resid, dim3(nparts), dim3(256), 0, st, Dold, R, Z, (int64_t)M * N, L,
+                     partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(64), 0, st, partial, nparts, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sumsq(const float* Y, int64_t ldY, int M, int N, double* partial, int nparts,
+                        double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_sumsq, dim3(nparts), dim3(256), 0, st, Y, ldY, M, N, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(64), 0, st, partial, nparts, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- shift probe
+struct Ladder16 {
+  int m[16], n[16];
+};
+
+__global__ void k_device_shifts(uint64_t seed, int k0, int count, int L, Ladder16 lad,
+                                int* out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count * L) return;
+  const int kk = t / L;
+  const int i = t - kk * L;
+  ShiftSpec sh;
+  sh.seed = seed;
+  sh.k = k0 + kk;
+  sh.scale = i;
+  sh.mode = 1;
+  sh.sr = sh.sc = 0;
+  int sr, sc;
+  resolve_shift(sh, lad.m[i], lad.n[i], &sr, &sc);
+  out[2 * t] = sr;
+  out[2 * t + 1] = sc;
+}
+
+hipError_t launch_device_shifts(uint64_t seed, int k0, int count, int L, const int* bm,
+                                const int* bn, int* out, hipStream_t st) {
+  Ladder16 lad;
+  for (int i = 0; i < 16; ++i) {
+    lad.m[i] = i < L ? bm[i] : 1;
+    lad.n[i] = i < L ? bn[i] : 1;
+  }
+  const int total = count * L;
+  hipLaunchKernelGGL(k_device_shifts, dim3((total + 255) / 256), dim3(256), 0, st, seed, k0,
+                     count, L, lad, out);
+  return hipGetLastError();
+}
+
+}  // namespace msld

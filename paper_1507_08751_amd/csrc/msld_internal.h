@@ -1,0 +1,104 @@
+// Internal declarations shared by the HIP kernels and the C-ABI runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace msld {
+
+// ---------------------------------------------------------------- shift hash
+// Cycle-spin shift of scale i at iteration k (Sec. 9, random cycle spinning).
+// Counter-based: SplitMix64 output mix (Steele, Lea & Flood 2014) of
+// seed + 0x9E3779B97F4A7C15 * (16 k + i + 1) mod 2^64; rows use the high 32 bits,
+// columns the low 32 bits, each reduced modulo the block size. One definition is
+// compiled for host and device so the kernels and msld_cycle_shift agree bit for bit.
+__host__ __device__ inline uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__host__ __device__ inline void cycle_shift(uint64_t seed, int k, int i, int m, int n,
+                                            int* sr, int* sc) {
+  const uint64_t ctr = 16ull * (uint64_t)k + (uint64_t)i + 1ull;
+  const uint64_t z = mix64(seed + 0x9E3779B97F4A7C15ull * ctr);
+  *sr = (int)((z >> 32) % (uint64_t)m);
+  *sc = (int)((z & 0xFFFFFFFFull) % (uint64_t)n);
+}
+
+// Shift of one scale for one launch: either fixed (sr, sc) or derived on device
+// from (seed, k, scale) so that graph replays can advance k in device memory.
+struct ShiftSpec {
+  uint64_t seed;
+  int k;          // iteration
+  int scale;      // scale index i
+  int mode;       // 0: none, 1: hashed from (seed, k, scale), 2: explicit (sr, sc)
+  int sr, sc;
+};
+
+__device__ inline void resolve_shift(const ShiftSpec& s, int m, int n, int* sr, int* sc) {
+  if (s.mode == 1) {
+    cycle_shift(s.seed, s.k, s.scale, m, n, sr, sc);
+  } else if (s.mode == 2) {
+    *sr = s.sr;
+    *sc = s.sc;
+  } else {
+    *sr = 0;
+    *sc = 0;
+  }
+}
+
+// ------------------------------------------------------------------ plans
+enum Tier { TIER_1X1 = 0, TIER_REG = 1, TIER_LDS = 2, TIER_PANEL = 3 };
+
+// Geometry of one scale's partition.
+struct ScaleGeom {
+  int M, N;       // matrix
+  int m, n;       // block
+  int P, Q;       // blocks per column / row of blocks
+  int trans;      // 1 if the logical block B is the transpose of the stored block
+  int mb, nb;     // logical block rows / columns, mb >= nb (B = block or block^T)
+};
+
+// Per-scale device buffers and counters.
+struct ScaleWork {
+  int* live_count;      // [1] blocks that passed the bound test this pass
+  int* live_list;       // [P*Q] block ids
+  float* rowpart;       // [P*Q*spb*m] partial row sums (strips narrower than a block)
+  float* fropart;       // [P*Q*spb] partial squared Frobenius norms
+  unsigned long long* stats;  // [4]: live blocks, sweeps, output rank, spare
+  // panel tier
+  float* pA;            // [slots][nbp][mb] column-major logical block
+  float* pW;            // [slots][nbp][nb] column-major right rotations
+  int* pflag;           // [slots][2]: rotated-in-sweep, converged
+  float* pg;            // [slots][nbp] thresholding gains
+  int slots;
+  int nbp;              // nb padded to a multiple of 2 * panel width
+  int pw;               // panel width
+};
+
+struct StreamPlan {
+  int ws;        // strip width in columns
+  int whole;     // 1: strips hold whole blocks (ws multiple of n), 0: blocks split
+  int spb;       // strips per block (whole == 0)
+  int kb;        // blocks per strip (whole == 1)
+  int spr;       // strips per block row
+};
+
+// ----------------------------------------------------------- launchers (kernels.hip)
+hipError_t launch_fill(float* p, float v, size_t count, hipStream_t st);
+hipError_t launch_consensus(const float* Y, int64_t ldY, const float* Dcur, float* Dnext,
+                            float* Z, float* R, int M, int N, int L, const int* scales1,
+                            const float* taus1, int n1, hipStream_t st);
+hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, ScaleWork& w,
+                        const float* Zin, const float* R, float* Zout, float* Dout,
+                        float tau, const ShiftSpec& sh, float jtol, int max_sweeps,
+                        int panel_sweeps, int num_cus, hipStream_t st);
+hipError_t launch_resid(const float* Dold, const float* R, const float* Z, int M, int N,
+                        int L, double* partial, int nparts, double* out, hipStream_t st);
+hipError_t launch_sumsq(const float* Y, int64_t ldY, int M, int N, double* partial,
+                        int nparts, double* out, hipStream_t st);
+hipError_t launch_device_shifts(uint64_t seed, int k0, int count, int L, const int* bm,
+                                const int* bn, int* out, hipStream_t st);
+
+}  // namespace msld

@@ -1,0 +1,88 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the header
+declares, and its host-side functions agree with the oracle bit for bit."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1507_08751_amd as msld
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "msld.h")
+
+
+def header_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(msld_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = msld.load()
+    syms = header_symbols()
+    assert len(syms) >= 10
+    for name in syms:
+        assert hasattr(lib, name), name
+    assert set(syms) == set(msld.EXPORTS)
+
+
+def test_struct_layout_matches_header():
+    # int32 M,N,L; 16+16 int32; 16 float; rho,max_iters,tol,check_every,cycle_spin,reserved; u64
+    assert ctypes.sizeof(msld.Params) == 4 * 3 + 4 * 48 + 4 * 6 + 8 + 4  # +4 alignment pad
+    assert msld.Params.shift_seed.offset % 8 == 0
+    assert ctypes.sizeof(msld.Result) == 4 + 4 + 8 + 3 * 8 * 16
+
+
+def test_status_strings():
+    lib = msld.load()
+    for code in [0, -1, -2, -3, -4, -5]:
+        assert lib.msld_status_string(code).startswith(b"MSLD_")
+
+
+def test_host_cycle_shift_matches_oracle_bit_exactly():
+    rng = np.random.default_rng(0)
+    for _ in range(2000):
+        seed = int(rng.integers(0, 2**63)) * 2 + int(rng.integers(0, 2))
+        k = int(rng.integers(0, 100000))
+        i = int(rng.integers(0, 16))
+        m = int(rng.choice([1, 2, 3, 4, 7, 8, 16, 32, 64, 100, 128, 512, 2048]))
+        n = int(rng.choice([1, 2, 4, 5, 8, 16, 32, 64, 128, 512, 943]))
+        assert msld.cycle_shift(seed, k, i, m, n) == O.cycle_shift(seed, k, i, m, n)
+
+
+def test_host_default_lambda_matches_oracle():
+    for (M, N, m, n) in [(64, 64, 1, 1), (64, 64, 4, 4), (512, 512, 512, 512),
+                         (8192, 8192, 128, 128), (128, 512, 128, 512), (1024, 256, 16, 16)]:
+        assert math.isclose(msld.default_lambda(M, N, m, n), O.default_lambda(M, N, m, n),
+                            rel_tol=1e-6)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(M=64, N=64, ladder=[(3, 3)]),            # block does not tile
+    dict(M=64, N=64, ladder=[]),                   # no scales
+    dict(M=64, N=64, ladder=[(4, 4)], rho=0.0),    # rho must be positive
+    dict(M=64, N=64, ladder=[(4, 4)], iters=0),
+    dict(M=64, N=64, ladder=[(4, 4)], tol=-1.0),
+    dict(M=64, N=64, ladder=[(4, 4)], check_every=0),
+])
+def test_invalid_params_rejected_on_host(bad):
+    bad = dict(bad)
+    M, N, ladder = bad.pop("M"), bad.pop("N"), bad.pop("ladder")
+    if not ladder:
+        p = msld.Params()
+        p.M, p.N, p.L, p.rho, p.max_iters, p.check_every = M, N, 0, 1.0, 1, 1
+        assert msld.load().msld_workspace_bytes(ctypes.byref(p)) == 0
+        return
+    assert msld.workspace_bytes(M, N, ladder, **bad) == 0
+
+
+def test_workspace_accounts_for_state_planes():
+    # R + two D buffers of L planes at least
+    M = N = 512
+    lad = [(1, 1), (4, 4), (16, 16), (64, 64), (512, 512)]
+    wb = msld.workspace_bytes(M, N, lad)
+    assert wb >= 4 * M * N * (1 + 2 * len(lad))

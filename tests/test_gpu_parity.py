@@ -1,0 +1,208 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances follow the target stated for this path: <= 1e-4 relative Frobenius error
+per block-wise SVT call and <= 1e-3 per final component after a fixed iteration
+count. The relative error divides by max(||ref||_F, 1e-3 ||input||_F) so that a
+component that is (nearly) zero is compared on the input's scale.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from synth import make_instance
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def rel_err(got, ref, scale):
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-3 * scale, 1e-30))
+
+
+def planted_input(M, N, m, n, seed, noise=0.05):
+    """Low-rank blobs at random (grid-unaligned) places plus noise, so that after a
+    shift some blocks pass the singular-value bound and others do not."""
+    rng = np.random.default_rng(seed)
+    V = noise * rng.standard_normal((M, N))
+    nblob = max(2, (M // max(m, 1)) * (N // max(n, 1)) // 3)
+    for _ in range(nblob):
+        h = int(rng.integers(1, m + 1))
+        w = int(rng.integers(1, n + 1))
+        r0 = int(rng.integers(0, M))
+        c0 = int(rng.integers(0, N))
+        u = rng.standard_normal(h)
+        v = rng.standard_normal(w)
+        rows = (r0 + np.arange(h)) % M
+        cols = (c0 + np.arange(w)) % N
+        V[np.ix_(rows, cols)] += np.outer(u, v) * rng.uniform(0.5, 3.0)
+    return V.astype(np.float32)
+
+
+def block_sigmas(V, m, n, s):
+    Vs = O.shift(V.astype(np.float64), s)
+    M, N = V.shape
+    Bk = Vs.reshape(M // m, m, N // n, n).transpose(0, 2, 1, 3).reshape(-1, m, n)
+    return np.linalg.svd(Bk, compute_uv=False)
+
+
+BSVT_CASES = [
+    # (M, N, m, n) covering every tier, ragged strips, transposed and group blocks
+    (64, 64, 1, 1),
+    (96, 160, 2, 2),
+    (96, 160, 4, 4),
+    (96, 160, 8, 8),
+    (96, 160, 16, 16),
+    (192, 320, 32, 32),
+    (192, 320, 64, 64),
+    (256, 384, 128, 128),
+    (48, 160, 16, 32),
+    (160, 48, 32, 16),
+    (120, 90, 6, 5),
+    (64, 96, 1, 32),
+    (96, 64, 32, 1),
+    (256, 256, 256, 256),
+    (512, 512, 512, 512),
+    (1024, 1024, 512, 512),
+    (128, 512, 128, 512),
+]
+
+
+@pytest.mark.parametrize("M,N,m,n", BSVT_CASES)
+def test_bsvt_call_parity(lib, M, N, m, n):
+    seed = M * 7 + N * 3 + m * 11 + n
+    V = planted_input(M, N, m, n, seed)
+    rng = np.random.default_rng(seed)
+    s = (int(rng.integers(0, m)), int(rng.integers(0, n)))
+    sig = block_sigmas(V, m, n, s)
+    tau = float(np.quantile(sig[:, 0], 0.5)) * 0.9 + 1e-3
+    ref = O.cycle_spun_bsvt(V.astype(np.float64), m, n, tau, s)
+    solver = lib.Solver(M, N, [(m, n)], iters=1)
+    print(f"case {M}x{N} block {m}x{n} tier={lib.TIERS[solver.tier(0)]} shift={s} tau={tau:.4f}",
+          flush=True)
+    Vd = torch.from_numpy(V).cuda()
+    Z = solver.bsvt(0, Vd, tau, s)
+    torch.cuda.synchronize()
+    Zg = Z.cpu().numpy()
+    err = rel_err(Zg, ref, np.linalg.norm(V))
+    live = int((sig[:, 0] > tau).sum())
+    print(f"  rel err {err:.2e}  blocks above tau {live}/{sig.shape[0]}", flush=True)
+    assert err <= 1e-4
+    solver.close()
+
+
+@pytest.mark.parametrize("case", ["zero", "tau0", "huge_tau", "rank_deficient", "repeated_sigma",
+                                  "near_tau"])
+def test_bsvt_edge_cases(lib, case):
+    M, N, m, n = 128, 128, 32, 32
+    rng = np.random.default_rng(1)
+    s = (5, 27)
+    if case == "zero":
+        V = np.zeros((M, N), np.float32)
+        tau = 1.0
+    elif case == "tau0":
+        V = rng.standard_normal((M, N)).astype(np.float32)
+        tau = 0.0
+    elif case == "huge_tau":
+        V = rng.standard_normal((M, N)).astype(np.float32)
+        tau = 1e6
+    elif case == "rank_deficient":
+        V = (rng.standard_normal((M, 3)) @ rng.standard_normal((3, N))).astype(np.float32)
+        tau = 2.0
+    elif case == "repeated_sigma":
+        # every shifted block is 3 * (orthogonal matrix): all singular values equal
+        V64 = np.zeros((M, N))
+        for p in range(M // m):
+            for q in range(N // n):
+                Qm, _ = np.linalg.qr(rng.standard_normal((m, n)))
+                for r in range(m):
+                    for c in range(n):
+                        V64[(p * m + s[0] + r) % M, (q * n + s[1] + c) % N] = 3.0 * Qm[r, c]
+        V = V64.astype(np.float32)
+        tau = 1.0
+    else:  # near_tau: singular values straddle tau closely
+        V = rng.standard_normal((M, N)).astype(np.float32)
+        sig = block_sigmas(V, m, n, s)
+        tau = float(np.median(sig[:, 0]))
+    ref = O.cycle_spun_bsvt(V.astype(np.float64), m, n, tau, s)
+    solver = lib.Solver(M, N, [(m, n)], iters=1)
+    Z = solver.bsvt(0, torch.from_numpy(V).cuda(), tau, s)
+    torch.cuda.synchronize()
+    err = rel_err(Z.cpu().numpy(), ref, max(np.linalg.norm(V), 1e-30))
+    print(f"edge {case}: rel err {err:.2e}", flush=True)
+    assert err <= 1e-4
+    solver.close()
+
+
+def test_device_shifts_bit_exact(lib):
+    lad = [(1, 1), (4, 4), (16, 32), (64, 64), (7, 5), (512, 512)]
+    solver = lib.Solver(512 * 7, 512 * 5, lad, iters=1, cycle_spin=True, seed=0xDEADBEEF12345)
+    got = solver.device_shifts(0, 300)
+    for k in range(300):
+        for i, (m, n) in enumerate(lad):
+            assert tuple(got[k, i]) == O.cycle_shift(0xDEADBEEF12345, k, i, m, n)
+    solver.close()
+
+
+def _admm_parity(lib, inst, iters, cycle_spin, seed, tol=1e-3, rho=1.0):
+    Yd = torch.from_numpy(inst.Y).cuda()
+    Z, info = lib.solve(Yd, inst.ladder, rho=rho, iters=iters, cycle_spin=cycle_spin, seed=seed)
+    torch.cuda.synchronize()
+    ref = O.admm(inst.Y, inst.ladder, rho=rho, iters=iters, cycle_spin=cycle_spin, seed=seed)
+    Zg = Z.double().cpu().numpy()
+    ny = np.linalg.norm(inst.Y)
+    errs = [rel_err(Zg[i], ref["Z"][i], ny) for i in range(len(inst.ladder))]
+    print(f"admm {inst.Y.shape} ladder={inst.ladder} K={iters} cs={cycle_spin}: errs="
+          + " ".join(f"{e:.2e}" for e in errs) + f" resid gpu={info['primal_resid']:.3e} "
+          f"oracle={ref['resid']:.3e} live={info['live']}", flush=True)
+    assert max(errs) <= tol
+    assert abs(info["primal_resid"] - ref["resid"]) <= 1e-3 * max(ref["resid"], 1e-6) + 1e-5
+    return Zg, info
+
+
+def test_admm_small_plain(lib):
+    inst = make_instance(64, 64, [(1, 1), (4, 4), (16, 16), (64, 64)], 0.05, seed=0)
+    lam = [O.default_lambda(64, 64, m, n) for (m, n) in inst.ladder]
+    assert np.allclose(lam, [4.8841, 6.6328, 10.3548, 18.0393], atol=1e-4)
+    _admm_parity(lib, inst, 200, False, 0)
+
+
+def test_admm_small_cycle_spin(lib):
+    inst = make_instance(128, 128, [(1, 1), (4, 4), (8, 8), (32, 32), (128, 128)], 0.03,
+                         noise=0.01, seed=3)
+    _admm_parity(lib, inst, 60, True, 7)
+
+
+def test_admm_rectangular_transposed_scales(lib):
+    inst = make_instance(96, 160, [(1, 1), (2, 4), (16, 32), (32, 16), (96, 160)], 0.05,
+                         noise=0.01, seed=5)
+    _admm_parity(lib, inst, 40, True, 3)
+
+
+def test_admm_512_cycle_spin(lib):
+    inst = make_instance(512, 512, [(1, 1), (4, 4), (16, 16), (64, 64), (512, 512)], 0.03,
+                         noise=0.01, seed=0)
+    _admm_parity(lib, inst, 100, True, 1)
+
+
+def test_determinism(lib):
+    inst = make_instance(256, 256, [(1, 1), (8, 8), (32, 32), (128, 128), (256, 256)], 0.02,
+                         noise=0.01, seed=9)
+    Yd = torch.from_numpy(inst.Y).cuda()
+    Z1, _ = lib.solve(Yd, inst.ladder, iters=20, cycle_spin=True, seed=4)
+    Z2, _ = lib.solve(Yd, inst.ladder, iters=20, cycle_spin=True, seed=4)
+    torch.cuda.synchronize()
+    assert torch.equal(Z1, Z2)
+
+
+def test_tolerance_stop(lib):
+    inst = make_instance(64, 64, [(1, 1), (4, 4), (64, 64)], 0.03, seed=2)
+    Yd = torch.from_numpy(inst.Y).cuda()
+    Z, info = lib.solve(Yd, inst.ladder, iters=3000, tol=1e-4, check_every=10)
+    ref = O.admm(inst.Y, inst.ladder, iters=3000, tol=1e-4, check_every=10)
+    print(f"tol stop: gpu iters {info['iters']} resid {info['primal_resid']:.3e}; oracle iters "
+          f"{ref['iters']} resid {ref['resid']:.3e}", flush=True)
+    assert info["iters"] % 10 == 0 and info["primal_resid"] <= 1e-4
+    assert abs(info["iters"] - ref["iters"]) <= 20
