@@ -109,6 +109,37 @@ msld_status msld_create(const msld_params *p, void *hip_stream, msld_solver **ou
 msld_status msld_solve(msld_solver *s, const float *d_Y, int64_t ldY, float *d_Z,
                        msld_result *info);
 
+/* Set the iterate to the ADMM starting point Z_i = U_i = 0 (d_Z is zeroed, the
+ * internal D planes too), the iteration counter k to 0 and the statistics to 0. */
+msld_status msld_reset(msld_solver *s, float *d_Z);
+
+/* Run `count` >= 1 further ADMM iterations k, k+1, ... (k continues from the last
+ * msld_reset / msld_step / msld_solve on this handle; cycle-spin shifts follow k)
+ * on the iterate held in d_Z (L x M x N, device) and the handle's D planes. If
+ * resid is non-NULL, the primal residual r of the last iteration is written to
+ * *resid (host) and the call synchronises; MSLD_ENUMERIC if r is not finite. Pass
+ * the same d_Y / d_Z as the msld_reset that started the run. */
+msld_status msld_step(msld_solver *s, const float *d_Y, int64_t ldY, float *d_Z,
+                      int32_t count, double *resid);
+
+/* Iteration count and per-scale live / sweep / rank counters accumulated since the
+ * last msld_reset (primal_resid is -1: use msld_step to obtain it). Synchronises. */
+msld_status msld_stats(msld_solver *s, msld_result *info);
+
+/* Kernel timing with HIP events on the handle's stream. msld_profile_begin(s, n)
+ * creates events for the next n iterations (each iteration records them as it is
+ * enqueued; later iterations are not recorded). msld_profile_end synchronises and
+ * returns elapsed milliseconds summed over the recorded iterations in
+ * ms[(L + 1) * 4]: for scale i, ms[4i + 0] the stream/bound pass (or the whole
+ * register-tier kernel), ms[4i + 1] the set-up of the SVD pass, ms[4i + 2] the
+ * Jacobi kernels (LDS tier kernel, or all panel-round launches), ms[4i + 3] the
+ * rest (gains, rebuild); ms[4L] the consensus pass. round_launches[L] receives the
+ * number of panel-round kernel launches per scale, *iters_recorded the number of
+ * iterations covered. */
+msld_status msld_profile_begin(msld_solver *s, int32_t max_iters);
+msld_status msld_profile_end(msld_solver *s, double *ms, int64_t *round_launches,
+                             int32_t *iters_recorded);
+
 /* One block-wise SVT call with scale `scale`'s block shape and an explicit shift
  * (Sec. 7 eq:bsvt with Sec. 9 Shift): d_Z = Shift_{-s}(BSVT_tau(Shift_s(d_V))),
  * where Shift_s(A)[r][c] = A[(r+sr) mod M][(c+sc) mod N]. d_V and d_Z are M x N

@@ -67,6 +67,15 @@ EXPORTS = {
     "msld_device_shifts": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                           ctypes.POINTER(ctypes.c_int32)]),
     "msld_scale_tier": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "msld_reset": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "msld_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                 ctypes.c_void_p, ctypes.c_int32,
+                                 ctypes.POINTER(ctypes.c_double)]),
+    "msld_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Result)]),
+    "msld_profile_begin": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "msld_profile_end": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_int32)]),
 }
 
 
@@ -196,6 +205,51 @@ class Solver:
         return out, {"iters": res.iters, "primal_resid": res.primal_resid,
                      "live": list(res.live)[:self.L], "sweeps": list(res.sweeps)[:self.L],
                      "rank": list(res.rank)[:self.L]}
+
+    def _check_yz(self, Y, Z):
+        torch = self._torch
+        if Y.dtype != torch.float32 or not Y.is_cuda or tuple(Y.shape) != (self.M, self.N) \
+                or Y.stride(1) != 1:
+            raise ValueError("Y must be an (M, N) float32 device tensor with unit column stride")
+        if Z.dtype != torch.float32 or tuple(Z.shape) != (self.L, self.M, self.N) \
+                or not Z.is_contiguous():
+            raise ValueError("Z must be a contiguous (L, M, N) float32 device tensor")
+
+    def reset(self, Z):
+        with self._torch.cuda.device(Z.device):
+            _check(self._lib.msld_reset(self._h, ctypes.c_void_p(Z.data_ptr())), "msld_reset")
+
+    def step(self, Y, Z, count=1, resid=False):
+        """Run `count` more iterations on the iterate Z; returns r of the last one or None."""
+        self._check_yz(Y, Z)
+        r = ctypes.c_double(-1.0)
+        with self._torch.cuda.device(Y.device):
+            st = self._lib.msld_step(self._h, ctypes.c_void_p(Y.data_ptr()),
+                                     ctypes.c_int64(Y.stride(0)), ctypes.c_void_p(Z.data_ptr()),
+                                     int(count), ctypes.byref(r) if resid else None)
+        _check(st, "msld_step")
+        return r.value if resid else None
+
+    def stats(self):
+        res = Result()
+        with self._torch.cuda.device(self.device):
+            _check(self._lib.msld_stats(self._h, ctypes.byref(res)), "msld_stats")
+        return {"iters": res.iters, "live": list(res.live)[:self.L],
+                "sweeps": list(res.sweeps)[:self.L], "rank": list(res.rank)[:self.L]}
+
+    def profile_begin(self, max_iters):
+        _check(self._lib.msld_profile_begin(self._h, int(max_iters)), "msld_profile_begin")
+
+    def profile_end(self):
+        ms = (ctypes.c_double * (4 * (self.L + 1)))()
+        rl = (ctypes.c_int64 * self.L)()
+        n = ctypes.c_int32()
+        with self._torch.cuda.device(self.device):
+            _check(self._lib.msld_profile_end(self._h, ms, rl, ctypes.byref(n)),
+                   "msld_profile_end")
+        per = [list(ms[4 * i:4 * i + 4]) for i in range(self.L)]
+        return {"scale_ms": per, "consensus_ms": ms[4 * self.L], "round_launches": list(rl),
+                "iters": n.value}
 
     def bsvt(self, scale, V, tau, shift=(0, 0), out=None):
         """Z = Shift_{-s}(BSVT_tau(Shift_s(V))) with scale `scale`'s block shape."""

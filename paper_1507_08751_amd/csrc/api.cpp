@@ -163,6 +163,12 @@ struct msld_solver {
   char* arena;
   double* host_res;  // pinned, 4 doubles
   ScaleWork work[MSLD_MAX_SCALES];
+  int k;              // next iteration index (drives the cycle-spin shifts)
+  int cur;            // which D buffer holds the current D_i
+  // profiling: per iteration 2 consensus events + 5 events per scale
+  int prof_cap, prof_n;
+  hipEvent_t* prof_ev;
+  int64_t round_launches[MSLD_MAX_SCALES];
 };
 
 namespace {
@@ -182,11 +188,13 @@ msld_status dev_err(msld_solver* s, hipError_t e) {
 float jacobi_tol(int mb) { return 4.0f * 5.9604645e-8f * std::sqrt((float)mb); }
 
 msld_status run_scale(msld_solver* s, int i, const float* Zin, const float* R, float* Zout,
-                      float* Dout, float tau, const ShiftSpec& sh) {
+                      float* Dout, float tau, const ShiftSpec& sh, hipEvent_t* ev) {
   const Plan& pl = s->plan;
   const ScaleGeom& g = pl.geom[i];
+  int rl = 0;
   MSLD_TRY(s, launch_scale(g, pl.tier[i], pl.sp[i], s->work[i], Zin, R, Zout, Dout, tau, sh,
-                           jacobi_tol(g.mb), 40, 20, s->num_cus, s->st));
+                           jacobi_tol(g.mb), 40, 20, s->num_cus, s->st, ev, &rl));
+  if (ev) s->round_launches[i] += rl;
   return MSLD_OK;
 }
 
@@ -290,6 +298,11 @@ msld_status msld_create(const msld_params* p, void* hip_stream, msld_solver** ou
 void msld_free(msld_solver* s) {
   if (!s) return;
   (void)hipStreamSynchronize(s->st);
+  if (s->prof_ev) {
+    for (size_t e = 0; e < (2 + 5 * (size_t)s->p.L) * (size_t)s->prof_cap; ++e)
+      (void)hipEventDestroy(s->prof_ev[e]);
+    std::free(s->prof_ev);
+  }
   if (s->arena) (void)hipFree(s->arena);
   if (s->host_res) (void)hipHostFree(s->host_res);
   delete s;
@@ -306,20 +319,37 @@ static msld_status zero_stats(msld_solver* s) {
   return MSLD_OK;
 }
 
-msld_status msld_solve(msld_solver* s, const float* d_Y, int64_t ldY, float* d_Z,
-                       msld_result* info) {
-  if (!s || !d_Y || !d_Z) return MSLD_EINVAL;
+static float* plane_R(msld_solver* s) {
+  return reinterpret_cast<float*>(s->arena + s->plan.off_R);
+}
+
+static float* plane_D(msld_solver* s, int which) {
+  const size_t MN = (size_t)s->p.M * s->p.N;
+  return reinterpret_cast<float*>(s->arena + s->plan.off_D) + (size_t)which * MN * s->p.L;
+}
+
+msld_status msld_reset(msld_solver* s, float* d_Z) {
+  if (!s || !d_Z) return MSLD_EINVAL;
   if (s->failed) return MSLD_EDEVICE;
+  const size_t MN = (size_t)s->p.M * s->p.N;
+  MSLD_TRY(s, launch_fill(d_Z, 0.f, MN * s->p.L, s->st));
+  MSLD_TRY(s, launch_fill(plane_D(s, 0), 0.f, MN * s->p.L, s->st));
+  s->k = 0;
+  s->cur = 0;
+  return zero_stats(s);
+}
+
+// One ADMM iteration k = s->k (eq:admm), D buffers ping-pong; when want_res the
+// residual r_k is computed on device into dres[0].
+static msld_status iterate_once(msld_solver* s, const float* d_Y, int64_t ldY, float* d_Z,
+                                bool want_res) {
   const msld_params& p = s->p;
-  const int M = p.M, N = p.N, L = p.L;
-  if (ldY < N) return MSLD_EINVAL;
-  const size_t MN = (size_t)M * N;
   const Plan& pl = s->plan;
-  float* R = reinterpret_cast<float*>(s->arena + pl.off_R);
-  float* D[2] = {reinterpret_cast<float*>(s->arena + pl.off_D),
-                 reinterpret_cast<float*>(s->arena + pl.off_D) + MN * L};
-  double* part = reinterpret_cast<double*>(s->arena + pl.off_part);
-  double* dres = reinterpret_cast<double*>(s->arena + pl.off_res);
+  const int M = p.M, N = p.N, L = p.L;
+  const size_t MN = (size_t)M * N;
+  float* R = plane_R(s);
+  float* Dc = plane_D(s, s->cur);
+  float* Dn = plane_D(s, 1 - s->cur);
   int scales1[16];
   float taus1[16];
   int n1 = 0;
@@ -329,70 +359,158 @@ msld_status msld_solve(msld_solver* s, const float* d_Y, int64_t ldY, float* d_Z
       taus1[n1] = pl.tau_default[i];
       ++n1;
     }
-  MSLD_TRY(s, launch_fill(d_Z, 0.f, MN * L, s->st));
-  MSLD_TRY(s, launch_fill(D[0], 0.f, MN * L, s->st));
-  msld_status zs = zero_stats(s);
-  if (zs != MSLD_OK) return zs;
-  const bool want_res = info != nullptr || p.tol > 0.f;
-  double ny2 = 1.0;
-  if (want_res) {
-    MSLD_TRY(s, launch_sumsq(d_Y, ldY, M, N, part, kResidParts, dres + 1, s->st));
-    MSLD_TRY(s, hipMemcpyAsync(s->host_res + 1, dres + 1, 8, hipMemcpyDeviceToHost, s->st));
+  hipEvent_t* ev = nullptr;
+  if (s->prof_ev && s->prof_n < s->prof_cap) {
+    ev = s->prof_ev + (size_t)s->prof_n * (2 + 5 * L);
+    ++s->prof_n;
+    MSLD_TRY(s, hipEventRecord(ev[0], s->st));
   }
-  int cur = 0;
-  int iters = 0;
+  MSLD_TRY(s, launch_consensus(d_Y, ldY, Dc, Dn, d_Z, R, M, N, L, scales1, taus1, n1, s->st));
+  if (ev) MSLD_TRY(s, hipEventRecord(ev[1], s->st));
+  for (int i = 0; i < L; ++i) {
+    if (pl.tier[i] == TIER_1X1) continue;
+    ShiftSpec sh;
+    sh.seed = p.shift_seed;
+    sh.k = s->k;
+    sh.scale = i;
+    sh.mode = p.cycle_spin ? 1 : 0;
+    sh.sr = sh.sc = 0;
+    float* Zi = d_Z + MN * i;
+    msld_status rs = run_scale(s, i, Zi, R, Zi, Dn + MN * i, pl.tau_default[i], sh,
+                               ev ? ev + 2 + 5 * i : nullptr);
+    if (rs != MSLD_OK) return rs;
+  }
+  if (want_res) {
+    double* part = reinterpret_cast<double*>(s->arena + pl.off_part);
+    double* dres = reinterpret_cast<double*>(s->arena + pl.off_res);
+    MSLD_TRY(s, launch_resid(Dc, R, d_Z, M, N, L, part, kResidParts, dres, s->st));
+  }
+  s->k += 1;
+  s->cur = 1 - s->cur;
+  return MSLD_OK;
+}
+
+static msld_status read_resid(msld_solver* s, const float* d_Y, int64_t ldY, double* out) {
+  const Plan& pl = s->plan;
+  double* part = reinterpret_cast<double*>(s->arena + pl.off_part);
+  double* dres = reinterpret_cast<double*>(s->arena + pl.off_res);
+  MSLD_TRY(s, launch_sumsq(d_Y, ldY, s->p.M, s->p.N, part, kResidParts, dres + 1, s->st));
+  MSLD_TRY(s, hipMemcpyAsync(s->host_res, dres, 16, hipMemcpyDeviceToHost, s->st));
+  MSLD_TRY(s, hipStreamSynchronize(s->st));
+  const double ny2 = s->host_res[1] > 0 ? s->host_res[1] : 1.0;
+  *out = std::sqrt(s->host_res[0] / ny2);
+  return std::isfinite(*out) ? MSLD_OK : MSLD_ENUMERIC;
+}
+
+msld_status msld_step(msld_solver* s, const float* d_Y, int64_t ldY, float* d_Z, int32_t count,
+                      double* resid) {
+  if (!s || !d_Y || !d_Z || count < 1) return MSLD_EINVAL;
+  if (s->failed) return MSLD_EDEVICE;
+  if (ldY < s->p.N) return MSLD_EINVAL;
+  for (int c = 0; c < count; ++c) {
+    msld_status st = iterate_once(s, d_Y, ldY, d_Z, resid != nullptr && c == count - 1);
+    if (st != MSLD_OK) return st;
+  }
+  if (resid) return read_resid(s, d_Y, ldY, resid);
+  return MSLD_OK;
+}
+
+msld_status msld_stats(msld_solver* s, msld_result* info) {
+  if (!s || !info) return MSLD_EINVAL;
+  if (s->failed) return MSLD_EDEVICE;
+  std::memset(info, 0, sizeof(*info));
+  info->iters = s->k;
+  info->primal_resid = -1.0;
+  for (int i = 0; i < s->p.L; ++i) {
+    unsigned long long st4[4];
+    MSLD_TRY(s, hipMemcpyAsync(st4, s->work[i].stats, sizeof(st4), hipMemcpyDeviceToHost, s->st));
+    MSLD_TRY(s, hipStreamSynchronize(s->st));
+    info->live[i] = st4[0];
+    info->sweeps[i] = st4[1];
+    info->rank[i] = st4[2];
+  }
+  return MSLD_OK;
+}
+
+msld_status msld_solve(msld_solver* s, const float* d_Y, int64_t ldY, float* d_Z,
+                       msld_result* info) {
+  if (!s || !d_Y || !d_Z) return MSLD_EINVAL;
+  if (s->failed) return MSLD_EDEVICE;
+  const msld_params& p = s->p;
+  if (ldY < p.N) return MSLD_EINVAL;
+  msld_status st = msld_reset(s, d_Z);
+  if (st != MSLD_OK) return st;
   double resid = -1.0;
   msld_status result = MSLD_OK;
   for (int k = 0; k < p.max_iters; ++k) {
-    MSLD_TRY(s, launch_consensus(d_Y, ldY, D[cur], D[1 - cur], d_Z, R, M, N, L, scales1, taus1,
-                                 n1, s->st));
-    for (int i = 0; i < L; ++i) {
-      if (pl.tier[i] == TIER_1X1) continue;
-      ShiftSpec sh;
-      sh.seed = p.shift_seed;
-      sh.k = k;
-      sh.scale = i;
-      sh.mode = p.cycle_spin ? 1 : 0;
-      sh.sr = sh.sc = 0;
-      float* Zi = d_Z + MN * i;
-      msld_status rs = run_scale(s, i, Zi, R, Zi, D[1 - cur] + MN * i, pl.tau_default[i], sh);
-      if (rs != MSLD_OK) return rs;
-    }
-    iters = k + 1;
+    const int iters = k + 1;
     const bool check = p.tol > 0.f && (iters % p.check_every == 0);
     const bool last = iters == p.max_iters;
-    if (check || (last && info)) {
-      MSLD_TRY(s, launch_resid(D[cur], R, d_Z, M, N, L, part, kResidParts, dres, s->st));
-      MSLD_TRY(s, hipMemcpyAsync(s->host_res, dres, 8, hipMemcpyDeviceToHost, s->st));
-      MSLD_TRY(s, hipStreamSynchronize(s->st));
-      ny2 = s->host_res[1] > 0 ? s->host_res[1] : 1.0;
-      resid = std::sqrt(s->host_res[0] / ny2);
-      if (!std::isfinite(resid)) {
-        result = MSLD_ENUMERIC;
-        cur = 1 - cur;
-        break;
-      }
-      if (check && resid <= (double)p.tol) {
-        cur = 1 - cur;
-        break;
-      }
+    const bool want = check || (last && info);
+    st = iterate_once(s, d_Y, ldY, d_Z, want);
+    if (st != MSLD_OK) return st;
+    if (want) {
+      result = read_resid(s, d_Y, ldY, &resid);
+      if (result != MSLD_OK) break;
+      if (check && resid <= (double)p.tol) break;
     }
-    cur = 1 - cur;
   }
   if (info) {
-    std::memset(info, 0, sizeof(*info));
-    info->iters = iters;
+    st = msld_stats(s, info);
+    if (st != MSLD_OK) return st;
     info->primal_resid = resid;
-    for (int i = 0; i < L; ++i) {
-      unsigned long long st4[4];
-      MSLD_TRY(s, hipMemcpyAsync(st4, s->work[i].stats, sizeof(st4), hipMemcpyDeviceToHost, s->st));
-      MSLD_TRY(s, hipStreamSynchronize(s->st));
-      info->live[i] = st4[0];
-      info->sweeps[i] = st4[1];
-      info->rank[i] = st4[2];
-    }
     info->status = result;
   }
+  return result;
+}
+
+msld_status msld_profile_begin(msld_solver* s, int32_t max_iters) {
+  if (!s || max_iters < 1) return MSLD_EINVAL;
+  if (s->failed) return MSLD_EDEVICE;
+  if (s->prof_ev) return MSLD_EINVAL;
+  const size_t per = 2 + 5 * (size_t)s->p.L;
+  const size_t n = per * (size_t)max_iters;
+  s->prof_ev = static_cast<hipEvent_t*>(std::calloc(n, sizeof(hipEvent_t)));
+  if (!s->prof_ev) return MSLD_ENOMEM;
+  for (size_t e = 0; e < n; ++e)
+    if (hipEventCreate(&s->prof_ev[e]) != hipSuccess) {
+      for (size_t f = 0; f < e; ++f) (void)hipEventDestroy(s->prof_ev[f]);
+      std::free(s->prof_ev);
+      s->prof_ev = nullptr;
+      return MSLD_EDEVICE;
+    }
+  s->prof_cap = max_iters;
+  s->prof_n = 0;
+  for (int i = 0; i < MSLD_MAX_SCALES; ++i) s->round_launches[i] = 0;
+  return MSLD_OK;
+}
+
+msld_status msld_profile_end(msld_solver* s, double* ms, int64_t* round_launches,
+                             int32_t* iters_recorded) {
+  if (!s || !ms || !round_launches || !iters_recorded) return MSLD_EINVAL;
+  if (!s->prof_ev) return MSLD_EINVAL;
+  const int L = s->p.L;
+  const size_t per = 2 + 5 * (size_t)L;
+  msld_status result = MSLD_OK;
+  if (hipStreamSynchronize(s->st) != hipSuccess) result = dev_err(s, hipErrorUnknown);
+  for (int i = 0; i < 4 * (L + 1); ++i) ms[i] = 0.0;
+  for (int it = 0; it < s->prof_n && result == MSLD_OK; ++it) {
+    hipEvent_t* ev = s->prof_ev + (size_t)it * per;
+    float t;
+    if (hipEventElapsedTime(&t, ev[0], ev[1]) == hipSuccess) ms[4 * L] += t;
+    for (int i = 0; i < L; ++i) {
+      if (s->plan.tier[i] == TIER_1X1) continue;
+      hipEvent_t* e5 = ev + 2 + 5 * i;
+      for (int j = 0; j < 4; ++j)
+        if (hipEventElapsedTime(&t, e5[j], e5[j + 1]) == hipSuccess) ms[4 * i + j] += t;
+    }
+  }
+  for (int i = 0; i < L; ++i) round_launches[i] = s->round_launches[i];
+  *iters_recorded = s->prof_n;
+  for (size_t e = 0; e < per * (size_t)s->prof_cap; ++e) (void)hipEventDestroy(s->prof_ev[e]);
+  std::free(s->prof_ev);
+  s->prof_ev = nullptr;
+  s->prof_cap = s->prof_n = 0;
   return result;
 }
 
@@ -429,7 +547,7 @@ msld_status msld_bsvt(msld_solver* s, int32_t scale, const float* d_V, float* d_
   }
   msld_status zs = zero_stats(s);
   if (zs != MSLD_OK) return zs;
-  return run_scale(s, scale, d_V, nullptr, d_Z, Dws, tau, sh);
+  return run_scale(s, scale, d_V, nullptr, d_Z, Dws, tau, sh, nullptr);
 }
 
 msld_status msld_device_shifts(msld_solver* s, int32_t k0, int32_t count, int32_t* out) {

@@ -854,11 +854,20 @@ size_t stream_lds_bytes(int m, const StreamPlan& sp) {
   return (size_t)4 * ((size_t)m * (sp.ws + 1) + 512 + 2 * (sp.ws + 1) + sp.ws + 1);
 }
 
+#define MSLD_EV(i)                                                    \
+  do {                                                                \
+    if (ev) {                                                         \
+      hipError_t ee_ = hipEventRecord(ev[(i)], st);                   \
+      if (ee_ != hipSuccess) return ee_;                              \
+    }                                                                 \
+  } while (0)
+
 hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, ScaleWork& w,
                         const float* Zin, const float* R, float* Zout, float* Dout, float tau,
                         const ShiftSpec& sh, float jtol, int max_sweeps, int panel_sweeps,
-                        int num_cus, hipStream_t st) {
+                        int num_cus, hipStream_t st, hipEvent_t* ev, int* round_launches) {
   hipError_t e;
+  MSLD_EV(0);
   const double tl = (double)tau * (double)tau *
                     (1.0 - 2.0 * (double)(g.m + g.n + 4) * (double)kEps);
   const float tau2lim = (float)tl;
@@ -875,7 +884,9 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
     else
       hipLaunchKernelGGL(k_tiny<8>, dim3(blocks), dim3(256), 0, st, Zin, R, Zout, Dout, g.M, g.N,
                          g.Q, nblk, tau, tau2lim, sh, jtol, max_sweeps, w.stats);
-    return hipGetLastError();
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    MSLD_EV(1); MSLD_EV(2); MSLD_EV(3); MSLD_EV(4);
+    return hipSuccess;
   }
   // stream pass: speculative zero-output write + bound + live list
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, w.live_count);
@@ -891,7 +902,9 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
   }
+  MSLD_EV(1);
   if (tier == TIER_LDS) {
+    MSLD_EV(2);
     int G = 1;
     const int threads = lds_tier_threads(g.nb, g.mb, &G);
     const size_t lds = lds_tier_bytes(g.mb, g.nb);
@@ -901,12 +914,15 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
     int grid = num_cus * per_cu;
     if (grid > nblk) grid = nblk;
     switch (G) {
-      case 1: return launch_lds_g<1>(grid, threads, lds, Zout, Dout, g, sh, tau, jtol, max_sweeps, w, st);
-      case 2: return launch_lds_g<2>(grid, threads, lds, Zout, Dout, g, sh, tau, jtol, max_sweeps, w, st);
-      case 4: return launch_lds_g<4>(grid, threads, lds, Zout, Dout, g, sh, tau, jtol, max_sweeps, w, st);
-      case 8: return launch_lds_g<8>(grid, threads, lds, Zout, Dout, g, sh, tau, jtol, max_sweeps, w, st);
-      default: return launch_lds_g<16>(grid, threads, lds, Zout, Dout, g, sh, tau, jtol, max_sweeps, w, st);
+      case 1: e = launch_lds_g<1>(grid, threads, lds, Zout, Dout, g, sh, tau, jtol, max_sweeps, w, st); break;
+      case 2: e = launch_lds_g<2>(grid, threads, lds, Zout, Dout, g, sh, tau, jtol, max_sweeps, w, st); break;
+      case 4: e = launch_lds_g<4>(grid, threads, lds, Zout, Dout, g, sh, tau, jtol, max_sweeps, w, st); break;
+      case 8: e = launch_lds_g<8>(grid, threads, lds, Zout, Dout, g, sh, tau, jtol, max_sweeps, w, st); break;
+      default: e = launch_lds_g<16>(grid, threads, lds, Zout, Dout, g, sh, tau, jtol, max_sweeps, w, st); break;
     }
+    if (e != hipSuccess) return e;
+    MSLD_EV(3); MSLD_EV(4);
+    return hipSuccess;
   }
   // panel tier
   const int slots_y = w.slots < 65535 ? w.slots : 65535;
@@ -922,6 +938,7 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
   const int npan = w.nbp / w.pw;
   const int G = 256 / w.pw;
   const size_t lds = (size_t)4 * 2 * w.pw * ((g.mb | 1) + (g.nb | 1));
+  MSLD_EV(2);
   for (int sweep = 0; sweep < panel_sweeps; ++sweep) {
     for (int rd = 0; rd < npan - 1; ++rd) {
       const dim3 grid(npan / 2, slots_y);
@@ -935,11 +952,13 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
         default: e = launch_round_g<64>(grid, lds, g, w, rd, jtol, st); break;
       }
       if (e != hipSuccess) return e;
+      if (round_launches) ++*round_launches;
     }
     hipLaunchKernelGGL(k_panel_sweep_end, dim3((w.slots + 255) / 256), dim3(256), 0, st,
                        w.live_count, w.pflag, w.stats);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
+  MSLD_EV(3);
   hipLaunchKernelGGL(k_panel_gain, dim3(slots_y), dim3(256), 0, st, g, w.live_count, w.pA, w.pg,
                      w.nbp, tau, w.stats);
   if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -948,7 +967,9 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
     hipLaunchKernelGGL(k_panel_rebuild, dim3(tiles, slots_y), dim3(256), 0, st, Zout, Dout, g,
                        sh, w.live_count, w.live_list, w.pA, w.pW, w.pg, w.nbp);
   }
-  return hipGetLastError();
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  MSLD_EV(4);
+  return hipSuccess;
 }
 
 // ------------------------------------------------------------------ residual

@@ -90,10 +90,13 @@ hipError_t launch_fill(float* p, float v, size_t count, hipStream_t st);
 hipError_t launch_consensus(const float* Y, int64_t ldY, const float* Dcur, float* Dnext,
                             float* Z, float* R, int M, int N, int L, const int* scales1,
                             const float* taus1, int n1, hipStream_t st);
+// ev (optional, 5 events): recorded before the scale pass, after the stream pass,
+// before the panel rounds, after the panel rounds and after the whole pass.
 hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, ScaleWork& w,
                         const float* Zin, const float* R, float* Zout, float* Dout,
                         float tau, const ShiftSpec& sh, float jtol, int max_sweeps,
-                        int panel_sweeps, int num_cus, hipStream_t st);
+                        int panel_sweeps, int num_cus, hipStream_t st, hipEvent_t* ev,
+                        int* round_launches);
 hipError_t launch_resid(const float* Dold, const float* R, const float* Z, int M, int N,
                         int L, double* partial, int nparts, double* out, hipStream_t st);
 hipError_t launch_sumsq(const float* Y, int64_t ldY, int M, int N, double* partial,
