@@ -116,7 +116,8 @@ def main():
         log(f"scale {i} ({m}x{n}, {tiers[i]}): stream {ms[0]:.2f} setup {ms[1]:.2f} "
             f"jacobi {ms[2]:.2f} finish {ms[3]:.2f} ms; live {stats['live'][i]} of {nblk * K} "
             f"block-iters, sweeps {stats['sweeps'][i]}, rank {stats['rank'][i]}, "
-            f"round launches {prof['round_launches'][i]}")
+            f"certified {stats['certified'][i]} (fail coupling {stats['fail_coupling'][i]}, "
+            f"bound {stats['fail_bound'][i]}), round launches {prof['round_launches'][i]}")
         if tiers[i] in ("lds", "panel") and (best is None or ms[2] > best[1]):
             best = (i, ms[2])
     roof = None

@@ -64,7 +64,13 @@ typedef enum {
  *   check_every : >= 1, residual cadence when tol > 0.
  *   cycle_spin  : 0 = fixed partition; 1 = random cycle spinning: scale i at
  *                 iteration k uses shift msld_cycle_shift(shift_seed, k, i, ...).
- *   shift_seed  : seed of the counter-based shift hash. */
+ *   shift_seed  : seed of the counter-based shift hash.
+ *   lowrank_min : blocks whose shorter side is >= this use the certified low-rank
+ *                 SVT (subspace iteration on the Gram matrix, one-sided Jacobi on the
+ *                 reduced block, and an a-posteriori certificate that bounds the
+ *                 error by the non-expansiveness of the prox; blocks that fail it
+ *                 fall back to panel Jacobi). 0 selects the default (128); a
+ *                 negative value disables the path. Results agree to rounding. */
 typedef struct msld_params {
   int32_t M, N, L;
   int32_t block_m[MSLD_MAX_SCALES];
@@ -75,7 +81,7 @@ typedef struct msld_params {
   float tol;
   int32_t check_every;
   int32_t cycle_spin;
-  int32_t reserved0;
+  int32_t lowrank_min;
   uint64_t shift_seed;
 } msld_params;
 
@@ -83,7 +89,9 @@ typedef struct msld_params {
  * (computed when info is requested). live[i] counts the blocks of scale i that
  * passed the singular-value bound test and were decomposed, summed over all
  * iterations; sweeps[i] sums the Jacobi sweeps run on them; rank[i] sums the
- * output ranks. */
+ * output ranks; certified[i] counts the blocks finished by the certified low-rank
+ * path (the rest of live[i] ran full Jacobi); fail_coupling[i] / fail_bound[i]
+ * count the blocks that path handed to Jacobi, by the test they failed. */
 typedef struct msld_result {
   int32_t iters;
   int32_t status;
@@ -91,6 +99,9 @@ typedef struct msld_result {
   uint64_t live[MSLD_MAX_SCALES];
   uint64_t sweeps[MSLD_MAX_SCALES];
   uint64_t rank[MSLD_MAX_SCALES];
+  uint64_t certified[MSLD_MAX_SCALES];
+  uint64_t fail_coupling[MSLD_MAX_SCALES];
+  uint64_t fail_bound[MSLD_MAX_SCALES];
 } msld_result;
 
 typedef struct msld_solver msld_solver; /* opaque */
@@ -175,8 +186,8 @@ msld_status msld_cycle_shift(uint64_t seed, int32_t k, int32_t i, int32_t m, int
 msld_status msld_device_shifts(msld_solver *s, int32_t k0, int32_t count, int32_t *out);
 
 /* Kernel tier the plan chose for scale i: 0 = 1x1 (fused in the consensus pass),
- * 1 = register tier (blocks up to 8 x 8), 2 = LDS tier, 3 = HBM panel tier.
- * Returns -1 for an invalid index. */
+ * 1 = register tier (blocks up to 8 x 8), 2 = LDS tier, 3 = HBM panel tier,
+ * 4 = certified low-rank path with panel fallback. Returns -1 for an invalid index. */
 int32_t msld_scale_tier(const msld_solver *s, int32_t scale);
 
 #ifdef __cplusplus

@@ -15,7 +15,7 @@ __all__ = ["load", "Solver", "solve", "bsvt", "cycle_shift", "default_lambda",
            "MAX_SCALES", "TIERS", "MsldError"]
 
 MAX_SCALES = 16
-TIERS = {0: "1x1", 1: "register", 2: "lds", 3: "panel"}
+TIERS = {0: "1x1", 1: "register", 2: "lds", 3: "panel", 4: "lowrank"}
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmsld.so")
 
 _lib = None
@@ -35,7 +35,7 @@ class Params(ctypes.Structure):
                 ("lambda_", ctypes.c_float * MAX_SCALES),
                 ("rho", ctypes.c_float), ("max_iters", ctypes.c_int32),
                 ("tol", ctypes.c_float), ("check_every", ctypes.c_int32),
-                ("cycle_spin", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("cycle_spin", ctypes.c_int32), ("lowrank_min", ctypes.c_int32),
                 ("shift_seed", ctypes.c_uint64)]
 
 
@@ -44,7 +44,10 @@ class Result(ctypes.Structure):
                 ("primal_resid", ctypes.c_double),
                 ("live", ctypes.c_uint64 * MAX_SCALES),
                 ("sweeps", ctypes.c_uint64 * MAX_SCALES),
-                ("rank", ctypes.c_uint64 * MAX_SCALES)]
+                ("rank", ctypes.c_uint64 * MAX_SCALES),
+                ("certified", ctypes.c_uint64 * MAX_SCALES),
+                ("fail_coupling", ctypes.c_uint64 * MAX_SCALES),
+                ("fail_bound", ctypes.c_uint64 * MAX_SCALES)]
 
 
 EXPORTS = {
@@ -118,7 +121,7 @@ def cycle_shift(seed, k, i, m, n):
 
 
 def make_params(M, N, ladder, lam=None, rho=1.0, iters=100, tol=0.0, check_every=1,
-                cycle_spin=False, seed=0) -> Params:
+                cycle_spin=False, seed=0, lowrank_min=0) -> Params:
     if len(ladder) < 1 or len(ladder) > MAX_SCALES:
         raise ValueError("ladder must have 1..16 scales")
     p = Params()
@@ -132,6 +135,7 @@ def make_params(M, N, ladder, lam=None, rho=1.0, iters=100, tol=0.0, check_every
     p.check_every = int(check_every)
     p.cycle_spin = 1 if cycle_spin else 0
     p.shift_seed = int(seed) & ((1 << 64) - 1)
+    p.lowrank_min = int(lowrank_min)
     return p
 
 
@@ -149,7 +153,7 @@ class Solver:
     """One planned decomposition problem (msld_create). Reusable across solves."""
 
     def __init__(self, M, N, ladder, lam=None, rho=1.0, iters=100, tol=0.0, check_every=1,
-                 cycle_spin=False, seed=0, device=None):
+                 cycle_spin=False, seed=0, device=None, lowrank_min=0):
         import torch
         self._torch = torch
         lib = load()
@@ -159,7 +163,7 @@ class Solver:
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
             else torch.device(device)
         self.params = make_params(M, N, ladder, lam, rho, iters, tol, check_every,
-                                  cycle_spin, seed)
+                                  cycle_spin, seed, lowrank_min)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             st = lib.msld_create(ctypes.byref(self.params), _stream_ptr(torch, self.device),
@@ -204,7 +208,10 @@ class Solver:
             return out, None
         return out, {"iters": res.iters, "primal_resid": res.primal_resid,
                      "live": list(res.live)[:self.L], "sweeps": list(res.sweeps)[:self.L],
-                     "rank": list(res.rank)[:self.L]}
+                     "rank": list(res.rank)[:self.L],
+                     "certified": list(res.certified)[:self.L],
+                     "fail_coupling": list(res.fail_coupling)[:self.L],
+                     "fail_bound": list(res.fail_bound)[:self.L]}
 
     def _check_yz(self, Y, Z):
         torch = self._torch
@@ -235,7 +242,10 @@ class Solver:
         with self._torch.cuda.device(self.device):
             _check(self._lib.msld_stats(self._h, ctypes.byref(res)), "msld_stats")
         return {"iters": res.iters, "live": list(res.live)[:self.L],
-                "sweeps": list(res.sweeps)[:self.L], "rank": list(res.rank)[:self.L]}
+                "sweeps": list(res.sweeps)[:self.L], "rank": list(res.rank)[:self.L],
+                "certified": list(res.certified)[:self.L],
+                "fail_coupling": list(res.fail_coupling)[:self.L],
+                "fail_bound": list(res.fail_bound)[:self.L]}
 
     def profile_begin(self, max_iters):
         _check(self._lib.msld_profile_begin(self._h, int(max_iters)), "msld_profile_begin")
@@ -275,19 +285,20 @@ class Solver:
 
 
 def solve(Y, ladder, lam=None, rho=1.0, iters=100, tol=0.0, check_every=1,
-          cycle_spin=False, seed=0):
+          cycle_spin=False, seed=0, lowrank_min=0):
     """One-shot decomposition: returns (Z [L, M, N] device tensor, info dict)."""
     s = Solver(Y.shape[0], Y.shape[1], ladder, lam, rho, iters, tol, check_every,
-               cycle_spin, seed, device=Y.device)
+               cycle_spin, seed, device=Y.device, lowrank_min=lowrank_min)
     try:
         return s.solve(Y)
     finally:
         s.close()
 
 
-def bsvt(V, m, n, tau, shift=(0, 0)):
+def bsvt(V, m, n, tau, shift=(0, 0), lowrank_min=0):
     """One block-wise SVT call on V with m x n blocks and shift s (Sec. 7 and 9)."""
-    s = Solver(V.shape[0], V.shape[1], [(m, n)], iters=1, device=V.device)
+    s = Solver(V.shape[0], V.shape[1], [(m, n)], iters=1, device=V.device,
+               lowrank_min=lowrank_min)
     try:
         return s.bsvt(0, V.contiguous(), tau, shift)
     finally:

@@ -1,6 +1,7 @@
 // C-ABI runtime: parameter validation, per-scale planning, workspace arena and the
 // ADMM driver loop (Sec. 7 eq:admm with the random cycle spinning of Sec. 9).
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <cmath>
 #include <cstdlib>
@@ -45,7 +46,19 @@ struct Plan {
   size_t off_count[MSLD_MAX_SCALES], off_list[MSLD_MAX_SCALES], off_rowp[MSLD_MAX_SCALES],
       off_frop[MSLD_MAX_SCALES], off_stats[MSLD_MAX_SCALES], off_pA[MSLD_MAX_SCALES],
       off_pW[MSLD_MAX_SCALES], off_pflag[MSLD_MAX_SCALES], off_pg[MSLD_MAX_SCALES];
+  int use_lr[MSLD_MAX_SCALES];
+  size_t off_lr[MSLD_MAX_SCALES];   // start of the low-rank buffers of the scale
 };
+
+constexpr int kLRP = 16;  // subspace width of the certified low-rank path
+
+// A block fits the LDS Jacobi tier if B and W fit the LDS budget, one workgroup
+// covers all column pairs, and G lanes x 32 rows per lane cover the rows.
+bool lds_fits(int mb, int nb) {
+  int G = 1;
+  const int threads = lds_tier_threads(nb, mb, &G);
+  return lds_tier_bytes(mb, nb) <= kLdsTierMax && threads <= 1024 && G * 32 >= mb;
+}
 
 double lambda_default(int M, int N, int m, int n) {
   return std::sqrt((double)m) + std::sqrt((double)n) +
@@ -97,14 +110,17 @@ msld_status make_plan(const msld_params* p, Plan* pl) {
     const double lam = p->lambda[i] > 0.f ? (double)p->lambda[i] : lambda_default(M, N, m, n);
     pl->tau_default[i] = (float)(lam / (double)p->rho);
     const int nblk = g.P * g.Q;
+    const int lr_min = p->lowrank_min == 0 ? 128 : p->lowrank_min;
+    const bool lr = lr_min > 0 && g.nb >= lr_min && g.nb >= 4 * kLRP;
     int tier;
     if (m == 1 && n == 1) tier = TIER_1X1;
     else if (m == n && (m == 2 || m == 4 || m == 8)) tier = TIER_REG;
-    else if (lds_tier_bytes(g.mb, g.nb) <= kLdsTierMax) tier = TIER_LDS;
+    else if (!lr && lds_fits(g.mb, g.nb)) tier = TIER_LDS;
     else tier = TIER_PANEL;
+    pl->use_lr[i] = lr ? 1 : 0;
     pl->tier[i] = tier;
-    pl->off_stats[i] = take(8 * 4);
-    if (tier == TIER_1X1 || tier == TIER_REG) continue;
+    pl->off_stats[i] = take(8 * 8);
+    if (tier == TIER_1X1) continue;
     // stream plan
     StreamPlan& sp = pl->sp[i];
     int ws = kStreamFloats / m;
@@ -143,8 +159,14 @@ msld_status make_plan(const msld_params* p, Plan* pl) {
       pl->nbp[i] = nbp;
       pl->off_pA[i] = take(4 * (size_t)nblk * nbp * g.mb);
       pl->off_pW[i] = take(4 * (size_t)nblk * nbp * g.nb);
-      pl->off_pflag[i] = take(4 * 2 * (size_t)nblk);
+      pl->off_pflag[i] = take(4 * 4 * (size_t)nblk);
       pl->off_pg[i] = take(4 * (size_t)nblk * nbp);
+      if (lr) {
+        const size_t nb2 = (size_t)g.nb * g.nb;
+        const size_t per = 3 * nb2 + 4 * (size_t)g.nb * kLRP + (size_t)g.mb * kLRP +
+                           (size_t)kLRP * g.nb + 2 * kLRP + 8;
+        pl->off_lr[i] = take(4 * ((size_t)nblk * per + (size_t)g.nb * kLRP + 64 + nblk));
+      }
     }
   }
   pl->bytes = off;
@@ -162,6 +184,8 @@ struct msld_solver {
   bool failed;
   char* arena;
   double* host_res;  // pinned, 4 doubles
+  int* host_ints;    // pinned, 2 per scale
+  rocblas_handle blas;
   ScaleWork work[MSLD_MAX_SCALES];
   int k;              // next iteration index (drives the cycle-spin shifts)
   int cur;            // which D buffer holds the current D_i
@@ -268,12 +292,34 @@ msld_status msld_create(const msld_params* p, void* hip_stream, msld_solver** ou
     delete s;
     return MSLD_ENOMEM;
   }
+  if (hipHostMalloc(&s->host_ints, 2 * MSLD_MAX_SCALES * sizeof(int), hipHostMallocDefault) !=
+      hipSuccess) {
+    (void)hipHostFree(s->host_res);
+    (void)hipFree(s->arena);
+    delete s;
+    return MSLD_ENOMEM;
+  }
+  bool need_blas = false;
+  for (int i = 0; i < p->L; ++i) need_blas = need_blas || s->plan.use_lr[i];
+  s->blas = nullptr;
+  if (need_blas) {
+    if (rocblas_create_handle(&s->blas) != rocblas_status_success ||
+        rocblas_set_stream(s->blas, s->st) != rocblas_status_success ||
+        rocblas_set_atomics_mode(s->blas, rocblas_atomics_not_allowed) != rocblas_status_success) {
+      if (s->blas) (void)rocblas_destroy_handle(s->blas);
+      (void)hipHostFree(s->host_ints);
+      (void)hipHostFree(s->host_res);
+      (void)hipFree(s->arena);
+      delete s;
+      return MSLD_EDEVICE;
+    }
+  }
   const Plan& pl = s->plan;
   for (int i = 0; i < p->L; ++i) {
     ScaleWork& w = s->work[i];
     std::memset(&w, 0, sizeof(w));
     w.stats = reinterpret_cast<unsigned long long*>(s->arena + pl.off_stats[i]);
-    if (pl.tier[i] == TIER_LDS || pl.tier[i] == TIER_PANEL) {
+    if (pl.tier[i] != TIER_1X1) {
       w.live_count = reinterpret_cast<int*>(s->arena + pl.off_count[i]);
       w.live_list = reinterpret_cast<int*>(s->arena + pl.off_list[i]);
       if (!pl.sp[i].whole) {
@@ -289,6 +335,30 @@ msld_status msld_create(const msld_params* p, void* hip_stream, msld_solver** ou
       w.slots = pl.geom[i].P * pl.geom[i].Q;
       w.nbp = pl.nbp[i];
       w.pw = pl.pw[i];
+      w.hostInts = s->host_ints + 2 * i;
+      if (pl.use_lr[i]) {
+        const ScaleGeom& g = pl.geom[i];
+        const size_t nb2 = (size_t)g.nb * g.nb;
+        const size_t slots = (size_t)w.slots;
+        float* f = reinterpret_cast<float*>(s->arena + pl.off_lr[i]);
+        w.use_lr = 1;
+        w.blas = s->blas;
+        w.lrG = f; f += slots * nb2;
+        w.lrP = f; f += slots * nb2;
+        w.lrQ = f; f += slots * nb2;
+        w.lrY = f; f += slots * g.nb * kLRP;
+        w.lrX = f; f += slots * g.nb * kLRP;
+        w.lrW = f; f += slots * g.nb * kLRP;
+        w.lrV = f; f += slots * g.nb * kLRP;
+        w.lrC = f; f += slots * g.mb * kLRP;
+        w.lrT = f; f += slots * kLRP * g.nb;
+        w.lrSig = f; f += 2 * slots * kLRP;   // sigma, then the deflation mask
+        w.lrScal = f; f += slots * 8;
+        w.lrOm = f; f += (size_t)g.nb * kLRP;
+        w.lrCount = reinterpret_cast<int*>(f);
+        w.lrFall = w.lrCount + 64;
+        w.lds_fallback = lds_fits(g.mb, g.nb) ? 1 : 0;
+      }
     }
   }
   *out = s;
@@ -303,19 +373,21 @@ void msld_free(msld_solver* s) {
       (void)hipEventDestroy(s->prof_ev[e]);
     std::free(s->prof_ev);
   }
+  if (s->blas) (void)rocblas_destroy_handle(s->blas);
   if (s->arena) (void)hipFree(s->arena);
   if (s->host_res) (void)hipHostFree(s->host_res);
+  if (s->host_ints) (void)hipHostFree(s->host_ints);
   delete s;
 }
 
 int32_t msld_scale_tier(const msld_solver* s, int32_t scale) {
   if (!s || scale < 0 || scale >= s->p.L) return -1;
-  return s->plan.tier[scale];
+  return s->plan.use_lr[scale] ? 4 : s->plan.tier[scale];
 }
 
 static msld_status zero_stats(msld_solver* s) {
   for (int i = 0; i < s->p.L; ++i)
-    MSLD_TRY(s, hipMemsetAsync(s->work[i].stats, 0, 8 * 4, s->st));
+    MSLD_TRY(s, hipMemsetAsync(s->work[i].stats, 0, 8 * 8, s->st));
   return MSLD_OK;
 }
 
@@ -422,12 +494,15 @@ msld_status msld_stats(msld_solver* s, msld_result* info) {
   info->iters = s->k;
   info->primal_resid = -1.0;
   for (int i = 0; i < s->p.L; ++i) {
-    unsigned long long st4[4];
-    MSLD_TRY(s, hipMemcpyAsync(st4, s->work[i].stats, sizeof(st4), hipMemcpyDeviceToHost, s->st));
+    unsigned long long st8[8];
+    MSLD_TRY(s, hipMemcpyAsync(st8, s->work[i].stats, sizeof(st8), hipMemcpyDeviceToHost, s->st));
     MSLD_TRY(s, hipStreamSynchronize(s->st));
-    info->live[i] = st4[0];
-    info->sweeps[i] = st4[1];
-    info->rank[i] = st4[2];
+    info->live[i] = st8[0];
+    info->sweeps[i] = st8[1];
+    info->rank[i] = st8[2];
+    info->certified[i] = st8[3];
+    info->fail_coupling[i] = st8[4];
+    info->fail_bound[i] = st8[5];
   }
   return MSLD_OK;
 }

@@ -134,20 +134,30 @@ hipError_t launch_consensus(const float* Y, int64_t ldY, const float* Dcur, floa
   return hipGetLastError();
 }
 
+__global__ void k_zero_int(int* p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = 0;
+}
+
+__global__ void k_zero_ints(int* p, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
 // ------------------------------------------------------- register tier (B <= 8)
-// One lane owns one B x B block: gather (R_b after Shift_s), singular-value bound
-// test (Sec. 8), cyclic one-sided Jacobi SVD in registers, soft-threshold of the
-// singular values (eq:svt) and the rebuild, written back to the same wrapped
-// coordinates (R_b^T then Shift_{-s}).
+// Register tier, live blocks only: one lane per block of the live list built by the
+// stream pass. The block's V is read back from D' = -V (written by the stream pass),
+// decomposed by cyclic one-sided Jacobi in registers, thresholded (eq:svt) and
+// written back with the dual update.
 template <int B>
-__global__ void __launch_bounds__(256) k_tiny(
-    const float* __restrict__ Zin, const float* __restrict__ R, float* __restrict__ Zout,
-    float* __restrict__ Dout, int M, int N, int Q, int nblk, float tau, float tau2lim,
-    ShiftSpec sh, float jtol, int max_sweeps, unsigned long long* __restrict__ stats) {
+__global__ void __launch_bounds__(256) k_tiny_live(
+    float* __restrict__ Zout, float* __restrict__ Dout, int M, int N, int Q, float tau,
+    ShiftSpec sh, float jtol, int max_sweeps, const int* __restrict__ live_count,
+    const int* __restrict__ live_list, unsigned long long* __restrict__ stats) {
   int sr, sc;
   resolve_shift(sh, B, B, &sr, &sc);
+  const int count = *live_count;
   const int stride = gridDim.x * blockDim.x;
-  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nblk; b += stride) {
+  for (int it = blockIdx.x * blockDim.x + threadIdx.x; it < count; it += stride) {
+    const int b = live_list[it];
     const int p = b / Q;
     const int q = b - p * Q;
     int rows[B], cols[B];
@@ -156,46 +166,14 @@ __global__ void __launch_bounds__(256) k_tiny(
       rows[i] = wrap_add(p * B + i, sr, M);
       cols[i] = wrap_add(q * B + i, sc, N);
     }
-    float a[B][B];
+    float a[B][B], v0[B][B];
 #pragma unroll
     for (int i = 0; i < B; ++i)
 #pragma unroll
       for (int j = 0; j < B; ++j) {
-        const int64_t o = (int64_t)rows[i] * N + cols[j];
-        a[i][j] = Zin[o] + (R ? R[o] : 0.f);
+        v0[i][j] = -Dout[(int64_t)rows[i] * N + cols[j]];
+        a[i][j] = v0[i][j];
       }
-    // bound of Sec. 8: max_r sum_k |a_rk| (sum_j |a_jk|), and ||a||_F^2
-    float cs[B];
-    float fro = 0.f;
-#pragma unroll
-    for (int j = 0; j < B; ++j) {
-      float s = 0.f;
-#pragma unroll
-      for (int i = 0; i < B; ++i) {
-        s += fabsf(a[i][j]);
-        fro += a[i][j] * a[i][j];
-      }
-      cs[j] = s;
-    }
-    float bnd = 0.f;
-#pragma unroll
-    for (int i = 0; i < B; ++i) {
-      float s = 0.f;
-#pragma unroll
-      for (int j = 0; j < B; ++j) s += fabsf(a[i][j]) * cs[j];
-      bnd = fmaxf(bnd, s);
-    }
-    if (fminf(bnd, fro) <= tau2lim) {
-#pragma unroll
-      for (int i = 0; i < B; ++i)
-#pragma unroll
-        for (int j = 0; j < B; ++j) {
-          const int64_t o = (int64_t)rows[i] * N + cols[j];
-          Zout[o] = 0.f;
-          if (Dout) Dout[o] = -a[i][j];
-        }
-      continue;
-    }
     float w[B][B];
 #pragma unroll
     for (int i = 0; i < B; ++i)
@@ -256,18 +234,13 @@ __global__ void __launch_bounds__(256) k_tiny(
 #pragma unroll
         for (int j = 0; j < B; ++j) z += g[j] * a[i][j] * w[c2][j];
         const int64_t o = (int64_t)rows[i] * N + cols[c2];
-        const float v = Zin[o] + (R ? R[o] : 0.f);
         Zout[o] = z;
-        if (Dout) Dout[o] = 2.f * z - v;
+        Dout[o] = 2.f * z - v0[i][c2];
       }
     atomicAdd(&stats[0], 1ull);
     atomicAdd(&stats[1], (unsigned long long)sweeps);
     atomicAdd(&stats[2], (unsigned long long)rank);
   }
-}
-
-__global__ void k_zero_int(int* p) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = 0;
 }
 
 // ---------------------------------------------------------------- stream pass
@@ -436,10 +409,12 @@ __device__ __forceinline__ void rr_pair(int round, int k, int ncols, int* a, int
 
 // Hestenes one-sided Jacobi on the columns of A (column j at A + j*lda, `arows`
 // rows), accumulating the same rotations into W (column j at W + j*ldw, `wrows`
-// rows). Each pair is handled by G consecutive lanes that split the rows; the
-// three inner products are reduced across the G lanes with xor shuffles. Returns
-// the number of sweeps run. All threads of the workgroup must call it.
-template <int G>
+// rows). Each pair is handled by G consecutive lanes; lane t owns rows t + G*i,
+// i < RPL (G * RPL >= arows, wrows), cached in registers for the step. The three
+// inner products are reduced across the G lanes with xor shuffles. Returns the
+// number of sweeps run; *any_rot tells whether any rotation was applied. All threads
+// of the workgroup must call it.
+template <int G, int RPL>
 __device__ int jacobi_sweeps(float* A, int lda, int arows, float* W, int ldw, int wrows,
                              int ncols, int max_sweeps, float tol, int* any_rot) {
   const int tid = threadIdx.x;
@@ -447,22 +422,35 @@ __device__ int jacobi_sweeps(float* A, int lda, int arows, float* W, int ldw, in
   const int grp = tid / G;
   const int t = tid - grp * G;
   const bool act = grp < npairs;
+  const int n1 = ncols - 1;
+  // round-robin schedule: pa = 0 or 1 + (grp - 1 + rd) mod n1, pb = 1 + (ncols - 2 - grp + rd) mod n1
+  const int ia = grp - 1;
+  const int ib = ncols - 2 - grp;
   int sweeps = 0;
   *any_rot = 0;
   for (int sw = 0; sw < max_sweeps; ++sw) {
     int rotated = 0;
-    for (int rd = 0; rd < ncols - 1; ++rd) {
+    for (int rd = 0; rd < n1; ++rd) {
       float al = 0.f, be = 0.f, ga = 0.f;
+      float x[RPL], y[RPL];
       int pa = 0, pb = 0;
       if (act) {
-        rr_pair(rd, grp, ncols, &pa, &pb);
+        int ta = ia + rd;
+        if (ta >= n1) ta -= n1;
+        int tb = ib + rd;
+        if (tb >= n1) tb -= n1;
+        pa = (grp == 0) ? 0 : 1 + ta;
+        pb = 1 + tb;
         const float* ap = A + pa * lda;
         const float* aq = A + pb * lda;
-        for (int r = t; r < arows; r += G) {
-          const float x = ap[r], y = aq[r];
-          al += x * x;
-          be += y * y;
-          ga += x * y;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const int r = t + G * i;
+          x[i] = r < arows ? ap[r] : 0.f;
+          y[i] = r < arows ? aq[r] : 0.f;
+          al += x[i] * x[i];
+          be += y[i] * y[i];
+          ga += x[i] * y[i];
         }
       }
 #pragma unroll
@@ -481,17 +469,26 @@ __device__ int jacobi_sweeps(float* A, int lda, int arows, float* W, int ldw, in
         const float s = c * tt;
         float* ap = A + pa * lda;
         float* aq = A + pb * lda;
-        for (int r = t; r < arows; r += G) {
-          const float x = ap[r], y = aq[r];
-          ap[r] = c * x - s * y;
-          aq[r] = s * x + c * y;
-        }
         float* wp = W + pa * ldw;
         float* wq = W + pb * ldw;
-        for (int r = t; r < wrows; r += G) {
-          const float x = wp[r], y = wq[r];
-          wp[r] = c * x - s * y;
-          wq[r] = s * x + c * y;
+        float u[RPL], v[RPL];
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const int r = t + G * i;
+          u[i] = r < wrows ? wp[r] : 0.f;
+          v[i] = r < wrows ? wq[r] : 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const int r = t + G * i;
+          if (r < arows) {
+            ap[r] = c * x[i] - s * y[i];
+            aq[r] = s * x[i] + c * y[i];
+          }
+          if (r < wrows) {
+            wp[r] = c * u[i] - s * v[i];
+            wq[r] = s * u[i] + c * v[i];
+          }
         }
       }
       __syncthreads();
@@ -506,7 +503,7 @@ __device__ int jacobi_sweeps(float* A, int lda, int arows, float* W, int ldw, in
 // ------------------------------------------------------------- LDS tier
 // One workgroup per live block (persistent over the live list). The logical block
 // B (block or its transpose, mb >= nb) and the rotation matrix W live in LDS.
-template <int G>
+template <int G, int RPL>
 __global__ void __launch_bounds__(1024) k_svd_lds(
     float* __restrict__ Zout, float* __restrict__ Dout, ScaleGeom g, ShiftSpec sh,
     float tau, float jtol, int max_sweeps, const int* __restrict__ live_count,
@@ -549,7 +546,7 @@ __global__ void __launch_bounds__(1024) k_svd_lds(
     }
     __syncthreads();
     int any_rot;
-    const int sweeps = jacobi_sweeps<G>(A, lda, mb, W, ldw, nb, nbp, max_sweeps, jtol, &any_rot);
+    const int sweeps = jacobi_sweeps<G, RPL>(A, lda, mb, W, ldw, nb, nbp, max_sweeps, jtol, &any_rot);
     // singular values sigma_j = ||B w_j||, gains max(1 - tau/sigma_j, 0)  (eq:svt)
     for (int jj = tid; jj < nb; jj += nt) {
       float s2 = 0.f;
@@ -657,14 +654,11 @@ __global__ void k_panel_init(ScaleGeom g, const int* live_count, float* pA, floa
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < pad;
          e += (int64_t)gridDim.x * blockDim.x)
       A[(int64_t)nb * mb + e] = 0.f;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      pflag[2 * it] = 0;
-      pflag[2 * it + 1] = 0;
-    }
+    if (blockIdx.x == 0 && threadIdx.x < 4) pflag[4 * it + threadIdx.x] = 0;
   }
 }
 
-template <int G>
+template <int G, int PRPL>
 __global__ void __launch_bounds__(256) k_panel_round(ScaleGeom g, const int* live_count,
                                                      float* pA, float* pW, int* pflag, int nbp,
                                                      int pw, int round, float jtol) {
@@ -679,7 +673,7 @@ __global__ void __launch_bounds__(256) k_panel_round(ScaleGeom g, const int* liv
   int pa, pb;
   rr_pair(round, blockIdx.x, npan, &pa, &pb);
   for (int it = blockIdx.y; it < count; it += gridDim.y) {
-    if (pflag[2 * it + 1]) continue;  // converged: uniform across the workgroup
+    if (pflag[4 * it + 1]) continue;  // converged: uniform across the workgroup
     float* gA = pA + (int64_t)it * nbp * mb;
     float* gW = pW + (int64_t)it * nbp * nb;
     for (int e = threadIdx.x; e < 2 * pw * mb; e += blockDim.x) {
@@ -696,8 +690,8 @@ __global__ void __launch_bounds__(256) k_panel_round(ScaleGeom g, const int* liv
     }
     __syncthreads();
     int any_rot;
-    jacobi_sweeps<G>(A, lda, mb, W, ldw, nb, 2 * pw, 1, jtol, &any_rot);
-    if (any_rot && threadIdx.x == 0) atomicOr(&pflag[2 * it], 1);
+    jacobi_sweeps<G, PRPL>(A, lda, mb, W, ldw, nb, 2 * pw, 1, jtol, &any_rot);
+    if (any_rot && threadIdx.x == 0) atomicOr(&pflag[4 * it], 1);
     for (int e = threadIdx.x; e < 2 * pw * mb; e += blockDim.x) {
       const int jj = e / mb;
       const int r = e - jj * mb;
@@ -719,22 +713,24 @@ __global__ void k_panel_sweep_end(const int* live_count, int* pflag,
   const int count = *live_count;
   for (int it = blockIdx.x * blockDim.x + threadIdx.x; it < count;
        it += gridDim.x * blockDim.x) {
-    if (pflag[2 * it + 1]) continue;
+    if (pflag[4 * it + 1]) continue;
     atomicAdd(&stats[1], 1ull);                   // one more sweep ran on this block
-    if (!pflag[2 * it]) pflag[2 * it + 1] = 1;   // no pair above tolerance: converged
-    pflag[2 * it] = 0;
+    if (!pflag[4 * it]) pflag[4 * it + 1] = 1;   // no pair above tolerance: converged
+    pflag[4 * it] = 0;
   }
 }
 
 __global__ void __launch_bounds__(256) k_panel_gain(ScaleGeom g, const int* live_count,
                                                     const float* pA, float* pg, int nbp,
-                                                    float tau, unsigned long long* stats) {
+                                                    float tau, unsigned long long* stats,
+                                                    const int* pflag) {
   __shared__ int s_rank;
   const int mb = g.mb, nb = g.nb;
   const int count = *live_count;
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   for (int it = blockIdx.x; it < count; it += gridDim.x) {
+    if (pflag[4 * it + 2]) continue;  // handled by the certified low-rank path
     if (threadIdx.x == 0) s_rank = 0;
     __syncthreads();
     const float* A = pA + (int64_t)it * nbp * mb;
@@ -764,7 +760,7 @@ __global__ void __launch_bounds__(256) k_panel_rebuild(float* __restrict__ Zout,
                                                        ShiftSpec sh, const int* live_count,
                                                        const int* live_list, const float* pA,
                                                        const float* pW, const float* pg,
-                                                       int nbp) {
+                                                       int nbp, const int* pflag) {
   __shared__ int lcols[4096];
   __shared__ float lg[4096];
   __shared__ int s_k;
@@ -777,6 +773,7 @@ __global__ void __launch_bounds__(256) k_panel_rebuild(float* __restrict__ Zout,
   const int tj = blockIdx.x - ti * tilesj;
   const int i0 = ti * 32, j0 = tj * 32;
   for (int it = blockIdx.y; it < count; it += gridDim.y) {
+    if (pflag[4 * it + 2]) continue;  // handled by the certified low-rank path
     const int blk = live_list[it];
     const int p = blk / Q;
     const int q = blk - p * Q;
@@ -820,29 +817,46 @@ template <int G>
 static hipError_t launch_lds_g(int grid, int threads, size_t lds, float* Zout, float* Dout,
                                const ScaleGeom& g, const ShiftSpec& sh, float tau, float jtol,
                                int max_sweeps, ScaleWork& w, hipStream_t st) {
-  hipLaunchKernelGGL(k_svd_lds<G>, dim3(grid), dim3(threads), lds, st, Zout, Dout, g, sh, tau,
-                     jtol, max_sweeps, w.live_count, w.live_list, w.stats);
+  // rows per lane: G * RPL >= mb
+  const int need = (g.mb + G - 1) / G;
+  if (need <= 8)
+    hipLaunchKernelGGL((k_svd_lds<G, 8>), dim3(grid), dim3(threads), lds, st, Zout, Dout, g, sh,
+                       tau, jtol, max_sweeps, w.live_count, w.live_list, w.stats);
+  else if (need <= 32)
+    hipLaunchKernelGGL((k_svd_lds<G, 32>), dim3(grid), dim3(threads), lds, st, Zout, Dout, g, sh,
+                       tau, jtol, max_sweeps, w.live_count, w.live_list, w.stats);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 template <int G>
 static hipError_t launch_round_g(dim3 grid, size_t lds, const ScaleGeom& g, ScaleWork& w,
                                  int round, float jtol, hipStream_t st) {
-  hipLaunchKernelGGL(k_panel_round<G>, grid, dim3(256), lds, st, g, w.live_count, w.pA, w.pW,
-                     w.pflag, w.nbp, w.pw, round, jtol);
+  // rows per lane for the panel pair: G * PRPL >= max(mb, nb)
+  const int need = (g.mb + G - 1) / G;
+  if (need <= 8)
+    hipLaunchKernelGGL((k_panel_round<G, 8>), grid, dim3(256), lds, st, g, w.live_count, w.pA,
+                       w.pW, w.pflag, w.nbp, w.pw, round, jtol);
+  else if (need <= 32)
+    hipLaunchKernelGGL((k_panel_round<G, 32>), grid, dim3(256), lds, st, g, w.live_count, w.pA,
+                       w.pW, w.pflag, w.nbp, w.pw, round, jtol);
+  else if (need <= 128)
+    hipLaunchKernelGGL((k_panel_round<G, 128>), grid, dim3(256), lds, st, g, w.live_count, w.pA,
+                       w.pW, w.pflag, w.nbp, w.pw, round, jtol);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 int lds_tier_threads(int nb, int mb, int* G) {
   const int pairs = (nb + 1) / 2;
   int gg = 1;
-  while (gg * 2 <= 16 && gg * 2 * 8 <= mb) gg *= 2;
-  while (gg > 1 && pairs * gg > 1024) gg >>= 1;
+  while (gg * 8 < mb && gg < 32) gg *= 2;   // rows per lane stay <= 8
   *G = gg;
   int threads = pairs * gg;
   threads = ((threads + 63) / 64) * 64;
-  if (threads > 1024) threads = 1024;
-  return threads;
+  return threads;   // the plan only uses the LDS tier when this is <= 1024
 }
 
 size_t lds_tier_bytes(int mb, int nb) {
@@ -872,22 +886,6 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
                     (1.0 - 2.0 * (double)(g.m + g.n + 4) * (double)kEps);
   const float tau2lim = (float)tl;
   const int nblk = g.P * g.Q;
-  if (tier == TIER_REG) {
-    int blocks = (nblk + 255) / 256;
-    if (blocks > 65535) blocks = 65535;
-    if (g.m == 2)
-      hipLaunchKernelGGL(k_tiny<2>, dim3(blocks), dim3(256), 0, st, Zin, R, Zout, Dout, g.M, g.N,
-                         g.Q, nblk, tau, tau2lim, sh, jtol, max_sweeps, w.stats);
-    else if (g.m == 4)
-      hipLaunchKernelGGL(k_tiny<4>, dim3(blocks), dim3(256), 0, st, Zin, R, Zout, Dout, g.M, g.N,
-                         g.Q, nblk, tau, tau2lim, sh, jtol, max_sweeps, w.stats);
-    else
-      hipLaunchKernelGGL(k_tiny<8>, dim3(blocks), dim3(256), 0, st, Zin, R, Zout, Dout, g.M, g.N,
-                         g.Q, nblk, tau, tau2lim, sh, jtol, max_sweeps, w.stats);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    MSLD_EV(1); MSLD_EV(2); MSLD_EV(3); MSLD_EV(4);
-    return hipSuccess;
-  }
   // stream pass: speculative zero-output write + bound + live list
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, w.live_count);
   if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -903,14 +901,32 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
     }
   }
   MSLD_EV(1);
+  if (tier == TIER_REG) {
+    MSLD_EV(2);
+    int blocks = num_cus * 8;
+    if (blocks * 256 > nblk) blocks = (nblk + 255) / 256;
+    if (g.m == 2)
+      hipLaunchKernelGGL(k_tiny_live<2>, dim3(blocks), dim3(256), 0, st, Zout, Dout, g.M, g.N, g.Q,
+                         tau, sh, jtol, max_sweeps, w.live_count, w.live_list, w.stats);
+    else if (g.m == 4)
+      hipLaunchKernelGGL(k_tiny_live<4>, dim3(blocks), dim3(256), 0, st, Zout, Dout, g.M, g.N, g.Q,
+                         tau, sh, jtol, max_sweeps, w.live_count, w.live_list, w.stats);
+    else
+      hipLaunchKernelGGL(k_tiny_live<8>, dim3(blocks), dim3(256), 0, st, Zout, Dout, g.M, g.N, g.Q,
+                         tau, sh, jtol, max_sweeps, w.live_count, w.live_list, w.stats);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    MSLD_EV(3); MSLD_EV(4);
+    return hipSuccess;
+  }
   if (tier == TIER_LDS) {
     MSLD_EV(2);
     int G = 1;
     const int threads = lds_tier_threads(g.nb, g.mb, &G);
     const size_t lds = lds_tier_bytes(g.mb, g.nb);
     int per_cu = (int)(160 * 1024 / (lds + 1024));
+    const int by_waves = 32 / ((threads + 63) / 64);
+    if (per_cu > by_waves) per_cu = by_waves;
     if (per_cu < 1) per_cu = 1;
-    if (per_cu > 8) per_cu = 8;
     int grid = num_cus * per_cu;
     if (grid > nblk) grid = nblk;
     switch (G) {
@@ -918,14 +934,28 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
       case 2: e = launch_lds_g<2>(grid, threads, lds, Zout, Dout, g, sh, tau, jtol, max_sweeps, w, st); break;
       case 4: e = launch_lds_g<4>(grid, threads, lds, Zout, Dout, g, sh, tau, jtol, max_sweeps, w, st); break;
       case 8: e = launch_lds_g<8>(grid, threads, lds, Zout, Dout, g, sh, tau, jtol, max_sweeps, w, st); break;
-      default: e = launch_lds_g<16>(grid, threads, lds, Zout, Dout, g, sh, tau, jtol, max_sweeps, w, st); break;
+      case 16: e = launch_lds_g<16>(grid, threads, lds, Zout, Dout, g, sh, tau, jtol, max_sweeps, w, st); break;
+      default: e = launch_lds_g<32>(grid, threads, lds, Zout, Dout, g, sh, tau, jtol, max_sweeps, w, st); break;
     }
     if (e != hipSuccess) return e;
     MSLD_EV(3); MSLD_EV(4);
     return hipSuccess;
   }
   // panel tier
-  const int slots_y = w.slots < 65535 ? w.slots : 65535;
+  int slots_y = w.slots < 65535 ? w.slots : 65535;
+  int fallback = 1;
+  if (w.use_lr) {
+    if ((e = hipMemcpyAsync(w.hostInts, w.live_count, sizeof(int), hipMemcpyDeviceToHost, st)) !=
+        hipSuccess)
+      return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    const int count = w.hostInts[0];
+    if (count <= 0) {
+      MSLD_EV(2); MSLD_EV(3); MSLD_EV(4);
+      return hipSuccess;
+    }
+    slots_y = count < 65535 ? count : 65535;
+  }
   {
     const int tiles = ((g.m + 31) / 32) * ((g.n + 31) / 32);
     hipLaunchKernelGGL(k_panel_load, dim3(tiles, slots_y), dim3(256), 0, st, Dout, g, sh,
@@ -935,10 +965,45 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
                        w.pW, w.pflag, w.nbp);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
+  MSLD_EV(2);
+  if (w.use_lr) {
+    if ((e = run_lowrank(g, w, Zout, Dout, tau, sh, jtol, w.hostInts[0], &fallback, st)) !=
+        hipSuccess)
+      return e;
+  }
+  MSLD_EV(3);
+  if (fallback == 0) {
+    MSLD_EV(4);
+    return hipSuccess;
+  }
+  if (w.use_lr && w.lds_fallback) {
+    // blocks that failed the certificate and fit in LDS: one-sided Jacobi LDS tier
+    int G = 1;
+    const int threads = lds_tier_threads(g.nb, g.mb, &G);
+    const size_t ldsb = lds_tier_bytes(g.mb, g.nb);
+    int per_cu = (int)(160 * 1024 / (ldsb + 1024));
+    if (per_cu < 1) per_cu = 1;
+    if (per_cu > 8) per_cu = 8;
+    int grid = num_cus * per_cu;
+    if (grid > fallback) grid = fallback;
+    ScaleWork fw = w;
+    fw.live_count = w.lrCount;
+    fw.live_list = w.lrFall;
+    switch (G) {
+      case 1: e = launch_lds_g<1>(grid, threads, ldsb, Zout, Dout, g, sh, tau, jtol, max_sweeps, fw, st); break;
+      case 2: e = launch_lds_g<2>(grid, threads, ldsb, Zout, Dout, g, sh, tau, jtol, max_sweeps, fw, st); break;
+      case 4: e = launch_lds_g<4>(grid, threads, ldsb, Zout, Dout, g, sh, tau, jtol, max_sweeps, fw, st); break;
+      case 8: e = launch_lds_g<8>(grid, threads, ldsb, Zout, Dout, g, sh, tau, jtol, max_sweeps, fw, st); break;
+      case 16: e = launch_lds_g<16>(grid, threads, ldsb, Zout, Dout, g, sh, tau, jtol, max_sweeps, fw, st); break;
+      default: e = launch_lds_g<32>(grid, threads, ldsb, Zout, Dout, g, sh, tau, jtol, max_sweeps, fw, st); break;
+    }
+    if (e != hipSuccess) return e;
+    MSLD_EV(4);
+    return hipSuccess;
+  }
   const int npan = w.nbp / w.pw;
   const int G = 256 / w.pw;
   const size_t lds = (size_t)4 * 2 * w.pw * ((g.mb | 1) + (g.nb | 1));
-  MSLD_EV(2);
   for (int sweep = 0; sweep < panel_sweeps; ++sweep) {
     for (int rd = 0; rd < npan - 1; ++rd) {
       const dim3 grid(npan / 2, slots_y);
@@ -958,14 +1023,13 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
                        w.live_count, w.pflag, w.stats);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  MSLD_EV(3);
   hipLaunchKernelGGL(k_panel_gain, dim3(slots_y), dim3(256), 0, st, g, w.live_count, w.pA, w.pg,
-                     w.nbp, tau, w.stats);
+                     w.nbp, tau, w.stats, w.pflag);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   {
     const int tiles = ((g.m + 31) / 32) * ((g.n + 31) / 32);
     hipLaunchKernelGGL(k_panel_rebuild, dim3(tiles, slots_y), dim3(256), 0, st, Zout, Dout, g,
-                       sh, w.live_count, w.live_list, w.pA, w.pW, w.pg, w.nbp);
+                       sh, w.live_count, w.live_list, w.pA, w.pW, w.pg, w.nbp, w.pflag);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   MSLD_EV(4);

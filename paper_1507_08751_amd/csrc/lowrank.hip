@@ -1,0 +1,768 @@
+// Certified low-rank BlockSVT for large blocks.
+//
+// For a live block B (logical mb x nb, mb >= nb) the soft-threshold of eq:svt only
+// needs the singular triplets with sigma > tau. A subspace iteration on the Gram
+// G = B^T B finds an orthonormal X (nb x p); one-sided Jacobi on B X gives
+// B V_r = A_f (orthogonal columns a_l = sigma_l u_l) with V_r = X W. Let L be the
+// columns with sigma_l > tau (live), plus those with tau/2 < sigma_l <= tau whose own
+// coupling ||u_l^T B - sigma_l v_l^T|| is tiny, and E = B (I - V_L V_L^T). The result
+// Z = sum_{l in L} max(1 - tau/sigma_l, 0) a_l v_l^T is accepted only if
+//   (i)  sigma_max(E) <= tau, checked with the upper bound
+//        lambda_max(E^T E) <= tr(E^T E) * ||(E^T E / tr)^8||_F^(1/8), and
+//   (ii) ||U_L^T E||_F is below a small fraction of ||B||_F.
+// Then B0 = U_L S_L V_L^T + (I - U_L U_L^T) E decouples, SVT(B0) = Z (columns of L
+// below tau threshold to zero), and since the proximal map is non-expansive
+// ||SVT(B) - Z||_F <= ||B - B0||_F = ||U_L^T E||_F.
+// Blocks that fail either test go to the panel Jacobi path. The plain matrix
+// products (Gram, subspace products, squarings) are rocBLAS batched GEMMs; the
+// orthonormalisation, the small Jacobi SVD, the certificate and the rebuild are the
+// kernels below.
+#include <rocblas/rocblas.h>
+
+#include "msld_internal.h"
+
+namespace msld {
+
+static constexpr float kCertMargin = 2e-3f;    // relative margin on tau^2 for test (i)
+static constexpr float kCouplingTol = 1e-5f;   // test (ii): ||U_L^T E||_F <= tol ||B||_F
+
+__device__ __forceinline__ int wrap_add2(int base, int off, int mod) {
+  int v = base + off;
+  return v >= mod ? v - mod : v;
+}
+
+__device__ __forceinline__ float block_sum(float v, float* red) {
+  // 256-thread workgroup sum; red holds >= 4 floats
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  float s = 0.f;
+  const int nw = blockDim.x >> 6;
+  for (int w = 0; w < nw; ++w) s += red[w];
+  return s;
+}
+
+// Fixed +-1/sqrt(nb) probe matrix (column-major nb x p) from an integer hash.
+__global__ void k_lr_omega(float* Om, int nb, int p) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nb * p) return;
+  uint64_t z = mix64(0x243F6A8885A308D3ull + (uint64_t)e);
+  Om[e] = ((z >> 63) ? 1.f : -1.f) * rsqrtf((float)nb);
+}
+
+// tr(G) per slot.
+__global__ void __launch_bounds__(256) k_lr_trace(const float* G, int nb, int64_t strideG,
+                                                  float* scal, int which) {
+  __shared__ float red[8];
+  const int slot = blockIdx.x;
+  const float* g = G + (int64_t)slot * strideG;
+  float s = 0.f;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) s += g[(int64_t)i * nb + i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) scal[slot * 8 + which] = s;
+}
+
+// Orthonormalise the p columns of Y (nb x p, column-major) into X by classical
+// Gram-Schmidt with re-orthogonalisation until a pass keeps at least half the norm
+// (at most 4 passes); a column that stays numerically dependent is set to zero.
+template <int P>
+__global__ void __launch_bounds__(256) k_lr_orth(const float* Y, float* X, int nb,
+                                                 int64_t stride) {
+  extern __shared__ float sy[];  // P x nb
+  __shared__ float red[4 * P];
+  __shared__ float coef[P];
+  const int slot = blockIdx.x;
+  const float* y = Y + (int64_t)slot * stride;
+  float* x = X + (int64_t)slot * stride;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  for (int e = tid; e < nb * P; e += blockDim.x) sy[e] = y[e];
+  __syncthreads();
+  for (int j = 0; j < P; ++j) {
+    float* yj = sy + j * nb;
+    // original norm
+    float n0 = 0.f;
+    for (int r = tid; r < nb; r += blockDim.x) n0 += yj[r] * yj[r];
+    n0 = block_sum(n0, red);
+    float nprev = n0;
+    bool dependent = true;
+    for (int pass = 0; pass < 4 && j > 0; ++pass) {
+      float part[P];
+#pragma unroll
+      for (int i = 0; i < P; ++i) part[i] = 0.f;
+      for (int r = tid; r < nb; r += blockDim.x) {
+        const float v = yj[r];
+#pragma unroll
+        for (int i = 0; i < P; ++i)
+          if (i < j) part[i] += sy[i * nb + r] * v;
+      }
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        float v = part[i];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        part[i] = v;
+      }
+      __syncthreads();
+      if (lane == 0)
+        for (int i = 0; i < j; ++i) red[wv * P + i] = part[i];
+      __syncthreads();
+      if (tid < j) coef[tid] = red[tid] + red[P + tid] + red[2 * P + tid] + red[3 * P + tid];
+      __syncthreads();
+      for (int r = tid; r < nb; r += blockDim.x) {
+        float v = yj[r];
+        for (int i = 0; i < j; ++i) v -= coef[i] * sy[i * nb + r];
+        yj[r] = v;
+      }
+      __syncthreads();
+      float nn = 0.f;
+      for (int r = tid; r < nb; r += blockDim.x) nn += yj[r] * yj[r];
+      nn = block_sum(nn, red);
+      if (nn >= 0.25f * nprev) {   // norm kept above 1/2: orthogonal to working precision
+        dependent = false;
+        nprev = nn;
+        break;
+      }
+      nprev = nn;
+    }
+    if (j == 0) dependent = false;
+    const float nrm = sqrtf(nprev);
+    const bool keep = !dependent && nrm > 1e-30f && nprev > 1e-12f * n0;
+    const float inv = keep ? 1.f / nrm : 0.f;
+    for (int r = tid; r < nb; r += blockDim.x) yj[r] = yj[r] * inv;
+    __syncthreads();
+  }
+  for (int e = tid; e < nb * P; e += blockDim.x) x[e] = sy[e];
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Same orthonormalisation with one wave per slot and the columns held in registers
+// (lane l owns rows l + 64 r, r < RPL): no LDS and no workgroup barriers.
+template <int P, int RPL>
+__global__ void __launch_bounds__(256) k_lr_orth_w(const float* Y, float* X, int nb,
+                                                   int64_t stride, int count) {
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int slot = blockIdx.x * 4 + wv;
+  if (slot >= count) return;  // the whole wave leaves together
+  const float* y = Y + (int64_t)slot * stride;
+  float* x = X + (int64_t)slot * stride;
+  float v[P][RPL];
+#pragma unroll
+  for (int j = 0; j < P; ++j)
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int row = lane + 64 * r;
+      v[j][r] = row < nb ? y[j * nb + row] : 0.f;
+    }
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    float n0 = 0.f;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) n0 += v[j][r] * v[j][r];
+    n0 = wave_sum(n0);
+    float nprev = n0;
+    bool dependent = j > 0;
+    if (j > 0) {
+      for (int pass = 0; pass < 4; ++pass) {
+        float c[P];
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+          if (i < j) {
+            float sdot = 0.f;
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) sdot += v[i][r] * v[j][r];
+            c[i] = wave_sum(sdot);
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+          float t = v[j][r];
+#pragma unroll
+          for (int i = 0; i < P; ++i)
+            if (i < j) t -= c[i] * v[i][r];
+          v[j][r] = t;
+        }
+        float nn = 0.f;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) nn += v[j][r] * v[j][r];
+        nn = wave_sum(nn);
+        const bool done = nn >= 0.25f * nprev;
+        nprev = nn;
+        if (done) {
+          dependent = false;
+          break;
+        }
+      }
+    }
+    const float nrm = sqrtf(nprev);
+    const bool keep = !dependent && nrm > 1e-30f && nprev > 1e-12f * n0;
+    const float inv = keep ? 1.f / nrm : 0.f;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) v[j][r] *= inv;
+  }
+#pragma unroll
+  for (int j = 0; j < P; ++j)
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int row = lane + 64 * r;
+      if (row < nb) x[j * nb + row] = v[j][r];
+    }
+}
+
+// Jacobi core shared with the other tiers (defined in kernels.hip is not visible
+// here, so the pair order and the rotation are restated for this translation unit).
+__device__ __forceinline__ void lr_pair(int round, int k, int ncols, int* a, int* b) {
+  const int n1 = ncols - 1;
+  *a = (k == 0) ? 0 : 1 + (k - 1 + round) % n1;
+  *b = 1 + (ncols - 2 - k + round) % n1;
+}
+
+// One-sided Jacobi on C = B X (mb x p) in LDS with the p x p rotation W; writes the
+// rotated columns A_f back over C, sigma_l = ||a_l||, and V_r = X W (nb x p).
+template <int P>
+__global__ void __launch_bounds__(256) k_lr_jacobi(float* C, const float* X, float* Vr,
+                                                   float* sig, int mb, int nb, float tol,
+                                                   int max_sweeps) {
+  extern __shared__ float sm[];
+  const int lda = mb | 1;
+  constexpr int LDW = P | 1;
+  float* A = sm;                 // P x lda
+  float* W = A + P * lda;        // P x LDW
+  __shared__ int s_rot;
+  const int slot = blockIdx.x;
+  float* c = C + (int64_t)slot * mb * P;
+  const float* x = X + (int64_t)slot * nb * P;
+  float* vr = Vr + (int64_t)slot * nb * P;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < mb * P; e += blockDim.x) {
+    const int j = e / mb, r = e - j * mb;
+    A[j * lda + r] = c[e];
+  }
+  for (int e = tid; e < P * P; e += blockDim.x) {
+    const int j = e / P, r = e - j * P;
+    W[j * LDW + r] = (j == r) ? 1.f : 0.f;
+  }
+  __syncthreads();
+  constexpr int G = 256 / (P / 2);
+  const int grp = tid / G, t = tid - grp * G;
+  for (int sw = 0; sw < max_sweeps; ++sw) {
+    int rotated = 0;
+    for (int rd = 0; rd < P - 1; ++rd) {
+      int pa, pb;
+      lr_pair(rd, grp, P, &pa, &pb);
+      float al = 0.f, be = 0.f, ga = 0.f;
+      const float* ap = A + pa * lda;
+      const float* aq = A + pb * lda;
+      for (int r = t; r < mb; r += G) {
+        const float u = ap[r], v = aq[r];
+        al += u * u;
+        be += v * v;
+        ga += u * v;
+      }
+#pragma unroll
+      for (int o = G >> 1; o > 0; o >>= 1) {
+        al += __shfl_xor(al, o);
+        be += __shfl_xor(be, o);
+        ga += __shfl_xor(ga, o);
+      }
+      if (fabsf(ga) > tol * sqrtf(al) * sqrtf(be)) {
+        rotated = 1;
+        const float zeta = (be - al) / (2.f * ga);
+        const float tt = (fabsf(zeta) > 1e18f)
+                             ? 0.5f / zeta
+                             : copysignf(1.f, zeta) / (fabsf(zeta) + sqrtf(1.f + zeta * zeta));
+        const float cs = 1.f / sqrtf(1.f + tt * tt);
+        const float sn = cs * tt;
+        float* wap = A + pa * lda;
+        float* waq = A + pb * lda;
+        for (int r = t; r < mb; r += G) {
+          const float u = wap[r], v = waq[r];
+          wap[r] = cs * u - sn * v;
+          waq[r] = sn * u + cs * v;
+        }
+        float* wp = W + pa * LDW;
+        float* wq = W + pb * LDW;
+        for (int r = t; r < P; r += G) {
+          const float u = wp[r], v = wq[r];
+          wp[r] = cs * u - sn * v;
+          wq[r] = sn * u + cs * v;
+        }
+      }
+      __syncthreads();
+    }
+    if (!__syncthreads_or(rotated)) break;
+  }
+  (void)s_rot;
+  // sigma and write-back
+  for (int j = tid >> 6; j < P; j += blockDim.x >> 6) {
+    float s2 = 0.f;
+    for (int r = (tid & 63); r < mb; r += 64) s2 += A[j * lda + r] * A[j * lda + r];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o);
+    if ((tid & 63) == 0) sig[slot * P + j] = sqrtf(s2);
+  }
+  for (int e = tid; e < mb * P; e += blockDim.x) {
+    const int j = e / mb, r = e - j * mb;
+    c[e] = A[j * lda + r];
+  }
+  // V_r = X W
+  for (int e = tid; e < nb * P; e += blockDim.x) {
+    const int l = e / nb, row = e - l * nb;
+    float v = 0.f;
+#pragma unroll
+    for (int j = 0; j < P; ++j) v += x[j * nb + row] * W[l * LDW + j];
+    vr[e] = v;
+  }
+}
+
+// Per direction l: c_l^2 = || T_l / sigma_l - sigma_l v_l^T ||^2 with T = A_f^T B
+// (= ||u_l^T E||^2). Deflation mask: live (sigma > tau) always; near-live
+// (tau/2 < sigma <= tau) when c_l <= 0.3 tol ||B||_F. scal[1] = sum of c_l^2 over the mask.
+template <int P>
+__global__ void __launch_bounds__(256) k_lr_coupling(const float* T, const float* sig,
+                                                     const float* Vr, int nb, float tau,
+                                                     float tol, float* scal, float* mask) {
+  __shared__ float red[8];
+  __shared__ float cl[P];
+  const int slot = blockIdx.x;
+  const float* t = T + (int64_t)slot * P * nb;
+  const float* vr = Vr + (int64_t)slot * nb * P;
+  const float* sg = sig + slot * P;
+  for (int l = 0; l < P; ++l) {
+    const float s = sg[l];
+    if (!(s > 0.5f * tau)) {          // uniform branch: sg is shared by all threads
+      if (threadIdx.x == 0) cl[l] = 0.f;
+      continue;
+    }
+    const float inv = 1.f / s;
+    float acc = 0.f;
+    for (int cidx = threadIdx.x; cidx < nb; cidx += blockDim.x) {
+      const float d = t[(int64_t)cidx * P + l] * inv - s * vr[l * nb + cidx];
+      acc += d * d;
+    }
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) cl[l] = acc;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const float trG = scal[slot * 8 + 0];
+    const float near_lim = 0.09f * tol * tol * trG;   // (0.3 tol ||B||_F)^2
+    float c2 = 0.f;
+    for (int l = 0; l < P; ++l) {
+      const float s = sg[l];
+      const bool live = s > tau;
+      const bool near = !live && s > 0.5f * tau && cl[l] <= near_lim;
+      const bool in = live || near;
+      mask[slot * P + l] = in ? 1.f : 0.f;
+      if (in) c2 += cl[l];
+    }
+    scal[slot * 8 + 1] = c2;
+  }
+}
+
+// H = V_L^T (G V_L) and VH = V_L H (nb x p); non-live columns are masked to zero.
+template <int P>
+__global__ void __launch_bounds__(256) k_lr_vh(const float* Wg, const float* Vr,
+                                               const float* mask, float* VH, int nb) {
+  __shared__ float H[P * P];
+  __shared__ float red[8];
+  const int slot = blockIdx.x;
+  const float* w = Wg + (int64_t)slot * nb * P;
+  const float* v = Vr + (int64_t)slot * nb * P;
+  const float* mk = mask + slot * P;
+  float* vh = VH + (int64_t)slot * nb * P;
+  for (int l = 0; l < P; ++l)
+    for (int k = 0; k < P; ++k) {
+      // the mask is the same for every thread, so the branch is uniform
+      if (!(mk[l] > 0.f && mk[k] > 0.f)) {
+        if (threadIdx.x == 0) H[l * P + k] = 0.f;
+        continue;
+      }
+      float acc = 0.f;
+      for (int r = threadIdx.x; r < nb; r += blockDim.x) acc += v[l * nb + r] * w[k * nb + r];
+      acc = block_sum(acc, red);
+      if (threadIdx.x == 0) H[l * P + k] = acc;
+    }
+  __syncthreads();
+  for (int e = threadIdx.x; e < nb * P; e += blockDim.x) {
+    const int k = e / nb, r = e - k * nb;
+    float s = 0.f;
+#pragma unroll
+    for (int l = 0; l < P; ++l) s += v[l * nb + r] * H[l * P + k];
+    vh[e] = s;
+  }
+}
+
+// E^T E = G - W_L V_L^T - V_L W_L^T + V_L H V_L^T (W = G V_r), written to Pm.
+template <int P>
+__global__ void __launch_bounds__(256) k_lr_ge(const float* G, const float* Wg, const float* Vr,
+                                               const float* VH, const float* mask, float* Pm,
+                                               int nb, float* part) {
+  __shared__ float lv[P];
+  __shared__ float red[8];
+  const int slot = blockIdx.y;
+  const float* g = G + (int64_t)slot * nb * nb;
+  const float* w = Wg + (int64_t)slot * nb * P;
+  const float* v = Vr + (int64_t)slot * nb * P;
+  const float* vh = VH + (int64_t)slot * nb * P;
+  float* pm = Pm + (int64_t)slot * nb * nb;
+  if (threadIdx.x < P) lv[threadIdx.x] = mask[slot * P + threadIdx.x];
+  __syncthreads();
+  const int64_t total = (int64_t)nb * nb;
+  float tr = 0.f, f2 = 0.f;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(e / nb), i = (int)(e - (int64_t)j * nb);  // column-major (i, j)
+    float s = g[e];
+#pragma unroll
+    for (int l = 0; l < P; ++l) {
+      if (lv[l] == 0.f) continue;
+      s -= w[l * nb + i] * v[l * nb + j] + v[l * nb + i] * w[l * nb + j];
+      s += vh[l * nb + i] * v[l * nb + j];
+    }
+    pm[e] = s;
+    if (i == j) tr += s;
+    f2 += s * s;
+  }
+  tr = block_sum(tr, red);
+  f2 = block_sum(f2, red);
+  if (threadIdx.x == 0) {
+    part[((int64_t)slot * gridDim.x + blockIdx.x) * 2] = tr;
+    part[((int64_t)slot * gridDim.x + blockIdx.x) * 2 + 1] = f2;
+  }
+}
+
+// Reduce the per-tile partials of k_lr_ge in a fixed order: scal[2] = tr(E^T E),
+// scal[4] = ||E^T E||_F / tr(E^T E) (stage-0 bound factor).
+__global__ void k_lr_ge_reduce(const float* part, int tiles, int count, float* scal) {
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= count) return;
+  float tr = 0.f, f2 = 0.f;
+  for (int t = 0; t < tiles; ++t) {
+    tr += part[((int64_t)slot * tiles + t) * 2];
+    f2 += part[((int64_t)slot * tiles + t) * 2 + 1];
+  }
+  scal[slot * 8 + 2] = tr;
+  scal[slot * 8 + 4] = tr > 0.f ? sqrtf(f2) / tr : 0.f;
+}
+
+// Scale each slot's nb x nb matrix by 1 / scal[which] (0 stays 0).
+__global__ void k_lr_scale(float* Pm, int nb, const float* scal, int which) {
+  const int slot = blockIdx.y;
+  const float tr = scal[slot * 8 + which];
+  const float inv = tr > 0.f ? 1.f / tr : 0.f;
+  float* pm = Pm + (int64_t)slot * nb * nb;
+  const int64_t total = (int64_t)nb * nb;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x)
+    pm[e] *= inv;
+}
+
+__global__ void __launch_bounds__(256) k_lr_frob(const float* Pm, int nb, float* scal,
+                                                 int which) {
+  __shared__ float red[8];
+  const int slot = blockIdx.x;
+  const float* pm = Pm + (int64_t)slot * nb * nb;
+  const int64_t total = (int64_t)nb * nb;
+  float acc = 0.f;
+  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) acc += pm[e] * pm[e];
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) scal[slot * 8 + which] = sqrtf(acc);
+}
+
+// ||Pm||_F per slot from per-tile partials (fixed reduction order).
+__global__ void __launch_bounds__(256) k_lr_frob_part(const float* Pm, int nb, float* part) {
+  __shared__ float red[8];
+  const int slot = blockIdx.y;
+  const float* pm = Pm + (int64_t)slot * nb * nb;
+  const int64_t total = (int64_t)nb * nb;
+  float acc = 0.f;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x)
+    acc += pm[e] * pm[e];
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) part[(int64_t)slot * gridDim.x + blockIdx.x] = acc;
+}
+
+__global__ void k_lr_frob_reduce(const float* part, int tiles, int count, float* scal,
+                                 int which) {
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= count) return;
+  float f2 = 0.f;
+  for (int t = 0; t < tiles; ++t) f2 += part[(int64_t)slot * tiles + t];
+  scal[slot * 8 + which] = sqrtf(f2);
+}
+
+// Certificate decision; flags per slot: [1] converged (panel rounds skip it),
+// [2] handled here (panel gain / rebuild skip it), [3] undecided after stage 0.
+// Stage 0 uses the Frobenius bound lambda_max(E^T E) <= ||E^T E||_F; slots it cannot
+// certify (but whose coupling passes) wait for stage 1, which uses the bound from the
+// eighth power. Fallback slots are listed (block ids) for the LDS Jacobi tier.
+__device__ __forceinline__ void lr_certify(int slot, const float* sig, float tau, int* pflag,
+                                           unsigned long long* stats) {
+  pflag[4 * slot + 1] = 1;
+  pflag[4 * slot + 2] = 1;
+  int k = 0;
+  for (int l = 0; l < 16; ++l) k += sig[slot * 16 + l] > tau;
+  atomicAdd(&stats[0], 1ull);
+  atomicAdd(&stats[2], (unsigned long long)k);
+  atomicAdd(&stats[3], 1ull);
+}
+
+__device__ __forceinline__ void lr_fallback(int slot, int* pflag, int* counts, int* fall,
+                                            const int* live_list) {
+  pflag[4 * slot + 2] = 0;
+  const int f = atomicAdd(&counts[0], 1);
+  fall[f] = live_list[slot];
+}
+
+__global__ void k_lr_decide(int count, const float* scal, const float* sig, float tau,
+                            int* pflag, int* counts, int* fall, const int* live_list,
+                            unsigned long long* stats, int stage, int power) {
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= count) return;
+  const float* sc = scal + slot * 8;
+  const float trG = sc[0], c2 = sc[1], trE = sc[2];
+  const float lim = tau * tau * (1.f - kCertMargin);
+  if (stage == 0) {
+    pflag[4 * slot + 3] = 0;
+    const bool c_ok = c2 <= kCouplingTol * kCouplingTol * trG && isfinite(c2) && isfinite(trE);
+    if (!c_ok) {
+      lr_fallback(slot, pflag, counts, fall, live_list);
+      atomicAdd(&stats[4], 1ull);
+      return;
+    }
+    const float b0 = trE > 0.f ? trE * sc[4] : 0.f;
+    if (b0 <= lim) {
+      lr_certify(slot, sig, tau, pflag, stats);
+    } else {
+      pflag[4 * slot + 3] = 1;
+      atomicAdd(&counts[1], 1);
+    }
+  } else {
+    // sc[3] = ||(E^T E / tr)^power||_F, so lambda_max <= tr * sc[3]^(1/power)
+    if (!pflag[4 * slot + 3]) return;
+    const float bp = trE > 0.f ? trE * powf(sc[3], 1.f / (float)power) : 0.f;
+    if (bp <= lim && isfinite(bp)) {
+      pflag[4 * slot + 3] = 0;
+      lr_certify(slot, sig, tau, pflag, stats);
+    } else if (stage == 2) {
+      pflag[4 * slot + 3] = 0;
+      lr_fallback(slot, pflag, counts, fall, live_list);
+      atomicAdd(&stats[5], 1ull);
+    } else {
+      atomicAdd(&counts[1], 1);   // still undecided after this stage
+    }
+  }
+}
+
+// Z = sum_{l in L} (1 - tau/sigma_l) a_l v_l^T for certified slots, scattered to the
+// shifted block coordinates with the dual update D' = 2 Z' - V.
+template <int P>
+__global__ void __launch_bounds__(256) k_lr_rebuild(float* __restrict__ Zout,
+                                                    float* __restrict__ Dout, ScaleGeom g,
+                                                    ShiftSpec sh, const int* live_list,
+                                                    const int* pflag, const float* Af,
+                                                    const float* Vr, const float* sig,
+                                                    float tau) {
+  __shared__ float gl[P];
+  const int M = g.M, N = g.N, m = g.m, n = g.n, Q = g.Q, mb = g.mb, nb = g.nb;
+  int sr, sc;
+  resolve_shift(sh, m, n, &sr, &sc);
+  const int slot = blockIdx.y;
+  if (!pflag[4 * slot + 2]) return;
+  if (threadIdx.x < P) {
+    const float s = sig[slot * P + threadIdx.x];
+    gl[threadIdx.x] = s > tau ? 1.f - tau / s : 0.f;
+  }
+  __syncthreads();
+  const int blk = live_list[slot];
+  const int p = blk / Q, q = blk - p * Q;
+  const float* af = Af + (int64_t)slot * mb * P;
+  const float* vr = Vr + (int64_t)slot * nb * P;
+  const int tilesj = (n + 31) / 32;
+  const int ti = blockIdx.x / tilesj, tj = blockIdx.x - (blockIdx.x / tilesj) * tilesj;
+  for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) {
+    const int i = ti * 32 + (e >> 5), j = tj * 32 + (e & 31);
+    if (i >= m || j >= n) continue;
+    const int r = g.trans ? j : i;
+    const int c = g.trans ? i : j;
+    float z = 0.f;
+#pragma unroll
+    for (int l = 0; l < P; ++l)
+      if (gl[l] > 0.f) z += gl[l] * af[l * mb + r] * vr[l * nb + c];
+    const int64_t o = (int64_t)wrap_add2(p * m + i, sr, M) * N + wrap_add2(q * n + j, sc, N);
+    const float v = -Dout[o];
+    Zout[o] = z;
+    Dout[o] = 2.f * z - v;
+  }
+}
+
+// ------------------------------------------------------------------ driver
+static hipError_t gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m,
+                       int n, int k, const float* A, int lda, int64_t sa, const float* B, int ldb,
+                       int64_t sb, float* C, int ldc, int64_t sc, int batch) {
+  const float one = 1.f, zero = 0.f;
+  rocblas_status s = rocblas_sgemm_strided_batched(h, ta, tb, m, n, k, &one, A, lda, sa, B, ldb,
+                                                   sb, &zero, C, ldc, sc, batch);
+  return s == rocblas_status_success ? hipSuccess : hipErrorLaunchFailure;
+}
+
+hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout, float tau,
+                       const ShiftSpec& sh, float jtol, int count, int* fallback_host,
+                       hipStream_t st) {
+  constexpr int P = 16;
+  hipError_t e;
+  rocblas_handle h = reinterpret_cast<rocblas_handle>(w.blas);
+  const int mb = g.mb, nb = g.nb;
+  const int64_t sB = (int64_t)w.nbp * mb;   // pA slot stride
+  const int64_t sG = (int64_t)nb * nb;
+  const int64_t sY = (int64_t)nb * P;
+  const int64_t sC = (int64_t)mb * P;
+  hipLaunchKernelGGL(k_lr_omega, dim3((nb * P + 255) / 256), dim3(256), 0, st, w.lrOm, nb, P);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, w.lrCount, 2);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // G = B^T B
+  if ((e = gemm(h, rocblas_operation_transpose, rocblas_operation_none, nb, nb, mb, w.pA, mb, sB,
+                w.pA, mb, sB, w.lrG, nb, sG, count)) != hipSuccess)
+    return e;
+  hipLaunchKernelGGL(k_lr_trace, dim3(count), dim3(256), 0, st, w.lrG, nb, sG, w.lrScal, 0);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // subspace iteration: X0 = orth(G Omega), then X <- orth(G (G X)) three times
+  // (seven products by G in total; orthonormalising every second product keeps every
+  // direction with sigma > tau / 2 representable while (2 sigma_1 / tau)^4 << 1/eps;
+  // an insufficiently converged subspace shows up in the coupling test)
+  const int q = 4;
+  for (int it = 0; it < q; ++it) {
+    if (it == 0) {
+      if ((e = gemm(h, rocblas_operation_none, rocblas_operation_none, nb, P, nb, w.lrG, nb, sG,
+                    w.lrOm, nb, 0, w.lrY, nb, sY, count)) != hipSuccess)
+        return e;
+    } else {
+      if ((e = gemm(h, rocblas_operation_none, rocblas_operation_none, nb, P, nb, w.lrG, nb, sG,
+                    w.lrX, nb, sY, w.lrW, nb, sY, count)) != hipSuccess)
+        return e;
+      if ((e = gemm(h, rocblas_operation_none, rocblas_operation_none, nb, P, nb, w.lrG, nb, sG,
+                    w.lrW, nb, sY, w.lrY, nb, sY, count)) != hipSuccess)
+        return e;
+    }
+    if (nb <= 128)
+      hipLaunchKernelGGL((k_lr_orth_w<P, 2>), dim3((count + 3) / 4), dim3(256), 0, st, w.lrY,
+                         w.lrX, nb, sY, count);
+    else if (nb <= 256)
+      hipLaunchKernelGGL((k_lr_orth_w<P, 4>), dim3((count + 3) / 4), dim3(256), 0, st, w.lrY,
+                         w.lrX, nb, sY, count);
+    else if (nb <= 512)
+      hipLaunchKernelGGL((k_lr_orth_w<P, 8>), dim3((count + 3) / 4), dim3(256), 0, st, w.lrY,
+                         w.lrX, nb, sY, count);
+    else
+      hipLaunchKernelGGL(k_lr_orth<P>, dim3(count), dim3(256), (size_t)4 * nb * P, st, w.lrY,
+                         w.lrX, nb, sY);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  // C = B X, Jacobi on C
+  if ((e = gemm(h, rocblas_operation_none, rocblas_operation_none, mb, P, nb, w.pA, mb, sB,
+                w.lrX, nb, sY, w.lrC, mb, sC, count)) != hipSuccess)
+    return e;
+  {
+    const size_t lds = (size_t)4 * (P * (mb | 1) + P * (P | 1));
+    // tighter rotation threshold than the other tiers: the reduced problem is only
+    // p columns wide and its residual orthogonality enters the coupling test
+    const float rr_tol = 5.9604645e-8f * sqrtf((float)mb);
+    (void)jtol;
+    hipLaunchKernelGGL(k_lr_jacobi<P>, dim3(count), dim3(256), lds, st, w.lrC, w.lrX, w.lrV,
+                       w.lrSig, mb, nb, rr_tol, 40);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  // coupling: T = A_f^T B (p x nb)
+  if ((e = gemm(h, rocblas_operation_transpose, rocblas_operation_none, P, nb, mb, w.lrC, mb, sC,
+                w.pA, mb, sB, w.lrT, P, (int64_t)P * nb, count)) != hipSuccess)
+    return e;
+  float* mask = w.lrSig + (size_t)w.slots * P;   // second half of the sigma buffer
+  hipLaunchKernelGGL(k_lr_coupling<P>, dim3(count), dim3(256), 0, st, w.lrT, w.lrSig, w.lrV, nb,
+                     tau, kCouplingTol, w.lrScal, mask);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // E^T E and its power bound
+  if ((e = gemm(h, rocblas_operation_none, rocblas_operation_none, nb, P, nb, w.lrG, nb, sG,
+                w.lrV, nb, sY, w.lrW, nb, sY, count)) != hipSuccess)
+    return e;
+  hipLaunchKernelGGL(k_lr_vh<P>, dim3(count), dim3(256), 0, st, w.lrW, w.lrV, mask, w.lrY, nb);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int tiles = (int)((sG + 255) / 256 < 64 ? (sG + 255) / 256 : 64);
+  hipLaunchKernelGGL(k_lr_ge<P>, dim3(tiles, count), dim3(256), 0, st, w.lrG, w.lrW, w.lrV,
+                     w.lrY, mask, w.lrP, nb, w.lrQ);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // stage 0: Frobenius bound of E^T E (partials were written to lrQ)
+  hipLaunchKernelGGL(k_lr_ge_reduce, dim3((count + 255) / 256), dim3(256), 0, st, w.lrQ, tiles,
+                     count, w.lrScal);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_lr_decide, dim3((count + 255) / 256), dim3(256), 0, st, count, w.lrScal,
+                     w.lrSig, tau, w.pflag, w.lrCount, w.lrFall, w.live_list, w.stats, 0, 1);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(w.hostInts + 1, w.lrCount + 1, sizeof(int), hipMemcpyDeviceToHost,
+                          st)) != hipSuccess)
+    return e;
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+  if (w.hostInts[1] > 0) {
+    // stage 1: square of E^T E / tr(E^T E); stage 2: its fourth power (eighth in all)
+    hipLaunchKernelGGL(k_lr_scale, dim3(tiles, count), dim3(256), 0, st, w.lrP, nb, w.lrScal, 2);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    float* a = w.lrP;
+    float* b = w.lrQ;
+    int power = 1;
+    for (int stage = 1; stage <= 2; ++stage) {
+      const int nsq = stage == 1 ? 1 : 2;
+      for (int s2 = 0; s2 < nsq; ++s2) {
+        if ((e = gemm(h, rocblas_operation_none, rocblas_operation_none, nb, nb, nb, a, nb, sG, a,
+                      nb, sG, b, nb, sG, count)) != hipSuccess)
+          return e;
+        float* t = a;
+        a = b;
+        b = t;
+        power *= 2;
+      }
+      const int ftiles = tiles;
+      hipLaunchKernelGGL(k_lr_frob_part, dim3(ftiles, count), dim3(256), 0, st, a, nb, w.lrT);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_lr_frob_reduce, dim3((count + 255) / 256), dim3(256), 0, st, w.lrT,
+                         ftiles, count, w.lrScal, 3);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, w.lrCount + 1, 1);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_lr_decide, dim3((count + 255) / 256), dim3(256), 0, st, count,
+                         w.lrScal, w.lrSig, tau, w.pflag, w.lrCount, w.lrFall, w.live_list,
+                         w.stats, stage, power);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      if (stage == 1) {
+        if ((e = hipMemcpyAsync(w.hostInts + 1, w.lrCount + 1, sizeof(int),
+                                hipMemcpyDeviceToHost, st)) != hipSuccess)
+          return e;
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+        if (w.hostInts[1] == 0) break;
+      }
+    }
+  }
+  {
+    const int tl = ((g.m + 31) / 32) * ((g.n + 31) / 32);
+    hipLaunchKernelGGL(k_lr_rebuild<P>, dim3(tl, count), dim3(256), 0, st, Zout, Dout, g, sh,
+                       w.live_list, w.pflag, w.lrC, w.lrV, w.lrSig, tau);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if ((e = hipMemcpyAsync(w.hostInts + 1, w.lrCount, sizeof(int), hipMemcpyDeviceToHost, st)) !=
+      hipSuccess)
+    return e;
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+  *fallback_host = w.hostInts[1];
+  return hipSuccess;
+}
+
+}  // namespace msld

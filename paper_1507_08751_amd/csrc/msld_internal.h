@@ -66,7 +66,8 @@ struct ScaleWork {
   int* live_list;       // [P*Q] block ids
   float* rowpart;       // [P*Q*spb*m] partial row sums (strips narrower than a block)
   float* fropart;       // [P*Q*spb] partial squared Frobenius norms
-  unsigned long long* stats;  // [4]: live blocks, sweeps, output rank, spare
+  unsigned long long* stats;  // [8]: live blocks, sweeps, output rank, certified,
+                              //      coupling failures, bound failures, spare x2
   // panel tier
   float* pA;            // [slots][nbp][mb] column-major logical block
   float* pW;            // [slots][nbp][nb] column-major right rotations
@@ -75,6 +76,25 @@ struct ScaleWork {
   int slots;
   int nbp;              // nb padded to a multiple of 2 * panel width
   int pw;               // panel width
+  // certified low-rank path (lowrank.hip); per slot unless noted
+  int use_lr;
+  void* blas;           // rocblas_handle
+  float* lrG;           // [slots][nb*nb] Gram B^T B
+  float* lrP;           // [slots][nb*nb] scratch for E^T E and its squarings
+  float* lrQ;           // [slots][nb*nb]
+  float* lrY;           // [slots][nb*p]
+  float* lrX;           // [slots][nb*p] orthonormal subspace basis
+  float* lrC;           // [slots][mb*p] B X, then the rotated columns a_l
+  float* lrT;           // [slots][p*nb] A_f^T B
+  float* lrW;           // [slots][nb*p] G V_r
+  float* lrV;           // [slots][nb*p] right vectors V_r
+  float* lrSig;         // [slots][p]
+  float* lrScal;        // [slots][8]
+  float* lrOm;          // [nb*p] probe matrix
+  int* lrCount;         // [4] device counters: fallback, undecided
+  int* lrFall;          // [slots] block ids that fall back to Jacobi
+  int lds_fallback;     // 1: fallback blocks fit the LDS Jacobi tier
+  int* hostInts;        // pinned host ints [2]
 };
 
 struct StreamPlan {
@@ -97,6 +117,10 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
                         float tau, const ShiftSpec& sh, float jtol, int max_sweeps,
                         int panel_sweeps, int num_cus, hipStream_t st, hipEvent_t* ev,
                         int* round_launches);
+hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout, float tau,
+                       const ShiftSpec& sh, float jtol, int count, int* fallback_host,
+                       hipStream_t st);
+__global__ void k_zero_ints(int* p, int n);
 hipError_t launch_resid(const float* Dold, const float* R, const float* Z, int M, int N,
                         int L, double* partial, int nparts, double* out, hipStream_t st);
 hipError_t launch_sumsq(const float* Y, int64_t ldY, int M, int N, double* partial,

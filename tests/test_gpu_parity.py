@@ -67,11 +67,26 @@ BSVT_CASES = [
     (512, 512, 512, 512),
     (1024, 1024, 512, 512),
     (128, 512, 128, 512),
+    (512, 64, 256, 16),      # tall LDS-tier block, 32 lanes per pair
+    (1024, 64, 512, 32),     # 32 rows per lane
+    (64, 1024, 32, 512),     # the same, transposed
 ]
+
+
+LOWRANK_CASES = [c for c in BSVT_CASES if min(c[2], c[3]) >= 64] + [(256, 384, 64, 64)]
 
 
 @pytest.mark.parametrize("M,N,m,n", BSVT_CASES)
 def test_bsvt_call_parity(lib, M, N, m, n):
+    _bsvt_case(lib, M, N, m, n, lowrank_min=-1)
+
+
+@pytest.mark.parametrize("M,N,m,n", LOWRANK_CASES)
+def test_bsvt_call_parity_lowrank(lib, M, N, m, n):
+    _bsvt_case(lib, M, N, m, n, lowrank_min=64)
+
+
+def _bsvt_case(lib, M, N, m, n, lowrank_min):
     seed = M * 7 + N * 3 + m * 11 + n
     V = planted_input(M, N, m, n, seed)
     rng = np.random.default_rng(seed)
@@ -79,17 +94,52 @@ def test_bsvt_call_parity(lib, M, N, m, n):
     sig = block_sigmas(V, m, n, s)
     tau = float(np.quantile(sig[:, 0], 0.5)) * 0.9 + 1e-3
     ref = O.cycle_spun_bsvt(V.astype(np.float64), m, n, tau, s)
-    solver = lib.Solver(M, N, [(m, n)], iters=1)
+    solver = lib.Solver(M, N, [(m, n)], iters=1, lowrank_min=lowrank_min)
     print(f"case {M}x{N} block {m}x{n} tier={lib.TIERS[solver.tier(0)]} shift={s} tau={tau:.4f}",
           flush=True)
     Vd = torch.from_numpy(V).cuda()
     Z = solver.bsvt(0, Vd, tau, s)
     torch.cuda.synchronize()
+    st = solver.stats()
     Zg = Z.cpu().numpy()
     err = rel_err(Zg, ref, np.linalg.norm(V))
     live = int((sig[:, 0] > tau).sum())
-    print(f"  rel err {err:.2e}  blocks above tau {live}/{sig.shape[0]}", flush=True)
+    print(f"  rel err {err:.2e}  blocks above tau {live}/{sig.shape[0]}  decomposed {st['live']} "
+          f"certified {st['certified']}", flush=True)
     assert err <= 1e-4
+    solver.close()
+
+
+@pytest.mark.parametrize("M,N,m,n", [(512, 512, 128, 128), (1024, 1024, 512, 512),
+                                     (256, 1024, 256, 512), (384, 256, 64, 64)])
+def test_lowrank_path_certifies_low_rank_blocks(lib, M, N, m, n):
+    """Blocks that are rank <= 3 plus small noise (all noise singular values far below
+    tau) must be finished by the certified low-rank path, not by the Jacobi fallback,
+    and still match the oracle to 1e-4."""
+    rng = np.random.default_rng(M + N + m)
+    s = (int(rng.integers(0, m)), int(rng.integers(0, n)))
+    V64 = 1e-3 * rng.standard_normal((M, N))
+    P, Q = M // m, N // n
+    for p in range(P):
+        for q in range(Q):
+            r = int(rng.integers(0, 4))
+            blk = rng.standard_normal((m, r)) @ rng.standard_normal((r, n)) if r else 0.0
+            rows = (p * m + s[0] + np.arange(m)) % M
+            cols = (q * n + s[1] + np.arange(n)) % N
+            V64[np.ix_(rows, cols)] += blk
+    V = V64.astype(np.float32)
+    tau = 0.5 * np.sqrt(m * n) ** 0.5 * 4.0
+    ref = O.cycle_spun_bsvt(V.astype(np.float64), m, n, tau, s)
+    solver = lib.Solver(M, N, [(m, n)], iters=1, lowrank_min=64)
+    assert lib.TIERS[solver.tier(0)] == "lowrank"
+    Z = solver.bsvt(0, torch.from_numpy(V).cuda(), tau, s)
+    torch.cuda.synchronize()
+    st = solver.stats()
+    err = rel_err(Z.cpu().numpy(), ref, np.linalg.norm(V))
+    print(f"lowrank {M}x{N} / {m}x{n}: err {err:.2e} decomposed {st['live']} certified "
+          f"{st['certified']} rank {st['rank']}", flush=True)
+    assert err <= 1e-4
+    assert st["live"][0] > 0 and st["certified"][0] == st["live"][0]
     solver.close()
 
 
@@ -146,9 +196,10 @@ def test_device_shifts_bit_exact(lib):
     solver.close()
 
 
-def _admm_parity(lib, inst, iters, cycle_spin, seed, tol=1e-3, rho=1.0):
+def _admm_parity(lib, inst, iters, cycle_spin, seed, tol=1e-3, rho=1.0, lowrank_min=0):
     Yd = torch.from_numpy(inst.Y).cuda()
-    Z, info = lib.solve(Yd, inst.ladder, rho=rho, iters=iters, cycle_spin=cycle_spin, seed=seed)
+    Z, info = lib.solve(Yd, inst.ladder, rho=rho, iters=iters, cycle_spin=cycle_spin, seed=seed,
+                        lowrank_min=lowrank_min)
     torch.cuda.synchronize()
     ref = O.admm(inst.Y, inst.ladder, rho=rho, iters=iters, cycle_spin=cycle_spin, seed=seed)
     Zg = Z.double().cpu().numpy()
@@ -156,7 +207,7 @@ def _admm_parity(lib, inst, iters, cycle_spin, seed, tol=1e-3, rho=1.0):
     errs = [rel_err(Zg[i], ref["Z"][i], ny) for i in range(len(inst.ladder))]
     print(f"admm {inst.Y.shape} ladder={inst.ladder} K={iters} cs={cycle_spin}: errs="
           + " ".join(f"{e:.2e}" for e in errs) + f" resid gpu={info['primal_resid']:.3e} "
-          f"oracle={ref['resid']:.3e} live={info['live']}", flush=True)
+          f"oracle={ref['resid']:.3e} live={info['live']} cert={info['certified']}", flush=True)
     assert max(errs) <= tol
     assert abs(info["primal_resid"] - ref["resid"]) <= 1e-3 * max(ref["resid"], 1e-6) + 1e-5
     return Zg, info
@@ -185,6 +236,15 @@ def test_admm_512_cycle_spin(lib):
     inst = make_instance(512, 512, [(1, 1), (4, 4), (16, 16), (64, 64), (512, 512)], 0.03,
                          noise=0.01, seed=0)
     _admm_parity(lib, inst, 100, True, 1)
+
+
+@pytest.mark.parametrize("lowrank_min", [-1, 64])
+def test_admm_8192_ladder_crop_parity(lib, lowrank_min):
+    """The benchmark's ladder (1, 8, 32, 128, 512) and density on a 1024^2 crop, with
+    cycle spinning; with and without the certified low-rank path."""
+    inst = make_instance(1024, 1024, [(1, 1), (8, 8), (32, 32), (128, 128), (512, 512)], 0.01,
+                         noise=0.01, seed=0)
+    _admm_parity(lib, inst, 12, True, 0, lowrank_min=lowrank_min)
 
 
 def test_determinism(lib):
