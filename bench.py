@@ -58,6 +58,143 @@ def cpu_baseline(size, threads_env):
                       f"(same ladder/density/noise), {dt:.2f} s, scaled by {size}^2/8192^2"}
 
 
+def serve_bench(args):
+    """Serving workload: a Poisson stream of decompositions of mixed sizes
+    ({128^2, 512^2, 1024x256, 2048^2}, ratio-4 ladders of 4-6 scales ending in the
+    full block, rank-1/rank-2 blocks at 2% + N(0, 0.01^2)), each retired at primal
+    residual <= 1e-4 (cap 300 iterations, no cycle spinning). First the saturation
+    rate of the continuous-batching server is measured with every request queued at
+    once; then the trace is replayed at 0.7 x that rate, and again with one request
+    at a time (FIFO) as the baseline."""
+    import numpy as np
+    import torch
+    import paper_1507_08751_amd as msld
+    from synth import make_instance, serving_trace
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    nreq, nwarm = args.requests, args.warm_requests
+    trace = serving_trace(nreq + nwarm, rate=1.0, seed=0)
+    log(f"serving: generating {len(trace)} requests ...")
+    reqs = []
+    for (t, M, N, lad, rank, dseed) in trace:
+        inst = make_instance(M, N, lad, 0.02, rank=rank, noise=0.01, seed=dseed,
+                             keep_components=False)
+        reqs.append((t, torch.from_numpy(inst.Y).to(dev), lad))
+
+    def run(active, rate, items):
+        srv = msld.Server(max_active=active, hbm_budget=args.hbm_budget << 30, num_streams=8,
+                          device=dev)
+        t0 = time.perf_counter()
+        arrivals = {}
+        lat = {}
+        iters = {}
+        nxt = 0
+        gaps = np.cumsum([0.0] + [items[i + 1][0] - items[i][0] for i in range(len(items) - 1)])
+        while len(lat) < len(items):
+            now = time.perf_counter() - t0
+            while nxt < len(items) and (rate is None or gaps[nxt] / rate <= now):
+                _, Y, lad = items[nxt]
+                arrivals[nxt] = (time.perf_counter() - t0) if rate is not None else 0.0
+                srv.submit(nxt, Y, lad, iters=300, tol=1e-4, check_every=1)
+                nxt += 1
+            done = srv.step()
+            tnow = time.perf_counter() - t0
+            for (rid, it, res, st, Z) in done:
+                lat[rid] = tnow - arrivals[rid]
+                iters[rid] = it
+                if len(lat) % 8 == 0:
+                    log(f"  serve(active={active}, rate={rate}): {len(lat)}/{len(items)} done "
+                        f"at {tnow:.1f} s")
+            if not done and srv.active == 0 and srv.queued == 0 and nxt < len(items):
+                time.sleep(max(0.0, gaps[nxt] / rate - (time.perf_counter() - t0)))
+        span = time.perf_counter() - t0
+        srv.close()
+        return span, lat, iters
+
+    warm = reqs[:nwarm]
+    meas = reqs[nwarm:]
+    run(args.max_active, None, warm)
+    span_sat, _, it_sat = run(args.max_active, None, meas)
+    sat = len(meas) / span_sat
+    rate = 0.7 * sat
+    log(f"serving saturation: {sat:.2f} solves/s ({span_sat:.2f} s for {len(meas)})")
+    span, lat, iters = run(args.max_active, rate, meas)
+    l = np.array([lat[i] for i in range(len(meas))]) * 1e3
+    span1, lat1, _ = run(1, rate, meas)
+    l1 = np.array([lat1[i] for i in range(len(meas))]) * 1e3
+    out = {"metric": "served solves/s, p99 latency @ primal residual <= 1e-4 (cap 300)",
+           "value": round(len(meas) / span, 4), "unit": "solves/s", "n_gpus": 1,
+           "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "Poisson requests, sizes {128^2, 512^2, 1024x256, 2048^2}, "
+                                  "ratio-4 ladders of 4-6 scales ending in the full block, "
+                                  "rank-1/2 blocks at 2% + N(0,0.01^2), tol 1e-4, cap 300",
+                      "requests": len(meas), "warmup_requests": nwarm,
+                      "arrival_rate": round(rate, 4), "max_active": args.max_active},
+           "saturation_solves_per_s": round(sat, 4),
+           "p50_ms": round(float(np.percentile(l, 50)), 2),
+           "p99_ms": round(float(np.percentile(l, 99)), 2),
+           "mean_iters": round(float(np.mean([iters[i] for i in range(len(meas))])), 1),
+           "baseline_one_at_a_time": {"solves_per_s": round(len(meas) / span1, 4),
+                                      "p50_ms": round(float(np.percentile(l1, 50)), 2),
+                                      "p99_ms": round(float(np.percentile(l1, 99)), 2)}}
+    print(json.dumps(out), flush=True)
+
+
+def batch_bench(args):
+    """Batched workload: independent decompositions of sizes drawn from {64^2, 128^2,
+    256^2, 128x512} with ladders {1,4,16,full} or {1,8,32,full}, rank-1 blocks at 2%
+    + N(0, 0.01^2), 100 iterations with cycle spinning (shift seed = instance id),
+    solved in one batch (stacked launches per shape class) and, as the baseline, one
+    solve at a time with the same kernels."""
+    import numpy as np
+    import torch
+    import paper_1507_08751_amd as msld
+    from synth import batch_instances
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    insts = batch_instances(args.instances, seed=0)
+    K = args.steps if args.steps != 50 else 100
+    probs = [{"M": i.Y.shape[0], "N": i.Y.shape[1], "ladder": i.ladder, "iters": K,
+              "cycle_spin": True, "seed": j} for j, i in enumerate(insts)]
+    Ys = [torch.from_numpy(i.Y).to(dev) for i in insts]
+    batch = msld.Batch(probs, device=dev)
+    outs, _ = batch.solve(Ys)          # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs, _ = batch.solve(Ys, outs)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    solvers = [msld.Solver(p["M"], p["N"], p["ladder"], iters=K, cycle_spin=True, seed=p["seed"],
+                           device=dev) for p in probs]
+    zs = [torch.empty_like(o) for o in outs]
+    solvers[0].solve(Ys[0], zs[0], info=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s, y, z in zip(solvers, Ys, zs):
+        s.solve(y, z, info=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter() - t0
+    worst = 0.0
+    for o, z in zip(outs, zs):
+        d = (o - z).norm().item() / max(z.norm().item(), 1e-12)
+        worst = max(worst, d)
+    out = {"metric": "batched solves/s (256 mixed instances, 100 iterations each)",
+           "value": round(len(insts) / tb, 4), "unit": "solves/s", "n_gpus": 1,
+           "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "sizes {64^2,128^2,256^2,128x512}, ladders {1,4,16,full} / "
+                                  "{1,8,32,full}, 2% rank-1 + N(0,0.01^2), cycle spinning",
+                      "instances": len(insts), "iters": K, "classes": batch.classes},
+           "batch_seconds": round(tb, 4), "one_at_a_time_seconds": round(t1, 4),
+           "one_at_a_time_solves_per_s": round(len(insts) / t1, 4),
+           "speedup": round(t1 / tb, 3), "max_rel_diff_batch_vs_alone": worst}
+    print(json.dumps(out), flush=True)
+    batch.close()
+    for s in solvers:
+        s.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -66,11 +203,23 @@ def main():
     ap.add_argument("--size", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2048)
+    ap.add_argument("--mode", choices=["iters", "serve", "batch"], default="iters")
+    ap.add_argument("--instances", type=int, default=256)
+    ap.add_argument("--requests", type=int, default=64)
+    ap.add_argument("--warm-requests", type=int, default=8)
+    ap.add_argument("--max-active", type=int, default=16)
+    ap.add_argument("--hbm-budget", type=int, default=64, help="GiB")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.mode == "serve":
+        serve_bench(args)
+        return
+    if args.mode == "batch":
+        batch_bench(args)
+        return
 
     import numpy as np
     import torch

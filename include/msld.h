@@ -185,6 +185,72 @@ msld_status msld_cycle_shift(uint64_t seed, int32_t k, int32_t i, int32_t m, int
  * 2 * L * count ints; the call synchronises. count >= 1. */
 msld_status msld_device_shifts(msld_solver *s, int32_t k0, int32_t count, int32_t *out);
 
+/* ------------------------------------------------------------------ batches
+ * Many independent decompositions (of uneven sizes and ladders) solved together.
+ * Instances whose parameters agree except for shift_seed form a class; the
+ * instances of a class are stacked along the rows of one set of planes, so each
+ * kernel of an ADMM iteration is launched once per class for all its instances and
+ * the low-rank path's GEMMs are batched across them. Every instance keeps its own
+ * shift seed (its cycle-spin shifts are those of a single solve with that seed), its
+ * own iteration count and residual test, so its result equals its solve alone. */
+typedef struct msld_batch msld_batch;
+
+/* Plan n >= 1 instances (params[0..n-1], host array) and allocate their workspace
+ * on the current device; work runs on hip_stream. */
+msld_status msld_batch_create(int32_t n, const msld_params *params, void *hip_stream,
+                              msld_batch **out);
+
+/* Number of classes (stacked launch groups) of the batch, -1 for NULL. */
+int32_t msld_batch_classes(const msld_batch *b);
+
+/* Solve every instance i from Z = U = 0: d_Y[i] (M_i x N_i, leading dimension
+ * ldY[i], device) in, d_Z[i] (L_i x M_i x N_i, device) out. d_Y, ldY, d_Z and info
+ * are host arrays of n entries (info may be NULL). An instance with tol > 0 stops at
+ * its own tolerance. Synchronises the stream. */
+msld_status msld_batch_solve(msld_batch *b, const float *const *d_Y, const int64_t *ldY,
+                             float *const *d_Z, msld_result *info);
+
+void msld_batch_free(msld_batch *b);   /* NULL-safe */
+
+/* ------------------------------------------------------------------ serving
+ * Continuous batching of independent decompositions (a request loop). Requests wait
+ * in a FIFO queue and are admitted, in order, while fewer than max_active are
+ * running: a request takes a free slot of a class (a stacked solver for its problem
+ * shape, min(max_active, 8) slots, as in the batches above); a new class is created
+ * when its HBM footprint (workspace plus stacked Y and Z planes) fits in
+ * hbm_budget_bytes, after releasing idle classes if needed. Each msld_server_step
+ * runs one ADMM iteration (Sec. 7 eq:admm, from Z = U = 0) for all active slots of
+ * each class with one set of launches (classes on the server's num_streams streams),
+ * reads the per-slot residuals back, and retires every request whose residual is
+ * <= its tol (checked every check_every iterations) or that reached max_iters,
+ * copying its Z planes to the request's buffer. A request's result is the same
+ * alone and in any mix: slots are independent instances of deterministic kernels. */
+typedef struct msld_server msld_server;
+
+/* max_active >= 1, hbm_budget_bytes > 0, 1 <= num_streams <= 64; streams are created
+ * at the default priority on the current device. */
+msld_status msld_server_create(int32_t max_active, size_t hbm_budget_bytes,
+                               int32_t num_streams, msld_server **out);
+
+/* Queue one request. d_Y (M x N, leading dimension ldY) and d_Z (L x M x N) are
+ * caller-owned device buffers that must stay valid until the request is reported
+ * done; d_Z receives Z_1..Z_L. MSLD_EINVAL if p is invalid or the footprint exceeds
+ * the whole budget. Does not touch the device. */
+msld_status msld_server_submit(msld_server *sv, const msld_params *p, const float *d_Y,
+                               int64_t ldY, float *d_Z, int64_t request_id);
+
+/* Admit, advance every active request by one iteration, retire, and report up to
+ * max_out finished requests (id, iterations run, last residual, status) in the
+ * caller's host arrays; *n_done receives the count, *n_active the running requests
+ * and *n_queued the requests still waiting (plus finished ones not yet reported).
+ * Synchronises the streams of requests due for a residual check. */
+msld_status msld_server_step(msld_server *sv, int64_t *done_ids, int32_t *done_iters,
+                             double *done_resid, int32_t *done_status, int32_t max_out,
+                             int32_t *n_done, int32_t *n_active, int32_t *n_queued);
+
+/* Free the server, its streams and the workspace of requests still active. NULL-safe. */
+void msld_server_free(msld_server *sv);
+
 /* Kernel tier the plan chose for scale i: 0 = 1x1 (fused in the consensus pass),
  * 1 = register tier (blocks up to 8 x 8), 2 = LDS tier, 3 = HBM panel tier,
  * 4 = certified low-rank path with panel fallback. Returns -1 for an invalid index. */

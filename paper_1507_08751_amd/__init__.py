@@ -11,7 +11,7 @@ import ctypes
 import math
 import os
 
-__all__ = ["load", "Solver", "solve", "bsvt", "cycle_shift", "default_lambda",
+__all__ = ["load", "Solver", "Batch", "Server", "solve", "bsvt", "cycle_shift", "default_lambda",
            "MAX_SCALES", "TIERS", "MsldError"]
 
 MAX_SCALES = 16
@@ -75,6 +75,26 @@ EXPORTS = {
                                  ctypes.c_void_p, ctypes.c_int32,
                                  ctypes.POINTER(ctypes.c_double)]),
     "msld_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Result)]),
+    "msld_batch_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(Params), ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_void_p)]),
+    "msld_batch_classes": (ctypes.c_int32, [ctypes.c_void_p]),
+    "msld_batch_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                        ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Result)]),
+    "msld_batch_free": (None, [ctypes.c_void_p]),
+    "msld_server_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_size_t, ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_void_p)]),
+    "msld_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Params),
+                                          ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                          ctypes.c_int64]),
+    "msld_server_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int32)]),
+    "msld_server_free": (None, [ctypes.c_void_p]),
     "msld_profile_begin": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "msld_profile_end": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_int64),
@@ -282,6 +302,137 @@ class Solver:
             _check(self._lib.msld_device_shifts(self._h, k0, count, buf), "msld_device_shifts")
         import numpy as np
         return np.array(buf, dtype=np.int64).reshape(count, self.L, 2)
+
+
+class Batch:
+    """Many independent decompositions solved together (msld_batch_*). `problems` is a
+    list of dicts with keys M, N, ladder and optional lam, rho, iters, tol,
+    check_every, cycle_spin, seed, lowrank_min."""
+
+    def __init__(self, problems, device=None):
+        import torch
+        self._torch = torch
+        self._lib = load()
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
+            else torch.device(device)
+        n = len(problems)
+        arr = (Params * n)()
+        self.shapes = []
+        for i, pr in enumerate(problems):
+            arr[i] = make_params(pr["M"], pr["N"], pr["ladder"], pr.get("lam"),
+                                 pr.get("rho", 1.0), pr.get("iters", 100), pr.get("tol", 0.0),
+                                 pr.get("check_every", 1), pr.get("cycle_spin", False),
+                                 pr.get("seed", 0), pr.get("lowrank_min", 0))
+            self.shapes.append((len(pr["ladder"]), pr["M"], pr["N"]))
+        self.n = n
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(self._lib.msld_batch_create(n, arr, _stream_ptr(torch, self.device),
+                                               ctypes.byref(h)), "msld_batch_create")
+        self._h = h
+
+    @property
+    def classes(self):
+        return int(self._lib.msld_batch_classes(self._h))
+
+    def solve(self, Ys, outs=None, info=True):
+        torch = self._torch
+        n = self.n
+        if outs is None:
+            outs = [torch.empty(sh, dtype=torch.float32, device=self.device) for sh in self.shapes]
+        ys = (ctypes.c_void_p * n)(*[y.data_ptr() for y in Ys])
+        lds = (ctypes.c_int64 * n)(*[y.stride(0) for y in Ys])
+        zs = (ctypes.c_void_p * n)(*[z.data_ptr() for z in outs])
+        res = (Result * n)() if info else None
+        with torch.cuda.device(self.device):
+            _check(self._lib.msld_batch_solve(self._h, ys, lds, zs, res), "msld_batch_solve")
+        infos = None
+        if info:
+            infos = [{"iters": r.iters, "primal_resid": r.primal_resid, "status": r.status}
+                     for r in res]
+        return outs, infos
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.msld_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching request loop of the library (msld_server_*).
+
+    submit() queues a decomposition of a device tensor Y into a caller-provided (or
+    new) Z tensor; step() admits, advances every active request by one iteration and
+    returns the requests that finished: [(id, iters, resid, status)]."""
+
+    def __init__(self, max_active=16, hbm_budget=64 << 30, num_streams=8, device=None):
+        import torch
+        self._torch = torch
+        self._lib = load()
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
+            else torch.device(device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(self._lib.msld_server_create(int(max_active), int(hbm_budget),
+                                                int(num_streams), ctypes.byref(h)),
+                   "msld_server_create")
+        self._h = h
+        self._keep = {}
+        self._cap = 256
+        self._ids = (ctypes.c_int64 * self._cap)()
+        self._its = (ctypes.c_int32 * self._cap)()
+        self._res = (ctypes.c_double * self._cap)()
+        self._sts = (ctypes.c_int32 * self._cap)()
+
+    def submit(self, request_id, Y, ladder, lam=None, rho=1.0, iters=300, tol=1e-4,
+               check_every=1, cycle_spin=False, seed=0, lowrank_min=0, out=None):
+        torch = self._torch
+        M, N = Y.shape
+        if out is None:
+            out = torch.empty((len(ladder), M, N), dtype=torch.float32, device=Y.device)
+        p = make_params(M, N, ladder, lam, rho, iters, tol, check_every, cycle_spin, seed,
+                        lowrank_min)
+        with torch.cuda.device(self.device):
+            _check(self._lib.msld_server_submit(self._h, ctypes.byref(p),
+                                                ctypes.c_void_p(Y.data_ptr()),
+                                                ctypes.c_int64(Y.stride(0)),
+                                                ctypes.c_void_p(out.data_ptr()),
+                                                ctypes.c_int64(int(request_id))),
+                   "msld_server_submit")
+        self._keep[int(request_id)] = (Y, out)
+        return out
+
+    def step(self):
+        nd, na, nq = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        with self._torch.cuda.device(self.device):
+            _check(self._lib.msld_server_step(self._h, self._ids, self._its, self._res,
+                                              self._sts, self._cap, ctypes.byref(nd),
+                                              ctypes.byref(na), ctypes.byref(nq)),
+                   "msld_server_step")
+        out = []
+        for k in range(nd.value):
+            rid = int(self._ids[k])
+            Y, Z = self._keep.pop(rid, (None, None))
+            out.append((rid, int(self._its[k]), float(self._res[k]), int(self._sts[k]), Z))
+        self.active, self.queued = na.value, nq.value
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.msld_server_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def solve(Y, ladder, lam=None, rho=1.0, iters=100, tol=0.0, check_every=1,

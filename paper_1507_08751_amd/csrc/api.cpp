@@ -1,29 +1,21 @@
-// C-ABI runtime: parameter validation, per-scale planning, workspace arena and the
-// ADMM driver loop (Sec. 7 eq:admm with the random cycle spinning of Sec. 9).
-#include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
-
+// C-ABI runtime: parameter validation, per-scale planning, workspace arena, the ADMM
+// driver loop (Sec. 7 eq:admm with the random cycle spinning of Sec. 9) and batched
+// solves of many independent instances grouped by shape.
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <vector>
 
-#include "../../include/msld.h"
-#include "msld_internal.h"
+#include "runtime.h"
 
 using namespace msld;
 
 namespace msld {
-int lds_tier_threads(int nb, int mb, int* G);
-size_t lds_tier_bytes(int mb, int nb);
-size_t stream_lds_bytes(int m, const StreamPlan& sp);
-}  // namespace msld
 
 namespace {
 
-constexpr size_t kLdsTierMax = 150 * 1024;   // LDS budget of one workgroup (160 KiB per CU)
-constexpr int kStreamFloats = 16384;         // stream-pass tile budget (floats)
-constexpr int kResidParts = 1024;
+constexpr int kResidPartsMax = 1024;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -32,25 +24,6 @@ int pow2_floor(int x) {
   while (p * 2 <= x) p *= 2;
   return p;
 }
-
-struct Plan {
-  ScaleGeom geom[MSLD_MAX_SCALES];
-  StreamPlan sp[MSLD_MAX_SCALES];
-  int tier[MSLD_MAX_SCALES];
-  int pw[MSLD_MAX_SCALES];
-  int nbp[MSLD_MAX_SCALES];
-  float tau_default[MSLD_MAX_SCALES];
-  size_t bytes;
-  // byte offsets inside the arena
-  size_t off_R, off_D, off_part, off_res, off_shift;
-  size_t off_count[MSLD_MAX_SCALES], off_list[MSLD_MAX_SCALES], off_rowp[MSLD_MAX_SCALES],
-      off_frop[MSLD_MAX_SCALES], off_stats[MSLD_MAX_SCALES], off_pA[MSLD_MAX_SCALES],
-      off_pW[MSLD_MAX_SCALES], off_pflag[MSLD_MAX_SCALES], off_pg[MSLD_MAX_SCALES];
-  int use_lr[MSLD_MAX_SCALES];
-  size_t off_lr[MSLD_MAX_SCALES];   // start of the low-rank buffers of the scale
-};
-
-constexpr int kLRP = 16;  // subspace width of the certified low-rank path
 
 // A block fits the LDS Jacobi tier if B and W fit the LDS budget, one workgroup
 // covers all column pairs, and G lanes x 32 rows per lane cover the rows.
@@ -65,7 +38,9 @@ double lambda_default(int M, int N, int m, int n) {
          std::sqrt(std::log((double)M * (double)N / (double)(m > n ? m : n)));
 }
 
-msld_status validate(const msld_params* p) {
+}  // namespace
+
+msld_status validate_params(const msld_params* p) {
   if (!p) return MSLD_EINVAL;
   if (p->M < 1 || p->N < 1 || p->M > (1 << 20) || p->N > (1 << 20)) return MSLD_EINVAL;
   if ((int64_t)p->M * p->N >= ((int64_t)1 << 31)) return MSLD_EINVAL;
@@ -83,12 +58,33 @@ msld_status validate(const msld_params* p) {
   return MSLD_OK;
 }
 
-msld_status make_plan(const msld_params* p, Plan* pl) {
-  msld_status st = validate(p);
+// Two parameter sets can share stacked launches when everything but the shift seed
+// agrees (the seed is per instance).
+bool same_class(const msld_params& a, const msld_params& b) {
+  if (a.M != b.M || a.N != b.N || a.L != b.L || a.rho != b.rho || a.max_iters != b.max_iters ||
+      a.tol != b.tol || a.check_every != b.check_every || a.cycle_spin != b.cycle_spin ||
+      a.lowrank_min != b.lowrank_min)
+    return false;
+  for (int i = 0; i < a.L; ++i)
+    if (a.block_m[i] != b.block_m[i] || a.block_n[i] != b.block_n[i] ||
+        a.lambda[i] != b.lambda[i])
+      return false;
+  return true;
+}
+
+msld_status make_plan(const msld_params* p, int ninst, Plan* pl) {
+  msld_status st = validate_params(p);
   if (st != MSLD_OK) return st;
+  if (ninst < 1 || (int64_t)ninst * p->M * p->N >= ((int64_t)1 << 31)) return MSLD_EINVAL;
   std::memset(pl, 0, sizeof(*pl));
-  const int M = p->M, N = p->N, L = p->L;
+  const int IM = p->M, N = p->N, L = p->L;
+  const int M = IM * ninst;
   const size_t MN = (size_t)M * N;
+  pl->ninst = ninst;
+  int parts = (int)(((size_t)IM * N + 4095) / 4096);
+  if (parts > kResidPartsMax) parts = kResidPartsMax;
+  if (parts < 1) parts = 1;
+  pl->resid_parts = parts;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -97,17 +93,20 @@ msld_status make_plan(const msld_params* p, Plan* pl) {
   };
   pl->off_R = take(4 * MN);
   pl->off_D = take(4 * MN * (size_t)L * 2);
-  pl->off_part = take(8 * (size_t)kResidParts);
-  pl->off_res = take(8 * 4);
+  pl->off_part = take(8 * (size_t)parts * ninst);
+  pl->off_res = take(8 * 2 * (size_t)ninst);
   pl->off_shift = take(4 * 2 * (size_t)L * 1024);
+  pl->off_inst = take(8 * (size_t)ninst + 4 * 2 * (size_t)ninst);
   for (int i = 0; i < L; ++i) {
     const int m = p->block_m[i], n = p->block_n[i];
     ScaleGeom& g = pl->geom[i];
-    g.M = M; g.N = N; g.m = m; g.n = n; g.P = M / m; g.Q = N / n;
+    g.M = M; g.N = N; g.m = m; g.n = n;
+    g.IM = IM; g.PI = IM / m; g.NI = ninst;
+    g.P = g.PI * ninst; g.Q = N / n;
     g.trans = m < n ? 1 : 0;
     g.mb = m < n ? n : m;
     g.nb = m < n ? m : n;
-    const double lam = p->lambda[i] > 0.f ? (double)p->lambda[i] : lambda_default(M, N, m, n);
+    const double lam = p->lambda[i] > 0.f ? (double)p->lambda[i] : lambda_default(IM, N, m, n);
     pl->tau_default[i] = (float)(lam / (double)p->rho);
     const int nblk = g.P * g.Q;
     const int lr_min = p->lowrank_min == 0 ? 128 : p->lowrank_min;
@@ -173,46 +172,143 @@ msld_status make_plan(const msld_params* p, Plan* pl) {
   return MSLD_OK;
 }
 
-}  // namespace
-
-struct msld_solver {
-  msld_params p;
-  Plan plan;
-  hipStream_t st;
-  int device;
-  int num_cus;
-  bool failed;
-  char* arena;
-  double* host_res;  // pinned, 4 doubles
-  int* host_ints;    // pinned, 2 per scale
-  rocblas_handle blas;
-  ScaleWork work[MSLD_MAX_SCALES];
-  int k;              // next iteration index (drives the cycle-spin shifts)
-  int cur;            // which D buffer holds the current D_i
-  // profiling: per iteration 2 consensus events + 5 events per scale
-  int prof_cap, prof_n;
-  hipEvent_t* prof_ev;
-  int64_t round_launches[MSLD_MAX_SCALES];
-};
-
-namespace {
-
 msld_status dev_err(msld_solver* s, hipError_t e) {
   if (e == hipSuccess) return MSLD_OK;
   if (s) s->failed = true;
   return MSLD_EDEVICE;
 }
 
-#define MSLD_TRY(s, call)                              \
-  do {                                                 \
-    hipError_t e_ = (call);                            \
-    if (e_ != hipSuccess) return dev_err((s), e_);     \
-  } while (0)
+size_t plane_elems(const msld_solver* s) { return (size_t)s->p.M * s->ninst * s->p.N; }
 
-float jacobi_tol(int mb) { return 4.0f * 5.9604645e-8f * std::sqrt((float)mb); }
+float* plane_R(msld_solver* s) { return reinterpret_cast<float*>(s->arena + s->plan.off_R); }
 
-msld_status run_scale(msld_solver* s, int i, const float* Zin, const float* R, float* Zout,
-                      float* Dout, float tau, const ShiftSpec& sh, hipEvent_t* ev) {
+float* plane_D(msld_solver* s, int which) {
+  return reinterpret_cast<float*>(s->arena + s->plan.off_D) +
+         (size_t)which * plane_elems(s) * s->p.L;
+}
+
+double* dev_res(msld_solver* s) { return reinterpret_cast<double*>(s->arena + s->plan.off_res); }
+
+static void destroy_solver(msld_solver* s) {
+  if (!s) return;
+  (void)hipStreamSynchronize(s->st);
+  if (s->prof_ev) {
+    for (size_t e = 0; e < (2 + 5 * (size_t)s->p.L) * (size_t)s->prof_cap; ++e)
+      (void)hipEventDestroy(s->prof_ev[e]);
+    std::free(s->prof_ev);
+  }
+  if (s->blas) (void)rocblas_destroy_handle(s->blas);
+  if (s->arena) (void)hipFree(s->arena);
+  if (s->host_res) (void)hipHostFree(s->host_res);
+  if (s->host_ints) (void)hipHostFree(s->host_ints);
+  delete s;
+}
+
+msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
+                          msld_solver** out) {
+  if (!out) return MSLD_EINVAL;
+  *out = nullptr;
+  msld_solver* s = new (std::nothrow) msld_solver();
+  if (!s) return MSLD_ENOMEM;
+  msld_status st = make_plan(p, ninst, &s->plan);
+  if (st != MSLD_OK) {
+    delete s;
+    return st;
+  }
+  s->p = *p;
+  s->ninst = ninst;
+  s->st = stream;
+  s->failed = false;
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return MSLD_EDEVICE;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, s->device) != hipSuccess) {
+    delete s;
+    return MSLD_EDEVICE;
+  }
+  s->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  if (hipMalloc(&s->arena, s->plan.bytes) != hipSuccess) {
+    s->arena = nullptr;
+    destroy_solver(s);
+    return MSLD_ENOMEM;
+  }
+  if (hipHostMalloc(&s->host_res, 2 * (size_t)ninst * sizeof(double), hipHostMallocDefault) !=
+          hipSuccess ||
+      hipHostMalloc(&s->host_ints, 2 * MSLD_MAX_SCALES * sizeof(int), hipHostMallocDefault) !=
+          hipSuccess) {
+    destroy_solver(s);
+    return MSLD_ENOMEM;
+  }
+  const Plan& pl = s->plan;
+  s->d_seed = reinterpret_cast<unsigned long long*>(s->arena + pl.off_inst);
+  s->d_k = reinterpret_cast<int*>(s->d_seed + ninst);
+  s->d_active = s->d_k + ninst;
+  bool need_blas = false;
+  for (int i = 0; i < p->L; ++i) need_blas = need_blas || pl.use_lr[i];
+  if (need_blas) {
+    if (rocblas_create_handle(&s->blas) != rocblas_status_success ||
+        rocblas_set_stream(s->blas, s->st) != rocblas_status_success ||
+        rocblas_set_atomics_mode(s->blas, rocblas_atomics_not_allowed) != rocblas_status_success) {
+      destroy_solver(s);
+      return MSLD_EDEVICE;
+    }
+  }
+  for (int i = 0; i < p->L; ++i) {
+    ScaleWork& w = s->work[i];
+    std::memset(&w, 0, sizeof(w));
+    w.stats = reinterpret_cast<unsigned long long*>(s->arena + pl.off_stats[i]);
+    w.hostInts = s->host_ints + 2 * i;
+    if (pl.tier[i] != TIER_1X1) {
+      w.live_count = reinterpret_cast<int*>(s->arena + pl.off_count[i]);
+      w.live_list = reinterpret_cast<int*>(s->arena + pl.off_list[i]);
+      if (!pl.sp[i].whole) {
+        w.rowpart = reinterpret_cast<float*>(s->arena + pl.off_rowp[i]);
+        w.fropart = reinterpret_cast<float*>(s->arena + pl.off_frop[i]);
+      }
+    }
+    if (pl.tier[i] == TIER_PANEL) {
+      const ScaleGeom& g = pl.geom[i];
+      w.pA = reinterpret_cast<float*>(s->arena + pl.off_pA[i]);
+      w.pW = reinterpret_cast<float*>(s->arena + pl.off_pW[i]);
+      w.pflag = reinterpret_cast<int*>(s->arena + pl.off_pflag[i]);
+      w.pg = reinterpret_cast<float*>(s->arena + pl.off_pg[i]);
+      w.slots = g.P * g.Q;
+      w.nbp = pl.nbp[i];
+      w.pw = pl.pw[i];
+      if (pl.use_lr[i]) {
+        const size_t nb2 = (size_t)g.nb * g.nb;
+        const size_t slots = (size_t)w.slots;
+        float* f = reinterpret_cast<float*>(s->arena + pl.off_lr[i]);
+        w.use_lr = 1;
+        w.blas = s->blas;
+        w.lrG = f; f += slots * nb2;
+        w.lrP = f; f += slots * nb2;
+        w.lrQ = f; f += slots * nb2;
+        w.lrY = f; f += slots * g.nb * kLRP;
+        w.lrX = f; f += slots * g.nb * kLRP;
+        w.lrW = f; f += slots * g.nb * kLRP;
+        w.lrV = f; f += slots * g.nb * kLRP;
+        w.lrC = f; f += slots * g.mb * kLRP;
+        w.lrT = f; f += slots * kLRP * g.nb;
+        w.lrSig = f; f += 2 * slots * kLRP;   // sigma, then the deflation mask
+        w.lrScal = f; f += slots * 8;
+        w.lrOm = f; f += (size_t)g.nb * kLRP;
+        w.lrCount = reinterpret_cast<int*>(f);
+        w.lrFall = w.lrCount + 64;
+        w.lds_fallback = lds_fits(g.mb, g.nb) ? 1 : 0;
+      }
+    }
+  }
+  *out = s;
+  return MSLD_OK;
+}
+
+static float jacobi_tol(int mb) { return 4.0f * 5.9604645e-8f * std::sqrt((float)mb); }
+
+static msld_status run_scale(msld_solver* s, int i, const float* Zin, const float* R, float* Zout,
+                             float* Dout, float tau, const ShiftSpec& sh, hipEvent_t* ev) {
   const Plan& pl = s->plan;
   const ScaleGeom& g = pl.geom[i];
   int rl = 0;
@@ -222,7 +318,117 @@ msld_status run_scale(msld_solver* s, int i, const float* Zin, const float* R, f
   return MSLD_OK;
 }
 
-}  // namespace
+static msld_status zero_stats(msld_solver* s) {
+  for (int i = 0; i < s->p.L; ++i)
+    MSLD_TRY(s, hipMemsetAsync(s->work[i].stats, 0, 8 * 8, s->st));
+  return MSLD_OK;
+}
+
+msld_status iterate_once(msld_solver* s, const float* d_Y, int64_t ldY, float* d_Z,
+                         bool want_res) {
+  const msld_params& p = s->p;
+  const Plan& pl = s->plan;
+  const int IM = p.M, N = p.N, L = p.L;
+  const int M = IM * s->ninst;
+  const size_t MN = plane_elems(s);
+  const bool stacked = s->ninst > 1;
+  float* R = plane_R(s);
+  float* Dc = plane_D(s, s->cur);
+  float* Dn = plane_D(s, 1 - s->cur);
+  int scales1[16];
+  float taus1[16];
+  int n1 = 0;
+  for (int i = 0; i < L; ++i)
+    if (pl.tier[i] == TIER_1X1) {
+      scales1[n1] = i;
+      taus1[n1] = pl.tau_default[i];
+      ++n1;
+    }
+  hipEvent_t* ev = nullptr;
+  if (s->prof_ev && s->prof_n < s->prof_cap) {
+    ev = s->prof_ev + (size_t)s->prof_n * (2 + 5 * L);
+    ++s->prof_n;
+    MSLD_TRY(s, hipEventRecord(ev[0], s->st));
+  }
+  MSLD_TRY(s, launch_consensus(d_Y, ldY, Dc, Dn, d_Z, R, M, N, L, scales1, taus1, n1, IM,
+                               stacked ? s->d_active : nullptr, s->st));
+  if (ev) MSLD_TRY(s, hipEventRecord(ev[1], s->st));
+  for (int i = 0; i < L; ++i) {
+    if (pl.tier[i] == TIER_1X1) continue;
+    ShiftSpec sh;
+    sh.seed = p.shift_seed;
+    sh.k = s->k;
+    sh.scale = i;
+    sh.mode = p.cycle_spin ? 1 : 0;
+    sh.sr = sh.sc = 0;
+    sh.iseed = stacked ? s->d_seed : nullptr;
+    sh.ik = stacked ? s->d_k : nullptr;
+    sh.iactive = stacked ? s->d_active : nullptr;
+    float* Zi = d_Z + MN * i;
+    msld_status rs = run_scale(s, i, Zi, R, Zi, Dn + MN * i, pl.tau_default[i], sh,
+                               ev ? ev + 2 + 5 * i : nullptr);
+    if (rs != MSLD_OK) return rs;
+  }
+  if (want_res) {
+    double* part = reinterpret_cast<double*>(s->arena + pl.off_part);
+    MSLD_TRY(s, launch_resid(Dc, R, d_Z, M, N, L, IM, s->ninst, part, pl.resid_parts, dev_res(s),
+                             s->st));
+  }
+  if (stacked) MSLD_TRY(s, launch_inc_active(s->d_k, s->d_active, s->ninst, s->st));
+  s->k += 1;
+  s->cur = 1 - s->cur;
+  return MSLD_OK;
+}
+
+// ||Y_z||^2 of every instance into dres[ninst + z].
+msld_status launch_ynorms(msld_solver* s, const float* d_Y, int64_t ldY) {
+  double* part = reinterpret_cast<double*>(s->arena + s->plan.off_part);
+  MSLD_TRY(s, launch_sumsq(d_Y, ldY, s->p.M, s->p.N, s->ninst, part, s->plan.resid_parts,
+                           dev_res(s) + s->ninst, s->st));
+  return MSLD_OK;
+}
+
+static msld_status reset_state(msld_solver* s, float* d_Z) {
+  const size_t MN = plane_elems(s);
+  MSLD_TRY(s, launch_fill(d_Z, 0.f, MN * s->p.L, s->st));
+  MSLD_TRY(s, launch_fill(plane_D(s, 0), 0.f, MN * s->p.L, s->st));
+  MSLD_TRY(s, launch_fill_ints(s->d_k, 0, (size_t)s->ninst, s->st));
+  MSLD_TRY(s, launch_fill_ints(s->d_active, 1, (size_t)s->ninst, s->st));
+  s->k = 0;
+  s->cur = 0;
+  return zero_stats(s);
+}
+
+// residual of instance 0 after an iterate_once(..., want_res = true)
+static msld_status read_resid(msld_solver* s, const float* d_Y, int64_t ldY, double* out) {
+  msld_status st = launch_ynorms(s, d_Y, ldY);
+  if (st != MSLD_OK) return st;
+  MSLD_TRY(s, hipMemcpyAsync(s->host_res, dev_res(s), 16, hipMemcpyDeviceToHost, s->st));
+  MSLD_TRY(s, hipStreamSynchronize(s->st));
+  const double ny2 = s->host_res[1] > 0 ? s->host_res[1] : 1.0;
+  *out = std::sqrt(s->host_res[0] / ny2);
+  return std::isfinite(*out) ? MSLD_OK : MSLD_ENUMERIC;
+}
+
+static msld_status fill_stats(msld_solver* s, msld_result* info) {
+  std::memset(info, 0, sizeof(*info));
+  info->iters = s->k;
+  info->primal_resid = -1.0;
+  for (int i = 0; i < s->p.L; ++i) {
+    unsigned long long st8[8];
+    MSLD_TRY(s, hipMemcpyAsync(st8, s->work[i].stats, sizeof(st8), hipMemcpyDeviceToHost, s->st));
+    MSLD_TRY(s, hipStreamSynchronize(s->st));
+    info->live[i] = st8[0];
+    info->sweeps[i] = st8[1];
+    info->rank[i] = st8[2];
+    info->certified[i] = st8[3];
+    info->fail_coupling[i] = st8[4];
+    info->fail_bound[i] = st8[5];
+  }
+  return MSLD_OK;
+}
+
+}  // namespace msld
 
 extern "C" {
 
@@ -256,222 +462,25 @@ msld_status msld_cycle_shift(uint64_t seed, int32_t k, int32_t i, int32_t m, int
 
 size_t msld_workspace_bytes(const msld_params* p) {
   Plan pl;
-  if (make_plan(p, &pl) != MSLD_OK) return 0;
+  if (make_plan(p, 1, &pl) != MSLD_OK) return 0;
   return pl.bytes;
 }
 
 msld_status msld_create(const msld_params* p, void* hip_stream, msld_solver** out) {
-  if (!out) return MSLD_EINVAL;
-  *out = nullptr;
-  msld_solver* s = new (std::nothrow) msld_solver();
-  if (!s) return MSLD_ENOMEM;
-  msld_status st = make_plan(p, &s->plan);
-  if (st != MSLD_OK) {
-    delete s;
-    return st;
-  }
-  s->p = *p;
-  s->st = reinterpret_cast<hipStream_t>(hip_stream);
-  s->failed = false;
-  if (hipGetDevice(&s->device) != hipSuccess) {
-    delete s;
-    return MSLD_EDEVICE;
-  }
-  hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, s->device) != hipSuccess) {
-    delete s;
-    return MSLD_EDEVICE;
-  }
-  s->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-  if (hipMalloc(&s->arena, s->plan.bytes) != hipSuccess) {
-    delete s;
-    return MSLD_ENOMEM;
-  }
-  if (hipHostMalloc(&s->host_res, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
-    (void)hipFree(s->arena);
-    delete s;
-    return MSLD_ENOMEM;
-  }
-  if (hipHostMalloc(&s->host_ints, 2 * MSLD_MAX_SCALES * sizeof(int), hipHostMallocDefault) !=
-      hipSuccess) {
-    (void)hipHostFree(s->host_res);
-    (void)hipFree(s->arena);
-    delete s;
-    return MSLD_ENOMEM;
-  }
-  bool need_blas = false;
-  for (int i = 0; i < p->L; ++i) need_blas = need_blas || s->plan.use_lr[i];
-  s->blas = nullptr;
-  if (need_blas) {
-    if (rocblas_create_handle(&s->blas) != rocblas_status_success ||
-        rocblas_set_stream(s->blas, s->st) != rocblas_status_success ||
-        rocblas_set_atomics_mode(s->blas, rocblas_atomics_not_allowed) != rocblas_status_success) {
-      if (s->blas) (void)rocblas_destroy_handle(s->blas);
-      (void)hipHostFree(s->host_ints);
-      (void)hipHostFree(s->host_res);
-      (void)hipFree(s->arena);
-      delete s;
-      return MSLD_EDEVICE;
-    }
-  }
-  const Plan& pl = s->plan;
-  for (int i = 0; i < p->L; ++i) {
-    ScaleWork& w = s->work[i];
-    std::memset(&w, 0, sizeof(w));
-    w.stats = reinterpret_cast<unsigned long long*>(s->arena + pl.off_stats[i]);
-    if (pl.tier[i] != TIER_1X1) {
-      w.live_count = reinterpret_cast<int*>(s->arena + pl.off_count[i]);
-      w.live_list = reinterpret_cast<int*>(s->arena + pl.off_list[i]);
-      if (!pl.sp[i].whole) {
-        w.rowpart = reinterpret_cast<float*>(s->arena + pl.off_rowp[i]);
-        w.fropart = reinterpret_cast<float*>(s->arena + pl.off_frop[i]);
-      }
-    }
-    if (pl.tier[i] == TIER_PANEL) {
-      w.pA = reinterpret_cast<float*>(s->arena + pl.off_pA[i]);
-      w.pW = reinterpret_cast<float*>(s->arena + pl.off_pW[i]);
-      w.pflag = reinterpret_cast<int*>(s->arena + pl.off_pflag[i]);
-      w.pg = reinterpret_cast<float*>(s->arena + pl.off_pg[i]);
-      w.slots = pl.geom[i].P * pl.geom[i].Q;
-      w.nbp = pl.nbp[i];
-      w.pw = pl.pw[i];
-      w.hostInts = s->host_ints + 2 * i;
-      if (pl.use_lr[i]) {
-        const ScaleGeom& g = pl.geom[i];
-        const size_t nb2 = (size_t)g.nb * g.nb;
-        const size_t slots = (size_t)w.slots;
-        float* f = reinterpret_cast<float*>(s->arena + pl.off_lr[i]);
-        w.use_lr = 1;
-        w.blas = s->blas;
-        w.lrG = f; f += slots * nb2;
-        w.lrP = f; f += slots * nb2;
-        w.lrQ = f; f += slots * nb2;
-        w.lrY = f; f += slots * g.nb * kLRP;
-        w.lrX = f; f += slots * g.nb * kLRP;
-        w.lrW = f; f += slots * g.nb * kLRP;
-        w.lrV = f; f += slots * g.nb * kLRP;
-        w.lrC = f; f += slots * g.mb * kLRP;
-        w.lrT = f; f += slots * kLRP * g.nb;
-        w.lrSig = f; f += 2 * slots * kLRP;   // sigma, then the deflation mask
-        w.lrScal = f; f += slots * 8;
-        w.lrOm = f; f += (size_t)g.nb * kLRP;
-        w.lrCount = reinterpret_cast<int*>(f);
-        w.lrFall = w.lrCount + 64;
-        w.lds_fallback = lds_fits(g.mb, g.nb) ? 1 : 0;
-      }
-    }
-  }
-  *out = s;
-  return MSLD_OK;
+  return create_solver(p, 1, reinterpret_cast<hipStream_t>(hip_stream), out);
 }
 
-void msld_free(msld_solver* s) {
-  if (!s) return;
-  (void)hipStreamSynchronize(s->st);
-  if (s->prof_ev) {
-    for (size_t e = 0; e < (2 + 5 * (size_t)s->p.L) * (size_t)s->prof_cap; ++e)
-      (void)hipEventDestroy(s->prof_ev[e]);
-    std::free(s->prof_ev);
-  }
-  if (s->blas) (void)rocblas_destroy_handle(s->blas);
-  if (s->arena) (void)hipFree(s->arena);
-  if (s->host_res) (void)hipHostFree(s->host_res);
-  if (s->host_ints) (void)hipHostFree(s->host_ints);
-  delete s;
-}
+void msld_free(msld_solver* s) { destroy_solver(s); }
 
 int32_t msld_scale_tier(const msld_solver* s, int32_t scale) {
   if (!s || scale < 0 || scale >= s->p.L) return -1;
   return s->plan.use_lr[scale] ? 4 : s->plan.tier[scale];
 }
 
-static msld_status zero_stats(msld_solver* s) {
-  for (int i = 0; i < s->p.L; ++i)
-    MSLD_TRY(s, hipMemsetAsync(s->work[i].stats, 0, 8 * 8, s->st));
-  return MSLD_OK;
-}
-
-static float* plane_R(msld_solver* s) {
-  return reinterpret_cast<float*>(s->arena + s->plan.off_R);
-}
-
-static float* plane_D(msld_solver* s, int which) {
-  const size_t MN = (size_t)s->p.M * s->p.N;
-  return reinterpret_cast<float*>(s->arena + s->plan.off_D) + (size_t)which * MN * s->p.L;
-}
-
 msld_status msld_reset(msld_solver* s, float* d_Z) {
   if (!s || !d_Z) return MSLD_EINVAL;
   if (s->failed) return MSLD_EDEVICE;
-  const size_t MN = (size_t)s->p.M * s->p.N;
-  MSLD_TRY(s, launch_fill(d_Z, 0.f, MN * s->p.L, s->st));
-  MSLD_TRY(s, launch_fill(plane_D(s, 0), 0.f, MN * s->p.L, s->st));
-  s->k = 0;
-  s->cur = 0;
-  return zero_stats(s);
-}
-
-// One ADMM iteration k = s->k (eq:admm), D buffers ping-pong; when want_res the
-// residual r_k is computed on device into dres[0].
-static msld_status iterate_once(msld_solver* s, const float* d_Y, int64_t ldY, float* d_Z,
-                                bool want_res) {
-  const msld_params& p = s->p;
-  const Plan& pl = s->plan;
-  const int M = p.M, N = p.N, L = p.L;
-  const size_t MN = (size_t)M * N;
-  float* R = plane_R(s);
-  float* Dc = plane_D(s, s->cur);
-  float* Dn = plane_D(s, 1 - s->cur);
-  int scales1[16];
-  float taus1[16];
-  int n1 = 0;
-  for (int i = 0; i < L; ++i)
-    if (pl.tier[i] == TIER_1X1) {
-      scales1[n1] = i;
-      taus1[n1] = pl.tau_default[i];
-      ++n1;
-    }
-  hipEvent_t* ev = nullptr;
-  if (s->prof_ev && s->prof_n < s->prof_cap) {
-    ev = s->prof_ev + (size_t)s->prof_n * (2 + 5 * L);
-    ++s->prof_n;
-    MSLD_TRY(s, hipEventRecord(ev[0], s->st));
-  }
-  MSLD_TRY(s, launch_consensus(d_Y, ldY, Dc, Dn, d_Z, R, M, N, L, scales1, taus1, n1, s->st));
-  if (ev) MSLD_TRY(s, hipEventRecord(ev[1], s->st));
-  for (int i = 0; i < L; ++i) {
-    if (pl.tier[i] == TIER_1X1) continue;
-    ShiftSpec sh;
-    sh.seed = p.shift_seed;
-    sh.k = s->k;
-    sh.scale = i;
-    sh.mode = p.cycle_spin ? 1 : 0;
-    sh.sr = sh.sc = 0;
-    float* Zi = d_Z + MN * i;
-    msld_status rs = run_scale(s, i, Zi, R, Zi, Dn + MN * i, pl.tau_default[i], sh,
-                               ev ? ev + 2 + 5 * i : nullptr);
-    if (rs != MSLD_OK) return rs;
-  }
-  if (want_res) {
-    double* part = reinterpret_cast<double*>(s->arena + pl.off_part);
-    double* dres = reinterpret_cast<double*>(s->arena + pl.off_res);
-    MSLD_TRY(s, launch_resid(Dc, R, d_Z, M, N, L, part, kResidParts, dres, s->st));
-  }
-  s->k += 1;
-  s->cur = 1 - s->cur;
-  return MSLD_OK;
-}
-
-static msld_status read_resid(msld_solver* s, const float* d_Y, int64_t ldY, double* out) {
-  const Plan& pl = s->plan;
-  double* part = reinterpret_cast<double*>(s->arena + pl.off_part);
-  double* dres = reinterpret_cast<double*>(s->arena + pl.off_res);
-  MSLD_TRY(s, launch_sumsq(d_Y, ldY, s->p.M, s->p.N, part, kResidParts, dres + 1, s->st));
-  MSLD_TRY(s, hipMemcpyAsync(s->host_res, dres, 16, hipMemcpyDeviceToHost, s->st));
-  MSLD_TRY(s, hipStreamSynchronize(s->st));
-  const double ny2 = s->host_res[1] > 0 ? s->host_res[1] : 1.0;
-  *out = std::sqrt(s->host_res[0] / ny2);
-  return std::isfinite(*out) ? MSLD_OK : MSLD_ENUMERIC;
+  return reset_state(s, d_Z);
 }
 
 msld_status msld_step(msld_solver* s, const float* d_Y, int64_t ldY, float* d_Z, int32_t count,
@@ -490,21 +499,7 @@ msld_status msld_step(msld_solver* s, const float* d_Y, int64_t ldY, float* d_Z,
 msld_status msld_stats(msld_solver* s, msld_result* info) {
   if (!s || !info) return MSLD_EINVAL;
   if (s->failed) return MSLD_EDEVICE;
-  std::memset(info, 0, sizeof(*info));
-  info->iters = s->k;
-  info->primal_resid = -1.0;
-  for (int i = 0; i < s->p.L; ++i) {
-    unsigned long long st8[8];
-    MSLD_TRY(s, hipMemcpyAsync(st8, s->work[i].stats, sizeof(st8), hipMemcpyDeviceToHost, s->st));
-    MSLD_TRY(s, hipStreamSynchronize(s->st));
-    info->live[i] = st8[0];
-    info->sweeps[i] = st8[1];
-    info->rank[i] = st8[2];
-    info->certified[i] = st8[3];
-    info->fail_coupling[i] = st8[4];
-    info->fail_bound[i] = st8[5];
-  }
-  return MSLD_OK;
+  return fill_stats(s, info);
 }
 
 msld_status msld_solve(msld_solver* s, const float* d_Y, int64_t ldY, float* d_Z,
@@ -513,7 +508,7 @@ msld_status msld_solve(msld_solver* s, const float* d_Y, int64_t ldY, float* d_Z
   if (s->failed) return MSLD_EDEVICE;
   const msld_params& p = s->p;
   if (ldY < p.N) return MSLD_EINVAL;
-  msld_status st = msld_reset(s, d_Z);
+  msld_status st = reset_state(s, d_Z);
   if (st != MSLD_OK) return st;
   double resid = -1.0;
   msld_status result = MSLD_OK;
@@ -531,7 +526,7 @@ msld_status msld_solve(msld_solver* s, const float* d_Y, int64_t ldY, float* d_Z
     }
   }
   if (info) {
-    st = msld_stats(s, info);
+    st = fill_stats(s, info);
     if (st != MSLD_OK) return st;
     info->primal_resid = resid;
     info->status = result;
@@ -593,15 +588,14 @@ msld_status msld_bsvt(msld_solver* s, int32_t scale, const float* d_V, float* d_
                       int32_t sr, int32_t sc) {
   if (!s || !d_V || !d_Z) return MSLD_EINVAL;
   if (s->failed) return MSLD_EDEVICE;
-  if (scale < 0 || scale >= s->p.L) return MSLD_EINVAL;
+  if (s->ninst != 1 || scale < 0 || scale >= s->p.L) return MSLD_EINVAL;
   const ScaleGeom& g = s->plan.geom[scale];
   if (sr < 0 || sr >= g.m || sc < 0 || sc >= g.n) return MSLD_EINVAL;
   if (!(tau >= 0.f) || !std::isfinite(tau)) return MSLD_EINVAL;
   const size_t MN = (size_t)g.M * g.N;
-  float* Dws = reinterpret_cast<float*>(s->arena + s->plan.off_D) + MN * scale;
+  float* Dws = plane_D(s, 0) + MN * scale;
   ShiftSpec sh;
-  sh.seed = 0;
-  sh.k = 0;
+  std::memset(&sh, 0, sizeof(sh));
   sh.scale = scale;
   sh.mode = 2;
   sh.sr = sr;
@@ -610,13 +604,13 @@ msld_status msld_bsvt(msld_solver* s, int32_t scale, const float* d_V, float* d_
     // 1x1 blocks: the entrywise soft-threshold of the consensus kernel, run with
     // L = 1, Y = V, an all-zero D plane and an all-zero Z plane: R = V and
     // Z' = soft(R, tau). The second D buffer serves as the Z plane.
-    float* Rws = reinterpret_cast<float*>(s->arena + s->plan.off_R);
-    float* Zp = reinterpret_cast<float*>(s->arena + s->plan.off_D) + MN * s->p.L;
+    float* Zp = plane_D(s, 1);
     int idx0 = 0;
     float t0 = tau;
     MSLD_TRY(s, launch_fill(Dws, 0.f, MN, s->st));
     MSLD_TRY(s, launch_fill(Zp, 0.f, MN, s->st));
-    MSLD_TRY(s, launch_consensus(d_V, g.N, Dws, Dws, Zp, Rws, g.M, g.N, 1, &idx0, &t0, 1, s->st));
+    MSLD_TRY(s, launch_consensus(d_V, g.N, Dws, Dws, Zp, plane_R(s), g.M, g.N, 1, &idx0, &t0, 1,
+                                 g.M, nullptr, s->st));
     MSLD_TRY(s, hipMemcpyAsync(d_Z, Zp, MN * 4, hipMemcpyDeviceToDevice, s->st));
     return MSLD_OK;
   }
@@ -636,5 +630,169 @@ msld_status msld_device_shifts(msld_solver* s, int32_t k0, int32_t count, int32_
   MSLD_TRY(s, hipStreamSynchronize(s->st));
   return MSLD_OK;
 }
+
+// ------------------------------------------------------------------ batches
+// Many independent decompositions solved together: instances whose parameters agree
+// except for the shift seed form a class and are stacked along the rows of one set
+// of planes, so every kernel of an iteration is launched once per class for all of
+// its instances (and the Gram / power GEMMs of the low-rank path are batched across
+// instances). Each instance keeps its own seed, iteration counter and residual.
+struct msld_batch {
+  struct Cls {
+    msld_params p;
+    std::vector<int> members;   // instance ids in slot order
+    msld_solver* s;
+    float* Y;                   // stacked Y (members x M x N)
+    float* Z;                   // stacked Z (L planes)
+  };
+  int n;
+  hipStream_t st;
+  std::vector<Cls> cls;
+  std::vector<int> cls_of, slot_of;
+};
+
+static void batch_destroy(msld_batch* b) {
+  if (!b) return;
+  for (auto& c : b->cls) {
+    if (c.s) destroy_solver(c.s);
+    if (c.Y) (void)hipFree(c.Y);
+    if (c.Z) (void)hipFree(c.Z);
+  }
+  delete b;
+}
+
+msld_status msld_batch_create(int32_t n, const msld_params* params, void* hip_stream,
+                              msld_batch** out) {
+  if (!out || n < 1 || !params) return MSLD_EINVAL;
+  *out = nullptr;
+  for (int i = 0; i < n; ++i)
+    if (validate_params(&params[i]) != MSLD_OK) return MSLD_EINVAL;
+  msld_batch* b = new (std::nothrow) msld_batch();
+  if (!b) return MSLD_ENOMEM;
+  b->n = n;
+  b->st = reinterpret_cast<hipStream_t>(hip_stream);
+  b->cls_of.assign(n, -1);
+  b->slot_of.assign(n, -1);
+  for (int i = 0; i < n; ++i) {
+    int c = -1;
+    for (size_t j = 0; j < b->cls.size(); ++j)
+      if (same_class(b->cls[j].p, params[i])) {
+        c = (int)j;
+        break;
+      }
+    if (c < 0) {
+      msld_batch::Cls nc;
+      nc.p = params[i];
+      nc.s = nullptr;
+      nc.Y = nc.Z = nullptr;
+      b->cls.push_back(nc);
+      c = (int)b->cls.size() - 1;
+    }
+    b->cls_of[i] = c;
+    b->slot_of[i] = (int)b->cls[c].members.size();
+    b->cls[c].members.push_back(i);
+  }
+  for (auto& c : b->cls) {
+    const int ni = (int)c.members.size();
+    msld_status st = create_solver(&c.p, ni, b->st, &c.s);
+    if (st != MSLD_OK) {
+      batch_destroy(b);
+      return st;
+    }
+    const size_t MN = (size_t)c.p.M * c.p.N * ni;
+    if (hipMalloc(&c.Y, 4 * MN) != hipSuccess || hipMalloc(&c.Z, 4 * MN * c.p.L) != hipSuccess) {
+      batch_destroy(b);
+      return MSLD_ENOMEM;
+    }
+    std::vector<unsigned long long> seeds(ni);
+    for (int z = 0; z < ni; ++z) seeds[z] = params[c.members[z]].shift_seed;
+    if (hipMemcpy(c.s->d_seed, seeds.data(), 8 * (size_t)ni, hipMemcpyHostToDevice) !=
+        hipSuccess) {
+      batch_destroy(b);
+      return MSLD_EDEVICE;
+    }
+  }
+  *out = b;
+  return MSLD_OK;
+}
+
+int32_t msld_batch_classes(const msld_batch* b) { return b ? (int32_t)b->cls.size() : -1; }
+
+msld_status msld_batch_solve(msld_batch* b, const float* const* d_Y, const int64_t* ldY,
+                             float* const* d_Z, msld_result* info) {
+  if (!b || !d_Y || !ldY || !d_Z) return MSLD_EINVAL;
+  for (int i = 0; i < b->n; ++i) {
+    const msld_params& p = b->cls[b->cls_of[i]].p;
+    if (!d_Y[i] || !d_Z[i] || ldY[i] < p.N) return MSLD_EINVAL;
+  }
+  msld_status result = MSLD_OK;
+  if (info) std::memset(info, 0, sizeof(msld_result) * b->n);
+  for (auto& c : b->cls) {
+    msld_solver* s = c.s;
+    const msld_params& p = c.p;
+    const int ni = (int)c.members.size();
+    const size_t inst = (size_t)p.M * p.N;
+    const size_t MN = inst * ni;
+    for (int z = 0; z < ni; ++z) {
+      const int i = c.members[z];
+      MSLD_TRY(s, hipMemcpy2DAsync(c.Y + inst * z, 4 * (size_t)p.N, d_Y[i], 4 * (size_t)ldY[i],
+                                   4 * (size_t)p.N, p.M, hipMemcpyDeviceToDevice, b->st));
+    }
+    msld_status st = reset_state(s, c.Z);
+    if (st != MSLD_OK) return st;
+    st = launch_ynorms(s, c.Y, p.N);
+    if (st != MSLD_OK) return st;
+    std::vector<int> active(ni, 1), iters(ni, 0);
+    std::vector<double> resid(ni, -1.0);
+    std::vector<int32_t> status(ni, MSLD_OK);
+    int n_active = ni;
+    for (int k = 0; k < p.max_iters && n_active > 0; ++k) {
+      const bool check = (p.tol > 0.f && (k + 1) % p.check_every == 0) || k + 1 == p.max_iters;
+      st = iterate_once(s, c.Y, p.N, c.Z, check);
+      if (st != MSLD_OK) return st;
+      for (int z = 0; z < ni; ++z)
+        if (active[z]) iters[z] = k + 1;
+      if (!check) continue;
+      MSLD_TRY(s, hipMemcpyAsync(s->host_res, dev_res(s), 16 * (size_t)ni, hipMemcpyDeviceToHost,
+                                 b->st));
+      MSLD_TRY(s, hipStreamSynchronize(b->st));
+      for (int z = 0; z < ni; ++z) {
+        if (!active[z]) continue;
+        const double ny2 = s->host_res[ni + z] > 0 ? s->host_res[ni + z] : 1.0;
+        resid[z] = std::sqrt(s->host_res[z] / ny2);
+        const bool bad = !std::isfinite(resid[z]);
+        if (bad || (p.tol > 0.f && resid[z] <= (double)p.tol)) {
+          if (bad) status[z] = MSLD_ENUMERIC;
+          active[z] = 0;
+          --n_active;
+          MSLD_TRY(s, launch_set_int(s->d_active, z, 0, b->st));
+        }
+      }
+    }
+    for (int z = 0; z < ni; ++z) {
+      const int i = c.members[z];
+      for (int l = 0; l < p.L; ++l)
+        MSLD_TRY(s, hipMemcpyAsync(d_Z[i] + inst * l, c.Z + MN * l + inst * z, 4 * inst,
+                                   hipMemcpyDeviceToDevice, b->st));
+      if (status[z] != MSLD_OK) result = (msld_status)status[z];
+    }
+    if (info) {
+      msld_result cls_info;
+      st = fill_stats(s, &cls_info);
+      if (st != MSLD_OK) return st;
+      for (int z = 0; z < ni; ++z) {
+        msld_result& r = info[c.members[z]];
+        r = cls_info;   // per-class kernel counters (shared by the class's instances)
+        r.iters = iters[z];
+        r.primal_resid = resid[z];
+        r.status = status[z];
+      }
+    }
+  }
+  if (hipStreamSynchronize(b->st) != hipSuccess) return MSLD_EDEVICE;
+  return result;
+}
+
+void msld_batch_free(msld_batch* b) { batch_destroy(b); }
 
 }  // extern "C"

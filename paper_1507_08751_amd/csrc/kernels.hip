@@ -50,7 +50,7 @@ __device__ __forceinline__ float soft(float v, float t) {
 __global__ void __launch_bounds__(256) k_consensus_v4(
     const float* __restrict__ Y, int64_t ldY, const float* __restrict__ Dcur,
     float* __restrict__ Dnext, float* __restrict__ Z, float* __restrict__ R, int M, int N,
-    int L, float invL, OneByOne ob) {
+    int L, float invL, OneByOne ob, int IM, const int* __restrict__ iactive) {
   const int64_t MN = (int64_t)M * N;
   const int total4 = (int)(MN >> 2);
   const int stride = gridDim.x * blockDim.x;
@@ -58,6 +58,7 @@ __global__ void __launch_bounds__(256) k_consensus_v4(
     const int flat = e << 2;
     const int r = flat / N;
     const int c = flat - r * N;
+    if (iactive && !iactive[r / IM]) continue;
     float4 y = *reinterpret_cast<const float4*>(Y + (int64_t)r * ldY + c);
     float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int j = 0; j < L; ++j) {
@@ -87,13 +88,14 @@ __global__ void __launch_bounds__(256) k_consensus_v4(
 __global__ void __launch_bounds__(256) k_consensus_s(
     const float* __restrict__ Y, int64_t ldY, const float* __restrict__ Dcur,
     float* __restrict__ Dnext, float* __restrict__ Z, float* __restrict__ R, int M, int N,
-    int L, float invL, OneByOne ob) {
+    int L, float invL, OneByOne ob, int IM, const int* __restrict__ iactive) {
   const int64_t MN = (int64_t)M * N;
   const int total = (int)MN;
   const int stride = gridDim.x * blockDim.x;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
     const int r = e / N;
     const int c = e - r * N;
+    if (iactive && !iactive[r / IM]) continue;
     float s = 0.f;
     for (int j = 0; j < L; ++j) s += Dcur[j * MN + e];
     const float rr = (Y[(int64_t)r * ldY + c] - s) * invL;
@@ -110,7 +112,8 @@ __global__ void __launch_bounds__(256) k_consensus_s(
 
 hipError_t launch_consensus(const float* Y, int64_t ldY, const float* Dcur, float* Dnext,
                             float* Z, float* R, int M, int N, int L, const int* scales1,
-                            const float* taus1, int n1, hipStream_t st) {
+                            const float* taus1, int n1, int IM, const int* iactive,
+                            hipStream_t st) {
   OneByOne ob;
   ob.n = n1;
   for (int t = 0; t < 16; ++t) {
@@ -127,10 +130,10 @@ hipError_t launch_consensus(const float* Y, int64_t ldY, const float* Dcur, floa
   if (blocks < 1) blocks = 1;
   if (vec)
     hipLaunchKernelGGL(k_consensus_v4, dim3((unsigned)blocks), dim3(256), 0, st, Y, ldY,
-                       Dcur, Dnext, Z, R, M, N, L, invL, ob);
+                       Dcur, Dnext, Z, R, M, N, L, invL, ob, IM, iactive);
   else
     hipLaunchKernelGGL(k_consensus_s, dim3((unsigned)blocks), dim3(256), 0, st, Y, ldY,
-                       Dcur, Dnext, Z, R, M, N, L, invL, ob);
+                       Dcur, Dnext, Z, R, M, N, L, invL, ob, IM, iactive);
   return hipGetLastError();
 }
 
@@ -142,6 +145,49 @@ __global__ void k_zero_ints(int* p, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
 
+__global__ void k_fill_ints(int* p, int v, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_set_int(int* p, int idx, int v) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) p[idx] = v;
+}
+
+__global__ void k_set_u64(unsigned long long* p, int idx, unsigned long long v) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) p[idx] = v;
+}
+
+// Per-instance iteration counters advance for the active instances only.
+__global__ void k_inc_active(int* k, const int* active, int n) {
+  const int z = blockIdx.x * blockDim.x + threadIdx.x;
+  if (z < n && active[z]) k[z] += 1;
+}
+
+hipError_t launch_fill_ints(int* p, int v, size_t count, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  size_t blocks = (count + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(k_fill_ints, dim3((unsigned)blocks), dim3(256), 0, st, p, v, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_int(int* p, int idx, int v, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, p, idx, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_u64(unsigned long long* p, int idx, unsigned long long v, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, st, p, idx, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_inc_active(int* k, const int* active, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_inc_active, dim3((n + 255) / 256), dim3(256), 0, st, k, active, n);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------- register tier (B <= 8)
 // Register tier, live blocks only: one lane per block of the live list built by the
 // stream pass. The block's V is read back from D' = -V (written by the stream pass),
@@ -149,22 +195,23 @@ __global__ void k_zero_ints(int* p, int n) {
 // written back with the dual update.
 template <int B>
 __global__ void __launch_bounds__(256) k_tiny_live(
-    float* __restrict__ Zout, float* __restrict__ Dout, int M, int N, int Q, float tau,
+    float* __restrict__ Zout, float* __restrict__ Dout, ScaleGeom g, float tau,
     ShiftSpec sh, float jtol, int max_sweeps, const int* __restrict__ live_count,
     const int* __restrict__ live_list, unsigned long long* __restrict__ stats) {
-  int sr, sc;
-  resolve_shift(sh, B, B, &sr, &sc);
+  const int N = g.N, Q = g.Q;
   const int count = *live_count;
   const int stride = gridDim.x * blockDim.x;
   for (int it = blockIdx.x * blockDim.x + threadIdx.x; it < count; it += stride) {
     const int b = live_list[it];
     const int p = b / Q;
     const int q = b - p * Q;
+    int sr, sc;
+    block_shift(sh, p / g.PI, B, B, &sr, &sc);
     int rows[B], cols[B];
 #pragma unroll
     for (int i = 0; i < B; ++i) {
-      rows[i] = wrap_add(p * B + i, sr, M);
-      cols[i] = wrap_add(q * B + i, sc, N);
+      rows[i] = grow(g, p, i, sr);
+      cols[i] = gcol(g, q, i, sc);
     }
     float a[B][B], v0[B][B];
 #pragma unroll
@@ -256,11 +303,12 @@ __global__ void __launch_bounds__(256) k_stream(
     int* __restrict__ live_count, int* __restrict__ live_list, float* __restrict__ rowpart,
     float* __restrict__ fropart) {
   extern __shared__ float smem[];
-  const int M = g.M, N = g.N, m = g.m, n = g.n, Q = g.Q;
-  int sr, sc;
-  resolve_shift(sh, m, n, &sr, &sc);
+  const int N = g.N, m = g.m, n = g.n, Q = g.Q;
   const int p = blockIdx.x / sp.spr;
   const int j = blockIdx.x - p * sp.spr;
+  if (!inst_active(sh, p / g.PI)) return;   // uniform: the strip lies in one instance
+  int sr, sc;
+  block_shift(sh, p / g.PI, m, n, &sr, &sc);
   int col0, w, q0 = 0, nq = 1, part = 0;
   if (sp.whole) {
     q0 = j * sp.kb;
@@ -285,8 +333,9 @@ __global__ void __launch_bounds__(256) k_stream(
   for (int e = tid; e < nel; e += 256) {
     const int r = e / w;
     const int c = e - r * w;
-    const int gr = wrap_add(p * m + r, sr, M);
-    const int gc = wrap_add(col0 + c, sc, N);
+    const int gr = grow(g, p, r, sr);
+    int gc = col0 + c + sc;
+    if (gc >= N) gc -= N;
     const int64_t o = (int64_t)gr * N + gc;
     const float v = Zin[o] + (R ? R[o] : 0.f);
     tile[r * ldt + c] = v;
@@ -372,9 +421,10 @@ __global__ void __launch_bounds__(256) k_stream(
 __global__ void __launch_bounds__(256) k_bound_reduce(ScaleGeom g, StreamPlan sp,
                                                       float tau2lim, int* live_count,
                                                       int* live_list, const float* rowpart,
-                                                      const float* fropart) {
+                                                      const float* fropart, ShiftSpec sh) {
   __shared__ float red[256];
   const int blk = blockIdx.x;
+  if (!inst_active(sh, (blk / g.Q) / g.PI)) return;
   const int m = g.m;
   float mx = 0.f;
   for (int r = threadIdx.x; r < m; r += 256) {
@@ -509,7 +559,7 @@ __global__ void __launch_bounds__(1024) k_svd_lds(
     float tau, float jtol, int max_sweeps, const int* __restrict__ live_count,
     const int* __restrict__ live_list, unsigned long long* __restrict__ stats) {
   extern __shared__ float smem[];
-  const int M = g.M, N = g.N, m = g.m, n = g.n, Q = g.Q;
+  const int N = g.N, m = g.m, n = g.n, Q = g.Q;
   const int mb = g.mb, nb = g.nb, trans = g.trans;
   const int nbp = (nb + 1) & ~1;
   const int lda = mb | 1;
@@ -519,8 +569,6 @@ __global__ void __launch_bounds__(1024) k_svd_lds(
   float* gain = W + nbp * ldw;
   int* lcols = reinterpret_cast<int*>(gain + nbp);
   __shared__ int s_k;
-  int sr, sc;
-  resolve_shift(sh, m, n, &sr, &sc);
   const int count = *live_count;
   const int nt = blockDim.x;
   const int tid = threadIdx.x;
@@ -528,11 +576,13 @@ __global__ void __launch_bounds__(1024) k_svd_lds(
     const int blk = live_list[it];
     const int p = blk / Q;
     const int q = blk - p * Q;
+    int sr, sc;
+    block_shift(sh, p / g.PI, m, n, &sr, &sc);
     // gather V = -D' (written by the stream pass) into logical column-major B
     for (int e = tid; e < m * n; e += nt) {
       const int i = e / n;
       const int j = e - i * n;
-      const int64_t o = (int64_t)wrap_add(p * m + i, sr, M) * N + wrap_add(q * n + j, sc, N);
+      const int64_t o = (int64_t)grow(g, p, i, sr) * N + gcol(g, q, j, sc);
       const float v = -Dout[o];
       if (!trans) A[j * lda + i] = v;
       else A[i * lda + j] = v;
@@ -577,7 +627,7 @@ __global__ void __launch_bounds__(1024) k_svd_lds(
         const int l = lcols[t];
         z += gain[l] * A[l * lda + r] * W[l * ldw + c];
       }
-      const int64_t o = (int64_t)wrap_add(p * m + i, sr, M) * N + wrap_add(q * n + j, sc, N);
+      const int64_t o = (int64_t)grow(g, p, i, sr) * N + gcol(g, q, j, sc);
       const float v = -Dout[o];
       Zout[o] = z;
       Dout[o] = 2.f * z - v;
@@ -595,9 +645,7 @@ __global__ void __launch_bounds__(256) k_panel_load(const float* __restrict__ Do
                                                     ShiftSpec sh, const int* live_count,
                                                     const int* live_list, float* pA, int nbp) {
   __shared__ float tile[32][33];
-  const int M = g.M, N = g.N, m = g.m, n = g.n, Q = g.Q, mb = g.mb;
-  int sr, sc;
-  resolve_shift(sh, m, n, &sr, &sc);
+  const int N = g.N, m = g.m, n = g.n, Q = g.Q, mb = g.mb;
   const int count = *live_count;
   const int tilesj = (n + 31) / 32;
   const int ti = blockIdx.x / tilesj;
@@ -607,14 +655,15 @@ __global__ void __launch_bounds__(256) k_panel_load(const float* __restrict__ Do
     const int blk = live_list[it];
     const int p = blk / Q;
     const int q = blk - p * Q;
+    int sr, sc;
+    block_shift(sh, p / g.PI, m, n, &sr, &sc);
     float* A = pA + (int64_t)it * nbp * mb;
     for (int e = threadIdx.x; e < 32 * 32; e += 256) {
       const int ii = e >> 5, jj = e & 31;
       const int i = i0 + ii, j = j0 + jj;
       float v = 0.f;
       if (i < m && j < n) {
-        const int64_t o =
-            (int64_t)wrap_add(p * m + i, sr, M) * N + wrap_add(q * n + j, sc, N);
+        const int64_t o = (int64_t)grow(g, p, i, sr) * N + gcol(g, q, j, sc);
         v = -Dout[o];
       }
       tile[ii][jj] = v;
@@ -764,9 +813,7 @@ __global__ void __launch_bounds__(256) k_panel_rebuild(float* __restrict__ Zout,
   __shared__ int lcols[4096];
   __shared__ float lg[4096];
   __shared__ int s_k;
-  const int M = g.M, N = g.N, m = g.m, n = g.n, Q = g.Q, mb = g.mb, nb = g.nb;
-  int sr, sc;
-  resolve_shift(sh, m, n, &sr, &sc);
+  const int N = g.N, m = g.m, n = g.n, Q = g.Q, mb = g.mb, nb = g.nb;
   const int count = *live_count;
   const int tilesj = (n + 31) / 32;
   const int ti = blockIdx.x / tilesj;
@@ -777,6 +824,8 @@ __global__ void __launch_bounds__(256) k_panel_rebuild(float* __restrict__ Zout,
     const int blk = live_list[it];
     const int p = blk / Q;
     const int q = blk - p * Q;
+    int sr, sc;
+    block_shift(sh, p / g.PI, m, n, &sr, &sc);
     const float* A = pA + (int64_t)it * nbp * mb;
     const float* W = pW + (int64_t)it * nbp * nb;
     const float* gg = pg + (int64_t)it * nbp;
@@ -803,7 +852,7 @@ __global__ void __launch_bounds__(256) k_panel_rebuild(float* __restrict__ Zout,
         const int l = lcols[t];
         z += lg[t] * A[(int64_t)l * mb + r] * W[(int64_t)l * nb + c];
       }
-      const int64_t o = (int64_t)wrap_add(p * m + i, sr, M) * N + wrap_add(q * n + j, sc, N);
+      const int64_t o = (int64_t)grow(g, p, i, sr) * N + gcol(g, q, j, sc);
       const float v = -Dout[o];
       Zout[o] = z;
       Dout[o] = 2.f * z - v;
@@ -896,7 +945,7 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (!sp.whole) {
       hipLaunchKernelGGL(k_bound_reduce, dim3(nblk), dim3(256), 0, st, g, sp, tau2lim,
-                         w.live_count, w.live_list, w.rowpart, w.fropart);
+                         w.live_count, w.live_list, w.rowpart, w.fropart, sh);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
   }
@@ -906,14 +955,14 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
     int blocks = num_cus * 8;
     if (blocks * 256 > nblk) blocks = (nblk + 255) / 256;
     if (g.m == 2)
-      hipLaunchKernelGGL(k_tiny_live<2>, dim3(blocks), dim3(256), 0, st, Zout, Dout, g.M, g.N, g.Q,
-                         tau, sh, jtol, max_sweeps, w.live_count, w.live_list, w.stats);
+      hipLaunchKernelGGL(k_tiny_live<2>, dim3(blocks), dim3(256), 0, st, Zout, Dout, g, tau, sh,
+                         jtol, max_sweeps, w.live_count, w.live_list, w.stats);
     else if (g.m == 4)
-      hipLaunchKernelGGL(k_tiny_live<4>, dim3(blocks), dim3(256), 0, st, Zout, Dout, g.M, g.N, g.Q,
-                         tau, sh, jtol, max_sweeps, w.live_count, w.live_list, w.stats);
+      hipLaunchKernelGGL(k_tiny_live<4>, dim3(blocks), dim3(256), 0, st, Zout, Dout, g, tau, sh,
+                         jtol, max_sweeps, w.live_count, w.live_list, w.stats);
     else
-      hipLaunchKernelGGL(k_tiny_live<8>, dim3(blocks), dim3(256), 0, st, Zout, Dout, g.M, g.N, g.Q,
-                         tau, sh, jtol, max_sweeps, w.live_count, w.live_list, w.stats);
+      hipLaunchKernelGGL(k_tiny_live<8>, dim3(blocks), dim3(256), 0, st, Zout, Dout, g, tau, sh,
+                         jtol, max_sweeps, w.live_count, w.live_list, w.stats);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     MSLD_EV(3); MSLD_EV(4);
     return hipSuccess;
@@ -1037,16 +1086,21 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
 }
 
 // ------------------------------------------------------------------ residual
-// sum_i ||D_i + R - Z_i'||^2 (= sum_i ||X_i - Z_i'||^2) with per-workgroup partials
-// reduced in a fixed order, so the value does not depend on scheduling.
+// sum_i ||D_i + R - Z_i'||^2 (= sum_i ||X_i - Z_i'||^2) per instance, with
+// per-workgroup partials reduced in a fixed order (independent of scheduling).
+// Instance z owns rows [z IM, (z+1) IM) of every plane; grid = (parts, NI).
 __global__ void __launch_bounds__(256) k_resid(const float* __restrict__ Dold,
                                                const float* __restrict__ R,
                                                const float* __restrict__ Z, int64_t MN, int L,
-                                               double* __restrict__ partial) {
+                                               int64_t inst_elems, double* __restrict__ partial) {
   __shared__ double red[256];
+  const int z = blockIdx.y;
   double acc = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < MN; e += stride) {
+  const int64_t base = (int64_t)z * inst_elems;
+  for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e0 < inst_elems;
+       e0 += stride) {
+    const int64_t e = base + e0;
     const float r = R[e];
     float s = 0.f;
     for (int i = 0; i < L; ++i) {
@@ -1061,19 +1115,20 @@ __global__ void __launch_bounds__(256) k_resid(const float* __restrict__ Dold,
     if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) partial[(int64_t)z * gridDim.x + blockIdx.x] = red[0];
 }
 
-__global__ void __launch_bounds__(256) k_sumsq(const float* __restrict__ Y, int64_t ldY, int M,
+__global__ void __launch_bounds__(256) k_sumsq(const float* __restrict__ Y, int64_t ldY, int IM,
                                                int N, double* __restrict__ partial) {
   __shared__ double red[256];
+  const int z = blockIdx.y;
   double acc = 0.0;
-  const int64_t MN = (int64_t)M * N;
+  const int64_t total = (int64_t)IM * N;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < MN; e += stride) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
     const int64_t r = e / N;
     const int64_t c = e - r * N;
-    const float y = Y[r * ldY + c];
+    const float y = Y[((int64_t)z * IM + r) * ldY + c];
     acc += (double)y * (double)y;
   }
   red[threadIdx.x] = acc;
@@ -1082,33 +1137,33 @@ __global__ void __launch_bounds__(256) k_sumsq(const float* __restrict__ Y, int6
     if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) partial[(int64_t)z * gridDim.x + blockIdx.x] = red[0];
 }
 
-__global__ void k_final_sum(const double* partial, int nparts, double* out) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    double s = 0.0;
-    for (int i = 0; i < nparts; ++i) s += partial[i];
-    out[0] = s;
-  }
+__global__ void k_final_sum(const double* partial, int nparts, int NI, double* out) {
+  const int z = blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= NI) return;
+  double s = 0.0;
+  for (int i = 0; i < nparts; ++i) s += partial[(int64_t)z * nparts + i];
+  out[z] = s;
 }
 
 hipError_t launch_resid(const float* Dold, const float* R, const float* Z, int M, int N, int L,
-                        double* partial, int nparts, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_resid, dim3(nparts), dim3(256), 0, st, Dold, R, Z, (int64_t)M * N, L,
-                     partial);
+                        int IM, int NI, double* partial, int nparts, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_resid, dim3(nparts, NI), dim3(256), 0, st, Dold, R, Z, (int64_t)M * N, L,
+                     (int64_t)IM * N, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(64), 0, st, partial, nparts, out);
+  hipLaunchKernelGGL(k_final_sum, dim3((NI + 63) / 64), dim3(64), 0, st, partial, nparts, NI, out);
   return hipGetLastError();
 }
 
-hipError_t launch_sumsq(const float* Y, int64_t ldY, int M, int N, double* partial, int nparts,
-                        double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_sumsq, dim3(nparts), dim3(256), 0, st, Y, ldY, M, N, partial);
+hipError_t launch_sumsq(const float* Y, int64_t ldY, int IM, int N, int NI, double* partial,
+                        int nparts, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_sumsq, dim3(nparts, NI), dim3(256), 0, st, Y, ldY, IM, N, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(64), 0, st, partial, nparts, out);
+  hipLaunchKernelGGL(k_final_sum, dim3((NI + 63) / 64), dim3(64), 0, st, partial, nparts, NI, out);
   return hipGetLastError();
 }
 
@@ -1129,8 +1184,11 @@ __global__ void k_device_shifts(uint64_t seed, int k0, int count, int L, Ladder1
   sh.scale = i;
   sh.mode = 1;
   sh.sr = sh.sc = 0;
+  sh.iseed = nullptr;
+  sh.ik = nullptr;
+  sh.iactive = nullptr;
   int sr, sc;
-  resolve_shift(sh, lad.m[i], lad.n[i], &sr, &sc);
+  block_shift(sh, 0, lad.m[i], lad.n[i], &sr, &sc);
   out[2 * t] = sr;
   out[2 * t + 1] = sc;
 }

@@ -574,9 +574,7 @@ __global__ void __launch_bounds__(256) k_lr_rebuild(float* __restrict__ Zout,
                                                     const float* Vr, const float* sig,
                                                     float tau) {
   __shared__ float gl[P];
-  const int M = g.M, N = g.N, m = g.m, n = g.n, Q = g.Q, mb = g.mb, nb = g.nb;
-  int sr, sc;
-  resolve_shift(sh, m, n, &sr, &sc);
+  const int N = g.N, m = g.m, n = g.n, Q = g.Q, mb = g.mb, nb = g.nb;
   const int slot = blockIdx.y;
   if (!pflag[4 * slot + 2]) return;
   if (threadIdx.x < P) {
@@ -586,6 +584,8 @@ __global__ void __launch_bounds__(256) k_lr_rebuild(float* __restrict__ Zout,
   __syncthreads();
   const int blk = live_list[slot];
   const int p = blk / Q, q = blk - p * Q;
+  int sr, sc;
+  block_shift(sh, p / g.PI, m, n, &sr, &sc);
   const float* af = Af + (int64_t)slot * mb * P;
   const float* vr = Vr + (int64_t)slot * nb * P;
   const int tilesj = (n + 31) / 32;
@@ -599,7 +599,7 @@ __global__ void __launch_bounds__(256) k_lr_rebuild(float* __restrict__ Zout,
 #pragma unroll
     for (int l = 0; l < P; ++l)
       if (gl[l] > 0.f) z += gl[l] * af[l * mb + r] * vr[l * nb + c];
-    const int64_t o = (int64_t)wrap_add2(p * m + i, sr, M) * N + wrap_add2(q * n + j, sc, N);
+    const int64_t o = (int64_t)grow(g, p, i, sr) * N + gcol(g, q, j, sc);
     const float v = -Dout[o];
     Zout[o] = z;
     Dout[o] = 2.f * z - v;

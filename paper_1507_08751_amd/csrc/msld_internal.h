@@ -26,19 +26,26 @@ __host__ __device__ inline void cycle_shift(uint64_t seed, int k, int i, int m, 
   *sc = (int)((z & 0xFFFFFFFFull) % (uint64_t)n);
 }
 
-// Shift of one scale for one launch: either fixed (sr, sc) or derived on device
-// from (seed, k, scale) so that graph replays can advance k in device memory.
+// Shift of one scale for one launch: none, hashed from (seed, k, scale) on device,
+// or explicit (sr, sc). Several independent instances of one shape can be stacked
+// along the rows of one set of planes; then each instance z has its own seed and
+// iteration counter (iseed[z], ik[z], device arrays) and an active flag.
 struct ShiftSpec {
   uint64_t seed;
   int k;          // iteration
   int scale;      // scale index i
   int mode;       // 0: none, 1: hashed from (seed, k, scale), 2: explicit (sr, sc)
   int sr, sc;
+  const unsigned long long* iseed;  // per-instance seeds (null: seed)
+  const int* ik;                    // per-instance iteration (null: k)
+  const int* iactive;               // per-instance active flag (null: all active)
 };
 
-__device__ inline void resolve_shift(const ShiftSpec& s, int m, int n, int* sr, int* sc) {
+__device__ inline void block_shift(const ShiftSpec& s, int z, int m, int n, int* sr, int* sc) {
   if (s.mode == 1) {
-    cycle_shift(s.seed, s.k, s.scale, m, n, sr, sc);
+    const uint64_t seed = s.iseed ? (uint64_t)s.iseed[z] : s.seed;
+    const int k = s.ik ? s.ik[z] : s.k;
+    cycle_shift(seed, k, s.scale, m, n, sr, sc);
   } else if (s.mode == 2) {
     *sr = s.sr;
     *sc = s.sc;
@@ -48,17 +55,38 @@ __device__ inline void resolve_shift(const ShiftSpec& s, int m, int n, int* sr, 
   }
 }
 
+__device__ inline bool inst_active(const ShiftSpec& s, int z) {
+  return s.iactive == nullptr || s.iactive[z] != 0;
+}
+
 // ------------------------------------------------------------------ plans
 enum Tier { TIER_1X1 = 0, TIER_REG = 1, TIER_LDS = 2, TIER_PANEL = 3 };
 
-// Geometry of one scale's partition.
+// Geometry of one scale's partition. M counts the rows of all stacked instances
+// (NI instances of IM rows each, IM = M for a single instance); P = NI * PI block rows.
 struct ScaleGeom {
-  int M, N;       // matrix
+  int M, N;       // stacked matrix
   int m, n;       // block
-  int P, Q;       // blocks per column / row of blocks
+  int P, Q;       // blocks per column / row of blocks (all instances)
   int trans;      // 1 if the logical block B is the transpose of the stored block
   int mb, nb;     // logical block rows / columns, mb >= nb (B = block or block^T)
+  int IM, PI, NI; // rows and block rows per instance, number of instances
 };
+
+// Stacked row of row i of block row p under a row shift sr: the shift wraps inside
+// the block's own instance (Shift_s of Sec. 9 applied per instance).
+__device__ inline int grow(const ScaleGeom& g, int p, int i, int sr) {
+  const int z = p / g.PI;
+  int local = (p - z * g.PI) * g.m + i + sr;
+  if (local >= g.IM) local -= g.IM;
+  return z * g.IM + local;
+}
+
+__device__ inline int gcol(const ScaleGeom& g, int q, int j, int sc) {
+  int c = q * g.n + j + sc;
+  if (c >= g.N) c -= g.N;
+  return c;
+}
 
 // Per-scale device buffers and counters.
 struct ScaleWork {
@@ -109,7 +137,8 @@ struct StreamPlan {
 hipError_t launch_fill(float* p, float v, size_t count, hipStream_t st);
 hipError_t launch_consensus(const float* Y, int64_t ldY, const float* Dcur, float* Dnext,
                             float* Z, float* R, int M, int N, int L, const int* scales1,
-                            const float* taus1, int n1, hipStream_t st);
+                            const float* taus1, int n1, int IM, const int* iactive,
+                            hipStream_t st);
 // ev (optional, 5 events): recorded before the scale pass, after the stream pass,
 // before the panel rounds, after the panel rounds and after the whole pass.
 hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, ScaleWork& w,
@@ -121,9 +150,11 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
                        const ShiftSpec& sh, float jtol, int count, int* fallback_host,
                        hipStream_t st);
 __global__ void k_zero_ints(int* p, int n);
+// Per-instance sums (instance z = rows [z IM, (z+1) IM)): out[z].
 hipError_t launch_resid(const float* Dold, const float* R, const float* Z, int M, int N,
-                        int L, double* partial, int nparts, double* out, hipStream_t st);
-hipError_t launch_sumsq(const float* Y, int64_t ldY, int M, int N, double* partial,
+                        int L, int IM, int NI, double* partial, int nparts, double* out,
+                        hipStream_t st);
+hipError_t launch_sumsq(const float* Y, int64_t ldY, int IM, int N, int NI, double* partial,
                         int nparts, double* out, hipStream_t st);
 hipError_t launch_device_shifts(uint64_t seed, int k0, int count, int L, const int* bm,
                                 const int* bn, int* out, hipStream_t st);

@@ -1,0 +1,98 @@
+// Host-side runtime shared by the C-ABI entry points (api.cpp) and the serving loop
+// (server.cpp): per-scale plans, the solver object and the ADMM iteration driver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/msld.h"
+#include "msld_internal.h"
+
+namespace msld {
+
+constexpr size_t kLdsTierMax = 150 * 1024;   // LDS budget of one workgroup (160 KiB per CU)
+constexpr int kStreamFloats = 16384;         // stream-pass tile budget (floats)
+constexpr int kLRP = 16;                     // subspace width of the certified low-rank path
+
+int lds_tier_threads(int nb, int mb, int* G);
+size_t lds_tier_bytes(int mb, int nb);
+size_t stream_lds_bytes(int m, const StreamPlan& sp);
+hipError_t launch_fill_ints(int* p, int v, size_t count, hipStream_t st);
+hipError_t launch_set_int(int* p, int idx, int v, hipStream_t st);
+hipError_t launch_inc_active(int* k, const int* active, int n, hipStream_t st);
+
+// Plan of one problem shape, for ninst instances stacked along the rows.
+struct Plan {
+  ScaleGeom geom[MSLD_MAX_SCALES];
+  StreamPlan sp[MSLD_MAX_SCALES];
+  int tier[MSLD_MAX_SCALES];
+  int pw[MSLD_MAX_SCALES];
+  int nbp[MSLD_MAX_SCALES];
+  int use_lr[MSLD_MAX_SCALES];
+  float tau_default[MSLD_MAX_SCALES];
+  int ninst;
+  int resid_parts;
+  size_t bytes;
+  // byte offsets inside the arena
+  size_t off_R, off_D, off_part, off_res, off_shift, off_inst;
+  size_t off_count[MSLD_MAX_SCALES], off_list[MSLD_MAX_SCALES], off_rowp[MSLD_MAX_SCALES],
+      off_frop[MSLD_MAX_SCALES], off_stats[MSLD_MAX_SCALES], off_pA[MSLD_MAX_SCALES],
+      off_pW[MSLD_MAX_SCALES], off_pflag[MSLD_MAX_SCALES], off_pg[MSLD_MAX_SCALES],
+      off_lr[MSLD_MAX_SCALES];
+};
+
+msld_status validate_params(const msld_params* p);
+msld_status make_plan(const msld_params* p, int ninst, Plan* pl);
+bool same_class(const msld_params& a, const msld_params& b);
+
+}  // namespace msld
+
+// The solver: workspace and state of ninst stacked instances of one shape.
+struct msld_solver {
+  msld_params p;
+  msld::Plan plan;
+  hipStream_t st;
+  int device;
+  int num_cus;
+  bool failed;
+  char* arena;
+  double* host_res;   // pinned: [0, ninst) residual sums, [ninst, 2 ninst) ||Y||^2
+  int* host_ints;     // pinned, 2 per scale
+  rocblas_handle blas;
+  msld::ScaleWork work[MSLD_MAX_SCALES];
+  int ninst;
+  int k;              // next iteration (single instance; stacked instances use d_k)
+  int cur;            // which D buffer holds the current D_i
+  unsigned long long* d_seed;   // [ninst] per-instance shift seeds (stacked only)
+  int* d_k;                     // [ninst] per-instance iteration counters
+  int* d_active;                // [ninst] active flags
+  // profiling: per iteration 2 consensus events + 5 events per scale
+  int prof_cap, prof_n;
+  hipEvent_t* prof_ev;
+  int64_t round_launches[MSLD_MAX_SCALES];
+};
+
+namespace msld {
+
+msld_status create_solver(const msld_params* p, int ninst, hipStream_t st, msld_solver** out);
+msld_status dev_err(msld_solver* s, hipError_t e);
+float* plane_R(msld_solver* s);
+float* plane_D(msld_solver* s, int which);
+size_t plane_elems(const msld_solver* s);   // elements of one stacked plane
+// One ADMM iteration on all active instances; with want_res the per-instance
+// residual sums land in device memory (dres[z]).
+msld_status iterate_once(msld_solver* s, const float* d_Y, int64_t ldY, float* d_Z,
+                         bool want_res);
+double* dev_res(msld_solver* s);
+msld_status launch_ynorms(msld_solver* s, const float* d_Y, int64_t ldY);
+
+}  // namespace msld
+
+#define MSLD_TRY(s, call)                                   \
+  do {                                                      \
+    hipError_t e_ = (call);                                 \
+    if (e_ != hipSuccess) return msld::dev_err((s), e_);    \
+  } while (0)
