@@ -102,6 +102,8 @@ typedef struct msld_result {
   uint64_t certified[MSLD_MAX_SCALES];
   uint64_t fail_coupling[MSLD_MAX_SCALES];
   uint64_t fail_bound[MSLD_MAX_SCALES];
+  uint64_t polar[MSLD_MAX_SCALES];        /* failed certificates finished by the polar route */
+  uint64_t polar_steps[MSLD_MAX_SCALES];  /* its Newton-Schulz steps (polar + sign, per chunk) */
 } msld_result;
 
 typedef struct msld_solver msld_solver; /* opaque */

@@ -47,7 +47,9 @@ class Result(ctypes.Structure):
                 ("rank", ctypes.c_uint64 * MAX_SCALES),
                 ("certified", ctypes.c_uint64 * MAX_SCALES),
                 ("fail_coupling", ctypes.c_uint64 * MAX_SCALES),
-                ("fail_bound", ctypes.c_uint64 * MAX_SCALES)]
+                ("fail_bound", ctypes.c_uint64 * MAX_SCALES),
+                ("polar", ctypes.c_uint64 * MAX_SCALES),
+                ("polar_steps", ctypes.c_uint64 * MAX_SCALES)]
 
 
 EXPORTS = {
@@ -231,7 +233,9 @@ class Solver:
                      "rank": list(res.rank)[:self.L],
                      "certified": list(res.certified)[:self.L],
                      "fail_coupling": list(res.fail_coupling)[:self.L],
-                     "fail_bound": list(res.fail_bound)[:self.L]}
+                     "fail_bound": list(res.fail_bound)[:self.L],
+                "polar": list(res.polar)[:self.L],
+                "polar_steps": list(res.polar_steps)[:self.L]}
 
     def _check_yz(self, Y, Z):
         torch = self._torch
@@ -265,7 +269,9 @@ class Solver:
                 "sweeps": list(res.sweeps)[:self.L], "rank": list(res.rank)[:self.L],
                 "certified": list(res.certified)[:self.L],
                 "fail_coupling": list(res.fail_coupling)[:self.L],
-                "fail_bound": list(res.fail_bound)[:self.L]}
+                "fail_bound": list(res.fail_bound)[:self.L],
+                "polar": list(res.polar)[:self.L],
+                "polar_steps": list(res.polar_steps)[:self.L]}
 
     def profile_begin(self, max_iters):
         _check(self._lib.msld_profile_begin(self._h, int(max_iters)), "msld_profile_begin")

@@ -1,6 +1,7 @@
 // C-ABI runtime: parameter validation, per-scale planning, workspace arena, the ADMM
 // driver loop (Sec. 7 eq:admm with the random cycle spinning of Sec. 9) and batched
 // solves of many independent instances grouped by shape.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -164,7 +165,16 @@ msld_status make_plan(const msld_params* p, int ninst, Plan* pl) {
         const size_t nb2 = (size_t)g.nb * g.nb;
         const size_t per = 3 * nb2 + 4 * (size_t)g.nb * kLRP + (size_t)g.mb * kLRP +
                            (size_t)kLRP * g.nb + 2 * kLRP + 8;
-        pl->off_lr[i] = take(4 * ((size_t)nblk * per + (size_t)g.nb * kLRP + 64 + nblk));
+        pl->off_lr[i] = take(4 * ((size_t)nblk * per + (size_t)g.nb * kLRP + 64 + 2 * nblk));
+        if (!lds_fits(g.mb, g.nb)) {
+          // polar fallback buffers for a chunk of failed certificates (<= 256 MiB)
+          const size_t pper = 3 * (size_t)g.mb * g.nb + 4 * nb2 + 4;
+          size_t cap = ((size_t)256 << 20) / (4 * pper);
+          if (cap < 1) cap = 1;
+          if (cap > (size_t)nblk) cap = (size_t)nblk;
+          pl->pl_cap[i] = (int)cap;
+          pl->off_pl[i] = take(4 * cap * pper);
+        }
       }
     }
   }
@@ -201,6 +211,7 @@ static void destroy_solver(msld_solver* s) {
   if (s->arena) (void)hipFree(s->arena);
   if (s->host_res) (void)hipHostFree(s->host_res);
   if (s->host_ints) (void)hipHostFree(s->host_ints);
+  if (s->host_pl) (void)hipHostFree(s->host_pl);
   delete s;
 }
 
@@ -240,6 +251,15 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
           hipSuccess) {
     destroy_solver(s);
     return MSLD_ENOMEM;
+  }
+  {
+    int cap = 0;
+    for (int i = 0; i < p->L; ++i) cap = std::max(cap, s->plan.pl_cap[i]);
+    if (cap > 0 && hipHostMalloc(&s->host_pl, 4 * (size_t)cap * sizeof(float),
+                                 hipHostMallocDefault) != hipSuccess) {
+      destroy_solver(s);
+      return MSLD_ENOMEM;
+    }
   }
   const Plan& pl = s->plan;
   s->d_seed = reinterpret_cast<unsigned long long*>(s->arena + pl.off_inst);
@@ -298,6 +318,21 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
         w.lrCount = reinterpret_cast<int*>(f);
         w.lrFall = w.lrCount + 64;
         w.lds_fallback = lds_fits(g.mb, g.nb) ? 1 : 0;
+        if (pl.pl_cap[i] > 0) {
+          const size_t cap = (size_t)pl.pl_cap[i];
+          const size_t x = (size_t)g.mb * g.nb;
+          float* q = reinterpret_cast<float*>(s->arena + pl.off_pl[i]);
+          w.plCap = pl.pl_cap[i];
+          w.plX0 = q; q += cap * x;
+          w.plXa = q; q += cap * x;
+          w.plXb = q; q += cap * x;
+          w.plT = q; q += cap * nb2;
+          w.plS = q; q += cap * nb2;
+          w.plY = q; q += cap * nb2;
+          w.plW = q; q += cap * nb2;
+          w.plScal = q;
+          w.hostPl = s->host_pl;
+        }
       }
     }
   }
@@ -319,8 +354,10 @@ static msld_status run_scale(msld_solver* s, int i, const float* Zin, const floa
 }
 
 static msld_status zero_stats(msld_solver* s) {
-  for (int i = 0; i < s->p.L; ++i)
+  for (int i = 0; i < s->p.L; ++i) {
     MSLD_TRY(s, hipMemsetAsync(s->work[i].stats, 0, 8 * 8, s->st));
+    for (long long& v : s->work[i].stats_host) v = 0;
+  }
   return MSLD_OK;
 }
 
@@ -424,6 +461,8 @@ static msld_status fill_stats(msld_solver* s, msld_result* info) {
     info->certified[i] = st8[3];
     info->fail_coupling[i] = st8[4];
     info->fail_bound[i] = st8[5];
+    info->polar[i] = (uint64_t)s->work[i].stats_host[0];
+    info->polar_steps[i] = (uint64_t)(s->work[i].stats_host[1] + s->work[i].stats_host[2]);
   }
   return MSLD_OK;
 }

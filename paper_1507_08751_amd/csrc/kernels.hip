@@ -1025,6 +1025,12 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
     MSLD_EV(4);
     return hipSuccess;
   }
+  if (w.use_lr && !w.lds_fallback) {
+    // failed certificates of blocks beyond the LDS tier: exact polar-route SVT
+    if ((e = run_polar(g, w, Zout, Dout, tau, sh, fallback, st)) != hipSuccess) return e;
+    MSLD_EV(4);
+    return hipSuccess;
+  }
   if (w.use_lr && w.lds_fallback) {
     // blocks that failed the certificate and fit in LDS: one-sided Jacobi LDS tier
     int G = 1;

@@ -517,14 +517,20 @@ __device__ __forceinline__ void lr_certify(int slot, const float* sig, float tau
   atomicAdd(&stats[3], 1ull);
 }
 
-__device__ __forceinline__ void lr_fallback(int slot, int* pflag, int* counts, int* fall,
-                                            const int* live_list) {
+// A slot whose certificate failed: its block id goes to fall[] (LDS Jacobi fallback) and
+// its slot index to fall[slots + f] (polar fallback); scal[5] keeps the remainder bound
+// on lambda_max(E^T E), or -1 when the coupling test failed (no deflation possible).
+__device__ __forceinline__ void lr_fallback(int slot, int slots, int* pflag, int* counts,
+                                            int* fall, const int* live_list, float* scal,
+                                            float bound) {
   pflag[4 * slot + 2] = 0;
+  scal[slot * 8 + 5] = bound;
   const int f = atomicAdd(&counts[0], 1);
   fall[f] = live_list[slot];
+  fall[slots + f] = slot;
 }
 
-__global__ void k_lr_decide(int count, const float* scal, const float* sig, float tau,
+__global__ void k_lr_decide(int count, int slots, float* scal, const float* sig, float tau,
                             int* pflag, int* counts, int* fall, const int* live_list,
                             unsigned long long* stats, int stage, int power) {
   const int slot = blockIdx.x * blockDim.x + threadIdx.x;
@@ -536,7 +542,7 @@ __global__ void k_lr_decide(int count, const float* scal, const float* sig, floa
     pflag[4 * slot + 3] = 0;
     const bool c_ok = c2 <= kCouplingTol * kCouplingTol * trG && isfinite(c2) && isfinite(trE);
     if (!c_ok) {
-      lr_fallback(slot, pflag, counts, fall, live_list);
+      lr_fallback(slot, slots, pflag, counts, fall, live_list, scal, -1.f);
       atomicAdd(&stats[4], 1ull);
       return;
     }
@@ -556,7 +562,7 @@ __global__ void k_lr_decide(int count, const float* scal, const float* sig, floa
       lr_certify(slot, sig, tau, pflag, stats);
     } else if (stage == 2) {
       pflag[4 * slot + 3] = 0;
-      lr_fallback(slot, pflag, counts, fall, live_list);
+      lr_fallback(slot, slots, pflag, counts, fall, live_list, scal, isfinite(bp) ? bp : -1.f);
       atomicAdd(&stats[5], 1ull);
     } else {
       atomicAdd(&counts[1], 1);   // still undecided after this stage
@@ -607,13 +613,22 @@ __global__ void __launch_bounds__(256) k_lr_rebuild(float* __restrict__ Zout,
 }
 
 // ------------------------------------------------------------------ driver
+hipError_t batched_sgemm(void* blas, bool ta, bool tb, int m, int n, int k, const float* A,
+                         int lda, int64_t sa, const float* B, int ldb, int64_t sb, float* C,
+                         int ldc, int64_t sc, int batch) {
+  const float one = 1.f, zero = 0.f;
+  rocblas_status s = rocblas_sgemm_strided_batched(
+      reinterpret_cast<rocblas_handle>(blas), ta ? rocblas_operation_transpose : rocblas_operation_none,
+      tb ? rocblas_operation_transpose : rocblas_operation_none, m, n, k, &one, A, lda, sa, B, ldb,
+      sb, &zero, C, ldc, sc, batch);
+  return s == rocblas_status_success ? hipSuccess : hipErrorLaunchFailure;
+}
+
 static hipError_t gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m,
                        int n, int k, const float* A, int lda, int64_t sa, const float* B, int ldb,
                        int64_t sb, float* C, int ldc, int64_t sc, int batch) {
-  const float one = 1.f, zero = 0.f;
-  rocblas_status s = rocblas_sgemm_strided_batched(h, ta, tb, m, n, k, &one, A, lda, sa, B, ldb,
-                                                   sb, &zero, C, ldc, sc, batch);
-  return s == rocblas_status_success ? hipSuccess : hipErrorLaunchFailure;
+  return batched_sgemm(h, ta == rocblas_operation_transpose, tb == rocblas_operation_transpose,
+                       m, n, k, A, lda, sa, B, ldb, sb, C, ldc, sc, batch);
 }
 
 hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout, float tau,
@@ -705,7 +720,7 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
   hipLaunchKernelGGL(k_lr_ge_reduce, dim3((count + 255) / 256), dim3(256), 0, st, w.lrQ, tiles,
                      count, w.lrScal);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_lr_decide, dim3((count + 255) / 256), dim3(256), 0, st, count, w.lrScal,
+  hipLaunchKernelGGL(k_lr_decide, dim3((count + 255) / 256), dim3(256), 0, st, count, w.slots, w.lrScal,
                      w.lrSig, tau, w.pflag, w.lrCount, w.lrFall, w.live_list, w.stats, 0, 1);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = hipMemcpyAsync(w.hostInts + 1, w.lrCount + 1, sizeof(int), hipMemcpyDeviceToHost,
@@ -731,15 +746,16 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
         power *= 2;
       }
       const int ftiles = tiles;
-      hipLaunchKernelGGL(k_lr_frob_part, dim3(ftiles, count), dim3(256), 0, st, a, nb, w.lrT);
+      // partials go to lrY (free after stage 0); lrT keeps A_f^T B for the polar route
+      hipLaunchKernelGGL(k_lr_frob_part, dim3(ftiles, count), dim3(256), 0, st, a, nb, w.lrY);
       if ((e = hipGetLastError()) != hipSuccess) return e;
-      hipLaunchKernelGGL(k_lr_frob_reduce, dim3((count + 255) / 256), dim3(256), 0, st, w.lrT,
+      hipLaunchKernelGGL(k_lr_frob_reduce, dim3((count + 255) / 256), dim3(256), 0, st, w.lrY,
                          ftiles, count, w.lrScal, 3);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, w.lrCount + 1, 1);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       hipLaunchKernelGGL(k_lr_decide, dim3((count + 255) / 256), dim3(256), 0, st, count,
-                         w.lrScal, w.lrSig, tau, w.pflag, w.lrCount, w.lrFall, w.live_list,
+                         w.slots, w.lrScal, w.lrSig, tau, w.pflag, w.lrCount, w.lrFall, w.live_list,
                          w.stats, stage, power);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       if (stage == 1) {

@@ -120,9 +120,22 @@ struct ScaleWork {
   float* lrScal;        // [slots][8]
   float* lrOm;          // [nb*p] probe matrix
   int* lrCount;         // [4] device counters: fallback, undecided
-  int* lrFall;          // [slots] block ids that fall back to Jacobi
+  int* lrFall;          // [2 slots] block ids, then slot indices, of failed certificates
   int lds_fallback;     // 1: fallback blocks fit the LDS Jacobi tier
   int* hostInts;        // pinned host ints [2]
+  // polar fallback (polar.hip) for failed certificates of blocks beyond the LDS tier;
+  // buffers hold plCap compacted blocks
+  int plCap;
+  float* plX0;          // [plCap][mb*nb] E' / alpha, later the thresholded block
+  float* plXa;          // [plCap][mb*nb] Newton-Schulz iterates
+  float* plXb;
+  float* plT;           // [plCap][nb*nb]
+  float* plS;
+  float* plY;
+  float* plW;
+  float* plScal;        // [plCap][4] alpha, alpha_S, deflated, ||B||_F
+  float* hostPl;        // pinned host copy of plScal
+  long long stats_host[3];   // polar blocks, polar steps, sign steps (host counters)
 };
 
 struct StreamPlan {
@@ -146,6 +159,11 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
                         float tau, const ShiftSpec& sh, float jtol, int max_sweeps,
                         int panel_sweeps, int num_cus, hipStream_t st, hipEvent_t* ev,
                         int* round_launches);
+hipError_t batched_sgemm(void* blas, bool ta, bool tb, int m, int n, int k, const float* A,
+                         int lda, int64_t sa, const float* B, int ldb, int64_t sb, float* C,
+                         int ldc, int64_t sc, int batch);
+hipError_t run_polar(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout, float tau,
+                     const ShiftSpec& sh, int nfall, hipStream_t st);
 hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout, float tau,
                        const ShiftSpec& sh, float jtol, int count, int* fallback_host,
                        hipStream_t st);

@@ -41,7 +41,8 @@ struct Plan {
   size_t off_count[MSLD_MAX_SCALES], off_list[MSLD_MAX_SCALES], off_rowp[MSLD_MAX_SCALES],
       off_frop[MSLD_MAX_SCALES], off_stats[MSLD_MAX_SCALES], off_pA[MSLD_MAX_SCALES],
       off_pW[MSLD_MAX_SCALES], off_pflag[MSLD_MAX_SCALES], off_pg[MSLD_MAX_SCALES],
-      off_lr[MSLD_MAX_SCALES];
+      off_lr[MSLD_MAX_SCALES], off_pl[MSLD_MAX_SCALES];
+  int pl_cap[MSLD_MAX_SCALES];   // polar fallback chunk (0: none)
 };
 
 msld_status validate_params(const msld_params* p);
@@ -61,6 +62,7 @@ struct msld_solver {
   char* arena;
   double* host_res;   // pinned: [0, ninst) residual sums, [ninst, 2 ninst) ||Y||^2
   int* host_ints;     // pinned, 2 per scale
+  float* host_pl;     // pinned, 4 per polar chunk slot (largest chunk of any scale)
   rocblas_handle blas;
   msld::ScaleWork work[MSLD_MAX_SCALES];
   int ninst;

@@ -34,7 +34,7 @@ def test_struct_layout_matches_header():
     # int32 M,N,L; 16+16 int32; 16 float; rho,max_iters,tol,check_every,cycle_spin,lowrank_min; u64
     assert ctypes.sizeof(msld.Params) == 4 * 3 + 4 * 48 + 4 * 6 + 8 + 4  # +4 alignment pad
     assert msld.Params.shift_seed.offset % 8 == 0
-    assert ctypes.sizeof(msld.Result) == 4 + 4 + 8 + 6 * 8 * 16
+    assert ctypes.sizeof(msld.Result) == 4 + 4 + 8 + 8 * 8 * 16
 
 
 def test_status_strings():

@@ -143,6 +143,61 @@ def test_lowrank_path_certifies_low_rank_blocks(lib, M, N, m, n):
     solver.close()
 
 
+def _clustered_block(rng, m, n, tau, kind):
+    """A block whose spectrum defeats the low-rank certificate: a few large singular
+    values over a bulk packed just below and just above tau ("bulk"), or a dense
+    spectrum with far more than 16 values above tau ("dense")."""
+    k = min(m, n)
+    U, _ = np.linalg.qr(rng.standard_normal((m, k)))
+    W, _ = np.linalg.qr(rng.standard_normal((n, k)))
+    if kind in ("bulk", "bulk_below"):
+        top = 1.03 if kind == "bulk" else 0.99
+        s = np.concatenate([tau * np.array([25.0, 9.0, 3.0]),
+                            tau * rng.uniform(0.6, top, k - 3)])
+    else:
+        s = tau * rng.uniform(0.0, 3.0, k)
+    return (U * s) @ W.T
+
+
+@pytest.mark.parametrize("M,N,m,n,kind", [(512, 512, 256, 256, "bulk"),
+                                          (1024, 1024, 512, 512, "bulk"),
+                                          (512, 512, 256, 256, "bulk_below"),
+                                          (512, 1024, 512, 512, "bulk_below"),
+                                          (256, 1024, 256, 512, "bulk"),
+                                          (1024, 512, 512, 256, "dense"),
+                                          (512, 512, 512, 512, "dense")])
+def test_polar_fallback_parity(lib, M, N, m, n, kind):
+    """Blocks whose certificate fails (a bulk of singular values crowding tau, or more
+    live values than the subspace holds) are finished by the polar route and must
+    still match the oracle to 1e-4. With the bulk entirely below tau the coupling
+    test passes and the remainder bound fails, so the deflated route is taken."""
+    rng = np.random.default_rng(M + 3 * N + m + (kind == "dense"))
+    s = (int(rng.integers(0, m)), int(rng.integers(0, n)))
+    tau = 2.0
+    V64 = np.zeros((M, N))
+    for p in range(M // m):
+        for q in range(N // n):
+            rows = (p * m + s[0] + np.arange(m)) % M
+            cols = (q * n + s[1] + np.arange(n)) % N
+            V64[np.ix_(rows, cols)] = _clustered_block(rng, m, n, tau, kind)
+    V = V64.astype(np.float32)
+    ref = O.cycle_spun_bsvt(V.astype(np.float64), m, n, tau, s)
+    solver = lib.Solver(M, N, [(m, n)], iters=1, lowrank_min=64)
+    assert lib.TIERS[solver.tier(0)] == "lowrank"
+    Z = solver.bsvt(0, torch.from_numpy(V).cuda(), tau, s)
+    torch.cuda.synchronize()
+    st = solver.stats()
+    err = rel_err(Z.cpu().numpy(), ref, np.linalg.norm(V))
+    print(f"polar {kind} {M}x{N} / {m}x{n}: err {err:.2e} decomposed {st['live']} certified "
+          f"{st['certified']} fail coupling {st['fail_coupling']} bound {st['fail_bound']} "
+          f"polar {st['polar']} steps {st['polar_steps']}", flush=True)
+    assert err <= 1e-4
+    assert st["polar"][0] > 0
+    if kind == "bulk_below":
+        assert st["fail_bound"][0] > 0
+    solver.close()
+
+
 @pytest.mark.parametrize("case", ["zero", "tau0", "huge_tau", "rank_deficient", "repeated_sigma",
                                   "near_tau"])
 def test_bsvt_edge_cases(lib, case):
