@@ -25,7 +25,6 @@ METRIC = "ADMM iters/s (8192², 5 scales) + served solves/s, p99 lat @ relerr≤
 LADDER = [(1, 1), (8, 8), (32, 32), (128, 128), (512, 512)]
 DENSITY = 0.01
 NOISE = 0.01
-PEAK_FP32_VALU_TFLOPS = 157.3   # MI355X published FP32 vector peak
 PEAK_HBM_GBS = 8000.0
 
 
@@ -33,11 +32,74 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def jacobi_flops(mb, nb, sweeps, rank):
-    """Algorithmic flops of one-sided Jacobi on mb x nb blocks (mb >= nb): per sweep
-    nb(nb-1)/2 pairs, each 3 inner products (6 mb), a rotation of two columns of B
-    (6 mb) and of W (6 nb); plus the rank-k rebuild 2 mb nb k."""
-    return sweeps * 3.0 * nb * (nb - 1) * (2 * mb + nb) + 2.0 * mb * nb * rank
+STREAM_BYTES_PER_ELEM = 16     # k_stream: read Z_i and R, write Z_i' and D_i'
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_stream__8192x8192_5scales_traffic.md")
+
+
+def consensus_bytes_per_elem(L, n1x1):
+    """k_consensus: read Y and the L planes D_i; write R; for each 1x1 scale read Z_i
+    and write Z_i' and D_i'."""
+    return 4 * (1 + L + 1 + 3 * n1x1)
+
+
+def kernels_source_digest():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_1507_08751_amd", "csrc", "kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per k_stream launch from the committed rocprofv3 counter summary:
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the stream kernel, each scaled by
+    what the same counter reads for a plain copy of known size. None when the summary
+    is missing or was taken on a different kernels.hip."""
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            kv = dict(line.strip("- `\n").split(": ", 1) for line in f
+                      if line.startswith("- `") and ": " in line)
+        if kv.get("kernels.hip digest") != kernels_source_digest():
+            return None
+        fr = float(kv["copy bytes read"]) / (1024.0 * float(kv["copy FETCH_SIZE KiB"]))
+        fw = float(kv["copy bytes written"]) / (1024.0 * float(kv["copy WRITE_SIZE KiB"]))
+        return (1024.0 * float(kv["k_stream FETCH_SIZE KiB"]) * fr
+                + 1024.0 * float(kv["k_stream WRITE_SIZE KiB"]) * fw)
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def stream_roofline(prof, tiers, M, N, K):
+    """Roofline of the dominant kernel, the stream pass (one launch per decomposed scale
+    and iteration), from its HIP-event times; and of the consensus pass."""
+    idx = [i for i, t in enumerate(tiers) if t != "1x1"]
+    launches = K * len(idx)
+    avg_ms = sum(prof["scale_ms"][i][0] for i in idx) / max(1, launches)
+    nbytes = STREAM_BYTES_PER_ELEM * M * N
+    gbs = nbytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": measured_traffic(),
+            "kernel": "k_stream", "launches": launches, "avg_launch_ms": round(avg_ms, 4),
+            "algorithmic_bytes_per_launch": nbytes}
+    n1 = sum(1 for t in tiers if t == "1x1")
+    cbytes = consensus_bytes_per_elem(len(tiers), n1) * M * N
+    cms = prof["consensus_ms"] / K
+    cgbs = cbytes / (cms * 1e-3) / 1e9 if cms > 0 else 0.0
+    extra = {"bound": "hbm", "achieved": round(cgbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+             "frac": round(cgbs / PEAK_HBM_GBS, 4), "kernel": "k_consensus",
+             "avg_launch_ms": round(cms, 4), "algorithmic_bytes_per_launch": cbytes}
+    return roof, extra
+
+
+def copy_calibration(nbytes=1 << 30, reps=3):
+    """Plain device-to-device copies of nbytes: what FETCH_SIZE / WRITE_SIZE read for
+    a kernel that moves a known number of bytes."""
+    import torch
+    dev = torch.device("cuda", 0)
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "copy", "bytes_per_copy": nbytes, "copies": reps}), flush=True)
 
 
 def cpu_baseline(size, threads_env):
@@ -202,8 +264,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--size", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=2048)
-    ap.add_argument("--mode", choices=["iters", "serve", "batch"], default="iters")
+    ap.add_argument("--cpu-sample", type=int, default=4096)
+    ap.add_argument("--mode", choices=["iters", "serve", "batch", "copy"], default="iters",
+                    help="copy: a plain device copy of known size, the calibration run for "
+                         "the HBM byte counters")
     ap.add_argument("--instances", type=int, default=256)
     ap.add_argument("--requests", type=int, default=64)
     ap.add_argument("--warm-requests", type=int, default=8)
@@ -219,6 +283,9 @@ def main():
         return
     if args.mode == "batch":
         batch_bench(args)
+        return
+    if args.mode == "copy":
+        copy_calibration()
         return
 
     import numpy as np
@@ -258,37 +325,15 @@ def main():
     ips = K / sec
     log(f"timed {K} iterations: {sec:.3f} s -> {ips:.2f} iters/s; resid after K+1: {r:.3e}")
     log(f"consensus ms total {prof['consensus_ms']:.2f}")
-    best = None
     for i, (m, n) in enumerate(LADDER):
         ms = prof["scale_ms"][i]
         nblk = (M // m) * (N // n)
         log(f"scale {i} ({m}x{n}, {tiers[i]}): stream {ms[0]:.2f} setup {ms[1]:.2f} "
-            f"jacobi {ms[2]:.2f} finish {ms[3]:.2f} ms; live {stats['live'][i]} of {nblk * K} "
+            f"svd {ms[2]:.2f} finish {ms[3]:.2f} ms; live {stats['live'][i]} of {nblk * K} "
             f"block-iters, sweeps {stats['sweeps'][i]}, rank {stats['rank'][i]}, "
             f"certified {stats['certified'][i]} (fail coupling {stats['fail_coupling'][i]}, "
-            f"bound {stats['fail_bound'][i]}), round launches {prof['round_launches'][i]}")
-        if tiers[i] in ("lds", "panel") and (best is None or ms[2] > best[1]):
-            best = (i, ms[2])
-    roof = None
-    if best is not None:
-        i, jac_ms = best
-        m, n = LADDER[i]
-        mb, nb = max(m, n), min(m, n)
-        flops = jacobi_flops(mb, nb, stats["sweeps"][i], stats["rank"][i])
-        if tiers[i] == "panel":
-            launches = max(1, prof["round_launches"][i])
-            kname = "k_panel_round"
-        else:
-            launches = K
-            kname = "k_svd_lds"
-        avg_ms = jac_ms / launches
-        achieved = flops / launches / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
-        roof = {"bound": "alu", "achieved": round(achieved, 3),
-                "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 5), "traffic": None,
-                "kernel": kname, "scale_block": f"{m}x{n}", "launches": launches,
-                "avg_launch_ms": round(avg_ms, 4),
-                "algorithmic_flops_per_launch": flops / launches}
+            f"bound {stats['fail_bound'][i]}, polar {stats['polar'][i]})")
+    roof, extra = stream_roofline(prof, tiers, M, N, K)
     out = {"metric": METRIC, "value": round(ips, 4), "unit": "iters/s", "n_gpus": 1, "steps": K,
            "warmup": W, "ms_per_step": round(1e3 * sec / K, 3), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -296,7 +341,11 @@ def main():
                                   f"rank-1 blocks per scale + N(0,0.01^2) noise, default lambda, "
                                   f"rho=1, random cycle spinning, {K} iterations from zero",
                       "M": M, "N": N, "ladder": [list(b) for b in LADDER], "iters": K},
-           "roofline": roof}
+           "roofline": roof, "roofline_consensus": extra,
+           "phases_ms_per_iter": {
+               "consensus": round(prof["consensus_ms"] / K, 4),
+               **{f"scale{i}_{m}x{n}_{tiers[i]}": [round(v / K, 4) for v in prof["scale_ms"][i]]
+                  for i, (m, n) in enumerate(LADDER) if tiers[i] != "1x1"}}}
     if not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         log(f"cpu baseline: oracle on {args.cpu_sample}^2 with {threads} threads ...")

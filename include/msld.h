@@ -69,8 +69,10 @@ typedef enum {
  *                 SVT (subspace iteration on the Gram matrix, one-sided Jacobi on the
  *                 reduced block, and an a-posteriori certificate that bounds the
  *                 error by the non-expansiveness of the prox; blocks that fail it
- *                 fall back to panel Jacobi). 0 selects the default (128); a
- *                 negative value disables the path. Results agree to rounding. */
+ *                 get an exact SVT: the LDS Jacobi tier, or the polar route for
+ *                 blocks too large for LDS). Blocks up to 128 x 128 use a fused
+ *                 one-kernel version. 0 selects the default (32); a negative value
+ *                 disables the path. Results agree to rounding. */
 typedef struct msld_params {
   int32_t M, N, L;
   int32_t block_m[MSLD_MAX_SCALES];
@@ -139,16 +141,18 @@ msld_status msld_step(msld_solver *s, const float *d_Y, int64_t ldY, float *d_Z,
  * last msld_reset (primal_resid is -1: use msld_step to obtain it). Synchronises. */
 msld_status msld_stats(msld_solver *s, msld_result *info);
 
-/* Kernel timing with HIP events on the handle's stream. msld_profile_begin(s, n)
+/* Kernel timing with HIP events on the streams that run each part (the consensus on
+ * the handle's stream, each scale on its own stream). msld_profile_begin(s, n)
  * creates events for the next n iterations (each iteration records them as it is
  * enqueued; later iterations are not recorded). msld_profile_end synchronises and
  * returns elapsed milliseconds summed over the recorded iterations in
- * ms[(L + 1) * 4]: for scale i, ms[4i + 0] the stream/bound pass (or the whole
- * register-tier kernel), ms[4i + 1] the set-up of the SVD pass, ms[4i + 2] the
- * Jacobi kernels (LDS tier kernel, or all panel-round launches), ms[4i + 3] the
- * rest (gains, rebuild); ms[4L] the consensus pass. round_launches[L] receives the
- * number of panel-round kernel launches per scale, *iters_recorded the number of
- * iterations covered. */
+ * ms[(L + 1) * 4]: for scale i, ms[4i + 0] the stream kernel (shifted gather, bound
+ * test, speculative write), ms[4i + 1] the rest of the set-up (bound reduction,
+ * panel load), ms[4i + 2] the SVD kernels (register / LDS / fused low-rank kernel,
+ * the batched low-rank path, or all panel-round launches), ms[4i + 3] the rest
+ * (fallbacks, gains, rebuild); ms[4L] the consensus pass. Scales run concurrently,
+ * so their times overlap. round_launches[L] receives the number of panel-round
+ * kernel launches per scale, *iters_recorded the number of iterations covered. */
 msld_status msld_profile_begin(msld_solver *s, int32_t max_iters);
 msld_status msld_profile_end(msld_solver *s, double *ms, int64_t *round_launches,
                              int32_t *iters_recorded);
@@ -255,7 +259,9 @@ void msld_server_free(msld_server *sv);
 
 /* Kernel tier the plan chose for scale i: 0 = 1x1 (fused in the consensus pass),
  * 1 = register tier (blocks up to 8 x 8), 2 = LDS tier, 3 = HBM panel tier,
- * 4 = certified low-rank path with panel fallback. Returns -1 for an invalid index. */
+ * 4 = certified low-rank path on batched GEMMs (failures: LDS tier or polar route),
+ * 5 = fused certified low-rank kernel for blocks up to 64 x 128 (failures: LDS
+ * tier). Returns -1 for an invalid index. */
 int32_t msld_scale_tier(const msld_solver *s, int32_t scale);
 
 #ifdef __cplusplus

@@ -15,7 +15,7 @@ __all__ = ["load", "Solver", "Batch", "Server", "solve", "bsvt", "cycle_shift", 
            "MAX_SCALES", "TIERS", "MsldError"]
 
 MAX_SCALES = 16
-TIERS = {0: "1x1", 1: "register", 2: "lds", 3: "panel", 4: "lowrank"}
+TIERS = {0: "1x1", 1: "register", 2: "lds", 3: "panel", 4: "lowrank", 5: "lowrank_small"}
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmsld.so")
 
 _lib = None

@@ -110,11 +110,17 @@ msld_status make_plan(const msld_params* p, int ninst, Plan* pl) {
     const double lam = p->lambda[i] > 0.f ? (double)p->lambda[i] : lambda_default(IM, N, m, n);
     pl->tau_default[i] = (float)(lam / (double)p->rho);
     const int nblk = g.P * g.Q;
-    const int lr_min = p->lowrank_min == 0 ? 128 : p->lowrank_min;
-    const bool lr = lr_min > 0 && g.nb >= lr_min && g.nb >= 4 * kLRP;
+    // certified low-rank paths: fused per-block kernel up to 64 x 128 (falls back to
+    // the LDS tier), batched-GEMM path beyond (falls back to the polar route)
+    const int lr_min = p->lowrank_min == 0 ? 32 : p->lowrank_min;
+    int sNB, sMB, sP;
+    const bool lrs = lr_min > 0 && g.nb >= lr_min && lr_small_shape(g.mb, g.nb, &sNB, &sMB, &sP) &&
+                     lds_fits(g.mb, g.nb) && lr_small_lds_bytes(sNB, sMB, sP) <= kLdsTierMax;
+    const bool lr = !lrs && lr_min > 0 && g.nb >= lr_min && g.nb >= 4 * kLRP;
     int tier;
     if (m == 1 && n == 1) tier = TIER_1X1;
     else if (m == n && (m == 2 || m == 4 || m == 8)) tier = TIER_REG;
+    else if (lrs) tier = TIER_LRS;
     else if (!lr && lds_fits(g.mb, g.nb)) tier = TIER_LDS;
     else tier = TIER_PANEL;
     pl->use_lr[i] = lr ? 1 : 0;
@@ -147,6 +153,7 @@ msld_status make_plan(const msld_params* p, int ninst, Plan* pl) {
       pl->off_rowp[i] = take(4 * (size_t)nblk * sp.spb * m);
       pl->off_frop[i] = take(4 * (size_t)nblk * sp.spb);
     }
+    if (tier == TIER_LRS) pl->off_lr[i] = take(4 * (64 + (size_t)nblk));   // fallback list
     if (tier == TIER_PANEL) {
       // panel width: two panels of A (mb rows) and W (nb rows) in LDS; 4 <= pw <= 64
       int pw = (int)(kLdsTierMax / 4 / (2 * ((size_t)(g.mb | 1) + (size_t)(g.nb | 1))));
@@ -164,8 +171,8 @@ msld_status make_plan(const msld_params* p, int ninst, Plan* pl) {
       if (lr) {
         const size_t nb2 = (size_t)g.nb * g.nb;
         const size_t per = 3 * nb2 + 4 * (size_t)g.nb * kLRP + (size_t)g.mb * kLRP +
-                           (size_t)kLRP * g.nb + 2 * kLRP + 8;
-        pl->off_lr[i] = take(4 * ((size_t)nblk * per + (size_t)g.nb * kLRP + 64 + 2 * nblk));
+                           (size_t)kLRP * g.nb + 3 * kLRP + 8;
+        pl->off_lr[i] = take(4 * ((size_t)nblk * per + (size_t)g.nb * kLRP + 64 + 3 * nblk));
         if (!lds_fits(g.mb, g.nb)) {
           // polar fallback buffers for a chunk of failed certificates (<= 256 MiB)
           const size_t pper = 3 * (size_t)g.mb * g.nb + 4 * nb2 + 4;
@@ -207,7 +214,15 @@ static void destroy_solver(msld_solver* s) {
       (void)hipEventDestroy(s->prof_ev[e]);
     std::free(s->prof_ev);
   }
-  if (s->blas) (void)rocblas_destroy_handle(s->blas);
+  for (int i = 0; i < MSLD_MAX_SCALES; ++i) {
+    if (s->blas[i]) (void)rocblas_destroy_handle(s->blas[i]);
+    if (s->sst[i]) {
+      (void)hipStreamSynchronize(s->sst[i]);
+      (void)hipStreamDestroy(s->sst[i]);
+    }
+    if (s->ev_join[i]) (void)hipEventDestroy(s->ev_join[i]);
+  }
+  if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
   if (s->arena) (void)hipFree(s->arena);
   if (s->host_res) (void)hipHostFree(s->host_res);
   if (s->host_ints) (void)hipHostFree(s->host_ints);
@@ -265,12 +280,32 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
   s->d_seed = reinterpret_cast<unsigned long long*>(s->arena + pl.off_inst);
   s->d_k = reinterpret_cast<int*>(s->d_seed + ninst);
   s->d_active = s->d_k + ninst;
-  bool need_blas = false;
-  for (int i = 0; i < p->L; ++i) need_blas = need_blas || pl.use_lr[i];
-  if (need_blas) {
-    if (rocblas_create_handle(&s->blas) != rocblas_status_success ||
-        rocblas_set_stream(s->blas, s->st) != rocblas_status_success ||
-        rocblas_set_atomics_mode(s->blas, rocblas_atomics_not_allowed) != rocblas_status_success) {
+  if (hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming) != hipSuccess) {
+    s->ev_fork = nullptr;
+    destroy_solver(s);
+    return MSLD_EDEVICE;
+  }
+  for (int i = 0; i < p->L; ++i) {
+    if (pl.tier[i] == TIER_1X1) continue;   // fused in the consensus pass
+    if (hipStreamCreateWithFlags(&s->sst[i], hipStreamNonBlocking) != hipSuccess) {
+      s->sst[i] = nullptr;
+      destroy_solver(s);
+      return MSLD_EDEVICE;
+    }
+    if (hipEventCreateWithFlags(&s->ev_join[i], hipEventDisableTiming) != hipSuccess) {
+      s->ev_join[i] = nullptr;
+      destroy_solver(s);
+      return MSLD_EDEVICE;
+    }
+    if (!pl.use_lr[i]) continue;
+    if (rocblas_create_handle(&s->blas[i]) != rocblas_status_success) {
+      s->blas[i] = nullptr;
+      destroy_solver(s);
+      return MSLD_EDEVICE;
+    }
+    if (rocblas_set_stream(s->blas[i], s->sst[i]) != rocblas_status_success ||
+        rocblas_set_atomics_mode(s->blas[i], rocblas_atomics_not_allowed) !=
+            rocblas_status_success) {
       destroy_solver(s);
       return MSLD_EDEVICE;
     }
@@ -288,6 +323,10 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
         w.fropart = reinterpret_cast<float*>(s->arena + pl.off_frop[i]);
       }
     }
+    if (pl.tier[i] == TIER_LRS) {
+      w.lrCount = reinterpret_cast<int*>(s->arena + pl.off_lr[i]);
+      w.lrFall = w.lrCount + 64;
+    }
     if (pl.tier[i] == TIER_PANEL) {
       const ScaleGeom& g = pl.geom[i];
       w.pA = reinterpret_cast<float*>(s->arena + pl.off_pA[i]);
@@ -302,7 +341,7 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
         const size_t slots = (size_t)w.slots;
         float* f = reinterpret_cast<float*>(s->arena + pl.off_lr[i]);
         w.use_lr = 1;
-        w.blas = s->blas;
+        w.blas = s->blas[i];
         w.lrG = f; f += slots * nb2;
         w.lrP = f; f += slots * nb2;
         w.lrQ = f; f += slots * nb2;
@@ -312,7 +351,7 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
         w.lrV = f; f += slots * g.nb * kLRP;
         w.lrC = f; f += slots * g.mb * kLRP;
         w.lrT = f; f += slots * kLRP * g.nb;
-        w.lrSig = f; f += 2 * slots * kLRP;   // sigma, then the deflation mask
+        w.lrSig = f; f += 3 * slots * kLRP;   // sigma, deflation mask, bound mask
         w.lrScal = f; f += slots * 8;
         w.lrOm = f; f += (size_t)g.nb * kLRP;
         w.lrCount = reinterpret_cast<int*>(f);
@@ -342,14 +381,27 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
 
 static float jacobi_tol(int mb) { return 4.0f * 5.9604645e-8f * std::sqrt((float)mb); }
 
+// Scale i's BlockSVT on its own stream; the caller forks it from s->st (after the
+// consensus) and joins it back.
 static msld_status run_scale(msld_solver* s, int i, const float* Zin, const float* R, float* Zout,
                              float* Dout, float tau, const ShiftSpec& sh, hipEvent_t* ev) {
   const Plan& pl = s->plan;
   const ScaleGeom& g = pl.geom[i];
   int rl = 0;
   MSLD_TRY(s, launch_scale(g, pl.tier[i], pl.sp[i], s->work[i], Zin, R, Zout, Dout, tau, sh,
-                           jacobi_tol(g.mb), 40, 20, s->num_cus, s->st, ev, &rl));
+                           jacobi_tol(g.mb), 40, 20, s->num_cus, s->sst[i], ev, &rl));
   if (ev) s->round_launches[i] += rl;
+  return MSLD_OK;
+}
+
+static msld_status fork_scale(msld_solver* s, int i) {
+  MSLD_TRY(s, hipStreamWaitEvent(s->sst[i], s->ev_fork, 0));
+  return MSLD_OK;
+}
+
+static msld_status join_scale(msld_solver* s, int i) {
+  MSLD_TRY(s, hipEventRecord(s->ev_join[i], s->sst[i]));
+  MSLD_TRY(s, hipStreamWaitEvent(s->st, s->ev_join[i], 0));
   return MSLD_OK;
 }
 
@@ -390,8 +442,17 @@ msld_status iterate_once(msld_solver* s, const float* d_Y, int64_t ldY, float* d
   MSLD_TRY(s, launch_consensus(d_Y, ldY, Dc, Dn, d_Z, R, M, N, L, scales1, taus1, n1, IM,
                                stacked ? s->d_active : nullptr, s->st));
   if (ev) MSLD_TRY(s, hipEventRecord(ev[1], s->st));
-  for (int i = 0; i < L; ++i) {
-    if (pl.tier[i] == TIER_1X1) continue;
+  MSLD_TRY(s, hipEventRecord(s->ev_fork, s->st));
+  // scales whose host driver never waits go first, so that their work is queued
+  // before a low-rank scale's host-side waits (live and fallback counts) begin
+  int order[MSLD_MAX_SCALES], no = 0;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int i = 0; i < L; ++i)
+      if (pl.tier[i] != TIER_1X1 && (pl.use_lr[i] != 0) == (pass == 1)) order[no++] = i;
+  for (int oi = 0; oi < no; ++oi) {
+    const int i = order[oi];
+    msld_status fs = fork_scale(s, i);
+    if (fs != MSLD_OK) return fs;
     ShiftSpec sh;
     sh.seed = p.shift_seed;
     sh.k = s->k;
@@ -404,6 +465,8 @@ msld_status iterate_once(msld_solver* s, const float* d_Y, int64_t ldY, float* d
     float* Zi = d_Z + MN * i;
     msld_status rs = run_scale(s, i, Zi, R, Zi, Dn + MN * i, pl.tau_default[i], sh,
                                ev ? ev + 2 + 5 * i : nullptr);
+    if (rs != MSLD_OK) return rs;
+    rs = join_scale(s, i);
     if (rs != MSLD_OK) return rs;
   }
   if (want_res) {
@@ -655,7 +718,11 @@ msld_status msld_bsvt(msld_solver* s, int32_t scale, const float* d_V, float* d_
   }
   msld_status zs = zero_stats(s);
   if (zs != MSLD_OK) return zs;
-  return run_scale(s, scale, d_V, nullptr, d_Z, Dws, tau, sh, nullptr);
+  MSLD_TRY(s, hipEventRecord(s->ev_fork, s->st));
+  msld_status rs = fork_scale(s, scale);
+  if (rs == MSLD_OK) rs = run_scale(s, scale, d_V, nullptr, d_Z, Dws, tau, sh, nullptr);
+  if (rs == MSLD_OK) rs = join_scale(s, scale);
+  return rs;
 }
 
 msld_status msld_device_shifts(msld_solver* s, int32_t k0, int32_t count, int32_t* out) {

@@ -329,18 +329,44 @@ __global__ void __launch_bounds__(256) k_stream(
   float* cq = cs + sp.ws + 1;               // w column squares
   unsigned* smax = reinterpret_cast<unsigned*>(cq + sp.ws + 1);  // nq row maxima
   const int tid = threadIdx.x;
-  const int nel = m * w;
-  for (int e = tid; e < nel; e += 256) {
-    const int r = e / w;
-    const int c = e - r * w;
-    const int gr = grow(g, p, r, sr);
+  // strips are at most 256 columns wide (the plan caps them): thread (row group rq,
+  // column c) walks rows rq, rq + rpp, ...; kU rows are loaded before any is stored,
+  // so every thread keeps 2 kU loads in flight
+  {
+    constexpr int kU = 8;
+    const int rpp = 256 / w;
+    const int c = tid % w;
+    const int rq = tid / w;
     int gc = col0 + c + sc;
     if (gc >= N) gc -= N;
-    const int64_t o = (int64_t)gr * N + gc;
-    const float v = Zin[o] + (R ? R[o] : 0.f);
-    tile[r * ldt + c] = v;
-    Zout[o] = 0.f;
-    Dout[o] = -v;
+    const bool act = rq < rpp;
+    const int z = p / g.PI;
+    const int rbase = (p - z * g.PI) * m + sr;   // instance-local row of block row 0
+    const int64_t zoff = (int64_t)z * g.IM;
+    for (int r0 = rq; act && r0 < m; r0 += kU * rpp) {
+      float v[kU];
+      int64_t o[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int r = r0 + u * rpp;
+        o[u] = -1;
+        v[u] = 0.f;
+        if (r < m) {
+          int lr = rbase + r;
+          if (lr >= g.IM) lr -= g.IM;
+          o[u] = (zoff + lr) * N + gc;
+          v[u] = Zin[o[u]] + (R ? R[o[u]] : 0.f);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        if (o[u] >= 0) {
+          tile[(r0 + u * rpp) * ldt + c] = v[u];
+          Zout[o[u]] = 0.f;
+          Dout[o[u]] = -v[u];
+        }
+      }
+    }
   }
   if (tid < nq) smax[tid] = 0u;
   __syncthreads();
@@ -930,7 +956,6 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
                         const ShiftSpec& sh, float jtol, int max_sweeps, int panel_sweeps,
                         int num_cus, hipStream_t st, hipEvent_t* ev, int* round_launches) {
   hipError_t e;
-  MSLD_EV(0);
   const double tl = (double)tau * (double)tau *
                     (1.0 - 2.0 * (double)(g.m + g.n + 4) * (double)kEps);
   const float tau2lim = (float)tl;
@@ -940,16 +965,17 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
   if ((e = hipGetLastError()) != hipSuccess) return e;
   {
     const size_t lds = stream_lds_bytes(g.m, sp);
+    MSLD_EV(0);   // events 0-1 bracket the stream kernel alone
     hipLaunchKernelGGL(k_stream, dim3(g.P * sp.spr), dim3(256), lds, st, Zin, R, Zout, Dout, g,
                        sp, sh, tau2lim, w.live_count, w.live_list, w.rowpart, w.fropart);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    MSLD_EV(1);
     if (!sp.whole) {
       hipLaunchKernelGGL(k_bound_reduce, dim3(nblk), dim3(256), 0, st, g, sp, tau2lim,
                          w.live_count, w.live_list, w.rowpart, w.fropart, sh);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
   }
-  MSLD_EV(1);
   if (tier == TIER_REG) {
     MSLD_EV(2);
     int blocks = num_cus * 8;
@@ -965,6 +991,38 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
                          jtol, max_sweeps, w.live_count, w.live_list, w.stats);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     MSLD_EV(3); MSLD_EV(4);
+    return hipSuccess;
+  }
+  if (tier == TIER_LRS) {
+    // fused certified low-rank kernel, then the LDS Jacobi tier on its failures
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, w.lrCount);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    MSLD_EV(2);
+    if ((e = launch_lr_small(g, w, Zout, Dout, tau, sh, num_cus, st)) != hipSuccess) return e;
+    MSLD_EV(3);
+    int G = 1;
+    const int threads = lds_tier_threads(g.nb, g.mb, &G);
+    const size_t ldsb = lds_tier_bytes(g.mb, g.nb);
+    int per_cu = (int)(160 * 1024 / (ldsb + 1024));
+    const int by_waves = 32 / ((threads + 63) / 64);
+    if (per_cu > by_waves) per_cu = by_waves;
+    if (per_cu > 2) per_cu = 2;   // failures are rare: a small persistent grid suffices
+    if (per_cu < 1) per_cu = 1;
+    int grid = num_cus * per_cu;
+    if (grid > nblk) grid = nblk;
+    ScaleWork fw = w;
+    fw.live_count = w.lrCount;
+    fw.live_list = w.lrFall;
+    switch (G) {
+      case 1: e = launch_lds_g<1>(grid, threads, ldsb, Zout, Dout, g, sh, tau, jtol, max_sweeps, fw, st); break;
+      case 2: e = launch_lds_g<2>(grid, threads, ldsb, Zout, Dout, g, sh, tau, jtol, max_sweeps, fw, st); break;
+      case 4: e = launch_lds_g<4>(grid, threads, ldsb, Zout, Dout, g, sh, tau, jtol, max_sweeps, fw, st); break;
+      case 8: e = launch_lds_g<8>(grid, threads, ldsb, Zout, Dout, g, sh, tau, jtol, max_sweeps, fw, st); break;
+      case 16: e = launch_lds_g<16>(grid, threads, ldsb, Zout, Dout, g, sh, tau, jtol, max_sweeps, fw, st); break;
+      default: e = launch_lds_g<32>(grid, threads, ldsb, Zout, Dout, g, sh, tau, jtol, max_sweeps, fw, st); break;
+    }
+    if (e != hipSuccess) return e;
+    MSLD_EV(4);
     return hipSuccess;
   }
   if (tier == TIER_LDS) {
@@ -1010,9 +1068,13 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
     hipLaunchKernelGGL(k_panel_load, dim3(tiles, slots_y), dim3(256), 0, st, Dout, g, sh,
                        w.live_count, w.live_list, w.pA, w.nbp);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_panel_init, dim3(64, slots_y), dim3(256), 0, st, g, w.live_count, w.pA,
-                       w.pW, w.pflag, w.nbp);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (!w.use_lr) {
+      // rotation accumulators and padding for the panel rounds (the low-rank path and
+      // its fallbacks use neither, and write every flag they read)
+      hipLaunchKernelGGL(k_panel_init, dim3(64, slots_y), dim3(256), 0, st, g, w.live_count,
+                         w.pA, w.pW, w.pflag, w.nbp);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
   }
   MSLD_EV(2);
   if (w.use_lr) {

@@ -5,18 +5,22 @@
 // G = B^T B finds an orthonormal X (nb x p); one-sided Jacobi on B X gives
 // B V_r = A_f (orthogonal columns a_l = sigma_l u_l) with V_r = X W. Let L be the
 // columns with sigma_l > tau (live), plus those with tau/2 < sigma_l <= tau whose own
-// coupling ||u_l^T B - sigma_l v_l^T|| is tiny, and E = B (I - V_L V_L^T). The result
-// Z = sum_{l in L} max(1 - tau/sigma_l, 0) a_l v_l^T is accepted only if
-//   (i)  sigma_max(E) <= tau, checked with the upper bound
-//        lambda_max(E^T E) <= tr(E^T E) * ||(E^T E / tr)^8||_F^(1/8), and
-//   (ii) ||U_L^T E||_F is below a small fraction of ||B||_F.
-// Then B0 = U_L S_L V_L^T + (I - U_L U_L^T) E decouples, SVT(B0) = Z (columns of L
+// coupling c_l = ||u_l^T B - sigma_l v_l^T|| is tiny, and E_L = B (I - V_L V_L^T). The
+// result Z = sum_{l in L} max(1 - tau/sigma_l, 0) a_l v_l^T is accepted only if
+//   (i)  sigma_max(E_L) <= tau, checked with the upper bound
+//        lambda_max(E_L^T E_L) <= max(max_{l in K} sigma_l^2, lambda_max(E^T E))
+//                                 + (sum_{l in K} sigma_l^2 c_l^2)^(1/2)
+//        (K: further well-converged directions outside L, E = B (I - V V^T) the
+//        remainder after L and K; a 2 x 2 block split of E_L^T E_L), with
+//        lambda_max(E^T E) <= tr * ||(E^T E / tr)^k||_F^(1/k) for k = 1, 2, 8, and
+//   (ii) ||U_L^T E_L||_F is below a small fraction of ||B||_F.
+// Then B0 = U_L S_L V_L^T + (I - U_L U_L^T) E_L decouples, SVT(B0) = Z (columns of L
 // below tau threshold to zero), and since the proximal map is non-expansive
-// ||SVT(B) - Z||_F <= ||B - B0||_F = ||U_L^T E||_F.
-// Blocks that fail either test go to the panel Jacobi path. The plain matrix
-// products (Gram, subspace products, squarings) are rocBLAS batched GEMMs; the
-// orthonormalisation, the small Jacobi SVD, the certificate and the rebuild are the
-// kernels below.
+// ||SVT(B) - Z||_F <= ||B - B0||_F = ||U_L^T E_L||_F.
+// Blocks that fail either test get an exact SVT: the LDS Jacobi tier when they fit
+// in LDS, else the polar route (polar.hip). The plain matrix products (Gram, subspace
+// products, squarings) are rocBLAS batched GEMMs; the orthonormalisation, the small
+// Jacobi SVD, the certificate and the rebuild are the kernels below.
 #include <rocblas/rocblas.h>
 
 #include "msld_internal.h"
@@ -144,8 +148,11 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
-// Same orthonormalisation with one wave per slot and the columns held in registers
-// (lane l owns rows l + 64 r, r < RPL): no LDS and no workgroup barriers.
+// Orthonormalisation with one wave per slot and the columns held in registers
+// (lane l owns rows l + 64 r, r < RPL): no LDS and no workgroup barriers. Classical
+// Gram-Schmidt with exactly two projection passes ("twice is enough"); a column whose
+// norm drops below half in both passes is numerically dependent and set to zero. The
+// fixed pass count keeps every register index static.
 template <int P, int RPL>
 __global__ void __launch_bounds__(256) k_lr_orth_w(const float* Y, float* X, int nb,
                                                    int64_t stride, int count) {
@@ -168,42 +175,38 @@ __global__ void __launch_bounds__(256) k_lr_orth_w(const float* Y, float* X, int
 #pragma unroll
     for (int r = 0; r < RPL; ++r) n0 += v[j][r] * v[j][r];
     n0 = wave_sum(n0);
-    float nprev = n0;
-    bool dependent = j > 0;
+    float nn = n0;
+    bool kept = true;
     if (j > 0) {
-      for (int pass = 0; pass < 4; ++pass) {
+      kept = false;
+      float nprev = n0;
+#pragma unroll
+      for (int pass = 0; pass < 2; ++pass) {
         float c[P];
 #pragma unroll
-        for (int i = 0; i < P; ++i) {
-          if (i < j) {
-            float sdot = 0.f;
+        for (int i = 0; i < j; ++i) {
+          float sdot = 0.f;
 #pragma unroll
-            for (int r = 0; r < RPL; ++r) sdot += v[i][r] * v[j][r];
-            c[i] = wave_sum(sdot);
-          }
+          for (int r = 0; r < RPL; ++r) sdot += v[i][r] * v[j][r];
+          c[i] = wave_sum(sdot);
         }
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
           float t = v[j][r];
 #pragma unroll
-          for (int i = 0; i < P; ++i)
-            if (i < j) t -= c[i] * v[i][r];
+          for (int i = 0; i < j; ++i) t -= c[i] * v[i][r];
           v[j][r] = t;
         }
-        float nn = 0.f;
+        float s = 0.f;
 #pragma unroll
-        for (int r = 0; r < RPL; ++r) nn += v[j][r] * v[j][r];
-        nn = wave_sum(nn);
-        const bool done = nn >= 0.25f * nprev;
+        for (int r = 0; r < RPL; ++r) s += v[j][r] * v[j][r];
+        nn = wave_sum(s);
+        kept = kept || nn >= 0.25f * nprev;
         nprev = nn;
-        if (done) {
-          dependent = false;
-          break;
-        }
       }
     }
-    const float nrm = sqrtf(nprev);
-    const bool keep = !dependent && nrm > 1e-30f && nprev > 1e-12f * n0;
+    const float nrm = sqrtf(nn);
+    const bool keep = kept && nrm > 1e-30f && nn > 1e-12f * n0;
     const float inv = keep ? 1.f / nrm : 0.f;
 #pragma unroll
     for (int r = 0; r < RPL; ++r) v[j][r] *= inv;
@@ -324,12 +327,17 @@ __global__ void __launch_bounds__(256) k_lr_jacobi(float* C, const float* X, flo
 }
 
 // Per direction l: c_l^2 = || T_l / sigma_l - sigma_l v_l^T ||^2 with T = A_f^T B
-// (= ||u_l^T E||^2). Deflation mask: live (sigma > tau) always; near-live
-// (tau/2 < sigma <= tau) when c_l <= 0.3 tol ||B||_F. scal[1] = sum of c_l^2 over the mask.
+// (= ||u_l^T B - sigma_l v_l^T||^2). Deflation set L (mask): live (sigma > tau) always;
+// near-live (tau/2 < sigma <= tau) when c_l <= 0.3 tol ||B||_F. scal[1] = sum of c_l^2
+// over L. For the remainder bound, other well-converged directions l' (not in L, with
+// sigma_l^2 c_l^2 <= (1e-3 tau^2)^2) are split off too: dmask marks L and them,
+// scal[7] = max sigma_l'^2 (with a relative allowance for the residual
+// non-orthogonality of the rotated columns) and scal[6] = sum sigma_l'^2 c_l'^2.
 template <int P>
 __global__ void __launch_bounds__(256) k_lr_coupling(const float* T, const float* sig,
                                                      const float* Vr, int nb, float tau,
-                                                     float tol, float* scal, float* mask) {
+                                                     float tol, float* scal, float* mask,
+                                                     float* dmask) {
   __shared__ float red[8];
   __shared__ float cl[P];
   const int slot = blockIdx.x;
@@ -338,7 +346,7 @@ __global__ void __launch_bounds__(256) k_lr_coupling(const float* T, const float
   const float* sg = sig + slot * P;
   for (int l = 0; l < P; ++l) {
     const float s = sg[l];
-    if (!(s > 0.5f * tau)) {          // uniform branch: sg is shared by all threads
+    if (!(s > 0.f)) {                 // uniform branch: sg is shared by all threads
       if (threadIdx.x == 0) cl[l] = 0.f;
       continue;
     }
@@ -355,86 +363,112 @@ __global__ void __launch_bounds__(256) k_lr_coupling(const float* T, const float
   if (threadIdx.x == 0) {
     const float trG = scal[slot * 8 + 0];
     const float near_lim = 0.09f * tol * tol * trG;   // (0.3 tol ||B||_F)^2
-    float c2 = 0.f;
+    float c2 = 0.f, omax = 0.f, cross = 0.f;
     for (int l = 0; l < P; ++l) {
       const float s = sg[l];
       const bool live = s > tau;
       const bool near = !live && s > 0.5f * tau && cl[l] <= near_lim;
       const bool in = live || near;
+      const float x = s * s * cl[l];
+      const bool split = !in && s > 0.f && s * sqrtf(cl[l]) <= 1e-3f * tau * tau;
       mask[slot * P + l] = in ? 1.f : 0.f;
+      dmask[slot * P + l] = (in || split) ? 1.f : 0.f;
       if (in) c2 += cl[l];
+      if (split) {
+        omax = fmaxf(omax, s * s);
+        cross += x;
+      }
     }
     scal[slot * 8 + 1] = c2;
+    scal[slot * 8 + 6] = cross;
+    scal[slot * 8 + 7] = omax * (1.f + 1e-4f);
   }
 }
 
-// H = V_L^T (G V_L) and VH = V_L H (nb x p); non-live columns are masked to zero.
+// Q = W - V H / 2 over the columns the mask selects (others zero), with W = G V_r and
+// H = V^T W (P x P, from a batched GEMM), so that E^T E = G - Q V^T - V Q^T for the
+// remainder E = B (I - V V^T) of the masked columns V.
 template <int P>
-__global__ void __launch_bounds__(256) k_lr_vh(const float* Wg, const float* Vr,
-                                               const float* mask, float* VH, int nb) {
-  __shared__ float H[P * P];
-  __shared__ float red[8];
+__global__ void __launch_bounds__(256) k_lr_q(const float* Wg, const float* Vr, const float* H,
+                                              const float* mask, float* Qo, int nb) {
+  __shared__ float h[P * P];
+  __shared__ float mk[P];
   const int slot = blockIdx.x;
   const float* w = Wg + (int64_t)slot * nb * P;
   const float* v = Vr + (int64_t)slot * nb * P;
-  const float* mk = mask + slot * P;
-  float* vh = VH + (int64_t)slot * nb * P;
-  for (int l = 0; l < P; ++l)
-    for (int k = 0; k < P; ++k) {
-      // the mask is the same for every thread, so the branch is uniform
-      if (!(mk[l] > 0.f && mk[k] > 0.f)) {
-        if (threadIdx.x == 0) H[l * P + k] = 0.f;
-        continue;
-      }
-      float acc = 0.f;
-      for (int r = threadIdx.x; r < nb; r += blockDim.x) acc += v[l * nb + r] * w[k * nb + r];
-      acc = block_sum(acc, red);
-      if (threadIdx.x == 0) H[l * P + k] = acc;
-    }
+  float* q = Qo + (int64_t)slot * nb * P;
+  if (threadIdx.x < P) mk[threadIdx.x] = mask[slot * P + threadIdx.x];
+  for (int e = threadIdx.x; e < P * P; e += blockDim.x) h[e] = H[(int64_t)slot * P * P + e];
   __syncthreads();
   for (int e = threadIdx.x; e < nb * P; e += blockDim.x) {
     const int k = e / nb, r = e - k * nb;
     float s = 0.f;
+    if (mk[k] > 0.f) {
+      float vh = 0.f;
 #pragma unroll
-    for (int l = 0; l < P; ++l) s += v[l * nb + r] * H[l * P + k];
-    vh[e] = s;
+      for (int l = 0; l < P; ++l)
+        if (mk[l] > 0.f) vh += v[l * nb + r] * h[k * P + l];   // H symmetric: H[l][k]
+      s = w[e] - 0.5f * vh;
+    }
+    q[e] = s;
   }
 }
 
-// E^T E = G - W_L V_L^T - V_L W_L^T + V_L H V_L^T (W = G V_r), written to Pm.
+// E^T E = G - Q V^T - V Q^T (masked columns of V_r) on 64 x 64 tiles, to Pm, with
+// per-tile partial trace and squared Frobenius norm. Q and V rows of the tile's row
+// and column ranges are staged in LDS.
 template <int P>
-__global__ void __launch_bounds__(256) k_lr_ge(const float* G, const float* Wg, const float* Vr,
-                                               const float* VH, const float* mask, float* Pm,
-                                               int nb, float* part) {
-  __shared__ float lv[P];
+__global__ void __launch_bounds__(256) k_lr_ge(const float* G, const float* Qm, const float* Vr,
+                                               const float* mask, float* Pm, int nb,
+                                               float* part) {
+  __shared__ float qi[64][P + 1], vi[64][P + 1], qj[64][P + 1], vj[64][P + 1];
+  __shared__ float mk[P];
   __shared__ float red[8];
   const int slot = blockIdx.y;
+  const int tn = (nb + 63) / 64;
+  const int ti = blockIdx.x % tn, tj = blockIdx.x / tn;
+  const int i0 = ti * 64, j0 = tj * 64;
   const float* g = G + (int64_t)slot * nb * nb;
-  const float* w = Wg + (int64_t)slot * nb * P;
+  const float* q = Qm + (int64_t)slot * nb * P;
   const float* v = Vr + (int64_t)slot * nb * P;
-  const float* vh = VH + (int64_t)slot * nb * P;
   float* pm = Pm + (int64_t)slot * nb * nb;
-  if (threadIdx.x < P) lv[threadIdx.x] = mask[slot * P + threadIdx.x];
+  const int tid = threadIdx.x;
+  if (tid < P) mk[tid] = mask[slot * P + tid];
   __syncthreads();
-  const int64_t total = (int64_t)nb * nb;
-  float tr = 0.f, f2 = 0.f;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int j = (int)(e / nb), i = (int)(e - (int64_t)j * nb);  // column-major (i, j)
-    float s = g[e];
+  for (int e = tid; e < 64 * P; e += 256) {
+    const int l = e / 64, r = e - l * 64;
+    const bool m = mk[l] > 0.f;
+    const int ri = i0 + r, rj = j0 + r;
+    qi[r][l] = ri < nb ? q[l * nb + ri] : 0.f;
+    vi[r][l] = (m && ri < nb) ? v[l * nb + ri] : 0.f;
+    qj[r][l] = rj < nb ? q[l * nb + rj] : 0.f;
+    vj[r][l] = (m && rj < nb) ? v[l * nb + rj] : 0.f;
+  }
+  __syncthreads();
+  const int il = tid & 63;
+  const int i = i0 + il;
+  float qa[P], va[P];
 #pragma unroll
-    for (int l = 0; l < P; ++l) {
-      if (lv[l] == 0.f) continue;
-      s -= w[l * nb + i] * v[l * nb + j] + v[l * nb + i] * w[l * nb + j];
-      s += vh[l * nb + i] * v[l * nb + j];
+  for (int l = 0; l < P; ++l) {
+    qa[l] = qi[il][l];
+    va[l] = vi[il][l];
+  }
+  float tr = 0.f, f2 = 0.f;
+  if (i < nb) {
+    for (int jl = tid >> 6; jl < 64; jl += 4) {
+      const int j = j0 + jl;
+      if (j >= nb) break;
+      float s = g[(int64_t)j * nb + i];
+#pragma unroll
+      for (int l = 0; l < P; ++l) s -= qa[l] * vj[jl][l] + va[l] * qj[jl][l];
+      pm[(int64_t)j * nb + i] = s;
+      if (i == j) tr += s;
+      f2 += s * s;
     }
-    pm[e] = s;
-    if (i == j) tr += s;
-    f2 += s * s;
   }
   tr = block_sum(tr, red);
   f2 = block_sum(f2, red);
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     part[((int64_t)slot * gridDim.x + blockIdx.x) * 2] = tr;
     part[((int64_t)slot * gridDim.x + blockIdx.x) * 2 + 1] = f2;
   }
@@ -454,28 +488,20 @@ __global__ void k_lr_ge_reduce(const float* part, int tiles, int count, float* s
   scal[slot * 8 + 4] = tr > 0.f ? sqrtf(f2) / tr : 0.f;
 }
 
-// Scale each slot's nb x nb matrix by 1 / scal[which] (0 stays 0).
-__global__ void k_lr_scale(float* Pm, int nb, const float* scal, int which) {
-  const int slot = blockIdx.y;
-  const float tr = scal[slot * 8 + which];
+// Gather the undecided slots' E^T E (slot-indexed Pm) into compact positions of Dst,
+// scaled by 1 / tr(E^T E) (0 stays 0), so that the squarings only touch those slots.
+__global__ void k_lr_gather_scale(const float* Pm, float* Dst, int nb, const int* list,
+                                  const float* scal) {
+  const int c = blockIdx.y;
+  const int slot = list[c];
+  const float tr = scal[slot * 8 + 2];
   const float inv = tr > 0.f ? 1.f / tr : 0.f;
-  float* pm = Pm + (int64_t)slot * nb * nb;
   const int64_t total = (int64_t)nb * nb;
+  const float* src = Pm + (int64_t)slot * total;
+  float* dst = Dst + (int64_t)c * total;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x)
-    pm[e] *= inv;
-}
-
-__global__ void __launch_bounds__(256) k_lr_frob(const float* Pm, int nb, float* scal,
-                                                 int which) {
-  __shared__ float red[8];
-  const int slot = blockIdx.x;
-  const float* pm = Pm + (int64_t)slot * nb * nb;
-  const int64_t total = (int64_t)nb * nb;
-  float acc = 0.f;
-  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) acc += pm[e] * pm[e];
-  acc = block_sum(acc, red);
-  if (threadIdx.x == 0) scal[slot * 8 + which] = sqrtf(acc);
+    dst[e] = src[e] * inv;
 }
 
 // ||Pm||_F per slot from per-tile partials (fixed reduction order).
@@ -492,13 +518,14 @@ __global__ void __launch_bounds__(256) k_lr_frob_part(const float* Pm, int nb, f
   if (threadIdx.x == 0) part[(int64_t)slot * gridDim.x + blockIdx.x] = acc;
 }
 
-__global__ void k_lr_frob_reduce(const float* part, int tiles, int count, float* scal,
-                                 int which) {
-  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
-  if (slot >= count) return;
+// Compact entry c belongs to slot list[c].
+__global__ void k_lr_frob_reduce(const float* part, int tiles, int count, const int* list,
+                                 float* scal, int which) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= count) return;
   float f2 = 0.f;
-  for (int t = 0; t < tiles; ++t) f2 += part[(int64_t)slot * tiles + t];
-  scal[slot * 8 + which] = sqrtf(f2);
+  for (int t = 0; t < tiles; ++t) f2 += part[(int64_t)c * tiles + t];
+  scal[list[c] * 8 + which] = sqrtf(f2);
 }
 
 // Certificate decision; flags per slot: [1] converged (panel rounds skip it),
@@ -533,8 +560,11 @@ __device__ __forceinline__ void lr_fallback(int slot, int slots, int* pflag, int
 __global__ void k_lr_decide(int count, int slots, float* scal, const float* sig, float tau,
                             int* pflag, int* counts, int* fall, const int* live_list,
                             unsigned long long* stats, int stage, int power) {
-  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
-  if (slot >= count) return;
+  // stage 0 walks all slots and lists the undecided ones at fall[2 slots ..];
+  // later stages walk that list
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= count) return;
+  const int slot = stage == 0 ? idx : fall[2 * slots + idx];
   const float* sc = scal + slot * 8;
   const float trG = sc[0], c2 = sc[1], trE = sc[2];
   const float lim = tau * tau * (1.f - kCertMargin);
@@ -546,17 +576,22 @@ __global__ void k_lr_decide(int count, int slots, float* scal, const float* sig,
       atomicAdd(&stats[4], 1ull);
       return;
     }
-    const float b0 = trE > 0.f ? trE * sc[4] : 0.f;
-    if (b0 <= lim) {
+    // lambda_max(E_L^T E_L) <= max(max_l' sigma_l'^2, lambda_max(E^T E)) + ||A'^T E||_2,
+    // l' over the split-off directions, E the remainder after them and L, and
+    // ||A'^T E||_F^2 <= sum sigma_l'^2 c_l'^2
+    const float b0 = fmaxf(sc[7], trE > 0.f ? trE * sc[4] : 0.f) + sqrtf(sc[6]);
+    if (b0 <= lim && isfinite(b0)) {
       lr_certify(slot, sig, tau, pflag, stats);
     } else {
       pflag[4 * slot + 3] = 1;
-      atomicAdd(&counts[1], 1);
+      const int u = atomicAdd(&counts[1], 1);
+      fall[2 * slots + u] = slot;
     }
   } else {
     // sc[3] = ||(E^T E / tr)^power||_F, so lambda_max <= tr * sc[3]^(1/power)
     if (!pflag[4 * slot + 3]) return;
-    const float bp = trE > 0.f ? trE * powf(sc[3], 1.f / (float)power) : 0.f;
+    const float bp = fmaxf(sc[7], trE > 0.f ? trE * powf(sc[3], 1.f / (float)power) : 0.f) +
+                     sqrtf(sc[6]);
     if (bp <= lim && isfinite(bp)) {
       pflag[4 * slot + 3] = 0;
       lr_certify(slot, sig, tau, pflag, stats);
@@ -702,22 +737,29 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
   if ((e = gemm(h, rocblas_operation_transpose, rocblas_operation_none, P, nb, mb, w.lrC, mb, sC,
                 w.pA, mb, sB, w.lrT, P, (int64_t)P * nb, count)) != hipSuccess)
     return e;
-  float* mask = w.lrSig + (size_t)w.slots * P;   // second half of the sigma buffer
+  float* mask = w.lrSig + (size_t)w.slots * P;       // second third of the sigma buffer
+  float* dmask = w.lrSig + 2 * (size_t)w.slots * P;  // last third
   hipLaunchKernelGGL(k_lr_coupling<P>, dim3(count), dim3(256), 0, st, w.lrT, w.lrSig, w.lrV, nb,
-                     tau, kCouplingTol, w.lrScal, mask);
+                     tau, kCouplingTol, w.lrScal, mask, dmask);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  // E^T E and its power bound
+  // E^T E and its power bound: W = G V_r, H = V_r^T W (into lrQ), Q = W - V H / 2
+  // (into lrY), E^T E = G - Q V^T - V Q^T (into lrP, partials into lrQ)
   if ((e = gemm(h, rocblas_operation_none, rocblas_operation_none, nb, P, nb, w.lrG, nb, sG,
                 w.lrV, nb, sY, w.lrW, nb, sY, count)) != hipSuccess)
     return e;
-  hipLaunchKernelGGL(k_lr_vh<P>, dim3(count), dim3(256), 0, st, w.lrW, w.lrV, mask, w.lrY, nb);
+  if ((e = gemm(h, rocblas_operation_transpose, rocblas_operation_none, P, P, nb, w.lrV, nb, sY,
+                w.lrW, nb, sY, w.lrQ, P, (int64_t)P * P, count)) != hipSuccess)
+    return e;
+  hipLaunchKernelGGL(k_lr_q<P>, dim3(count), dim3(256), 0, st, w.lrW, w.lrV, w.lrQ, dmask, w.lrY,
+                     nb);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int gtiles = ((nb + 63) / 64) * ((nb + 63) / 64);
+  hipLaunchKernelGGL(k_lr_ge<P>, dim3(gtiles, count), dim3(256), 0, st, w.lrG, w.lrY, w.lrV,
+                     dmask, w.lrP, nb, w.lrQ);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int tiles = (int)((sG + 255) / 256 < 64 ? (sG + 255) / 256 : 64);
-  hipLaunchKernelGGL(k_lr_ge<P>, dim3(tiles, count), dim3(256), 0, st, w.lrG, w.lrW, w.lrV,
-                     w.lrY, mask, w.lrP, nb, w.lrQ);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
   // stage 0: Frobenius bound of E^T E (partials were written to lrQ)
-  hipLaunchKernelGGL(k_lr_ge_reduce, dim3((count + 255) / 256), dim3(256), 0, st, w.lrQ, tiles,
+  hipLaunchKernelGGL(k_lr_ge_reduce, dim3((count + 255) / 256), dim3(256), 0, st, w.lrQ, gtiles,
                      count, w.lrScal);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_lr_decide, dim3((count + 255) / 256), dim3(256), 0, st, count, w.slots, w.lrScal,
@@ -727,18 +769,22 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
                           st)) != hipSuccess)
     return e;
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-  if (w.hostInts[1] > 0) {
-    // stage 1: square of E^T E / tr(E^T E); stage 2: its fourth power (eighth in all)
-    hipLaunchKernelGGL(k_lr_scale, dim3(tiles, count), dim3(256), 0, st, w.lrP, nb, w.lrScal, 2);
+  const int und = w.hostInts[1];
+  if (und > 0) {
+    // stage 1: square of E^T E / tr(E^T E); stage 2: its fourth power (eighth in all),
+    // on the undecided slots only, gathered to compact positions (lrQ, then lrP)
+    const int* ulist = w.lrFall + 2 * w.slots;
+    hipLaunchKernelGGL(k_lr_gather_scale, dim3(tiles, und), dim3(256), 0, st, w.lrP, w.lrQ, nb,
+                       ulist, w.lrScal);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    float* a = w.lrP;
-    float* b = w.lrQ;
+    float* a = w.lrQ;
+    float* b = w.lrP;
     int power = 1;
     for (int stage = 1; stage <= 2; ++stage) {
       const int nsq = stage == 1 ? 1 : 2;
       for (int s2 = 0; s2 < nsq; ++s2) {
         if ((e = gemm(h, rocblas_operation_none, rocblas_operation_none, nb, nb, nb, a, nb, sG, a,
-                      nb, sG, b, nb, sG, count)) != hipSuccess)
+                      nb, sG, b, nb, sG, und)) != hipSuccess)
           return e;
         float* t = a;
         a = b;
@@ -747,14 +793,14 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
       }
       const int ftiles = tiles;
       // partials go to lrY (free after stage 0); lrT keeps A_f^T B for the polar route
-      hipLaunchKernelGGL(k_lr_frob_part, dim3(ftiles, count), dim3(256), 0, st, a, nb, w.lrY);
+      hipLaunchKernelGGL(k_lr_frob_part, dim3(ftiles, und), dim3(256), 0, st, a, nb, w.lrY);
       if ((e = hipGetLastError()) != hipSuccess) return e;
-      hipLaunchKernelGGL(k_lr_frob_reduce, dim3((count + 255) / 256), dim3(256), 0, st, w.lrY,
-                         ftiles, count, w.lrScal, 3);
+      hipLaunchKernelGGL(k_lr_frob_reduce, dim3((und + 255) / 256), dim3(256), 0, st, w.lrY,
+                         ftiles, und, ulist, w.lrScal, 3);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, w.lrCount + 1, 1);
       if ((e = hipGetLastError()) != hipSuccess) return e;
-      hipLaunchKernelGGL(k_lr_decide, dim3((count + 255) / 256), dim3(256), 0, st, count,
+      hipLaunchKernelGGL(k_lr_decide, dim3((und + 255) / 256), dim3(256), 0, st, und,
                          w.slots, w.lrScal, w.lrSig, tau, w.pflag, w.lrCount, w.lrFall, w.live_list,
                          w.stats, stage, power);
       if ((e = hipGetLastError()) != hipSuccess) return e;

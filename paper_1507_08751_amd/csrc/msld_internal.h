@@ -60,7 +60,7 @@ __device__ inline bool inst_active(const ShiftSpec& s, int z) {
 }
 
 // ------------------------------------------------------------------ plans
-enum Tier { TIER_1X1 = 0, TIER_REG = 1, TIER_LDS = 2, TIER_PANEL = 3 };
+enum Tier { TIER_1X1 = 0, TIER_REG = 1, TIER_LDS = 2, TIER_PANEL = 3, TIER_LRS = 5 };
 
 // Geometry of one scale's partition. M counts the rows of all stacked instances
 // (NI instances of IM rows each, IM = M for a single instance); P = NI * PI block rows.
@@ -116,11 +116,12 @@ struct ScaleWork {
   float* lrT;           // [slots][p*nb] A_f^T B
   float* lrW;           // [slots][nb*p] G V_r
   float* lrV;           // [slots][nb*p] right vectors V_r
-  float* lrSig;         // [slots][p]
+  float* lrSig;         // [3][slots][p]: sigma, deflation mask, remainder-bound mask
   float* lrScal;        // [slots][8]
   float* lrOm;          // [nb*p] probe matrix
   int* lrCount;         // [4] device counters: fallback, undecided
-  int* lrFall;          // [2 slots] block ids, then slot indices, of failed certificates
+  int* lrFall;          // [3 slots] block ids, then slot indices, of failed certificates;
+                        // then the slots left undecided by the stage-0 bound
   int lds_fallback;     // 1: fallback blocks fit the LDS Jacobi tier
   int* hostInts;        // pinned host ints [2]
   // polar fallback (polar.hip) for failed certificates of blocks beyond the LDS tier;
@@ -159,6 +160,10 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
                         float tau, const ShiftSpec& sh, float jtol, int max_sweeps,
                         int panel_sweeps, int num_cus, hipStream_t st, hipEvent_t* ev,
                         int* round_launches);
+int lr_small_shape(int mb, int nb, int* NB, int* MB, int* P);
+size_t lr_small_lds_bytes(int NB, int MB, int P);
+hipError_t launch_lr_small(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout,
+                           float tau, const ShiftSpec& sh, int num_cus, hipStream_t st);
 hipError_t batched_sgemm(void* blas, bool ta, bool tb, int m, int n, int k, const float* A,
                          int lda, int64_t sa, const float* B, int ldb, int64_t sb, float* C,
                          int ldc, int64_t sc, int batch);

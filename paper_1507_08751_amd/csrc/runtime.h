@@ -63,7 +63,12 @@ struct msld_solver {
   double* host_res;   // pinned: [0, ninst) residual sums, [ninst, 2 ninst) ||Y||^2
   int* host_ints;     // pinned, 2 per scale
   float* host_pl;     // pinned, 4 per polar chunk slot (largest chunk of any scale)
-  rocblas_handle blas;
+  // scales are independent between two consensus passes: each runs on its own
+  // stream (forked from st after the consensus, joined before the residual)
+  hipStream_t sst[MSLD_MAX_SCALES];
+  hipEvent_t ev_fork;
+  hipEvent_t ev_join[MSLD_MAX_SCALES];
+  rocblas_handle blas[MSLD_MAX_SCALES];   // one per low-rank scale, bound to its stream
   msld::ScaleWork work[MSLD_MAX_SCALES];
   int ninst;
   int k;              // next iteration (single instance; stacked instances use d_k)

@@ -75,6 +75,11 @@ BSVT_CASES = [
 
 LOWRANK_CASES = [c for c in BSVT_CASES if min(c[2], c[3]) >= 64] + [(256, 384, 64, 64)]
 
+# blocks the fused certified kernel handles (shorter side 32..64, longer side <= 128)
+SMALL_LR_CASES = [c for c in BSVT_CASES
+                  if 32 <= min(c[2], c[3]) <= 64 and max(c[2], c[3]) <= 128] + [
+    (128, 512, 32, 128), (256, 256, 64, 128), (96, 192, 48, 96), (160, 96, 40, 24 * 2)]
+
 
 @pytest.mark.parametrize("M,N,m,n", BSVT_CASES)
 def test_bsvt_call_parity(lib, M, N, m, n):
@@ -86,7 +91,12 @@ def test_bsvt_call_parity_lowrank(lib, M, N, m, n):
     _bsvt_case(lib, M, N, m, n, lowrank_min=64)
 
 
-def _bsvt_case(lib, M, N, m, n, lowrank_min):
+@pytest.mark.parametrize("M,N,m,n", SMALL_LR_CASES)
+def test_bsvt_call_parity_lowrank_small(lib, M, N, m, n):
+    _bsvt_case(lib, M, N, m, n, lowrank_min=0, tier="lowrank_small")
+
+
+def _bsvt_case(lib, M, N, m, n, lowrank_min, tier=None):
     seed = M * 7 + N * 3 + m * 11 + n
     V = planted_input(M, N, m, n, seed)
     rng = np.random.default_rng(seed)
@@ -97,6 +107,8 @@ def _bsvt_case(lib, M, N, m, n, lowrank_min):
     solver = lib.Solver(M, N, [(m, n)], iters=1, lowrank_min=lowrank_min)
     print(f"case {M}x{N} block {m}x{n} tier={lib.TIERS[solver.tier(0)]} shift={s} tau={tau:.4f}",
           flush=True)
+    if tier is not None:
+        assert lib.TIERS[solver.tier(0)] == tier
     Vd = torch.from_numpy(V).cuda()
     Z = solver.bsvt(0, Vd, tau, s)
     torch.cuda.synchronize()
@@ -131,7 +143,7 @@ def test_lowrank_path_certifies_low_rank_blocks(lib, M, N, m, n):
     tau = 0.5 * np.sqrt(m * n) ** 0.5 * 4.0
     ref = O.cycle_spun_bsvt(V.astype(np.float64), m, n, tau, s)
     solver = lib.Solver(M, N, [(m, n)], iters=1, lowrank_min=64)
-    assert lib.TIERS[solver.tier(0)] == "lowrank"
+    assert lib.TIERS[solver.tier(0)] in ("lowrank", "lowrank_small")
     Z = solver.bsvt(0, torch.from_numpy(V).cuda(), tau, s)
     torch.cuda.synchronize()
     st = solver.stats()
@@ -195,6 +207,38 @@ def test_polar_fallback_parity(lib, M, N, m, n, kind):
     assert st["polar"][0] > 0
     if kind == "bulk_below":
         assert st["fail_bound"][0] > 0
+    solver.close()
+
+
+@pytest.mark.parametrize("M,N,m,n,kind", [(256, 256, 64, 64, "dense"),
+                                          (256, 256, 64, 64, "bulk_below"),
+                                          (128, 128, 32, 32, "bulk"),
+                                          (256, 128, 128, 64, "bulk_below")])
+def test_small_lowrank_fallback_parity(lib, M, N, m, n, kind):
+    """Blocks of the fused certified kernel whose certificate fails are listed and
+    finished by the LDS Jacobi tier; the mix must match the oracle to 1e-4."""
+    rng = np.random.default_rng(M + 5 * N + m + n)
+    s = (int(rng.integers(0, m)), int(rng.integers(0, n)))
+    tau = 2.0
+    V64 = np.zeros((M, N))
+    for p in range(M // m):
+        for q in range(N // n):
+            rows = (p * m + s[0] + np.arange(m)) % M
+            cols = (q * n + s[1] + np.arange(n)) % N
+            V64[np.ix_(rows, cols)] = _clustered_block(rng, m, n, tau, kind)
+    V = V64.astype(np.float32)
+    ref = O.cycle_spun_bsvt(V.astype(np.float64), m, n, tau, s)
+    solver = lib.Solver(M, N, [(m, n)], iters=1)
+    assert lib.TIERS[solver.tier(0)] == "lowrank_small"
+    Z = solver.bsvt(0, torch.from_numpy(V).cuda(), tau, s)
+    torch.cuda.synchronize()
+    st = solver.stats()
+    err = rel_err(Z.cpu().numpy(), ref, np.linalg.norm(V))
+    print(f"small lowrank {kind} {M}x{N} / {m}x{n}: err {err:.2e} decomposed {st['live']} "
+          f"certified {st['certified']} fail coupling {st['fail_coupling']} bound "
+          f"{st['fail_bound']}", flush=True)
+    assert err <= 1e-4
+    assert st["fail_coupling"][0] + st["fail_bound"][0] > 0
     solver.close()
 
 
