@@ -32,8 +32,8 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-STREAM_BYTES_PER_ELEM = 16     # k_stream: read Z_i and R, write Z_i' and D_i'
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_stream__8192x8192_5scales_traffic.md")
+STREAM_BYTES_PER_ELEM = 16     # per decomposed scale: read Z_i and R, write Z_i' and D_i'
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_stream_all__8192x8192_5scales_traffic.md")
 
 
 def consensus_bytes_per_elem(L, n1x1):
@@ -49,7 +49,7 @@ def kernels_source_digest():
 
 
 def measured_traffic():
-    """HBM bytes per k_stream launch from the committed rocprofv3 counter summary:
+    """HBM bytes per k_stream_all launch from the committed rocprofv3 counter summary:
     FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the stream kernel, each scaled by
     what the same counter reads for a plain copy of known size. None when the summary
     is missing or was taken on a different kernels.hip."""
@@ -61,23 +61,23 @@ def measured_traffic():
             return None
         fr = float(kv["copy bytes read"]) / (1024.0 * float(kv["copy FETCH_SIZE KiB"]))
         fw = float(kv["copy bytes written"]) / (1024.0 * float(kv["copy WRITE_SIZE KiB"]))
-        return (1024.0 * float(kv["k_stream FETCH_SIZE KiB"]) * fr
-                + 1024.0 * float(kv["k_stream WRITE_SIZE KiB"]) * fw)
+        return (1024.0 * float(kv["k_stream_all FETCH_SIZE KiB"]) * fr
+                + 1024.0 * float(kv["k_stream_all WRITE_SIZE KiB"]) * fw)
     except (OSError, KeyError, ValueError):
         return None
 
 
 def stream_roofline(prof, tiers, M, N, K):
-    """Roofline of the dominant kernel, the stream pass (one launch per decomposed scale
-    and iteration), from its HIP-event times; and of the consensus pass."""
+    """Roofline of the dominant kernel, the stream pass of all decomposed scales (one
+    launch per iteration), from its HIP-event times; and of the consensus pass."""
     idx = [i for i, t in enumerate(tiers) if t != "1x1"]
-    launches = K * len(idx)
-    avg_ms = sum(prof["scale_ms"][i][0] for i in idx) / max(1, launches)
-    nbytes = STREAM_BYTES_PER_ELEM * M * N
+    launches = K
+    avg_ms = prof["stream_ms"] / max(1, launches)
+    nbytes = STREAM_BYTES_PER_ELEM * M * N * len(idx)
     gbs = nbytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": measured_traffic(),
-            "kernel": "k_stream", "launches": launches, "avg_launch_ms": round(avg_ms, 4),
+            "kernel": "k_stream_all", "launches": launches, "avg_launch_ms": round(avg_ms, 4),
             "algorithmic_bytes_per_launch": nbytes}
     n1 = sum(1 for t in tiers if t == "1x1")
     cbytes = consensus_bytes_per_elem(len(tiers), n1) * M * N
@@ -324,11 +324,12 @@ def main():
     sec = t1 - t0
     ips = K / sec
     log(f"timed {K} iterations: {sec:.3f} s -> {ips:.2f} iters/s; resid after K+1: {r:.3e}")
-    log(f"consensus ms total {prof['consensus_ms']:.2f}")
+    log(f"consensus ms total {prof['consensus_ms']:.2f}, stream pass (all scales) "
+        f"{prof['stream_ms']:.2f}")
     for i, (m, n) in enumerate(LADDER):
         ms = prof["scale_ms"][i]
         nblk = (M // m) * (N // n)
-        log(f"scale {i} ({m}x{n}, {tiers[i]}): stream {ms[0]:.2f} setup {ms[1]:.2f} "
+        log(f"scale {i} ({m}x{n}, {tiers[i]}): setup {ms[1]:.2f} "
             f"svd {ms[2]:.2f} finish {ms[3]:.2f} ms; live {stats['live'][i]} of {nblk * K} "
             f"block-iters, sweeps {stats['sweeps'][i]}, rank {stats['rank'][i]}, "
             f"certified {stats['certified'][i]} (fail coupling {stats['fail_coupling'][i]}, "
@@ -344,6 +345,7 @@ def main():
            "roofline": roof, "roofline_consensus": extra,
            "phases_ms_per_iter": {
                "consensus": round(prof["consensus_ms"] / K, 4),
+               "stream_all": round(prof["stream_ms"] / K, 4),
                **{f"scale{i}_{m}x{n}_{tiers[i]}": [round(v / K, 4) for v in prof["scale_ms"][i]]
                   for i, (m, n) in enumerate(LADDER) if tiers[i] != "1x1"}}}
     if not args.no_cpu_baseline:

@@ -146,12 +146,13 @@ msld_status msld_stats(msld_solver *s, msld_result *info);
  * creates events for the next n iterations (each iteration records them as it is
  * enqueued; later iterations are not recorded). msld_profile_end synchronises and
  * returns elapsed milliseconds summed over the recorded iterations in
- * ms[(L + 1) * 4]: for scale i, ms[4i + 0] the stream kernel (shifted gather, bound
- * test, speculative write), ms[4i + 1] the rest of the set-up (bound reduction,
- * panel load), ms[4i + 2] the SVD kernels (register / LDS / fused low-rank kernel,
- * the batched low-rank path, or all panel-round launches), ms[4i + 3] the rest
- * (fallbacks, gains, rebuild); ms[4L] the consensus pass. Scales run concurrently,
- * so their times overlap. round_launches[L] receives the number of panel-round
+ * ms[(L + 1) * 4]: ms[4L] the consensus pass, ms[4L + 1] the stream pass of all
+ * decomposed scales (one launch: shifted gather, bound test, speculative write);
+ * for scale i, ms[4i + 1] the rest of the set-up (bound reduction, panel load),
+ * ms[4i + 2] the SVD kernels (register / LDS / fused low-rank kernel, the batched
+ * low-rank path, or all panel-round launches), ms[4i + 3] the rest (fallbacks,
+ * gains, rebuild); ms[4i + 0] stays 0 (the stream pass is shared). Scales run
+ * concurrently, so their times overlap. round_launches[L] receives the number of panel-round
  * kernel launches per scale, *iters_recorded the number of iterations covered. */
 msld_status msld_profile_begin(msld_solver *s, int32_t max_iters);
 msld_status msld_profile_end(msld_solver *s, double *ms, int64_t *round_launches,

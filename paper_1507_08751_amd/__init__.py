@@ -284,8 +284,8 @@ class Solver:
             _check(self._lib.msld_profile_end(self._h, ms, rl, ctypes.byref(n)),
                    "msld_profile_end")
         per = [list(ms[4 * i:4 * i + 4]) for i in range(self.L)]
-        return {"scale_ms": per, "consensus_ms": ms[4 * self.L], "round_launches": list(rl),
-                "iters": n.value}
+        return {"scale_ms": per, "consensus_ms": ms[4 * self.L],
+                "stream_ms": ms[4 * self.L + 1], "round_launches": list(rl), "iters": n.value}
 
     def bsvt(self, scale, V, tau, shift=(0, 0), out=None):
         """Z = Shift_{-s}(BSVT_tau(Shift_s(V))) with scale `scale`'s block shape."""

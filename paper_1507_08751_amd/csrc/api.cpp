@@ -210,7 +210,7 @@ static void destroy_solver(msld_solver* s) {
   if (!s) return;
   (void)hipStreamSynchronize(s->st);
   if (s->prof_ev) {
-    for (size_t e = 0; e < (2 + 5 * (size_t)s->p.L) * (size_t)s->prof_cap; ++e)
+    for (size_t e = 0; e < (4 + 5 * (size_t)s->p.L) * (size_t)s->prof_cap; ++e)
       (void)hipEventDestroy(s->prof_ev[e]);
     std::free(s->prof_ev);
   }
@@ -375,6 +375,29 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
       }
     }
   }
+  // fused stream-pass descriptor
+  {
+    StreamAll& a = s->sall;
+    std::memset(&a, 0, sizeof(a));
+    a.plane = plane_elems(s);
+    size_t lds = 0;
+    for (int i = 0; i < p->L; ++i) {
+      if (pl.tier[i] == TIER_1X1) continue;
+      StreamScale& d = a.s[a.n];
+      d.g = pl.geom[i];
+      d.sp = pl.sp[i];
+      d.scale = i;
+      d.tau2lim = stream_tau2lim(pl.geom[i], pl.tau_default[i]);
+      d.live_count = s->work[i].live_count;
+      d.live_list = s->work[i].live_list;
+      d.rowpart = s->work[i].rowpart;
+      d.fropart = s->work[i].fropart;
+      a.first[a.n + 1] = a.first[a.n] + pl.geom[i].P * pl.sp[i].spr;
+      lds = std::max(lds, stream_lds_bytes(pl.geom[i].m, pl.sp[i]));
+      ++a.n;
+    }
+    s->sall_lds = lds;
+  }
   *out = s;
   return MSLD_OK;
 }
@@ -384,12 +407,14 @@ static float jacobi_tol(int mb) { return 4.0f * 5.9604645e-8f * std::sqrt((float
 // Scale i's BlockSVT on its own stream; the caller forks it from s->st (after the
 // consensus) and joins it back.
 static msld_status run_scale(msld_solver* s, int i, const float* Zin, const float* R, float* Zout,
-                             float* Dout, float tau, const ShiftSpec& sh, hipEvent_t* ev) {
+                             float* Dout, float tau, const ShiftSpec& sh, hipEvent_t* ev,
+                             bool stream_done) {
   const Plan& pl = s->plan;
   const ScaleGeom& g = pl.geom[i];
   int rl = 0;
   MSLD_TRY(s, launch_scale(g, pl.tier[i], pl.sp[i], s->work[i], Zin, R, Zout, Dout, tau, sh,
-                           jacobi_tol(g.mb), 40, 20, s->num_cus, s->sst[i], ev, &rl));
+                           jacobi_tol(g.mb), 40, 20, s->num_cus, s->sst[i], ev, &rl,
+                           stream_done));
   if (ev) s->round_launches[i] += rl;
   return MSLD_OK;
 }
@@ -435,13 +460,28 @@ msld_status iterate_once(msld_solver* s, const float* d_Y, int64_t ldY, float* d
     }
   hipEvent_t* ev = nullptr;
   if (s->prof_ev && s->prof_n < s->prof_cap) {
-    ev = s->prof_ev + (size_t)s->prof_n * (2 + 5 * L);
+    ev = s->prof_ev + (size_t)s->prof_n * (4 + 5 * L);
     ++s->prof_n;
     MSLD_TRY(s, hipEventRecord(ev[0], s->st));
   }
   MSLD_TRY(s, launch_consensus(d_Y, ldY, Dc, Dn, d_Z, R, M, N, L, scales1, taus1, n1, IM,
                                stacked ? s->d_active : nullptr, s->st));
   if (ev) MSLD_TRY(s, hipEventRecord(ev[1], s->st));
+  {
+    // stream pass of every decomposed scale in one launch
+    ShiftSpec sh;
+    sh.seed = p.shift_seed;
+    sh.k = s->k;
+    sh.scale = 0;
+    sh.mode = p.cycle_spin ? 1 : 0;
+    sh.sr = sh.sc = 0;
+    sh.iseed = stacked ? s->d_seed : nullptr;
+    sh.ik = stacked ? s->d_k : nullptr;
+    sh.iactive = stacked ? s->d_active : nullptr;
+    if (ev) MSLD_TRY(s, hipEventRecord(ev[2], s->st));
+    MSLD_TRY(s, launch_stream_all(s->sall, s->sall_lds, d_Z, R, Dn, sh, s->st));
+    if (ev) MSLD_TRY(s, hipEventRecord(ev[3], s->st));
+  }
   MSLD_TRY(s, hipEventRecord(s->ev_fork, s->st));
   // scales whose host driver never waits go first, so that their work is queued
   // before a low-rank scale's host-side waits (live and fallback counts) begin
@@ -464,7 +504,7 @@ msld_status iterate_once(msld_solver* s, const float* d_Y, int64_t ldY, float* d
     sh.iactive = stacked ? s->d_active : nullptr;
     float* Zi = d_Z + MN * i;
     msld_status rs = run_scale(s, i, Zi, R, Zi, Dn + MN * i, pl.tau_default[i], sh,
-                               ev ? ev + 2 + 5 * i : nullptr);
+                               ev ? ev + 4 + 5 * i : nullptr, true);
     if (rs != MSLD_OK) return rs;
     rs = join_scale(s, i);
     if (rs != MSLD_OK) return rs;
@@ -640,7 +680,7 @@ msld_status msld_profile_begin(msld_solver* s, int32_t max_iters) {
   if (!s || max_iters < 1) return MSLD_EINVAL;
   if (s->failed) return MSLD_EDEVICE;
   if (s->prof_ev) return MSLD_EINVAL;
-  const size_t per = 2 + 5 * (size_t)s->p.L;
+  const size_t per = 4 + 5 * (size_t)s->p.L;
   const size_t n = per * (size_t)max_iters;
   s->prof_ev = static_cast<hipEvent_t*>(std::calloc(n, sizeof(hipEvent_t)));
   if (!s->prof_ev) return MSLD_ENOMEM;
@@ -662,7 +702,7 @@ msld_status msld_profile_end(msld_solver* s, double* ms, int64_t* round_launches
   if (!s || !ms || !round_launches || !iters_recorded) return MSLD_EINVAL;
   if (!s->prof_ev) return MSLD_EINVAL;
   const int L = s->p.L;
-  const size_t per = 2 + 5 * (size_t)L;
+  const size_t per = 4 + 5 * (size_t)L;
   msld_status result = MSLD_OK;
   if (hipStreamSynchronize(s->st) != hipSuccess) result = dev_err(s, hipErrorUnknown);
   for (int i = 0; i < 4 * (L + 1); ++i) ms[i] = 0.0;
@@ -670,9 +710,10 @@ msld_status msld_profile_end(msld_solver* s, double* ms, int64_t* round_launches
     hipEvent_t* ev = s->prof_ev + (size_t)it * per;
     float t;
     if (hipEventElapsedTime(&t, ev[0], ev[1]) == hipSuccess) ms[4 * L] += t;
+    if (s->sall.n > 0 && hipEventElapsedTime(&t, ev[2], ev[3]) == hipSuccess) ms[4 * L + 1] += t;
     for (int i = 0; i < L; ++i) {
       if (s->plan.tier[i] == TIER_1X1) continue;
-      hipEvent_t* e5 = ev + 2 + 5 * i;
+      hipEvent_t* e5 = ev + 4 + 5 * i;
       for (int j = 0; j < 4; ++j)
         if (hipEventElapsedTime(&t, e5[j], e5[j + 1]) == hipSuccess) ms[4 * i + j] += t;
     }
@@ -720,7 +761,7 @@ msld_status msld_bsvt(msld_solver* s, int32_t scale, const float* d_V, float* d_
   if (zs != MSLD_OK) return zs;
   MSLD_TRY(s, hipEventRecord(s->ev_fork, s->st));
   msld_status rs = fork_scale(s, scale);
-  if (rs == MSLD_OK) rs = run_scale(s, scale, d_V, nullptr, d_Z, Dws, tau, sh, nullptr);
+  if (rs == MSLD_OK) rs = run_scale(s, scale, d_V, nullptr, d_Z, Dws, tau, sh, nullptr, false);
   if (rs == MSLD_OK) rs = join_scale(s, scale);
   return rs;
 }

@@ -297,15 +297,16 @@ __global__ void __launch_bounds__(256) k_tiny_live(
 // bound exceeds tau enter the live list; the SVD pass later reads their V back
 // from D' = -V and overwrites both outputs.
 // A workgroup handles all m rows of one block row and a strip of `w` columns.
-__global__ void __launch_bounds__(256) k_stream(
-    const float* __restrict__ Zin, const float* __restrict__ R, float* __restrict__ Zout,
-    float* __restrict__ Dout, ScaleGeom g, StreamPlan sp, ShiftSpec sh, float tau2lim,
-    int* __restrict__ live_count, int* __restrict__ live_list, float* __restrict__ rowpart,
-    float* __restrict__ fropart) {
-  extern __shared__ float smem[];
+// One strip (item) of one scale; smem is the workgroup's dynamic LDS.
+__device__ __forceinline__ void stream_strip(
+    int item, const float* __restrict__ Zin, const float* __restrict__ R,
+    float* __restrict__ Zout, float* __restrict__ Dout, const ScaleGeom& g,
+    const StreamPlan& sp, const ShiftSpec& sh, float tau2lim, int* __restrict__ live_count,
+    int* __restrict__ live_list, float* __restrict__ rowpart, float* __restrict__ fropart,
+    float* smem) {
   const int N = g.N, m = g.m, n = g.n, Q = g.Q;
-  const int p = blockIdx.x / sp.spr;
-  const int j = blockIdx.x - p * sp.spr;
+  const int p = item / sp.spr;
+  const int j = item - p * sp.spr;
   if (!inst_active(sh, p / g.PI)) return;   // uniform: the strip lies in one instance
   int sr, sc;
   block_shift(sh, p / g.PI, m, n, &sr, &sc);
@@ -321,9 +322,12 @@ __global__ void __launch_bounds__(256) k_stream(
     col0 = q0 * n + part * sp.ws;
     w = min(sp.ws, n - part * sp.ws);
   }
+  // The tile keeps |v| rounded up to bfloat16 (only the bound reads it, and a
+  // rounded-up magnitude keeps it an upper bound); the column |.| and squared sums
+  // are accumulated from the float values while they stream through.
   const int ldt = w + 1;
-  float* tile = smem;                       // m x ldt
-  float* pcs = tile + m * ldt;              // 256 partial column |.| sums
+  unsigned short* tile = reinterpret_cast<unsigned short*>(smem);   // m x ldt
+  float* pcs = smem + ((m * ldt + 1) >> 1);  // 256 partial column |.| sums
   float* pcq = pcs + 256;                   // 256 partial column squares
   float* cs = pcq + 256;                    // w column sums
   float* cq = cs + sp.ws + 1;               // w column squares
@@ -332,9 +336,9 @@ __global__ void __launch_bounds__(256) k_stream(
   // strips are at most 256 columns wide (the plan caps them): thread (row group rq,
   // column c) walks rows rq, rq + rpp, ...; kU rows are loaded before any is stored,
   // so every thread keeps 2 kU loads in flight
+  const int rpp = 256 / w;
   {
     constexpr int kU = 8;
-    const int rpp = 256 / w;
     const int c = tid % w;
     const int rq = tid / w;
     int gc = col0 + c + sc;
@@ -343,6 +347,7 @@ __global__ void __launch_bounds__(256) k_stream(
     const int z = p / g.PI;
     const int rbase = (p - z * g.PI) * m + sr;   // instance-local row of block row 0
     const int64_t zoff = (int64_t)z * g.IM;
+    float sabs = 0.f, ssq = 0.f;
     for (int r0 = rq; act && r0 < m; r0 += kU * rpp) {
       float v[kU];
       int64_t o[kU];
@@ -361,51 +366,34 @@ __global__ void __launch_bounds__(256) k_stream(
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
         if (o[u] >= 0) {
-          tile[(r0 + u * rpp) * ldt + c] = v[u];
+          const float a = fabsf(v[u]);
+          sabs += a;
+          ssq += v[u] * v[u];
+          // round the magnitude up to bfloat16 (beyond the largest finite bfloat16, and
+          // for NaN, infinity: the block then always counts as live)
+          const unsigned ab = __float_as_uint(a);
+          const unsigned bits = ab > 0x7F7F0000u ? 0x7F80u : (ab + 0xFFFFu) >> 16;
+          tile[(r0 + u * rpp) * ldt + c] = (unsigned short)bits;
           Zout[o[u]] = 0.f;
           Dout[o[u]] = -v[u];
         }
       }
     }
+    if (act) {
+      pcs[tid] = sabs;
+      pcq[tid] = ssq;
+    }
   }
   if (tid < nq) smax[tid] = 0u;
   __syncthreads();
-  // column sums: rg row groups of w threads
-  const int rg = 256 / w > 0 ? 256 / w : 1;
-  if (w <= 256) {
-    if (tid < rg * w) {
-      const int c = tid % w;
-      const int gq = tid / w;
-      float s = 0.f, s2 = 0.f;
-      for (int r = gq; r < m; r += rg) {
-        const float v = tile[r * ldt + c];
-        s += fabsf(v);
-        s2 += v * v;
-      }
-      pcs[tid] = s;
-      pcq[tid] = s2;
+  if (tid < w) {
+    float s = 0.f, s2 = 0.f;
+    for (int gq = 0; gq < rpp; ++gq) {
+      s += pcs[gq * w + tid];
+      s2 += pcq[gq * w + tid];
     }
-    __syncthreads();
-    if (tid < w) {
-      float s = 0.f, s2 = 0.f;
-      for (int gq = 0; gq < rg; ++gq) {
-        s += pcs[gq * w + tid];
-        s2 += pcq[gq * w + tid];
-      }
-      cs[tid] = s;
-      cq[tid] = s2;
-    }
-  } else {
-    for (int c = tid; c < w; c += 256) {
-      float s = 0.f, s2 = 0.f;
-      for (int r = 0; r < m; ++r) {
-        const float v = tile[r * ldt + c];
-        s += fabsf(v);
-        s2 += v * v;
-      }
-      cs[c] = s;
-      cq[c] = s2;
-    }
+    cs[tid] = s;
+    cq[tid] = s2;
   }
   __syncthreads();
   // weighted row sums per (row, block segment)
@@ -414,10 +402,10 @@ __global__ void __launch_bounds__(256) k_stream(
   for (int e = tid; e < npairs; e += 256) {
     const int s = e / m;
     const int r = e - s * m;
-    const float* row = tile + r * ldt + s * segw;
+    const unsigned short* row = tile + r * ldt + s * segw;
     const float* csg = cs + s * segw;
     float acc = 0.f;
-    for (int c = 0; c < segw; ++c) acc += fabsf(row[c]) * csg[c];
+    for (int c = 0; c < segw; ++c) acc += __uint_as_float((unsigned)row[c] << 16) * csg[c];
     if (sp.whole) {
       atomicMax(&smax[s], __float_as_uint(acc));
     } else {
@@ -441,6 +429,47 @@ __global__ void __launch_bounds__(256) k_stream(
     for (int c = 0; c < w; ++c) fro += cq[c];
     fropart[((int64_t)p * Q + q0) * sp.spb + part] = fro;
   }
+}
+
+__global__ void __launch_bounds__(256) k_stream(
+    const float* __restrict__ Zin, const float* __restrict__ R, float* __restrict__ Zout,
+    float* __restrict__ Dout, ScaleGeom g, StreamPlan sp, ShiftSpec sh, float tau2lim,
+    int* __restrict__ live_count, int* __restrict__ live_list, float* __restrict__ rowpart,
+    float* __restrict__ fropart) {
+  extern __shared__ float smem[];
+  stream_strip(blockIdx.x, Zin, R, Zout, Dout, g, sp, sh, tau2lim, live_count, live_list,
+               rowpart, fropart, smem);
+}
+
+// The stream pass of every decomposed scale in one launch: workgroup b takes item
+// b - first[i] of the scale i whose item range holds b.
+__global__ void __launch_bounds__(256) k_stream_all(StreamAll a, const float* __restrict__ Z,
+                                                    const float* __restrict__ R,
+                                                    float* __restrict__ D, ShiftSpec sh) {
+  extern __shared__ float smem[];
+  const int b = blockIdx.x;
+  int i = 0;
+  while (i + 1 < a.n && b >= a.first[i + 1]) ++i;
+  const StreamScale& d = a.s[i];
+  ShiftSpec shi = sh;
+  shi.scale = d.scale;
+  const size_t off = a.plane * (size_t)d.scale;
+  stream_strip(b - a.first[i], Z + off, R, const_cast<float*>(Z) + off, D + off, d.g, d.sp, shi,
+               d.tau2lim, d.live_count, d.live_list, d.rowpart, d.fropart, smem);
+}
+
+__global__ void k_zero_counts(StreamAll a) {
+  if ((int)threadIdx.x < a.n) *a.s[threadIdx.x].live_count = 0;
+}
+
+hipError_t launch_stream_all(const StreamAll& a, size_t lds, const float* Z, const float* R,
+                             float* D, const ShiftSpec& sh, hipStream_t st) {
+  if (a.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(64), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_stream_all, dim3(a.first[a.n]), dim3(256), lds, st, a, Z, R, D, sh);
+  return hipGetLastError();
 }
 
 // Completes the bound of blocks split over several strips (fixed summation order).
@@ -940,7 +969,8 @@ size_t lds_tier_bytes(int mb, int nb) {
 }
 
 size_t stream_lds_bytes(int m, const StreamPlan& sp) {
-  return (size_t)4 * ((size_t)m * (sp.ws + 1) + 512 + 2 * (sp.ws + 1) + sp.ws + 1);
+  // bfloat16 tile (m x (ws + 1)), then 512 + 2 (ws + 1) + ws + 1 floats
+  return (size_t)4 * (((size_t)m * (sp.ws + 1) + 1) / 2 + 512 + 2 * (sp.ws + 1) + sp.ws + 1);
 }
 
 #define MSLD_EV(i)                                                    \
@@ -951,24 +981,33 @@ size_t stream_lds_bytes(int m, const StreamPlan& sp) {
     }                                                                 \
   } while (0)
 
+float stream_tau2lim(const ScaleGeom& g, float tau) {
+  // skip only if the bound is below tau^2 by more than its rounding error
+  const double tl = (double)tau * (double)tau *
+                    (1.0 - 2.0 * (double)(g.m + g.n + 4) * (double)kEps);
+  return (float)tl;
+}
+
 hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, ScaleWork& w,
                         const float* Zin, const float* R, float* Zout, float* Dout, float tau,
                         const ShiftSpec& sh, float jtol, int max_sweeps, int panel_sweeps,
-                        int num_cus, hipStream_t st, hipEvent_t* ev, int* round_launches) {
+                        int num_cus, hipStream_t st, hipEvent_t* ev, int* round_launches,
+                        bool stream_done) {
   hipError_t e;
-  const double tl = (double)tau * (double)tau *
-                    (1.0 - 2.0 * (double)(g.m + g.n + 4) * (double)kEps);
-  const float tau2lim = (float)tl;
+  const float tau2lim = stream_tau2lim(g, tau);
   const int nblk = g.P * g.Q;
-  // stream pass: speculative zero-output write + bound + live list
-  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, w.live_count);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // stream pass: speculative zero-output write + bound + live list (unless the caller
+  // ran it for all scales at once)
   {
-    const size_t lds = stream_lds_bytes(g.m, sp);
     MSLD_EV(0);   // events 0-1 bracket the stream kernel alone
-    hipLaunchKernelGGL(k_stream, dim3(g.P * sp.spr), dim3(256), lds, st, Zin, R, Zout, Dout, g,
-                       sp, sh, tau2lim, w.live_count, w.live_list, w.rowpart, w.fropart);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (!stream_done) {
+      hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, w.live_count);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      const size_t lds = stream_lds_bytes(g.m, sp);
+      hipLaunchKernelGGL(k_stream, dim3(g.P * sp.spr), dim3(256), lds, st, Zin, R, Zout, Dout,
+                         g, sp, sh, tau2lim, w.live_count, w.live_list, w.rowpart, w.fropart);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     MSLD_EV(1);
     if (!sp.whole) {
       hipLaunchKernelGGL(k_bound_reduce, dim3(nblk), dim3(256), 0, st, g, sp, tau2lim,

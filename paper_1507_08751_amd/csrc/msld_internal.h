@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include "../../include/msld.h"
 
 namespace msld {
 
@@ -147,7 +148,29 @@ struct StreamPlan {
   int spr;       // strips per block row
 };
 
+// Stream pass of every decomposed scale in one launch (kernel argument; plane i of a
+// stacked plane array starts at plane * scale).
+struct StreamScale {
+  ScaleGeom g;
+  StreamPlan sp;
+  int scale;
+  float tau2lim;
+  int* live_count;
+  int* live_list;
+  float* rowpart;
+  float* fropart;
+};
+struct StreamAll {
+  int n;                       // decomposed scales
+  int first[MSLD_MAX_SCALES + 1];  // first workgroup of each scale; first[n] = grid
+  size_t plane;                // elements per plane
+  StreamScale s[MSLD_MAX_SCALES];
+};
+
 // ----------------------------------------------------------- launchers (kernels.hip)
+hipError_t launch_stream_all(const StreamAll& a, size_t lds, const float* Z, const float* R,
+                             float* D, const ShiftSpec& sh, hipStream_t st);
+float stream_tau2lim(const ScaleGeom& g, float tau);
 hipError_t launch_fill(float* p, float v, size_t count, hipStream_t st);
 hipError_t launch_consensus(const float* Y, int64_t ldY, const float* Dcur, float* Dnext,
                             float* Z, float* R, int M, int N, int L, const int* scales1,
@@ -159,7 +182,8 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
                         const float* Zin, const float* R, float* Zout, float* Dout,
                         float tau, const ShiftSpec& sh, float jtol, int max_sweeps,
                         int panel_sweeps, int num_cus, hipStream_t st, hipEvent_t* ev,
-                        int* round_launches);
+                        int* round_launches,
+                        bool stream_done);
 int lr_small_shape(int mb, int nb, int* NB, int* MB, int* P);
 size_t lr_small_lds_bytes(int NB, int MB, int P);
 hipError_t launch_lr_small(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout,

@@ -70,13 +70,15 @@ struct msld_solver {
   hipEvent_t ev_join[MSLD_MAX_SCALES];
   rocblas_handle blas[MSLD_MAX_SCALES];   // one per low-rank scale, bound to its stream
   msld::ScaleWork work[MSLD_MAX_SCALES];
+  msld::StreamAll sall;   // the stream pass of all decomposed scales (one launch)
+  size_t sall_lds;
   int ninst;
   int k;              // next iteration (single instance; stacked instances use d_k)
   int cur;            // which D buffer holds the current D_i
   unsigned long long* d_seed;   // [ninst] per-instance shift seeds (stacked only)
   int* d_k;                     // [ninst] per-instance iteration counters
   int* d_active;                // [ninst] active flags
-  // profiling: per iteration 2 consensus events + 5 events per scale
+  // profiling: per iteration 2 consensus events, 2 for the fused stream pass, 5 per scale
   int prof_cap, prof_n;
   hipEvent_t* prof_ev;
   int64_t round_launches[MSLD_MAX_SCALES];
