@@ -18,7 +18,7 @@ HIPCC_FLAGS = [
 ]
 
 
-LINK = ["-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
+LINK = ["-L/opt/rocm/lib", "-lrocblas", "-pthread", "-Wl,-rpath,/opt/rocm/lib"]
 
 
 def hipcc():

@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "runtime.h"
@@ -170,8 +171,9 @@ msld_status make_plan(const msld_params* p, int ninst, Plan* pl) {
       pl->off_pg[i] = take(4 * (size_t)nblk * nbp);
       if (lr) {
         const size_t nb2 = (size_t)g.nb * g.nb;
+        const size_t tn = ((size_t)g.nb + 63) / 64;
         const size_t per = 3 * nb2 + 4 * (size_t)g.nb * kLRP + (size_t)g.mb * kLRP +
-                           (size_t)kLRP * g.nb + 3 * kLRP + 8;
+                           (size_t)kLRP * g.nb + 3 * kLRP + 8 + (size_t)g.nb * (tn + 1);
         pl->off_lr[i] = take(4 * ((size_t)nblk * per + (size_t)g.nb * kLRP + 64 + 3 * nblk));
         if (!lds_fits(g.mb, g.nb)) {
           // polar fallback buffers for a chunk of failed certificates (<= 256 MiB)
@@ -268,8 +270,9 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
     return MSLD_ENOMEM;
   }
   {
+    // scales run concurrently: each low-rank scale gets its own slice
     int cap = 0;
-    for (int i = 0; i < p->L; ++i) cap = std::max(cap, s->plan.pl_cap[i]);
+    for (int i = 0; i < p->L; ++i) cap += s->plan.pl_cap[i];
     if (cap > 0 && hipHostMalloc(&s->host_pl, 4 * (size_t)cap * sizeof(float),
                                  hipHostMallocDefault) != hipSuccess) {
       destroy_solver(s);
@@ -353,6 +356,7 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
         w.lrT = f; f += slots * kLRP * g.nb;
         w.lrSig = f; f += 3 * slots * kLRP;   // sigma, deflation mask, bound mask
         w.lrScal = f; f += slots * 8;
+        w.lrRow = f; f += slots * (size_t)g.nb * (((size_t)g.nb + 63) / 64 + 1);
         w.lrOm = f; f += (size_t)g.nb * kLRP;
         w.lrCount = reinterpret_cast<int*>(f);
         w.lrFall = w.lrCount + 64;
@@ -370,7 +374,9 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
           w.plY = q; q += cap * nb2;
           w.plW = q; q += cap * nb2;
           w.plScal = q;
-          w.hostPl = s->host_pl;
+          size_t hoff = 0;
+          for (int i2 = 0; i2 < i; ++i2) hoff += 4 * (size_t)pl.pl_cap[i2];
+          w.hostPl = s->host_pl + hoff;
         }
       }
     }
@@ -489,11 +495,15 @@ msld_status iterate_once(msld_solver* s, const float* d_Y, int64_t ldY, float* d
   for (int pass = 0; pass < 2; ++pass)
     for (int i = 0; i < L; ++i)
       if (pl.tier[i] != TIER_1X1 && (pl.use_lr[i] != 0) == (pass == 1)) order[no++] = i;
+  // fork every scale first (stream order only), then issue their work; the scales
+  // whose host driver waits on the device get a host thread each (but the last), so
+  // that one scale's waits do not hold back the issue of another's work
+  ShiftSpec shs[MSLD_MAX_SCALES];
   for (int oi = 0; oi < no; ++oi) {
     const int i = order[oi];
     msld_status fs = fork_scale(s, i);
     if (fs != MSLD_OK) return fs;
-    ShiftSpec sh;
+    ShiftSpec& sh = shs[i];
     sh.seed = p.shift_seed;
     sh.k = s->k;
     sh.scale = i;
@@ -502,11 +512,40 @@ msld_status iterate_once(msld_solver* s, const float* d_Y, int64_t ldY, float* d
     sh.iseed = stacked ? s->d_seed : nullptr;
     sh.ik = stacked ? s->d_k : nullptr;
     sh.iactive = stacked ? s->d_active : nullptr;
+  }
+  hipError_t herr[MSLD_MAX_SCALES];
+  int rls[MSLD_MAX_SCALES];
+  auto issue = [&](int i) {
     float* Zi = d_Z + MN * i;
-    msld_status rs = run_scale(s, i, Zi, R, Zi, Dn + MN * i, pl.tau_default[i], sh,
-                               ev ? ev + 4 + 5 * i : nullptr, true);
-    if (rs != MSLD_OK) return rs;
-    rs = join_scale(s, i);
+    rls[i] = 0;
+    herr[i] = launch_scale(pl.geom[i], pl.tier[i], pl.sp[i], s->work[i], Zi, R, Zi, Dn + MN * i,
+                           pl.tau_default[i], shs[i], jacobi_tol(pl.geom[i].mb), 40, 20,
+                           s->num_cus, s->sst[i], ev ? ev + 4 + 5 * i : nullptr, &rls[i],
+                           true);
+  };
+  std::vector<std::thread> workers;
+  int first_waiting = no;
+  for (int oi = 0; oi < no; ++oi)
+    if (pl.use_lr[order[oi]]) {
+      first_waiting = oi;
+      break;
+    }
+  for (int oi = 0; oi < first_waiting; ++oi) issue(order[oi]);
+  for (int oi = first_waiting; oi + 1 < no; ++oi) {
+    const int i = order[oi];
+    try {
+      workers.emplace_back(issue, i);
+    } catch (...) {
+      issue(i);   // no thread available: issue in order
+    }
+  }
+  if (first_waiting < no) issue(order[no - 1]);
+  for (auto& t : workers) t.join();
+  for (int oi = 0; oi < no; ++oi) {
+    const int i = order[oi];
+    if (herr[i] != hipSuccess) return dev_err(s, herr[i]);
+    if (ev) s->round_launches[i] += rls[i];
+    msld_status rs = join_scale(s, i);
     if (rs != MSLD_OK) return rs;
   }
   if (want_res) {

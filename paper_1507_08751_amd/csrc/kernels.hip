@@ -273,17 +273,20 @@ __global__ void __launch_bounds__(256) k_tiny_live(
       g[j] = sig > tau ? 1.f - tau / sig : 0.f;
       rank += g[j] > 0.f;
     }
+    // rank 0: the stream pass already wrote Z' = 0, D' = -V
+    if (rank > 0) {
 #pragma unroll
-    for (int i = 0; i < B; ++i)
+      for (int i = 0; i < B; ++i)
 #pragma unroll
-      for (int c2 = 0; c2 < B; ++c2) {
-        float z = 0.f;
+        for (int c2 = 0; c2 < B; ++c2) {
+          float z = 0.f;
 #pragma unroll
-        for (int j = 0; j < B; ++j) z += g[j] * a[i][j] * w[c2][j];
-        const int64_t o = (int64_t)rows[i] * N + cols[c2];
-        Zout[o] = z;
-        Dout[o] = 2.f * z - v0[i][c2];
-      }
+          for (int j = 0; j < B; ++j) z += g[j] * a[i][j] * w[c2][j];
+          const int64_t o = (int64_t)rows[i] * N + cols[c2];
+          Zout[o] = z;
+          Dout[o] = 2.f * z - v0[i][c2];
+        }
+    }
     atomicAdd(&stats[0], 1ull);
     atomicAdd(&stats[1], (unsigned long long)sweeps);
     atomicAdd(&stats[2], (unsigned long long)rank);
@@ -672,7 +675,8 @@ __global__ void __launch_bounds__(1024) k_svd_lds(
     __syncthreads();
     const int k = s_k;
     // rebuild B' = sum_j g_j (B w_j) w_j^T and scatter to the wrapped coordinates
-    for (int e = tid; e < m * n; e += nt) {
+    // (rank 0: the stream pass already wrote Z' = 0, D' = -V)
+    for (int e = tid; k > 0 && e < m * n; e += nt) {
       const int i = e / n;
       const int j = e - i * n;
       const int r = trans ? j : i;

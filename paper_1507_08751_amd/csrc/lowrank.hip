@@ -12,7 +12,8 @@
 //                                 + (sum_{l in K} sigma_l^2 c_l^2)^(1/2)
 //        (K: further well-converged directions outside L, E = B (I - V V^T) the
 //        remainder after L and K; a 2 x 2 block split of E_L^T E_L), with
-//        lambda_max(E^T E) <= tr * ||(E^T E / tr)^k||_F^(1/k) for k = 1, 2, 8, and
+//        lambda_max(E^T E) <= min(||E^T E||_F, Collatz-Wielandt bound of |E^T E| with the
+//        vector of its row sums), then tr * ||(E^T E / tr)^k||_F^(1/k), k = 2, 8, and
 //   (ii) ||U_L^T E_L||_F is below a small fraction of ||B||_F.
 // Then B0 = U_L S_L V_L^T + (I - U_L U_L^T) E_L decouples, SVT(B0) = Z (columns of L
 // below tau threshold to zero), and since the proximal map is non-expansive
@@ -420,10 +421,11 @@ __global__ void __launch_bounds__(256) k_lr_q(const float* Wg, const float* Vr, 
 template <int P>
 __global__ void __launch_bounds__(256) k_lr_ge(const float* G, const float* Qm, const float* Vr,
                                                const float* mask, float* Pm, int nb,
-                                               float* part) {
+                                               float* part, float* rowpart) {
   __shared__ float qi[64][P + 1], vi[64][P + 1], qj[64][P + 1], vj[64][P + 1];
   __shared__ float mk[P];
   __shared__ float red[8];
+  __shared__ float rs[4][64];
   const int slot = blockIdx.y;
   const int tn = (nb + 63) / 64;
   const int ti = blockIdx.x % tn, tj = blockIdx.x / tn;
@@ -453,7 +455,7 @@ __global__ void __launch_bounds__(256) k_lr_ge(const float* G, const float* Qm, 
     qa[l] = qi[il][l];
     va[l] = vi[il][l];
   }
-  float tr = 0.f, f2 = 0.f;
+  float tr = 0.f, f2 = 0.f, ra = 0.f;
   if (i < nb) {
     for (int jl = tid >> 6; jl < 64; jl += 4) {
       const int j = j0 + jl;
@@ -464,13 +466,87 @@ __global__ void __launch_bounds__(256) k_lr_ge(const float* G, const float* Qm, 
       pm[(int64_t)j * nb + i] = s;
       if (i == j) tr += s;
       f2 += s * s;
+      ra += fabsf(s);
     }
   }
+  rs[tid >> 6][il] = ra;
   tr = block_sum(tr, red);
   f2 = block_sum(f2, red);
   if (tid == 0) {
     part[((int64_t)slot * gridDim.x + blockIdx.x) * 2] = tr;
     part[((int64_t)slot * gridDim.x + blockIdx.x) * 2 + 1] = f2;
+  }
+  // partial row |.| sums of this tile column (rows i0.., columns j0..j0+63)
+  if (tid < 64 && i < nb)
+    rowpart[(int64_t)slot * nb * (tn + 1) + (int64_t)tj * nb + i] =
+        rs[0][il] + rs[1][il] + rs[2][il] + rs[3][il];
+}
+
+// Collatz-Wielandt bound for the symmetric M = E^T E (in Pm): with r = |M| 1 and
+// y = |M| r, lambda_max(M) <= rho(|M|) <= max_i y_i / r_i (a row with r_i = 0 is zero).
+// Three small steps on the tile partials, all in a fixed summation order:
+// k_lr_rsum: r_i = sum over tile columns of the row partials of k_lr_ge (slice tn);
+// k_lr_cwy: per 64 x 64 tile, partial y_i over its columns (slices 0..tn-1);
+// k_lr_cwmax: y_i, the ratio, its maximum; scal[4] = min(||M||_F, bound) / tr(M).
+__global__ void __launch_bounds__(256) k_lr_rsum(float* rowpart, int nb) {
+  const int slot = blockIdx.y;
+  const int tn = (nb + 63) / 64;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  float* rp = rowpart + (int64_t)slot * nb * (tn + 1);
+  float v = 0.f;
+  for (int t = 0; t < tn; ++t) v += rp[(int64_t)t * nb + i];
+  rp[(int64_t)tn * nb + i] = v;
+}
+
+__global__ void __launch_bounds__(256) k_lr_cwy(const float* Pm, float* rowpart, int nb) {
+  __shared__ float rj[64];
+  __shared__ float ys[4][64];
+  const int slot = blockIdx.y;
+  const int tn = (nb + 63) / 64;
+  const int ti = blockIdx.x % tn, tj = blockIdx.x / tn;
+  const int i0 = ti * 64, j0 = tj * 64;
+  float* rp = rowpart + (int64_t)slot * nb * (tn + 1);
+  const float* pm = Pm + (int64_t)slot * nb * nb;
+  const int tid = threadIdx.x;
+  if (tid < 64) rj[tid] = j0 + tid < nb ? rp[(int64_t)tn * nb + j0 + tid] : 0.f;
+  __syncthreads();
+  const int il = tid & 63, i = i0 + il;
+  float y = 0.f;
+  if (i < nb)
+    for (int jl = tid >> 6; jl < 64; jl += 4) {
+      const int j = j0 + jl;
+      if (j >= nb) break;
+      y += fabsf(pm[(int64_t)j * nb + i]) * rj[jl];
+    }
+  ys[tid >> 6][il] = y;
+  __syncthreads();
+  if (tid < 64 && i < nb) rp[(int64_t)tj * nb + i] = ys[0][il] + ys[1][il] + ys[2][il] + ys[3][il];
+}
+
+__global__ void __launch_bounds__(256) k_lr_cwmax(const float* rowpart, int nb, float* scal) {
+  __shared__ float red[8];
+  const int slot = blockIdx.x;
+  const int tn = (nb + 63) / 64;
+  const float* rp = rowpart + (int64_t)slot * nb * (tn + 1);
+  float best = 0.f;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    float y = 0.f;
+    for (int t = 0; t < tn; ++t) y += rp[(int64_t)t * nb + i];
+    const float ri = rp[(int64_t)tn * nb + i];
+    if (ri > 0.f) best = fmaxf(best, y / ri);
+    else if (y > 0.f) best = __int_as_float(0x7f800000);   // not for a symmetric M
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) best = fmaxf(best, __shfl_xor(best, o));
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) red[wv] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float b = 0.f;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) b = fmaxf(b, red[w]);
+    const float tr = scal[slot * 8 + 2];
+    if (tr > 0.f && isfinite(b)) scal[slot * 8 + 4] = fminf(scal[slot * 8 + 4], b / tr);
   }
 }
 
@@ -615,14 +691,19 @@ __global__ void __launch_bounds__(256) k_lr_rebuild(float* __restrict__ Zout,
                                                     const float* Vr, const float* sig,
                                                     float tau) {
   __shared__ float gl[P];
+  __shared__ int s_any;
   const int N = g.N, m = g.m, n = g.n, Q = g.Q, mb = g.mb, nb = g.nb;
   const int slot = blockIdx.y;
   if (!pflag[4 * slot + 2]) return;
+  if (threadIdx.x == 0) s_any = 0;
+  __syncthreads();
   if (threadIdx.x < P) {
     const float s = sig[slot * P + threadIdx.x];
     gl[threadIdx.x] = s > tau ? 1.f - tau / s : 0.f;
+    if (s > tau) s_any = 1;
   }
   __syncthreads();
+  if (!s_any) return;   // Z = 0: the stream pass already wrote Z' = 0, D' = -V
   const int blk = live_list[slot];
   const int p = blk / Q, q = blk - p * Q;
   int sr, sc;
@@ -755,12 +836,18 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int gtiles = ((nb + 63) / 64) * ((nb + 63) / 64);
   hipLaunchKernelGGL(k_lr_ge<P>, dim3(gtiles, count), dim3(256), 0, st, w.lrG, w.lrY, w.lrV,
-                     dmask, w.lrP, nb, w.lrQ);
+                     dmask, w.lrP, nb, w.lrQ, w.lrRow);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int tiles = (int)((sG + 255) / 256 < 64 ? (sG + 255) / 256 : 64);
   // stage 0: Frobenius bound of E^T E (partials were written to lrQ)
   hipLaunchKernelGGL(k_lr_ge_reduce, dim3((count + 255) / 256), dim3(256), 0, st, w.lrQ, gtiles,
                      count, w.lrScal);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_lr_rsum, dim3((nb + 255) / 256, count), dim3(256), 0, st, w.lrRow, nb);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_lr_cwy, dim3(gtiles, count), dim3(256), 0, st, w.lrP, w.lrRow, nb);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_lr_cwmax, dim3(count), dim3(256), 0, st, w.lrRow, nb, w.lrScal);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_lr_decide, dim3((count + 255) / 256), dim3(256), 0, st, count, w.slots, w.lrScal,
                      w.lrSig, tau, w.pflag, w.lrCount, w.lrFall, w.live_list, w.stats, 0, 1);

@@ -11,7 +11,8 @@
 //   the remainder E_L = B (I - V_L V_L^T) is bounded through the remainder E after L and
 //   the further well-converged directions K: lambda_max(E_L^T E_L) <= max(max_{l in K}
 //   sigma_l^2, lambda_max(E^T E)) + (sum_{l in K} sigma_l^2 c_l^2)^(1/2), with
-//   lambda_max(E^T E) <= tr * ||(E^T E / tr)^k||_F^(1/k), k = 1, 2, 8.
+//   lambda_max(E^T E) <= min(||E^T E||_F, the Collatz-Wielandt bound of |E^T E| with its
+//   row sums), then tr * ||(E^T E / tr)^k||_F^(1/k), k = 2, 8.
 // Accepted blocks get Z = sum_{l in L, sigma_l > tau} (1 - tau / sigma_l) a_l v_l^T
 // (the error is at most the tested coupling, by non-expansiveness of the prox of
 // eq:svt); the others are listed for the LDS Jacobi tier, which runs right after.
@@ -40,6 +41,19 @@ __device__ __forceinline__ float bsum(float v, float* red) {
   float s = 0.f;
 #pragma unroll
   for (int w = 0; w < kNT / 64; ++w) s += red[w];
+  return s;
+}
+
+__device__ __forceinline__ float bmax(float v, float* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  float s = 0.f;
+#pragma unroll
+  for (int w = 0; w < kNT / 64; ++w) s = fmaxf(s, red[w]);
   return s;
 }
 
@@ -412,10 +426,28 @@ __global__ void __launch_bounds__(kNT, 4) k_lr_small(float* __restrict__ Zout,
       }
       tr = bsum(tr, red);
       f2 = bsum(f2, red);
+      // Collatz-Wielandt bound of |E^T E| with its row sums r: lambda_max <= max_i
+      // (|E^T E| r)_i / r_i (r kept in Bs, free from here on)
+      __syncthreads();
+      for (int i = tid; i < NB; i += kNT) {
+        float v = 0.f;
+        for (int j = 0; j < NB; ++j) v += fabsf(Gs[j * LDG + i]);
+        Bs[i] = v;
+      }
+      __syncthreads();
+      float cw = 0.f;
+      for (int i = tid; i < NB; i += kNT) {
+        float y = 0.f;
+        for (int j = 0; j < NB; ++j) y += fabsf(Gs[i * LDG + j]) * Bs[j];
+        const float ri = Bs[i];
+        if (ri > 0.f) cw = fmaxf(cw, y / ri);
+        else if (y > 0.f) cw = __int_as_float(0x7f800000);
+      }
+      cw = bmax(cw, red);
       // lambda_max(E_L^T E_L) <= max(max_l' sigma_l'^2, lambda_max(E^T E)) + cross term,
       // l' the well-converged directions split off besides L, E the remainder after both
       const float omax = s_omax, cross = s_cross;
-      const float b0 = fmaxf(omax, tr > 0.f ? sqrtf(f2) : 0.f) + cross;
+      const float b0 = fmaxf(omax, tr > 0.f ? fminf(sqrtf(f2), cw) : 0.f) + cross;
       if (b0 <= lim && isfinite(b0)) {
         state = 1;
       } else if (!(tr > 0.f) || !isfinite(tr)) {
@@ -445,8 +477,12 @@ __global__ void __launch_bounds__(kNT, 4) k_lr_small(float* __restrict__ Zout,
         }
       }
     }
-    if (state == 1) {
-      // Z = sum_L (1 - tau / sigma_l)_+ a_l v_l^T, scattered with D' = 2 Z' - V
+    int nlive = 0;
+#pragma unroll
+    for (int l = 0; l < P; ++l) nlive += (mask[l] > 0.f && sig[l] > tau) ? 1 : 0;
+    if (state == 1 && nlive > 0) {
+      // Z = sum_L (1 - tau / sigma_l)_+ a_l v_l^T, scattered with D' = 2 Z' - V (with no
+      // live direction the stream pass already wrote Z' = 0, D' = -V)
       for (int e = tid; e < m * n; e += kNT) {
         const int i = e / n, j = e - i * n;
         const int r = g.trans ? j : i;
@@ -466,10 +502,8 @@ __global__ void __launch_bounds__(kNT, 4) k_lr_small(float* __restrict__ Zout,
     }
     if (tid == 0) {
       if (state == 1) {
-        int k = 0;
-        for (int l = 0; l < P; ++l) k += (mask[l] > 0.f && sig[l] > tau) ? 1 : 0;
         atomicAdd(&stats[0], 1ull);
-        atomicAdd(&stats[2], (unsigned long long)k);
+        atomicAdd(&stats[2], (unsigned long long)nlive);
         atomicAdd(&stats[3], 1ull);
       } else {
         atomicAdd(&stats[state == -1 ? 4 : 5], 1ull);

@@ -119,6 +119,7 @@ struct ScaleWork {
   float* lrV;           // [slots][nb*p] right vectors V_r
   float* lrSig;         // [3][slots][p]: sigma, deflation mask, remainder-bound mask
   float* lrScal;        // [slots][8]
+  float* lrRow;         // [slots][nb / 64 + 1][nb] row partials of |E^T E| and row sums
   float* lrOm;          // [nb*p] probe matrix
   int* lrCount;         // [4] device counters: fallback, undecided
   int* lrFall;          // [3 slots] block ids, then slot indices, of failed certificates;
