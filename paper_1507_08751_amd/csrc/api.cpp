@@ -154,7 +154,7 @@ msld_status make_plan(const msld_params* p, int ninst, Plan* pl) {
       pl->off_rowp[i] = take(4 * (size_t)nblk * sp.spb * m);
       pl->off_frop[i] = take(4 * (size_t)nblk * sp.spb);
     }
-    if (tier == TIER_LRS) pl->off_lr[i] = take(4 * (64 + (size_t)nblk));   // fallback list
+    if (tier == TIER_LRS) pl->off_lr[i] = take(4 * (64 + 2 * (size_t)nblk));   // fallback lists
     if (tier == TIER_PANEL) {
       // panel width: two panels of A (mb rows) and W (nb rows) in LDS; 4 <= pw <= 64
       int pw = (int)(kLdsTierMax / 4 / (2 * ((size_t)(g.mb | 1) + (size_t)(g.nb | 1))));

@@ -1037,12 +1037,18 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
     return hipSuccess;
   }
   if (tier == TIER_LRS) {
-    // fused certified low-rank kernel, then the LDS Jacobi tier on its failures
-    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, w.lrCount);
+    // fused certified low-rank kernel; its failures get a retry with a twice wider
+    // subspace, and what still fails goes to the LDS Jacobi tier
+    hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, w.lrCount, 2);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     MSLD_EV(2);
-    if ((e = launch_lr_small(g, w, Zout, Dout, tau, sh, num_cus, st)) != hipSuccess) return e;
+    if ((e = launch_lr_small(g, w, Zout, Dout, tau, sh, num_cus, 0, w.live_count, w.live_list,
+                             w.lrCount, w.lrFall, st)) != hipSuccess)
+      return e;
     MSLD_EV(3);
+    if ((e = launch_lr_small(g, w, Zout, Dout, tau, sh, num_cus, 1, w.lrCount, w.lrFall,
+                             w.lrCount + 1, w.lrFall + nblk, st)) != hipSuccess)
+      return e;
     int G = 1;
     const int threads = lds_tier_threads(g.nb, g.mb, &G);
     const size_t ldsb = lds_tier_bytes(g.mb, g.nb);
@@ -1054,8 +1060,8 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
     int grid = num_cus * per_cu;
     if (grid > nblk) grid = nblk;
     ScaleWork fw = w;
-    fw.live_count = w.lrCount;
-    fw.live_list = w.lrFall;
+    fw.live_count = w.lrCount + 1;
+    fw.live_list = w.lrFall + nblk;
     switch (G) {
       case 1: e = launch_lds_g<1>(grid, threads, ldsb, Zout, Dout, g, sh, tau, jtol, max_sweeps, fw, st); break;
       case 2: e = launch_lds_g<2>(grid, threads, ldsb, Zout, Dout, g, sh, tau, jtol, max_sweeps, fw, st); break;

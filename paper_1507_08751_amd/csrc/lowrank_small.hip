@@ -520,7 +520,8 @@ size_t lr_small_lds_bytes(int NB, int MB, int P) {
               (size_t)P * (MB + 1) + (size_t)P * (P + 1));
 }
 
-// (NB, MB) padded sizes the fused kernel is instantiated for; 0 when none fits.
+// (NB, MB) padded sizes the fused kernel is instantiated for, and the subspace width of
+// its first pass (the retry pass on failures uses twice that); 0 when none fits.
 int lr_small_shape(int mb, int nb, int* NB, int* MB, int* P) {
   // beyond 64 columns the batched-GEMM path is faster (its products keep the whole
   // chip busy, while this kernel holds one block per workgroup)
@@ -533,26 +534,37 @@ int lr_small_shape(int mb, int nb, int* NB, int* MB, int* P) {
   return 1;
 }
 
+// One pass of the fused kernel over (count, list); failures are appended to
+// (fcount, flist). pass 0 uses the first subspace width, pass 1 twice that.
 hipError_t launch_lr_small(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout,
-                           float tau, const ShiftSpec& sh, int num_cus, hipStream_t st) {
+                           float tau, const ShiftSpec& sh, int num_cus, int pass,
+                           const int* count, const int* list, int* fcount, int* flist,
+                           hipStream_t st) {
   int NB = 0, MB = 0, P = 0;
   if (!lr_small_shape(g.mb, g.nb, &NB, &MB, &P)) return hipErrorInvalidValue;
+  if (pass) P *= 2;
   const size_t lds = lr_small_lds_bytes(NB, MB, P);
   int per_cu = (int)(160 * 1024 / (lds + 2048));
   if (per_cu > 8) per_cu = 8;
+  if (pass && per_cu > 1) per_cu = 1;   // the retry list is short
   if (per_cu < 1) per_cu = 1;
   int grid = num_cus * per_cu;
   const int nblk = g.P * g.Q;
   if (grid > nblk) grid = nblk;
 #define MSLD_LRS(nb_, mb_, p_)                                                                  \
-  if (NB == nb_ && MB == mb_)                                                                   \
+  if (NB == nb_ && MB == mb_ && P == p_)                                                        \
     hipLaunchKernelGGL((k_lr_small<nb_, mb_, p_>), dim3(grid), dim3(kNT), lds, st, Zout, Dout, \
-                       g, sh, tau, w.live_count, w.live_list, w.lrCount, w.lrFall, w.stats)
+                       g, sh, tau, count, list, fcount, flist, w.stats)
   MSLD_LRS(32, 32, 4);
   else MSLD_LRS(32, 64, 4);
   else MSLD_LRS(32, 128, 4);
+  else MSLD_LRS(32, 32, 8);
+  else MSLD_LRS(32, 64, 8);
+  else MSLD_LRS(32, 128, 8);
   else MSLD_LRS(64, 64, 8);
   else MSLD_LRS(64, 128, 8);
+  else MSLD_LRS(64, 64, 16);
+  else MSLD_LRS(64, 128, 16);
   else return hipErrorInvalidValue;
 #undef MSLD_LRS
   return hipGetLastError();

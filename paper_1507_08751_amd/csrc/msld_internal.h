@@ -188,7 +188,9 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
 int lr_small_shape(int mb, int nb, int* NB, int* MB, int* P);
 size_t lr_small_lds_bytes(int NB, int MB, int P);
 hipError_t launch_lr_small(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout,
-                           float tau, const ShiftSpec& sh, int num_cus, hipStream_t st);
+                           float tau, const ShiftSpec& sh, int num_cus, int pass,
+                           const int* count, const int* list, int* fcount, int* flist,
+                           hipStream_t st);
 hipError_t batched_sgemm(void* blas, bool ta, bool tb, int m, int n, int k, const float* A,
                          int lda, int64_t sa, const float* B, int ldb, int64_t sb, float* C,
                          int ldc, int64_t sc, int batch);

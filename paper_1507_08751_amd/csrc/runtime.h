@@ -14,7 +14,7 @@
 namespace msld {
 
 constexpr size_t kLdsTierMax = 150 * 1024;   // LDS budget of one workgroup (160 KiB per CU)
-constexpr int kStreamFloats = 16384;         // stream-pass tile budget (floats)
+constexpr int kStreamFloats = 16384;         // stream-pass tile budget (elements)
 constexpr int kLRP = 16;                     // subspace width of the certified low-rank path
 
 int lds_tier_threads(int nb, int mb, int* G);
