@@ -23,9 +23,14 @@ Parity status per function (what independent facts pin it; see tests/):
   admm                pinned: KKT conditions and a vanishing duality gap at
                       convergence, scaling / transpose invariances, trivial
                       ladders, ground-truth recovery on sparse instances.
+  noise_svt,          pinned: prox optimality of the Frobenius norm (zero inside
+  scale_lambda        the ball, the subgradient condition outside), the lambda
+                      special case of the MN x 1 block, and the noisy program's
+                      KKT conditions / duality gap through admm(kinds=...).
 """
 from .msld_oracle import (  # noqa: F401
     MASK64, splitmix64_mix, cycle_shift, default_lambda, shift, unshift, svt,
     block_svt, cycle_spun_bsvt, admm, block_nuclear_norm, block_dual_norm,
-    kkt_report, skip_bound_sq,
+    kkt_report, skip_bound_sq, KIND_BLOCK, KIND_NOISE, noise_svt, scale_lambda,
+    scale_norm, scale_dual_norm,
 )

@@ -97,15 +97,39 @@ def cycle_spun_bsvt(A: np.ndarray, m: int, n: int, tau: float, s) -> np.ndarray:
     return unshift(block_svt(shift(A, s), m, n, tau), s)
 
 
+# ------------------------------------------------------------------ noise scale
+# Sec. 2 (multi-scale low rank + noise): the noise matrix is one more scale whose
+# reshape R_Z takes the whole M x N matrix to an MN x 1 vector; the block-wise nuclear
+# norm of that scale is then the Frobenius norm (Sec. 3, remark after eq:cvx).
+KIND_BLOCK = 0       # block-wise nuclear norm over an m_i x n_i partition
+KIND_NOISE = 1       # nuclear norm of the MN x 1 reshape (Frobenius norm)
+
+
+def noise_svt(A: np.ndarray, tau: float) -> np.ndarray:
+    """SVT of eq:svt applied to the MN x 1 reshape R_Z(A), placed back by R_Z^T."""
+    A = np.asarray(A, dtype=np.float64)
+    return svt(A.reshape(-1, 1), tau).reshape(A.shape)
+
+
+def scale_lambda(M: int, N: int, m: int, n: int, kind: int = KIND_BLOCK) -> float:
+    """eq:lambda for scale i; the noise scale's block is MN x 1 (Sec. 4 notes its
+    lambda ~ sqrt(MN))."""
+    if kind == KIND_NOISE:
+        return default_lambda(M, N, M * N, 1)
+    return default_lambda(M, N, m, n)
+
+
 # --------------------------------------------------------------------------- ADMM
 def admm(Y, ladder, lam=None, rho=1.0, iters=100, cycle_spin=False, seed=0,
-         tol=0.0, check_every=1, history=False):
+         tol=0.0, check_every=1, history=False, kinds=None):
     """ADMM of Sec. 7 (eq:admm) for eq:cvx, with the random cycle spinning of Sec. 9.
 
     Per iteration k, in the paper's order:
         X_i <- (Z_i - U_i) + (Y - sum_j (Z_j - U_j)) / L
         Z_i <- Shift_{-s}(BSVT_{lambda_i/rho}(Shift_s(X_i + U_i)))   (s = 0 without spinning)
         U_i <- U_i - (Z_i - X_i)
+    kinds[i] == KIND_NOISE makes scale i the noise scale of Sec. 2 (its Z-step is the
+    SVT of the MN x 1 reshape, which no shift changes; its block size must be M x N).
     Readings where the paper is silent: Z_i = U_i = 0 at start; the returned
     components are Z_i (exactly block-low-rank); primal residual
     r_k = sqrt(sum_i ||X_i - Z_i||_F^2) / ||Y||_F with the new Z_i; when tol > 0 the
@@ -115,8 +139,9 @@ def admm(Y, ladder, lam=None, rho=1.0, iters=100, cycle_spin=False, seed=0,
     M, N = Y.shape
     ladder = [(int(m), int(n)) for (m, n) in ladder]
     L = len(ladder)
+    kinds = [KIND_BLOCK] * L if kinds is None else [int(x) for x in kinds]
     if lam is None:
-        lam = [default_lambda(M, N, m, n) for (m, n) in ladder]
+        lam = [scale_lambda(M, N, m, n, kinds[i]) for i, (m, n) in enumerate(ladder)]
     lam = [float(x) for x in lam]
     Z = np.zeros((L, M, N))
     U = np.zeros((L, M, N))
@@ -131,6 +156,9 @@ def admm(Y, ladder, lam=None, rho=1.0, iters=100, cycle_spin=False, seed=0,
         for i in range(L):
             X[i] = (Z[i] - U[i]) + (Y - S) / L
         for i, (m, n) in enumerate(ladder):
+            if kinds[i] == KIND_NOISE:
+                Z[i] = noise_svt(X[i] + U[i], lam[i] / rho)
+                continue
             s = cycle_shift(seed, k, i, m, n) if cycle_spin else (0, 0)
             Z[i] = cycle_spun_bsvt(X[i] + U[i], m, n, lam[i] / rho, s)
         U = U - (Z - X)
@@ -159,7 +187,21 @@ def block_dual_norm(A, m, n) -> float:
     return float(np.linalg.svd(Bk.reshape(P * Q, m, n), compute_uv=False).max())
 
 
-def kkt_report(Y, ladder, lam, rho, Z, U):
+def scale_norm(A, m, n, kind=KIND_BLOCK) -> float:
+    """The norm of scale i in eq:cvx (Frobenius for the noise scale)."""
+    if kind == KIND_NOISE:
+        return float(np.linalg.norm(A))
+    return block_nuclear_norm(A, m, n)
+
+
+def scale_dual_norm(A, m, n, kind=KIND_BLOCK) -> float:
+    """Its dual norm (Sec. 3); the Frobenius norm is self-dual."""
+    if kind == KIND_NOISE:
+        return float(np.linalg.norm(A))
+    return block_dual_norm(A, m, n)
+
+
+def kkt_report(Y, ladder, lam, rho, Z, U, kinds=None):
     """Optimality diagnostics for eq:cvx from an ADMM state (no cycle spinning).
 
     Dual certificate: at a fixed point all U_i coincide and Q = rho * mean_i U_i
@@ -170,13 +212,14 @@ def kkt_report(Y, ladder, lam, rho, Z, U):
     """
     Y = np.asarray(Y, dtype=np.float64)
     L = len(ladder)
+    kinds = [KIND_BLOCK] * L if kinds is None else list(kinds)
     Ubar = np.mean(U, axis=0)
     Q = rho * Ubar
-    ratios = [block_dual_norm(Q, m, n) / lam[i] for i, (m, n) in enumerate(ladder)]
+    ratios = [scale_dual_norm(Q, m, n, kinds[i]) / lam[i] for i, (m, n) in enumerate(ladder)]
     Qs = Q / max(1.0, max(ratios))
     dual = float((Qs * Y).sum())
     Zf = Z + (Y - Z.sum(axis=0)) / L
-    primal = float(sum(lam[i] * block_nuclear_norm(Zf[i], m, n)
+    primal = float(sum(lam[i] * scale_norm(Zf[i], m, n, kinds[i])
                        for i, (m, n) in enumerate(ladder)))
     spread = float(max(np.linalg.norm(U[i] - Ubar) for i in range(L)) /
                    max(np.linalg.norm(Ubar), 1e-300))

@@ -281,3 +281,61 @@ def test_admm_tolerance_stop_and_history():
     assert out["iters"] % 5 == 0 and out["resid"] <= 1e-2 and out["iters"] < 500
     assert len(out["history"]) == out["iters"]
     assert all(h > 1e-2 for h in out["history"][4:out["iters"] - 1:5])
+
+
+# ------------------------------------------------------------------ noise scale
+@pytest.mark.parametrize("scale", [0.3, 3.0])
+def test_noise_svt_prox_optimality(scale):
+    """The noise scale's Z-step is the prox of tau ||.||_F (Sec. 2: SVT of the MN x 1
+    reshape). Optimality: 0 in Z - V + tau dF(Z) with dF(0) the unit ball and
+    dF(Z) = Z / ||Z||_F otherwise; checked on both sides of ||V||_F = tau."""
+    rng = np.random.default_rng(11)
+    V = scale * rng.standard_normal((12, 9))
+    tau = 1.7
+    Z = O.noise_svt(V, tau)
+    nv = np.linalg.norm(V)
+    if nv <= tau:
+        assert np.abs(Z).max() == 0.0
+    else:
+        nz = np.linalg.norm(Z)
+        assert nz > 0
+        assert np.abs(Z - V + tau * Z / nz).max() < 1e-12
+        # the prox is the minimiser: compare with perturbed candidates
+        f = lambda X: 0.5 * ((X - V) ** 2).sum() + tau * np.linalg.norm(X)
+        for _ in range(20):
+            D = 1e-3 * rng.standard_normal(V.shape)
+            assert f(Z) <= f(Z + D) + 1e-15
+
+
+def test_noise_lambda_is_the_mn_by_1_block():
+    """eq:lambda on the MN x 1 block: sqrt(MN) + 1 + sqrt(log 1) = sqrt(MN) + 1, the
+    sqrt(MN) scaling Sec. 4 states for the noise matrix."""
+    assert abs(O.scale_lambda(64, 48, 64, 48, O.KIND_NOISE) - (math.sqrt(64 * 48) + 1)) < 1e-12
+    assert O.scale_lambda(64, 48, 8, 4) == O.default_lambda(64, 48, 8, 4)
+
+
+def test_admm_noise_only_converges_to_Y():
+    """With the noise scale alone the constraint X = Y decides: Z -> Y."""
+    rng = np.random.default_rng(3)
+    Y = rng.standard_normal((16, 12))
+    out = O.admm(Y, [(16, 12)], rho=1.0, iters=400, kinds=[O.KIND_NOISE])
+    assert np.abs(out["Z"][0] - Y).max() < 1e-8
+
+
+def test_admm_noisy_program_kkt_and_gap():
+    """eq:noisy (Sec. 6): sparse + low rank + noise scale. At convergence the dual
+    certificate Q = rho mean U_i meets every scale's dual norm bound (Frobenius for
+    the noise scale) and the duality gap vanishes."""
+    inst = make_instance(16, 16, [(1, 1), (16, 16)], 0.05, noise=0.05, seed=2)
+    Y = inst.Y.astype(np.float64)
+    ladder = [(1, 1), (16, 16), (16, 16)]
+    kinds = [O.KIND_BLOCK, O.KIND_BLOCK, O.KIND_NOISE]
+    lam = [O.scale_lambda(16, 16, m, n, k) for (m, n), k in zip(ladder, kinds)]
+    lam[2] *= 0.25          # a noise weight that leaves both other scales active
+    out = O.admm(Y, ladder, lam=lam, rho=1.0, iters=3000, kinds=kinds)
+    rep = O.kkt_report(Y, ladder, lam, 1.0, out["Z"], out["U"], kinds=kinds)
+    assert out["resid"] < 1e-7
+    assert rep["u_spread"] < 1e-7
+    assert max(rep["dual_ratio"]) <= 1 + 1e-7
+    assert rep["dual_ratio"][2] > 1 - 1e-6          # the noise component is non-zero
+    assert abs(rep["gap"]) < 1e-6
