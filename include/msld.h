@@ -72,7 +72,15 @@ typedef enum {
  *                 get an exact SVT: the LDS Jacobi tier, or the polar route for
  *                 blocks too large for LDS). Blocks up to 128 x 128 use a fused
  *                 one-kernel version. 0 selects the default (32); a negative value
- *                 disables the path. Results agree to rounding. */
+ *                 disables the path. Results agree to rounding.
+ *   kind[i]     : MSLD_KIND_BLOCK (0): block-wise nuclear norm over the partition;
+ *                 MSLD_KIND_NOISE (1): the noise scale of Sec. 2, whose reshape takes
+ *                 the whole matrix to an MN x 1 vector, so its norm is the Frobenius
+ *                 norm and its Z-step z = v max(1 - tau / ||v||_F, 0); requires
+ *                 block (M, N); no shift applies; the default lambda is eq:lambda on
+ *                 the MN x 1 block, sqrt(MN) + 1. Zero-initialised params mean all 0. */
+#define MSLD_KIND_BLOCK 0
+#define MSLD_KIND_NOISE 1
 typedef struct msld_params {
   int32_t M, N, L;
   int32_t block_m[MSLD_MAX_SCALES];
@@ -85,6 +93,7 @@ typedef struct msld_params {
   int32_t cycle_spin;
   int32_t lowrank_min;
   uint64_t shift_seed;
+  int32_t kind[MSLD_MAX_SCALES];
 } msld_params;
 
 /* Outcome of one msld_solve. primal_resid is r_k of the last iteration run
@@ -262,7 +271,7 @@ void msld_server_free(msld_server *sv);
  * 1 = register tier (blocks up to 8 x 8), 2 = LDS tier, 3 = HBM panel tier,
  * 4 = certified low-rank path on batched GEMMs (failures: LDS tier or polar route),
  * 5 = fused certified low-rank kernel for blocks up to 64 x 128 (failures: LDS
- * tier). Returns -1 for an invalid index. */
+ * tier), 6 = noise scale (Frobenius prox). Returns -1 for an invalid index. */
 int32_t msld_scale_tier(const msld_solver *s, int32_t scale);
 
 #ifdef __cplusplus

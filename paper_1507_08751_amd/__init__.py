@@ -12,10 +12,11 @@ import math
 import os
 
 __all__ = ["load", "Solver", "Batch", "Server", "solve", "bsvt", "cycle_shift", "default_lambda",
-           "MAX_SCALES", "TIERS", "MsldError"]
+           "MAX_SCALES", "TIERS", "MsldError", "KIND_BLOCK", "KIND_NOISE"]
 
 MAX_SCALES = 16
-TIERS = {0: "1x1", 1: "register", 2: "lds", 3: "panel", 4: "lowrank", 5: "lowrank_small"}
+TIERS = {0: "1x1", 1: "register", 2: "lds", 3: "panel", 4: "lowrank", 5: "lowrank_small",
+         6: "noise"}
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmsld.so")
 
 _lib = None
@@ -36,7 +37,10 @@ class Params(ctypes.Structure):
                 ("rho", ctypes.c_float), ("max_iters", ctypes.c_int32),
                 ("tol", ctypes.c_float), ("check_every", ctypes.c_int32),
                 ("cycle_spin", ctypes.c_int32), ("lowrank_min", ctypes.c_int32),
-                ("shift_seed", ctypes.c_uint64)]
+                ("shift_seed", ctypes.c_uint64), ("kind", ctypes.c_int32 * MAX_SCALES)]
+
+KIND_BLOCK = 0
+KIND_NOISE = 1
 
 
 class Result(ctypes.Structure):
@@ -143,7 +147,7 @@ def cycle_shift(seed, k, i, m, n):
 
 
 def make_params(M, N, ladder, lam=None, rho=1.0, iters=100, tol=0.0, check_every=1,
-                cycle_spin=False, seed=0, lowrank_min=0) -> Params:
+                cycle_spin=False, seed=0, lowrank_min=0, kinds=None) -> Params:
     if len(ladder) < 1 or len(ladder) > MAX_SCALES:
         raise ValueError("ladder must have 1..16 scales")
     p = Params()
@@ -158,6 +162,8 @@ def make_params(M, N, ladder, lam=None, rho=1.0, iters=100, tol=0.0, check_every
     p.cycle_spin = 1 if cycle_spin else 0
     p.shift_seed = int(seed) & ((1 << 64) - 1)
     p.lowrank_min = int(lowrank_min)
+    for i in range(len(ladder)):
+        p.kind[i] = int(kinds[i]) if kinds is not None else KIND_BLOCK
     return p
 
 
@@ -175,7 +181,7 @@ class Solver:
     """One planned decomposition problem (msld_create). Reusable across solves."""
 
     def __init__(self, M, N, ladder, lam=None, rho=1.0, iters=100, tol=0.0, check_every=1,
-                 cycle_spin=False, seed=0, device=None, lowrank_min=0):
+                 cycle_spin=False, seed=0, device=None, lowrank_min=0, kinds=None):
         import torch
         self._torch = torch
         lib = load()
@@ -185,7 +191,7 @@ class Solver:
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
             else torch.device(device)
         self.params = make_params(M, N, ladder, lam, rho, iters, tol, check_every,
-                                  cycle_spin, seed, lowrank_min)
+                                  cycle_spin, seed, lowrank_min, kinds)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             st = lib.msld_create(ctypes.byref(self.params), _stream_ptr(torch, self.device),

@@ -56,6 +56,8 @@ msld_status validate_params(const msld_params* p) {
     const int m = p->block_m[i], n = p->block_n[i];
     if (m < 1 || n < 1 || p->M % m || p->N % n) return MSLD_EINVAL;
     if (!std::isfinite(p->lambda[i])) return MSLD_EINVAL;
+    if (p->kind[i] != MSLD_KIND_BLOCK && p->kind[i] != MSLD_KIND_NOISE) return MSLD_EINVAL;
+    if (p->kind[i] == MSLD_KIND_NOISE && (m != p->M || n != p->N)) return MSLD_EINVAL;
   }
   return MSLD_OK;
 }
@@ -69,7 +71,7 @@ bool same_class(const msld_params& a, const msld_params& b) {
     return false;
   for (int i = 0; i < a.L; ++i)
     if (a.block_m[i] != b.block_m[i] || a.block_n[i] != b.block_n[i] ||
-        a.lambda[i] != b.lambda[i])
+        a.lambda[i] != b.lambda[i] || a.kind[i] != b.kind[i])
       return false;
   return true;
 }
@@ -108,9 +110,19 @@ msld_status make_plan(const msld_params* p, int ninst, Plan* pl) {
     g.trans = m < n ? 1 : 0;
     g.mb = m < n ? n : m;
     g.nb = m < n ? m : n;
-    const double lam = p->lambda[i] > 0.f ? (double)p->lambda[i] : lambda_default(IM, N, m, n);
+    const bool noise = p->kind[i] == MSLD_KIND_NOISE;
+    const double lam = p->lambda[i] > 0.f ? (double)p->lambda[i]
+                       : noise ? lambda_default(IM, N, IM * N, 1)   // the MN x 1 block
+                               : lambda_default(IM, N, m, n);
     pl->tau_default[i] = (float)(lam / (double)p->rho);
     const int nblk = g.P * g.Q;
+    if (noise) {
+      // Frobenius prox: per-instance partial sums of squares and gains
+      pl->tier[i] = TIER_FRO;
+      pl->off_stats[i] = take(8 * 8);
+      pl->off_lr[i] = take(8 * (size_t)kFroParts * ninst + 4 * (size_t)ninst);
+      continue;
+    }
     // certified low-rank paths: fused per-block kernel up to 64 x 128 (falls back to
     // the LDS tier), batched-GEMM path beyond (falls back to the polar route)
     const int lr_min = p->lowrank_min == 0 ? 32 : p->lowrank_min;
@@ -318,6 +330,11 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
     std::memset(&w, 0, sizeof(w));
     w.stats = reinterpret_cast<unsigned long long*>(s->arena + pl.off_stats[i]);
     w.hostInts = s->host_ints + 2 * i;
+    if (pl.tier[i] == TIER_FRO) {
+      w.froPart = reinterpret_cast<double*>(s->arena + pl.off_lr[i]);
+      w.froGain = reinterpret_cast<float*>(w.froPart + (size_t)kFroParts * ninst);
+      continue;
+    }
     if (pl.tier[i] != TIER_1X1) {
       w.live_count = reinterpret_cast<int*>(s->arena + pl.off_count[i]);
       w.live_list = reinterpret_cast<int*>(s->arena + pl.off_list[i]);
@@ -388,7 +405,7 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
     a.plane = plane_elems(s);
     size_t lds = 0;
     for (int i = 0; i < p->L; ++i) {
-      if (pl.tier[i] == TIER_1X1) continue;
+      if (pl.tier[i] == TIER_1X1 || pl.tier[i] == TIER_FRO) continue;
       StreamScale& d = a.s[a.n];
       d.g = pl.geom[i];
       d.sp = pl.sp[i];

@@ -985,6 +985,87 @@ size_t stream_lds_bytes(int m, const StreamPlan& sp) {
     }                                                                 \
   } while (0)
 
+// ------------------------------------------------------------ noise scale
+// The noise scale of Sec. 2 reshapes the whole (instance) matrix to an MN x 1 vector;
+// the SVT of eq:svt on it is z = v max(1 - tau / ||v||_F, 0) with v = Z + R. Three
+// steps: per-instance partial sums of squares (fixed order), the gain, the update with
+// the fused dual D' = 2 Z' - V.
+__global__ void __launch_bounds__(256) k_fro_norm(const float* __restrict__ Zin,
+                                                  const float* __restrict__ R,
+                                                  int64_t inst_elems,
+                                                  const int* __restrict__ iactive,
+                                                  double* __restrict__ part) {
+  __shared__ double red[256];
+  const int z = blockIdx.y;
+  double acc = 0.0;
+  if (!iactive || iactive[z]) {
+    const int64_t base = (int64_t)z * inst_elems;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < inst_elems;
+         e += (int64_t)gridDim.x * blockDim.x) {
+      const float v = Zin[base + e] + (R ? R[base + e] : 0.f);
+      acc += (double)v * (double)v;
+    }
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(int64_t)z * gridDim.x + blockIdx.x] = red[0];
+}
+
+__global__ void k_fro_gain(const double* __restrict__ part, int parts, int ninst, float tau,
+                           const int* __restrict__ iactive, float* __restrict__ gain,
+                           unsigned long long* __restrict__ stats) {
+  const int z = blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= ninst) return;
+  if (iactive && !iactive[z]) return;
+  double ss = 0.0;
+  for (int b = 0; b < parts; ++b) ss += part[(int64_t)z * parts + b];
+  const double nv = sqrt(ss);
+  const float g = nv > (double)tau ? (float)(1.0 - (double)tau / nv) : 0.f;
+  gain[z] = g;
+  atomicAdd(&stats[0], 1ull);
+  if (g > 0.f) atomicAdd(&stats[2], 1ull);
+}
+
+__global__ void __launch_bounds__(256) k_fro_apply(const float* __restrict__ Zin,
+                                                   const float* __restrict__ R,
+                                                   float* __restrict__ Zout,
+                                                   float* __restrict__ Dout, int64_t inst_elems,
+                                                   int ninst, const int* __restrict__ iactive,
+                                                   const float* __restrict__ gain) {
+  const int64_t total = inst_elems * ninst;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int z = (int)(e / inst_elems);
+    if (iactive && !iactive[z]) continue;
+    const float v = Zin[e] + (R ? R[e] : 0.f);
+    const float zz = gain[z] * v;
+    Zout[e] = zz;
+    Dout[e] = 2.f * zz - v;
+  }
+}
+
+static hipError_t launch_noise(const ScaleGeom& g, ScaleWork& w, const float* Zin,
+                               const float* R, float* Zout, float* Dout, float tau,
+                               const ShiftSpec& sh, hipStream_t st) {
+  const int64_t inst = (int64_t)g.IM * g.N;
+  hipLaunchKernelGGL(k_fro_norm, dim3(kFroParts, g.NI), dim3(256), 0, st, Zin, R, inst,
+                     sh.iactive, w.froPart);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fro_gain, dim3((g.NI + 255) / 256), dim3(256), 0, st, w.froPart,
+                     kFroParts, g.NI, tau, sh.iactive, w.froGain, w.stats);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  int64_t blocks = (inst * g.NI + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(k_fro_apply, dim3((unsigned)blocks), dim3(256), 0, st, Zin, R, Zout, Dout,
+                     inst, g.NI, sh.iactive, w.froGain);
+  return hipGetLastError();
+}
+
 float stream_tau2lim(const ScaleGeom& g, float tau) {
   // skip only if the bound is below tau^2 by more than its rounding error
   const double tl = (double)tau * (double)tau *
@@ -998,6 +1079,12 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
                         int num_cus, hipStream_t st, hipEvent_t* ev, int* round_launches,
                         bool stream_done) {
   hipError_t e;
+  if (tier == TIER_FRO) {
+    MSLD_EV(0); MSLD_EV(1); MSLD_EV(2);
+    if ((e = launch_noise(g, w, Zin, R, Zout, Dout, tau, sh, st)) != hipSuccess) return e;
+    MSLD_EV(3); MSLD_EV(4);
+    return hipSuccess;
+  }
   const float tau2lim = stream_tau2lim(g, tau);
   const int nblk = g.P * g.Q;
   // stream pass: speculative zero-output write + bound + live list (unless the caller

@@ -61,7 +61,9 @@ __device__ inline bool inst_active(const ShiftSpec& s, int z) {
 }
 
 // ------------------------------------------------------------------ plans
-enum Tier { TIER_1X1 = 0, TIER_REG = 1, TIER_LDS = 2, TIER_PANEL = 3, TIER_LRS = 5 };
+enum Tier { TIER_1X1 = 0, TIER_REG = 1, TIER_LDS = 2, TIER_PANEL = 3, TIER_LRS = 5,
+            TIER_FRO = 6 };
+constexpr int kFroParts = 512;   // partial sums per instance of the noise scale's norm
 
 // Geometry of one scale's partition. M counts the rows of all stacked instances
 // (NI instances of IM rows each, IM = M for a single instance); P = NI * PI block rows.
@@ -91,6 +93,8 @@ __device__ inline int gcol(const ScaleGeom& g, int q, int j, int sc) {
 
 // Per-scale device buffers and counters.
 struct ScaleWork {
+  double* froPart;      // noise scale: [ninst][kFroParts] partial sums of squares
+  float* froGain;       // noise scale: [ninst] gains max(1 - tau / ||v||_F, 0)
   int* live_count;      // [1] blocks that passed the bound test this pass
   int* live_list;       // [P*Q] block ids
   float* rowpart;       // [P*Q*spb*m] partial row sums (strips narrower than a block)

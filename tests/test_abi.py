@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layout_matches_header():
     # int32 M,N,L; 16+16 int32; 16 float; rho,max_iters,tol,check_every,cycle_spin,lowrank_min; u64
-    assert ctypes.sizeof(msld.Params) == 4 * 3 + 4 * 48 + 4 * 6 + 8 + 4  # +4 alignment pad
+    assert ctypes.sizeof(msld.Params) == 4 * 3 + 4 * 48 + 4 * 6 + 8 + 4 + 4 * 16  # +4 pad
     assert msld.Params.shift_seed.offset % 8 == 0
     assert ctypes.sizeof(msld.Result) == 4 + 4 + 8 + 8 * 8 * 16
 
@@ -68,6 +68,8 @@ def test_host_default_lambda_matches_oracle():
     dict(M=64, N=64, ladder=[(4, 4)], iters=0),
     dict(M=64, N=64, ladder=[(4, 4)], tol=-1.0),
     dict(M=64, N=64, ladder=[(4, 4)], check_every=0),
+    dict(M=64, N=64, ladder=[(4, 4)], kinds=[1]),          # noise scale needs the full block
+    dict(M=64, N=64, ladder=[(64, 64)], kinds=[2]),         # unknown kind
 ])
 def test_invalid_params_rejected_on_host(bad):
     bad = dict(bad)
@@ -86,3 +88,11 @@ def test_workspace_accounts_for_state_planes():
     lad = [(1, 1), (4, 4), (16, 16), (64, 64), (512, 512)]
     wb = msld.workspace_bytes(M, N, lad)
     assert wb >= 4 * M * N * (1 + 2 * len(lad))
+
+
+def test_noise_scale_plans():
+    """A ladder with the noise scale (whole-matrix MN x 1 reshape) is a valid plan (its
+    default lambda is checked against the oracle by the GPU parity test)."""
+    M, N = 64, 48
+    assert msld.workspace_bytes(M, N, [(1, 1), (M, N)], kinds=[0, 1]) > 0
+    assert msld.workspace_bytes(M, N, [(1, 1), (M, N), (M, N)], kinds=[0, 0, 1]) > 0

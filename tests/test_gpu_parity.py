@@ -365,3 +365,47 @@ def test_tolerance_stop(lib):
           f"{ref['iters']} resid {ref['resid']:.3e}", flush=True)
     assert info["iters"] % 10 == 0 and info["primal_resid"] <= 1e-4
     assert abs(info["iters"] - ref["iters"]) <= 20
+
+
+# ------------------------------------------------------------------ noise scale
+def test_noise_scale_bsvt_parity(lib):
+    """One Z-step of the noise scale (SVT of the MN x 1 reshape) against the oracle,
+    on both sides of the threshold."""
+    M, N = 96, 160
+    rng = np.random.default_rng(21)
+    V = rng.standard_normal((M, N)).astype(np.float32)
+    solver = lib.Solver(M, N, [(1, 1), (M, N)], iters=1, kinds=[0, 1])
+    assert lib.TIERS[solver.tier(1)] == "noise"
+    nv = float(np.linalg.norm(V.astype(np.float64)))
+    for tau in (0.37 * nv, 1.5 * nv):
+        ref = O.noise_svt(V.astype(np.float64), tau)
+        Z = solver.bsvt(1, torch.from_numpy(V).cuda(), tau, (0, 0))
+        torch.cuda.synchronize()
+        err = rel_err(Z.cpu().numpy(), ref, nv)
+        print(f"noise bsvt tau={tau:.2f} ||V||={nv:.2f}: err {err:.2e}", flush=True)
+        assert err <= 1e-4
+    solver.close()
+
+
+@pytest.mark.parametrize("cycle_spin", [False, True])
+def test_admm_with_noise_scale_parity(lib, cycle_spin):
+    """ADMM on eq:noisy (sparse + blocks + full + noise scale, default lambdas) after a
+    fixed count, per component against the oracle (1e-3)."""
+    M = N = 128
+    ladder = [(1, 1), (8, 8), (32, 32), (M, N), (M, N)]
+    kinds = [0, 0, 0, 0, 1]
+    inst = make_instance(M, N, ladder[:4], 0.03, noise=0.05, seed=4, keep_components=False)
+    iters = 80
+    ref = O.admm(inst.Y.astype(np.float64), ladder, rho=1.0, iters=iters,
+                 cycle_spin=cycle_spin, seed=5, kinds=kinds)
+    solver = lib.Solver(M, N, ladder, rho=1.0, iters=iters, cycle_spin=cycle_spin, seed=5,
+                        kinds=kinds)
+    Z, info = solver.solve(torch.from_numpy(inst.Y).cuda())
+    torch.cuda.synchronize()
+    Zg = Z.cpu().numpy()
+    errs = [rel_err(Zg[i], ref["Z"][i], np.linalg.norm(inst.Y)) for i in range(len(ladder))]
+    print(f"noise admm cs={cycle_spin}: errs {['%.1e' % e for e in errs]} "
+          f"noise norm {np.linalg.norm(ref['Z'][4]):.3f}", flush=True)
+    assert max(errs) <= 1e-3
+    assert np.linalg.norm(ref["Z"][4]) > 0          # the noise component is active
+    solver.close()
