@@ -27,6 +27,10 @@ Parity status per function (what independent facts pin it; see tests/):
   scale_lambda        the ball, the subgradient condition outside), the lambda
                       special case of the MN x 1 block, and the noisy program's
                       KKT conditions / duality gap through admm(kinds=...).
+  admm(mask=...)      pinned: a full mask is the plain iteration; one masked
+                      full-size scale recovers a low-rank matrix from 60% of its
+                      entries (nuclear-norm completion); KKT with the dual
+                      certificate supported on the observed entries.
 """
 from .msld_oracle import (  # noqa: F401
     MASK64, splitmix64_mix, cycle_shift, default_lambda, shift, unshift, svt,

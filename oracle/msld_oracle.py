@@ -121,7 +121,7 @@ def scale_lambda(M: int, N: int, m: int, n: int, kind: int = KIND_BLOCK) -> floa
 
 # --------------------------------------------------------------------------- ADMM
 def admm(Y, ladder, lam=None, rho=1.0, iters=100, cycle_spin=False, seed=0,
-         tol=0.0, check_every=1, history=False, kinds=None):
+         tol=0.0, check_every=1, history=False, kinds=None, mask=None):
     """ADMM of Sec. 7 (eq:admm) for eq:cvx, with the random cycle spinning of Sec. 9.
 
     Per iteration k, in the paper's order:
@@ -130,6 +130,9 @@ def admm(Y, ladder, lam=None, rho=1.0, iters=100, cycle_spin=False, seed=0,
         U_i <- U_i - (Z_i - X_i)
     kinds[i] == KIND_NOISE makes scale i the noise scale of Sec. 2 (its Z-step is the
     SVT of the MN x 1 reshape, which no shift changes; its block size must be M x N).
+    mask (M x N, true = observed) applies the data consistency of the collaborative
+    filtering experiment of Sec. 10: the X-update above only on observed entries,
+    X_i = Z_i - U_i on the others; the residual is then relative to ||P_obs(Y)||_F.
     Readings where the paper is silent: Z_i = U_i = 0 at start; the returned
     components are Z_i (exactly block-low-rank); primal residual
     r_k = sqrt(sum_i ||X_i - Z_i||_F^2) / ||Y||_F with the new Z_i; when tol > 0 the
@@ -146,6 +149,9 @@ def admm(Y, ladder, lam=None, rho=1.0, iters=100, cycle_spin=False, seed=0,
     Z = np.zeros((L, M, N))
     U = np.zeros((L, M, N))
     X = np.zeros((L, M, N))
+    obs = None if mask is None else np.asarray(mask, dtype=bool)
+    if obs is not None:
+        Y = np.where(obs, Y, 0.0)          # unobserved entries carry no data
     ny = np.linalg.norm(Y)
     ny = ny if ny > 0 else 1.0
     hist = []
@@ -154,7 +160,10 @@ def admm(Y, ladder, lam=None, rho=1.0, iters=100, cycle_spin=False, seed=0,
     for k in range(int(iters)):
         S = (Z - U).sum(axis=0)
         for i in range(L):
-            X[i] = (Z[i] - U[i]) + (Y - S) / L
+            if obs is None:
+                X[i] = (Z[i] - U[i]) + (Y - S) / L
+            else:
+                X[i] = np.where(obs, (Z[i] - U[i]) + (Y - S) / L, Z[i] - U[i])
         for i, (m, n) in enumerate(ladder):
             if kinds[i] == KIND_NOISE:
                 Z[i] = noise_svt(X[i] + U[i], lam[i] / rho)
@@ -201,24 +210,28 @@ def scale_dual_norm(A, m, n, kind=KIND_BLOCK) -> float:
     return block_dual_norm(A, m, n)
 
 
-def kkt_report(Y, ladder, lam, rho, Z, U, kinds=None):
+def kkt_report(Y, ladder, lam, rho, Z, U, kinds=None, mask=None):
     """Optimality diagnostics for eq:cvx from an ADMM state (no cycle spinning).
 
     Dual certificate: at a fixed point all U_i coincide and Q = rho * mean_i U_i
     satisfies Q in lambda_i * subdifferential of ||Z_i||_(i) (the condition of
     Thm A.3 with the dual norm of Sec. 3). For any Q with ||Q||*_(i) <= lambda_i,
     <Q, Y> lower-bounds the optimum (weak duality), so Q is scaled into that set.
-    The primal value is taken at the feasible point Z_i + (Y - sum_j Z_j)/L.
+    The primal value is taken at the feasible point Z_i + (Y - sum_j Z_j)/L. With a
+    mask the constraint holds on observed entries only: Q must vanish elsewhere
+    ("off_support") and the feasible point corrects observed entries only.
     """
     Y = np.asarray(Y, dtype=np.float64)
     L = len(ladder)
     kinds = [KIND_BLOCK] * L if kinds is None else list(kinds)
+    obs = np.ones(Y.shape, dtype=bool) if mask is None else np.asarray(mask, dtype=bool)
+    Y = np.where(obs, Y, 0.0)
     Ubar = np.mean(U, axis=0)
     Q = rho * Ubar
     ratios = [scale_dual_norm(Q, m, n, kinds[i]) / lam[i] for i, (m, n) in enumerate(ladder)]
     Qs = Q / max(1.0, max(ratios))
     dual = float((Qs * Y).sum())
-    Zf = Z + (Y - Z.sum(axis=0)) / L
+    Zf = Z + np.where(obs, Y - Z.sum(axis=0), 0.0) / L
     primal = float(sum(lam[i] * scale_norm(Zf[i], m, n, kinds[i])
                        for i, (m, n) in enumerate(ladder)))
     spread = float(max(np.linalg.norm(U[i] - Ubar) for i in range(L)) /
@@ -226,8 +239,9 @@ def kkt_report(Y, ladder, lam, rho, Z, U, kinds=None):
     return {"primal": primal, "dual": dual,
             "gap": (primal - dual) / max(abs(primal), 1e-300),
             "dual_ratio": ratios, "u_spread": spread,
-            "consensus": float(np.linalg.norm(Y - Z.sum(axis=0)) /
-                               max(np.linalg.norm(Y), 1e-300))}
+            "consensus": float(np.linalg.norm(np.where(obs, Y - Z.sum(axis=0), 0.0)) /
+                               max(np.linalg.norm(Y), 1e-300)),
+            "off_support": float(np.abs(np.where(obs, 0.0, Q)).max(initial=0.0))}
 
 
 def skip_bound_sq(B) -> float:
