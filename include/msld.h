@@ -150,7 +150,18 @@ msld_status msld_step(msld_solver *s, const float *d_Y, int64_t ldY, float *d_Z,
  * last msld_reset (primal_resid is -1: use msld_step to obtain it). Synchronises. */
 msld_status msld_stats(msld_solver *s, msld_result *info);
 
-/* Kernel timing with HIP events on the streams that run each part (the consensus on
+/* Masked data consistency (the collaborative-filtering variant of Sec. 10): with a
+ * mask set, the X-update of eq:admm applies its consensus correction only on observed
+ * entries and keeps X_i = Z_i - U_i on the others, so the constraint sum_i X_i = Y
+ * holds on the observed entries only; unobserved entries of Y are never read into
+ * the iteration and the residual is relative to ||P_observed(Y)||_F. d_mask is an
+ * M x N row-major byte array on the device (nonzero = observed), leading dimension
+ * ldmask >= N; it is caller-owned and must stay valid for every msld_solve /
+ * msld_reset / msld_step that follows. NULL clears the mask. Single solvers only
+ * (MSLD_EINVAL for batch / server classes). */
+msld_status msld_set_mask(msld_solver *s, const uint8_t *d_mask, int64_t ldmask);
+
+/* Kernel timing with HIP events/* Kernel timing with HIP events on the streams that run each part (the consensus on
  * the handle's stream, each scale on its own stream). msld_profile_begin(s, n)
  * creates events for the next n iterations (each iteration records them as it is
  * enqueued; later iterations are not recorded). msld_profile_end synchronises and

@@ -65,6 +65,7 @@ EXPORTS = {
                                  ctypes.c_void_p, ctypes.c_float, ctypes.c_int32,
                                  ctypes.c_int32]),
     "msld_free": (None, [ctypes.c_void_p]),
+    "msld_set_mask": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
     "msld_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Params)]),
     "msld_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "msld_default_lambda": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -278,6 +279,20 @@ class Solver:
                 "fail_bound": list(res.fail_bound)[:self.L],
                 "polar": list(res.polar)[:self.L],
                 "polar_steps": list(res.polar_steps)[:self.L]}
+
+    def set_mask(self, mask):
+        """Observed-entry mask (M x N bool / uint8 device tensor, kept alive by the
+        solver) for the masked data consistency of Sec. 10; None clears it."""
+        torch = self._torch
+        if mask is None:
+            self._mask = None
+            _check(self._lib.msld_set_mask(self._h, None, 0), "msld_set_mask")
+            return
+        if tuple(mask.shape) != (self.M, self.N) or not mask.is_cuda:
+            raise ValueError("mask must be an (M, N) device tensor")
+        m = mask.to(torch.uint8).contiguous()
+        self._mask = m
+        _check(self._lib.msld_set_mask(self._h, m.data_ptr(), self.N), "msld_set_mask")
 
     def profile_begin(self, max_iters):
         _check(self._lib.msld_profile_begin(self._h, int(max_iters)), "msld_profile_begin")

@@ -129,7 +129,9 @@ msld_status make_plan(const msld_params* p, int ninst, Plan* pl) {
     int sNB, sMB, sP;
     const bool lrs = lr_min > 0 && g.nb >= lr_min && lr_small_shape(g.mb, g.nb, &sNB, &sMB, &sP) &&
                      lds_fits(g.mb, g.nb) && lr_small_lds_bytes(sNB, sMB, sP) <= kLdsTierMax;
-    const bool lr = !lrs && lr_min > 0 && g.nb >= lr_min && g.nb >= 4 * kLRP;
+    // (narrower blocks take it only when the alternative would be the HBM panel tier)
+    const bool lr = !lrs && lr_min > 0 && g.nb >= lr_min &&
+                    (g.nb >= 4 * kLRP || (g.nb >= 2 * kLRP && !lds_fits(g.mb, g.nb)));
     int tier;
     if (m == 1 && n == 1) tier = TIER_1X1;
     else if (m == n && (m == 2 || m == 4 || m == 8)) tier = TIER_REG;
@@ -488,7 +490,7 @@ msld_status iterate_once(msld_solver* s, const float* d_Y, int64_t ldY, float* d
     MSLD_TRY(s, hipEventRecord(ev[0], s->st));
   }
   MSLD_TRY(s, launch_consensus(d_Y, ldY, Dc, Dn, d_Z, R, M, N, L, scales1, taus1, n1, IM,
-                               stacked ? s->d_active : nullptr, s->st));
+                               stacked ? s->d_active : nullptr, s->mask, s->ldmask, s->st));
   if (ev) MSLD_TRY(s, hipEventRecord(ev[1], s->st));
   {
     // stream pass of every decomposed scale in one launch
@@ -579,8 +581,8 @@ msld_status iterate_once(msld_solver* s, const float* d_Y, int64_t ldY, float* d
 // ||Y_z||^2 of every instance into dres[ninst + z].
 msld_status launch_ynorms(msld_solver* s, const float* d_Y, int64_t ldY) {
   double* part = reinterpret_cast<double*>(s->arena + s->plan.off_part);
-  MSLD_TRY(s, launch_sumsq(d_Y, ldY, s->p.M, s->p.N, s->ninst, part, s->plan.resid_parts,
-                           dev_res(s) + s->ninst, s->st));
+  MSLD_TRY(s, launch_sumsq(d_Y, ldY, s->p.M, s->p.N, s->ninst, s->mask, s->ldmask, part,
+                           s->plan.resid_parts, dev_res(s) + s->ninst, s->st));
   return MSLD_OK;
 }
 
@@ -783,6 +785,15 @@ msld_status msld_profile_end(msld_solver* s, double* ms, int64_t* round_launches
   return result;
 }
 
+msld_status msld_set_mask(msld_solver* s, const uint8_t* d_mask, int64_t ldmask) {
+  if (!s) return MSLD_EINVAL;
+  if (s->ninst != 1) return MSLD_EINVAL;
+  if (d_mask && ldmask < s->p.N) return MSLD_EINVAL;
+  s->mask = d_mask;
+  s->ldmask = d_mask ? ldmask : 0;
+  return MSLD_OK;
+}
+
 msld_status msld_bsvt(msld_solver* s, int32_t scale, const float* d_V, float* d_Z, float tau,
                       int32_t sr, int32_t sc) {
   if (!s || !d_V || !d_Z) return MSLD_EINVAL;
@@ -809,7 +820,7 @@ msld_status msld_bsvt(msld_solver* s, int32_t scale, const float* d_V, float* d_
     MSLD_TRY(s, launch_fill(Dws, 0.f, MN, s->st));
     MSLD_TRY(s, launch_fill(Zp, 0.f, MN, s->st));
     MSLD_TRY(s, launch_consensus(d_V, g.N, Dws, Dws, Zp, plane_R(s), g.M, g.N, 1, &idx0, &t0, 1,
-                                 g.M, nullptr, s->st));
+                                 g.M, nullptr, nullptr, 0, s->st));
     MSLD_TRY(s, hipMemcpyAsync(d_Z, Zp, MN * 4, hipMemcpyDeviceToDevice, s->st));
     return MSLD_OK;
   }

@@ -50,7 +50,8 @@ __device__ __forceinline__ float soft(float v, float t) {
 __global__ void __launch_bounds__(256) k_consensus_v4(
     const float* __restrict__ Y, int64_t ldY, const float* __restrict__ Dcur,
     float* __restrict__ Dnext, float* __restrict__ Z, float* __restrict__ R, int M, int N,
-    int L, float invL, OneByOne ob, int IM, const int* __restrict__ iactive) {
+    int L, float invL, OneByOne ob, int IM, const int* __restrict__ iactive,
+    const uint8_t* __restrict__ mask, int64_t ldmask) {
   const int64_t MN = (int64_t)M * N;
   const int total4 = (int)(MN >> 2);
   const int stride = gridDim.x * blockDim.x;
@@ -68,6 +69,13 @@ __global__ void __launch_bounds__(256) k_consensus_v4(
     float4 rr;
     rr.x = (y.x - s.x) * invL; rr.y = (y.y - s.y) * invL;
     rr.z = (y.z - s.z) * invL; rr.w = (y.w - s.w) * invL;
+    if (mask) {   // masked data consistency: no correction on unobserved entries
+      const uint8_t* mk = mask + (int64_t)r * ldmask + c;
+      if (!mk[0]) rr.x = 0.f;
+      if (!mk[1]) rr.y = 0.f;
+      if (!mk[2]) rr.z = 0.f;
+      if (!mk[3]) rr.w = 0.f;
+    }
     for (int t = 0; t < ob.n; ++t) {
       const int j = ob.idx[t];
       const float tau = ob.tau[t];
@@ -88,7 +96,8 @@ __global__ void __launch_bounds__(256) k_consensus_v4(
 __global__ void __launch_bounds__(256) k_consensus_s(
     const float* __restrict__ Y, int64_t ldY, const float* __restrict__ Dcur,
     float* __restrict__ Dnext, float* __restrict__ Z, float* __restrict__ R, int M, int N,
-    int L, float invL, OneByOne ob, int IM, const int* __restrict__ iactive) {
+    int L, float invL, OneByOne ob, int IM, const int* __restrict__ iactive,
+    const uint8_t* __restrict__ mask, int64_t ldmask) {
   const int64_t MN = (int64_t)M * N;
   const int total = (int)MN;
   const int stride = gridDim.x * blockDim.x;
@@ -98,7 +107,8 @@ __global__ void __launch_bounds__(256) k_consensus_s(
     if (iactive && !iactive[r / IM]) continue;
     float s = 0.f;
     for (int j = 0; j < L; ++j) s += Dcur[j * MN + e];
-    const float rr = (Y[(int64_t)r * ldY + c] - s) * invL;
+    float rr = (Y[(int64_t)r * ldY + c] - s) * invL;
+    if (mask && !mask[(int64_t)r * ldmask + c]) rr = 0.f;   // unobserved entry
     for (int t = 0; t < ob.n; ++t) {
       const int j = ob.idx[t];
       const float v = Z[j * MN + e] + rr;
@@ -113,7 +123,7 @@ __global__ void __launch_bounds__(256) k_consensus_s(
 hipError_t launch_consensus(const float* Y, int64_t ldY, const float* Dcur, float* Dnext,
                             float* Z, float* R, int M, int N, int L, const int* scales1,
                             const float* taus1, int n1, int IM, const int* iactive,
-                            hipStream_t st) {
+                            const uint8_t* mask, int64_t ldmask, hipStream_t st) {
   OneByOne ob;
   ob.n = n1;
   for (int t = 0; t < 16; ++t) {
@@ -130,10 +140,10 @@ hipError_t launch_consensus(const float* Y, int64_t ldY, const float* Dcur, floa
   if (blocks < 1) blocks = 1;
   if (vec)
     hipLaunchKernelGGL(k_consensus_v4, dim3((unsigned)blocks), dim3(256), 0, st, Y, ldY,
-                       Dcur, Dnext, Z, R, M, N, L, invL, ob, IM, iactive);
+                       Dcur, Dnext, Z, R, M, N, L, invL, ob, IM, iactive, mask, ldmask);
   else
     hipLaunchKernelGGL(k_consensus_s, dim3((unsigned)blocks), dim3(256), 0, st, Y, ldY,
-                       Dcur, Dnext, Z, R, M, N, L, invL, ob, IM, iactive);
+                       Dcur, Dnext, Z, R, M, N, L, invL, ob, IM, iactive, mask, ldmask);
   return hipGetLastError();
 }
 
@@ -1323,7 +1333,8 @@ __global__ void __launch_bounds__(256) k_resid(const float* __restrict__ Dold,
 }
 
 __global__ void __launch_bounds__(256) k_sumsq(const float* __restrict__ Y, int64_t ldY, int IM,
-                                               int N, double* __restrict__ partial) {
+                                               int N, const uint8_t* __restrict__ mask,
+                                               int64_t ldmask, double* __restrict__ partial) {
   __shared__ double red[256];
   const int z = blockIdx.y;
   double acc = 0.0;
@@ -1333,6 +1344,7 @@ __global__ void __launch_bounds__(256) k_sumsq(const float* __restrict__ Y, int6
     const int64_t r = e / N;
     const int64_t c = e - r * N;
     const float y = Y[((int64_t)z * IM + r) * ldY + c];
+    if (mask && !mask[((int64_t)z * IM + r) * ldmask + c]) continue;   // unobserved
     acc += (double)y * (double)y;
   }
   red[threadIdx.x] = acc;
@@ -1362,9 +1374,11 @@ hipError_t launch_resid(const float* Dold, const float* R, const float* Z, int M
   return hipGetLastError();
 }
 
-hipError_t launch_sumsq(const float* Y, int64_t ldY, int IM, int N, int NI, double* partial,
-                        int nparts, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_sumsq, dim3(nparts, NI), dim3(256), 0, st, Y, ldY, IM, N, partial);
+hipError_t launch_sumsq(const float* Y, int64_t ldY, int IM, int N, int NI, const uint8_t* mask,
+                        int64_t ldmask, double* partial, int nparts, double* out,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_sumsq, dim3(nparts, NI), dim3(256), 0, st, Y, ldY, IM, N, mask, ldmask,
+                     partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_final_sum, dim3((NI + 63) / 64), dim3(64), 0, st, partial, nparts, NI, out);

@@ -180,7 +180,7 @@ hipError_t launch_fill(float* p, float v, size_t count, hipStream_t st);
 hipError_t launch_consensus(const float* Y, int64_t ldY, const float* Dcur, float* Dnext,
                             float* Z, float* R, int M, int N, int L, const int* scales1,
                             const float* taus1, int n1, int IM, const int* iactive,
-                            hipStream_t st);
+                            const uint8_t* mask, int64_t ldmask, hipStream_t st);
 // ev (optional, 5 events): recorded before the scale pass, after the stream pass,
 // before the panel rounds, after the panel rounds and after the whole pass.
 hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, ScaleWork& w,
@@ -208,8 +208,9 @@ __global__ void k_zero_ints(int* p, int n);
 hipError_t launch_resid(const float* Dold, const float* R, const float* Z, int M, int N,
                         int L, int IM, int NI, double* partial, int nparts, double* out,
                         hipStream_t st);
-hipError_t launch_sumsq(const float* Y, int64_t ldY, int IM, int N, int NI, double* partial,
-                        int nparts, double* out, hipStream_t st);
+hipError_t launch_sumsq(const float* Y, int64_t ldY, int IM, int N, int NI, const uint8_t* mask,
+                        int64_t ldmask, double* partial, int nparts, double* out,
+                        hipStream_t st);
 hipError_t launch_device_shifts(uint64_t seed, int k0, int count, int L, const int* bm,
                                 const int* bn, int* out, hipStream_t st);
 

@@ -71,6 +71,8 @@ struct msld_solver {
   rocblas_handle blas[MSLD_MAX_SCALES];   // one per low-rank scale, bound to its stream
   msld::ScaleWork work[MSLD_MAX_SCALES];
   msld::StreamAll sall;   // the stream pass of all decomposed scales (one launch)
+  const uint8_t* mask;    // observed-entry mask (caller-owned, device) or null
+  int64_t ldmask;
   size_t sall_lds;
   int ninst;
   int k;              // next iteration (single instance; stacked instances use d_k)

@@ -152,6 +152,24 @@ def serving_trace(count, rate, seed=0, density=0.02, noise=0.01):
     return out
 
 
+def completion_instance(M=1682, N=943, groups=23, observed=0.063, seed=0, noise=0.3):
+    """Stand-in for a ratings matrix (items x users, users grouped along the columns):
+    a global rank-2 term, one rank-1 term per user group of N / groups columns, noise,
+    and a uniformly random set of observed entries (fraction `observed`).
+
+    Returns (Y float32 with unobserved entries set to 0, mask bool, truth float64)."""
+    if N % groups:
+        raise ValueError("groups must divide N")
+    rng = np.random.default_rng(seed)
+    T = rng.standard_normal((M, 2)) @ rng.standard_normal((2, N))
+    w = N // groups
+    for g in range(groups):
+        T[:, g * w:(g + 1) * w] += np.outer(rng.standard_normal(M), rng.standard_normal(w))
+    Y = T + noise * rng.standard_normal((M, N))
+    mask = rng.random((M, N)) < observed
+    return np.where(mask, Y, 0.0).astype(np.float32), mask, T
+
+
 def lcm_blocks(ladder):
     a, b = 1, 1
     for (m, n) in ladder:

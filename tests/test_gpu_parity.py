@@ -409,3 +409,70 @@ def test_admm_with_noise_scale_parity(lib, cycle_spin):
     assert max(errs) <= 1e-3
     assert np.linalg.norm(ref["Z"][4]) > 0          # the noise component is active
     solver.close()
+
+
+# ------------------------------------------------------------- masked consistency
+def test_full_mask_equals_no_mask(lib):
+    """A mask with every entry observed leaves the iteration unchanged (bitwise)."""
+    M, N = 128, 96
+    ladder = [(1, 1), (8, 8), (32, 32)]
+    inst = make_instance(M, N, ladder, 0.05, noise=0.01, seed=8, keep_components=False)
+    Y = torch.from_numpy(inst.Y).cuda()
+    a = lib.Solver(M, N, ladder, iters=30, cycle_spin=True, seed=3)
+    Za, _ = a.solve(Y)
+    b = lib.Solver(M, N, ladder, iters=30, cycle_spin=True, seed=3)
+    b.set_mask(torch.ones((M, N), dtype=torch.uint8, device="cuda"))
+    Zb, _ = b.solve(Y)
+    torch.cuda.synchronize()
+    assert torch.equal(Za, Zb)
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("cycle_spin", [False, True])
+def test_admm_masked_parity(lib, cycle_spin):
+    """Masked data consistency (Sec. 10): 70% of the entries observed, unobserved
+    entries of Y set to garbage that must not leak in; per component against the
+    oracle after a fixed count (1e-3)."""
+    M, N = 128, 96
+    ladder = [(1, 1), (8, 8), (32, 32), (M, N)]
+    inst = make_instance(M, N, ladder, 0.05, noise=0.01, seed=9, keep_components=False)
+    rng = np.random.default_rng(10)
+    mask = rng.random((M, N)) < 0.7
+    Yg = np.where(mask, inst.Y, 1e3).astype(np.float32)   # unobserved: garbage
+    iters = 60
+    ref = O.admm(inst.Y.astype(np.float64), ladder, rho=1.0, iters=iters,
+                 cycle_spin=cycle_spin, seed=4, mask=mask)
+    solver = lib.Solver(M, N, ladder, rho=1.0, iters=iters, cycle_spin=cycle_spin, seed=4)
+    solver.set_mask(torch.from_numpy(mask.astype(np.uint8)).cuda())
+    Z, info = solver.solve(torch.from_numpy(Yg).cuda())
+    torch.cuda.synchronize()
+    Zg = Z.cpu().numpy()
+    scale = np.linalg.norm(np.where(mask, inst.Y, 0.0))
+    errs = [rel_err(Zg[i], ref["Z"][i], scale) for i in range(len(ladder))]
+    print(f"masked admm cs={cycle_spin}: errs {['%.1e' % e for e in errs]} "
+          f"resid gpu {info['primal_resid']:.3e} oracle {ref['resid']:.3e}", flush=True)
+    assert max(errs) <= 1e-3
+    assert abs(info["primal_resid"] - ref["resid"]) <= 1e-2 * ref["resid"] + 1e-6
+    solver.close()
+
+
+def test_completion_workload_parity(lib):
+    """The collaborative-filtering stand-in at full size (1682 x 943, 93.7% missing,
+    scales 1682 x 41 and 1682 x 943): 6 iterations against the oracle (1e-3)."""
+    from synth import completion_instance
+    M, N = 1682, 943
+    ladder = [(M, 41), (M, N)]
+    Y, mask, _ = completion_instance(M, N, groups=23, observed=0.063, seed=0)
+    ref = O.admm(Y.astype(np.float64), ladder, rho=1.0, iters=6, mask=mask)
+    solver = lib.Solver(M, N, ladder, rho=1.0, iters=6)
+    print(f"completion tiers {[lib.TIERS[solver.tier(i)] for i in range(2)]}", flush=True)
+    solver.set_mask(torch.from_numpy(mask.astype(np.uint8)).cuda())
+    Z, info = solver.solve(torch.from_numpy(Y).cuda())
+    torch.cuda.synchronize()
+    Zg = Z.cpu().numpy()
+    scale = np.linalg.norm(Y)
+    errs = [rel_err(Zg[i], ref["Z"][i], scale) for i in range(2)]
+    print(f"completion 1682x943: errs {errs}", flush=True)
+    assert max(errs) <= 1e-3
+    solver.close()
