@@ -136,6 +136,65 @@ def completion_bench(args, iters=100, warm=5):
     print(json.dumps(out), flush=True)
 
 
+def spin_bench(args, iters=20, warm=2, spins=16):
+    """Averaged cycle spinning (Sec. 9): 1024 x 1024, scales {1, 4, 16, 64, 1024}
+    squared, default lambda, rho = 1, the Z-step of the 4, 16 and 64 scales averaged
+    over 16 shifts (every shift of the 4 x 4 scale, 16 hashed shifts of the others;
+    the whole-matrix scale has one distinct shift). Iterations per second over `iters`
+    after `warm`; the oracle times one iteration."""
+    import numpy as np
+    import torch
+    import paper_1507_08751_amd as msld
+    from synth import make_instance
+    M = N = 1024
+    ladder = [(1, 1), (4, 4), (16, 16), (64, 64), (M, N)]
+    inst = make_instance(M, N, ladder, 0.02, noise=0.01, seed=0, keep_components=False)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    Yd = torch.from_numpy(inst.Y).to(dev)
+    Z = torch.empty((len(ladder), M, N), dtype=torch.float32, device=dev)
+    solver = msld.Solver(M, N, ladder, rho=1.0, iters=iters, cycle_spin=True, seed=1,
+                         spin_count=spins, device=dev)
+    solver.reset(Z)
+    solver.step(Yd, Z, warm)
+    solver.reset(Z)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solver.step(Yd, Z, iters)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    tiers = [msld.TIERS[solver.tier(i)] for i in range(len(ladder))]
+    solver.close()
+    # the same ladder with one random shift per iteration, for the cost ratio
+    one = msld.Solver(M, N, ladder, rho=1.0, iters=iters, cycle_spin=True, seed=1, device=dev)
+    one.reset(Z)
+    one.step(Yd, Z, warm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    one.step(Yd, Z, iters)
+    torch.cuda.synchronize()
+    sec1 = time.perf_counter() - t0
+    one.close()
+    out = {"metric": f"averaged cycle spinning ADMM iters/s (1024 x 1024, {spins} shifts)",
+           "value": round(iters / sec, 3), "unit": "iters/s", "n_gpus": 1, "steps": iters,
+           "warmup": warm, "ms_per_step": round(1e3 * sec / iters, 3),
+           "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"1024x1024, scales 1,4,16,64,1024 squared, {spins} shifts "
+                                  "averaged per scale and iteration, rho=1",
+                      "tiers": tiers,
+                      "single_shift_iters_per_s": round(iters / sec1, 3)}}
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        t0 = time.perf_counter()
+        oracle.admm(inst.Y, ladder, rho=1.0, iters=1, cycle_spin=True, seed=1,
+                    spin_count=spins)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": 1 / dt, "unit": "iters/s", "cores": threads,
+                               "kind": "oracle", "sample": f"1 iteration, {dt:.2f} s"}
+    print(json.dumps(out), flush=True)
+
+
 def copy_calibration(nbytes=1 << 30, reps=3):
     """Plain device-to-device copies of nbytes: what FETCH_SIZE / WRITE_SIZE read for
     a kernel that moves a known number of bytes."""
@@ -312,7 +371,7 @@ def main():
     ap.add_argument("--size", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=4096)
-    ap.add_argument("--mode", choices=["iters", "serve", "batch", "copy", "completion"],
+    ap.add_argument("--mode", choices=["iters", "serve", "batch", "copy", "completion", "spin"],
                     default="iters",
                     help="copy: a plain device copy of known size, the calibration run for "
                          "the HBM byte counters")
@@ -337,6 +396,9 @@ def main():
         return
     if args.mode == "completion":
         completion_bench(args)
+        return
+    if args.mode == "spin":
+        spin_bench(args)
         return
 
     import numpy as np

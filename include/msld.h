@@ -78,7 +78,20 @@ typedef enum {
  *                 the whole matrix to an MN x 1 vector, so its norm is the Frobenius
  *                 norm and its Z-step z = v max(1 - tau / ||v||_F, 0); requires
  *                 block (M, N); no shift applies; the default lambda is eq:lambda on
- *                 the MN x 1 block, sqrt(MN) + 1. Zero-initialised params mean all 0. */
+ *                 the MN x 1 block, sqrt(MN) + 1. Zero-initialised params mean all 0.
+ *   spin_count  : cycle spinning of Sec. 9 as an average (needs cycle_spin = 1).
+ *                 0 or 1: one random shift per scale and iteration (above). c > 1:
+ *                 the Z-step of every block scale other than 1 x 1 is the mean of
+ *                 Shift_{-s}(BlockSVT(Shift_s(V))) over a shift set S. An axis the
+ *                 block spans whole (m = M or n = N) has one distinct shift (a cyclic
+ *                 shift only permutes inside each block there), so there are
+ *                 mr x nc distinct shifts, mr = (m == M ? 1 : m), nc likewise. When
+ *                 c >= mr nc, S is all of them in row-major order (full cycle
+ *                 spinning, translation invariant); else the c shifts
+ *                 msld_cycle_shift(shift_seed + j, k, i, ...), j = 0..c-1. Scales
+ *                 with mr nc = 1 keep the single random shift. Costs |S| BlockSVTs
+ *                 per averaged scale and iteration and two more M x N planes.
+ *                 Must be >= 0. */
 #define MSLD_KIND_BLOCK 0
 #define MSLD_KIND_NOISE 1
 typedef struct msld_params {
@@ -94,6 +107,7 @@ typedef struct msld_params {
   int32_t lowrank_min;
   uint64_t shift_seed;
   int32_t kind[MSLD_MAX_SCALES];
+  int32_t spin_count;
 } msld_params;
 
 /* Outcome of one msld_solve. primal_resid is r_k of the last iteration run

@@ -31,10 +31,17 @@ Parity status per function (what independent facts pin it; see tests/):
                       full-size scale recovers a low-rank matrix from 60% of its
                       entries (nuclear-norm completion); KKT with the dual
                       certificate supported on the observed entries.
+  spin_shifts,        pinned: averaging over every shift makes the Z-step exactly
+  spin_extent,        translation equivariant (it is not for a single shift), also
+  averaged_bsvt       with the reduced set of a block that spans an axis; a shift
+                      along such an axis leaves the shifted BlockSVT unchanged; one
+                      hashed shift is the random cycle spinning of the plain
+                      iteration; tau = 0 gives the input back (the 1/|S| factor);
+                      the average of proxes stays non-expansive.
 """
 from .msld_oracle import (  # noqa: F401
     MASK64, splitmix64_mix, cycle_shift, default_lambda, shift, unshift, svt,
     block_svt, cycle_spun_bsvt, admm, block_nuclear_norm, block_dual_norm,
     kkt_report, skip_bound_sq, KIND_BLOCK, KIND_NOISE, noise_svt, scale_lambda,
-    scale_norm, scale_dual_norm,
+    scale_norm, scale_dual_norm, spin_shifts, spin_extent, averaged_bsvt,
 )

@@ -97,6 +97,34 @@ def cycle_spun_bsvt(A: np.ndarray, m: int, n: int, tau: float, s) -> np.ndarray:
     return unshift(block_svt(shift(A, s), m, n, tau), s)
 
 
+def spin_extent(M: int, N: int, m: int, n: int):
+    """Distinct shifts per axis for cycle spinning of an m x n partition of an M x N
+    matrix. A cyclic shift along an axis the block spans whole (m = M or n = N) only
+    permutes rows or columns inside each block, which the block's SVT follows exactly,
+    so that axis contributes a single shift (reading of Sec. 9)."""
+    return (1 if m == M else m), (1 if n == N else n)
+
+
+def spin_shifts(seed: int, k: int, i: int, m: int, n: int, count: int, M=None, N=None):
+    """The shift set S of iteration k, scale i for averaged cycle spinning (Sec. 9).
+    With count >= mr nc (mr x nc = spin_extent) it is every shift (s_r, s_c) in
+    [0, mr) x [0, nc), in row-major order; otherwise `count` draws of the shift hash
+    with seeds seed + j."""
+    mr, nc = spin_extent(M if M is not None else -1, N if N is not None else -1, m, n)
+    if count >= mr * nc:
+        return [(r, c) for r in range(mr) for c in range(nc)]
+    return [cycle_shift(seed + j, k, i, m, n) for j in range(count)]
+
+
+def averaged_bsvt(A: np.ndarray, m: int, n: int, tau: float, shifts) -> np.ndarray:
+    """Cycle spinning of Sec. 9 as an average over a shift set S:
+    (1/|S|) sum_{s in S} Shift_{-s}(BSVT_tau(Shift_s(A)))."""
+    acc = np.zeros(np.shape(A))
+    for s in shifts:
+        acc += cycle_spun_bsvt(A, m, n, tau, s)
+    return acc / len(shifts)
+
+
 # ------------------------------------------------------------------ noise scale
 # Sec. 2 (multi-scale low rank + noise): the noise matrix is one more scale whose
 # reshape R_Z takes the whole M x N matrix to an MN x 1 vector; the block-wise nuclear
@@ -121,7 +149,7 @@ def scale_lambda(M: int, N: int, m: int, n: int, kind: int = KIND_BLOCK) -> floa
 
 # --------------------------------------------------------------------------- ADMM
 def admm(Y, ladder, lam=None, rho=1.0, iters=100, cycle_spin=False, seed=0,
-         tol=0.0, check_every=1, history=False, kinds=None, mask=None):
+         tol=0.0, check_every=1, history=False, kinds=None, mask=None, spin_count=1):
     """ADMM of Sec. 7 (eq:admm) for eq:cvx, with the random cycle spinning of Sec. 9.
 
     Per iteration k, in the paper's order:
@@ -130,6 +158,10 @@ def admm(Y, ladder, lam=None, rho=1.0, iters=100, cycle_spin=False, seed=0,
         U_i <- U_i - (Z_i - X_i)
     kinds[i] == KIND_NOISE makes scale i the noise scale of Sec. 2 (its Z-step is the
     SVT of the MN x 1 reshape, which no shift changes; its block size must be M x N).
+    spin_count > 1 (with cycle_spin) averages each block scale's Z-step over the shift
+    set spin_shifts(seed, k, i, m, n, spin_count, M, N) of Sec. 9 (every distinct shift
+    when spin_count covers them); scales with a single distinct shift (1 x 1, the
+    whole matrix) and noise scales keep the plain iteration.
     mask (M x N, true = observed) applies the data consistency of the collaborative
     filtering experiment of Sec. 10: the X-update above only on observed entries,
     X_i = Z_i - U_i on the others; the residual is then relative to ||P_obs(Y)||_F.
@@ -167,6 +199,11 @@ def admm(Y, ladder, lam=None, rho=1.0, iters=100, cycle_spin=False, seed=0,
         for i, (m, n) in enumerate(ladder):
             if kinds[i] == KIND_NOISE:
                 Z[i] = noise_svt(X[i] + U[i], lam[i] / rho)
+                continue
+            mr, nc = spin_extent(M, N, m, n)
+            if cycle_spin and spin_count > 1 and mr * nc > 1:
+                S = spin_shifts(seed, k, i, m, n, int(spin_count), M, N)
+                Z[i] = averaged_bsvt(X[i] + U[i], m, n, lam[i] / rho, S)
                 continue
             s = cycle_shift(seed, k, i, m, n) if cycle_spin else (0, 0)
             Z[i] = cycle_spun_bsvt(X[i] + U[i], m, n, lam[i] / rho, s)

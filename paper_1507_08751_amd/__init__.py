@@ -37,7 +37,8 @@ class Params(ctypes.Structure):
                 ("rho", ctypes.c_float), ("max_iters", ctypes.c_int32),
                 ("tol", ctypes.c_float), ("check_every", ctypes.c_int32),
                 ("cycle_spin", ctypes.c_int32), ("lowrank_min", ctypes.c_int32),
-                ("shift_seed", ctypes.c_uint64), ("kind", ctypes.c_int32 * MAX_SCALES)]
+                ("shift_seed", ctypes.c_uint64), ("kind", ctypes.c_int32 * MAX_SCALES),
+                ("spin_count", ctypes.c_int32)]
 
 KIND_BLOCK = 0
 KIND_NOISE = 1
@@ -148,7 +149,7 @@ def cycle_shift(seed, k, i, m, n):
 
 
 def make_params(M, N, ladder, lam=None, rho=1.0, iters=100, tol=0.0, check_every=1,
-                cycle_spin=False, seed=0, lowrank_min=0, kinds=None) -> Params:
+                cycle_spin=False, seed=0, lowrank_min=0, kinds=None, spin_count=0) -> Params:
     if len(ladder) < 1 or len(ladder) > MAX_SCALES:
         raise ValueError("ladder must have 1..16 scales")
     p = Params()
@@ -165,6 +166,7 @@ def make_params(M, N, ladder, lam=None, rho=1.0, iters=100, tol=0.0, check_every
     p.lowrank_min = int(lowrank_min)
     for i in range(len(ladder)):
         p.kind[i] = int(kinds[i]) if kinds is not None else KIND_BLOCK
+    p.spin_count = int(spin_count)
     return p
 
 
@@ -182,7 +184,8 @@ class Solver:
     """One planned decomposition problem (msld_create). Reusable across solves."""
 
     def __init__(self, M, N, ladder, lam=None, rho=1.0, iters=100, tol=0.0, check_every=1,
-                 cycle_spin=False, seed=0, device=None, lowrank_min=0, kinds=None):
+                 cycle_spin=False, seed=0, device=None, lowrank_min=0, kinds=None,
+                 spin_count=0):
         import torch
         self._torch = torch
         lib = load()
@@ -192,7 +195,7 @@ class Solver:
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
             else torch.device(device)
         self.params = make_params(M, N, ladder, lam, rho, iters, tol, check_every,
-                                  cycle_spin, seed, lowrank_min, kinds)
+                                  cycle_spin, seed, lowrank_min, kinds, spin_count)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             st = lib.msld_create(ctypes.byref(self.params), _stream_ptr(torch, self.device),
@@ -334,7 +337,7 @@ class Solver:
 class Batch:
     """Many independent decompositions solved together (msld_batch_*). `problems` is a
     list of dicts with keys M, N, ladder and optional lam, rho, iters, tol,
-    check_every, cycle_spin, seed, lowrank_min."""
+    check_every, cycle_spin, seed, lowrank_min, kinds, spin_count."""
 
     def __init__(self, problems, device=None):
         import torch
@@ -349,7 +352,8 @@ class Batch:
             arr[i] = make_params(pr["M"], pr["N"], pr["ladder"], pr.get("lam"),
                                  pr.get("rho", 1.0), pr.get("iters", 100), pr.get("tol", 0.0),
                                  pr.get("check_every", 1), pr.get("cycle_spin", False),
-                                 pr.get("seed", 0), pr.get("lowrank_min", 0))
+                                 pr.get("seed", 0), pr.get("lowrank_min", 0),
+                                 pr.get("kinds"), pr.get("spin_count", 0))
             self.shapes.append((len(pr["ladder"]), pr["M"], pr["N"]))
         self.n = n
         h = ctypes.c_void_p()

@@ -52,6 +52,7 @@ msld_status validate_params(const msld_params* p) {
   if (!(p->tol >= 0.f) || !std::isfinite(p->tol)) return MSLD_EINVAL;
   if (p->check_every < 1) return MSLD_EINVAL;
   if (p->cycle_spin != 0 && p->cycle_spin != 1) return MSLD_EINVAL;
+  if (p->spin_count < 0) return MSLD_EINVAL;
   for (int i = 0; i < p->L; ++i) {
     const int m = p->block_m[i], n = p->block_n[i];
     if (m < 1 || n < 1 || p->M % m || p->N % n) return MSLD_EINVAL;
@@ -67,7 +68,7 @@ msld_status validate_params(const msld_params* p) {
 bool same_class(const msld_params& a, const msld_params& b) {
   if (a.M != b.M || a.N != b.N || a.L != b.L || a.rho != b.rho || a.max_iters != b.max_iters ||
       a.tol != b.tol || a.check_every != b.check_every || a.cycle_spin != b.cycle_spin ||
-      a.lowrank_min != b.lowrank_min)
+      a.lowrank_min != b.lowrank_min || a.spin_count != b.spin_count)
     return false;
   for (int i = 0; i < a.L; ++i)
     if (a.block_m[i] != b.block_m[i] || a.block_n[i] != b.block_n[i] ||
@@ -142,6 +143,15 @@ msld_status make_plan(const msld_params* p, int ninst, Plan* pl) {
     pl->tier[i] = tier;
     pl->off_stats[i] = take(8 * 8);
     if (tier == TIER_1X1) continue;
+    // averaged cycle spinning: a cyclic shift along an axis the block spans whole
+    // permutes rows (columns) inside each block, which its SVT follows exactly, so
+    // that axis has one distinct shift; a scale with a single one keeps the plain step
+    const int64_t mr = m == IM ? 1 : m, nc = n == N ? 1 : n;
+    if (p->cycle_spin && p->spin_count > 1 && mr * nc > 1) {
+      pl->spin_full[i] = p->spin_count >= mr * nc ? 1 : 0;
+      pl->spin[i] = (int)(pl->spin_full[i] ? mr * nc : p->spin_count);
+      pl->off_spin[i] = take(4 * MN * 2);
+    }
     // stream plan
     StreamPlan& sp = pl->sp[i];
     int ws = kStreamFloats / m;
@@ -331,6 +341,10 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
     ScaleWork& w = s->work[i];
     std::memset(&w, 0, sizeof(w));
     w.stats = reinterpret_cast<unsigned long long*>(s->arena + pl.off_stats[i]);
+    if (pl.spin[i]) {
+      w.spinAcc = reinterpret_cast<float*>(s->arena + pl.off_spin[i]);
+      w.spinTmp = w.spinAcc + plane_elems(s);
+    }
     w.hostInts = s->host_ints + 2 * i;
     if (pl.tier[i] == TIER_FRO) {
       w.froPart = reinterpret_cast<double*>(s->arena + pl.off_lr[i]);
@@ -407,7 +421,8 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
     a.plane = plane_elems(s);
     size_t lds = 0;
     for (int i = 0; i < p->L; ++i) {
-      if (pl.tier[i] == TIER_1X1 || pl.tier[i] == TIER_FRO) continue;
+      // (averaged scales run their own stream pass per shift)
+      if (pl.tier[i] == TIER_1X1 || pl.tier[i] == TIER_FRO || pl.spin[i]) continue;
       StreamScale& d = a.s[a.n];
       d.g = pl.geom[i];
       d.sp = pl.sp[i];
@@ -504,7 +519,7 @@ msld_status iterate_once(msld_solver* s, const float* d_Y, int64_t ldY, float* d
     sh.ik = stacked ? s->d_k : nullptr;
     sh.iactive = stacked ? s->d_active : nullptr;
     if (ev) MSLD_TRY(s, hipEventRecord(ev[2], s->st));
-    MSLD_TRY(s, launch_stream_all(s->sall, s->sall_lds, d_Z, R, Dn, sh, s->st));
+    if (s->sall.n > 0) MSLD_TRY(s, launch_stream_all(s->sall, s->sall_lds, d_Z, R, Dn, sh, s->st));
     if (ev) MSLD_TRY(s, hipEventRecord(ev[3], s->st));
   }
   MSLD_TRY(s, hipEventRecord(s->ev_fork, s->st));
@@ -537,10 +552,42 @@ msld_status iterate_once(msld_solver* s, const float* d_Y, int64_t ldY, float* d
   auto issue = [&](int i) {
     float* Zi = d_Z + MN * i;
     rls[i] = 0;
-    herr[i] = launch_scale(pl.geom[i], pl.tier[i], pl.sp[i], s->work[i], Zi, R, Zi, Dn + MN * i,
-                           pl.tau_default[i], shs[i], jacobi_tol(pl.geom[i].mb), 40, 20,
-                           s->num_cus, s->sst[i], ev ? ev + 4 + 5 * i : nullptr, &rls[i],
-                           true);
+    if (!pl.spin[i]) {
+      herr[i] = launch_scale(pl.geom[i], pl.tier[i], pl.sp[i], s->work[i], Zi, R, Zi,
+                             Dn + MN * i, pl.tau_default[i], shs[i], jacobi_tol(pl.geom[i].mb),
+                             40, 20, s->num_cus, s->sst[i], ev ? ev + 4 + 5 * i : nullptr,
+                             &rls[i], true);
+      return;
+    }
+    // averaged cycle spinning: Z_i stays the input of every shift's Z-step until the
+    // finish kernel replaces it by the mean (phase timings cover the first shift)
+    const ScaleWork& w = s->work[i];
+    const int nc = pl.geom[i].n == N ? 1 : pl.geom[i].n;
+    const int* act = stacked ? s->d_active : nullptr;
+    const size_t inst = (size_t)IM * N;
+    hipError_t e = hipSuccess;
+    for (int j = 0; j < pl.spin[i] && e == hipSuccess; ++j) {
+      ShiftSpec sj = shs[i];
+      if (pl.spin_full[i]) {
+        sj.mode = 2;
+        sj.sr = j / nc;
+        sj.sc = j % nc;
+      } else {
+        sj.seed_add = (uint64_t)j;
+      }
+      float* out = j == 0 ? w.spinAcc : w.spinTmp;
+      int rl = 0;
+      e = launch_scale(pl.geom[i], pl.tier[i], pl.sp[i], s->work[i], Zi, R, out, Dn + MN * i,
+                       pl.tau_default[i], sj, jacobi_tol(pl.geom[i].mb), 40, 20, s->num_cus,
+                       s->sst[i], (ev && j == 0) ? ev + 4 + 5 * i : nullptr, &rl, false);
+      rls[i] += rl;
+      if (e == hipSuccess && j > 0)
+        e = launch_spin_acc(w.spinAcc, w.spinTmp, MN, inst, act, s->sst[i]);
+    }
+    if (e == hipSuccess)
+      e = launch_spin_finish(Zi, Dn + MN * i, R, w.spinAcc, 1.0f / (float)pl.spin[i], MN, inst,
+                             act, s->sst[i]);
+    herr[i] = e;
   };
   std::vector<std::thread> workers;
   int first_waiting = no;

@@ -33,6 +33,86 @@ hipError_t launch_fill(float* p, float v, size_t count, hipStream_t st) {
   return hipGetLastError();
 }
 
+// ------------------------------------------------------ averaged cycle spinning
+// Cycle spinning of Sec. 9 as a mean over a shift set S: the Z-step of a scale runs
+// once per shift into a scratch plane, k_spin_acc sums the results, and k_spin_finish
+// forms Z' = Acc / |S| and D' = 2 Z' - (Z + R) (the D form of the ADMM update).
+// Rows of retired instances (iactive[z] == 0, z = row / IM) are left untouched.
+__global__ void k_spin_acc(float* __restrict__ acc, const float* __restrict__ zs, size_t n,
+                           size_t inst_elems, const int* __restrict__ iactive, bool vec4) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (vec4) {
+    for (; 4 * i < n; i += stride) {
+      if (iactive && !iactive[4 * i / inst_elems]) continue;
+      float4 a = reinterpret_cast<float4*>(acc)[i];
+      const float4 b = reinterpret_cast<const float4*>(zs)[i];
+      a.x += b.x; a.y += b.y; a.z += b.z; a.w += b.w;
+      reinterpret_cast<float4*>(acc)[i] = a;
+    }
+  } else {
+    for (; i < n; i += stride) {
+      if (iactive && !iactive[i / inst_elems]) continue;
+      acc[i] += zs[i];
+    }
+  }
+}
+
+__global__ void k_spin_finish(float* __restrict__ Z, float* __restrict__ D,
+                              const float* __restrict__ R, const float* __restrict__ acc,
+                              float inv, size_t n, size_t inst_elems,
+                              const int* __restrict__ iactive, bool vec4) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (vec4) {
+    for (; 4 * i < n; i += stride) {
+      if (iactive && !iactive[4 * i / inst_elems]) continue;
+      const float4 z = reinterpret_cast<const float4*>(Z)[i];
+      const float4 r = reinterpret_cast<const float4*>(R)[i];
+      const float4 a = reinterpret_cast<const float4*>(acc)[i];
+      float4 zn, d;
+      zn.x = a.x * inv; zn.y = a.y * inv; zn.z = a.z * inv; zn.w = a.w * inv;
+      d.x = 2.f * zn.x - (z.x + r.x);
+      d.y = 2.f * zn.y - (z.y + r.y);
+      d.z = 2.f * zn.z - (z.z + r.z);
+      d.w = 2.f * zn.w - (z.w + r.w);
+      reinterpret_cast<float4*>(Z)[i] = zn;
+      reinterpret_cast<float4*>(D)[i] = d;
+    }
+  } else {
+    for (; i < n; i += stride) {
+      if (iactive && !iactive[i / inst_elems]) continue;
+      const float zn = acc[i] * inv;
+      D[i] = 2.f * zn - (Z[i] + R[i]);
+      Z[i] = zn;
+    }
+  }
+}
+
+static unsigned spin_blocks(size_t work) {
+  size_t b = (work + 255) / 256;
+  if (b > 8192) b = 8192;
+  return (unsigned)(b ? b : 1);
+}
+
+hipError_t launch_spin_acc(float* acc, const float* zs, size_t n, size_t inst_elems,
+                           const int* iactive, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const bool vec4 = inst_elems % 4 == 0;
+  hipLaunchKernelGGL(k_spin_acc, dim3(spin_blocks(vec4 ? n / 4 : n)), dim3(256), 0, st, acc, zs,
+                     n, inst_elems, iactive, vec4);
+  return hipGetLastError();
+}
+
+hipError_t launch_spin_finish(float* Z, float* D, const float* R, const float* acc, float inv,
+                              size_t n, size_t inst_elems, const int* iactive, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const bool vec4 = inst_elems % 4 == 0;
+  hipLaunchKernelGGL(k_spin_finish, dim3(spin_blocks(vec4 ? n / 4 : n)), dim3(256), 0, st, Z, D,
+                     R, acc, inv, n, inst_elems, iactive, vec4);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------- consensus pass
 // R = (Y - sum_j D_j) / L  (X-update of eq:admm), fused with every 1x1 scale:
 // for 1x1 blocks the block-wise SVT is the entrywise soft-threshold (Sec. 7), so

@@ -40,11 +40,12 @@ struct ShiftSpec {
   const unsigned long long* iseed;  // per-instance seeds (null: seed)
   const int* ik;                    // per-instance iteration (null: k)
   const int* iactive;               // per-instance active flag (null: all active)
+  uint64_t seed_add = 0;            // added to the seed in mode 1 (j-th shift of a spin set)
 };
 
 __device__ inline void block_shift(const ShiftSpec& s, int z, int m, int n, int* sr, int* sc) {
   if (s.mode == 1) {
-    const uint64_t seed = s.iseed ? (uint64_t)s.iseed[z] : s.seed;
+    const uint64_t seed = (s.iseed ? (uint64_t)s.iseed[z] : s.seed) + s.seed_add;
     const int k = s.ik ? s.ik[z] : s.k;
     cycle_shift(seed, k, s.scale, m, n, sr, sc);
   } else if (s.mode == 2) {
@@ -93,6 +94,8 @@ __device__ inline int gcol(const ScaleGeom& g, int q, int j, int sc) {
 
 // Per-scale device buffers and counters.
 struct ScaleWork {
+  float* spinAcc;       // averaged cycle spinning: [plane] sum over the shift set
+  float* spinTmp;       // [plane] one shift's Z-step
   double* froPart;      // noise scale: [ninst][kFroParts] partial sums of squares
   float* froGain;       // noise scale: [ninst] gains max(1 - tau / ||v||_F, 0)
   int* live_count;      // [1] blocks that passed the bound test this pass
@@ -177,6 +180,10 @@ hipError_t launch_stream_all(const StreamAll& a, size_t lds, const float* Z, con
                              float* D, const ShiftSpec& sh, hipStream_t st);
 float stream_tau2lim(const ScaleGeom& g, float tau);
 hipError_t launch_fill(float* p, float v, size_t count, hipStream_t st);
+hipError_t launch_spin_acc(float* acc, const float* zs, size_t n, size_t inst_elems,
+                           const int* iactive, hipStream_t st);
+hipError_t launch_spin_finish(float* Z, float* D, const float* R, const float* acc, float inv,
+                              size_t n, size_t inst_elems, const int* iactive, hipStream_t st);
 hipError_t launch_consensus(const float* Y, int64_t ldY, const float* Dcur, float* Dnext,
                             float* Z, float* R, int M, int N, int L, const int* scales1,
                             const float* taus1, int n1, int IM, const int* iactive,

@@ -43,6 +43,11 @@ struct Plan {
       off_pW[MSLD_MAX_SCALES], off_pflag[MSLD_MAX_SCALES], off_pg[MSLD_MAX_SCALES],
       off_lr[MSLD_MAX_SCALES], off_pl[MSLD_MAX_SCALES];
   int pl_cap[MSLD_MAX_SCALES];   // polar fallback chunk (0: none)
+  // averaged cycle spinning: shifts per iteration (0: one random shift), whether the
+  // set is every shift, and the accumulator + scratch planes
+  int spin[MSLD_MAX_SCALES];
+  int spin_full[MSLD_MAX_SCALES];
+  size_t off_spin[MSLD_MAX_SCALES];
 };
 
 msld_status validate_params(const msld_params* p);

@@ -31,8 +31,10 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_layout_matches_header():
-    # int32 M,N,L; 16+16 int32; 16 float; rho,max_iters,tol,check_every,cycle_spin,lowrank_min; u64
-    assert ctypes.sizeof(msld.Params) == 4 * 3 + 4 * 48 + 4 * 6 + 8 + 4 + 4 * 16  # +4 pad
+    # int32 M,N,L; 16+16 int32; 16 float; rho,max_iters,tol,check_every,cycle_spin,lowrank_min;
+    # 4 pad; u64 seed; 16 int32 kinds; int32 spin_count; 4 tail pad
+    assert ctypes.sizeof(msld.Params) == 4 * 3 + 4 * 48 + 4 * 6 + 4 + 8 + 4 * 16 + 4 + 4
+    assert msld.Params.spin_count.offset == ctypes.sizeof(msld.Params) - 8
     assert msld.Params.shift_seed.offset % 8 == 0
     assert ctypes.sizeof(msld.Result) == 4 + 4 + 8 + 8 * 8 * 16
 
@@ -70,6 +72,7 @@ def test_host_default_lambda_matches_oracle():
     dict(M=64, N=64, ladder=[(4, 4)], check_every=0),
     dict(M=64, N=64, ladder=[(4, 4)], kinds=[1]),          # noise scale needs the full block
     dict(M=64, N=64, ladder=[(64, 64)], kinds=[2]),         # unknown kind
+    dict(M=64, N=64, ladder=[(4, 4)], cycle_spin=True, spin_count=-1),
 ])
 def test_invalid_params_rejected_on_host(bad):
     bad = dict(bad)
@@ -96,3 +99,20 @@ def test_noise_scale_plans():
     M, N = 64, 48
     assert msld.workspace_bytes(M, N, [(1, 1), (M, N)], kinds=[0, 1]) > 0
     assert msld.workspace_bytes(M, N, [(1, 1), (M, N), (M, N)], kinds=[0, 0, 1]) > 0
+
+
+def test_averaged_spinning_adds_two_planes_per_block_scale():
+    """spin_count > 1 with cycle spinning keeps an accumulator and a scratch plane for
+    every scale with more than one distinct shift (not 1 x 1, not the whole matrix)."""
+    M = N = 256
+    lad = [(1, 1), (4, 4), (16, 16), (256, 256)]
+    base = msld.workspace_bytes(M, N, lad, cycle_spin=True)
+    avg = msld.workspace_bytes(M, N, lad, cycle_spin=True, spin_count=4)
+    assert avg - base >= 2 * 2 * 4 * M * N
+    assert avg - base < 2 * 2 * 4 * M * N + 2 * 2 * 256
+    # a scale that spans the rows still has n distinct shifts
+    lad2 = [(1, 1), (256, 16)]
+    assert msld.workspace_bytes(M, N, lad2, cycle_spin=True, spin_count=4) - \
+        msld.workspace_bytes(M, N, lad2, cycle_spin=True) >= 2 * 4 * M * N
+    # without cycle spinning the count is ignored
+    assert msld.workspace_bytes(M, N, lad, spin_count=4) == msld.workspace_bytes(M, N, lad)

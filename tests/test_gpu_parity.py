@@ -476,3 +476,68 @@ def test_completion_workload_parity(lib):
     print(f"completion 1682x943: errs {errs}", flush=True)
     assert max(errs) <= 1e-3
     solver.close()
+
+
+# ---------------------------------------------------------- averaged cycle spinning
+SPIN_CASES = {
+    "hashed3": ([(1, 1), (4, 4), (16, 16), (32, 96)], 3),
+    "full64": ([(1, 1), (2, 2), (4, 4), (8, 8), (32, 32)], 64),
+    "spanning": ([(1, 1), (64, 8), (16, 96), (64, 96)], 16),
+}
+
+
+@pytest.mark.parametrize("case", list(SPIN_CASES))
+def test_admm_averaged_spinning_parity(lib, case):
+    """Cycle spinning as an average over a shift set against the oracle (1e-3): 3
+    hashed shifts; every shift of the 2 x 2, 4 x 4 and 8 x 8 scales (64 hashed for
+    32 x 32); blocks spanning an axis (8 column shifts of 64 x 8, 16 row shifts of
+    16 x 96, the whole matrix unaveraged)."""
+    M, N = 64, 96
+    ladder, spin_count = SPIN_CASES[case]
+    inst = make_instance(M, N, ladder, 0.05, noise=0.01, seed=11, keep_components=False)
+    iters = 25
+    ref = O.admm(inst.Y.astype(np.float64), ladder, rho=1.0, iters=iters, cycle_spin=True,
+                 seed=13, spin_count=spin_count)
+    solver = lib.Solver(M, N, ladder, rho=1.0, iters=iters, cycle_spin=True, seed=13,
+                        spin_count=spin_count)
+    Z, info = solver.solve(torch.from_numpy(inst.Y).cuda())
+    torch.cuda.synchronize()
+    Zg = Z.cpu().numpy()
+    errs = [rel_err(Zg[i], ref["Z"][i], np.linalg.norm(inst.Y)) for i in range(len(ladder))]
+    print(f"averaged spin {case}: errs {['%.1e' % e for e in errs]}", flush=True)
+    assert max(errs) <= 1e-3
+    # differs from the single-shift iteration (the average is really taken)
+    one = O.admm(inst.Y.astype(np.float64), ladder, rho=1.0, iters=iters, cycle_spin=True,
+                 seed=13)
+    assert max(rel_err(one["Z"][i], ref["Z"][i], np.linalg.norm(inst.Y))
+               for i in range(1, len(ladder))) > 1e-2
+    solver.close()
+
+
+def test_averaged_spinning_stacked_matches_alone(lib):
+    """Three averaged-spinning problems of one shape in a batch (stacked launches, per
+    instance seeds) agree with each solved alone (1e-5, the batch path's own bar)."""
+    M = N = 64
+    ladder = [(1, 1), (4, 4), (16, 16), (64, 64)]
+    probs, Ys, alone = [], [], []
+    for j in range(3):
+        inst = make_instance(M, N, ladder, 0.05, noise=0.01, seed=20 + j, keep_components=False)
+        Ys.append(torch.from_numpy(inst.Y).cuda())
+        probs.append(dict(M=M, N=N, ladder=ladder, iters=12, cycle_spin=True, seed=100 + j,
+                          spin_count=4))
+        s = lib.Solver(M, N, ladder, iters=12, cycle_spin=True, seed=100 + j, spin_count=4)
+        Z, _ = s.solve(Ys[-1])
+        torch.cuda.synchronize()
+        alone.append(Z.cpu().numpy())
+        s.close()
+    b = lib.Batch(probs)
+    assert b.classes == 1
+    outs, infos = b.solve(Ys)
+    torch.cuda.synchronize()
+    for j in range(3):
+        got = outs[j].cpu().numpy()
+        ny = float(np.linalg.norm(Ys[j].cpu().numpy()))
+        err = max(rel_err(got[i], alone[j][i], ny) for i in range(len(ladder)))
+        print(f"stacked averaged spin instance {j}: {err:.1e}", flush=True)
+        assert err <= 1e-5, j
+    b.close()

@@ -378,3 +378,70 @@ def test_admm_masked_kkt_and_gap():
     assert rep["off_support"] < 1e-12
     assert max(rep["dual_ratio"]) <= 1 + 1e-9
     assert abs(rep["gap"]) < 2e-7
+
+
+# ------------------------------------------------------------ averaged spinning
+def test_full_cycle_spinning_is_translation_equivariant():
+    """Averaging over every shift (Sec. 9) makes the block-wise SVT translation
+    invariant: T(Shift_t V) = Shift_t T(V) for any t, which a single partition is not."""
+    rng = np.random.default_rng(4)
+    V = rng.standard_normal((12, 16))
+    m, n, tau = 4, 4, 0.9
+    S = O.spin_shifts(0, 0, 0, m, n, m * n)
+    assert len(S) == m * n and len(set(S)) == m * n
+    T = lambda A: O.averaged_bsvt(A, m, n, tau, S)
+    t = (3, 5)
+    assert np.abs(T(O.shift(V, t)) - O.shift(T(V), t)).max() < 1e-12
+    single = lambda A: O.cycle_spun_bsvt(A, m, n, tau, (0, 0))
+    assert np.abs(single(O.shift(V, t)) - O.shift(single(V), t)).max() > 1e-3
+
+
+def test_spin_count_one_is_random_cycle_spinning():
+    inst = make_instance(32, 32, [(1, 1), (4, 4), (16, 16)], 0.05, noise=0.01, seed=3)
+    a = O.admm(inst.Y, inst.ladder, iters=15, cycle_spin=True, seed=7)
+    b = O.admm(inst.Y, inst.ladder, iters=15, cycle_spin=True, seed=7, spin_count=1)
+    assert np.array_equal(a["Z"], b["Z"])
+    # the first hashed shift of a spin set is the plain random shift
+    assert O.spin_shifts(7, 3, 2, 16, 16, 4)[0] == O.cycle_shift(7, 3, 2, 16, 16)
+
+
+def test_averaged_prox_is_nonexpansive():
+    """Each Shift_{-s} BSVT Shift_s is a prox (firmly non-expansive), so their average
+    is non-expansive: ||T(A) - T(B)|| <= ||A - B||."""
+    rng = np.random.default_rng(6)
+    S = O.spin_shifts(1, 0, 0, 8, 8, 5)
+    for _ in range(5):
+        A = rng.standard_normal((16, 24))
+        B = A + 0.3 * rng.standard_normal((16, 24))
+        TA = O.averaged_bsvt(A, 8, 8, 1.1, S)
+        TB = O.averaged_bsvt(B, 8, 8, 1.1, S)
+        assert np.linalg.norm(TA - TB) <= np.linalg.norm(A - B) + 1e-12
+
+
+def test_averaged_bsvt_normalisation():
+    """tau = 0 makes every shifted BlockSVT the identity, so the mean is the input; tau
+    above every block norm makes it zero (checks the 1/|S| factor and the unshift)."""
+    rng = np.random.default_rng(9)
+    V = rng.standard_normal((16, 16))
+    S = O.spin_shifts(2, 1, 1, 4, 8, 7)
+    assert np.abs(O.averaged_bsvt(V, 4, 8, 0.0, S) - V).max() < 1e-12
+    assert np.abs(O.averaged_bsvt(V, 4, 8, 1e3, S)).max() == 0.0
+
+
+def test_spanning_axis_needs_one_shift():
+    """A block that spans all rows (m = M): a cyclic row shift permutes rows inside each
+    block, so the shifted BlockSVT does not change, and the reduced full set (column
+    shifts only) is still translation equivariant in both axes."""
+    rng = np.random.default_rng(10)
+    V = rng.standard_normal((12, 16))
+    M, N, m, n, tau = 12, 16, 12, 4, 1.3
+    assert O.spin_extent(M, N, m, n) == (1, 4)
+    for r in (1, 5, 11):
+        a = O.cycle_spun_bsvt(V, m, n, tau, (r, 3))
+        b = O.cycle_spun_bsvt(V, m, n, tau, (0, 3))
+        assert np.abs(a - b).max() < 1e-12
+    S = O.spin_shifts(0, 0, 0, m, n, 100, M, N)
+    assert S == [(0, 0), (0, 1), (0, 2), (0, 3)]
+    T = lambda A: O.averaged_bsvt(A, m, n, tau, S)
+    for t in ((5, 3), (0, 7), (4, 0)):
+        assert np.abs(T(O.shift(V, t)) - O.shift(T(V), t)).max() < 1e-12
