@@ -38,10 +38,17 @@ Parity status per function (what independent facts pin it; see tests/):
                       hashed shift is the random cycle spinning of the plain
                       iteration; tau = 0 gives the input back (the 1/|S| factor);
                       the average of proxes stays non-expansive.
+  st_shift,           pinned: brute-force index loops over the video (patch pixels
+  spacetime_bsvt,     with wrap in y, x, t) give the same thresholded blocks; a patch
+  scale_bsvt          one image row wide equals the contiguous W x bt partition; the
+                      whole image equals the contiguous M x bt partition; equivariance
+                      under video shifts after averaging over every shift; ADMM with
+                      space-time scales reaches the KKT conditions of eq:cvx.
 """
 from .msld_oracle import (  # noqa: F401
     MASK64, splitmix64_mix, cycle_shift, default_lambda, shift, unshift, svt,
     block_svt, cycle_spun_bsvt, admm, block_nuclear_norm, block_dual_norm,
     kkt_report, skip_bound_sq, KIND_BLOCK, KIND_NOISE, noise_svt, scale_lambda,
     scale_norm, scale_dual_norm, spin_shifts, spin_extent, averaged_bsvt,
+    KIND_SPATIAL, st_shift, st_unshift, spacetime_bsvt, scale_bsvt,
 )

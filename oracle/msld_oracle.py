@@ -116,12 +116,12 @@ def spin_shifts(seed: int, k: int, i: int, m: int, n: int, count: int, M=None, N
     return [cycle_shift(seed + j, k, i, m, n) for j in range(count)]
 
 
-def averaged_bsvt(A: np.ndarray, m: int, n: int, tau: float, shifts) -> np.ndarray:
+def averaged_bsvt(A: np.ndarray, m: int, n: int, tau: float, shifts, geo=None) -> np.ndarray:
     """Cycle spinning of Sec. 9 as an average over a shift set S:
-    (1/|S|) sum_{s in S} Shift_{-s}(BSVT_tau(Shift_s(A)))."""
+    (1/|S|) sum_{s in S} Shift_{-s}(BSVT_tau(Shift_s(A))) (geo: see scale_bsvt)."""
     acc = np.zeros(np.shape(A))
     for s in shifts:
-        acc += cycle_spun_bsvt(A, m, n, tau, s)
+        acc += scale_bsvt(A, m, n, tau, s, geo)
     return acc / len(shifts)
 
 
@@ -139,6 +139,68 @@ def noise_svt(A: np.ndarray, tau: float) -> np.ndarray:
     return svt(A.reshape(-1, 1), tau).reshape(A.shape)
 
 
+# -------------------------------------------------------------- space-time blocks
+# Sec. 2 (general block reshape R_b) and the video / DCE experiments of Sec. 10: the
+# rows of Y are the pixels of an H x W image in row-major order (row y W + x) and the
+# columns are frames. A space-time block is a ph x pw pixel patch over bt consecutive
+# frames, reshaped to a (ph pw) x bt matrix (row dy pw + dx of the block is pixel
+# (y0 + dy, x0 + dx)); a patch spanning every frame (bt = N) is the space-only
+# decimation of the face experiment. Shift_s is the cyclic shift of the video in
+# (y, x, t).
+KIND_SPATIAL = 2     # block-wise nuclear norm over the space-time partition
+
+
+def st_shift(A: np.ndarray, W: int, pw: int, s):
+    """Shift_s of Sec. 9 on the video: V[y, x, t] <- V[(y+sy) mod H, (x+sx) mod W,
+    (t+st) mod N]. Reading: the patch shift (sy, sx) is drawn as one residue
+    s_r mod (ph pw) with sy = s_r div pw, sx = s_r mod pw; st = s_c."""
+    M, N = A.shape
+    sy, sx = divmod(int(s[0]), pw)
+    V = np.asarray(A).reshape(M // W, W, N)
+    return np.roll(V, (-sy, -sx, -int(s[1])), axis=(0, 1, 2)).reshape(M, N)
+
+
+def st_unshift(A: np.ndarray, W: int, pw: int, s):
+    """Shift_{-s}, the inverse of `st_shift`."""
+    M, N = A.shape
+    sy, sx = divmod(int(s[0]), pw)
+    V = np.asarray(A).reshape(M // W, W, N)
+    return np.roll(V, (sy, sx, int(s[1])), axis=(0, 1, 2)).reshape(M, N)
+
+
+def _st_blocks(A: np.ndarray, W: int, ph: int, pw: int, bt: int) -> np.ndarray:
+    """All R_b(A) of the space-time partition, stacked as (nblocks, ph pw, bt)."""
+    M, N = A.shape
+    H = M // W
+    if H * W != M or H % ph or W % pw or N % bt:
+        raise ValueError("patch and frame block must tile the video")
+    T = np.asarray(A, dtype=np.float64).reshape(H // ph, ph, W // pw, pw, N // bt, bt)
+    return T.transpose(0, 2, 4, 1, 3, 5).reshape(-1, ph * pw, bt)
+
+
+def _st_unblocks(Bk: np.ndarray, M: int, N: int, W: int, ph: int, pw: int, bt: int):
+    """sum_b R_b^T(B_b) for the space-time partition (adjoint of `_st_blocks`)."""
+    H = M // W
+    T = Bk.reshape(H // ph, W // pw, N // bt, ph, pw, bt).transpose(0, 3, 1, 4, 2, 5)
+    return T.reshape(M, N)
+
+
+def spacetime_bsvt(A: np.ndarray, W: int, ph: int, pw: int, bt: int, tau: float):
+    """eq:bsvt over the space-time partition: every (ph pw) x bt block thresholded."""
+    M, N = A.shape
+    Bk = _st_blocks(A, W, ph, pw, bt)
+    return _st_unblocks(svt(Bk, tau), M, N, W, ph, pw, bt)
+
+
+def scale_bsvt(A: np.ndarray, m: int, n: int, tau: float, s, geo=None) -> np.ndarray:
+    """Shift_{-s}(BSVT_tau(Shift_s(A))) of one scale: the contiguous m x n partition
+    (geo None) or the space-time partition geo = (W, pw) with ph = m / pw, bt = n."""
+    if geo is None:
+        return cycle_spun_bsvt(A, m, n, tau, s)
+    W, pw = geo
+    return st_unshift(spacetime_bsvt(st_shift(A, W, pw, s), W, m // pw, pw, n, tau), W, pw, s)
+
+
 def scale_lambda(M: int, N: int, m: int, n: int, kind: int = KIND_BLOCK) -> float:
     """eq:lambda for scale i; the noise scale's block is MN x 1 (Sec. 4 notes its
     lambda ~ sqrt(MN))."""
@@ -149,7 +211,8 @@ def scale_lambda(M: int, N: int, m: int, n: int, kind: int = KIND_BLOCK) -> floa
 
 # --------------------------------------------------------------------------- ADMM
 def admm(Y, ladder, lam=None, rho=1.0, iters=100, cycle_spin=False, seed=0,
-         tol=0.0, check_every=1, history=False, kinds=None, mask=None, spin_count=1):
+         tol=0.0, check_every=1, history=False, kinds=None, mask=None, spin_count=1,
+         image_w=None, patch_w=None):
     """ADMM of Sec. 7 (eq:admm) for eq:cvx, with the random cycle spinning of Sec. 9.
 
     Per iteration k, in the paper's order:
@@ -162,6 +225,8 @@ def admm(Y, ladder, lam=None, rho=1.0, iters=100, cycle_spin=False, seed=0,
     set spin_shifts(seed, k, i, m, n, spin_count, M, N) of Sec. 9 (every distinct shift
     when spin_count covers them); scales with a single distinct shift (1 x 1, the
     whole matrix) and noise scales keep the plain iteration.
+    kinds[i] == KIND_SPATIAL makes scale i a space-time partition (rows = pixels of an
+    image of width image_w, ladder entry (ph pw, bt), patch width patch_w[i]).
     mask (M x N, true = observed) applies the data consistency of the collaborative
     filtering experiment of Sec. 10: the X-update above only on observed entries,
     X_i = Z_i - U_i on the others; the residual is then relative to ||P_obs(Y)||_F.
@@ -189,6 +254,8 @@ def admm(Y, ladder, lam=None, rho=1.0, iters=100, cycle_spin=False, seed=0,
     hist = []
     r = float("nan")
     k_done = 0
+    geos = [(int(image_w), int(patch_w[i])) if kinds[i] == KIND_SPATIAL else None
+            for i in range(L)]
     for k in range(int(iters)):
         S = (Z - U).sum(axis=0)
         for i in range(L):
@@ -203,10 +270,10 @@ def admm(Y, ladder, lam=None, rho=1.0, iters=100, cycle_spin=False, seed=0,
             mr, nc = spin_extent(M, N, m, n)
             if cycle_spin and spin_count > 1 and mr * nc > 1:
                 S = spin_shifts(seed, k, i, m, n, int(spin_count), M, N)
-                Z[i] = averaged_bsvt(X[i] + U[i], m, n, lam[i] / rho, S)
+                Z[i] = averaged_bsvt(X[i] + U[i], m, n, lam[i] / rho, S, geos[i])
                 continue
             s = cycle_shift(seed, k, i, m, n) if cycle_spin else (0, 0)
-            Z[i] = cycle_spun_bsvt(X[i] + U[i], m, n, lam[i] / rho, s)
+            Z[i] = scale_bsvt(X[i] + U[i], m, n, lam[i] / rho, s, geos[i])
         U = U - (Z - X)
         r = float(np.sqrt(((X - Z) ** 2).sum()) / ny)
         k_done = k + 1
@@ -233,21 +300,28 @@ def block_dual_norm(A, m, n) -> float:
     return float(np.linalg.svd(Bk.reshape(P * Q, m, n), compute_uv=False).max())
 
 
-def scale_norm(A, m, n, kind=KIND_BLOCK) -> float:
-    """The norm of scale i in eq:cvx (Frobenius for the noise scale)."""
+def scale_norm(A, m, n, kind=KIND_BLOCK, geo=None) -> float:
+    """The norm of scale i in eq:cvx (Frobenius for the noise scale; geo = (W, pw)
+    for a space-time scale)."""
     if kind == KIND_NOISE:
         return float(np.linalg.norm(A))
+    if geo is not None:
+        Bk = _st_blocks(A, geo[0], m // geo[1], geo[1], n)
+        return float(np.linalg.svd(Bk, compute_uv=False).sum())
     return block_nuclear_norm(A, m, n)
 
 
-def scale_dual_norm(A, m, n, kind=KIND_BLOCK) -> float:
+def scale_dual_norm(A, m, n, kind=KIND_BLOCK, geo=None) -> float:
     """Its dual norm (Sec. 3); the Frobenius norm is self-dual."""
     if kind == KIND_NOISE:
         return float(np.linalg.norm(A))
+    if geo is not None:
+        Bk = _st_blocks(A, geo[0], m // geo[1], geo[1], n)
+        return float(np.linalg.svd(Bk, compute_uv=False).max())
     return block_dual_norm(A, m, n)
 
 
-def kkt_report(Y, ladder, lam, rho, Z, U, kinds=None, mask=None):
+def kkt_report(Y, ladder, lam, rho, Z, U, kinds=None, mask=None, image_w=None, patch_w=None):
     """Optimality diagnostics for eq:cvx from an ADMM state (no cycle spinning).
 
     Dual certificate: at a fixed point all U_i coincide and Q = rho * mean_i U_i
@@ -261,15 +335,18 @@ def kkt_report(Y, ladder, lam, rho, Z, U, kinds=None, mask=None):
     Y = np.asarray(Y, dtype=np.float64)
     L = len(ladder)
     kinds = [KIND_BLOCK] * L if kinds is None else list(kinds)
+    geos = [(int(image_w), int(patch_w[i])) if kinds[i] == KIND_SPATIAL else None
+            for i in range(L)]
     obs = np.ones(Y.shape, dtype=bool) if mask is None else np.asarray(mask, dtype=bool)
     Y = np.where(obs, Y, 0.0)
     Ubar = np.mean(U, axis=0)
     Q = rho * Ubar
-    ratios = [scale_dual_norm(Q, m, n, kinds[i]) / lam[i] for i, (m, n) in enumerate(ladder)]
+    ratios = [scale_dual_norm(Q, m, n, kinds[i], geos[i]) / lam[i]
+              for i, (m, n) in enumerate(ladder)]
     Qs = Q / max(1.0, max(ratios))
     dual = float((Qs * Y).sum())
     Zf = Z + np.where(obs, Y - Z.sum(axis=0), 0.0) / L
-    primal = float(sum(lam[i] * scale_norm(Zf[i], m, n, kinds[i])
+    primal = float(sum(lam[i] * scale_norm(Zf[i], m, n, kinds[i], geos[i])
                        for i, (m, n) in enumerate(ladder)))
     spread = float(max(np.linalg.norm(U[i] - Ubar) for i in range(L)) /
                    max(np.linalg.norm(Ubar), 1e-300))

@@ -445,3 +445,91 @@ def test_spanning_axis_needs_one_shift():
     T = lambda A: O.averaged_bsvt(A, m, n, tau, S)
     for t in ((5, 3), (0, 7), (4, 0)):
         assert np.abs(T(O.shift(V, t)) - O.shift(T(V), t)).max() < 1e-12
+
+
+# ------------------------------------------------------------- space-time blocks
+def _brute_spacetime(A, H, W, ph, pw, bt, tau, s):
+    """Space-time BlockSVT by index loops: gather each shifted (ph pw) x bt block pixel
+    by pixel with wrap in y, x and t, threshold it with a library SVD, scatter back."""
+    M, N = A.shape
+    sy, sx = divmod(s[0], pw)
+    Z = np.zeros_like(A)
+    for py in range(H // ph):
+        for px in range(W // pw):
+            for pt in range(N // bt):
+                rows, cols = [], []
+                for dy in range(ph):
+                    for dx in range(pw):
+                        y = (py * ph + dy + sy) % H
+                        x = (px * pw + dx + sx) % W
+                        rows.append(y * W + x)
+                for dt in range(bt):
+                    cols.append((pt * bt + dt + s[1]) % N)
+                B = A[np.ix_(rows, cols)]
+                U, S, Vt = np.linalg.svd(B, full_matrices=False)
+                Z[np.ix_(rows, cols)] = (U * np.maximum(S - tau, 0)) @ Vt
+    return Z
+
+
+@pytest.mark.parametrize("s", [(0, 0), (4, 1), (5, 3), (1, 2)])
+def test_spacetime_bsvt_matches_index_loops(s):
+    rng = np.random.default_rng(12)
+    H, W, N, ph, pw, bt = 4, 6, 6, 2, 3, 2
+    A = rng.standard_normal((H * W, N))
+    tau = 0.8
+    got = O.scale_bsvt(A, ph * pw, bt, tau, s, geo=(W, pw))
+    ref = _brute_spacetime(A, H, W, ph, pw, bt, tau, s)
+    assert np.abs(got - ref).max() < 1e-12
+    # not the contiguous partition of the same block size
+    assert np.abs(got - O.cycle_spun_bsvt(A, ph * pw, bt, tau, s)).max() > 1e-3
+
+
+def test_spacetime_reduces_to_contiguous_partitions():
+    """A patch one image row wide is the contiguous W x bt partition (a shift along x
+    only permutes inside the block); the whole image is the M x bt partition."""
+    rng = np.random.default_rng(13)
+    H, W, N = 6, 8, 12
+    A = rng.standard_normal((H * W, N))
+    for s in [(0, 0), (5, 2), (3, 7)]:
+        row = O.scale_bsvt(A, W, 4, 1.1, s, geo=(W, W))
+        assert np.abs(row - O.cycle_spun_bsvt(A, W, 4, 1.1, (0, s[1]))).max() < 1e-12
+        full = O.scale_bsvt(A, H * W, 3, 1.1, (s[0] * W, s[1]), geo=(W, W))
+        assert np.abs(full - O.cycle_spun_bsvt(A, H * W, 3, 1.1, (0, s[1]))).max() < 1e-12
+
+
+def test_spacetime_full_spinning_is_video_shift_equivariant():
+    rng = np.random.default_rng(14)
+    H, W, N, ph, pw, bt = 4, 4, 4, 2, 2, 2
+    V = rng.standard_normal((H * W, N))
+    S = O.spin_shifts(0, 0, 0, ph * pw, bt, 1000, H * W, N)
+    assert len(S) == ph * pw * bt
+    T = lambda A: O.averaged_bsvt(A, ph * pw, bt, 0.7, S, geo=(W, pw))
+    t = (3 * pw + 1, 1)          # video shift (3, 1, 1)
+    assert np.abs(T(O.st_shift(V, W, pw, t)) - O.st_shift(T(V), W, pw, t)).max() < 1e-12
+    one = lambda A: O.scale_bsvt(A, ph * pw, bt, 0.7, (0, 0), geo=(W, pw))
+    assert np.abs(one(O.st_shift(V, W, pw, t)) - O.st_shift(one(V), W, pw, t)).max() > 1e-3
+
+
+def test_admm_spacetime_kkt_and_gap():
+    """ADMM with space-time scales (2 x 2 x 2, space-only 4 x 4 patches over all frames,
+    and the whole video) reaches the KKT conditions of eq:cvx with their dual norms."""
+    H = W = 8
+    N = 8
+    rng = np.random.default_rng(15)
+    Y = 0.05 * rng.standard_normal((H * W, N))
+    Y[:, :] += np.outer(rng.standard_normal(H * W), rng.standard_normal(N)) * 0.3
+    Y[9, 3] += 2.0
+    # a rank-1 space-only blob on the 4 x 4 patch at (4, 4)
+    pix = [(4 + dy) * W + 4 + dx for dy in range(4) for dx in range(4)]
+    Y[pix, :] += 0.8 * np.outer(rng.standard_normal(16), rng.standard_normal(N))
+    ladder = [(1, 1), (4, 2), (16, N), (H * W, N)]
+    kinds = [0, O.KIND_SPATIAL, O.KIND_SPATIAL, 0]
+    pws = [1, 2, 4, 1]
+    out = O.admm(Y, ladder, rho=2.0, iters=2000, kinds=kinds, image_w=W, patch_w=pws)
+    rep = O.kkt_report(Y, ladder, out["lam"], 2.0, out["Z"], out["U"], kinds=kinds,
+                       image_w=W, patch_w=pws)
+    assert out["resid"] < 1e-7
+    assert rep["consensus"] < 1e-7
+    assert max(rep["dual_ratio"]) <= 1 + 1e-9
+    assert abs(rep["gap"]) < 2e-7
+    assert np.abs(out["Z"][2]).max() > 0.1          # the space-time scale carries the blob
