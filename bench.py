@@ -195,6 +195,56 @@ def spin_bench(args, iters=20, warm=2, spins=16):
     print(json.dumps(out), flush=True)
 
 
+def video_bench(args, iters=50, warm=5):
+    """Space-time blocks (general block reshape of Sec. 2; the surveillance-video
+    experiment of Sec. 10): a 144 x 176 pixel x 192 frame stand-in as a 25344 x 192
+    matrix, scales 1 x 1 x 1, 4 x 4 x 4, 16 x 16 x 16 and the whole video, default
+    lambda, rho = 1, random cycle spinning. Iterations per second over `iters` after
+    `warm`; the oracle times one iteration."""
+    import torch
+    import paper_1507_08751_amd as msld
+    from synth import video_instance
+    H, W, T = 144, 176, 192
+    M, N = H * W, T
+    Y = video_instance(H, W, T, seed=0)
+    ladder = [(1, 1), (16, 4), (256, 16), (M, N)]
+    kinds = [msld.KIND_BLOCK, msld.KIND_SPATIAL, msld.KIND_SPATIAL, msld.KIND_BLOCK]
+    pws = [1, 4, 16, 1]
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    Yd = torch.from_numpy(Y).to(dev)
+    Z = torch.empty((len(ladder), M, N), dtype=torch.float32, device=dev)
+    solver = msld.Solver(M, N, ladder, rho=1.0, iters=iters, cycle_spin=True, seed=1,
+                         kinds=kinds, image_w=W, patch_w=pws, device=dev)
+    solver.reset(Z)
+    solver.step(Yd, Z, warm)
+    solver.reset(Z)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solver.step(Yd, Z, iters)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    tiers = [msld.TIERS[solver.tier(i)] for i in range(len(ladder))]
+    solver.close()
+    out = {"metric": "space-time ADMM iters/s (144 x 176 x 192 video stand-in)",
+           "value": round(iters / sec, 3), "unit": "iters/s", "n_gpus": 1, "steps": iters,
+           "warmup": warm, "ms_per_step": round(1e3 * sec / iters, 3),
+           "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "video 144x176 pixels x 192 frames as 25344x192, space-time "
+                                  "blocks 1x1x1, 4x4x4, 16x16x16 and the whole video, "
+                                  "rho=1, random cycle spinning", "tiers": tiers}}
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        t0 = time.perf_counter()
+        oracle.admm(Y, ladder, rho=1.0, iters=1, cycle_spin=True, seed=1, kinds=kinds,
+                    image_w=W, patch_w=pws)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": 1 / dt, "unit": "iters/s", "cores": threads,
+                               "kind": "oracle", "sample": f"1 iteration, {dt:.2f} s"}
+    print(json.dumps(out), flush=True)
+
+
 def copy_calibration(nbytes=1 << 30, reps=3):
     """Plain device-to-device copies of nbytes: what FETCH_SIZE / WRITE_SIZE read for
     a kernel that moves a known number of bytes."""
@@ -371,7 +421,8 @@ def main():
     ap.add_argument("--size", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=4096)
-    ap.add_argument("--mode", choices=["iters", "serve", "batch", "copy", "completion", "spin"],
+    ap.add_argument("--mode", choices=["iters", "serve", "batch", "copy", "completion", "spin",
+                                       "video"],
                     default="iters",
                     help="copy: a plain device copy of known size, the calibration run for "
                          "the HBM byte counters")
@@ -399,6 +450,9 @@ def main():
         return
     if args.mode == "spin":
         spin_bench(args)
+        return
+    if args.mode == "video":
+        video_bench(args)
         return
 
     import numpy as np

@@ -91,9 +91,22 @@ typedef enum {
  *                 msld_cycle_shift(shift_seed + j, k, i, ...), j = 0..c-1. Scales
  *                 with mr nc = 1 keep the single random shift. Costs |S| BlockSVTs
  *                 per averaged scale and iteration and two more M x N planes.
- *                 Must be >= 0. */
+ *                 Must be >= 0.
+ *   image_w     : for space-time scales: the rows of Y are the pixels of an
+ *                 H x image_w image in row-major order (row y * image_w + x; M must
+ *                 be H * image_w) and the columns are frames. 0 when unused.
+ *   patch_w[i]  : MSLD_KIND_SPATIAL (2) scales (the general block reshape R_b of
+ *                 Sec. 2, as in the video and DCE experiments of Sec. 10): a block is
+ *                 a ph x pw pixel patch (pw = patch_w[i], ph = block_m[i] / pw) over
+ *                 block_n[i] consecutive frames, reshaped to block_m[i] x block_n[i]
+ *                 (block row dy * pw + dx is pixel (y0 + dy, x0 + dx)); pw must
+ *                 divide block_m[i] and image_w, ph must divide H. Cycle spinning
+ *                 shifts the video cyclically in (y, x, t); the hashed row residue
+ *                 s_r in [0, ph pw) gives (sy, sx) = (s_r / pw, s_r % pw). Other
+ *                 kinds ignore patch_w. */
 #define MSLD_KIND_BLOCK 0
 #define MSLD_KIND_NOISE 1
+#define MSLD_KIND_SPATIAL 2
 typedef struct msld_params {
   int32_t M, N, L;
   int32_t block_m[MSLD_MAX_SCALES];
@@ -108,6 +121,8 @@ typedef struct msld_params {
   uint64_t shift_seed;
   int32_t kind[MSLD_MAX_SCALES];
   int32_t spin_count;
+  int32_t image_w;
+  int32_t patch_w[MSLD_MAX_SCALES];
 } msld_params;
 
 /* Outcome of one msld_solve. primal_resid is r_k of the last iteration run

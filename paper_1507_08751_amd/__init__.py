@@ -38,10 +38,12 @@ class Params(ctypes.Structure):
                 ("tol", ctypes.c_float), ("check_every", ctypes.c_int32),
                 ("cycle_spin", ctypes.c_int32), ("lowrank_min", ctypes.c_int32),
                 ("shift_seed", ctypes.c_uint64), ("kind", ctypes.c_int32 * MAX_SCALES),
-                ("spin_count", ctypes.c_int32)]
+                ("spin_count", ctypes.c_int32), ("image_w", ctypes.c_int32),
+                ("patch_w", ctypes.c_int32 * MAX_SCALES)]
 
 KIND_BLOCK = 0
 KIND_NOISE = 1
+KIND_SPATIAL = 2
 
 
 class Result(ctypes.Structure):
@@ -149,7 +151,8 @@ def cycle_shift(seed, k, i, m, n):
 
 
 def make_params(M, N, ladder, lam=None, rho=1.0, iters=100, tol=0.0, check_every=1,
-                cycle_spin=False, seed=0, lowrank_min=0, kinds=None, spin_count=0) -> Params:
+                cycle_spin=False, seed=0, lowrank_min=0, kinds=None, spin_count=0,
+                image_w=0, patch_w=None) -> Params:
     if len(ladder) < 1 or len(ladder) > MAX_SCALES:
         raise ValueError("ladder must have 1..16 scales")
     p = Params()
@@ -167,6 +170,9 @@ def make_params(M, N, ladder, lam=None, rho=1.0, iters=100, tol=0.0, check_every
     for i in range(len(ladder)):
         p.kind[i] = int(kinds[i]) if kinds is not None else KIND_BLOCK
     p.spin_count = int(spin_count)
+    p.image_w = int(image_w)
+    for i in range(len(ladder)):
+        p.patch_w[i] = int(patch_w[i]) if patch_w is not None else 0
     return p
 
 
@@ -185,7 +191,7 @@ class Solver:
 
     def __init__(self, M, N, ladder, lam=None, rho=1.0, iters=100, tol=0.0, check_every=1,
                  cycle_spin=False, seed=0, device=None, lowrank_min=0, kinds=None,
-                 spin_count=0):
+                 spin_count=0, image_w=0, patch_w=None):
         import torch
         self._torch = torch
         lib = load()
@@ -195,7 +201,8 @@ class Solver:
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
             else torch.device(device)
         self.params = make_params(M, N, ladder, lam, rho, iters, tol, check_every,
-                                  cycle_spin, seed, lowrank_min, kinds, spin_count)
+                                  cycle_spin, seed, lowrank_min, kinds, spin_count, image_w,
+                                  patch_w)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             st = lib.msld_create(ctypes.byref(self.params), _stream_ptr(torch, self.device),
@@ -337,7 +344,7 @@ class Solver:
 class Batch:
     """Many independent decompositions solved together (msld_batch_*). `problems` is a
     list of dicts with keys M, N, ladder and optional lam, rho, iters, tol,
-    check_every, cycle_spin, seed, lowrank_min, kinds, spin_count."""
+    check_every, cycle_spin, seed, lowrank_min, kinds, spin_count, image_w, patch_w."""
 
     def __init__(self, problems, device=None):
         import torch
@@ -353,7 +360,8 @@ class Batch:
                                  pr.get("rho", 1.0), pr.get("iters", 100), pr.get("tol", 0.0),
                                  pr.get("check_every", 1), pr.get("cycle_spin", False),
                                  pr.get("seed", 0), pr.get("lowrank_min", 0),
-                                 pr.get("kinds"), pr.get("spin_count", 0))
+                                 pr.get("kinds"), pr.get("spin_count", 0),
+                                 pr.get("image_w", 0), pr.get("patch_w"))
             self.shapes.append((len(pr["ladder"]), pr["M"], pr["N"]))
         self.n = n
         h = ctypes.c_void_p()

@@ -53,12 +53,21 @@ msld_status validate_params(const msld_params* p) {
   if (p->check_every < 1) return MSLD_EINVAL;
   if (p->cycle_spin != 0 && p->cycle_spin != 1) return MSLD_EINVAL;
   if (p->spin_count < 0) return MSLD_EINVAL;
+  if (p->image_w < 0 || (p->image_w > 0 && p->M % p->image_w)) return MSLD_EINVAL;
   for (int i = 0; i < p->L; ++i) {
     const int m = p->block_m[i], n = p->block_n[i];
     if (m < 1 || n < 1 || p->M % m || p->N % n) return MSLD_EINVAL;
     if (!std::isfinite(p->lambda[i])) return MSLD_EINVAL;
-    if (p->kind[i] != MSLD_KIND_BLOCK && p->kind[i] != MSLD_KIND_NOISE) return MSLD_EINVAL;
+    if (p->kind[i] != MSLD_KIND_BLOCK && p->kind[i] != MSLD_KIND_NOISE &&
+        p->kind[i] != MSLD_KIND_SPATIAL)
+      return MSLD_EINVAL;
     if (p->kind[i] == MSLD_KIND_NOISE && (m != p->M || n != p->N)) return MSLD_EINVAL;
+    if (p->kind[i] == MSLD_KIND_SPATIAL) {
+      // ph x pw patches tile the H x W image, bt = n frames tile the columns
+      const int pw = p->patch_w[i];
+      if (p->image_w == 0 || pw < 1 || m % pw || p->image_w % pw) return MSLD_EINVAL;
+      if ((p->M / p->image_w) % (m / pw)) return MSLD_EINVAL;
+    }
   }
   return MSLD_OK;
 }
@@ -68,11 +77,13 @@ msld_status validate_params(const msld_params* p) {
 bool same_class(const msld_params& a, const msld_params& b) {
   if (a.M != b.M || a.N != b.N || a.L != b.L || a.rho != b.rho || a.max_iters != b.max_iters ||
       a.tol != b.tol || a.check_every != b.check_every || a.cycle_spin != b.cycle_spin ||
-      a.lowrank_min != b.lowrank_min || a.spin_count != b.spin_count)
+      a.lowrank_min != b.lowrank_min || a.spin_count != b.spin_count ||
+      a.image_w != b.image_w)
     return false;
   for (int i = 0; i < a.L; ++i)
     if (a.block_m[i] != b.block_m[i] || a.block_n[i] != b.block_n[i] ||
-        a.lambda[i] != b.lambda[i] || a.kind[i] != b.kind[i])
+        a.lambda[i] != b.lambda[i] || a.kind[i] != b.kind[i] ||
+        (a.kind[i] == MSLD_KIND_SPATIAL && a.patch_w[i] != b.patch_w[i]))
       return false;
   return true;
 }
@@ -111,6 +122,12 @@ msld_status make_plan(const msld_params* p, int ninst, Plan* pl) {
     g.trans = m < n ? 1 : 0;
     g.mb = m < n ? n : m;
     g.nb = m < n ? m : n;
+    if (p->kind[i] == MSLD_KIND_SPATIAL) {
+      g.pw = p->patch_w[i];
+      g.ph = m / g.pw;
+      g.iw = p->image_w;
+      g.ih = IM / p->image_w;
+    }
     const bool noise = p->kind[i] == MSLD_KIND_NOISE;
     const double lam = p->lambda[i] > 0.f ? (double)p->lambda[i]
                        : noise ? lambda_default(IM, N, IM * N, 1)   // the MN x 1 block
@@ -131,7 +148,8 @@ msld_status make_plan(const msld_params* p, int ninst, Plan* pl) {
     const bool lrs = lr_min > 0 && g.nb >= lr_min && lr_small_shape(g.mb, g.nb, &sNB, &sMB, &sP) &&
                      lds_fits(g.mb, g.nb) && lr_small_lds_bytes(sNB, sMB, sP) <= kLdsTierMax;
     // (narrower blocks take it only when the alternative would be the HBM panel tier)
-    const bool lr = !lrs && lr_min > 0 && g.nb >= lr_min &&
+    // (the orthonormalisation keeps p columns of nb in LDS: nb <= 2048)
+    const bool lr = !lrs && lr_min > 0 && g.nb >= lr_min && g.nb <= 2048 &&
                     (g.nb >= 4 * kLRP || (g.nb >= 2 * kLRP && !lds_fits(g.mb, g.nb)));
     int tier;
     if (m == 1 && n == 1) tier = TIER_1X1;
@@ -181,7 +199,8 @@ msld_status make_plan(const msld_params* p, int ninst, Plan* pl) {
     if (tier == TIER_LRS) pl->off_lr[i] = take(4 * (64 + 2 * (size_t)nblk));   // fallback lists
     if (tier == TIER_PANEL) {
       // panel width: two panels of A (mb rows) and W (nb rows) in LDS; 4 <= pw <= 64
-      int pw = (int)(kLdsTierMax / 4 / (2 * ((size_t)(g.mb | 1) + (size_t)(g.nb | 1))));
+      // (the low-rank path only uses the panel layout, padded to a multiple of 8)
+      int pw = lr ? 4 : (int)(kLdsTierMax / 4 / (2 * ((size_t)(g.mb | 1) + (size_t)(g.nb | 1))));
       if (pw > 64) pw = 64;
       pw = pow2_floor(pw < 1 ? 1 : pw);
       while (pw > 4 && 2 * pw > g.nb) pw >>= 1;

@@ -438,7 +438,8 @@ __device__ __forceinline__ void stream_strip(
     if (gc >= N) gc -= N;
     const bool act = rq < rpp;
     const int z = p / g.PI;
-    const int rbase = (p - z * g.PI) * m + sr;   // instance-local row of block row 0
+    const int pl = p - z * g.PI;
+    const int rbase = pl * m + sr;   // instance-local row of block row 0 (contiguous)
     const int64_t zoff = (int64_t)z * g.IM;
     float sabs = 0.f, ssq = 0.f;
     for (int r0 = rq; act && r0 < m; r0 += kU * rpp) {
@@ -450,8 +451,13 @@ __device__ __forceinline__ void stream_strip(
         o[u] = -1;
         v[u] = 0.f;
         if (r < m) {
-          int lr = rbase + r;
-          if (lr >= g.IM) lr -= g.IM;
+          int lr;
+          if (g.pw) {
+            lr = local_row(g, pl, r, sr);
+          } else {
+            lr = rbase + r;
+            if (lr >= g.IM) lr -= g.IM;
+          }
           o[u] = (zoff + lr) * N + gc;
           v[u] = Zin[o[u]] + (R ? R[o[u]] : 0.f);
         }

@@ -30,6 +30,7 @@ namespace msld {
 
 static constexpr float kCertMargin = 2e-3f;    // relative margin on tau^2 for test (i)
 static constexpr float kCouplingTol = 1e-5f;   // test (ii): ||U_L^T E||_F <= tol ||B||_F
+static constexpr size_t kJacobiLdsMax = 150 * 1024;   // LDS stage of k_lr_jacobi
 
 __device__ __forceinline__ int wrap_add2(int base, int off, int mod) {
   int v = base + off;
@@ -324,6 +325,137 @@ __global__ void __launch_bounds__(256) k_lr_jacobi(float* C, const float* X, flo
 #pragma unroll
     for (int j = 0; j < P; ++j) v += x[j * nb + row] * W[l * LDW + j];
     vr[e] = v;
+  }
+}
+
+// Tall blocks, whose C does not fit the LDS stage of k_lr_jacobi: the same outputs
+// from the p x p Gram K = C^T C accumulated in float64 over row chunks and its
+// eigen-decomposition K = W diag(lambda) W^T by cyclic two-sided Jacobi in float64:
+// A_f = C W (orthogonal columns), sigma_l = sqrt(lambda_l), V_r = X W.
+template <int P>
+__global__ void __launch_bounds__(256) k_lr_gram64(const float* C, int mb, int rows,
+                                                   double* part, int64_t part_stride) {
+  static_assert(P * P == 256, "one Gram entry per thread");
+  __shared__ float tile[64][P + 1];
+  const int slot = blockIdx.y, ch = blockIdx.x;
+  const float* c = C + (int64_t)slot * mb * P;
+  const int r0 = ch * rows;
+  const int r1 = min(mb, r0 + rows);
+  const int tid = threadIdx.x;
+  const int a = tid / P, b = tid - (tid / P) * P;
+  double acc = 0.0;
+  for (int t0 = r0; t0 < r1; t0 += 64) {
+    for (int e = tid; e < 64 * P; e += 256) {
+      const int j = e / 64, r = e - j * 64;
+      tile[r][j] = (t0 + r < r1) ? c[(int64_t)j * mb + t0 + r] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int r = 0; r < 64; ++r) acc += (double)tile[r][a] * (double)tile[r][b];
+    __syncthreads();
+  }
+  part[(int64_t)slot * part_stride + (int64_t)ch * 256 + tid] = acc;
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) k_lr_eig64(const double* part, int chunks,
+                                                  int64_t part_stride, const float* X,
+                                                  float* Vr, float* sig, float* Wf, int nb) {
+  __shared__ double K[P][P + 1];
+  __shared__ double V[P][P + 1];
+  __shared__ double cs[P / 2], sn[P / 2];
+  __shared__ int s_rot;
+  const int slot = blockIdx.x, tid = threadIdx.x;
+  const double* pp = part + (int64_t)slot * part_stride;
+  if (tid < P * P) {
+    double k = 0.0;
+    for (int ch = 0; ch < chunks; ++ch) k += pp[(int64_t)ch * 256 + tid];
+    K[tid / P][tid % P] = k;
+    V[tid / P][tid % P] = (tid / P == tid % P) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int sw = 0; sw < 40; ++sw) {
+    if (tid == 0) s_rot = 0;
+    __syncthreads();
+    for (int rd = 0; rd < P - 1; ++rd) {
+      if (tid < P / 2) {
+        int p, q;
+        lr_pair(rd, tid, P, &p, &q);
+        const double app = K[p][p], aqq = K[q][q], apq = K[p][q];
+        double c = 1.0, s = 0.0;
+        if (apq != 0.0 && fabs(apq) > 1e-14 * sqrt(fabs(app) * fabs(aqq))) {
+          const double th = (aqq - app) / (2.0 * apq);
+          const double t = fabs(th) > 1e150 ? 0.5 / th
+                                            : copysign(1.0, th) / (fabs(th) + sqrt(th * th + 1.0));
+          c = 1.0 / sqrt(t * t + 1.0);
+          s = t * c;
+          s_rot = 1;
+        }
+        cs[tid] = c;
+        sn[tid] = s;
+      }
+      __syncthreads();
+      if (tid < (P / 2) * P) {   // K <- K J and V <- V J (columns p, q of every pair)
+        const int k = tid / P, r = tid - (tid / P) * P;
+        int p, q;
+        lr_pair(rd, k, P, &p, &q);
+        const double c = cs[k], s = sn[k];
+        const double kp = K[r][p], kq = K[r][q];
+        K[r][p] = c * kp - s * kq;
+        K[r][q] = s * kp + c * kq;
+        const double vp = V[r][p], vq = V[r][q];
+        V[r][p] = c * vp - s * vq;
+        V[r][q] = s * vp + c * vq;
+      }
+      __syncthreads();
+      if (tid < (P / 2) * P) {   // K <- J^T K (rows p, q)
+        const int k = tid / P, col = tid - (tid / P) * P;
+        int p, q;
+        lr_pair(rd, k, P, &p, &q);
+        const double c = cs[k], s = sn[k];
+        const double kp = K[p][col], kq = K[q][col];
+        K[p][col] = c * kp - s * kq;
+        K[q][col] = s * kp + c * kq;
+      }
+      __syncthreads();
+    }
+    const int rot = s_rot;
+    __syncthreads();
+    if (!rot) break;
+  }
+  if (tid < P) sig[slot * P + tid] = (float)sqrt(fmax(K[tid][tid], 0.0));
+  float* wf = Wf + (int64_t)slot * P * P;
+  if (tid < P * P) wf[tid] = (float)V[tid / P][tid % P];   // row j, column l: W_jl
+  const float* x = X + (int64_t)slot * nb * P;
+  float* vr = Vr + (int64_t)slot * nb * P;
+  for (int e = tid; e < nb * P; e += blockDim.x) {
+    const int l = e / nb, row = e - l * nb;
+    double v = 0.0;
+#pragma unroll
+    for (int j = 0; j < P; ++j) v += (double)x[j * nb + row] * V[j][l];
+    vr[e] = (float)v;
+  }
+}
+
+// C <- C W per slot (A_f of the tall path), one row per thread.
+template <int P>
+__global__ void __launch_bounds__(256) k_lr_rot_c(float* C, const float* Wf, int mb) {
+  __shared__ float w[P * P];
+  const int slot = blockIdx.y;
+  for (int e = threadIdx.x; e < P * P; e += blockDim.x) w[e] = Wf[(int64_t)slot * P * P + e];
+  __syncthreads();
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= mb) return;
+  float* c = C + (int64_t)slot * mb * P;
+  float v[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) v[j] = c[(int64_t)j * mb + r];
+#pragma unroll
+  for (int l = 0; l < P; ++l) {
+    float o = 0.f;
+#pragma unroll
+    for (int j = 0; j < P; ++j) o += v[j] * w[j * P + l];
+    c[(int64_t)l * mb + r] = o;
   }
 }
 
@@ -810,9 +942,29 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
     // p columns wide and its residual orthogonality enters the coupling test
     const float rr_tol = 5.9604645e-8f * sqrtf((float)mb);
     (void)jtol;
-    hipLaunchKernelGGL(k_lr_jacobi<P>, dim3(count), dim3(256), lds, st, w.lrC, w.lrX, w.lrV,
-                       w.lrSig, mb, nb, rr_tol, 40);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (lds <= kJacobiLdsMax) {
+      hipLaunchKernelGGL(k_lr_jacobi<P>, dim3(count), dim3(256), lds, st, w.lrC, w.lrX, w.lrV,
+                         w.lrSig, mb, nb, rr_tol, 40);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    } else {
+      // tall blocks: float64 Gram of C in row chunks (partials in lrQ, free here), its
+      // eigen-decomposition (rotation into lrP, free here), then A_f = C W
+      const int64_t pstride = (int64_t)nb * nb / 2;   // doubles per slot in lrQ
+      int chunks = (mb + 511) / 512;
+      if (chunks > pstride / 256) chunks = (int)(pstride / 256);
+      const int rows = (mb + chunks - 1) / chunks;
+      chunks = (mb + rows - 1) / rows;
+      double* part = reinterpret_cast<double*>(w.lrQ);
+      hipLaunchKernelGGL(k_lr_gram64<P>, dim3(chunks, count), dim3(256), 0, st, w.lrC, mb, rows,
+                         part, pstride);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_lr_eig64<P>, dim3(count), dim3(256), 0, st, part, chunks, pstride,
+                         w.lrX, w.lrV, w.lrSig, w.lrP, nb);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_lr_rot_c<P>, dim3((mb + 255) / 256, count), dim3(256), 0, st, w.lrC,
+                         w.lrP, mb);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
   }
   // coupling: T = A_f^T B (p x nb)
   if ((e = gemm(h, rocblas_operation_transpose, rocblas_operation_none, P, nb, mb, w.lrC, mb, sC,

@@ -75,15 +75,36 @@ struct ScaleGeom {
   int trans;      // 1 if the logical block B is the transpose of the stored block
   int mb, nb;     // logical block rows / columns, mb >= nb (B = block or block^T)
   int IM, PI, NI; // rows and block rows per instance, number of instances
+  int pw, ph;     // space-time blocks: pixel patch (0: contiguous row blocks)
+  int iw, ih;     // image whose pixels are the rows of an instance (space-time only)
 };
+
+// Instance-local row of row i of the block-row pl under a row shift sr. Contiguous
+// partitions: row pl m + i + sr with cyclic wrap. Space-time partitions: pixel
+// (dy, dx) = (i / pw, i % pw) of patch pl (patches in row-major order over the
+// image), under the patch shift (sy, sx) = (sr / pw, sr % pw), with wrap in y and x.
+__device__ inline int local_row(const ScaleGeom& g, int pl, int i, int sr) {
+  if (g.pw) {
+    const int qx = g.iw / g.pw;
+    const int py = pl / qx, px = pl - py * qx;
+    const int sy = sr / g.pw, sx = sr - sy * g.pw;
+    const int dy = i / g.pw, dx = i - dy * g.pw;
+    int y = py * g.ph + dy + sy;
+    if (y >= g.ih) y -= g.ih;
+    int x = px * g.pw + dx + sx;
+    if (x >= g.iw) x -= g.iw;
+    return y * g.iw + x;
+  }
+  int local = pl * g.m + i + sr;
+  if (local >= g.IM) local -= g.IM;
+  return local;
+}
 
 // Stacked row of row i of block row p under a row shift sr: the shift wraps inside
 // the block's own instance (Shift_s of Sec. 9 applied per instance).
 __device__ inline int grow(const ScaleGeom& g, int p, int i, int sr) {
   const int z = p / g.PI;
-  int local = (p - z * g.PI) * g.m + i + sr;
-  if (local >= g.IM) local -= g.IM;
-  return z * g.IM + local;
+  return z * g.IM + local_row(g, p - z * g.PI, i, sr);
 }
 
 __device__ inline int gcol(const ScaleGeom& g, int q, int j, int sc) {

@@ -170,6 +170,32 @@ def completion_instance(M=1682, N=943, groups=23, observed=0.063, seed=0, noise=
     return np.where(mask, Y, 0.0).astype(np.float32), mask, T
 
 
+def video_instance(H=144, W=176, T=192, objects=6, radius=6.0, seed=0, noise=0.01):
+    """Stand-in for a surveillance video as a (H W) x T matrix (pixel y W + x per row,
+    one frame per column): a static background image whose brightness drifts slowly
+    (rank 1), `objects` Gaussian blobs of the given radius moving on straight lines
+    with wrap (local in space and time), and noise.
+
+    Returns Y as float32."""
+    rng = np.random.default_rng(seed)
+    bg = 0.5 + 0.5 * rng.random((H, W))
+    t = np.arange(T)
+    gain = 1.0 + 0.1 * np.sin(2 * np.pi * t / T)
+    V = bg[:, :, None] * gain[None, None, :]
+    yy, xx = np.mgrid[0:H, 0:W]
+    for _ in range(objects):
+        y0, x0 = rng.random() * H, rng.random() * W
+        vy, vx = rng.uniform(-1.0, 1.0, size=2)
+        amp = rng.uniform(0.3, 0.8)
+        for f in range(T):
+            cy, cx = (y0 + vy * f) % H, (x0 + vx * f) % W
+            dy = np.minimum(np.abs(yy - cy), H - np.abs(yy - cy))
+            dx = np.minimum(np.abs(xx - cx), W - np.abs(xx - cx))
+            V[:, :, f] += amp * np.exp(-(dy ** 2 + dx ** 2) / (2 * radius ** 2))
+    Y = V.reshape(H * W, T) + noise * rng.standard_normal((H * W, T))
+    return Y.astype(np.float32)
+
+
 def lcm_blocks(ladder):
     a, b = 1, 1
     for (m, n) in ladder:

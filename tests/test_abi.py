@@ -32,9 +32,9 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layout_matches_header():
     # int32 M,N,L; 16+16 int32; 16 float; rho,max_iters,tol,check_every,cycle_spin,lowrank_min;
-    # 4 pad; u64 seed; 16 int32 kinds; int32 spin_count; 4 tail pad
-    assert ctypes.sizeof(msld.Params) == 4 * 3 + 4 * 48 + 4 * 6 + 4 + 8 + 4 * 16 + 4 + 4
-    assert msld.Params.spin_count.offset == ctypes.sizeof(msld.Params) - 8
+    # 4 pad; u64 seed; 16 int32 kinds; int32 spin_count, image_w; 16 int32 patch_w
+    assert ctypes.sizeof(msld.Params) == 4 * 3 + 4 * 48 + 4 * 6 + 4 + 8 + 4 * 16 + 8 + 4 * 16
+    assert msld.Params.patch_w.offset == ctypes.sizeof(msld.Params) - 64
     assert msld.Params.shift_seed.offset % 8 == 0
     assert ctypes.sizeof(msld.Result) == 4 + 4 + 8 + 8 * 8 * 16
 
@@ -73,6 +73,11 @@ def test_host_default_lambda_matches_oracle():
     dict(M=64, N=64, ladder=[(4, 4)], kinds=[1]),          # noise scale needs the full block
     dict(M=64, N=64, ladder=[(64, 64)], kinds=[2]),         # unknown kind
     dict(M=64, N=64, ladder=[(4, 4)], cycle_spin=True, spin_count=-1),
+    dict(M=64, N=64, ladder=[(16, 4)], kinds=[2], patch_w=[4]),               # no image_w
+    dict(M=64, N=64, ladder=[(16, 4)], kinds=[2], image_w=8, patch_w=[3]),    # pw !| m
+    dict(M=64, N=64, ladder=[(16, 4)], kinds=[2], image_w=8, patch_w=[16]),   # pw !| W
+    dict(M=64, N=64, ladder=[(8, 4)], kinds=[2], image_w=16, patch_w=[1]),    # ph !| H
+    dict(M=64, N=64, ladder=[(4, 4)], image_w=7),                             # W !| M
 ])
 def test_invalid_params_rejected_on_host(bad):
     bad = dict(bad)
@@ -116,3 +121,12 @@ def test_averaged_spinning_adds_two_planes_per_block_scale():
         msld.workspace_bytes(M, N, lad2, cycle_spin=True) >= 2 * 4 * M * N
     # without cycle spinning the count is ignored
     assert msld.workspace_bytes(M, N, lad, spin_count=4) == msld.workspace_bytes(M, N, lad)
+
+
+def test_spacetime_scales_plan():
+    """Space-time scales: 4 x 4 and 2 x 8 pixel patches of an 8 x 8 image (rows) over 4
+    frames, and space-only 8 x 8 patches over all frames."""
+    M, N = 64, 16
+    lad = [(1, 1), (16, 4), (16, 4), (64, 16)]
+    assert msld.workspace_bytes(M, N, lad, kinds=[0, 2, 2, 2], image_w=8,
+                                patch_w=[1, 4, 8, 8]) > 0

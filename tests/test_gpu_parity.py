@@ -122,6 +122,15 @@ def _bsvt_case(lib, M, N, m, n, lowrank_min, tier=None):
     solver.close()
 
 
+# blocks too tall for the LDS stage of the reduced Jacobi (float64 Gram route)
+TALL_CASES = [(4096, 128, 4096, 64), (96, 6144, 96, 6144), (25344, 192, 25344, 192)]
+
+
+@pytest.mark.parametrize("M,N,m,n", TALL_CASES)
+def test_bsvt_call_parity_tall(lib, M, N, m, n):
+    _bsvt_case(lib, M, N, m, n, 0, "lowrank")
+
+
 @pytest.mark.parametrize("M,N,m,n", [(512, 512, 128, 128), (1024, 1024, 512, 512),
                                      (256, 1024, 256, 512), (384, 256, 64, 64)])
 def test_lowrank_path_certifies_low_rank_blocks(lib, M, N, m, n):
@@ -541,3 +550,114 @@ def test_averaged_spinning_stacked_matches_alone(lib):
         print(f"stacked averaged spin instance {j}: {err:.1e}", flush=True)
         assert err <= 1e-5, j
     b.close()
+
+
+# ------------------------------------------------------------ space-time blocks
+def st_tiles(A, W, ph, pw, bt):
+    """Blocks (ph pw) x bt of the unshifted space-time partition of A (rows = pixels of
+    an image of width W, columns = frames)."""
+    M, N = A.shape
+    H = M // W
+    return A.reshape(H // ph, ph, W // pw, pw, N // bt, bt).transpose(0, 2, 4, 1, 3, 5) \
+        .reshape(-1, ph * pw, bt)
+
+
+def st_untiles(B, M, N, W, ph, pw, bt):
+    H = M // W
+    return B.reshape(H // ph, W // pw, N // bt, ph, pw, bt).transpose(0, 3, 1, 4, 2, 5) \
+        .reshape(M, N)
+
+
+# (H, W, frames, ph, pw, bt): register, LDS, transposed LDS, fused low-rank, batched
+# low-rank (whole image) tiers; square and rectangular patches
+SPACETIME_CASES = [
+    (16, 24, 32, 2, 2, 2),
+    (16, 24, 32, 2, 2, 4),
+    (16, 24, 32, 4, 4, 4),
+    (12, 20, 40, 4, 4, 40),
+    (16, 24, 32, 8, 8, 32),
+    (32, 32, 32, 8, 4, 32),
+    (32, 32, 16, 16, 16, 16),
+    (16, 16, 64, 16, 16, 64),
+]
+
+
+@pytest.mark.parametrize("H,W,T,ph,pw,bt", SPACETIME_CASES)
+def test_bsvt_call_parity_spacetime(lib, H, W, T, ph, pw, bt):
+    """One BlockSVT over a space-time partition (the general reshape of Sec. 2) with a
+    video shift, against the oracle (1e-4)."""
+    M, N, m = H * W, T, ph * pw
+    seed = H * 7 + W * 3 + ph * 11 + bt
+    rng = np.random.default_rng(seed)
+    nblk = (H // ph) * (W // pw) * (T // bt)
+    amp = np.where(rng.random(nblk) < 0.5, rng.uniform(1, 3, nblk), 0.0)
+    B = amp[:, None, None] * (rng.standard_normal((nblk, m, 1)) @ rng.standard_normal((nblk, 1, bt)))
+    V = (st_untiles(B, M, N, W, ph, pw, bt) + 0.05 * rng.standard_normal((M, N))).astype(np.float32)
+    s = (int(rng.integers(0, m)), int(rng.integers(0, bt)))
+    sig = np.linalg.svd(st_tiles(O.st_shift(V.astype(np.float64), W, pw, s), W, ph, pw, bt),
+                        compute_uv=False)
+    tau = float(np.quantile(sig[:, 0], 0.5)) * 0.9 + 1e-3
+    ref = O.scale_bsvt(V.astype(np.float64), m, bt, tau, s, geo=(W, pw))
+    solver = lib.Solver(M, N, [(m, bt)], iters=1, kinds=[lib.KIND_SPATIAL], image_w=W,
+                        patch_w=[pw])
+    print(f"spacetime {H}x{W}x{T} block {ph}x{pw}x{bt} tier={lib.TIERS[solver.tier(0)]} "
+          f"shift={s} tau={tau:.3f}", flush=True)
+    Z = solver.bsvt(0, torch.from_numpy(V).cuda(), tau, s)
+    torch.cuda.synchronize()
+    err = rel_err(Z.cpu().numpy(), ref, np.linalg.norm(V))
+    print(f"  rel err {err:.2e}, blocks above tau {int((sig[:, 0] > tau).sum())}/{len(sig)}",
+          flush=True)
+    assert err <= 1e-4
+    solver.close()
+
+
+@pytest.mark.parametrize("cycle_spin", [False, True])
+def test_admm_spacetime_parity(lib, cycle_spin):
+    """ADMM with space-time scales (2 x 2 x 2, 4 x 4 x 4, space-only 8 x 8 patches, the
+    whole video) on a 16 x 16 x 16 video stand-in, against the oracle (1e-3)."""
+    from synth import video_instance
+    H = W = 16
+    T = 16
+    Y = video_instance(H, W, T, objects=2, radius=2.0, seed=3)
+    M, N = H * W, T
+    ladder = [(1, 1), (4, 2), (16, 4), (64, T), (M, N)]
+    kinds = [0, 2, 2, 2, 0]
+    pws = [1, 2, 4, 8, 1]
+    iters = 40
+    ref = O.admm(Y.astype(np.float64), ladder, rho=1.0, iters=iters, cycle_spin=cycle_spin,
+                 seed=17, kinds=kinds, image_w=W, patch_w=pws)
+    solver = lib.Solver(M, N, ladder, rho=1.0, iters=iters, cycle_spin=cycle_spin, seed=17,
+                        kinds=kinds, image_w=W, patch_w=pws)
+    Z, info = solver.solve(torch.from_numpy(Y).cuda())
+    torch.cuda.synchronize()
+    Zg = Z.cpu().numpy()
+    errs = [rel_err(Zg[i], ref["Z"][i], np.linalg.norm(Y)) for i in range(len(ladder))]
+    print(f"spacetime admm cs={cycle_spin}: errs {['%.1e' % e for e in errs]} norms "
+          f"{['%.2f' % np.linalg.norm(z) for z in ref['Z']]}", flush=True)
+    assert max(errs) <= 1e-3
+    solver.close()
+
+
+def test_video_workload_parity(lib):
+    """The surveillance-video stand-in at full size (144 x 176 pixels x 192 frames,
+    scales 1 x 1 x 1, 4 x 4 x 4, 16 x 16 x 16 and the whole video, cycle spinning):
+    3 iterations against the oracle (1e-3)."""
+    from synth import video_instance
+    H, W, T = 144, 176, 192
+    Y = video_instance(H, W, T, seed=0)
+    M, N = H * W, T
+    ladder = [(1, 1), (16, 4), (256, 16), (M, N)]
+    kinds = [0, 2, 2, 0]
+    pws = [1, 4, 16, 1]
+    ref = O.admm(Y.astype(np.float64), ladder, rho=1.0, iters=3, cycle_spin=True, seed=5,
+                 kinds=kinds, image_w=W, patch_w=pws)
+    solver = lib.Solver(M, N, ladder, rho=1.0, iters=3, cycle_spin=True, seed=5, kinds=kinds,
+                        image_w=W, patch_w=pws)
+    print(f"video tiers {[lib.TIERS[solver.tier(i)] for i in range(len(ladder))]}", flush=True)
+    Z, info = solver.solve(torch.from_numpy(Y).cuda())
+    torch.cuda.synchronize()
+    Zg = Z.cpu().numpy()
+    errs = [rel_err(Zg[i], ref["Z"][i], np.linalg.norm(Y)) for i in range(len(ladder))]
+    print(f"video 25344x192: errs {['%.1e' % e for e in errs]}", flush=True)
+    assert max(errs) <= 1e-3
+    solver.close()
