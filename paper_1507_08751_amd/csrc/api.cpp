@@ -153,7 +153,7 @@ msld_status make_plan(const msld_params* p, int ninst, Plan* pl) {
                     (g.nb >= 4 * kLRP || (g.nb >= 2 * kLRP && !lds_fits(g.mb, g.nb)));
     int tier;
     if (m == 1 && n == 1) tier = TIER_1X1;
-    else if (m == n && (m == 2 || m == 4 || m == 8)) tier = TIER_REG;
+    else if (reg_tier_shape(m, n)) tier = TIER_REG;
     else if (lrs) tier = TIER_LRS;
     else if (!lr && lds_fits(g.mb, g.nb)) tier = TIER_LDS;
     else tier = TIER_PANEL;

@@ -278,16 +278,20 @@ hipError_t launch_inc_active(int* k, const int* active, int n, hipStream_t st) {
   return hipGetLastError();
 }
 
-// ------------------------------------------------------- register tier (B <= 8)
+// ------------------------------------------------------- register tier (small blocks)
 // Register tier, live blocks only: one lane per block of the live list built by the
-// stream pass. The block's V is read back from D' = -V (written by the stream pass),
-// decomposed by cyclic one-sided Jacobi in registers, thresholded (eq:svt) and
-// written back with the dual update.
-template <int B>
+// stream pass. The block's V (SM x SN as stored) is read back from D' = -V (written by
+// the stream pass), decomposed by cyclic one-sided Jacobi in registers on the shorter
+// side (LN columns of length LM: the block, or its transpose when SM < SN),
+// thresholded (eq:svt) and written back with the dual update.
+template <int SM, int SN>
 __global__ void __launch_bounds__(256) k_tiny_live(
     float* __restrict__ Zout, float* __restrict__ Dout, ScaleGeom g, float tau,
     ShiftSpec sh, float jtol, int max_sweeps, const int* __restrict__ live_count,
     const int* __restrict__ live_list, unsigned long long* __restrict__ stats) {
+  constexpr bool TR = SM < SN;
+  constexpr int LM = TR ? SN : SM;
+  constexpr int LN = TR ? SM : SN;
   const int N = g.N, Q = g.Q;
   const int count = *live_count;
   const int stride = gridDim.x * blockDim.x;
@@ -296,36 +300,38 @@ __global__ void __launch_bounds__(256) k_tiny_live(
     const int p = b / Q;
     const int q = b - p * Q;
     int sr, sc;
-    block_shift(sh, p / g.PI, B, B, &sr, &sc);
-    int rows[B], cols[B];
+    block_shift(sh, p / g.PI, SM, SN, &sr, &sc);
+    int rows[SM], cols[SN];
 #pragma unroll
-    for (int i = 0; i < B; ++i) {
-      rows[i] = grow(g, p, i, sr);
-      cols[i] = gcol(g, q, i, sc);
-    }
-    float a[B][B], v0[B][B];
+    for (int i = 0; i < SM; ++i) rows[i] = grow(g, p, i, sr);
 #pragma unroll
-    for (int i = 0; i < B; ++i)
+    for (int j = 0; j < SN; ++j) cols[j] = gcol(g, q, j, sc);
+    // a[i][j] (LM x LN) is the logical block: stored (i, j), or (j, i) when transposed
+    float a[LM][LN], v0[LM][LN];
 #pragma unroll
-      for (int j = 0; j < B; ++j) {
-        v0[i][j] = -Dout[(int64_t)rows[i] * N + cols[j]];
+    for (int i = 0; i < LM; ++i)
+#pragma unroll
+      for (int j = 0; j < LN; ++j) {
+        const int r = TR ? rows[j] : rows[i];
+        const int c = TR ? cols[i] : cols[j];
+        v0[i][j] = -Dout[(int64_t)r * N + c];
         a[i][j] = v0[i][j];
       }
-    float w[B][B];
+    float w[LN][LN];
 #pragma unroll
-    for (int i = 0; i < B; ++i)
+    for (int i = 0; i < LN; ++i)
 #pragma unroll
-      for (int j = 0; j < B; ++j) w[i][j] = (i == j) ? 1.f : 0.f;
+      for (int j = 0; j < LN; ++j) w[i][j] = (i == j) ? 1.f : 0.f;
     int sweeps = 0;
     for (int swp = 0; swp < max_sweeps; ++swp) {
       bool rot = false;
 #pragma unroll
-      for (int pp = 0; pp < B - 1; ++pp)
+      for (int pp = 0; pp < LN - 1; ++pp)
 #pragma unroll
-        for (int qq = pp + 1; qq < B; ++qq) {
+        for (int qq = pp + 1; qq < LN; ++qq) {
           float al = 0.f, be = 0.f, ga = 0.f;
 #pragma unroll
-          for (int i = 0; i < B; ++i) {
+          for (int i = 0; i < LM; ++i) {
             al += a[i][pp] * a[i][pp];
             be += a[i][qq] * a[i][qq];
             ga += a[i][pp] * a[i][qq];
@@ -339,10 +345,13 @@ __global__ void __launch_bounds__(256) k_tiny_live(
             const float c = 1.f / sqrtf(1.f + t * t);
             const float s = c * t;
 #pragma unroll
-            for (int i = 0; i < B; ++i) {
+            for (int i = 0; i < LM; ++i) {
               const float x = a[i][pp], y = a[i][qq];
               a[i][pp] = c * x - s * y;
               a[i][qq] = s * x + c * y;
+            }
+#pragma unroll
+            for (int i = 0; i < LN; ++i) {
               const float u = w[i][pp], v = w[i][qq];
               w[i][pp] = c * u - s * v;
               w[i][qq] = s * u + c * v;
@@ -352,27 +361,29 @@ __global__ void __launch_bounds__(256) k_tiny_live(
       ++sweeps;
       if (!rot) break;
     }
-    float g[B];
+    float gn[LN];
     int rank = 0;
 #pragma unroll
-    for (int j = 0; j < B; ++j) {
+    for (int j = 0; j < LN; ++j) {
       float s2 = 0.f;
 #pragma unroll
-      for (int i = 0; i < B; ++i) s2 += a[i][j] * a[i][j];
+      for (int i = 0; i < LM; ++i) s2 += a[i][j] * a[i][j];
       const float sig = sqrtf(s2);
-      g[j] = sig > tau ? 1.f - tau / sig : 0.f;
-      rank += g[j] > 0.f;
+      gn[j] = sig > tau ? 1.f - tau / sig : 0.f;
+      rank += gn[j] > 0.f;
     }
     // rank 0: the stream pass already wrote Z' = 0, D' = -V
     if (rank > 0) {
 #pragma unroll
-      for (int i = 0; i < B; ++i)
+      for (int i = 0; i < LM; ++i)
 #pragma unroll
-        for (int c2 = 0; c2 < B; ++c2) {
+        for (int c2 = 0; c2 < LN; ++c2) {
           float z = 0.f;
 #pragma unroll
-          for (int j = 0; j < B; ++j) z += g[j] * a[i][j] * w[c2][j];
-          const int64_t o = (int64_t)rows[i] * N + cols[c2];
+          for (int j = 0; j < LN; ++j) z += gn[j] * a[i][j] * w[c2][j];
+          const int r = TR ? rows[c2] : rows[i];
+          const int c = TR ? cols[i] : cols[c2];
+          const int64_t o = (int64_t)r * N + c;
           Zout[o] = z;
           Dout[o] = 2.f * z - v0[i][c2];
         }
@@ -381,6 +392,22 @@ __global__ void __launch_bounds__(256) k_tiny_live(
     atomicAdd(&stats[1], (unsigned long long)sweeps);
     atomicAdd(&stats[2], (unsigned long long)rank);
   }
+}
+
+template <int SM, int SN>
+static bool tiny_launch(int blocks, const ScaleGeom& g, float* Zout, float* Dout, float tau,
+                        const ShiftSpec& sh, float jtol, int max_sweeps, const ScaleWork& w,
+                        hipStream_t st) {
+  if (g.m != SM || g.n != SN) return false;
+  hipLaunchKernelGGL((k_tiny_live<SM, SN>), dim3(blocks), dim3(256), 0, st, Zout, Dout, g, tau,
+                     sh, jtol, max_sweeps, w.live_count, w.live_list, w.stats);
+  return true;
+}
+
+bool reg_tier_shape(int m, int n) {
+  const int lo = m < n ? m : n, hi = m < n ? n : m;
+  if (lo == hi) return lo == 2 || lo == 4 || lo == 8;
+  return (lo == 2 && (hi == 4 || hi == 8 || hi == 16)) || (lo == 4 && (hi == 8 || hi == 16));
 }
 
 // ---------------------------------------------------------------- stream pass
@@ -1206,15 +1233,21 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
     MSLD_EV(2);
     int blocks = num_cus * 8;
     if (blocks * 256 > nblk) blocks = (nblk + 255) / 256;
-    if (g.m == 2)
-      hipLaunchKernelGGL(k_tiny_live<2>, dim3(blocks), dim3(256), 0, st, Zout, Dout, g, tau, sh,
-                         jtol, max_sweeps, w.live_count, w.live_list, w.stats);
-    else if (g.m == 4)
-      hipLaunchKernelGGL(k_tiny_live<4>, dim3(blocks), dim3(256), 0, st, Zout, Dout, g, tau, sh,
-                         jtol, max_sweeps, w.live_count, w.live_list, w.stats);
-    else
-      hipLaunchKernelGGL(k_tiny_live<8>, dim3(blocks), dim3(256), 0, st, Zout, Dout, g, tau, sh,
-                         jtol, max_sweeps, w.live_count, w.live_list, w.stats);
+    const bool ok =
+        tiny_launch<2, 2>(blocks, g, Zout, Dout, tau, sh, jtol, max_sweeps, w, st) ||
+        tiny_launch<4, 4>(blocks, g, Zout, Dout, tau, sh, jtol, max_sweeps, w, st) ||
+        tiny_launch<8, 8>(blocks, g, Zout, Dout, tau, sh, jtol, max_sweeps, w, st) ||
+        tiny_launch<4, 2>(blocks, g, Zout, Dout, tau, sh, jtol, max_sweeps, w, st) ||
+        tiny_launch<2, 4>(blocks, g, Zout, Dout, tau, sh, jtol, max_sweeps, w, st) ||
+        tiny_launch<8, 2>(blocks, g, Zout, Dout, tau, sh, jtol, max_sweeps, w, st) ||
+        tiny_launch<2, 8>(blocks, g, Zout, Dout, tau, sh, jtol, max_sweeps, w, st) ||
+        tiny_launch<16, 2>(blocks, g, Zout, Dout, tau, sh, jtol, max_sweeps, w, st) ||
+        tiny_launch<2, 16>(blocks, g, Zout, Dout, tau, sh, jtol, max_sweeps, w, st) ||
+        tiny_launch<8, 4>(blocks, g, Zout, Dout, tau, sh, jtol, max_sweeps, w, st) ||
+        tiny_launch<4, 8>(blocks, g, Zout, Dout, tau, sh, jtol, max_sweeps, w, st) ||
+        tiny_launch<16, 4>(blocks, g, Zout, Dout, tau, sh, jtol, max_sweeps, w, st) ||
+        tiny_launch<4, 16>(blocks, g, Zout, Dout, tau, sh, jtol, max_sweeps, w, st);
+    if (!ok) return hipErrorInvalidValue;   // the plan only picks shapes listed here
     if ((e = hipGetLastError()) != hipSuccess) return e;
     MSLD_EV(3); MSLD_EV(4);
     return hipSuccess;

@@ -201,6 +201,7 @@ hipError_t launch_stream_all(const StreamAll& a, size_t lds, const float* Z, con
                              float* D, const ShiftSpec& sh, hipStream_t st);
 float stream_tau2lim(const ScaleGeom& g, float tau);
 hipError_t launch_fill(float* p, float v, size_t count, hipStream_t st);
+bool reg_tier_shape(int m, int n);   // block shapes of the register tier
 hipError_t launch_spin_acc(float* acc, const float* zs, size_t n, size_t inst_elems,
                            const int* iactive, hipStream_t st);
 hipError_t launch_spin_finish(float* Z, float* D, const float* R, const float* acc, float inv,

@@ -61,6 +61,16 @@ BSVT_CASES = [
     (48, 160, 16, 32),
     (160, 48, 32, 16),
     (120, 90, 6, 5),
+    (64, 96, 16, 4),         # rectangular register-tier blocks, both orientations
+    (96, 64, 4, 16),
+    (64, 64, 8, 2),
+    (64, 64, 2, 8),
+    (96, 96, 16, 2),
+    (96, 96, 2, 16),
+    (64, 96, 8, 4),
+    (96, 64, 4, 8),
+    (96, 96, 4, 2),
+    (96, 96, 2, 4),
     (64, 96, 1, 32),
     (96, 64, 32, 1),
     (256, 256, 256, 256),
