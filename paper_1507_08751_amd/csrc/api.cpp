@@ -189,11 +189,23 @@ msld_status make_plan(const msld_params* p, int ninst, Plan* pl) {
       sp.spb = (n + ws - 1) / ws;
       sp.spr = g.Q * sp.spb;
     }
+    sp.rowbound = (sp.whole || sp.ws >= 8) ? 1 : 0;
+    sp.cst = sp.spb;
+    sp.rch = m;
+    if (!sp.rowbound) {
+      // Frobenius bound only: strips of up to 256 columns and 128 rows (coalesced rows,
+      // and enough strips per block to spread a tall block over the chip)
+      sp.ws = n < 256 ? n : 256;
+      sp.cst = (n + sp.ws - 1) / sp.ws;
+      sp.rch = 128;
+      sp.spb = sp.cst * ((m + sp.rch - 1) / sp.rch);
+      sp.spr = g.Q * sp.spb;
+    }
     if (stream_lds_bytes(m, sp) > kLdsTierMax) return MSLD_EINVAL;
     pl->off_count[i] = take(4);
     pl->off_list[i] = take(4 * (size_t)nblk);
     if (!sp.whole) {
-      pl->off_rowp[i] = take(4 * (size_t)nblk * sp.spb * m);
+      if (sp.rowbound) pl->off_rowp[i] = take(4 * (size_t)nblk * sp.spb * m);
       pl->off_frop[i] = take(4 * (size_t)nblk * sp.spb);
     }
     if (tier == TIER_LRS) pl->off_lr[i] = take(4 * (64 + 2 * (size_t)nblk));   // fallback lists
@@ -218,6 +230,7 @@ msld_status make_plan(const msld_params* p, int ninst, Plan* pl) {
         const size_t per = 3 * nb2 + 4 * (size_t)g.nb * kLRP + (size_t)g.mb * kLRP +
                            (size_t)kLRP * g.nb + 3 * kLRP + 8 + (size_t)g.nb * (tn + 1);
         pl->off_lr[i] = take(4 * ((size_t)nblk * per + (size_t)g.nb * kLRP + 64 + 3 * nblk));
+        if (g.mb >= 4 * g.nb) pl->off_split[i] = take(4 * kSplitFloats);
         if (!lds_fits(g.mb, g.nb)) {
           // polar fallback buffers for a chunk of failed certificates (<= 256 MiB)
           const size_t pper = 3 * (size_t)g.mb * g.nb + 4 * nb2 + 4;
@@ -374,7 +387,8 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
       w.live_count = reinterpret_cast<int*>(s->arena + pl.off_count[i]);
       w.live_list = reinterpret_cast<int*>(s->arena + pl.off_list[i]);
       if (!pl.sp[i].whole) {
-        w.rowpart = reinterpret_cast<float*>(s->arena + pl.off_rowp[i]);
+        w.rowpart = pl.sp[i].rowbound ? reinterpret_cast<float*>(s->arena + pl.off_rowp[i])
+                                      : nullptr;
         w.fropart = reinterpret_cast<float*>(s->arena + pl.off_frop[i]);
       }
     }
@@ -410,6 +424,8 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
         w.lrScal = f; f += slots * 8;
         w.lrRow = f; f += slots * (size_t)g.nb * (((size_t)g.nb + 63) / 64 + 1);
         w.lrOm = f; f += (size_t)g.nb * kLRP;
+        w.lrSplit = pl.off_split[i] ? reinterpret_cast<float*>(s->arena + pl.off_split[i])
+                                    : nullptr;
         w.lrCount = reinterpret_cast<int*>(f);
         w.lrFall = w.lrCount + 64;
         w.lds_fallback = lds_fits(g.mb, g.nb) ? 1 : 0;

@@ -430,7 +430,7 @@ __device__ __forceinline__ void stream_strip(
   if (!inst_active(sh, p / g.PI)) return;   // uniform: the strip lies in one instance
   int sr, sc;
   block_shift(sh, p / g.PI, m, n, &sr, &sc);
-  int col0, w, q0 = 0, nq = 1, part = 0;
+  int col0, w, q0 = 0, nq = 1, part = 0, rlo = 0, rhi = m;
   if (sp.whole) {
     q0 = j * sp.kb;
     nq = min(sp.kb, Q - q0);
@@ -439,15 +439,18 @@ __device__ __forceinline__ void stream_strip(
   } else {
     q0 = j / sp.spb;
     part = j - q0 * sp.spb;
-    col0 = q0 * n + part * sp.ws;
-    w = min(sp.ws, n - part * sp.ws);
+    const int rpart = part / sp.cst, cpart = part - (part / sp.cst) * sp.cst;
+    col0 = q0 * n + cpart * sp.ws;
+    w = min(sp.ws, n - cpart * sp.ws);
+    rlo = rpart * sp.rch;
+    rhi = min(m, rlo + sp.rch);
   }
   // The tile keeps |v| rounded up to bfloat16 (only the bound reads it, and a
   // rounded-up magnitude keeps it an upper bound); the column |.| and squared sums
   // are accumulated from the float values while they stream through.
   const int ldt = w + 1;
   unsigned short* tile = reinterpret_cast<unsigned short*>(smem);   // m x ldt
-  float* pcs = smem + ((m * ldt + 1) >> 1);  // 256 partial column |.| sums
+  float* pcs = smem + (sp.rowbound ? ((m * ldt + 1) >> 1) : 0);  // 256 partial column |.| sums
   float* pcq = pcs + 256;                   // 256 partial column squares
   float* cs = pcq + 256;                    // w column sums
   float* cq = cs + sp.ws + 1;               // w column squares
@@ -469,7 +472,7 @@ __device__ __forceinline__ void stream_strip(
     const int rbase = pl * m + sr;   // instance-local row of block row 0 (contiguous)
     const int64_t zoff = (int64_t)z * g.IM;
     float sabs = 0.f, ssq = 0.f;
-    for (int r0 = rq; act && r0 < m; r0 += kU * rpp) {
+    for (int r0 = rlo + rq; act && r0 < rhi; r0 += kU * rpp) {
       float v[kU];
       int64_t o[kU];
 #pragma unroll
@@ -477,7 +480,7 @@ __device__ __forceinline__ void stream_strip(
         const int r = r0 + u * rpp;
         o[u] = -1;
         v[u] = 0.f;
-        if (r < m) {
+        if (r < rhi) {
           int lr;
           if (g.pw) {
             lr = local_row(g, pl, r, sr);
@@ -499,7 +502,7 @@ __device__ __forceinline__ void stream_strip(
           // for NaN, infinity: the block then always counts as live)
           const unsigned ab = __float_as_uint(a);
           const unsigned bits = ab > 0x7F7F0000u ? 0x7F80u : (ab + 0xFFFFu) >> 16;
-          tile[(r0 + u * rpp) * ldt + c] = (unsigned short)bits;
+          if (sp.rowbound) tile[(r0 + u * rpp) * ldt + c] = (unsigned short)bits;
           Zout[o[u]] = 0.f;
           Dout[o[u]] = -v[u];
         }
@@ -524,7 +527,7 @@ __device__ __forceinline__ void stream_strip(
   __syncthreads();
   // weighted row sums per (row, block segment)
   const int segw = sp.whole ? n : w;
-  const int npairs = m * nq;
+  const int npairs = sp.rowbound ? m * nq : 0;
   for (int e = tid; e < npairs; e += 256) {
     const int s = e / m;
     const int r = e - s * m;
@@ -544,7 +547,7 @@ __device__ __forceinline__ void stream_strip(
     if (tid < nq) {
       float fro = 0.f;
       for (int c = 0; c < n; ++c) fro += cq[tid * n + c];
-      const float bnd = __uint_as_float(smax[tid]);
+      const float bnd = sp.rowbound ? __uint_as_float(smax[tid]) : fro;
       if (fminf(bnd, fro) > tau2lim) {
         const int slot = atomicAdd(live_count, 1);
         live_list[slot] = p * Q + q0 + tid;
@@ -608,7 +611,8 @@ __global__ void __launch_bounds__(256) k_bound_reduce(ScaleGeom g, StreamPlan sp
   if (!inst_active(sh, (blk / g.Q) / g.PI)) return;
   const int m = g.m;
   float mx = 0.f;
-  for (int r = threadIdx.x; r < m; r += 256) {
+  if (!sp.rowbound) mx = __int_as_float(0x7f800000);   // Frobenius bound alone
+  for (int r = threadIdx.x; sp.rowbound && r < m; r += 256) {
     float s = 0.f;
     for (int t = 0; t < sp.spb; ++t) s += rowpart[((int64_t)blk * sp.spb + t) * m + r];
     mx = fmaxf(mx, s);
@@ -1096,8 +1100,10 @@ size_t lds_tier_bytes(int mb, int nb) {
 }
 
 size_t stream_lds_bytes(int m, const StreamPlan& sp) {
-  // bfloat16 tile (m x (ws + 1)), then 512 + 2 (ws + 1) + ws + 1 floats
-  return (size_t)4 * (((size_t)m * (sp.ws + 1) + 1) / 2 + 512 + 2 * (sp.ws + 1) + sp.ws + 1);
+  // bfloat16 tile (m x (ws + 1), only for the row bound), then 512 + 2 (ws + 1) + ws + 1
+  // floats
+  const size_t tile = sp.rowbound ? ((size_t)m * (sp.ws + 1) + 1) / 2 : 0;
+  return (size_t)4 * (tile + 512 + 2 * (sp.ws + 1) + sp.ws + 1);
 }
 
 #define MSLD_EV(i)                                                    \

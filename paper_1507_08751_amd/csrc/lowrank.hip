@@ -860,6 +860,102 @@ __global__ void __launch_bounds__(256) k_lr_rebuild(float* __restrict__ Zout,
   }
 }
 
+// ------------------------------------------------ split-K products of tall blocks
+// C = A^T B for blocks with many more rows than columns (A: K x Ma, B: K x Nb, both
+// column-major with leading dimension K, slot strides sa, sb), when too few output
+// tiles exist to fill the chip: the rows are split into `chunks` ranges of KC rows,
+// each workgroup forms one 64 x 64 output tile of one range, and a second kernel
+// sums the ranges in a fixed order into C (leading dimension ldc, slot stride sc).
+__global__ void __launch_bounds__(256) k_tall_atb_part(const float* __restrict__ A, int64_t sa,
+                                                       int Ma, const float* __restrict__ B,
+                                                       int64_t sb, int Nb, int K, int KC,
+                                                       float* __restrict__ part, int chunks) {
+  __shared__ float As[32][64 + 4];
+  __shared__ float Bs[32][64 + 4];
+  const int tilesN = (Nb + 63) / 64;
+  const int ti = blockIdx.x / tilesN, tj = blockIdx.x - (blockIdx.x / tilesN) * tilesN;
+  const int ch = blockIdx.y, slot = blockIdx.z;
+  const float* a = A + (int64_t)slot * sa;
+  const float* b = B + (int64_t)slot * sb;
+  const int k0 = ch * KC, k1 = min(K, k0 + KC);
+  const int t = threadIdx.x;
+  const int ty = t / 16, tx = t - (t / 16) * 16;
+  float acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.f;
+  for (int kb = k0; kb < k1; kb += 32) {
+    const int kk = t & 31;
+    const int k = kb + kk;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int c = (t >> 5) + 8 * u;
+      const int ia = ti * 64 + c, jb = tj * 64 + c;
+      As[kk][c] = (k < k1 && ia < Ma) ? a[(int64_t)ia * K + k] : 0.f;
+      Bs[kk][c] = (k < k1 && jb < Nb) ? b[(int64_t)jb * K + k] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int q = 0; q < 32; ++q) {
+      const float4 x = *reinterpret_cast<const float4*>(&As[q][ty * 4]);
+      const float4 y = *reinterpret_cast<const float4*>(&Bs[q][tx * 4]);
+      const float xa[4] = {x.x, x.y, x.z, x.w}, yb[4] = {y.x, y.y, y.z, y.w};
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] += xa[u] * yb[v];
+    }
+    __syncthreads();
+  }
+  float* o = part + ((int64_t)slot * chunks + ch) * Ma * Nb;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = ti * 64 + ty * 4 + u, j = tj * 64 + tx * 4 + v;
+      if (i < Ma && j < Nb) o[(int64_t)j * Ma + i] = acc[u][v];
+    }
+}
+
+__global__ void __launch_bounds__(256) k_tall_atb_sum(const float* __restrict__ part, int Ma,
+                                                      int Nb, int chunks, float* __restrict__ C,
+                                                      int ldc, int64_t sc) {
+  const int slot = blockIdx.y;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= Ma * Nb) return;
+  const int j = e / Ma, i = e - (e / Ma) * Ma;
+  const float* pp = part + (int64_t)slot * chunks * Ma * Nb;
+  float s = 0.f;
+  for (int c = 0; c < chunks; ++c) s += pp[(int64_t)c * Ma * Nb + e];
+  C[(int64_t)slot * sc + (int64_t)j * ldc + i] = s;
+}
+
+// Split-K A^T B when it pays (tall blocks, few output tiles, partials fit `cap`
+// floats); returns false (nothing launched) otherwise.
+static bool tall_atb(const float* A, int64_t sa, int Ma, const float* B, int64_t sb, int Nb,
+                     int K, float* C, int ldc, int64_t sc, int count, float* part, size_t cap,
+                     hipStream_t st, hipError_t* err) {
+  *err = hipSuccess;
+  if (!part || K < 4 * Nb) return false;
+  const int tiles = ((Ma + 63) / 64) * ((Nb + 63) / 64);
+  if ((int64_t)count * tiles >= 256) return false;
+  int chunks = (K + 255) / 256;
+  if (chunks > 64) chunks = 64;
+  while (chunks > 1 && (size_t)count * chunks * Ma * Nb > cap) --chunks;
+  if (chunks < 2) return false;
+  int KC = (K + chunks - 1) / chunks;
+  KC = (KC + 31) / 32 * 32;
+  chunks = (K + KC - 1) / KC;
+  hipLaunchKernelGGL(k_tall_atb_part, dim3(tiles, chunks, count), dim3(256), 0, st, A, sa, Ma, B,
+                     sb, Nb, K, KC, part, chunks);
+  if ((*err = hipGetLastError()) != hipSuccess) return true;
+  hipLaunchKernelGGL(k_tall_atb_sum, dim3((Ma * Nb + 255) / 256, count), dim3(256), 0, st, part,
+                     Ma, Nb, chunks, C, ldc, sc);
+  *err = hipGetLastError();
+  return true;
+}
+
 // ------------------------------------------------------------------ driver
 hipError_t batched_sgemm(void* blas, bool ta, bool tb, int m, int n, int k, const float* A,
                          int lda, int64_t sa, const float* B, int ldb, int64_t sb, float* C,
@@ -895,9 +991,14 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
   hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, w.lrCount, 2);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // G = B^T B
-  if ((e = gemm(h, rocblas_operation_transpose, rocblas_operation_none, nb, nb, mb, w.pA, mb, sB,
-                w.pA, mb, sB, w.lrG, nb, sG, count)) != hipSuccess)
+  if (!tall_atb(w.pA, sB, nb, w.pA, sB, nb, mb, w.lrG, nb, sG, count, w.lrSplit, kSplitFloats,
+                st, &e)) {
+    if ((e = gemm(h, rocblas_operation_transpose, rocblas_operation_none, nb, nb, mb, w.pA, mb,
+                  sB, w.pA, mb, sB, w.lrG, nb, sG, count)) != hipSuccess)
+      return e;
+  } else if (e != hipSuccess) {
     return e;
+  }
   hipLaunchKernelGGL(k_lr_trace, dim3(count), dim3(256), 0, st, w.lrG, nb, sG, w.lrScal, 0);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // subspace iteration: X0 = orth(G Omega), then X <- orth(G (G X)) three times
@@ -967,9 +1068,14 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
     }
   }
   // coupling: T = A_f^T B (p x nb)
-  if ((e = gemm(h, rocblas_operation_transpose, rocblas_operation_none, P, nb, mb, w.lrC, mb, sC,
-                w.pA, mb, sB, w.lrT, P, (int64_t)P * nb, count)) != hipSuccess)
+  if (!tall_atb(w.lrC, sC, P, w.pA, sB, nb, mb, w.lrT, P, (int64_t)P * nb, count, w.lrSplit,
+                kSplitFloats, st, &e)) {
+    if ((e = gemm(h, rocblas_operation_transpose, rocblas_operation_none, P, nb, mb, w.lrC, mb,
+                  sC, w.pA, mb, sB, w.lrT, P, (int64_t)P * nb, count)) != hipSuccess)
+      return e;
+  } else if (e != hipSuccess) {
     return e;
+  }
   float* mask = w.lrSig + (size_t)w.slots * P;       // second third of the sigma buffer
   float* dmask = w.lrSig + 2 * (size_t)w.slots * P;  // last third
   hipLaunchKernelGGL(k_lr_coupling<P>, dim3(count), dim3(256), 0, st, w.lrT, w.lrSig, w.lrV, nb,

@@ -64,6 +64,7 @@ __device__ inline bool inst_active(const ShiftSpec& s, int z) {
 // ------------------------------------------------------------------ plans
 enum Tier { TIER_1X1 = 0, TIER_REG = 1, TIER_LDS = 2, TIER_PANEL = 3, TIER_LRS = 5,
             TIER_FRO = 6 };
+constexpr size_t kSplitFloats = (size_t)4 << 20;   // split-K partials of tall blocks
 constexpr int kFroParts = 512;   // partial sums per instance of the noise scale's norm
 
 // Geometry of one scale's partition. M counts the rows of all stacked instances
@@ -149,6 +150,7 @@ struct ScaleWork {
   float* lrScal;        // [slots][8]
   float* lrRow;         // [slots][nb / 64 + 1][nb] row partials of |E^T E| and row sums
   float* lrOm;          // [nb*p] probe matrix
+  float* lrSplit;       // [kSplitFloats] split-K partials of tall blocks (null: none)
   int* lrCount;         // [4] device counters: fallback, undecided
   int* lrFall;          // [3 slots] block ids, then slot indices, of failed certificates;
                         // then the slots left undecided by the stage-0 bound
@@ -175,6 +177,11 @@ struct StreamPlan {
   int spb;       // strips per block (whole == 0)
   int kb;        // blocks per strip (whole == 1)
   int spr;       // strips per block row
+  int rowbound;  // 1: row-weighted bound of Sec. 8 and Frobenius; 0: Frobenius only (blocks
+                 // so tall that strips are under 8 columns: the row partials would be as
+                 // large as the block)
+  int cst;       // column strips per block (whole == 0); spb = cst * row chunks
+  int rch;       // rows per strip (m unless rowbound == 0)
 };
 
 // Stream pass of every decomposed scale in one launch (kernel argument; plane i of a

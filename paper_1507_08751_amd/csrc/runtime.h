@@ -43,6 +43,7 @@ struct Plan {
       off_pW[MSLD_MAX_SCALES], off_pflag[MSLD_MAX_SCALES], off_pg[MSLD_MAX_SCALES],
       off_lr[MSLD_MAX_SCALES], off_pl[MSLD_MAX_SCALES];
   int pl_cap[MSLD_MAX_SCALES];   // polar fallback chunk (0: none)
+  size_t off_split[MSLD_MAX_SCALES];   // split-K partials (tall low-rank blocks; 0: none)
   // averaged cycle spinning: shifts per iteration (0: one random shift), whether the
   // set is every shift, and the accumulator + scratch planes
   int spin[MSLD_MAX_SCALES];

@@ -133,7 +133,8 @@ def _bsvt_case(lib, M, N, m, n, lowrank_min, tier=None):
 
 
 # blocks too tall for the LDS stage of the reduced Jacobi (float64 Gram route)
-TALL_CASES = [(4096, 128, 4096, 64), (96, 6144, 96, 6144), (25344, 192, 25344, 192)]
+TALL_CASES = [(4096, 128, 4096, 64), (96, 6144, 96, 6144), (25344, 192, 25344, 192),
+              (65536, 64, 65536, 64)]
 
 
 @pytest.mark.parametrize("M,N,m,n", TALL_CASES)
