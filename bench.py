@@ -68,12 +68,14 @@ def measured_traffic():
 
 
 def stream_roofline(prof, tiers, M, N, K):
-    """Roofline of the dominant kernel, the stream pass of all decomposed scales (one
-    launch per iteration), from its HIP-event times; and of the consensus pass."""
+    """Roofline of the dominant kernel, k_stream_all, the stream pass: one launch per
+    decomposed scale and iteration, each moving 16 B per element of the M x N plane;
+    the HIP events bracket the pass, so the average launch time is the pass time over
+    the launches. And of the consensus pass."""
     idx = [i for i, t in enumerate(tiers) if t != "1x1"]
-    launches = K
+    launches = K * len(idx)
     avg_ms = prof["stream_ms"] / max(1, launches)
-    nbytes = STREAM_BYTES_PER_ELEM * M * N * len(idx)
+    nbytes = STREAM_BYTES_PER_ELEM * M * N
     gbs = nbytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": measured_traffic(),

@@ -192,6 +192,13 @@ msld_status make_plan(const msld_params* p, int ninst, Plan* pl) {
     sp.rowbound = (sp.whole || sp.ws >= 8) ? 1 : 0;
     sp.cst = sp.spb;
     sp.rch = m;
+    sp.align = 0;
+    if (!sp.whole && sp.rowbound && N % 32 == 0 && sp.ws % 32 == 0) {
+      sp.align = 1;
+      sp.cst = (n + sp.ws - 1) / sp.ws + 1;
+      sp.spb = sp.cst;
+      sp.spr = g.Q * sp.spb;
+    }
     if (!sp.rowbound) {
       // Frobenius bound only: strips of up to 256 columns and 128 rows (coalesced rows,
       // and enough strips per block to spread a tall block over the chip)
@@ -454,7 +461,6 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
     StreamAll& a = s->sall;
     std::memset(&a, 0, sizeof(a));
     a.plane = plane_elems(s);
-    size_t lds = 0;
     for (int i = 0; i < p->L; ++i) {
       // (averaged scales run their own stream pass per shift)
       if (pl.tier[i] == TIER_1X1 || pl.tier[i] == TIER_FRO || pl.spin[i]) continue;
@@ -468,10 +474,8 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
       d.rowpart = s->work[i].rowpart;
       d.fropart = s->work[i].fropart;
       a.first[a.n + 1] = a.first[a.n] + pl.geom[i].P * pl.sp[i].spr;
-      lds = std::max(lds, stream_lds_bytes(pl.geom[i].m, pl.sp[i]));
       ++a.n;
     }
-    s->sall_lds = lds;
   }
   *out = s;
   return MSLD_OK;
@@ -554,7 +558,7 @@ msld_status iterate_once(msld_solver* s, const float* d_Y, int64_t ldY, float* d
     sh.ik = stacked ? s->d_k : nullptr;
     sh.iactive = stacked ? s->d_active : nullptr;
     if (ev) MSLD_TRY(s, hipEventRecord(ev[2], s->st));
-    if (s->sall.n > 0) MSLD_TRY(s, launch_stream_all(s->sall, s->sall_lds, d_Z, R, Dn, sh, s->st));
+    if (s->sall.n > 0) MSLD_TRY(s, launch_stream_all(s->sall, d_Z, R, Dn, sh, s->st));
     if (ev) MSLD_TRY(s, hipEventRecord(ev[3], s->st));
   }
   MSLD_TRY(s, hipEventRecord(s->ev_fork, s->st));

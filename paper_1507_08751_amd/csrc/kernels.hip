@@ -440,10 +440,28 @@ __device__ __forceinline__ void stream_strip(
     q0 = j / sp.spb;
     part = j - q0 * sp.spb;
     const int rpart = part / sp.cst, cpart = part - (part / sp.cst) * sp.cst;
-    col0 = q0 * n + cpart * sp.ws;
-    w = min(sp.ws, n - cpart * sp.ws);
+    int start = cpart * sp.ws;
+    if (sp.align) {
+      // a = columns before the block's first 32-column boundary (global columns,
+      // N a multiple of 32, so the boundaries survive the wrap)
+      const int a = (32 - (q0 * n + sc) % 32) % 32;
+      start = cpart == 0 ? 0 : (a == 0 ? cpart * sp.ws : a + (cpart - 1) * sp.ws);
+      const int end = cpart == 0 ? (a == 0 ? sp.ws : a) : start + sp.ws;
+      w = min(end, n) - start;
+    } else {
+      w = min(sp.ws, n - start);
+    }
+    col0 = q0 * n + start;
     rlo = rpart * sp.rch;
     rhi = min(m, rlo + sp.rch);
+    if (w <= 0) {
+      // empty strip (aligned layout): zero partials for the bound
+      const int64_t blk = (int64_t)p * Q + q0;
+      if (sp.rowbound)
+        for (int r = threadIdx.x; r < m; r += 256) rowpart[(blk * sp.spb + part) * m + r] = 0.f;
+      if (threadIdx.x == 0) fropart[blk * sp.spb + part] = 0.f;
+      return;
+    }
   }
   // The tile keeps |v| rounded up to bfloat16 (only the bound reads it, and a
   // rounded-up magnitude keeps it an upper bound); the column |.| and squared sums
@@ -591,14 +609,28 @@ __global__ void k_zero_counts(StreamAll a) {
   if ((int)threadIdx.x < a.n) *a.s[threadIdx.x].live_count = 0;
 }
 
-hipError_t launch_stream_all(const StreamAll& a, size_t lds, const float* Z, const float* R,
-                             float* D, const ShiftSpec& sh, hipStream_t st) {
+size_t stream_lds_bytes(int m, const StreamPlan& sp);
+
+// One launch per scale on the caller's stream, each with its own LDS size (a shared
+// launch would reserve the largest tile for every workgroup and halve the occupancy
+// of the small-block scales).
+hipError_t launch_stream_all(const StreamAll& a, const float* Z, const float* R, float* D,
+                             const ShiftSpec& sh, hipStream_t st) {
   if (a.n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(64), 0, st, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_stream_all, dim3(a.first[a.n]), dim3(256), lds, st, a, Z, R, D, sh);
-  return hipGetLastError();
+  for (int i = 0; i < a.n; ++i) {
+    StreamAll b = a;
+    b.n = 1;
+    b.s[0] = a.s[i];
+    b.first[0] = 0;
+    b.first[1] = a.first[i + 1] - a.first[i];
+    const size_t lds = stream_lds_bytes(a.s[i].g.m, a.s[i].sp);
+    hipLaunchKernelGGL(k_stream_all, dim3(b.first[1]), dim3(256), lds, st, b, Z, R, D, sh);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // Completes the bound of blocks split over several strips (fixed summation order).
@@ -613,8 +645,18 @@ __global__ void __launch_bounds__(256) k_bound_reduce(ScaleGeom g, StreamPlan sp
   float mx = 0.f;
   if (!sp.rowbound) mx = __int_as_float(0x7f800000);   // Frobenius bound alone
   for (int r = threadIdx.x; sp.rowbound && r < m; r += 256) {
+    // the strip partials of one row, 8 loads in flight (the sum order is fixed)
+    const float* rp = rowpart + (int64_t)blk * sp.spb * m + r;
     float s = 0.f;
-    for (int t = 0; t < sp.spb; ++t) s += rowpart[((int64_t)blk * sp.spb + t) * m + r];
+    int t = 0;
+    for (; t + 8 <= sp.spb; t += 8) {
+      float x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = rp[(int64_t)(t + u) * m];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += x[u];
+    }
+    for (; t < sp.spb; ++t) s += rp[(int64_t)t * m];
     mx = fmaxf(mx, s);
   }
   red[threadIdx.x] = mx;

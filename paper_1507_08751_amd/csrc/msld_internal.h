@@ -182,6 +182,9 @@ struct StreamPlan {
                  // large as the block)
   int cst;       // column strips per block (whole == 0); spb = cst * row chunks
   int rch;       // rows per strip (m unless rowbound == 0)
+  int align;     // 1: strip edges on global 32-column (128-byte) boundaries: the first
+                 // strip of a block takes the columns up to the first boundary, so
+                 // cst = ceil(n / ws) + 1 and a strip may be empty
 };
 
 // Stream pass of every decomposed scale in one launch (kernel argument; plane i of a
@@ -204,8 +207,8 @@ struct StreamAll {
 };
 
 // ----------------------------------------------------------- launchers (kernels.hip)
-hipError_t launch_stream_all(const StreamAll& a, size_t lds, const float* Z, const float* R,
-                             float* D, const ShiftSpec& sh, hipStream_t st);
+hipError_t launch_stream_all(const StreamAll& a, const float* Z, const float* R, float* D,
+                             const ShiftSpec& sh, hipStream_t st);
 float stream_tau2lim(const ScaleGeom& g, float tau);
 hipError_t launch_fill(float* p, float v, size_t count, hipStream_t st);
 bool reg_tier_shape(int m, int n);   // block shapes of the register tier

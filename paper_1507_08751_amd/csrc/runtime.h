@@ -79,7 +79,6 @@ struct msld_solver {
   msld::StreamAll sall;   // the stream pass of all decomposed scales (one launch)
   const uint8_t* mask;    // observed-entry mask (caller-owned, device) or null
   int64_t ldmask;
-  size_t sall_lds;
   int ninst;
   int k;              // next iteration (single instance; stacked instances use d_k)
   int cur;            // which D buffer holds the current D_i
