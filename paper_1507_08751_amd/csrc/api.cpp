@@ -236,7 +236,7 @@ msld_status make_plan(const msld_params* p, int ninst, Plan* pl) {
         const size_t tn = ((size_t)g.nb + 63) / 64;
         const size_t per = 3 * nb2 + 4 * (size_t)g.nb * kLRP + (size_t)g.mb * kLRP +
                            (size_t)kLRP * g.nb + 3 * kLRP + 8 + (size_t)g.nb * (tn + 1);
-        pl->off_lr[i] = take(4 * ((size_t)nblk * per + (size_t)g.nb * kLRP + 64 + 3 * nblk));
+        pl->off_lr[i] = take(4 * ((size_t)nblk * per + (size_t)g.nb * kLRP + 64 + 4 * nblk));
         if (g.mb >= 4 * g.nb) pl->off_split[i] = take(4 * kSplitFloats);
         if (!lds_fits(g.mb, g.nb)) {
           // polar fallback buffers for a chunk of failed certificates (<= 256 MiB)

@@ -15,6 +15,8 @@
 //        lambda_max(E^T E) <= min(||E^T E||_F, Collatz-Wielandt bound of |E^T E| with the
 //        vector of its row sums), then tr * ||(E^T E / tr)^k||_F^(1/k), k = 2, 8, and
 //   (ii) ||U_L^T E_L||_F is below a small fraction of ||B||_F.
+// The bound of (i) is tried first with tr(E^T E) = ||B||_F^2 - sum ||B v_l||^2, which
+// needs no E^T E; only the slots it leaves undecided get E^T E and the finer bounds.
 // Then B0 = U_L S_L V_L^T + (I - U_L U_L^T) E_L decouples, SVT(B0) = Z (columns of L
 // below tau threshold to zero), and since the proximal map is non-expansive
 // ||SVT(B) - Z||_F <= ||B - B0||_F = ||U_L^T E_L||_F.
@@ -553,12 +555,12 @@ __global__ void __launch_bounds__(256) k_lr_q(const float* Wg, const float* Vr, 
 template <int P>
 __global__ void __launch_bounds__(256) k_lr_ge(const float* G, const float* Qm, const float* Vr,
                                                const float* mask, float* Pm, int nb,
-                                               float* part, float* rowpart) {
+                                               float* part, float* rowpart, const int* list) {
   __shared__ float qi[64][P + 1], vi[64][P + 1], qj[64][P + 1], vj[64][P + 1];
   __shared__ float mk[P];
   __shared__ float red[8];
   __shared__ float rs[4][64];
-  const int slot = blockIdx.y;
+  const int slot = list ? list[blockIdx.y] : blockIdx.y;
   const int tn = (nb + 63) / 64;
   const int ti = blockIdx.x % tn, tj = blockIdx.x / tn;
   const int i0 = ti * 64, j0 = tj * 64;
@@ -620,8 +622,8 @@ __global__ void __launch_bounds__(256) k_lr_ge(const float* G, const float* Qm, 
 // k_lr_rsum: r_i = sum over tile columns of the row partials of k_lr_ge (slice tn);
 // k_lr_cwy: per 64 x 64 tile, partial y_i over its columns (slices 0..tn-1);
 // k_lr_cwmax: y_i, the ratio, its maximum; scal[4] = min(||M||_F, bound) / tr(M).
-__global__ void __launch_bounds__(256) k_lr_rsum(float* rowpart, int nb) {
-  const int slot = blockIdx.y;
+__global__ void __launch_bounds__(256) k_lr_rsum(float* rowpart, int nb, const int* list) {
+  const int slot = list ? list[blockIdx.y] : blockIdx.y;
   const int tn = (nb + 63) / 64;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nb) return;
@@ -631,10 +633,11 @@ __global__ void __launch_bounds__(256) k_lr_rsum(float* rowpart, int nb) {
   rp[(int64_t)tn * nb + i] = v;
 }
 
-__global__ void __launch_bounds__(256) k_lr_cwy(const float* Pm, float* rowpart, int nb) {
+__global__ void __launch_bounds__(256) k_lr_cwy(const float* Pm, float* rowpart, int nb,
+                                                const int* list) {
   __shared__ float rj[64];
   __shared__ float ys[4][64];
-  const int slot = blockIdx.y;
+  const int slot = list ? list[blockIdx.y] : blockIdx.y;
   const int tn = (nb + 63) / 64;
   const int ti = blockIdx.x % tn, tj = blockIdx.x / tn;
   const int i0 = ti * 64, j0 = tj * 64;
@@ -656,9 +659,10 @@ __global__ void __launch_bounds__(256) k_lr_cwy(const float* Pm, float* rowpart,
   if (tid < 64 && i < nb) rp[(int64_t)tj * nb + i] = ys[0][il] + ys[1][il] + ys[2][il] + ys[3][il];
 }
 
-__global__ void __launch_bounds__(256) k_lr_cwmax(const float* rowpart, int nb, float* scal) {
+__global__ void __launch_bounds__(256) k_lr_cwmax(const float* rowpart, int nb, float* scal,
+                                                  const int* list) {
   __shared__ float red[8];
-  const int slot = blockIdx.x;
+  const int slot = list ? list[blockIdx.x] : blockIdx.x;
   const int tn = (nb + 63) / 64;
   const float* rp = rowpart + (int64_t)slot * nb * (tn + 1);
   float best = 0.f;
@@ -684,9 +688,11 @@ __global__ void __launch_bounds__(256) k_lr_cwmax(const float* rowpart, int nb, 
 
 // Reduce the per-tile partials of k_lr_ge in a fixed order: scal[2] = tr(E^T E),
 // scal[4] = ||E^T E||_F / tr(E^T E) (stage-0 bound factor).
-__global__ void k_lr_ge_reduce(const float* part, int tiles, int count, float* scal) {
-  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
-  if (slot >= count) return;
+__global__ void k_lr_ge_reduce(const float* part, int tiles, int count, float* scal,
+                               const int* list) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= count) return;
+  const int slot = list ? list[idx] : idx;
   float tr = 0.f, f2 = 0.f;
   for (int t = 0; t < tiles; ++t) {
     tr += part[((int64_t)slot * tiles + t) * 2];
@@ -765,17 +771,45 @@ __device__ __forceinline__ void lr_fallback(int slot, int slots, int* pflag, int
   fall[slots + f] = slot;
 }
 
-__global__ void k_lr_decide(int count, int slots, float* scal, const float* sig, float tau,
-                            int* pflag, int* counts, int* fall, const int* live_list,
-                            unsigned long long* stats, int stage, int power) {
-  // stage 0 walks all slots and lists the undecided ones at fall[2 slots ..];
-  // later stages walk that list
+__global__ void k_lr_decide(int count, int slots, float* scal, const float* sig,
+                            const float* dmask, float tau, int* pflag, int* counts, int* fall,
+                            const int* live_list, unsigned long long* stats, int stage,
+                            int power) {
+  // stage -1 walks all slots and lists the undecided ones at fall[3 slots ..]; stage 0
+  // walks that list and lists its undecided ones at fall[2 slots ..]; later stages walk
+  // that second list
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= count) return;
-  const int slot = stage == 0 ? idx : fall[2 * slots + idx];
+  const int slot = stage < 0 ? idx : stage == 0 ? fall[3 * slots + idx] : fall[2 * slots + idx];
   const float* sc = scal + slot * 8;
   const float trG = sc[0], c2 = sc[1], trE = sc[2];
   const float lim = tau * tau * (1.f - kCertMargin);
+  if (stage < 0) {
+    pflag[4 * slot + 3] = 0;
+    const bool c_ok = c2 <= kCouplingTol * kCouplingTol * trG && isfinite(c2) && isfinite(trG);
+    if (!c_ok) {
+      lr_fallback(slot, slots, pflag, counts, fall, live_list, scal, -1.f);
+      atomicAdd(&stats[4], 1ull);
+      return;
+    }
+    // lambda_max(E^T E) <= tr(E^T E) = ||B||_F^2 - sum_l ||B v_l||^2 over the deflated
+    // and split-off directions (V_r orthonormal), with a rounding allowance of 1e-4
+    // ||B||_F^2 for the cancellation; the same 2 x 2 split bound as stage 0
+    float s2 = 0.f;
+    for (int l = 0; l < 16; ++l) {
+      const float sg = sig[slot * 16 + l];
+      if (dmask[slot * 16 + l] > 0.f) s2 += sg * sg;
+    }
+    const float trEF = fmaxf(trG - s2, 0.f) + 1e-4f * trG;
+    const float bF = fmaxf(sc[7], trEF) + sqrtf(sc[6]);
+    if (bF <= lim && isfinite(bF)) {
+      lr_certify(slot, sig, tau, pflag, stats);
+    } else {
+      const int u = atomicAdd(&counts[1], 1);
+      fall[3 * slots + u] = slot;
+    }
+    return;
+  }
   if (stage == 0) {
     pflag[4 * slot + 3] = 0;
     const bool c_ok = c2 <= kCouplingTol * kCouplingTol * trG && isfinite(c2) && isfinite(trE);
@@ -1081,40 +1115,59 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
   hipLaunchKernelGGL(k_lr_coupling<P>, dim3(count), dim3(256), 0, st, w.lrT, w.lrSig, w.lrV, nb,
                      tau, kCouplingTol, w.lrScal, mask, dmask);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  // E^T E and its power bound: W = G V_r, H = V_r^T W (into lrQ), Q = W - V H / 2
-  // (into lrY), E^T E = G - Q V^T - V Q^T (into lrP, partials into lrQ)
-  if ((e = gemm(h, rocblas_operation_none, rocblas_operation_none, nb, P, nb, w.lrG, nb, sG,
-                w.lrV, nb, sY, w.lrW, nb, sY, count)) != hipSuccess)
-    return e;
-  if ((e = gemm(h, rocblas_operation_transpose, rocblas_operation_none, P, P, nb, w.lrV, nb, sY,
-                w.lrW, nb, sY, w.lrQ, P, (int64_t)P * P, count)) != hipSuccess)
-    return e;
-  hipLaunchKernelGGL(k_lr_q<P>, dim3(count), dim3(256), 0, st, w.lrW, w.lrV, w.lrQ, dmask, w.lrY,
-                     nb);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  const int gtiles = ((nb + 63) / 64) * ((nb + 63) / 64);
-  hipLaunchKernelGGL(k_lr_ge<P>, dim3(gtiles, count), dim3(256), 0, st, w.lrG, w.lrY, w.lrV,
-                     dmask, w.lrP, nb, w.lrQ, w.lrRow);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  const int tiles = (int)((sG + 255) / 256 < 64 ? (sG + 255) / 256 : 64);
-  // stage 0: Frobenius bound of E^T E (partials were written to lrQ)
-  hipLaunchKernelGGL(k_lr_ge_reduce, dim3((count + 255) / 256), dim3(256), 0, st, w.lrQ, gtiles,
-                     count, w.lrScal);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_lr_rsum, dim3((nb + 255) / 256, count), dim3(256), 0, st, w.lrRow, nb);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_lr_cwy, dim3(gtiles, count), dim3(256), 0, st, w.lrP, w.lrRow, nb);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_lr_cwmax, dim3(count), dim3(256), 0, st, w.lrRow, nb, w.lrScal);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_lr_decide, dim3((count + 255) / 256), dim3(256), 0, st, count, w.slots, w.lrScal,
-                     w.lrSig, tau, w.pflag, w.lrCount, w.lrFall, w.live_list, w.stats, 0, 1);
+  // stage -1: the trace bound on lambda_max(E^T E) needs no E^T E; the slots it leaves
+  // undecided (listed at fall[3 slots ..]) get E^T E and its finer bounds
+  hipLaunchKernelGGL(k_lr_decide, dim3((count + 255) / 256), dim3(256), 0, st, count, w.slots,
+                     w.lrScal, w.lrSig, dmask, tau, w.pflag, w.lrCount, w.lrFall, w.live_list,
+                     w.stats, -1, 1);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = hipMemcpyAsync(w.hostInts + 1, w.lrCount + 1, sizeof(int), hipMemcpyDeviceToHost,
                           st)) != hipSuccess)
     return e;
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-  const int und = w.hostInts[1];
+  const int undF = w.hostInts[1];
+  int und = 0;
+  const int tiles = (int)((sG + 255) / 256 < 64 ? (sG + 255) / 256 : 64);
+  if (undF > 0) {
+    const int* flist = w.lrFall + 3 * w.slots;
+    // E^T E and its power bound: W = G V_r, H = V_r^T W (into lrQ), Q = W - V H / 2
+    // (into lrY), E^T E = G - Q V^T - V Q^T (into lrP, partials into lrQ)
+    if ((e = gemm(h, rocblas_operation_none, rocblas_operation_none, nb, P, nb, w.lrG, nb, sG,
+                  w.lrV, nb, sY, w.lrW, nb, sY, count)) != hipSuccess)
+      return e;
+    if ((e = gemm(h, rocblas_operation_transpose, rocblas_operation_none, P, P, nb, w.lrV, nb,
+                  sY, w.lrW, nb, sY, w.lrQ, P, (int64_t)P * P, count)) != hipSuccess)
+      return e;
+    hipLaunchKernelGGL(k_lr_q<P>, dim3(count), dim3(256), 0, st, w.lrW, w.lrV, w.lrQ, dmask,
+                       w.lrY, nb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int gtiles = ((nb + 63) / 64) * ((nb + 63) / 64);
+    hipLaunchKernelGGL(k_lr_ge<P>, dim3(gtiles, undF), dim3(256), 0, st, w.lrG, w.lrY, w.lrV,
+                       dmask, w.lrP, nb, w.lrQ, w.lrRow, flist);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // stage 0: Frobenius and Collatz-Wielandt bounds of E^T E (partials were written to lrQ)
+    hipLaunchKernelGGL(k_lr_ge_reduce, dim3((undF + 255) / 256), dim3(256), 0, st, w.lrQ,
+                       gtiles, undF, w.lrScal, flist);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_lr_rsum, dim3((nb + 255) / 256, undF), dim3(256), 0, st, w.lrRow, nb,
+                       flist);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_lr_cwy, dim3(gtiles, undF), dim3(256), 0, st, w.lrP, w.lrRow, nb, flist);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_lr_cwmax, dim3(undF), dim3(256), 0, st, w.lrRow, nb, w.lrScal, flist);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, w.lrCount + 1, 1);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_lr_decide, dim3((undF + 255) / 256), dim3(256), 0, st, undF, w.slots,
+                       w.lrScal, w.lrSig, dmask, tau, w.pflag, w.lrCount, w.lrFall, w.live_list,
+                       w.stats, 0, 1);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(w.hostInts + 1, w.lrCount + 1, sizeof(int), hipMemcpyDeviceToHost,
+                            st)) != hipSuccess)
+      return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    und = w.hostInts[1];
+  }
   if (und > 0) {
     // stage 1: square of E^T E / tr(E^T E); stage 2: its fourth power (eighth in all),
     // on the undecided slots only, gathered to compact positions (lrQ, then lrP)
@@ -1146,8 +1199,8 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
       hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, w.lrCount + 1, 1);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       hipLaunchKernelGGL(k_lr_decide, dim3((und + 255) / 256), dim3(256), 0, st, und,
-                         w.slots, w.lrScal, w.lrSig, tau, w.pflag, w.lrCount, w.lrFall, w.live_list,
-                         w.stats, stage, power);
+                         w.slots, w.lrScal, w.lrSig, dmask, tau, w.pflag, w.lrCount, w.lrFall,
+                         w.live_list, w.stats, stage, power);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       if (stage == 1) {
         if ((e = hipMemcpyAsync(w.hostInts + 1, w.lrCount + 1, sizeof(int),

@@ -152,8 +152,9 @@ struct ScaleWork {
   float* lrOm;          // [nb*p] probe matrix
   float* lrSplit;       // [kSplitFloats] split-K partials of tall blocks (null: none)
   int* lrCount;         // [4] device counters: fallback, undecided
-  int* lrFall;          // [3 slots] block ids, then slot indices, of failed certificates;
-                        // then the slots left undecided by the stage-0 bound
+  int* lrFall;          // [4 slots] block ids, then slot indices, of failed certificates;
+                        // then the slots left undecided by the stage-0 bound; then those
+                        // left undecided by the trace bound (stage -1)
   int lds_fallback;     // 1: fallback blocks fit the LDS Jacobi tier
   int* hostInts;        // pinned host ints [2]
   // polar fallback (polar.hip) for failed certificates of blocks beyond the LDS tier;
