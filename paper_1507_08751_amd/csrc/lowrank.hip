@@ -2,8 +2,9 @@
 //
 // For a live block B (logical mb x nb, mb >= nb) the soft-threshold of eq:svt only
 // needs the singular triplets with sigma > tau. A subspace iteration on the Gram
-// G = B^T B finds an orthonormal X (nb x p); one-sided Jacobi on B X gives
-// B V_r = A_f (orthogonal columns a_l = sigma_l u_l) with V_r = X W. Let L be the
+// G = B^T B finds an orthonormal X (nb x p); the SVD of the reduced block B X (from
+// its float64 Gram) gives B V_r = A_f (orthogonal columns a_l = sigma_l u_l) with
+// V_r = X W. Let L be the
 // columns with sigma_l > tau (live), plus those with tau/2 < sigma_l <= tau whose own
 // coupling c_l = ||u_l^T B - sigma_l v_l^T|| is tiny, and E_L = B (I - V_L V_L^T). The
 // result Z = sum_{l in L} max(1 - tau/sigma_l, 0) a_l v_l^T is accepted only if
@@ -22,8 +23,8 @@
 // ||SVT(B) - Z||_F <= ||B - B0||_F = ||U_L^T E_L||_F.
 // Blocks that fail either test get an exact SVT: the LDS Jacobi tier when they fit
 // in LDS, else the polar route (polar.hip). The plain matrix products (Gram, subspace
-// products, squarings) are rocBLAS batched GEMMs; the orthonormalisation, the small
-// Jacobi SVD, the certificate and the rebuild are the kernels below.
+// products, squarings) are rocBLAS batched GEMMs; the orthonormalisation, the reduced
+// SVD, the certificate and the rebuild are the kernels below.
 #include <rocblas/rocblas.h>
 
 #include "msld_internal.h"
@@ -32,7 +33,6 @@ namespace msld {
 
 static constexpr float kCertMargin = 2e-3f;    // relative margin on tau^2 for test (i)
 static constexpr float kCouplingTol = 1e-5f;   // test (ii): ||U_L^T E||_F <= tol ||B||_F
-static constexpr size_t kJacobiLdsMax = 150 * 1024;   // LDS stage of k_lr_jacobi
 
 __device__ __forceinline__ int wrap_add2(int base, int off, int mod) {
   int v = base + off;
@@ -224,116 +224,20 @@ __global__ void __launch_bounds__(256) k_lr_orth_w(const float* Y, float* X, int
     }
 }
 
-// Jacobi core shared with the other tiers (defined in kernels.hip is not visible
-// here, so the pair order and the rotation are restated for this translation unit).
+// Round-robin pair order of a cyclic Jacobi sweep over ncols (even) indices: ncols - 1
+// rounds of ncols / 2 disjoint pairs (the same order as the tiers in kernels.hip, which
+// is not visible from this translation unit).
 __device__ __forceinline__ void lr_pair(int round, int k, int ncols, int* a, int* b) {
   const int n1 = ncols - 1;
   *a = (k == 0) ? 0 : 1 + (k - 1 + round) % n1;
   *b = 1 + (ncols - 2 - k + round) % n1;
 }
 
-// One-sided Jacobi on C = B X (mb x p) in LDS with the p x p rotation W; writes the
-// rotated columns A_f back over C, sigma_l = ||a_l||, and V_r = X W (nb x p).
-template <int P>
-__global__ void __launch_bounds__(256) k_lr_jacobi(float* C, const float* X, float* Vr,
-                                                   float* sig, int mb, int nb, float tol,
-                                                   int max_sweeps) {
-  extern __shared__ float sm[];
-  const int lda = mb | 1;
-  constexpr int LDW = P | 1;
-  float* A = sm;                 // P x lda
-  float* W = A + P * lda;        // P x LDW
-  __shared__ int s_rot;
-  const int slot = blockIdx.x;
-  float* c = C + (int64_t)slot * mb * P;
-  const float* x = X + (int64_t)slot * nb * P;
-  float* vr = Vr + (int64_t)slot * nb * P;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < mb * P; e += blockDim.x) {
-    const int j = e / mb, r = e - j * mb;
-    A[j * lda + r] = c[e];
-  }
-  for (int e = tid; e < P * P; e += blockDim.x) {
-    const int j = e / P, r = e - j * P;
-    W[j * LDW + r] = (j == r) ? 1.f : 0.f;
-  }
-  __syncthreads();
-  constexpr int G = 256 / (P / 2);
-  const int grp = tid / G, t = tid - grp * G;
-  for (int sw = 0; sw < max_sweeps; ++sw) {
-    int rotated = 0;
-    for (int rd = 0; rd < P - 1; ++rd) {
-      int pa, pb;
-      lr_pair(rd, grp, P, &pa, &pb);
-      float al = 0.f, be = 0.f, ga = 0.f;
-      const float* ap = A + pa * lda;
-      const float* aq = A + pb * lda;
-      for (int r = t; r < mb; r += G) {
-        const float u = ap[r], v = aq[r];
-        al += u * u;
-        be += v * v;
-        ga += u * v;
-      }
-#pragma unroll
-      for (int o = G >> 1; o > 0; o >>= 1) {
-        al += __shfl_xor(al, o);
-        be += __shfl_xor(be, o);
-        ga += __shfl_xor(ga, o);
-      }
-      if (fabsf(ga) > tol * sqrtf(al) * sqrtf(be)) {
-        rotated = 1;
-        const float zeta = (be - al) / (2.f * ga);
-        const float tt = (fabsf(zeta) > 1e18f)
-                             ? 0.5f / zeta
-                             : copysignf(1.f, zeta) / (fabsf(zeta) + sqrtf(1.f + zeta * zeta));
-        const float cs = 1.f / sqrtf(1.f + tt * tt);
-        const float sn = cs * tt;
-        float* wap = A + pa * lda;
-        float* waq = A + pb * lda;
-        for (int r = t; r < mb; r += G) {
-          const float u = wap[r], v = waq[r];
-          wap[r] = cs * u - sn * v;
-          waq[r] = sn * u + cs * v;
-        }
-        float* wp = W + pa * LDW;
-        float* wq = W + pb * LDW;
-        for (int r = t; r < P; r += G) {
-          const float u = wp[r], v = wq[r];
-          wp[r] = cs * u - sn * v;
-          wq[r] = sn * u + cs * v;
-        }
-      }
-      __syncthreads();
-    }
-    if (!__syncthreads_or(rotated)) break;
-  }
-  (void)s_rot;
-  // sigma and write-back
-  for (int j = tid >> 6; j < P; j += blockDim.x >> 6) {
-    float s2 = 0.f;
-    for (int r = (tid & 63); r < mb; r += 64) s2 += A[j * lda + r] * A[j * lda + r];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o);
-    if ((tid & 63) == 0) sig[slot * P + j] = sqrtf(s2);
-  }
-  for (int e = tid; e < mb * P; e += blockDim.x) {
-    const int j = e / mb, r = e - j * mb;
-    c[e] = A[j * lda + r];
-  }
-  // V_r = X W
-  for (int e = tid; e < nb * P; e += blockDim.x) {
-    const int l = e / nb, row = e - l * nb;
-    float v = 0.f;
-#pragma unroll
-    for (int j = 0; j < P; ++j) v += x[j * nb + row] * W[l * LDW + j];
-    vr[e] = v;
-  }
-}
-
-// Tall blocks, whose C does not fit the LDS stage of k_lr_jacobi: the same outputs
-// from the p x p Gram K = C^T C accumulated in float64 over row chunks and its
-// eigen-decomposition K = W diag(lambda) W^T by cyclic two-sided Jacobi in float64:
-// A_f = C W (orthogonal columns), sigma_l = sqrt(lambda_l), V_r = X W.
+// SVD of the reduced block C = B X (mb x p): the p x p Gram K = C^T C accumulated in
+// float64 over row chunks and its eigen-decomposition K = W diag(lambda) W^T by cyclic
+// two-sided Jacobi in float64 (parallel pair order): A_f = C W (orthogonal columns
+// a_l = sigma_l u_l), sigma_l = sqrt(lambda_l), V_r = X W. The coupling test of the
+// certificate bounds what the float32 product C W loses in orthogonality.
 template <int P>
 __global__ void __launch_bounds__(256) k_lr_gram64(const float* C, int mb, int rows,
                                                    double* part, int64_t part_stride) {
@@ -1067,39 +971,28 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
                          w.lrX, nb, sY);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  // C = B X, Jacobi on C
+  // C = B X, then its SVD: the float64 Gram C^T C in row chunks (partials in lrQ, free
+  // here), its eigen-decomposition (rotation into lrP, free here), A_f = C W
   if ((e = gemm(h, rocblas_operation_none, rocblas_operation_none, mb, P, nb, w.pA, mb, sB,
                 w.lrX, nb, sY, w.lrC, mb, sC, count)) != hipSuccess)
     return e;
   {
-    const size_t lds = (size_t)4 * (P * (mb | 1) + P * (P | 1));
-    // tighter rotation threshold than the other tiers: the reduced problem is only
-    // p columns wide and its residual orthogonality enters the coupling test
-    const float rr_tol = 5.9604645e-8f * sqrtf((float)mb);
     (void)jtol;
-    if (lds <= kJacobiLdsMax) {
-      hipLaunchKernelGGL(k_lr_jacobi<P>, dim3(count), dim3(256), lds, st, w.lrC, w.lrX, w.lrV,
-                         w.lrSig, mb, nb, rr_tol, 40);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-    } else {
-      // tall blocks: float64 Gram of C in row chunks (partials in lrQ, free here), its
-      // eigen-decomposition (rotation into lrP, free here), then A_f = C W
-      const int64_t pstride = (int64_t)nb * nb / 2;   // doubles per slot in lrQ
-      int chunks = (mb + 511) / 512;
-      if (chunks > pstride / 256) chunks = (int)(pstride / 256);
-      const int rows = (mb + chunks - 1) / chunks;
-      chunks = (mb + rows - 1) / rows;
-      double* part = reinterpret_cast<double*>(w.lrQ);
-      hipLaunchKernelGGL(k_lr_gram64<P>, dim3(chunks, count), dim3(256), 0, st, w.lrC, mb, rows,
-                         part, pstride);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-      hipLaunchKernelGGL(k_lr_eig64<P>, dim3(count), dim3(256), 0, st, part, chunks, pstride,
-                         w.lrX, w.lrV, w.lrSig, w.lrP, nb);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-      hipLaunchKernelGGL(k_lr_rot_c<P>, dim3((mb + 255) / 256, count), dim3(256), 0, st, w.lrC,
-                         w.lrP, mb);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
+    const int64_t pstride = (int64_t)nb * nb / 2;   // doubles per slot in lrQ
+    int chunks = (mb + 511) / 512;
+    if (chunks > pstride / 256) chunks = (int)(pstride / 256);
+    const int rows = (mb + chunks - 1) / chunks;
+    chunks = (mb + rows - 1) / rows;
+    double* part = reinterpret_cast<double*>(w.lrQ);
+    hipLaunchKernelGGL(k_lr_gram64<P>, dim3(chunks, count), dim3(256), 0, st, w.lrC, mb, rows,
+                       part, pstride);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_lr_eig64<P>, dim3(count), dim3(256), 0, st, part, chunks, pstride,
+                       w.lrX, w.lrV, w.lrSig, w.lrP, nb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_lr_rot_c<P>, dim3((mb + 255) / 256, count), dim3(256), 0, st, w.lrC,
+                       w.lrP, mb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   // coupling: T = A_f^T B (p x nb)
   if (!tall_atb(w.lrC, sC, P, w.pA, sB, nb, mb, w.lrT, P, (int64_t)P * nb, count, w.lrSplit,
