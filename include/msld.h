@@ -179,6 +179,18 @@ msld_status msld_step(msld_solver *s, const float *d_Y, int64_t ldY, float *d_Z,
  * last msld_reset (primal_resid is -1: use msld_step to obtain it). Synchronises. */
 msld_status msld_stats(msld_solver *s, msld_result *info);
 
+/* Iterations as HIP graphs (not a step of the paper: launch overhead). When no scale
+ * of the plan takes the batched low-rank path (whose driver reads live and fallback
+ * counts on the host), msld_step, msld_solve and msld_batch_solve capture one ADMM
+ * iteration per D-buffer parity into a HIP graph on first use and replay it for every
+ * iteration whose residual is not read; the shift seed and iteration counter then live
+ * on the device. Graphs are keyed by the Y and Z buffers and the mask; new buffers are
+ * captured again. Results equal those of plain launches.
+ * enable != 0 allows graphs (the default), 0 forces plain launches. Returns 1 if
+ * iterations will be replayed from graphs, 0 if not (disabled, or the plan needs host
+ * waits), or a negative msld_status. Synchronises the solver's stream. */
+int32_t msld_set_graph(msld_solver* s, int32_t enable);
+
 /* Masked data consistency (the collaborative-filtering variant of Sec. 10): with a
  * mask set, the X-update of eq:admm applies its consensus correction only on observed
  * entries and keeps X_i = Z_i - U_i on the others, so the constraint sum_i X_i = Y

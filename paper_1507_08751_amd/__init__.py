@@ -69,6 +69,7 @@ EXPORTS = {
                                  ctypes.c_int32]),
     "msld_free": (None, [ctypes.c_void_p]),
     "msld_set_mask": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
+    "msld_set_graph": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "msld_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Params)]),
     "msld_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "msld_default_lambda": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -289,6 +290,15 @@ class Solver:
                 "fail_bound": list(res.fail_bound)[:self.L],
                 "polar": list(res.polar)[:self.L],
                 "polar_steps": list(res.polar_steps)[:self.L]}
+
+    def set_graph(self, enable=True):
+        """Allow (default) or forbid replaying iterations from captured HIP graphs;
+        returns whether iterations will be replayed from graphs (msld_set_graph)."""
+        with self._torch.cuda.device(self.device):
+            r = int(self._lib.msld_set_graph(self._h, 1 if enable else 0))
+        if r < 0:
+            _check(r, "msld_set_graph")
+        return r == 1
 
     def set_mask(self, mask):
         """Observed-entry mask (M x N bool / uint8 device tensor, kept alive by the

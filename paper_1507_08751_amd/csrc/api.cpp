@@ -271,9 +271,18 @@ float* plane_D(msld_solver* s, int which) {
 
 double* dev_res(msld_solver* s) { return reinterpret_cast<double*>(s->arena + s->plan.off_res); }
 
+static void drop_graphs(msld_solver* s) {
+  for (auto& g : s->gx)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+}
+
 static void destroy_solver(msld_solver* s) {
   if (!s) return;
   (void)hipStreamSynchronize(s->st);
+  drop_graphs(s);
   if (s->prof_ev) {
     for (size_t e = 0; e < (4 + 5 * (size_t)s->p.L) * (size_t)s->prof_cap; ++e)
       (void)hipEventDestroy(s->prof_ev[e]);
@@ -288,6 +297,7 @@ static void destroy_solver(msld_solver* s) {
     if (s->ev_join[i]) (void)hipEventDestroy(s->ev_join[i]);
   }
   if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
+  if (s->cst) (void)hipStreamDestroy(s->cst);
   if (s->arena) (void)hipFree(s->arena);
   if (s->host_res) (void)hipHostFree(s->host_res);
   if (s->host_ints) (void)hipHostFree(s->host_ints);
@@ -346,6 +356,25 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
   s->d_seed = reinterpret_cast<unsigned long long*>(s->arena + pl.off_inst);
   s->d_k = reinterpret_cast<int*>(s->d_seed + ninst);
   s->d_active = s->d_k + ninst;
+  // an iteration can be captured once no scale's driver waits on the host (the batched
+  // low-rank path reads its live and fallback counts); such solvers keep the shift
+  // seed and iteration counter on the device, so a replay needs no host values
+  s->graphable = true;
+  for (int i = 0; i < p->L; ++i)
+    if (pl.use_lr[i]) s->graphable = false;
+  s->graph_on = s->graphable;
+  if (s->graphable && hipStreamCreateWithFlags(&s->cst, hipStreamNonBlocking) != hipSuccess) {
+    s->cst = nullptr;
+    destroy_solver(s);
+    return MSLD_EDEVICE;
+  }
+  if (ninst == 1) {
+    const unsigned long long seed = p->shift_seed;
+    if (hipMemcpy(s->d_seed, &seed, sizeof(seed), hipMemcpyHostToDevice) != hipSuccess) {
+      destroy_solver(s);
+      return MSLD_EDEVICE;
+    }
+  }
   if (hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming) != hipSuccess) {
     s->ev_fork = nullptr;
     destroy_solver(s);
@@ -524,7 +553,9 @@ msld_status iterate_once(msld_solver* s, const float* d_Y, int64_t ldY, float* d
   const int IM = p.M, N = p.N, L = p.L;
   const int M = IM * s->ninst;
   const size_t MN = plane_elems(s);
-  const bool stacked = s->ninst > 1;
+  // per-instance device seeds, iteration counters and activity flags: stacked instances,
+  // and single solves that may be captured into a graph
+  const bool stacked = s->ninst > 1 || s->graphable;
   float* R = plane_R(s);
   float* Dc = plane_D(s, s->cur);
   float* Dn = plane_D(s, 1 - s->cur);
@@ -664,6 +695,47 @@ msld_status iterate_once(msld_solver* s, const float* d_Y, int64_t ldY, float* d
   return MSLD_OK;
 }
 
+msld_status step_iteration(msld_solver* s, const float* d_Y, int64_t ldY, float* d_Z,
+                           bool want_res) {
+  if (want_res || !s->graph_on || s->prof_ev) return iterate_once(s, d_Y, ldY, d_Z, want_res);
+  if (s->gY != d_Y || s->gZ != d_Z || s->gldY != ldY) {
+    drop_graphs(s);
+    s->gY = d_Y;
+    s->gZ = d_Z;
+    s->gldY = ldY;
+  }
+  const int c = s->cur;
+  if (!s->gx[c]) {
+    // captured on the solver's own stream (the null stream cannot be captured); the
+    // graph is then launched on the caller's stream
+    const int k0 = s->k;
+    hipStream_t st0 = s->st;
+    hipGraph_t g = nullptr;
+    MSLD_TRY(s, hipStreamBeginCapture(s->cst, hipStreamCaptureModeThreadLocal));
+    s->st = s->cst;
+    const msld_status st = iterate_once(s, d_Y, ldY, d_Z, false);
+    const hipError_t ec = hipStreamEndCapture(s->cst, &g);
+    s->st = st0;
+    s->k = k0;
+    s->cur = c;
+    if (st != MSLD_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (ec != hipSuccess || !g) return dev_err(s, ec != hipSuccess ? ec : hipErrorUnknown);
+    const hipError_t ei = hipGraphInstantiate(&s->gx[c], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+      s->gx[c] = nullptr;
+      return dev_err(s, ei);
+    }
+  }
+  MSLD_TRY(s, hipGraphLaunch(s->gx[c], s->st));
+  s->k += 1;
+  s->cur = 1 - s->cur;
+  return MSLD_OK;
+}
+
 // ||Y_z||^2 of every instance into dres[ninst + z].
 msld_status launch_ynorms(msld_solver* s, const float* d_Y, int64_t ldY) {
   double* part = reinterpret_cast<double*>(s->arena + s->plan.off_part);
@@ -775,7 +847,7 @@ msld_status msld_step(msld_solver* s, const float* d_Y, int64_t ldY, float* d_Z,
   if (s->failed) return MSLD_EDEVICE;
   if (ldY < s->p.N) return MSLD_EINVAL;
   for (int c = 0; c < count; ++c) {
-    msld_status st = iterate_once(s, d_Y, ldY, d_Z, resid != nullptr && c == count - 1);
+    msld_status st = step_iteration(s, d_Y, ldY, d_Z, resid != nullptr && c == count - 1);
     if (st != MSLD_OK) return st;
   }
   if (resid) return read_resid(s, d_Y, ldY, resid);
@@ -803,7 +875,7 @@ msld_status msld_solve(msld_solver* s, const float* d_Y, int64_t ldY, float* d_Z
     const bool check = p.tol > 0.f && (iters % p.check_every == 0);
     const bool last = iters == p.max_iters;
     const bool want = check || (last && info);
-    st = iterate_once(s, d_Y, ldY, d_Z, want);
+    st = step_iteration(s, d_Y, ldY, d_Z, want);
     if (st != MSLD_OK) return st;
     if (want) {
       result = read_resid(s, d_Y, ldY, &resid);
@@ -877,7 +949,17 @@ msld_status msld_set_mask(msld_solver* s, const uint8_t* d_mask, int64_t ldmask)
   if (d_mask && ldmask < s->p.N) return MSLD_EINVAL;
   s->mask = d_mask;
   s->ldmask = d_mask ? ldmask : 0;
+  drop_graphs(s);   // captured iterations hold the previous mask
   return MSLD_OK;
+}
+
+int32_t msld_set_graph(msld_solver* s, int32_t enable) {
+  if (!s) return MSLD_EINVAL;
+  if (s->failed) return MSLD_EDEVICE;
+  if (hipStreamSynchronize(s->st) != hipSuccess) return dev_err(s, hipErrorUnknown);
+  drop_graphs(s);
+  s->graph_on = s->graphable && enable != 0;
+  return s->graph_on ? 1 : 0;
 }
 
 msld_status msld_bsvt(msld_solver* s, int32_t scale, const float* d_V, float* d_Z, float tau,
@@ -1048,7 +1130,7 @@ msld_status msld_batch_solve(msld_batch* b, const float* const* d_Y, const int64
     int n_active = ni;
     for (int k = 0; k < p.max_iters && n_active > 0; ++k) {
       const bool check = (p.tol > 0.f && (k + 1) % p.check_every == 0) || k + 1 == p.max_iters;
-      st = iterate_once(s, c.Y, p.N, c.Z, check);
+      st = step_iteration(s, c.Y, p.N, c.Z, check);
       if (st != MSLD_OK) return st;
       for (int z = 0; z < ni; ++z)
         if (active[z]) iters[z] = k + 1;

@@ -89,6 +89,15 @@ struct msld_solver {
   int prof_cap, prof_n;
   hipEvent_t* prof_ev;
   int64_t round_launches[MSLD_MAX_SCALES];
+  // HIP graphs of one iteration (one per D-buffer parity) for plans whose iteration
+  // never waits on the host; keyed by the Y / Z buffers they were captured with
+  bool graphable;
+  bool graph_on;
+  hipStream_t cst;   // capture stream (the caller's stream may be the null stream)
+  hipGraphExec_t gx[2];
+  const float* gY;
+  int64_t gldY;
+  float* gZ;
 };
 
 namespace msld {
@@ -102,6 +111,10 @@ size_t plane_elems(const msld_solver* s);   // elements of one stacked plane
 // residual sums land in device memory (dres[z]).
 msld_status iterate_once(msld_solver* s, const float* d_Y, int64_t ldY, float* d_Z,
                          bool want_res);
+// iterate_once, replayed from a captured HIP graph when the plan allows it and no
+// residual is wanted
+msld_status step_iteration(msld_solver* s, const float* d_Y, int64_t ldY, float* d_Z,
+                           bool want_res);
 double* dev_res(msld_solver* s);
 msld_status launch_ynorms(msld_solver* s, const float* d_Y, int64_t ldY);
 
