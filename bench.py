@@ -376,6 +376,16 @@ def batch_bench(args):
     torch.cuda.set_device(dev)
     insts = batch_instances(args.instances, seed=0)
     K = args.steps if args.steps != 50 else 100
+    # autotuned launch choice for every block size of the batch (before any plan)
+    tuned = {}
+    t0 = time.perf_counter()
+    for (m, n) in sorted({(m, n) for i in insts for (m, n) in i.ladder if m * n > 1}):
+        r = msld.autotune(m, n, device=dev)
+        tuned[f"{m}x{n}"] = {"tier": r["tier"], "lds_cap": r["lds_cap"],
+                             "lrs_wide": r["lrs_wide"],
+                             "us_per_block": round(r["us_per_block"], 4),
+                             "us_default": round(r["us_default"], 4)}
+    tune_s = time.perf_counter() - t0
     probs = [{"M": i.Y.shape[0], "N": i.Y.shape[1], "ladder": i.ladder, "iters": K,
               "cycle_spin": True, "seed": j} for j, i in enumerate(insts)]
     Ys = [torch.from_numpy(i.Y).to(dev) for i in insts]
@@ -405,7 +415,8 @@ def batch_bench(args):
            "higher_is_better": True, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "sizes {64^2,128^2,256^2,128x512}, ladders {1,4,16,full} / "
                                   "{1,8,32,full}, 2% rank-1 + N(0,0.01^2), cycle spinning",
-                      "instances": len(insts), "iters": K, "classes": batch.classes},
+                      "instances": len(insts), "iters": K, "classes": batch.classes,
+                      "autotuned": tuned, "autotune_seconds": round(tune_s, 2)},
            "batch_seconds": round(tb, 4), "one_at_a_time_seconds": round(t1, 4),
            "one_at_a_time_solves_per_s": round(len(insts) / t1, 4),
            "speedup": round(t1 / tb, 3), "max_rel_diff_batch_vs_alone": worst}

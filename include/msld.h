@@ -179,6 +179,33 @@ msld_status msld_step(msld_solver *s, const float *d_Y, int64_t ldY, float *d_Z,
  * last msld_reset (primal_resid is -1: use msld_step to obtain it). Synchronises. */
 msld_status msld_stats(msld_solver *s, msld_result *info);
 
+/* Autotuner of the BlockSVT launch choice per block size (not a step of the paper).
+ * Times, on the current device and the given stream, the tiers and launch shapes that
+ * apply to m x n blocks (register tier; fused certified low-rank kernel with first
+ * subspace width p or 2p; LDS Jacobi tier with at most 1, 2, 4 or as many workgroups
+ * per compute unit as fit; certified low-rank path on batched GEMMs), one block-wise
+ * SVT call each on a synthetic matrix of up to 4096 such blocks (rank-1 blocks at about
+ * twice the threshold on half of them, small noise), and records the fastest in a
+ * process-wide cache keyed by (m, n, device architecture). Solvers, batches and server
+ * classes created afterwards use the cached choice for every scale of that block size
+ * (alone or in a batch alike; a plan's lowrank_min < 0 still excludes the low-rank
+ * tiers), so results do not depend on batch composition; all candidates compute the
+ * same block-wise SVT up to rounding. m, n in [1, 4096], not both 1. Allocates device
+ * memory while it runs; call it when no solver is being created on another thread.
+ * Errors: MSLD_EINVAL, MSLD_ENOMEM, MSLD_EDEVICE (no candidate could be timed). */
+typedef struct msld_tune_result {
+  int32_t tier;        /* chosen tier, msld_scale_tier numbering */
+  int32_t lds_cap;     /* LDS tier: workgroups per compute unit (0: as many as fit) */
+  int32_t lrs_wide;    /* fused low-rank kernel: 1 = first pass with 2p (no retry pass) */
+  int32_t candidates;  /* configurations timed */
+  float us_per_block;  /* time of the chosen one, microseconds per block */
+  float us_default;    /* time of the built-in choice, microseconds per block */
+} msld_tune_result;
+msld_status msld_autotune(int32_t m, int32_t n, void* hip_stream, msld_tune_result* out);
+
+/* Forget every autotuned choice; plans created afterwards use the built-in choice. */
+void msld_autotune_clear(void);
+
 /* Iterations as HIP graphs (not a step of the paper: launch overhead). When no scale
  * of the plan takes the batched low-rank path (whose driver reads live and fallback
  * counts on the host), msld_step, msld_solve and msld_batch_solve capture one ADMM

@@ -46,6 +46,12 @@ KIND_NOISE = 1
 KIND_SPATIAL = 2
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("tier", ctypes.c_int32), ("lds_cap", ctypes.c_int32),
+                ("lrs_wide", ctypes.c_int32), ("candidates", ctypes.c_int32),
+                ("us_per_block", ctypes.c_float), ("us_default", ctypes.c_float)]
+
+
 class Result(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("primal_resid", ctypes.c_double),
@@ -70,6 +76,9 @@ EXPORTS = {
     "msld_free": (None, [ctypes.c_void_p]),
     "msld_set_mask": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
     "msld_set_graph": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "msld_autotune": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                     ctypes.c_void_p]),
+    "msld_autotune_clear": (None, []),
     "msld_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Params)]),
     "msld_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "msld_default_lambda": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -503,3 +512,24 @@ def bsvt(V, m, n, tau, shift=(0, 0), lowrank_min=0):
         return s.bsvt(0, V.contiguous(), tau, shift)
     finally:
         s.close()
+
+
+def autotune(m, n, device=None):
+    """Time the BlockSVT launch choices for m x n blocks on the device and record the
+    fastest for later plans (msld_autotune); returns the choice as a dict."""
+    import torch
+    lib = load()
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None \
+        else torch.device(device)
+    r = TuneResult()
+    with torch.cuda.device(dev):
+        _check(lib.msld_autotune(int(m), int(n), _stream_ptr(torch, dev), ctypes.byref(r)),
+               "msld_autotune")
+    return {"tier": TIERS.get(r.tier, str(r.tier)), "lds_cap": r.lds_cap,
+            "lrs_wide": bool(r.lrs_wide), "candidates": r.candidates,
+            "us_per_block": r.us_per_block, "us_default": r.us_default}
+
+
+def autotune_clear():
+    """Forget every autotuned choice (msld_autotune_clear)."""
+    load().msld_autotune_clear()

@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmsld.so")
-SOURCES = ["kernels.hip", "lowrank.hip", "lowrank_small.hip", "polar.hip", "api.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "lowrank.hip", "lowrank_small.hip", "polar.hip", "api.cpp", "server.cpp",
+           "tune.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -27,6 +27,8 @@ int pow2_floor(int x) {
   return p;
 }
 
+}  // namespace
+
 // A block fits the LDS Jacobi tier if B and W fit the LDS budget, one workgroup
 // covers all column pairs, and G lanes x 32 rows per lane cover the rows.
 bool lds_fits(int mb, int nb) {
@@ -39,8 +41,6 @@ double lambda_default(int M, int N, int m, int n) {
   return std::sqrt((double)m) + std::sqrt((double)n) +
          std::sqrt(std::log((double)M * (double)N / (double)(m > n ? m : n)));
 }
-
-}  // namespace
 
 msld_status validate_params(const msld_params* p) {
   if (!p) return MSLD_EINVAL;
@@ -149,14 +149,33 @@ msld_status make_plan(const msld_params* p, int ninst, Plan* pl) {
                      lds_fits(g.mb, g.nb) && lr_small_lds_bytes(sNB, sMB, sP) <= kLdsTierMax;
     // (narrower blocks take it only when the alternative would be the HBM panel tier)
     // (the orthonormalisation keeps p columns of nb in LDS: nb <= 2048)
-    const bool lr = !lrs && lr_min > 0 && g.nb >= lr_min && g.nb <= 2048 &&
-                    (g.nb >= 4 * kLRP || (g.nb >= 2 * kLRP && !lds_fits(g.mb, g.nb)));
+    bool lr = !lrs && lr_min > 0 && g.nb >= lr_min && g.nb <= 2048 &&
+              (g.nb >= 4 * kLRP || (g.nb >= 2 * kLRP && !lds_fits(g.mb, g.nb)));
     int tier;
     if (m == 1 && n == 1) tier = TIER_1X1;
     else if (reg_tier_shape(m, n)) tier = TIER_REG;
     else if (lrs) tier = TIER_LRS;
     else if (!lr && lds_fits(g.mb, g.nb)) tier = TIER_LDS;
     else tier = TIER_PANEL;
+    // an autotuned choice for this block size (msld_autotune), where it applies
+    TuneCfg tc;
+    if (tier != TIER_1X1 && tune_lookup(m, n, &tc)) {
+      if (tc.tier == TIER_REG && reg_tier_shape(m, n)) {
+        tier = TIER_REG;
+        lr = false;
+      } else if (tc.tier == TIER_LRS && lrs) {
+        tier = TIER_LRS;
+        lr = false;
+        pl->lrs_wide[i] = tc.lrs_wide;
+      } else if (tc.tier == TIER_LDS && lds_fits(g.mb, g.nb)) {
+        tier = TIER_LDS;
+        lr = false;
+        pl->lds_cap[i] = tc.lds_cap;
+      } else if (tc.tier == kTierLowRank && lr_min > 0 && g.nb >= lr_min && g.nb <= 2048) {
+        tier = TIER_PANEL;
+        lr = true;
+      }
+    }
     pl->use_lr[i] = lr ? 1 : 0;
     pl->tier[i] = tier;
     pl->off_stats[i] = take(8 * 8);
@@ -409,6 +428,8 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
     ScaleWork& w = s->work[i];
     std::memset(&w, 0, sizeof(w));
     w.stats = reinterpret_cast<unsigned long long*>(s->arena + pl.off_stats[i]);
+    w.lds_cap = pl.lds_cap[i];
+    w.lrs_wide = pl.lrs_wide[i];
     if (pl.spin[i]) {
       w.spinAcc = reinterpret_cast<float*>(s->arena + pl.off_spin[i]);
       w.spinTmp = w.spinAcc + plane_elems(s);

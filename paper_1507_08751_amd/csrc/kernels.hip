@@ -231,6 +231,10 @@ __global__ void k_zero_int(int* p) {
   if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = 0;
 }
 
+__global__ void k_copy_count(const int* src, int* dst) {
+  if (threadIdx.x == 0) *dst = *src;
+}
+
 __global__ void k_zero_ints(int* p, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
@@ -1302,17 +1306,23 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
   }
   if (tier == TIER_LRS) {
     // fused certified low-rank kernel; its failures get a retry with a twice wider
-    // subspace, and what still fails goes to the LDS Jacobi tier
+    // subspace (unless the first pass already used it), and what still fails goes to
+    // the LDS Jacobi tier
     hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, w.lrCount, 2);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     MSLD_EV(2);
-    if ((e = launch_lr_small(g, w, Zout, Dout, tau, sh, num_cus, 0, w.live_count, w.live_list,
-                             w.lrCount, w.lrFall, st)) != hipSuccess)
+    if ((e = launch_lr_small(g, w, Zout, Dout, tau, sh, num_cus, w.lrs_wide ? 2 : 0,
+                             w.live_count, w.live_list, w.lrCount, w.lrFall, st)) != hipSuccess)
       return e;
     MSLD_EV(3);
-    if ((e = launch_lr_small(g, w, Zout, Dout, tau, sh, num_cus, 1, w.lrCount, w.lrFall,
-                             w.lrCount + 1, w.lrFall + nblk, st)) != hipSuccess)
+    if (w.lrs_wide) {
+      // the failures of the wide pass are the fallback list
+      hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(64), 0, st, w.lrCount, w.lrCount + 1);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    } else if ((e = launch_lr_small(g, w, Zout, Dout, tau, sh, num_cus, 1, w.lrCount, w.lrFall,
+                                    w.lrCount + 1, w.lrFall + nblk, st)) != hipSuccess) {
       return e;
+    }
     int G = 1;
     const int threads = lds_tier_threads(g.nb, g.mb, &G);
     const size_t ldsb = lds_tier_bytes(g.mb, g.nb);
@@ -1325,7 +1335,7 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
     if (grid > nblk) grid = nblk;
     ScaleWork fw = w;
     fw.live_count = w.lrCount + 1;
-    fw.live_list = w.lrFall + nblk;
+    fw.live_list = w.lrs_wide ? w.lrFall : w.lrFall + nblk;
     switch (G) {
       case 1: e = launch_lds_g<1>(grid, threads, ldsb, Zout, Dout, g, sh, tau, jtol, max_sweeps, fw, st); break;
       case 2: e = launch_lds_g<2>(grid, threads, ldsb, Zout, Dout, g, sh, tau, jtol, max_sweeps, fw, st); break;
@@ -1347,6 +1357,7 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
     const int by_waves = 32 / ((threads + 63) / 64);
     if (per_cu > by_waves) per_cu = by_waves;
     if (per_cu < 1) per_cu = 1;
+    if (w.lds_cap > 0 && per_cu > w.lds_cap) per_cu = w.lds_cap;   // autotuned
     int grid = num_cus * per_cu;
     if (grid > nblk) grid = nblk;
     switch (G) {

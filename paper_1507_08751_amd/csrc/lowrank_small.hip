@@ -535,18 +535,19 @@ int lr_small_shape(int mb, int nb, int* NB, int* MB, int* P) {
 }
 
 // One pass of the fused kernel over (count, list); failures are appended to
-// (fcount, flist). pass 0 uses the first subspace width, pass 1 twice that.
+// (fcount, flist). pass 0 uses the first subspace width, pass 1 (a retry on few blocks)
+// and pass 2 (a first pass over all live blocks) twice that.
 hipError_t launch_lr_small(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout,
                            float tau, const ShiftSpec& sh, int num_cus, int pass,
                            const int* count, const int* list, int* fcount, int* flist,
                            hipStream_t st) {
   int NB = 0, MB = 0, P = 0;
   if (!lr_small_shape(g.mb, g.nb, &NB, &MB, &P)) return hipErrorInvalidValue;
-  if (pass) P *= 2;
+  if (pass) P *= 2;   // pass 1: retry of the failures, pass 2: wide first pass
   const size_t lds = lr_small_lds_bytes(NB, MB, P);
   int per_cu = (int)(160 * 1024 / (lds + 2048));
   if (per_cu > 8) per_cu = 8;
-  if (pass && per_cu > 1) per_cu = 1;   // the retry list is short
+  if (pass == 1 && per_cu > 1) per_cu = 1;   // the retry list is short
   if (per_cu < 1) per_cu = 1;
   int grid = num_cus * per_cu;
   const int nblk = g.P * g.Q;

@@ -118,6 +118,8 @@ __device__ inline int gcol(const ScaleGeom& g, int q, int j, int sc) {
 struct ScaleWork {
   float* spinAcc;       // averaged cycle spinning: [plane] sum over the shift set
   float* spinTmp;       // [plane] one shift's Z-step
+  int lds_cap;          // LDS tier: workgroups per CU cap (0: as many as fit)
+  int lrs_wide;         // fused low-rank kernel: first pass with 2p, no retry pass
   double* froPart;      // noise scale: [ninst][kFroParts] partial sums of squares
   float* froGain;       // noise scale: [ninst] gains max(1 - tau / ||v||_F, 0)
   int* live_count;      // [1] blocks that passed the bound test this pass

@@ -44,12 +44,26 @@ struct Plan {
       off_lr[MSLD_MAX_SCALES], off_pl[MSLD_MAX_SCALES];
   int pl_cap[MSLD_MAX_SCALES];   // polar fallback chunk (0: none)
   size_t off_split[MSLD_MAX_SCALES];   // split-K partials (tall low-rank blocks; 0: none)
+  int lds_cap[MSLD_MAX_SCALES];    // LDS tier: workgroups per CU cap (0: as many as fit)
+  int lrs_wide[MSLD_MAX_SCALES];   // fused low-rank kernel: first pass with 2p
   // averaged cycle spinning: shifts per iteration (0: one random shift), whether the
   // set is every shift, and the accumulator + scratch planes
   int spin[MSLD_MAX_SCALES];
   int spin_full[MSLD_MAX_SCALES];
   size_t off_spin[MSLD_MAX_SCALES];
 };
+
+// Autotuned launch choice of one block size (tune.cpp); tier in msld_scale_tier
+// numbering (kTierLowRank for the batched low-rank path).
+constexpr int kTierLowRank = 4;
+struct TuneCfg {
+  int tier;
+  int lds_cap;
+  int lrs_wide;
+};
+bool tune_lookup(int m, int n, TuneCfg* out);
+bool lds_fits(int mb, int nb);
+double lambda_default(int M, int N, int m, int n);
 
 msld_status validate_params(const msld_params* p);
 msld_status make_plan(const msld_params* p, int ninst, Plan* pl);
