@@ -672,3 +672,36 @@ def test_video_workload_parity(lib):
     print(f"video 25344x192: errs {['%.1e' % e for e in errs]}", flush=True)
     assert max(errs) <= 1e-3
     solver.close()
+
+
+@pytest.mark.parametrize("spin_count", [4, 64])
+def test_admm_spacetime_averaged_spinning_parity(lib, spin_count):
+    """Space-time scales with averaged cycle spinning (4 hashed video shifts, or every
+    shift of the 2 x 2 x 2 and 4 x 4 x 4 scales with 64) against the oracle (1e-3)."""
+    H = W = 16
+    T = 8
+    M, N = H * W, T
+    rng = np.random.default_rng(7)
+    Y = 0.5 * np.outer(rng.random(M) + 0.5, 1 + 0.1 * rng.standard_normal(N))
+    for _ in range(4):   # rank-1 space-time blobs on 4 x 4 pixel patches over 4 frames
+        y0, x0, t0 = (int(v) for v in rng.integers(0, [H - 4, W - 4, T - 4]))
+        pix = [(y0 + dy) * W + x0 + dx for dy in range(4) for dx in range(4)]
+        Y[np.ix_(pix, range(t0, t0 + 4))] += 2.0 * np.outer(rng.standard_normal(16),
+                                                             rng.standard_normal(4))
+    spikes = rng.integers(0, M * N, 6)
+    Y.flat[spikes] += 4.0
+    Y = (Y + 0.01 * rng.standard_normal((M, N))).astype(np.float32)
+    ladder = [(1, 1), (4, 2), (16, 4), (M, N)]
+    kinds = [0, 2, 2, 0]
+    pws = [1, 2, 4, 1]
+    ref = O.admm(Y.astype(np.float64), ladder, rho=1.0, iters=20, cycle_spin=True, seed=3,
+                 kinds=kinds, image_w=W, patch_w=pws, spin_count=spin_count)
+    solver = lib.Solver(M, N, ladder, rho=1.0, iters=20, cycle_spin=True, seed=3, kinds=kinds,
+                        image_w=W, patch_w=pws, spin_count=spin_count)
+    Z, _ = solver.solve(torch.from_numpy(Y).cuda())
+    torch.cuda.synchronize()
+    Zg = Z.cpu().numpy()
+    errs = [rel_err(Zg[i], ref["Z"][i], np.linalg.norm(Y)) for i in range(len(ladder))]
+    print(f"spacetime averaged spin {spin_count}: errs {['%.1e' % e for e in errs]}", flush=True)
+    assert max(errs) <= 1e-3
+    solver.close()
