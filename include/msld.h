@@ -72,7 +72,9 @@ typedef enum {
  *                 get an exact SVT: the LDS Jacobi tier, or the polar route for
  *                 blocks too large for LDS). Blocks up to 128 x 128 use a fused
  *                 one-kernel version. 0 selects the default (32); a negative value
- *                 disables the path. Results agree to rounding.
+ *                 disables the path. Blocks of 16 to 31 columns too tall for the LDS
+ *                 and panel tiers (more than about 4800 rows) take it as well.
+ *                 Results agree to rounding.
  *   kind[i]     : MSLD_KIND_BLOCK (0): block-wise nuclear norm over the partition;
  *                 MSLD_KIND_NOISE (1): the noise scale of Sec. 2, whose reshape takes
  *                 the whole matrix to an MN x 1 vector, so its norm is the Frobenius

@@ -149,8 +149,13 @@ msld_status make_plan(const msld_params* p, int ninst, Plan* pl) {
                      lds_fits(g.mb, g.nb) && lr_small_lds_bytes(sNB, sMB, sP) <= kLdsTierMax;
     // (narrower blocks take it only when the alternative would be the HBM panel tier)
     // (the orthonormalisation keeps p columns of nb in LDS: nb <= 2048)
-    bool lr = !lrs && lr_min > 0 && g.nb >= lr_min && g.nb <= 2048 &&
-              (g.nb >= 4 * kLRP || (g.nb >= 2 * kLRP && !lds_fits(g.mb, g.nb)));
+    // (tall blocks of 16..31 columns that fit neither LDS nor the panel tier take it too)
+    const bool panel_fits =
+        kLdsTierMax / 4 / (2 * ((size_t)(g.mb | 1) + (size_t)(g.nb | 1))) >= 4;
+    bool lr = !lrs && lr_min > 0 && g.nb <= 2048 &&
+              ((g.nb >= lr_min &&
+                (g.nb >= 4 * kLRP || (g.nb >= 2 * kLRP && !lds_fits(g.mb, g.nb)))) ||
+               (g.nb >= kLRP && !lds_fits(g.mb, g.nb) && !panel_fits));
     int tier;
     if (m == 1 && n == 1) tier = TIER_1X1;
     else if (reg_tier_shape(m, n)) tier = TIER_REG;

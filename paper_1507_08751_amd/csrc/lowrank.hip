@@ -928,7 +928,7 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, w.lrCount, 2);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  // G = B^T B
+  // G = B^T B (split-K for tall blocks)
   if (!tall_atb(w.pA, sB, nb, w.pA, sB, nb, mb, w.lrG, nb, sG, count, w.lrSplit, kSplitFloats,
                 st, &e)) {
     if ((e = gemm(h, rocblas_operation_transpose, rocblas_operation_none, nb, nb, mb, w.pA, mb,
@@ -978,12 +978,20 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
     return e;
   {
     (void)jtol;
-    const int64_t pstride = (int64_t)nb * nb / 2;   // doubles per slot in lrQ
+    // partials: lrQ (nb^2 floats per slot) when it holds one chunk of p^2 doubles, else
+    // the split-K buffer of tall blocks (free between the Gram and the coupling product)
+    int64_t pstride = (int64_t)nb * nb / 2;   // doubles per slot
+    double* part = reinterpret_cast<double*>(w.lrQ);
+    if (pstride < 256) {
+      if (!w.lrSplit || (int64_t)count * 256 > (int64_t)(kSplitFloats / 2))
+        return hipErrorInvalidValue;   // the plan gives blocks this narrow a split buffer
+      pstride = (int64_t)(kSplitFloats / 2) / count;
+      part = reinterpret_cast<double*>(w.lrSplit);
+    }
     int chunks = (mb + 511) / 512;
     if (chunks > pstride / 256) chunks = (int)(pstride / 256);
     const int rows = (mb + chunks - 1) / chunks;
     chunks = (mb + rows - 1) / rows;
-    double* part = reinterpret_cast<double*>(w.lrQ);
     hipLaunchKernelGGL(k_lr_gram64<P>, dim3(chunks, count), dim3(256), 0, st, w.lrC, mb, rows,
                        part, pstride);
     if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -196,6 +196,33 @@ def video_instance(H=144, W=176, T=192, objects=6, radius=6.0, seed=0, noise=0.0
     return Y.astype(np.float32)
 
 
+def spacetime_instance(H, W, T, blobs, rank=2, spikes=0.001, noise=0.01, seed=0):
+    """Stand-in for an image series as a (H W) x T matrix (pixel y W + x per row, one
+    frame or lighting condition per column): a global rank-`rank` term with positive
+    factors, rank-1 space-time blobs (`blobs` = list of (ph, pw, bt, count, amp): `count`
+    blobs on random ph x pw pixel patches over bt consecutive columns, not aligned to any
+    grid), sparse spikes at a fraction `spikes` of the entries, and noise. Used for the
+    face illumination (space-only blobs, bt = T) and DCE (contrast curves over time)
+    workloads of the paper, whose data are not available.
+
+    Returns Y as float32."""
+    rng = np.random.default_rng(seed)
+    M = H * W
+    Y = (rng.random((M, rank)) + 0.5) @ (rng.random((rank, T)) + 0.5) / rank
+    for (ph, pw, bt, count, amp) in blobs:
+        for _ in range(count):
+            y0, x0 = int(rng.integers(0, H - ph + 1)), int(rng.integers(0, W - pw + 1))
+            t0 = int(rng.integers(0, T - bt + 1))
+            pix = [(y0 + dy) * W + x0 + dx for dy in range(ph) for dx in range(pw)]
+            Y[np.ix_(pix, range(t0, t0 + bt))] += amp * np.outer(rng.standard_normal(ph * pw),
+                                                                rng.standard_normal(bt))
+    k = int(spikes * M * T)
+    if k:
+        Y.flat[rng.choice(M * T, k, replace=False)] += rng.choice([-3.0, 3.0], k)
+    Y += noise * rng.standard_normal((M, T))
+    return Y.astype(np.float32)
+
+
 def lcm_blocks(ladder):
     a, b = 1, 1
     for (m, n) in ladder:

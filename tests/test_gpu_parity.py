@@ -705,3 +705,38 @@ def test_admm_spacetime_averaged_spinning_parity(lib, spin_count):
     print(f"spacetime averaged spin {spin_count}: errs {['%.1e' % e for e in errs]}", flush=True)
     assert max(errs) <= 1e-3
     solver.close()
+
+
+SPACETIME_WORKLOADS = {
+    # face illumination stand-in: 192 x 168 pixels x 64 lighting conditions, space-only
+    # decimation (8 x 8 and 24 x 24 patches over all 64 columns)
+    "face": (192, 168, 64, [(1, 1), (64, 64), (576, 64), (192 * 168, 64)], [0, 2, 2, 0],
+             [1, 8, 24, 1], [(8, 8, 64, 40, 0.4), (24, 24, 64, 8, 0.2)]),
+    # DCE stand-in: a 160 x 112 slice (the paper's 154 rows padded to tile by 16) x 20
+    # contrast phases, 4 x 4 and 16 x 16 spatial blocks over all phases
+    "dce": (160, 112, 20, [(1, 1), (16, 20), (256, 20), (160 * 112, 20)], [0, 2, 2, 0],
+            [1, 4, 16, 1], [(4, 4, 20, 60, 1.0), (16, 16, 20, 10, 0.3)]),
+}
+
+
+@pytest.mark.parametrize("name", list(SPACETIME_WORKLOADS))
+def test_spacetime_workload_parity(lib, name):
+    """Full-size stand-ins of the face and DCE experiments (Sec. 10): 3 iterations with
+    cycle spinning against the oracle (1e-3)."""
+    from synth import spacetime_instance
+    H, W, T, ladder, kinds, pws, blobs = SPACETIME_WORKLOADS[name]
+    Y = spacetime_instance(H, W, T, blobs, seed=4)
+    M, N = H * W, T
+    ref = O.admm(Y.astype(np.float64), ladder, rho=1.0, iters=3, cycle_spin=True, seed=6,
+                 kinds=kinds, image_w=W, patch_w=pws)
+    solver = lib.Solver(M, N, ladder, rho=1.0, iters=3, cycle_spin=True, seed=6, kinds=kinds,
+                        image_w=W, patch_w=pws)
+    print(f"{name} tiers {[lib.TIERS[solver.tier(i)] for i in range(len(ladder))]}", flush=True)
+    Z, _ = solver.solve(torch.from_numpy(Y).cuda())
+    torch.cuda.synchronize()
+    Zg = Z.cpu().numpy()
+    errs = [rel_err(Zg[i], ref["Z"][i], np.linalg.norm(Y)) for i in range(len(ladder))]
+    print(f"{name}: errs {['%.1e' % e for e in errs]} norms "
+          f"{['%.1f' % np.linalg.norm(z) for z in ref['Z']]}", flush=True)
+    assert max(errs) <= 1e-3
+    solver.close()
