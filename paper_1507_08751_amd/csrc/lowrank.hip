@@ -459,11 +459,13 @@ __global__ void __launch_bounds__(256) k_lr_q(const float* Wg, const float* Vr, 
 template <int P>
 __global__ void __launch_bounds__(256) k_lr_ge(const float* G, const float* Qm, const float* Vr,
                                                const float* mask, float* Pm, int nb,
-                                               float* part, float* rowpart, const int* list) {
+                                               float* part, float* rowpart, const int* list,
+                                               const int* lcount) {
   __shared__ float qi[64][P + 1], vi[64][P + 1], qj[64][P + 1], vj[64][P + 1];
   __shared__ float mk[P];
   __shared__ float red[8];
   __shared__ float rs[4][64];
+  if (lcount && (int)blockIdx.y >= *lcount) return;
   const int slot = list ? list[blockIdx.y] : blockIdx.y;
   const int tn = (nb + 63) / 64;
   const int ti = blockIdx.x % tn, tj = blockIdx.x / tn;
@@ -526,7 +528,9 @@ __global__ void __launch_bounds__(256) k_lr_ge(const float* G, const float* Qm, 
 // k_lr_rsum: r_i = sum over tile columns of the row partials of k_lr_ge (slice tn);
 // k_lr_cwy: per 64 x 64 tile, partial y_i over its columns (slices 0..tn-1);
 // k_lr_cwmax: y_i, the ratio, its maximum; scal[4] = min(||M||_F, bound) / tr(M).
-__global__ void __launch_bounds__(256) k_lr_rsum(float* rowpart, int nb, const int* list) {
+__global__ void __launch_bounds__(256) k_lr_rsum(float* rowpart, int nb, const int* list,
+                                                 const int* lcount) {
+  if (lcount && (int)blockIdx.y >= *lcount) return;
   const int slot = list ? list[blockIdx.y] : blockIdx.y;
   const int tn = (nb + 63) / 64;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -538,9 +542,10 @@ __global__ void __launch_bounds__(256) k_lr_rsum(float* rowpart, int nb, const i
 }
 
 __global__ void __launch_bounds__(256) k_lr_cwy(const float* Pm, float* rowpart, int nb,
-                                                const int* list) {
+                                                const int* list, const int* lcount) {
   __shared__ float rj[64];
   __shared__ float ys[4][64];
+  if (lcount && (int)blockIdx.y >= *lcount) return;
   const int slot = list ? list[blockIdx.y] : blockIdx.y;
   const int tn = (nb + 63) / 64;
   const int ti = blockIdx.x % tn, tj = blockIdx.x / tn;
@@ -564,8 +569,9 @@ __global__ void __launch_bounds__(256) k_lr_cwy(const float* Pm, float* rowpart,
 }
 
 __global__ void __launch_bounds__(256) k_lr_cwmax(const float* rowpart, int nb, float* scal,
-                                                  const int* list) {
+                                                  const int* list, const int* lcount) {
   __shared__ float red[8];
+  if (lcount && (int)blockIdx.x >= *lcount) return;
   const int slot = list ? list[blockIdx.x] : blockIdx.x;
   const int tn = (nb + 63) / 64;
   const float* rp = rowpart + (int64_t)slot * nb * (tn + 1);
@@ -593,9 +599,9 @@ __global__ void __launch_bounds__(256) k_lr_cwmax(const float* rowpart, int nb, 
 // Reduce the per-tile partials of k_lr_ge in a fixed order: scal[2] = tr(E^T E),
 // scal[4] = ||E^T E||_F / tr(E^T E) (stage-0 bound factor).
 __global__ void k_lr_ge_reduce(const float* part, int tiles, int count, float* scal,
-                               const int* list) {
+                               const int* list, const int* lcount) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= count) return;
+  if (idx >= count || (lcount && idx >= *lcount)) return;
   const int slot = list ? list[idx] : idx;
   float tr = 0.f, f2 = 0.f;
   for (int t = 0; t < tiles; ++t) {
@@ -679,11 +685,11 @@ __global__ void k_lr_decide(int count, int slots, float* scal, const float* sig,
                             const float* dmask, float tau, int* pflag, int* counts, int* fall,
                             const int* live_list, unsigned long long* stats, int stage,
                             int power) {
-  // stage -1 walks all slots and lists the undecided ones at fall[3 slots ..]; stage 0
-  // walks that list and lists its undecided ones at fall[2 slots ..]; later stages walk
-  // that second list
+  // stage -1 walks all slots and lists the undecided ones at fall[3 slots ..] (their
+  // count ends in counts[2]); stage 0 walks that list and lists its undecided ones at
+  // fall[2 slots ..]; later stages walk that second list
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= count) return;
+  if (idx >= count || (stage == 0 && idx >= counts[2])) return;
   const int slot = stage < 0 ? idx : stage == 0 ? fall[3 * slots + idx] : fall[2 * slots + idx];
   const float* sc = scal + slot * 8;
   const float trG = sc[0], c2 = sc[1], trE = sc[2];
@@ -1017,20 +1023,21 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
                      tau, kCouplingTol, w.lrScal, mask, dmask);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // stage -1: the trace bound on lambda_max(E^T E) needs no E^T E; the slots it leaves
-  // undecided (listed at fall[3 slots ..]) get E^T E and its finer bounds
+  // undecided (listed at fall[3 slots ..], counted in counts[2]) get E^T E and its finer
+  // bounds. The launches below cover every slot and return early past that count, so
+  // the host does not wait for it.
   hipLaunchKernelGGL(k_lr_decide, dim3((count + 255) / 256), dim3(256), 0, st, count, w.slots,
                      w.lrScal, w.lrSig, dmask, tau, w.pflag, w.lrCount, w.lrFall, w.live_list,
                      w.stats, -1, 1);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = hipMemcpyAsync(w.hostInts + 1, w.lrCount + 1, sizeof(int), hipMemcpyDeviceToHost,
-                          st)) != hipSuccess)
-    return e;
-  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-  const int undF = w.hostInts[1];
-  int und = 0;
+  hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(64), 0, st, w.lrCount + 1, w.lrCount + 2);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, w.lrCount + 1, 1);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int* flist = w.lrFall + 3 * w.slots;
+  const int* fcount = w.lrCount + 2;
   const int tiles = (int)((sG + 255) / 256 < 64 ? (sG + 255) / 256 : 64);
-  if (undF > 0) {
-    const int* flist = w.lrFall + 3 * w.slots;
+  {
     // E^T E and its power bound: W = G V_r, H = V_r^T W (into lrQ), Q = W - V H / 2
     // (into lrY), E^T E = G - Q V^T - V Q^T (into lrP, partials into lrQ)
     if ((e = gemm(h, rocblas_operation_none, rocblas_operation_none, nb, P, nb, w.lrG, nb, sG,
@@ -1043,32 +1050,32 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
                        w.lrY, nb);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int gtiles = ((nb + 63) / 64) * ((nb + 63) / 64);
-    hipLaunchKernelGGL(k_lr_ge<P>, dim3(gtiles, undF), dim3(256), 0, st, w.lrG, w.lrY, w.lrV,
-                       dmask, w.lrP, nb, w.lrQ, w.lrRow, flist);
+    hipLaunchKernelGGL(k_lr_ge<P>, dim3(gtiles, count), dim3(256), 0, st, w.lrG, w.lrY, w.lrV,
+                       dmask, w.lrP, nb, w.lrQ, w.lrRow, flist, fcount);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // stage 0: Frobenius and Collatz-Wielandt bounds of E^T E (partials were written to lrQ)
-    hipLaunchKernelGGL(k_lr_ge_reduce, dim3((undF + 255) / 256), dim3(256), 0, st, w.lrQ,
-                       gtiles, undF, w.lrScal, flist);
+    hipLaunchKernelGGL(k_lr_ge_reduce, dim3((count + 255) / 256), dim3(256), 0, st, w.lrQ,
+                       gtiles, count, w.lrScal, flist, fcount);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_lr_rsum, dim3((nb + 255) / 256, undF), dim3(256), 0, st, w.lrRow, nb,
-                       flist);
+    hipLaunchKernelGGL(k_lr_rsum, dim3((nb + 255) / 256, count), dim3(256), 0, st, w.lrRow, nb,
+                       flist, fcount);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_lr_cwy, dim3(gtiles, undF), dim3(256), 0, st, w.lrP, w.lrRow, nb, flist);
+    hipLaunchKernelGGL(k_lr_cwy, dim3(gtiles, count), dim3(256), 0, st, w.lrP, w.lrRow, nb, flist,
+                       fcount);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_lr_cwmax, dim3(undF), dim3(256), 0, st, w.lrRow, nb, w.lrScal, flist);
+    hipLaunchKernelGGL(k_lr_cwmax, dim3(count), dim3(256), 0, st, w.lrRow, nb, w.lrScal, flist,
+                       fcount);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, w.lrCount + 1, 1);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_lr_decide, dim3((undF + 255) / 256), dim3(256), 0, st, undF, w.slots,
+    hipLaunchKernelGGL(k_lr_decide, dim3((count + 255) / 256), dim3(256), 0, st, count, w.slots,
                        w.lrScal, w.lrSig, dmask, tau, w.pflag, w.lrCount, w.lrFall, w.live_list,
                        w.stats, 0, 1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = hipMemcpyAsync(w.hostInts + 1, w.lrCount + 1, sizeof(int), hipMemcpyDeviceToHost,
-                            st)) != hipSuccess)
-      return e;
-    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-    und = w.hostInts[1];
   }
+  if ((e = hipMemcpyAsync(w.hostInts + 1, w.lrCount + 1, sizeof(int), hipMemcpyDeviceToHost,
+                          st)) != hipSuccess)
+    return e;
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+  const int und = w.hostInts[1];
   if (und > 0) {
     // stage 1: square of E^T E / tr(E^T E); stage 2: its fourth power (eighth in all),
     // on the undecided slots only, gathered to compact positions (lrQ, then lrP)

@@ -153,7 +153,7 @@ struct ScaleWork {
   float* lrRow;         // [slots][nb / 64 + 1][nb] row partials of |E^T E| and row sums
   float* lrOm;          // [nb*p] probe matrix
   float* lrSplit;       // [kSplitFloats] split-K partials of tall blocks (null: none)
-  int* lrCount;         // [4] device counters: fallback, undecided
+  int* lrCount;         // [4] device counters: fallback, undecided, undecided by the trace bound
   int* lrFall;          // [4 slots] block ids, then slot indices, of failed certificates;
                         // then the slots left undecided by the stage-0 bound; then those
                         // left undecided by the trace bound (stage -1)
@@ -246,6 +246,7 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
                        const ShiftSpec& sh, float jtol, int count, int* fallback_host,
                        hipStream_t st);
 __global__ void k_zero_ints(int* p, int n);
+__global__ void k_copy_count(const int* src, int* dst);
 // Per-instance sums (instance z = rows [z IM, (z+1) IM)): out[z].
 hipError_t launch_resid(const float* Dold, const float* R, const float* Z, int M, int N,
                         int L, int IM, int NI, double* partial, int nparts, double* out,
