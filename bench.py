@@ -278,14 +278,14 @@ def cpu_baseline(size, threads_env):
                       f"(same ladder/density/noise), {dt:.2f} s, scaled by {size}^2/8192^2"}
 
 
-def serve_bench(args):
+def serving_measure(nreq, nwarm, max_active, hbm_budget_gib, baseline=True):
     """Serving workload: a Poisson stream of decompositions of mixed sizes
     ({128^2, 512^2, 1024x256, 2048^2}, ratio-4 ladders of 4-6 scales ending in the
     full block, rank-1/rank-2 blocks at 2% + N(0, 0.01^2)), each retired at primal
     residual <= 1e-4 (cap 300 iterations, no cycle spinning). First the saturation
     rate of the continuous-batching server is measured with every request queued at
-    once; then the trace is replayed at 0.7 x that rate, and again with one request
-    at a time (FIFO) as the baseline."""
+    once; then the trace is replayed at 0.7 x that rate, and (baseline) again with one
+    request at a time (FIFO). Returns the figures as a dict."""
     import numpy as np
     import torch
     import paper_1507_08751_amd as msld
@@ -293,7 +293,6 @@ def serve_bench(args):
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    nreq, nwarm = args.requests, args.warm_requests
     trace = serving_trace(nreq + nwarm, rate=1.0, seed=0)
     log(f"serving: generating {len(trace)} requests ...")
     reqs = []
@@ -303,7 +302,7 @@ def serve_bench(args):
         reqs.append((t, torch.from_numpy(inst.Y).to(dev), lad))
 
     def run(active, rate, items):
-        srv = msld.Server(max_active=active, hbm_budget=args.hbm_budget << 30, num_streams=8,
+        srv = msld.Server(max_active=active, hbm_budget=hbm_budget_gib << 30, num_streams=8,
                           device=dev)
         t0 = time.perf_counter()
         arrivals = {}
@@ -334,30 +333,43 @@ def serve_bench(args):
 
     warm = reqs[:nwarm]
     meas = reqs[nwarm:]
-    run(args.max_active, None, warm)
-    span_sat, _, it_sat = run(args.max_active, None, meas)
+    run(max_active, None, warm)
+    span_sat, _, it_sat = run(max_active, None, meas)
     sat = len(meas) / span_sat
     rate = 0.7 * sat
     log(f"serving saturation: {sat:.2f} solves/s ({span_sat:.2f} s for {len(meas)})")
-    span, lat, iters = run(args.max_active, rate, meas)
+    span, lat, iters = run(max_active, rate, meas)
     l = np.array([lat[i] for i in range(len(meas))]) * 1e3
-    span1, lat1, _ = run(1, rate, meas)
-    l1 = np.array([lat1[i] for i in range(len(meas))]) * 1e3
-    out = {"metric": "served solves/s, p99 latency @ primal residual <= 1e-4 (cap 300)",
-           "value": round(len(meas) / span, 4), "unit": "solves/s", "n_gpus": 1,
-           "higher_is_better": True, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "Poisson requests, sizes {128^2, 512^2, 1024x256, 2048^2}, "
-                                  "ratio-4 ladders of 4-6 scales ending in the full block, "
-                                  "rank-1/2 blocks at 2% + N(0,0.01^2), tol 1e-4, cap 300",
-                      "requests": len(meas), "warmup_requests": nwarm,
-                      "arrival_rate": round(rate, 4), "max_active": args.max_active},
+    out = {"solves_per_s": round(len(meas) / span, 4),
            "saturation_solves_per_s": round(sat, 4),
            "p50_ms": round(float(np.percentile(l, 50)), 2),
            "p99_ms": round(float(np.percentile(l, 99)), 2),
            "mean_iters": round(float(np.mean([iters[i] for i in range(len(meas))])), 1),
-           "baseline_one_at_a_time": {"solves_per_s": round(len(meas) / span1, 4),
-                                      "p50_ms": round(float(np.percentile(l1, 50)), 2),
-                                      "p99_ms": round(float(np.percentile(l1, 99)), 2)}}
+           "requests": len(meas), "warmup_requests": nwarm, "arrival_rate": round(rate, 4),
+           "max_active": max_active,
+           "workload": "Poisson requests, sizes {128^2, 512^2, 1024x256, 2048^2}, ratio-4 "
+                       "ladders of 4-6 scales ending in the full block, rank-1/2 blocks at "
+                       "2% + N(0,0.01^2), retire at primal residual <= 1e-4, cap 300"}
+    if baseline:
+        span1, lat1, _ = run(1, rate, meas)
+        l1 = np.array([lat1[i] for i in range(len(meas))]) * 1e3
+        out["baseline_one_at_a_time"] = {"solves_per_s": round(len(meas) / span1, 4),
+                                         "p50_ms": round(float(np.percentile(l1, 50)), 2),
+                                         "p99_ms": round(float(np.percentile(l1, 99)), 2)}
+    return out
+
+
+def serve_bench(args):
+    """The serving workload on its own (serving_measure with the one-at-a-time
+    baseline), printed as its own JSON line."""
+    r = serving_measure(args.requests, args.warm_requests, args.max_active, args.hbm_budget)
+    out = {"metric": "served solves/s, p99 latency @ primal residual <= 1e-4 (cap 300)",
+           "value": r["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+           "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {k: r[k] for k in ("workload", "requests", "warmup_requests",
+                                        "arrival_rate", "max_active")},
+           **{k: r[k] for k in ("saturation_solves_per_s", "p50_ms", "p99_ms", "mean_iters",
+                                "baseline_one_at_a_time")}}
     print(json.dumps(out), flush=True)
 
 
@@ -444,6 +456,10 @@ def main():
     ap.add_argument("--warm-requests", type=int, default=8)
     ap.add_argument("--max-active", type=int, default=16)
     ap.add_argument("--hbm-budget", type=int, default=64, help="GiB")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the short serving measurement of the default run")
+    ap.add_argument("--serve-requests", type=int, default=16,
+                    help="requests of the default run's serving measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -528,6 +544,15 @@ def main():
                "stream_all": round(prof["stream_ms"] / K, 4),
                **{f"scale{i}_{m}x{n}_{tiers[i]}": [round(v / K, 4) for v in prof["scale_ms"][i]]
                   for i, (m, n) in enumerate(LADDER) if tiers[i] != "1x1"}}}
+    solver.close()
+    del Z, Y
+    torch.cuda.empty_cache()
+    if not args.no_serving:
+        # the served half of the metric: a short run of the serving workload (saturation,
+        # then Poisson arrivals at 0.7 x saturation); bench.py --mode serve runs it longer
+        # with the one-at-a-time baseline
+        out["serving"] = serving_measure(args.serve_requests, 4, args.max_active,
+                                         args.hbm_budget, baseline=False)
     if not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         log(f"cpu baseline: oracle on {args.cpu_sample}^2 with {threads} threads ...")
@@ -535,7 +560,6 @@ def main():
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
-    solver.close()
 
 
 if __name__ == "__main__":
