@@ -24,7 +24,6 @@ namespace {
 
 constexpr float kSmallCertMargin = 2e-3f;    // relative margin on tau^2
 constexpr float kSmallCouplingTol = 1e-5f;   // sum_L c_l^2 <= tol^2 ||B||_F^2
-constexpr int kNT = 256;                     // threads per workgroup
 
 __device__ __forceinline__ float wsum(float v) {
 #pragma unroll
@@ -32,6 +31,7 @@ __device__ __forceinline__ float wsum(float v) {
   return v;
 }
 
+template <int NT>
 __device__ __forceinline__ float bsum(float v, float* red) {
   v = wsum(v);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -40,10 +40,11 @@ __device__ __forceinline__ float bsum(float v, float* red) {
   __syncthreads();
   float s = 0.f;
 #pragma unroll
-  for (int w = 0; w < kNT / 64; ++w) s += red[w];
+  for (int w = 0; w < NT / 64; ++w) s += red[w];
   return s;
 }
 
+template <int NT>
 __device__ __forceinline__ float bmax(float v, float* red) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
@@ -53,17 +54,18 @@ __device__ __forceinline__ float bmax(float v, float* red) {
   __syncthreads();
   float s = 0.f;
 #pragma unroll
-  for (int w = 0; w < kNT / 64; ++w) s = fmaxf(s, red[w]);
+  for (int w = 0; w < NT / 64; ++w) s = fmaxf(s, red[w]);
   return s;
 }
 
 // C = A^T A for A with K rows and NB columns (column j at A + j * lda), C column-major
-// with leading dimension ldc. Each thread owns a TI x TI tile of interleaved rows and
-// columns (i = ti + 16 a, j = tj + 16 b).
-template <int NB>
+// with leading dimension ldc. Each of TG x TG threads owns a TI x TI tile of
+// interleaved rows and columns (i = ti + TG a, j = tj + TG b).
+template <int NB, int NT>
 __device__ __forceinline__ void ata(const float* A, int lda, int K, float* C, int ldc) {
-  constexpr int TI = NB / 16;
-  const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
+  constexpr int TG = NT == 256 ? 16 : 8;   // TG x TG threads, each a TI x TI tile
+  constexpr int TI = NB / TG;
+  const int ti = threadIdx.x % TG, tj = threadIdx.x / TG;
   float acc[TI][TI];
 #pragma unroll
   for (int a = 0; a < TI; ++a)
@@ -72,9 +74,9 @@ __device__ __forceinline__ void ata(const float* A, int lda, int K, float* C, in
   for (int r = 0; r < K; ++r) {
     float x[TI], y[TI];
 #pragma unroll
-    for (int a = 0; a < TI; ++a) x[a] = A[(ti + 16 * a) * lda + r];
+    for (int a = 0; a < TI; ++a) x[a] = A[(ti + TG * a) * lda + r];
 #pragma unroll
-    for (int b = 0; b < TI; ++b) y[b] = A[(tj + 16 * b) * lda + r];
+    for (int b = 0; b < TI; ++b) y[b] = A[(tj + TG * b) * lda + r];
 #pragma unroll
     for (int a = 0; a < TI; ++a)
 #pragma unroll
@@ -83,13 +85,13 @@ __device__ __forceinline__ void ata(const float* A, int lda, int K, float* C, in
 #pragma unroll
   for (int a = 0; a < TI; ++a)
 #pragma unroll
-    for (int b = 0; b < TI; ++b) C[(tj + 16 * b) * ldc + ti + 16 * a] = acc[a][b];
+    for (int b = 0; b < TI; ++b) C[(tj + TG * b) * ldc + ti + TG * a] = acc[a][b];
 }
 
 // Y = M X for the symmetric NB x NB matrix M (ld ldm) and X (NB x P, ld NB).
-template <int NB, int P>
+template <int NB, int P, int NT>
 __device__ __forceinline__ void sym_mul(const float* M, int ldm, const float* X, float* Y) {
-  for (int o = threadIdx.x; o < NB * P; o += kNT) {
+  for (int o = threadIdx.x; o < NB * P; o += NT) {
     const int l = o / NB, i = o - l * NB;
     const float* mi = M + i * ldm;   // column i = row i (symmetric)
     const float* xl = X + l * NB;
@@ -175,21 +177,21 @@ __device__ __forceinline__ void orth_w0(float* X) {
 }
 
 // Frobenius norm squared of the NB x NB matrix M (ld ldm).
-template <int NB>
+template <int NB, int NT>
 __device__ __forceinline__ float frob2(const float* M, int ldm, float* red) {
   float s = 0.f;
-  for (int o = threadIdx.x; o < NB * NB; o += kNT) {
+  for (int o = threadIdx.x; o < NB * NB; o += NT) {
     const int j = o / NB, i = o - j * NB;
     const float v = M[j * ldm + i];
     s += v * v;
   }
-  return bsum(s, red);
+  return bsum<NT>(s, red);
 }
 
 }  // namespace
 
-template <int NB, int MB, int P>
-__global__ void __launch_bounds__(kNT, 4) k_lr_small(float* __restrict__ Zout,
+template <int NB, int MB, int P, int NT>
+__global__ void __launch_bounds__(NT) k_lr_small(float* __restrict__ Zout,
                                                   float* __restrict__ Dout, ScaleGeom g,
                                                   ShiftSpec sh, float tau,
                                                   const int* __restrict__ live_count,
@@ -208,7 +210,7 @@ __global__ void __launch_bounds__(kNT, 4) k_lr_small(float* __restrict__ Zout,
   float* Ws = Xs + NB * P;          // NB x P: G X, then V_r
   float* Cs = Ws + NB * P;          // P x LDC: B X, then A_f
   float* Rj = Cs + P * LDC;         // P x LDW Jacobi rotations
-  __shared__ float red[kNT / 64];
+  __shared__ float red[NT / 64];
   __shared__ float sig[P], mask[P], dmask[P], cl[P], H[P * P];
   __shared__ float s_trG, s_omax, s_cross;
   __shared__ int s_state;
@@ -222,50 +224,50 @@ __global__ void __launch_bounds__(kNT, 4) k_lr_small(float* __restrict__ Zout,
     int sr, sc;
     block_shift(sh, p / g.PI, m, n, &sr, &sc);
     // B = V = -D' (written by the stream pass), logical column-major, zero-padded
-    for (int e = tid; e < NB * LDB; e += kNT) Bs[e] = 0.f;
+    for (int e = tid; e < NB * LDB; e += NT) Bs[e] = 0.f;
     __syncthreads();
-    for (int e = tid; e < m * n; e += kNT) {
+    for (int e = tid; e < m * n; e += NT) {
       const int i = e / n, j = e - i * n;
       const float v = -Dout[(int64_t)grow(g, p, i, sr) * N + gcol(g, q, j, sc)];
       if (!g.trans) Bs[j * LDB + i] = v;
       else Bs[i * LDB + j] = v;
     }
     __syncthreads();
-    ata<NB>(Bs, LDB, MB, Gs, LDG);
+    ata<NB, NT>(Bs, LDB, MB, Gs, LDG);
     __syncthreads();
     {
       float t = 0.f;
-      for (int i = tid; i < NB; i += kNT) t += Gs[i * LDG + i];
-      t = bsum(t, red);
+      for (int i = tid; i < NB; i += NT) t += Gs[i * LDG + i];
+      t = bsum<NT>(t, red);
       if (tid == 0) s_trG = t;
     }
     // X0 = orth(G Omega), Omega = fixed +-1 probe
-    for (int o = tid; o < NB * P; o += kNT) {
+    for (int o = tid; o < NB * P; o += NT) {
       const uint64_t z = mix64(0x243F6A8885A308D3ull + (uint64_t)o);
       Xs[o] = (z >> 63) ? 1.f : -1.f;
     }
     __syncthreads();
-    sym_mul<NB, P>(Gs, LDG, Xs, Ws);
+    sym_mul<NB, P, NT>(Gs, LDG, Xs, Ws);
     __syncthreads();
     orth_w0<NB, P>(Ws);
-    for (int o = tid; o < NB * P; o += kNT) Xs[o] = Ws[o];
+    for (int o = tid; o < NB * P; o += NT) Xs[o] = Ws[o];
     __syncthreads();
     for (int rep = 0; rep < 3; ++rep) {
-      sym_mul<NB, P>(Gs, LDG, Xs, Ws);
+      sym_mul<NB, P, NT>(Gs, LDG, Xs, Ws);
       __syncthreads();
-      sym_mul<NB, P>(Gs, LDG, Ws, Xs);
+      sym_mul<NB, P, NT>(Gs, LDG, Ws, Xs);
       __syncthreads();
       orth_w0<NB, P>(Xs);
     }
     // C = B X
-    for (int o = tid; o < MB * P; o += kNT) {
+    for (int o = tid; o < MB * P; o += NT) {
       const int l = o / MB, r = o - l * MB;
       float s = 0.f;
 #pragma unroll 8
       for (int k = 0; k < NB; ++k) s += Bs[k * LDB + r] * Xs[l * NB + k];
       Cs[l * LDC + r] = s;
     }
-    for (int o = tid; o < P * LDW; o += kNT) {
+    for (int o = tid; o < P * LDW; o += NT) {
       const int j = o / LDW, r = o - j * LDW;
       Rj[o] = (j == r) ? 1.f : 0.f;
     }
@@ -273,12 +275,12 @@ __global__ void __launch_bounds__(kNT, 4) k_lr_small(float* __restrict__ Zout,
     // one-sided Jacobi on the P columns of C (one wave per column pair)
     {
       const float rr_tol = 5.9604645e-8f * sqrtf((float)mb);
-      const int grp = tid >> 6, t = tid & 63;
-      const bool act = grp < P / 2;
+      const int t = tid & 63;
       for (int sw = 0; sw < 40; ++sw) {
         int rotated = 0;
         for (int rd = 0; rd < P - 1; ++rd) {
-          if (act) {
+          // pair group grp on wave grp mod (NT / 64)
+          for (int grp = tid >> 6; grp < P / 2; grp += NT / 64) {
             const int n1 = P - 1;
             const int pa = (grp == 0) ? 0 : 1 + (grp - 1 + rd) % n1;
             const int pb = 1 + (P - 2 - grp + rd) % n1;
@@ -322,13 +324,13 @@ __global__ void __launch_bounds__(kNT, 4) k_lr_small(float* __restrict__ Zout,
       }
     }
     // sigma_l = ||a_l||, V_r = X R (into Ws)
-    for (int l = tid >> 6; l < P; l += kNT / 64) {
+    for (int l = tid >> 6; l < P; l += NT / 64) {
       float s2 = 0.f;
       for (int r = tid & 63; r < MB; r += 64) s2 += Cs[l * LDC + r] * Cs[l * LDC + r];
       s2 = wsum(s2);
       if ((tid & 63) == 0) sig[l] = sqrtf(s2);
     }
-    for (int o = tid; o < NB * P; o += kNT) {
+    for (int o = tid; o < NB * P; o += NT) {
       const int l = o / NB, row = o - l * NB;
       float v = 0.f;
 #pragma unroll
@@ -337,7 +339,7 @@ __global__ void __launch_bounds__(kNT, 4) k_lr_small(float* __restrict__ Zout,
     }
     __syncthreads();
     // T = A_f^T B (P x NB, T[c P + l]) into Xs
-    for (int o = tid; o < NB * P; o += kNT) {
+    for (int o = tid; o < NB * P; o += NT) {
       const int c = o / P, l = o - c * P;
       float s = 0.f;
 #pragma unroll 8
@@ -346,7 +348,7 @@ __global__ void __launch_bounds__(kNT, 4) k_lr_small(float* __restrict__ Zout,
     }
     __syncthreads();
     // coupling per direction, deflation mask
-    for (int l = tid >> 6; l < P; l += kNT / 64) {
+    for (int l = tid >> 6; l < P; l += NT / 64) {
       const float s = sig[l];
       float acc = 0.f;
       if (s > 0.f) {
@@ -388,9 +390,9 @@ __global__ void __launch_bounds__(kNT, 4) k_lr_small(float* __restrict__ Zout,
     int state = s_state;   // 0 undecided, 1 certified, -1 coupling failure, -2 bound failure
     if (state == 0) {
       // Wg = G V_r into Xs; H = V_L^T Wg; Q = Wg - V_L H / 2 (in place, row by row)
-      sym_mul<NB, P>(Gs, LDG, Ws, Xs);
+      sym_mul<NB, P, NT>(Gs, LDG, Ws, Xs);
       __syncthreads();
-      for (int o = tid; o < P * P; o += kNT) {
+      for (int o = tid; o < P * P; o += NT) {
         const int l = o / P, k = o - l * P;
         float s = 0.f;
         if (dmask[l] > 0.f && dmask[k] > 0.f)
@@ -398,7 +400,7 @@ __global__ void __launch_bounds__(kNT, 4) k_lr_small(float* __restrict__ Zout,
         H[o] = s;
       }
       __syncthreads();
-      for (int i = tid; i < NB; i += kNT) {
+      for (int i = tid; i < NB; i += NT) {
         float q[P];
 #pragma unroll
         for (int k = 0; k < P; ++k) {
@@ -413,7 +415,7 @@ __global__ void __launch_bounds__(kNT, 4) k_lr_small(float* __restrict__ Zout,
       __syncthreads();
       // E^T E = G - Q V_L^T - V_L Q^T in place, with its trace and Frobenius norm
       float tr = 0.f, f2 = 0.f;
-      for (int o = tid; o < NB * NB; o += kNT) {
+      for (int o = tid; o < NB * NB; o += NT) {
         const int j = o / NB, i = o - j * NB;
         float s = Gs[j * LDG + i];
 #pragma unroll
@@ -424,26 +426,26 @@ __global__ void __launch_bounds__(kNT, 4) k_lr_small(float* __restrict__ Zout,
         if (i == j) tr += s;
         f2 += s * s;
       }
-      tr = bsum(tr, red);
-      f2 = bsum(f2, red);
+      tr = bsum<NT>(tr, red);
+      f2 = bsum<NT>(f2, red);
       // Collatz-Wielandt bound of |E^T E| with its row sums r: lambda_max <= max_i
       // (|E^T E| r)_i / r_i (r kept in Bs, free from here on)
       __syncthreads();
-      for (int i = tid; i < NB; i += kNT) {
+      for (int i = tid; i < NB; i += NT) {
         float v = 0.f;
         for (int j = 0; j < NB; ++j) v += fabsf(Gs[j * LDG + i]);
         Bs[i] = v;
       }
       __syncthreads();
       float cw = 0.f;
-      for (int i = tid; i < NB; i += kNT) {
+      for (int i = tid; i < NB; i += NT) {
         float y = 0.f;
         for (int j = 0; j < NB; ++j) y += fabsf(Gs[i * LDG + j]) * Bs[j];
         const float ri = Bs[i];
         if (ri > 0.f) cw = fmaxf(cw, y / ri);
         else if (y > 0.f) cw = __int_as_float(0x7f800000);
       }
-      cw = bmax(cw, red);
+      cw = bmax<NT>(cw, red);
       // lambda_max(E_L^T E_L) <= max(max_l' sigma_l'^2, lambda_max(E^T E)) + cross term,
       // l' the well-converged directions split off besides L, E the remainder after both
       const float omax = s_omax, cross = s_cross;
@@ -455,23 +457,23 @@ __global__ void __launch_bounds__(kNT, 4) k_lr_small(float* __restrict__ Zout,
       } else {
         // stage 1: (E^T E / tr)^2; stage 2: its fourth power (eighth in all)
         const float inv = 1.f / tr;
-        for (int o = tid; o < NB * NB; o += kNT) {
+        for (int o = tid; o < NB * NB; o += NT) {
           const int j = o / NB, i = o - j * NB;
           Gs[j * LDG + i] *= inv;
         }
         __syncthreads();
-        ata<NB>(Gs, LDG, NB, Bs, LDG);
+        ata<NB, NT>(Gs, LDG, NB, Bs, LDG);
         __syncthreads();
-        const float s1 = sqrtf(sqrtf(frob2<NB>(Bs, LDG, red)));
+        const float s1 = sqrtf(sqrtf(frob2<NB, NT>(Bs, LDG, red)));
         const float b1 = fmaxf(omax, tr * s1) + cross;
         if (b1 <= lim && isfinite(b1)) {
           state = 1;
         } else {
-          ata<NB>(Bs, LDG, NB, Gs, LDG);
+          ata<NB, NT>(Bs, LDG, NB, Gs, LDG);
           __syncthreads();
-          ata<NB>(Gs, LDG, NB, Bs, LDG);
+          ata<NB, NT>(Gs, LDG, NB, Bs, LDG);
           __syncthreads();
-          const float f8 = frob2<NB>(Bs, LDG, red);
+          const float f8 = frob2<NB, NT>(Bs, LDG, red);
           const float b2 = fmaxf(omax, tr * powf(f8, 1.f / 16.f)) + cross;
           state = (b2 <= lim && isfinite(b2)) ? 1 : -2;
         }
@@ -483,7 +485,7 @@ __global__ void __launch_bounds__(kNT, 4) k_lr_small(float* __restrict__ Zout,
     if (state == 1 && nlive > 0) {
       // Z = sum_L (1 - tau / sigma_l)_+ a_l v_l^T, scattered with D' = 2 Z' - V (with no
       // live direction the stream pass already wrote Z' = 0, D' = -V)
-      for (int e = tid; e < m * n; e += kNT) {
+      for (int e = tid; e < m * n; e += NT) {
         const int i = e / n, j = e - i * n;
         const int r = g.trans ? j : i;
         const int c = g.trans ? i : j;
@@ -545,27 +547,38 @@ hipError_t launch_lr_small(const ScaleGeom& g, ScaleWork& w, float* Zout, float*
   if (!lr_small_shape(g.mb, g.nb, &NB, &MB, &P)) return hipErrorInvalidValue;
   if (pass) P *= 2;   // pass 1: retry of the failures, pass 2: wide first pass
   const size_t lds = lr_small_lds_bytes(NB, MB, P);
+  // first passes over 32-wide blocks: one wave per workgroup (no barrier waits across
+  // waves, more blocks in flight per CU); 64-wide blocks and the retry pass (twice the
+  // column pairs): four waves
+  const int NT = (NB == 32 && pass != 1) ? 64 : 256;
   int per_cu = (int)(160 * 1024 / (lds + 2048));
-  if (per_cu > 8) per_cu = 8;
+  const int cap = NT == 64 ? 16 : 8;
+  if (per_cu > cap) per_cu = cap;
   if (pass == 1 && per_cu > 1) per_cu = 1;   // the retry list is short
   if (per_cu < 1) per_cu = 1;
   int grid = num_cus * per_cu;
   const int nblk = g.P * g.Q;
   if (grid > nblk) grid = nblk;
-#define MSLD_LRS(nb_, mb_, p_)                                                                  \
-  if (NB == nb_ && MB == mb_ && P == p_)                                                        \
-    hipLaunchKernelGGL((k_lr_small<nb_, mb_, p_>), dim3(grid), dim3(kNT), lds, st, Zout, Dout, \
-                       g, sh, tau, count, list, fcount, flist, w.stats)
-  MSLD_LRS(32, 32, 4);
-  else MSLD_LRS(32, 64, 4);
-  else MSLD_LRS(32, 128, 4);
-  else MSLD_LRS(32, 32, 8);
-  else MSLD_LRS(32, 64, 8);
-  else MSLD_LRS(32, 128, 8);
-  else MSLD_LRS(64, 64, 8);
-  else MSLD_LRS(64, 128, 8);
-  else MSLD_LRS(64, 64, 16);
-  else MSLD_LRS(64, 128, 16);
+#define MSLD_LRS(nb_, mb_, p_, nt_)                                                             \
+  if (NB == nb_ && MB == mb_ && P == p_ && NT == nt_)                                           \
+    hipLaunchKernelGGL((k_lr_small<nb_, mb_, p_, nt_>), dim3(grid), dim3(nt_), lds, st, Zout,  \
+                       Dout, g, sh, tau, count, list, fcount, flist, w.stats)
+  MSLD_LRS(32, 32, 4, 64);
+  else MSLD_LRS(32, 64, 4, 64);
+  else MSLD_LRS(32, 128, 4, 64);
+  else MSLD_LRS(32, 32, 8, 64);
+  else MSLD_LRS(32, 64, 8, 64);
+  else MSLD_LRS(32, 128, 8, 64);
+  else MSLD_LRS(32, 32, 4, 256);
+  else MSLD_LRS(32, 64, 4, 256);
+  else MSLD_LRS(32, 128, 4, 256);
+  else MSLD_LRS(32, 32, 8, 256);
+  else MSLD_LRS(32, 64, 8, 256);
+  else MSLD_LRS(32, 128, 8, 256);
+  else MSLD_LRS(64, 64, 8, 256);
+  else MSLD_LRS(64, 128, 8, 256);
+  else MSLD_LRS(64, 64, 16, 256);
+  else MSLD_LRS(64, 128, 16, 256);
   else return hipErrorInvalidValue;
 #undef MSLD_LRS
   return hipGetLastError();
