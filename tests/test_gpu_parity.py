@@ -740,3 +740,58 @@ def test_spacetime_workload_parity(lib, name):
           f"{['%.1f' % np.linalg.norm(z) for z in ref['Z']]}", flush=True)
     assert max(errs) <= 1e-3
     solver.close()
+
+
+_FULL = {}
+
+
+def _full_size_input():
+    if "Y" not in _FULL:
+        M = N = 8192
+        ladder = [(1, 1), (8, 8), (32, 32), (128, 128), (512, 512)]
+        _FULL["Y"] = make_instance(M, N, ladder, 0.01, noise=0.01, seed=0,
+                                   keep_components=False).Y
+    return _FULL["Y"]
+
+
+@pytest.mark.parametrize("m", [8, 32, 128, 512])
+def test_full_size_bsvt_sampled_parity(lib, m):
+    """At the benchmark's full size (8192 x 8192 input of the benchmark: 1% rank-1 blocks
+    per scale of 1/8/32/128/512 plus N(0, 0.01^2)), one BlockSVT call per decomposed
+    scale with a random shift and the default threshold, in the tier the benchmark uses;
+    sampled blocks (every live one among a random sample, plus the largest) against the
+    oracle's SVT of the same shifted block (1e-4 of the block)."""
+    M = N = 8192
+    V = _full_size_input()
+    rng = np.random.default_rng(m)
+    s = (int(rng.integers(0, m)), int(rng.integers(0, m)))
+    tau = O.default_lambda(M, N, m, m)
+    solver = lib.Solver(M, N, [(m, m)], iters=1)
+    print(f"full size {m}x{m}: tier {lib.TIERS[solver.tier(0)]}, shift {s}, tau {tau:.2f}",
+          flush=True)
+    Z = solver.bsvt(0, torch.from_numpy(V).cuda(), tau, s)
+    torch.cuda.synchronize()
+    Zs = O.shift(Z.cpu().numpy(), s)        # the shifted frame: block (p, q) is contiguous
+    Vs = O.shift(V.astype(np.float64), s)
+    nb = M // m
+    cand = {(int(p), int(q)) for p, q in rng.integers(0, nb, size=(40, 2))}
+    fro = np.sqrt((Vs.reshape(nb, m, nb, m) ** 2).sum(axis=(1, 3)))
+    for f in np.argsort(fro.ravel())[-8:]:          # the 8 largest blocks
+        cand.add((int(f // nb), int(f % nb)))
+    norms = {}
+    for (p, q) in cand:
+        norms[(p, q)] = np.linalg.norm(Vs[p * m:(p + 1) * m, q * m:(q + 1) * m], 2)
+    live = [b for b in cand if norms[b] > tau]
+    assert live, "the sample holds no live block"
+    checked = 0
+    worst = 0.0
+    for (p, q) in sorted(cand):
+        blk = Vs[p * m:(p + 1) * m, q * m:(q + 1) * m]
+        ref = O.svt(blk, tau)
+        got = Zs[p * m:(p + 1) * m, q * m:(q + 1) * m]
+        err = float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-3 * np.linalg.norm(blk)))
+        worst = max(worst, err)
+        checked += 1
+        assert err <= 1e-4, ((p, q), err)
+    print(f"  {checked} sampled blocks ({len(live)} live), worst rel err {worst:.2e}", flush=True)
+    solver.close()
