@@ -648,6 +648,7 @@ msld_status iterate_once(msld_solver* s, const float* d_Y, int64_t ldY, float* d
   auto issue = [&](int i) {
     float* Zi = d_Z + MN * i;
     rls[i] = 0;
+    (void)hipSetDevice(s->device);   // worker threads start on device 0
     if (!pl.spin[i]) {
       herr[i] = launch_scale(pl.geom[i], pl.tier[i], pl.sp[i], s->work[i], Zi, R, Zi,
                              Dn + MN * i, pl.tau_default[i], shs[i], jacobi_tol(pl.geom[i].mb),
@@ -1052,9 +1053,12 @@ struct msld_batch {
     msld_solver* s;
     float* Y;                   // stacked Y (members x M x N)
     float* Z;                   // stacked Z (L planes)
+    hipStream_t st;             // the class's own stream (classes run concurrently)
+    hipEvent_t done;            // end of the class's work in a solve
   };
   int n;
   hipStream_t st;
+  hipEvent_t ev_in = nullptr;   // the caller's stream position at the start of a solve
   std::vector<Cls> cls;
   std::vector<int> cls_of, slot_of;
 };
@@ -1065,9 +1069,88 @@ static void batch_destroy(msld_batch* b) {
     if (c.s) destroy_solver(c.s);
     if (c.Y) (void)hipFree(c.Y);
     if (c.Z) (void)hipFree(c.Z);
+    if (c.done) (void)hipEventDestroy(c.done);
+    if (c.st) (void)hipStreamDestroy(c.st);
   }
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   delete b;
 }
+
+}  // extern "C"
+
+// One class of a batch solve, on the class's stream: gather its instances, iterate,
+// scatter the components, fill the instances' results. MSLD_ENUMERIC when an instance
+// ended with a non-finite residual (the others still finish).
+static msld_status batch_solve_class(msld_batch* b, size_t ci, const float* const* d_Y,
+                                     const int64_t* ldY, float* const* d_Z, msld_result* info) {
+  auto& c = b->cls[ci];
+  msld_solver* s = c.s;
+  const msld_params& p = c.p;
+  const int ni = (int)c.members.size();
+  const size_t inst = (size_t)p.M * p.N;
+  const size_t MN = inst * ni;
+  MSLD_TRY(s, hipSetDevice(s->device));   // the calling thread may be a fresh worker
+  MSLD_TRY(s, hipStreamWaitEvent(c.st, b->ev_in, 0));
+  for (int z = 0; z < ni; ++z) {
+    const int i = c.members[z];
+    MSLD_TRY(s, hipMemcpy2DAsync(c.Y + inst * z, 4 * (size_t)p.N, d_Y[i], 4 * (size_t)ldY[i],
+                                 4 * (size_t)p.N, p.M, hipMemcpyDeviceToDevice, c.st));
+  }
+  msld_status st = reset_state(s, c.Z);
+  if (st != MSLD_OK) return st;
+  st = launch_ynorms(s, c.Y, p.N);
+  if (st != MSLD_OK) return st;
+  std::vector<int> active(ni, 1), iters(ni, 0);
+  std::vector<double> resid(ni, -1.0);
+  std::vector<int32_t> status(ni, MSLD_OK);
+  int n_active = ni;
+  for (int k = 0; k < p.max_iters && n_active > 0; ++k) {
+    const bool check = (p.tol > 0.f && (k + 1) % p.check_every == 0) || k + 1 == p.max_iters;
+    st = step_iteration(s, c.Y, p.N, c.Z, check);
+    if (st != MSLD_OK) return st;
+    for (int z = 0; z < ni; ++z)
+      if (active[z]) iters[z] = k + 1;
+    if (!check) continue;
+    MSLD_TRY(s, hipMemcpyAsync(s->host_res, dev_res(s), 16 * (size_t)ni, hipMemcpyDeviceToHost,
+                               c.st));
+    MSLD_TRY(s, hipStreamSynchronize(c.st));
+    for (int z = 0; z < ni; ++z) {
+      if (!active[z]) continue;
+      const double ny2 = s->host_res[ni + z] > 0 ? s->host_res[ni + z] : 1.0;
+      resid[z] = std::sqrt(s->host_res[z] / ny2);
+      const bool bad = !std::isfinite(resid[z]);
+      if (bad || (p.tol > 0.f && resid[z] <= (double)p.tol)) {
+        if (bad) status[z] = MSLD_ENUMERIC;
+        active[z] = 0;
+        --n_active;
+        MSLD_TRY(s, launch_set_int(s->d_active, z, 0, c.st));
+      }
+    }
+  }
+  msld_status result = MSLD_OK;
+  for (int z = 0; z < ni; ++z) {
+    const int i = c.members[z];
+    for (int l = 0; l < p.L; ++l)
+      MSLD_TRY(s, hipMemcpyAsync(d_Z[i] + inst * l, c.Z + MN * l + inst * z, 4 * inst,
+                                 hipMemcpyDeviceToDevice, c.st));
+    if (status[z] != MSLD_OK) result = (msld_status)status[z];
+  }
+  if (info) {
+    msld_result cls_info;
+    st = fill_stats(s, &cls_info);
+    if (st != MSLD_OK) return st;
+    for (int z = 0; z < ni; ++z) {
+      msld_result& r = info[c.members[z]];
+      r = cls_info;   // per-class kernel counters (shared by the class's instances)
+      r.iters = iters[z];
+      r.primal_resid = resid[z];
+      r.status = status[z];
+    }
+  }
+  return result;
+}
+
+extern "C" {
 
 msld_status msld_batch_create(int32_t n, const msld_params* params, void* hip_stream,
                               msld_batch** out) {
@@ -1093,6 +1176,8 @@ msld_status msld_batch_create(int32_t n, const msld_params* params, void* hip_st
       nc.p = params[i];
       nc.s = nullptr;
       nc.Y = nc.Z = nullptr;
+      nc.st = nullptr;
+      nc.done = nullptr;
       b->cls.push_back(nc);
       c = (int)b->cls.size() - 1;
     }
@@ -1100,9 +1185,19 @@ msld_status msld_batch_create(int32_t n, const msld_params* params, void* hip_st
     b->slot_of[i] = (int)b->cls[c].members.size();
     b->cls[c].members.push_back(i);
   }
+  if (hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess) {
+    b->ev_in = nullptr;
+    batch_destroy(b);
+    return MSLD_EDEVICE;
+  }
   for (auto& c : b->cls) {
     const int ni = (int)c.members.size();
-    msld_status st = create_solver(&c.p, ni, b->st, &c.s);
+    if (hipStreamCreateWithFlags(&c.st, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c.done, hipEventDisableTiming) != hipSuccess) {
+      batch_destroy(b);
+      return MSLD_EDEVICE;
+    }
+    msld_status st = create_solver(&c.p, ni, c.st, &c.s);
     if (st != MSLD_OK) {
       batch_destroy(b);
       return st;
@@ -1133,69 +1228,30 @@ msld_status msld_batch_solve(msld_batch* b, const float* const* d_Y, const int64
     const msld_params& p = b->cls[b->cls_of[i]].p;
     if (!d_Y[i] || !d_Z[i] || ldY[i] < p.N) return MSLD_EINVAL;
   }
-  msld_status result = MSLD_OK;
   if (info) std::memset(info, 0, sizeof(msld_result) * b->n);
-  for (auto& c : b->cls) {
-    msld_solver* s = c.s;
-    const msld_params& p = c.p;
-    const int ni = (int)c.members.size();
-    const size_t inst = (size_t)p.M * p.N;
-    const size_t MN = inst * ni;
-    for (int z = 0; z < ni; ++z) {
-      const int i = c.members[z];
-      MSLD_TRY(s, hipMemcpy2DAsync(c.Y + inst * z, 4 * (size_t)p.N, d_Y[i], 4 * (size_t)ldY[i],
-                                   4 * (size_t)p.N, p.M, hipMemcpyDeviceToDevice, b->st));
+  // every class starts after the caller's prior work on its stream, runs on its own
+  // stream from its own host thread (a class's host waits do not hold back the others),
+  // and the caller's stream waits for all of them at the end
+  if (hipEventRecord(b->ev_in, b->st) != hipSuccess) return MSLD_EDEVICE;
+  std::vector<msld_status> cres(b->cls.size(), MSLD_OK);
+  auto run_class = [&](size_t ci) { cres[ci] = batch_solve_class(b, ci, d_Y, ldY, d_Z, info); };
+  std::vector<std::thread> workers;
+  for (size_t ci = 1; ci < b->cls.size(); ++ci) {
+    try {
+      workers.emplace_back(run_class, ci);
+    } catch (...) {
+      run_class(ci);   // no thread available: run it here
     }
-    msld_status st = reset_state(s, c.Z);
-    if (st != MSLD_OK) return st;
-    st = launch_ynorms(s, c.Y, p.N);
-    if (st != MSLD_OK) return st;
-    std::vector<int> active(ni, 1), iters(ni, 0);
-    std::vector<double> resid(ni, -1.0);
-    std::vector<int32_t> status(ni, MSLD_OK);
-    int n_active = ni;
-    for (int k = 0; k < p.max_iters && n_active > 0; ++k) {
-      const bool check = (p.tol > 0.f && (k + 1) % p.check_every == 0) || k + 1 == p.max_iters;
-      st = step_iteration(s, c.Y, p.N, c.Z, check);
-      if (st != MSLD_OK) return st;
-      for (int z = 0; z < ni; ++z)
-        if (active[z]) iters[z] = k + 1;
-      if (!check) continue;
-      MSLD_TRY(s, hipMemcpyAsync(s->host_res, dev_res(s), 16 * (size_t)ni, hipMemcpyDeviceToHost,
-                                 b->st));
-      MSLD_TRY(s, hipStreamSynchronize(b->st));
-      for (int z = 0; z < ni; ++z) {
-        if (!active[z]) continue;
-        const double ny2 = s->host_res[ni + z] > 0 ? s->host_res[ni + z] : 1.0;
-        resid[z] = std::sqrt(s->host_res[z] / ny2);
-        const bool bad = !std::isfinite(resid[z]);
-        if (bad || (p.tol > 0.f && resid[z] <= (double)p.tol)) {
-          if (bad) status[z] = MSLD_ENUMERIC;
-          active[z] = 0;
-          --n_active;
-          MSLD_TRY(s, launch_set_int(s->d_active, z, 0, b->st));
-        }
-      }
-    }
-    for (int z = 0; z < ni; ++z) {
-      const int i = c.members[z];
-      for (int l = 0; l < p.L; ++l)
-        MSLD_TRY(s, hipMemcpyAsync(d_Z[i] + inst * l, c.Z + MN * l + inst * z, 4 * inst,
-                                   hipMemcpyDeviceToDevice, b->st));
-      if (status[z] != MSLD_OK) result = (msld_status)status[z];
-    }
-    if (info) {
-      msld_result cls_info;
-      st = fill_stats(s, &cls_info);
-      if (st != MSLD_OK) return st;
-      for (int z = 0; z < ni; ++z) {
-        msld_result& r = info[c.members[z]];
-        r = cls_info;   // per-class kernel counters (shared by the class's instances)
-        r.iters = iters[z];
-        r.primal_resid = resid[z];
-        r.status = status[z];
-      }
-    }
+  }
+  if (!b->cls.empty()) run_class(0);
+  for (auto& t : workers) t.join();
+  msld_status result = MSLD_OK;
+  for (size_t ci = 0; ci < b->cls.size(); ++ci) {
+    auto& c = b->cls[ci];
+    if (cres[ci] != MSLD_OK && (result == MSLD_OK || result == MSLD_ENUMERIC)) result = cres[ci];
+    if (hipEventRecord(c.done, c.st) != hipSuccess ||
+        hipStreamWaitEvent(b->st, c.done, 0) != hipSuccess)
+      result = MSLD_EDEVICE;
   }
   if (hipStreamSynchronize(b->st) != hipSuccess) return MSLD_EDEVICE;
   return result;
