@@ -14,6 +14,7 @@
 #include <cstring>
 #include <deque>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "runtime.h"
@@ -264,17 +265,34 @@ msld_status msld_server_step(msld_server* sv, int64_t* done_ids, int32_t* done_i
       c->stepped = true;
     }
   // 2. one iteration for every class with active slots, enqueued before any wait
+  // (classes whose iteration waits on the host run from worker threads, so that those
+  // waits do not delay the other classes' launches)
   std::vector<int32_t> failed(sv->cls.size(), MSLD_OK);
-  for (size_t i = 0; i < sv->cls.size(); ++i) {
+  auto issue = [&](size_t i) {
     msld_server::Cls* c = sv->cls[i];
-    if (c->nactive == 0) continue;
-    msld_status st = iterate_once(c->s, c->Y, c->p.N, c->Z, true);
+    msld_status st = hipSetDevice(c->s->device) == hipSuccess ? MSLD_OK : MSLD_EDEVICE;
+    if (st == MSLD_OK) st = iterate_once(c->s, c->Y, c->p.N, c->Z, true);
     if (st == MSLD_OK &&
         hipMemcpyAsync(c->s->host_res, dev_res(c->s), 16 * (size_t)c->slots,
                        hipMemcpyDeviceToHost, c->st) != hipSuccess)
       st = MSLD_EDEVICE;
     failed[i] = st;
+  };
+  std::vector<std::thread> workers;
+  for (size_t i = 0; i < sv->cls.size(); ++i) {
+    msld_server::Cls* c = sv->cls[i];
+    if (c->nactive == 0) continue;
+    if (c->s->graphable) {   // no host waits: issue from this thread
+      issue(i);
+      continue;
+    }
+    try {
+      workers.emplace_back(issue, i);
+    } catch (...) {
+      issue(i);
+    }
   }
+  for (auto& t : workers) t.join();
   // 3. residuals, retirement
   for (size_t i = 0; i < sv->cls.size(); ++i) {
     msld_server::Cls* c = sv->cls[i];
