@@ -694,20 +694,25 @@ __device__ __forceinline__ void rr_pair(int round, int k, int ncols, int* a, int
 // i < RPL (G * RPL >= arows, wrows), cached in registers for the step. The three
 // inner products are reduced across the G lanes with xor shuffles. Returns the
 // number of sweeps run; *any_rot tells whether any rotation was applied. All threads
-// of the workgroup must call it.
-template <int G, int RPL>
+// of the workgroup must call it. With SG > 0 the workgroup is one wavefront holding
+// 64 / SG independent matrices, one per group of SG lanes (lanes of a disabled group,
+// en == false, take part in the barriers only); the sweep loop then runs until every
+// group has converged, and a converged group's extra sweeps rotate nothing, so each
+// group's result and sweep count are those it would have alone.
+template <int G, int RPL, int SG = 0>
 __device__ int jacobi_sweeps(float* A, int lda, int arows, float* W, int ldw, int wrows,
-                             int ncols, int max_sweeps, float tol, int* any_rot) {
-  const int tid = threadIdx.x;
+                             int ncols, int max_sweeps, float tol, int* any_rot, bool en = true) {
+  const int tid = SG ? (int)(threadIdx.x % SG) : (int)threadIdx.x;
   const int npairs = ncols >> 1;
   const int grp = tid / G;
   const int t = tid - grp * G;
-  const bool act = grp < npairs;
+  const bool act = en && grp < npairs;
   const int n1 = ncols - 1;
   // round-robin schedule: pa = 0 or 1 + (grp - 1 + rd) mod n1, pb = 1 + (ncols - 2 - grp + rd) mod n1
   const int ia = grp - 1;
   const int ib = ncols - 2 - grp;
   int sweeps = 0;
+  [[maybe_unused]] bool done = false;
   *any_rot = 0;
   for (int sw = 0; sw < max_sweeps; ++sw) {
     int rotated = 0;
@@ -774,17 +779,31 @@ __device__ int jacobi_sweeps(float* A, int lda, int arows, float* W, int ldw, in
       }
       __syncthreads();
     }
-    ++sweeps;
-    if (!__syncthreads_or(rotated)) break;
-    *any_rot = 1;
+    if constexpr (SG == 0) {
+      ++sweeps;
+      if (!__syncthreads_or(rotated)) break;
+      *any_rot = 1;
+    } else {
+      const unsigned long long bal = __ballot(rotated);
+      const int sb = threadIdx.x / SG;
+      const bool mine = ((bal >> (sb * SG)) & ((1ull << SG) - 1ull)) != 0ull;
+      if (!done) {
+        ++sweeps;
+        if (mine) *any_rot = 1;
+        else done = true;
+      }
+      if (!__syncthreads_or(!done)) break;
+    }
   }
   return sweeps;
 }
 
 // ------------------------------------------------------------- LDS tier
-// One workgroup per live block (persistent over the live list). The logical block
-// B (block or its transpose, mb >= nb) and the rotation matrix W live in LDS.
-template <int G, int RPL>
+// One workgroup per live block (persistent over the live list), or, for blocks whose
+// pairs fill at most half a wavefront (BPW > 1), one wavefront of 64 lanes holding BPW
+// blocks, one per group of 64 / BPW lanes. The logical block B (block or its
+// transpose, mb >= nb) and the rotation matrix W live in LDS, one region per block.
+template <int G, int RPL, int BPW>
 __global__ void __launch_bounds__(1024) k_svd_lds(
     float* __restrict__ Zout, float* __restrict__ Dout, ScaleGeom g, ShiftSpec sh,
     float tau, float jtol, int max_sweeps, const int* __restrict__ live_count,
@@ -795,22 +814,26 @@ __global__ void __launch_bounds__(1024) k_svd_lds(
   const int nbp = (nb + 1) & ~1;
   const int lda = mb | 1;
   const int ldw = nb | 1;
-  float* A = smem;
+  constexpr int SG = BPW > 1 ? 64 / BPW : 0;
+  const int sb = BPW > 1 ? (int)threadIdx.x / SG : 0;
+  float* A = smem + sb * (nbp * lda + nbp * ldw + 2 * nbp);
   float* W = A + nbp * lda;
   float* gain = W + nbp * ldw;
   int* lcols = reinterpret_cast<int*>(gain + nbp);
-  __shared__ int s_k;
+  __shared__ int s_k[BPW];
   const int count = *live_count;
-  const int nt = blockDim.x;
-  const int tid = threadIdx.x;
-  for (int it = blockIdx.x; it < count; it += gridDim.x) {
-    const int blk = live_list[it];
+  const int nt = BPW > 1 ? SG : (int)blockDim.x;
+  const int tid = BPW > 1 ? (int)threadIdx.x - sb * SG : (int)threadIdx.x;
+  for (int base = blockIdx.x * BPW; base < count; base += gridDim.x * BPW) {
+    const int it = base + sb;
+    const bool valid = it < count;
+    const int blk = valid ? live_list[it] : 0;
     const int p = blk / Q;
     const int q = blk - p * Q;
     int sr, sc;
     block_shift(sh, p / g.PI, m, n, &sr, &sc);
     // gather V = -D' (written by the stream pass) into logical column-major B
-    for (int e = tid; e < m * n; e += nt) {
+    for (int e = tid; valid && e < m * n; e += nt) {
       const int i = e / n;
       const int j = e - i * n;
       const int64_t o = (int64_t)grow(g, p, i, sr) * N + gcol(g, q, j, sc);
@@ -818,35 +841,36 @@ __global__ void __launch_bounds__(1024) k_svd_lds(
       if (!trans) A[j * lda + i] = v;
       else A[i * lda + j] = v;
     }
-    if (nbp > nb)
+    if (valid && nbp > nb)
       for (int r = tid; r < mb; r += nt) A[nb * lda + r] = 0.f;
-    for (int e = tid; e < nbp * nb; e += nt) {
+    for (int e = tid; valid && e < nbp * nb; e += nt) {
       const int jj = e / nb;
       const int c = e - jj * nb;
       W[jj * ldw + c] = (jj == c) ? 1.f : 0.f;
     }
     __syncthreads();
     int any_rot;
-    const int sweeps = jacobi_sweeps<G, RPL>(A, lda, mb, W, ldw, nb, nbp, max_sweeps, jtol, &any_rot);
+    const int sweeps = jacobi_sweeps<G, RPL, SG>(A, lda, mb, W, ldw, nb, nbp, max_sweeps, jtol,
+                                                 &any_rot, valid);
     // singular values sigma_j = ||B w_j||, gains max(1 - tau/sigma_j, 0)  (eq:svt)
-    for (int jj = tid; jj < nb; jj += nt) {
+    for (int jj = tid; valid && jj < nb; jj += nt) {
       float s2 = 0.f;
       for (int r = 0; r < mb; ++r) s2 += A[jj * lda + r] * A[jj * lda + r];
       const float sig = sqrtf(s2);
       gain[jj] = sig > tau ? 1.f - tau / sig : 0.f;
     }
     __syncthreads();
-    if (tid == 0) {
+    if (valid && tid == 0) {
       int k = 0;
       for (int jj = 0; jj < nb; ++jj)
         if (gain[jj] > 0.f) lcols[k++] = jj;
-      s_k = k;
+      s_k[sb] = k;
       atomicAdd(&stats[0], 1ull);
       atomicAdd(&stats[1], (unsigned long long)sweeps);
       atomicAdd(&stats[2], (unsigned long long)k);
     }
     __syncthreads();
-    const int k = s_k;
+    const int k = valid ? s_k[sb] : 0;
     // rebuild B' = sum_j g_j (B w_j) w_j^T and scatter to the wrapped coordinates
     // (rank 0: the stream pass already wrote Z' = 0, D' = -V)
     for (int e = tid; k > 0 && e < m * n; e += nt) {
@@ -1097,15 +1121,35 @@ __global__ void __launch_bounds__(256) k_panel_rebuild(float* __restrict__ Zout,
 template <int G>
 static hipError_t launch_lds_g(int grid, int threads, size_t lds, float* Zout, float* Dout,
                                const ScaleGeom& g, const ShiftSpec& sh, float tau, float jtol,
-                               int max_sweeps, ScaleWork& w, hipStream_t st) {
+                               int max_sweeps, ScaleWork& w, hipStream_t st, int bpw = 1) {
   // rows per lane: G * RPL >= mb
   const int need = (g.mb + G - 1) / G;
+  if (bpw > 1) {
+    // several blocks per wavefront: lds holds bpw block regions
+    if constexpr (G <= 8) {
+      if (need > 8 || threads != 64 || ((g.nb + 1) / 2) * G > 64 / bpw) return hipErrorInvalidValue;
+      if (bpw == 2)
+        hipLaunchKernelGGL((k_svd_lds<G, 8, 2>), dim3(grid), dim3(64), lds, st, Zout, Dout, g,
+                           sh, tau, jtol, max_sweeps, w.live_count, w.live_list, w.stats);
+      else if (bpw == 4)
+        hipLaunchKernelGGL((k_svd_lds<G, 8, 4>), dim3(grid), dim3(64), lds, st, Zout, Dout, g,
+                           sh, tau, jtol, max_sweeps, w.live_count, w.live_list, w.stats);
+      else if (bpw == 8)
+        hipLaunchKernelGGL((k_svd_lds<G, 8, 8>), dim3(grid), dim3(64), lds, st, Zout, Dout, g,
+                           sh, tau, jtol, max_sweeps, w.live_count, w.live_list, w.stats);
+      else
+        return hipErrorInvalidValue;
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
   if (need <= 8)
-    hipLaunchKernelGGL((k_svd_lds<G, 8>), dim3(grid), dim3(threads), lds, st, Zout, Dout, g, sh,
-                       tau, jtol, max_sweeps, w.live_count, w.live_list, w.stats);
+    hipLaunchKernelGGL((k_svd_lds<G, 8, 1>), dim3(grid), dim3(threads), lds, st, Zout, Dout, g,
+                       sh, tau, jtol, max_sweeps, w.live_count, w.live_list, w.stats);
   else if (need <= 32)
-    hipLaunchKernelGGL((k_svd_lds<G, 32>), dim3(grid), dim3(threads), lds, st, Zout, Dout, g, sh,
-                       tau, jtol, max_sweeps, w.live_count, w.live_list, w.stats);
+    hipLaunchKernelGGL((k_svd_lds<G, 32, 1>), dim3(grid), dim3(threads), lds, st, Zout, Dout, g,
+                       sh, tau, jtol, max_sweeps, w.live_count, w.live_list, w.stats);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -1138,6 +1182,17 @@ int lds_tier_threads(int nb, int mb, int* G) {
   int threads = pairs * gg;
   threads = ((threads + 63) / 64) * 64;
   return threads;   // the plan only uses the LDS tier when this is <= 1024
+}
+
+static int lds_tier_pack(int nb, int mb) {
+  // blocks per wavefront: pairs * G lanes rounded up to a power of two (at least 8)
+  int G = 1;
+  const int threads = lds_tier_threads(nb, mb, &G);
+  const int lanes = ((nb + 1) / 2) * G;
+  if (threads != 64 || G > 8 || lanes > 32) return 1;
+  int sg = 8;
+  while (sg < lanes) sg *= 2;
+  return 64 / sg;
 }
 
 size_t lds_tier_bytes(int mb, int nb) {
@@ -1352,19 +1407,21 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
     MSLD_EV(2);
     int G = 1;
     const int threads = lds_tier_threads(g.nb, g.mb, &G);
-    const size_t lds = lds_tier_bytes(g.mb, g.nb);
+    const int bpw = lds_tier_pack(g.nb, g.mb);
+    const size_t lds = lds_tier_bytes(g.mb, g.nb) * bpw;
     int per_cu = (int)(160 * 1024 / (lds + 1024));
     const int by_waves = 32 / ((threads + 63) / 64);
     if (per_cu > by_waves) per_cu = by_waves;
     if (per_cu < 1) per_cu = 1;
     if (w.lds_cap > 0 && per_cu > w.lds_cap) per_cu = w.lds_cap;   // autotuned
     int grid = num_cus * per_cu;
-    if (grid > nblk) grid = nblk;
+    const int units = (nblk + bpw - 1) / bpw;
+    if (grid > units) grid = units;
     switch (G) {
-      case 1: e = launch_lds_g<1>(grid, threads, lds, Zout, Dout, g, sh, tau, jtol, max_sweeps, w, st); break;
-      case 2: e = launch_lds_g<2>(grid, threads, lds, Zout, Dout, g, sh, tau, jtol, max_sweeps, w, st); break;
-      case 4: e = launch_lds_g<4>(grid, threads, lds, Zout, Dout, g, sh, tau, jtol, max_sweeps, w, st); break;
-      case 8: e = launch_lds_g<8>(grid, threads, lds, Zout, Dout, g, sh, tau, jtol, max_sweeps, w, st); break;
+      case 1: e = launch_lds_g<1>(grid, threads, lds, Zout, Dout, g, sh, tau, jtol, max_sweeps, w, st, bpw); break;
+      case 2: e = launch_lds_g<2>(grid, threads, lds, Zout, Dout, g, sh, tau, jtol, max_sweeps, w, st, bpw); break;
+      case 4: e = launch_lds_g<4>(grid, threads, lds, Zout, Dout, g, sh, tau, jtol, max_sweeps, w, st, bpw); break;
+      case 8: e = launch_lds_g<8>(grid, threads, lds, Zout, Dout, g, sh, tau, jtol, max_sweeps, w, st, bpw); break;
       case 16: e = launch_lds_g<16>(grid, threads, lds, Zout, Dout, g, sh, tau, jtol, max_sweeps, w, st); break;
       default: e = launch_lds_g<32>(grid, threads, lds, Zout, Dout, g, sh, tau, jtol, max_sweeps, w, st); break;
     }
