@@ -232,6 +232,9 @@ msld_status make_plan(const msld_params* p, int ninst, Plan* pl) {
       sp.spb = sp.cst * ((m + sp.rch - 1) / sp.rch);
       sp.spr = g.Q * sp.spb;
     }
+    // a bfloat16 tile of 16 KiB or more leaves room for few workgroups per compute unit:
+    // 512 threads each then keep twice the loads in flight for the same LDS
+    sp.nt = (sp.rowbound && (size_t)m * (sp.ws + 1) * 2 >= 16384) ? 512 : 256;
     if (stream_lds_bytes(m, sp) > kLdsTierMax) return MSLD_EINVAL;
     pl->off_count[i] = take(4);
     pl->off_list[i] = take(4 * (size_t)nblk);

@@ -421,7 +421,8 @@ bool reg_tier_shape(int m, int n) {
 // bound exceeds tau enter the live list; the SVD pass later reads their V back
 // from D' = -V and overwrites both outputs.
 // A workgroup handles all m rows of one block row and a strip of `w` columns.
-// One strip (item) of one scale; smem is the workgroup's dynamic LDS.
+// One strip (item) of one scale; smem is the workgroup's dynamic LDS; NT threads.
+template <int NT>
 __device__ __forceinline__ void stream_strip(
     int item, const float* __restrict__ Zin, const float* __restrict__ R,
     float* __restrict__ Zout, float* __restrict__ Dout, const ScaleGeom& g,
@@ -462,7 +463,7 @@ __device__ __forceinline__ void stream_strip(
       // empty strip (aligned layout): zero partials for the bound
       const int64_t blk = (int64_t)p * Q + q0;
       if (sp.rowbound)
-        for (int r = threadIdx.x; r < m; r += 256) rowpart[(blk * sp.spb + part) * m + r] = 0.f;
+        for (int r = threadIdx.x; r < m; r += NT) rowpart[(blk * sp.spb + part) * m + r] = 0.f;
       if (threadIdx.x == 0) fropart[blk * sp.spb + part] = 0.f;
       return;
     }
@@ -472,16 +473,16 @@ __device__ __forceinline__ void stream_strip(
   // are accumulated from the float values while they stream through.
   const int ldt = w + 1;
   unsigned short* tile = reinterpret_cast<unsigned short*>(smem);   // m x ldt
-  float* pcs = smem + (sp.rowbound ? ((m * ldt + 1) >> 1) : 0);  // 256 partial column |.| sums
-  float* pcq = pcs + 256;                   // 256 partial column squares
-  float* cs = pcq + 256;                    // w column sums
+  float* pcs = smem + (sp.rowbound ? ((m * ldt + 1) >> 1) : 0);  // NT partial column |.| sums
+  float* pcq = pcs + NT;                    // NT partial column squares
+  float* cs = pcq + NT;                     // w column sums
   float* cq = cs + sp.ws + 1;               // w column squares
   unsigned* smax = reinterpret_cast<unsigned*>(cq + sp.ws + 1);  // nq row maxima
   const int tid = threadIdx.x;
   // strips are at most 256 columns wide (the plan caps them): thread (row group rq,
   // column c) walks rows rq, rq + rpp, ...; kU rows are loaded before any is stored,
   // so every thread keeps 2 kU loads in flight
-  const int rpp = 256 / w;
+  const int rpp = NT / w;
   {
     constexpr int kU = 8;
     const int c = tid % w;
@@ -550,7 +551,7 @@ __device__ __forceinline__ void stream_strip(
   // weighted row sums per (row, block segment)
   const int segw = sp.whole ? n : w;
   const int npairs = sp.rowbound ? m * nq : 0;
-  for (int e = tid; e < npairs; e += 256) {
+  for (int e = tid; e < npairs; e += NT) {
     const int s = e / m;
     const int r = e - s * m;
     const unsigned short* row = tile + r * ldt + s * segw;
@@ -582,19 +583,21 @@ __device__ __forceinline__ void stream_strip(
   }
 }
 
-__global__ void __launch_bounds__(256) k_stream(
+template <int NT>
+__global__ void __launch_bounds__(NT) k_stream(
     const float* __restrict__ Zin, const float* __restrict__ R, float* __restrict__ Zout,
     float* __restrict__ Dout, ScaleGeom g, StreamPlan sp, ShiftSpec sh, float tau2lim,
     int* __restrict__ live_count, int* __restrict__ live_list, float* __restrict__ rowpart,
     float* __restrict__ fropart) {
   extern __shared__ float smem[];
-  stream_strip(blockIdx.x, Zin, R, Zout, Dout, g, sp, sh, tau2lim, live_count, live_list,
+  stream_strip<NT>(blockIdx.x, Zin, R, Zout, Dout, g, sp, sh, tau2lim, live_count, live_list,
                rowpart, fropart, smem);
 }
 
 // The stream pass of every decomposed scale in one launch: workgroup b takes item
 // b - first[i] of the scale i whose item range holds b.
-__global__ void __launch_bounds__(256) k_stream_all(StreamAll a, const float* __restrict__ Z,
+template <int NT>
+__global__ void __launch_bounds__(NT) k_stream_all(StreamAll a, const float* __restrict__ Z,
                                                     const float* __restrict__ R,
                                                     float* __restrict__ D, ShiftSpec sh) {
   extern __shared__ float smem[];
@@ -605,7 +608,7 @@ __global__ void __launch_bounds__(256) k_stream_all(StreamAll a, const float* __
   ShiftSpec shi = sh;
   shi.scale = d.scale;
   const size_t off = a.plane * (size_t)d.scale;
-  stream_strip(b - a.first[i], Z + off, R, const_cast<float*>(Z) + off, D + off, d.g, d.sp, shi,
+  stream_strip<NT>(b - a.first[i], Z + off, R, const_cast<float*>(Z) + off, D + off, d.g, d.sp, shi,
                d.tau2lim, d.live_count, d.live_list, d.rowpart, d.fropart, smem);
 }
 
@@ -631,7 +634,10 @@ hipError_t launch_stream_all(const StreamAll& a, const float* Z, const float* R,
     b.first[0] = 0;
     b.first[1] = a.first[i + 1] - a.first[i];
     const size_t lds = stream_lds_bytes(a.s[i].g.m, a.s[i].sp);
-    hipLaunchKernelGGL(k_stream_all, dim3(b.first[1]), dim3(256), lds, st, b, Z, R, D, sh);
+    if (a.s[i].sp.nt == 512)
+      hipLaunchKernelGGL(k_stream_all<512>, dim3(b.first[1]), dim3(512), lds, st, b, Z, R, D, sh);
+    else
+      hipLaunchKernelGGL(k_stream_all<256>, dim3(b.first[1]), dim3(256), lds, st, b, Z, R, D, sh);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
@@ -1201,10 +1207,10 @@ size_t lds_tier_bytes(int mb, int nb) {
 }
 
 size_t stream_lds_bytes(int m, const StreamPlan& sp) {
-  // bfloat16 tile (m x (ws + 1), only for the row bound), then 512 + 2 (ws + 1) + ws + 1
+  // bfloat16 tile (m x (ws + 1), only for the row bound), then 2 nt + 2 (ws + 1) + ws + 1
   // floats
   const size_t tile = sp.rowbound ? ((size_t)m * (sp.ws + 1) + 1) / 2 : 0;
-  return (size_t)4 * (tile + 512 + 2 * (sp.ws + 1) + sp.ws + 1);
+  return (size_t)4 * (tile + 2 * (size_t)sp.nt + 2 * (sp.ws + 1) + sp.ws + 1);
 }
 
 #define MSLD_EV(i)                                                    \
@@ -1325,8 +1331,14 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
       hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, w.live_count);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       const size_t lds = stream_lds_bytes(g.m, sp);
-      hipLaunchKernelGGL(k_stream, dim3(g.P * sp.spr), dim3(256), lds, st, Zin, R, Zout, Dout,
-                         g, sp, sh, tau2lim, w.live_count, w.live_list, w.rowpart, w.fropart);
+      if (sp.nt == 512)
+        hipLaunchKernelGGL(k_stream<512>, dim3(g.P * sp.spr), dim3(512), lds, st, Zin, R, Zout,
+                           Dout, g, sp, sh, tau2lim, w.live_count, w.live_list, w.rowpart,
+                           w.fropart);
+      else
+        hipLaunchKernelGGL(k_stream<256>, dim3(g.P * sp.spr), dim3(256), lds, st, Zin, R, Zout,
+                           Dout, g, sp, sh, tau2lim, w.live_count, w.live_list, w.rowpart,
+                           w.fropart);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     MSLD_EV(1);

@@ -188,6 +188,7 @@ struct StreamPlan {
   int align;     // 1: strip edges on global 32-column (128-byte) boundaries: the first
                  // strip of a block takes the columns up to the first boundary, so
                  // cst = ceil(n / ws) + 1 and a strip may be empty
+  int nt;        // threads per workgroup, 256 or 512
 };
 
 // Stream pass of every decomposed scale in one launch (kernel argument; plane i of a
