@@ -340,7 +340,7 @@ __global__ void __launch_bounds__(256) k_tiny_live(
             be += a[i][qq] * a[i][qq];
             ga += a[i][pp] * a[i][qq];
           }
-          if (fabsf(ga) > jtol * sqrtf(al) * sqrtf(be)) {
+          if (jacobi_rotates(ga, al, be, jtol)) {
             rot = true;
             const float zeta = (be - al) / (2.f * ga);
             const float t = (fabsf(zeta) > 1e18f)
@@ -751,7 +751,7 @@ __device__ int jacobi_sweeps(float* A, int lda, int arows, float* W, int ldw, in
         be += __shfl_xor(be, o);
         ga += __shfl_xor(ga, o);
       }
-      if (act && fabsf(ga) > tol * sqrtf(al) * sqrtf(be)) {
+      if (act && jacobi_rotates(ga, al, be, tol)) {
         rotated = 1;
         const float zeta = (be - al) / (2.f * ga);
         const float tt = (fabsf(zeta) > 1e18f)

@@ -296,7 +296,7 @@ __global__ void __launch_bounds__(NT) k_lr_small(float* __restrict__ Zout,
             al = wsum(al);
             be = wsum(be);
             ga = wsum(ga);
-            if (fabsf(ga) > rr_tol * sqrtf(al) * sqrtf(be)) {
+            if (jacobi_rotates(ga, al, be, rr_tol)) {
               rotated = 1;
               const float zeta = (be - al) / (2.f * ga);
               const float tt = (fabsf(zeta) > 1e18f)

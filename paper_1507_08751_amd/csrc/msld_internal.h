@@ -57,6 +57,13 @@ __device__ inline void block_shift(const ShiftSpec& s, int z, int m, int n, int*
   }
 }
 
+// One-sided Jacobi rotation test for a column pair with squared norms al, be and inner
+// product ga: rotate while |ga| > tol sqrt(al) sqrt(be). A threshold needs no correctly
+// rounded square root, so the hardware one (one instruction) serves.
+__device__ inline bool jacobi_rotates(float ga, float al, float be, float tol) {
+  return fabsf(ga) > tol * __builtin_amdgcn_sqrtf(al) * __builtin_amdgcn_sqrtf(be);
+}
+
 __device__ inline bool inst_active(const ShiftSpec& s, int z) {
   return s.iactive == nullptr || s.iactive[z] != 0;
 }
