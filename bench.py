@@ -21,6 +21,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# The solver runs each scale (and a batch each shape class) on a HIP stream of its own;
+# streams only run side by side on hardware queues of their own, and HIP's default of
+# 4 queues per process puts several of them on one. Read once, when HIP initialises,
+# so it is set before torch is imported.
+HW_QUEUES = "16"
+os.environ["GPU_MAX_HW_QUEUES"] = HW_QUEUES
+
 METRIC = "ADMM iters/s (8192², 5 scales) + served solves/s, p99 lat @ relerr≤1e-3"
 LADDER = [(1, 1), (8, 8), (32, 32), (128, 128), (512, 512)]
 DENSITY = 0.01
@@ -537,7 +544,8 @@ def main():
            "config": {"workload": f"ADMM on {M}x{N} fp32, blocks 1/8/32/128/512, 1% active "
                                   f"rank-1 blocks per scale + N(0,0.01^2) noise, default lambda, "
                                   f"rho=1, random cycle spinning, {K} iterations from zero",
-                      "M": M, "N": N, "ladder": [list(b) for b in LADDER], "iters": K},
+                      "M": M, "N": N, "ladder": [list(b) for b in LADDER], "iters": K,
+                      "hw_queues": int(HW_QUEUES)},
            "roofline": roof, "roofline_consensus": extra,
            "phases_ms_per_iter": {
                "consensus": round(prof["consensus_ms"] / K, 4),

@@ -4,6 +4,11 @@ Argument marshalling only: every step of the ADMM / block-wise SVT iteration run
 in the library's HIP kernels. PyTorch supplies device memory and the stream.
 There is no CPU fallback: without the built library (``python -m
 paper_1507_08751_amd.build``) every call raises.
+
+A solver runs each scale on a HIP stream of its own (a batch: each shape class, a
+server: each active class). Streams only run side by side on hardware queues of their
+own, so set ``GPU_MAX_HW_QUEUES`` (HIP's default is 4 per process) to 16 or so before
+HIP initialises, i.e. before torch is imported.
 """
 from __future__ import annotations
 

@@ -4,6 +4,9 @@ import sys
 # the oracle works on many tiny matrices: threaded BLAS only adds overhead there
 for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
     os.environ.setdefault(_v, "1")
+# the hardware queue count the benchmark runs with: every scale stream (and batch class)
+# then runs on a queue of its own, so the tests see the same concurrency
+os.environ["GPU_MAX_HW_QUEUES"] = "16"
 
 import pytest
 
