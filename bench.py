@@ -23,10 +23,9 @@ if ROOT not in sys.path:
 
 # The solver runs each scale (and a batch each shape class) on a HIP stream of its own;
 # streams only run side by side on hardware queues of their own, and HIP's default of
-# 4 queues per process puts several of them on one. Read once, when HIP initialises,
-# so it is set before torch is imported.
-HW_QUEUES = "16"
-os.environ["GPU_MAX_HW_QUEUES"] = HW_QUEUES
+# 4 queues per process puts several of them on one. HIP reads the count once, when it
+# initialises, so main() sets it (--hw-queues) before anything imports torch.
+HW_QUEUES = 16
 
 METRIC = "ADMM iters/s (8192², 5 scales) + served solves/s, p99 lat @ relerr≤1e-3"
 LADDER = [(1, 1), (8, 8), (32, 32), (128, 128), (512, 512)]
@@ -463,11 +462,18 @@ def main():
     ap.add_argument("--warm-requests", type=int, default=8)
     ap.add_argument("--max-active", type=int, default=16)
     ap.add_argument("--hbm-budget", type=int, default=64, help="GiB")
+    ap.add_argument("--hw-queues", type=int, default=16,
+                    help="hardware queues per process (GPU_MAX_HW_QUEUES), 1..32")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the short serving measurement of the default run")
     ap.add_argument("--serve-requests", type=int, default=16,
                     help="requests of the default run's serving measurement")
     args = ap.parse_args()
+    if not 1 <= args.hw_queues <= 32:
+        ap.error("--hw-queues must be in 1..32")
+    global HW_QUEUES
+    HW_QUEUES = args.hw_queues
+    os.environ["GPU_MAX_HW_QUEUES"] = str(HW_QUEUES)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -545,7 +551,7 @@ def main():
                                   f"rank-1 blocks per scale + N(0,0.01^2) noise, default lambda, "
                                   f"rho=1, random cycle spinning, {K} iterations from zero",
                       "M": M, "N": N, "ladder": [list(b) for b in LADDER], "iters": K,
-                      "hw_queues": int(HW_QUEUES)},
+                      "hw_queues": HW_QUEUES},
            "roofline": roof, "roofline_consensus": extra,
            "phases_ms_per_iter": {
                "consensus": round(prof["consensus_ms"] / K, 4),

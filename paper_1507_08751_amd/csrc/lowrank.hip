@@ -455,7 +455,9 @@ __global__ void __launch_bounds__(256) k_lr_q(const float* Wg, const float* Vr, 
 
 // E^T E = G - Q V^T - V Q^T (masked columns of V_r) on 64 x 64 tiles, to Pm, with
 // per-tile partial trace and squared Frobenius norm. Q and V rows of the tile's row
-// and column ranges are staged in LDS.
+// and column ranges are staged in LDS; each thread accumulates a 2 x 8 block (rows
+// i0 + il + 32 a, columns j0 + jg + 8 b), so one LDS value feeds several FMAs, and
+// each wave reads and writes 128-byte column segments of G and Pm.
 template <int P>
 __global__ void __launch_bounds__(256) k_lr_ge(const float* G, const float* Qm, const float* Vr,
                                                const float* mask, float* Pm, int nb,
@@ -464,7 +466,7 @@ __global__ void __launch_bounds__(256) k_lr_ge(const float* G, const float* Qm, 
   __shared__ float qi[64][P + 1], vi[64][P + 1], qj[64][P + 1], vj[64][P + 1];
   __shared__ float mk[P];
   __shared__ float red[8];
-  __shared__ float rs[4][64];
+  __shared__ float rs[8][64];
   if (lcount && (int)blockIdx.y >= *lcount) return;
   const int slot = list ? list[blockIdx.y] : blockIdx.y;
   const int tn = (nb + 63) / 64;
@@ -487,39 +489,56 @@ __global__ void __launch_bounds__(256) k_lr_ge(const float* G, const float* Qm, 
     vj[r][l] = (m && rj < nb) ? v[l * nb + rj] : 0.f;
   }
   __syncthreads();
-  const int il = tid & 63;
-  const int i = i0 + il;
-  float qa[P], va[P];
+  const int il = tid & 31;
+  const int jg = tid >> 5;
+  float acc[2][8];
 #pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) acc[a][b] = 0.f;
+#pragma unroll 4
   for (int l = 0; l < P; ++l) {
-    qa[l] = qi[il][l];
-    va[l] = vi[il][l];
-  }
-  float tr = 0.f, f2 = 0.f, ra = 0.f;
-  if (i < nb) {
-    for (int jl = tid >> 6; jl < 64; jl += 4) {
-      const int j = j0 + jl;
-      if (j >= nb) break;
-      float s = g[(int64_t)j * nb + i];
+    const float qa0 = qi[il][l], qa1 = qi[il + 32][l];
+    const float va0 = vi[il][l], va1 = vi[il + 32][l];
 #pragma unroll
-      for (int l = 0; l < P; ++l) s -= qa[l] * vj[jl][l] + va[l] * qj[jl][l];
-      pm[(int64_t)j * nb + i] = s;
-      if (i == j) tr += s;
-      f2 += s * s;
-      ra += fabsf(s);
+    for (int b = 0; b < 8; ++b) {
+      const float qb = qj[jg + 8 * b][l], vb = vj[jg + 8 * b][l];
+      acc[0][b] += qa0 * vb + va0 * qb;
+      acc[1][b] += qa1 * vb + va1 * qb;
     }
   }
-  rs[tid >> 6][il] = ra;
-  tr = block_sum(tr, red);
+  float tr = 0.f, f2 = 0.f;
+  float ra[2] = {0.f, 0.f};
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const int i = i0 + il + 32 * a;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int j = j0 + jg + 8 * b;
+      if (i < nb && j < nb) {
+        const float sv = g[(int64_t)j * nb + i] - acc[a][b];
+        pm[(int64_t)j * nb + i] = sv;
+        if (i == j) tr += sv;
+        f2 += sv * sv;
+        ra[a] += fabsf(sv);
+      }
+    }
+  }
+  rs[jg][il] = ra[0];
+  rs[jg][il + 32] = ra[1];
+  tr = block_sum(tr, red);   // its barriers also order the rs writes before the reads
   f2 = block_sum(f2, red);
   if (tid == 0) {
     part[((int64_t)slot * gridDim.x + blockIdx.x) * 2] = tr;
     part[((int64_t)slot * gridDim.x + blockIdx.x) * 2 + 1] = f2;
   }
   // partial row |.| sums of this tile column (rows i0.., columns j0..j0+63)
-  if (tid < 64 && i < nb)
-    rowpart[(int64_t)slot * nb * (tn + 1) + (int64_t)tj * nb + i] =
-        rs[0][il] + rs[1][il] + rs[2][il] + rs[3][il];
+  if (tid < 64 && i0 + tid < nb) {
+    float r = 0.f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) r += rs[k][tid];
+    rowpart[(int64_t)slot * nb * (tn + 1) + (int64_t)tj * nb + i0 + tid] = r;
+  }
 }
 
 // Collatz-Wielandt bound for the symmetric M = E^T E (in Pm): with r = |M| 1 and
