@@ -407,7 +407,17 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
     destroy_solver(s);
     return MSLD_EDEVICE;
   }
-  for (int i = 0; i < p->L; ++i) {
+  // Streams of the low-rank scales first: once a process holds all its hardware queues,
+  // HIP attaches a new stream to the least used one, so the long low-rank chains get
+  // queues of their own before the short scales share what is left.
+  int corder[MSLD_MAX_SCALES];
+  int nco = 0;
+  for (int i = p->L - 1; i >= 0; --i)
+    if (pl.use_lr[i]) corder[nco++] = i;
+  for (int i = 0; i < p->L; ++i)
+    if (!pl.use_lr[i]) corder[nco++] = i;
+  for (int ci = 0; ci < nco; ++ci) {
+    const int i = corder[ci];
     if (pl.tier[i] == TIER_1X1) continue;   // fused in the consensus pass
     if (hipStreamCreateWithFlags(&s->sst[i], hipStreamNonBlocking) != hipSuccess) {
       s->sst[i] = nullptr;
