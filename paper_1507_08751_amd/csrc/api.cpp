@@ -407,15 +407,31 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
     destroy_solver(s);
     return MSLD_EDEVICE;
   }
-  // Streams of the low-rank scales first: once a process holds all its hardware queues,
-  // HIP attaches a new stream to the least used one, so the long low-rank chains get
-  // queues of their own before the short scales share what is left.
+  // Stream creation order. Once a process holds all its hardware queues (HIP reads the
+  // count from GPU_MAX_HW_QUEUES, default 4), HIP attaches a new stream to the least
+  // used one. When the scale streams outnumber the queues left beside the caller's, the
+  // low-rank scales' streams come first, so their long chains get queues of their own
+  // and the short scales share what is left; otherwise scale order (measured faster
+  // when every stream has a queue of its own).
+  int hwq = 4;
+  if (const char* q = std::getenv("GPU_MAX_HW_QUEUES")) {
+    const int v = std::atoi(q);
+    if (v > 0) hwq = v;
+  }
+  int nst = 0;
+  for (int i = 0; i < p->L; ++i)
+    if (pl.tier[i] != TIER_1X1) ++nst;
+  const bool scarce = nst + 1 > hwq;
   int corder[MSLD_MAX_SCALES];
   int nco = 0;
-  for (int i = p->L - 1; i >= 0; --i)
-    if (pl.use_lr[i]) corder[nco++] = i;
-  for (int i = 0; i < p->L; ++i)
-    if (!pl.use_lr[i]) corder[nco++] = i;
+  if (scarce) {
+    for (int i = p->L - 1; i >= 0; --i)
+      if (pl.use_lr[i]) corder[nco++] = i;
+    for (int i = 0; i < p->L; ++i)
+      if (!pl.use_lr[i]) corder[nco++] = i;
+  } else {
+    for (int i = 0; i < p->L; ++i) corder[nco++] = i;
+  }
   for (int ci = 0; ci < nco; ++ci) {
     const int i = corder[ci];
     if (pl.tier[i] == TIER_1X1) continue;   // fused in the consensus pass
