@@ -622,7 +622,7 @@ size_t stream_lds_bytes(int m, const StreamPlan& sp);
 // launch would reserve the largest tile for every workgroup and halve the occupancy
 // of the small-block scales).
 hipError_t launch_stream_all(const StreamAll& a, const float* Z, const float* R, float* D,
-                             const ShiftSpec& sh, hipStream_t st) {
+                             const ShiftSpec& sh, hipStream_t st, hipEvent_t* after_scale) {
   if (a.n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(64), 0, st, a);
   hipError_t e = hipGetLastError();
@@ -639,6 +639,10 @@ hipError_t launch_stream_all(const StreamAll& a, const float* Z, const float* R,
     else
       hipLaunchKernelGGL(k_stream_all<256>, dim3(b.first[1]), dim3(256), lds, st, b, Z, R, D, sh);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    // the scale's own fork point: its BlockSVT needs no other scale's stream pass
+    if (after_scale && after_scale[a.s[i].scale] &&
+        (e = hipEventRecord(after_scale[a.s[i].scale], st)) != hipSuccess)
+      return e;
   }
   return hipSuccess;
 }

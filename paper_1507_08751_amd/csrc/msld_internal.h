@@ -219,7 +219,8 @@ struct StreamAll {
 
 // ----------------------------------------------------------- launchers (kernels.hip)
 hipError_t launch_stream_all(const StreamAll& a, const float* Z, const float* R, float* D,
-                             const ShiftSpec& sh, hipStream_t st);
+                             const ShiftSpec& sh, hipStream_t st,
+                             hipEvent_t* after_scale = nullptr);
 float stream_tau2lim(const ScaleGeom& g, float tau);
 hipError_t launch_fill(float* p, float v, size_t count, hipStream_t st);
 bool reg_tier_shape(int m, int n);   // block shapes of the register tier

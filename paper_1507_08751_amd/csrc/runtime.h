@@ -88,6 +88,8 @@ struct msld_solver {
   hipStream_t sst[MSLD_MAX_SCALES];
   hipEvent_t ev_fork;
   hipEvent_t ev_join[MSLD_MAX_SCALES];
+  hipEvent_t ev_sfork[MSLD_MAX_SCALES];   // after scale i's stream pass (its own fork point)
+  int early_fork;   // scales fork after their own stream pass (planes <= 2^24 elements)
   rocblas_handle blas[MSLD_MAX_SCALES];   // one per low-rank scale, bound to its stream
   msld::ScaleWork work[MSLD_MAX_SCALES];
   msld::StreamAll sall;   // the stream pass of all decomposed scales (one launch)
