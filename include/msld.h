@@ -152,7 +152,13 @@ typedef struct msld_solver msld_solver; /* opaque */
 
 /* Validate p, plan the kernels of every scale and allocate the workspace on the
  * current device. hip_stream is a hipStream_t (NULL = default stream). On success
- * *out holds a new handle; on failure *out is NULL. */
+ * *out holds a new handle; on failure *out is NULL.
+ * Each decomposed scale runs its BlockSVT on a stream the handle creates (forked from
+ * and joined back into hip_stream every iteration). Streams run side by side only on
+ * hardware queues of their own: HIP takes the count per process from the environment
+ * variable GPU_MAX_HW_QUEUES (default 4) when it initialises. When the scale streams
+ * outnumber the queues left beside the caller's, the low-rank scales' streams are
+ * created first so that their long chains get queues of their own. */
 msld_status msld_create(const msld_params *p, void *hip_stream, msld_solver **out);
 
 /* Run the ADMM of eq:admm on Y (M x N, leading dimension ldY >= N, device) and
