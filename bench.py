@@ -486,8 +486,8 @@ def main():
     HW_QUEUES = args.hw_queues
     os.environ["GPU_MAX_HW_QUEUES"] = str(HW_QUEUES)
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
-                          "n_gpus": args.gpus}))
+        print(json.dumps({"error": "bench.py measures one GPU (the multi-GPU path is a "
+                                   "design only); --gpus must be 1", "n_gpus": args.gpus}))
         sys.exit(2)
     if args.mode == "serve":
         serve_bench(args)
