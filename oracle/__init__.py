@@ -6,12 +6,18 @@ The product path (the HIP library and its Python binding) never touches it, and
 this package never touches the product path: the two share no code, only the
 seeded inputs of the ``synth`` module.
 
-Everything here is plain numpy in float64, written step by step from the paper
-(Ong & Lustig, "Beyond Low Rank + Sparse: Multi-scale Low Rank Matrix
-Decomposition"). A dense SVD from LAPACK (numpy.linalg.svd) serves as the
-library step inside singular value thresholding.
+Everything here is float64, written step by step from the paper (Ong & Lustig,
+"Beyond Low Rank + Sparse: Multi-scale Low Rank Matrix Decomposition"): plain numpy
+for the iteration, and the oracle's own one-sided Jacobi SVD in plain C
+(jacobi.c, compiled with gcc into libmsld_oracle.so on first use) inside singular
+value thresholding. LAPACK (numpy.linalg.svd) appears only in the optimality
+diagnostics (block nuclear and dual norms of kkt_report), which check results and
+produce none.
 
 Parity status per function (what independent facts pin it; see tests/):
+  jacobi_svd          pinned: reconstruction to 1e-13 ||B||, orthonormal U and V,
+                      singular values against LAPACK's, exact diagonal / rank-1 /
+                      orthogonal-column cases, the transposed (m < n) route.
   cycle_shift         pinned: SplitMix64 published output for seed 0, and the
                       block-wise identities of the shifted operator.
   default_lambda      pinned: the special cases of the boxed lambda formula.
@@ -46,7 +52,7 @@ Parity status per function (what independent facts pin it; see tests/):
                       space-time scales reaches the KKT conditions of eq:cvx.
 """
 from .msld_oracle import (  # noqa: F401
-    MASK64, splitmix64_mix, cycle_shift, default_lambda, shift, unshift, svt,
+    MASK64, splitmix64_mix, jacobi_svd, build_jacobi, cycle_shift, default_lambda, shift, unshift, svt,
     block_svt, cycle_spun_bsvt, admm, block_nuclear_norm, block_dual_norm,
     kkt_report, skip_bound_sq, KIND_BLOCK, KIND_NOISE, noise_svt, scale_lambda,
     scale_norm, scale_dual_norm, spin_shifts, spin_extent, averaged_bsvt,

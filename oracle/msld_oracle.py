@@ -7,7 +7,10 @@ ADMM parameter, X_i / Z_i / U_i the ADMM variables.
 """
 from __future__ import annotations
 
+import ctypes
 import math
+import os
+import subprocess
 
 import numpy as np
 
@@ -58,13 +61,86 @@ def default_lambda(M: int, N: int, m: int, n: int) -> float:
     return math.sqrt(m) + math.sqrt(n) + math.sqrt(math.log(M * N / max(m, n)))
 
 
+# ------------------------------------------------------------------- Jacobi SVD
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_JACOBI_SRC = os.path.join(_HERE, "jacobi.c")
+_JACOBI_LIB = os.path.join(_HERE, "libmsld_oracle.so")
+_jacobi = None
+
+
+def build_jacobi(force: bool = False) -> str:
+    """Compile jacobi.c (plain C, float64, OpenMP) into libmsld_oracle.so next to it."""
+    stale = (not os.path.exists(_JACOBI_LIB) or
+             os.path.getmtime(_JACOBI_LIB) < os.path.getmtime(_JACOBI_SRC))
+    if force or stale:
+        tmp = _JACOBI_LIB + ".tmp%d" % os.getpid()
+        subprocess.run(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+                        _JACOBI_SRC, "-lm", "-o", tmp], check=True)
+        os.replace(tmp, _JACOBI_LIB)
+    return _JACOBI_LIB
+
+
+def _jacobi_lib():
+    global _jacobi
+    if _jacobi is None:
+        lib = ctypes.CDLL(build_jacobi())
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.msld_oracle_jacobi_svd.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp,
+                                               dp, dp, ctypes.POINTER(ctypes.c_int), ctypes.c_int]
+        lib.msld_oracle_jacobi_svd.restype = ctypes.c_int
+        _jacobi = lib
+    return _jacobi
+
+
+def jacobi_svd(B: np.ndarray, max_sweeps: int = 100, return_sweeps: bool = False):
+    """Thin SVD B = U diag(s) V^T by one-sided (Hestenes) Jacobi in float64 (jacobi.c):
+    column pairs are rotated, round-robin order, until every pair is orthogonal to
+    working precision; s_j = ||B v_j||. Works on (m, n) or a stack (..., m, n); a block
+    with m < n goes through its transpose. Singular values come back in descending
+    order; a zero singular value has a zero left vector. Raises if a block has not
+    converged after max_sweeps sweeps."""
+    B = np.asarray(B, dtype=np.float64)
+    *lead, m, n = B.shape
+    flip = m < n
+    A = np.swapaxes(B, -1, -2) if flip else B
+    mm, nn = (n, m) if flip else (m, n)
+    A = np.ascontiguousarray(A.reshape(-1, mm, nn))
+    nb = A.shape[0]
+    U = np.empty((nb, mm, nn))
+    s = np.empty((nb, nn))
+    V = np.empty((nb, nn, nn))
+    sw = np.zeros(nb, dtype=np.int32)
+    if nb:
+        dp = ctypes.POINTER(ctypes.c_double)
+        rc = _jacobi_lib().msld_oracle_jacobi_svd(
+            nb, mm, nn, A.ctypes.data_as(dp), U.ctypes.data_as(dp), s.ctypes.data_as(dp),
+            V.ctypes.data_as(dp), sw.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+            int(max_sweeps))
+        if rc < 0:
+            raise RuntimeError("jacobi_svd: a block did not converge in %d sweeps" % max_sweeps)
+    order = np.argsort(-s, axis=-1, kind="stable")
+    s = np.take_along_axis(s, order, axis=-1)
+    U = np.take_along_axis(U, order[:, None, :], axis=-1)
+    V = np.take_along_axis(V, order[:, None, :], axis=-1)
+    if flip:
+        U, V = V, U
+    k = min(m, n)
+    U = U.reshape(*lead, m, k)
+    V = V.reshape(*lead, n, k)
+    s = s.reshape(*lead, k)
+    if return_sweeps:
+        return U, s, V, sw.reshape(lead)
+    return U, s, V
+
+
 # --------------------------------------------------------------------------- SVT
 def svt(B: np.ndarray, tau: float) -> np.ndarray:
-    """Singular value soft-threshold of Sec. 7 (eq:svt): U max(Sigma - tau, 0) V^T.
-    Works on a single matrix (m, n) or a stack (..., m, n)."""
-    U, S, Vt = np.linalg.svd(B, full_matrices=False)
+    """Singular value soft-threshold of Sec. 7 (eq:svt): U max(Sigma - tau, 0) V^T, with
+    the singular triplets from the oracle's own Jacobi SVD. Works on a single matrix
+    (m, n) or a stack (..., m, n)."""
+    U, S, V = jacobi_svd(B)
     S = np.maximum(S - tau, 0.0)
-    return np.matmul(U * S[..., None, :], Vt)
+    return np.matmul(U * S[..., None, :], np.swapaxes(V, -1, -2))
 
 
 def _blocks(A: np.ndarray, m: int, n: int) -> np.ndarray:

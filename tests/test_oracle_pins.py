@@ -71,6 +71,68 @@ def test_lambda_special_cases():
                         rel_tol=1e-15)
 
 
+# ------------------------------------------------------- Jacobi SVD (eq:svt's SVD)
+@pytest.mark.parametrize("shape", [(12, 12), (40, 17), (17, 40), (1, 9), (9, 1), (64, 64),
+                                   (3, 130)])
+def test_jacobi_svd_reconstruction_and_orthogonality(shape):
+    """B = U diag(s) V^T to 1e-13 ||B||, U and V with orthonormal columns, singular
+    values equal to LAPACK's (a library routine, used here only as a checker)."""
+    rng = np.random.default_rng(sum(shape))
+    B = rng.standard_normal(shape) * np.exp(rng.uniform(-3, 3, size=(1, shape[1])))
+    U, s, V = O.jacobi_svd(B)
+    k = min(shape)
+    assert U.shape == (shape[0], k) and V.shape == (shape[1], k) and s.shape == (k,)
+    nb = np.linalg.norm(B)
+    assert np.linalg.norm(U * s @ V.T - B) <= 1e-13 * nb
+    assert np.abs(U.T @ U - np.eye(k)).max() <= 1e-13
+    assert np.abs(V.T @ V - np.eye(k)).max() <= 1e-13
+    assert np.all(np.diff(s) <= 0) and s[-1] >= 0
+    assert np.abs(s - np.linalg.svd(B, compute_uv=False)).max() <= 1e-13 * s[0]
+
+
+def test_jacobi_svd_exact_cases():
+    rng = np.random.default_rng(3)
+    # diagonal (already orthogonal columns): no rotation, |d| sorted, one sweep
+    d = np.array([0.5, -3.0, 0.0, 2.0, -1e-3])
+    U, s, V, sw = O.jacobi_svd(np.diag(d), return_sweeps=True)
+    assert sw == 1
+    assert np.array_equal(s, np.sort(np.abs(d))[::-1])
+    # rank one: sigma_1 = ||u|| ||v||, the rest zero to rounding
+    u, v = rng.standard_normal(30), rng.standard_normal(20)
+    s = O.jacobi_svd(np.outer(u, v))[1]
+    assert abs(s[0] - np.linalg.norm(u) * np.linalg.norm(v)) <= 1e-13 * s[0]
+    assert s[1:].max() <= 1e-13 * s[0]
+    # orthogonal columns of chosen lengths: those lengths exactly (to rounding)
+    Q = np.linalg.qr(rng.standard_normal((25, 6)))[0]
+    lens = np.array([4.0, 1.0, 9.0, 0.25, 2.0, 7.0])
+    s = O.jacobi_svd(Q * lens)[1]
+    assert np.abs(s - np.sort(lens)[::-1]).max() <= 1e-13 * 9.0
+    # zero block and zero columns: zero singular values with zero left vectors
+    Z = np.zeros((6, 4))
+    U, s, V = O.jacobi_svd(Z)
+    assert np.all(s == 0) and np.all(U == 0)
+    B = rng.standard_normal((8, 5))
+    B[:, 2] = 0.0
+    U, s, V = O.jacobi_svd(B)
+    assert s[-1] == 0.0 and np.all(U[:, -1] == 0.0)
+    assert np.linalg.norm(U * s @ V.T - B) <= 1e-13 * np.linalg.norm(B)
+
+
+def test_jacobi_svd_batched_equals_single():
+    rng = np.random.default_rng(5)
+    B = rng.standard_normal((7, 10, 6))
+    U, s, V = O.jacobi_svd(B)
+    for b in range(7):
+        u1, s1, v1 = O.jacobi_svd(B[b])
+        assert np.array_equal(s[b], s1) and np.array_equal(U[b], u1) and np.array_equal(V[b], v1)
+
+
+def test_jacobi_svd_sweep_cap_is_reported():
+    rng = np.random.default_rng(9)
+    with pytest.raises(RuntimeError):
+        O.jacobi_svd(rng.standard_normal((30, 30)), max_sweeps=1)
+
+
 # ------------------------------------------------------------------ SVT (eq:svt)
 def _spec_norm(A):
     return math.sqrt(max(np.linalg.eigvalsh(A.T @ A).max(), 0.0))
