@@ -473,6 +473,8 @@ def main():
     ap.add_argument("--hw-queues", type=int, default=None,
                     help="hardware queues per process (GPU_MAX_HW_QUEUES), 1..32; default 4 "
                          "for the 8192^2 run, 16 for the other modes")
+    ap.add_argument("--fork-mode", type=int, default=0, choices=[0, 1, 2],
+                    help="where the scales fork from the main stream (msld_params.fork_mode)")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the short serving measurement of the default run")
     ap.add_argument("--serve-requests", type=int, default=16,
@@ -522,7 +524,8 @@ def main():
     Y = torch.from_numpy(inst.Y).to(dev)
     L = len(LADDER)
     Z = torch.empty((L, M, N), dtype=torch.float32, device=dev)
-    solver = msld.Solver(M, N, LADDER, rho=1.0, iters=K, cycle_spin=True, seed=0, device=dev)
+    solver = msld.Solver(M, N, LADDER, rho=1.0, iters=K, cycle_spin=True, seed=0, device=dev,
+                         fork_mode=args.fork_mode)
     tiers = [msld.TIERS[solver.tier(i)] for i in range(L)]
     log("tiers:", tiers)
     if W > 0:
@@ -553,7 +556,8 @@ def main():
             f"svd {ms[2]:.2f} finish {ms[3]:.2f} ms; live {stats['live'][i]} of {nblk * K} "
             f"block-iters, sweeps {stats['sweeps'][i]}, rank {stats['rank'][i]}, "
             f"certified {stats['certified'][i]} (fail coupling {stats['fail_coupling'][i]}, "
-            f"bound {stats['fail_bound'][i]}, polar {stats['polar'][i]})")
+            f"bound {stats['fail_bound'][i]}, polar {stats['polar'][i]}); undecided by the trace "
+            f"bound {stats['undecided'][i]}")
     roof, extra = stream_roofline(prof, tiers, M, N, K)
     out = {"metric": METRIC, "value": round(ips, 4), "unit": "iters/s", "n_gpus": 1, "steps": K,
            "warmup": W, "ms_per_step": round(1e3 * sec / K, 3), "higher_is_better": True,

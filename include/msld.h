@@ -105,7 +105,13 @@ typedef enum {
  *                 divide block_m[i] and image_w, ph must divide H. Cycle spinning
  *                 shifts the video cyclically in (y, x, t); the hashed row residue
  *                 s_r in [0, ph pw) gives (sy, sx) = (s_r / pw, s_r % pw). Other
- *                 kinds ignore patch_w. */
+ *                 kinds ignore patch_w.
+ *   fork_mode   : where the scales' BlockSVT work forks from the main stream (results
+ *                 are identical, only the schedule changes): 0 = automatic (each
+ *                 scale right after its own stream pass on planes of at most 2^24
+ *                 elements, one fork after every pass on larger planes); 1 = always
+ *                 right after each scale's own pass; 2 = always one fork after every
+ *                 pass. Other values: MSLD_EINVAL. */
 #define MSLD_KIND_BLOCK 0
 #define MSLD_KIND_NOISE 1
 #define MSLD_KIND_SPATIAL 2
@@ -125,10 +131,15 @@ typedef struct msld_params {
   int32_t spin_count;
   int32_t image_w;
   int32_t patch_w[MSLD_MAX_SCALES];
+  int32_t fork_mode;
 } msld_params;
 
 /* Outcome of one msld_solve. primal_resid is r_k of the last iteration run
- * (computed when info is requested). live[i] counts the blocks of scale i that
+ * (computed when info is requested); dual_resid is rho ||Z^k - Z^(k-1)||_F / ||Y||_F
+ * over all scales for that iteration (the change of the block-low-rank components,
+ * the dual residual of ADMM; reported only, it stops nothing), -1 when not computed.
+ * status is MSLD_ENUMERIC when Y holds a NaN or Inf (checked before the first
+ * iteration) or the residual became non-finite. live[i] counts the blocks of scale i that
  * passed the singular-value bound test and were decomposed, summed over all
  * iterations; sweeps[i] sums the Jacobi sweeps run on them; rank[i] sums the
  * output ranks; certified[i] counts the blocks finished by the certified low-rank
@@ -138,6 +149,7 @@ typedef struct msld_result {
   int32_t iters;
   int32_t status;
   double primal_resid;
+  double dual_resid;
   uint64_t live[MSLD_MAX_SCALES];
   uint64_t sweeps[MSLD_MAX_SCALES];
   uint64_t rank[MSLD_MAX_SCALES];
@@ -146,6 +158,9 @@ typedef struct msld_result {
   uint64_t fail_bound[MSLD_MAX_SCALES];
   uint64_t polar[MSLD_MAX_SCALES];        /* failed certificates finished by the polar route */
   uint64_t polar_steps[MSLD_MAX_SCALES];  /* its Newton-Schulz steps (polar + sign, per chunk) */
+  uint64_t undecided[MSLD_MAX_SCALES];    /* low-rank blocks whose certificate needed the
+                                             remainder Gram E^T E (the trace bound left them
+                                             undecided) */
 } msld_result;
 
 typedef struct msld_solver msld_solver; /* opaque */
@@ -237,7 +252,7 @@ int32_t msld_set_graph(msld_solver* s, int32_t enable);
  * (MSLD_EINVAL for batch / server classes). */
 msld_status msld_set_mask(msld_solver *s, const uint8_t *d_mask, int64_t ldmask);
 
-/* Kernel timing with HIP events/* Kernel timing with HIP events on the streams that run each part (the consensus on
+/* Kernel timing with HIP events on the streams that run each part (the consensus on
  * the handle's stream, each scale on its own stream). msld_profile_begin(s, n)
  * creates events for the next n iterations (each iteration records them as it is
  * enqueued; later iterations are not recorded). msld_profile_end synchronises and

@@ -23,10 +23,9 @@
  *
  * Pair order: the round-robin (tournament) ordering, n - 1 rounds of n / 2 disjoint
  * pairs per sweep (one column idles per round when n is odd), a cyclic ordering for
- * which one-sided Jacobi converges (Brent & Luk 1985).  Pairs of one round touch
- * disjoint columns, so they may run in any order or in parallel with the same result:
- * large blocks spread a round over threads, batches of small blocks spread the blocks.
- * Blocks with m < n are handled by the caller through B^T.
+ * which one-sided Jacobi converges (Brent & Luk 1985).  Each block is decomposed by one
+ * thread; a batch of blocks is spread over OpenMP threads (the result does not depend
+ * on the thread count).  Blocks with m < n are handled by the caller through B^T.
  */
 #include <math.h>
 #include <stdint.h>
@@ -49,6 +48,7 @@ static int jacobi_pair(double *A, double *V, int m, int n, int p, int q, double 
   if (p > q) { const int t = p; p = q; q = t; }
   double *ap = A + (size_t)p * m, *aq = A + (size_t)q * m;
   double al = 0.0, be = 0.0, ga = 0.0;
+#pragma omp simd reduction(+ : al, be, ga)
   for (int i = 0; i < m; ++i) {
     al += ap[i] * ap[i];
     be += aq[i] * aq[i];
@@ -59,12 +59,14 @@ static int jacobi_pair(double *A, double *V, int m, int n, int p, int q, double 
   const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
   const double c = 1.0 / sqrt(1.0 + t * t);
   const double s = c * t;
+#pragma omp simd
   for (int i = 0; i < m; ++i) {
     const double x = ap[i], y = aq[i];
     ap[i] = c * x - s * y;
     aq[i] = s * x + c * y;
   }
   double *vp = V + (size_t)p * n, *vq = V + (size_t)q * n;
+#pragma omp simd
   for (int i = 0; i < n; ++i) {
     const double x = vp[i], y = vq[i];
     vp[i] = c * x - s * y;
@@ -75,8 +77,8 @@ static int jacobi_pair(double *A, double *V, int m, int n, int p, int q, double 
 
 /* SVD of one block given column-major in A (m x n, m >= n; overwritten by U diag(s)).
  * V (n x n column-major) receives the right vectors, s the singular values (unsorted).
- * Returns the sweeps run. par: spread each round over OpenMP threads. */
-static int jacobi_one(double *A, double *V, double *s, int m, int n, int max_sweeps, int par) {
+ * Returns the sweeps run. */
+static int jacobi_one(double *A, double *V, double *s, int m, int n, int max_sweeps) {
   const double tol = (double)(m > 32 ? m : 32) * ldexp(1.0, -52);
   double f2 = 0.0;
   for (size_t e = 0; e < (size_t)m * n; ++e) f2 += A[e] * A[e];
@@ -88,22 +90,12 @@ static int jacobi_one(double *A, double *V, double *s, int m, int n, int max_swe
   if (n > 1) {
     for (; sweeps < max_sweeps;) {
       int rotated = 0;
-      for (int r = 0; r < n2 - 1; ++r) {
-        if (par) {
-#pragma omp parallel for schedule(static) reduction(| : rotated)
-          for (int k = 0; k < n2 / 2; ++k) {
-            int a, b;
-            rr_pair(r, k, n2, &a, &b);
-            rotated |= jacobi_pair(A, V, m, n, a, b, tol, delta2);
-          }
-        } else {
-          for (int k = 0; k < n2 / 2; ++k) {
-            int a, b;
-            rr_pair(r, k, n2, &a, &b);
-            rotated |= jacobi_pair(A, V, m, n, a, b, tol, delta2);
-          }
+      for (int r = 0; r < n2 - 1; ++r)
+        for (int k = 0; k < n2 / 2; ++k) {
+          int a, b;
+          rr_pair(r, k, n2, &a, &b);
+          rotated |= jacobi_pair(A, V, m, n, a, b, tol, delta2);
         }
-      }
       ++sweeps;
       if (!rotated) break;
     }
@@ -125,8 +117,7 @@ int msld_oracle_jacobi_svd(int nb, int m, int n, const double *B, double *U, dou
                            double *V, int *sweeps, int max_sweeps) {
   if (nb <= 0 || m <= 0 || n <= 0 || m < n) return nb == 0 ? 0 : -2;
   int worst = 0, fail = 0;
-  const int big = (n >= 128 && nb < 8);
-#pragma omp parallel for schedule(dynamic, 1) reduction(max : worst) reduction(| : fail) if (!big)
+#pragma omp parallel for schedule(dynamic, 1) reduction(max : worst) reduction(| : fail)
   for (int b = 0; b < nb; ++b) {
     double *A = (double *)malloc(sizeof(double) * (size_t)m * n);
     double *W = (double *)malloc(sizeof(double) * (size_t)n * n);
@@ -134,7 +125,7 @@ int msld_oracle_jacobi_svd(int nb, int m, int n, const double *B, double *U, dou
     for (int i = 0; i < m; ++i)
       for (int j = 0; j < n; ++j) A[(size_t)j * m + i] = src[(size_t)i * n + j];
     double *sb = s + (size_t)b * n;
-    const int sw = jacobi_one(A, W, sb, m, n, max_sweeps, big);
+    const int sw = jacobi_one(A, W, sb, m, n, max_sweeps);
     if (sw >= max_sweeps && max_sweeps > 0) {
       /* the last sweep may still have rotated: check orthogonality once more */
       const double tol = (double)(m > 32 ? m : 32) * ldexp(1.0, -52);

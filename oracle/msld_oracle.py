@@ -74,7 +74,7 @@ def build_jacobi(force: bool = False) -> str:
              os.path.getmtime(_JACOBI_LIB) < os.path.getmtime(_JACOBI_SRC))
     if force or stale:
         tmp = _JACOBI_LIB + ".tmp%d" % os.getpid()
-        subprocess.run(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+        subprocess.run(["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=c99",
                         _JACOBI_SRC, "-lm", "-o", tmp], check=True)
         os.replace(tmp, _JACOBI_LIB)
     return _JACOBI_LIB
@@ -309,7 +309,8 @@ def admm(Y, ladder, lam=None, rho=1.0, iters=100, cycle_spin=False, seed=0,
     Readings where the paper is silent: Z_i = U_i = 0 at start; the returned
     components are Z_i (exactly block-low-rank); primal residual
     r_k = sqrt(sum_i ||X_i - Z_i||_F^2) / ||Y||_F with the new Z_i; when tol > 0 the
-    loop stops after iteration k if (k+1) % check_every == 0 and r_k <= tol.
+    loop stops after iteration k if (k+1) % check_every == 0 and r_k <= tol. The dual
+    residual rho ||Z^k - Z^(k-1)||_F / ||Y||_F of the last iteration is reported only.
     """
     Y = np.asarray(Y, dtype=np.float64)
     M, N = Y.shape
@@ -329,10 +330,12 @@ def admm(Y, ladder, lam=None, rho=1.0, iters=100, cycle_spin=False, seed=0,
     ny = ny if ny > 0 else 1.0
     hist = []
     r = float("nan")
+    dual = float("nan")
     k_done = 0
     geos = [(int(image_w), int(patch_w[i])) if kinds[i] == KIND_SPATIAL else None
             for i in range(L)]
     for k in range(int(iters)):
+        Zprev = Z.copy()
         S = (Z - U).sum(axis=0)
         for i in range(L):
             if obs is None:
@@ -352,12 +355,13 @@ def admm(Y, ladder, lam=None, rho=1.0, iters=100, cycle_spin=False, seed=0,
             Z[i] = scale_bsvt(X[i] + U[i], m, n, lam[i] / rho, s, geos[i])
         U = U - (Z - X)
         r = float(np.sqrt(((X - Z) ** 2).sum()) / ny)
+        dual = float(rho * np.sqrt(((Z - Zprev) ** 2).sum()) / ny)
         k_done = k + 1
         if history:
             hist.append(r)
         if tol > 0 and k_done % int(check_every) == 0 and r <= tol:
             break
-    return {"Z": Z, "X": X, "U": U, "iters": k_done, "resid": r,
+    return {"Z": Z, "X": X, "U": U, "iters": k_done, "resid": r, "dual": dual,
             "history": hist, "lam": lam}
 
 

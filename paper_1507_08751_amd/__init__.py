@@ -44,7 +44,7 @@ class Params(ctypes.Structure):
                 ("cycle_spin", ctypes.c_int32), ("lowrank_min", ctypes.c_int32),
                 ("shift_seed", ctypes.c_uint64), ("kind", ctypes.c_int32 * MAX_SCALES),
                 ("spin_count", ctypes.c_int32), ("image_w", ctypes.c_int32),
-                ("patch_w", ctypes.c_int32 * MAX_SCALES)]
+                ("patch_w", ctypes.c_int32 * MAX_SCALES), ("fork_mode", ctypes.c_int32)]
 
 KIND_BLOCK = 0
 KIND_NOISE = 1
@@ -59,7 +59,7 @@ class TuneResult(ctypes.Structure):
 
 class Result(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32),
-                ("primal_resid", ctypes.c_double),
+                ("primal_resid", ctypes.c_double), ("dual_resid", ctypes.c_double),
                 ("live", ctypes.c_uint64 * MAX_SCALES),
                 ("sweeps", ctypes.c_uint64 * MAX_SCALES),
                 ("rank", ctypes.c_uint64 * MAX_SCALES),
@@ -67,7 +67,8 @@ class Result(ctypes.Structure):
                 ("fail_coupling", ctypes.c_uint64 * MAX_SCALES),
                 ("fail_bound", ctypes.c_uint64 * MAX_SCALES),
                 ("polar", ctypes.c_uint64 * MAX_SCALES),
-                ("polar_steps", ctypes.c_uint64 * MAX_SCALES)]
+                ("polar_steps", ctypes.c_uint64 * MAX_SCALES),
+                ("undecided", ctypes.c_uint64 * MAX_SCALES)]
 
 
 EXPORTS = {
@@ -167,7 +168,7 @@ def cycle_shift(seed, k, i, m, n):
 
 def make_params(M, N, ladder, lam=None, rho=1.0, iters=100, tol=0.0, check_every=1,
                 cycle_spin=False, seed=0, lowrank_min=0, kinds=None, spin_count=0,
-                image_w=0, patch_w=None) -> Params:
+                image_w=0, patch_w=None, fork_mode=0) -> Params:
     if len(ladder) < 1 or len(ladder) > MAX_SCALES:
         raise ValueError("ladder must have 1..16 scales")
     p = Params()
@@ -188,6 +189,7 @@ def make_params(M, N, ladder, lam=None, rho=1.0, iters=100, tol=0.0, check_every
     p.image_w = int(image_w)
     for i in range(len(ladder)):
         p.patch_w[i] = int(patch_w[i]) if patch_w is not None else 0
+    p.fork_mode = int(fork_mode)
     return p
 
 
@@ -206,7 +208,7 @@ class Solver:
 
     def __init__(self, M, N, ladder, lam=None, rho=1.0, iters=100, tol=0.0, check_every=1,
                  cycle_spin=False, seed=0, device=None, lowrank_min=0, kinds=None,
-                 spin_count=0, image_w=0, patch_w=None):
+                 spin_count=0, image_w=0, patch_w=None, fork_mode=0):
         import torch
         self._torch = torch
         lib = load()
@@ -217,7 +219,7 @@ class Solver:
             else torch.device(device)
         self.params = make_params(M, N, ladder, lam, rho, iters, tol, check_every,
                                   cycle_spin, seed, lowrank_min, kinds, spin_count, image_w,
-                                  patch_w)
+                                  patch_w, fork_mode)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             st = lib.msld_create(ctypes.byref(self.params), _stream_ptr(torch, self.device),
@@ -261,13 +263,15 @@ class Solver:
         if not info:
             return out, None
         return out, {"iters": res.iters, "primal_resid": res.primal_resid,
+                     "dual_resid": res.dual_resid,
                      "live": list(res.live)[:self.L], "sweeps": list(res.sweeps)[:self.L],
                      "rank": list(res.rank)[:self.L],
                      "certified": list(res.certified)[:self.L],
                      "fail_coupling": list(res.fail_coupling)[:self.L],
                      "fail_bound": list(res.fail_bound)[:self.L],
                 "polar": list(res.polar)[:self.L],
-                "polar_steps": list(res.polar_steps)[:self.L]}
+                "polar_steps": list(res.polar_steps)[:self.L],
+                "undecided": list(res.undecided)[:self.L]}
 
     def _check_yz(self, Y, Z):
         torch = self._torch
@@ -303,7 +307,8 @@ class Solver:
                 "fail_coupling": list(res.fail_coupling)[:self.L],
                 "fail_bound": list(res.fail_bound)[:self.L],
                 "polar": list(res.polar)[:self.L],
-                "polar_steps": list(res.polar_steps)[:self.L]}
+                "polar_steps": list(res.polar_steps)[:self.L],
+                "undecided": list(res.undecided)[:self.L]}
 
     def set_graph(self, enable=True):
         """Allow (default) or forbid replaying iterations from captured HIP graphs;
@@ -499,10 +504,11 @@ class Server:
 
 
 def solve(Y, ladder, lam=None, rho=1.0, iters=100, tol=0.0, check_every=1,
-          cycle_spin=False, seed=0, lowrank_min=0):
+          cycle_spin=False, seed=0, lowrank_min=0, fork_mode=0):
     """One-shot decomposition: returns (Z [L, M, N] device tensor, info dict)."""
     s = Solver(Y.shape[0], Y.shape[1], ladder, lam, rho, iters, tol, check_every,
-               cycle_spin, seed, device=Y.device, lowrank_min=lowrank_min)
+               cycle_spin, seed, device=Y.device, lowrank_min=lowrank_min,
+               fork_mode=fork_mode)
     try:
         return s.solve(Y)
     finally:

@@ -4,22 +4,23 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmsld.so")
-SOURCES = ["kernels.hip", "lowrank.hip", "lowrank_small.hip", "polar.hip", "api.cpp", "server.cpp",
-           "tune.cpp"]
+OBJ = os.path.join(os.path.dirname(HERE), "_build")
+SOURCES = ["kernels.hip", "lowrank.hip", "lowrank_small.hip", "mfma.hip", "polar.hip", "api.cpp",
+           "server.cpp", "tune.cpp"]
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions stay off (only compiler-scheduled scalar FP32)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
 ]
 
-
-LINK = ["-L/opt/rocm/lib", "-lrocblas", "-pthread", "-Wl,-rpath,/opt/rocm/lib"]
+LINK = ["-pthread"]
 
 
 def hipcc():
@@ -29,16 +30,32 @@ def hipcc():
     return "hipcc"
 
 
-def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = OUT + ".tmp"
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-x", "hip"] + srcs + LINK + ["-o", tmp]
+def _compile(src: str, verbose: bool) -> str:
+    obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
+    cmd = [hipcc()] + HIPCC_FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libmsld.so")
+        raise RuntimeError(f"hipcc failed compiling {src}")
+    return obj
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every source (in parallel, one hipcc per file) and link libmsld.so."""
+    os.makedirs(OBJ, exist_ok=True)
+    jobs = max(1, min(len(SOURCES), os.cpu_count() or 1, 16))
+    with ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+    tmp = OUT + ".tmp"
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + LINK + ["-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed linking libmsld.so")
     os.replace(tmp, OUT)
     return OUT
 

@@ -53,6 +53,7 @@ msld_status validate_params(const msld_params* p) {
   if (p->check_every < 1) return MSLD_EINVAL;
   if (p->cycle_spin != 0 && p->cycle_spin != 1) return MSLD_EINVAL;
   if (p->spin_count < 0) return MSLD_EINVAL;
+  if (p->fork_mode < 0 || p->fork_mode > 2) return MSLD_EINVAL;
   if (p->image_w < 0 || (p->image_w > 0 && p->M % p->image_w)) return MSLD_EINVAL;
   for (int i = 0; i < p->L; ++i) {
     const int m = p->block_m[i], n = p->block_n[i];
@@ -74,11 +75,15 @@ msld_status validate_params(const msld_params* p) {
 
 // Two parameter sets can share stacked launches when everything but the shift seed
 // agrees (the seed is per instance).
+bool host_waits(const Plan& pl, int i) {
+  return pl.use_lr[i] && !lds_fits(pl.geom[i].mb, pl.geom[i].nb);
+}
+
 bool same_class(const msld_params& a, const msld_params& b) {
   if (a.M != b.M || a.N != b.N || a.L != b.L || a.rho != b.rho || a.max_iters != b.max_iters ||
       a.tol != b.tol || a.check_every != b.check_every || a.cycle_spin != b.cycle_spin ||
       a.lowrank_min != b.lowrank_min || a.spin_count != b.spin_count ||
-      a.image_w != b.image_w)
+      a.image_w != b.image_w || a.fork_mode != b.fork_mode)
     return false;
   for (int i = 0; i < a.L; ++i)
     if (a.block_m[i] != b.block_m[i] || a.block_n[i] != b.block_n[i] ||
@@ -109,8 +114,8 @@ msld_status make_plan(const msld_params* p, int ninst, Plan* pl) {
   };
   pl->off_R = take(4 * MN);
   pl->off_D = take(4 * MN * (size_t)L * 2);
-  pl->off_part = take(8 * (size_t)parts * ninst);
-  pl->off_res = take(8 * 2 * (size_t)ninst);
+  pl->off_part = take(8 * 2 * (size_t)parts * ninst);
+  pl->off_res = take(8 * 3 * (size_t)ninst);   // primal sums, ||Y||^2, dual sums
   pl->off_shift = take(4 * 2 * (size_t)L * 1024);
   pl->off_inst = take(8 * (size_t)ninst + 4 * 2 * (size_t)ninst);
   for (int i = 0; i < L; ++i) {
@@ -254,17 +259,25 @@ msld_status make_plan(const msld_params* p, int ninst, Plan* pl) {
       const int nbp = (g.nb + 2 * pw - 1) / (2 * pw) * (2 * pw);
       pl->pw[i] = pw;
       pl->nbp[i] = nbp;
-      pl->off_pA[i] = take(4 * (size_t)nblk * nbp * g.mb);
-      pl->off_pW[i] = take(4 * (size_t)nblk * nbp * g.nb);
+      if (!lr) {
+        // HBM panels of the block one-sided Jacobi (the low-rank path reads every block
+        // straight from the iterate and needs only the per-slot flags)
+        pl->off_pA[i] = take(4 * (size_t)nblk * nbp * g.mb);
+        pl->off_pW[i] = take(4 * (size_t)nblk * nbp * g.nb);
+        pl->off_pg[i] = take(4 * (size_t)nblk * nbp);
+      }
       pl->off_pflag[i] = take(4 * 4 * (size_t)nblk);
-      pl->off_pg[i] = take(4 * (size_t)nblk * nbp);
       if (lr) {
         const size_t nb2 = (size_t)g.nb * g.nb;
         const size_t tn = ((size_t)g.nb + 63) / 64;
         const size_t per = 3 * nb2 + 4 * (size_t)g.nb * kLRP + (size_t)g.mb * kLRP +
                            (size_t)kLRP * g.nb + 3 * kLRP + 8 + (size_t)g.nb * (tn + 1);
-        pl->off_lr[i] = take(4 * ((size_t)nblk * per + (size_t)g.nb * kLRP + 64 + 4 * nblk));
-        if (g.mb >= 4 * g.nb) pl->off_split[i] = take(4 * kSplitFloats);
+        pl->off_lr[i] = take(4 * ((size_t)nblk * per + (size_t)g.nb * kLRP + 64 + 5 * nblk));
+        // split partials of tall blocks and the float64 Gram partials of the reduced
+        // block, both sized by the block shape and the slot count
+        const int ch = split_chunks(g.mb, g.nb);
+        if (ch > 1) pl->off_split[i] = take(4 * (size_t)nblk * ch * nb2);
+        pl->off_part64[i] = take(8 * (size_t)nblk * ((g.mb + 511) / 512) * 256);
         if (!lds_fits(g.mb, g.nb)) {
           // polar fallback buffers for a chunk of failed certificates (<= 256 MiB)
           const size_t pper = 3 * (size_t)g.mb * g.nb + 4 * nb2 + 4;
@@ -316,7 +329,6 @@ static void destroy_solver(msld_solver* s) {
     std::free(s->prof_ev);
   }
   for (int i = 0; i < MSLD_MAX_SCALES; ++i) {
-    if (s->blas[i]) (void)rocblas_destroy_handle(s->blas[i]);
     if (s->sst[i]) {
       (void)hipStreamSynchronize(s->sst[i]);
       (void)hipStreamDestroy(s->sst[i]);
@@ -363,7 +375,7 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
     destroy_solver(s);
     return MSLD_ENOMEM;
   }
-  if (hipHostMalloc(&s->host_res, 2 * (size_t)ninst * sizeof(double), hipHostMallocDefault) !=
+  if (hipHostMalloc(&s->host_res, 3 * (size_t)ninst * sizeof(double), hipHostMallocDefault) !=
           hipSuccess ||
       hipHostMalloc(&s->host_ints, 2 * MSLD_MAX_SCALES * sizeof(int), hipHostMallocDefault) !=
           hipSuccess) {
@@ -384,12 +396,13 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
   s->d_seed = reinterpret_cast<unsigned long long*>(s->arena + pl.off_inst);
   s->d_k = reinterpret_cast<int*>(s->d_seed + ninst);
   s->d_active = s->d_k + ninst;
-  // an iteration can be captured once no scale's driver waits on the host (the batched
-  // low-rank path reads its live and fallback counts); such solvers keep the shift
-  // seed and iteration counter on the device, so a replay needs no host values
+  // an iteration can be captured once no scale's driver waits on the host (only a
+  // low-rank scale whose blocks exceed the LDS tier reads its fallback count back, to
+  // size the polar route); such solvers keep the shift seed and iteration counter on
+  // the device, so a replay needs no host values
   s->graphable = true;
   for (int i = 0; i < p->L; ++i)
-    if (pl.use_lr[i]) s->graphable = false;
+    if (host_waits(pl, i)) s->graphable = false;
   s->graph_on = s->graphable;
   if (s->graphable && hipStreamCreateWithFlags(&s->cst, hipStreamNonBlocking) != hipSuccess) {
     s->cst = nullptr;
@@ -451,18 +464,6 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
       destroy_solver(s);
       return MSLD_EDEVICE;
     }
-    if (!pl.use_lr[i]) continue;
-    if (rocblas_create_handle(&s->blas[i]) != rocblas_status_success) {
-      s->blas[i] = nullptr;
-      destroy_solver(s);
-      return MSLD_EDEVICE;
-    }
-    if (rocblas_set_stream(s->blas[i], s->sst[i]) != rocblas_status_success ||
-        rocblas_set_atomics_mode(s->blas[i], rocblas_atomics_not_allowed) !=
-            rocblas_status_success) {
-      destroy_solver(s);
-      return MSLD_EDEVICE;
-    }
   }
   for (int i = 0; i < p->L; ++i) {
     ScaleWork& w = s->work[i];
@@ -495,10 +496,12 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
     }
     if (pl.tier[i] == TIER_PANEL) {
       const ScaleGeom& g = pl.geom[i];
-      w.pA = reinterpret_cast<float*>(s->arena + pl.off_pA[i]);
-      w.pW = reinterpret_cast<float*>(s->arena + pl.off_pW[i]);
+      if (!pl.use_lr[i]) {
+        w.pA = reinterpret_cast<float*>(s->arena + pl.off_pA[i]);
+        w.pW = reinterpret_cast<float*>(s->arena + pl.off_pW[i]);
+        w.pg = reinterpret_cast<float*>(s->arena + pl.off_pg[i]);
+      }
       w.pflag = reinterpret_cast<int*>(s->arena + pl.off_pflag[i]);
-      w.pg = reinterpret_cast<float*>(s->arena + pl.off_pg[i]);
       w.slots = g.P * g.Q;
       w.nbp = pl.nbp[i];
       w.pw = pl.pw[i];
@@ -507,7 +510,6 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
         const size_t slots = (size_t)w.slots;
         float* f = reinterpret_cast<float*>(s->arena + pl.off_lr[i]);
         w.use_lr = 1;
-        w.blas = s->blas[i];
         w.lrG = f; f += slots * nb2;
         w.lrP = f; f += slots * nb2;
         w.lrQ = f; f += slots * nb2;
@@ -523,6 +525,9 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
         w.lrOm = f; f += (size_t)g.nb * kLRP;
         w.lrSplit = pl.off_split[i] ? reinterpret_cast<float*>(s->arena + pl.off_split[i])
                                     : nullptr;
+        w.lrChunks = w.lrSplit ? split_chunks(g.mb, g.nb) : 1;
+        w.lrPart64 = reinterpret_cast<double*>(s->arena + pl.off_part64[i]);
+        w.lrChunks64 = (g.mb + 511) / 512;
         w.lrCount = reinterpret_cast<int*>(f);
         w.lrFall = w.lrCount + 64;
         w.lds_fallback = lds_fits(g.mb, g.nb) ? 1 : 0;
@@ -552,8 +557,10 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
   // chains then share the chip with the remaining passes, which pays while the passes
   // are short: planes of up to 2^24 elements (video stand-in +5.7%, batches +3%). At
   // 8192^2 the iteration gained 1.3% but the HBM-bound passes ran 2.4x slower, so large
-  // planes keep them uncontended.
-  s->early_fork = plane_elems(s) <= ((size_t)1 << 24) ? 1 : 0;
+  // planes keep them uncontended. The caller can force either schedule (fork_mode).
+  s->early_fork = p->fork_mode == 1   ? 1
+                  : p->fork_mode == 2 ? 0
+                                      : (plane_elems(s) <= ((size_t)1 << 24) ? 1 : 0);
   {
     StreamAll& a = s->sall;
     std::memset(&a, 0, sizeof(a));
@@ -673,15 +680,16 @@ msld_status iterate_once(msld_solver* s, const float* d_Y, int64_t ldY, float* d
     if (ev) MSLD_TRY(s, hipEventRecord(ev[3], s->st));
   }
   MSLD_TRY(s, hipEventRecord(s->ev_fork, s->st));
-  // scales whose host driver never waits go first, so that their work is queued
-  // before a low-rank scale's host-side waits (live and fallback counts) begin
+  // issue order: the scales with the largest blocks first (their BlockSVT chains are the
+  // longest, so the critical path is queued earliest); every scale's work is enqueued
+  // from this thread: a low-rank scale whose fallback is the polar route defers its one
+  // read-back (finish_fallback) until all scales are queued
   int order[MSLD_MAX_SCALES], no = 0;
-  for (int pass = 0; pass < 2; ++pass)
-    for (int i = 0; i < L; ++i)
-      if (pl.tier[i] != TIER_1X1 && (pl.use_lr[i] != 0) == (pass == 1)) order[no++] = i;
-  // fork every scale first (stream order only), then issue their work; the scales
-  // whose host driver waits on the device get a host thread each (but the last), so
-  // that one scale's waits do not hold back the issue of another's work
+  for (int i = 0; i < L; ++i)
+    if (pl.tier[i] != TIER_1X1) order[no++] = i;
+  std::stable_sort(order, order + no, [&](int x, int y) {
+    return (int64_t)pl.geom[x].m * pl.geom[x].n > (int64_t)pl.geom[y].m * pl.geom[y].n;
+  });
   ShiftSpec shs[MSLD_MAX_SCALES];
   for (int oi = 0; oi < no; ++oi) {
     const int i = order[oi];
@@ -704,19 +712,21 @@ msld_status iterate_once(msld_solver* s, const float* d_Y, int64_t ldY, float* d
   }
   hipError_t herr[MSLD_MAX_SCALES];
   int rls[MSLD_MAX_SCALES];
+  int deferred[MSLD_MAX_SCALES];
   auto issue = [&](int i) {
     float* Zi = d_Z + MN * i;
     rls[i] = 0;
-    (void)hipSetDevice(s->device);   // worker threads start on device 0
+    deferred[i] = 0;
     if (!pl.spin[i]) {
       herr[i] = launch_scale(pl.geom[i], pl.tier[i], pl.sp[i], s->work[i], Zi, R, Zi,
                              Dn + MN * i, pl.tau_default[i], shs[i], jacobi_tol(pl.geom[i].mb),
                              40, 20, s->num_cus, s->sst[i], ev ? ev + 4 + 5 * i : nullptr,
-                             &rls[i], true);
+                             &rls[i], true, &deferred[i]);
       return;
     }
     // averaged cycle spinning: Z_i stays the input of every shift's Z-step until the
-    // finish kernel replaces it by the mean (phase timings cover the first shift)
+    // finish kernel replaces it by the mean (phase timings cover the first shift); each
+    // shift's fallback completes before its Z-step is accumulated
     const ScaleWork& w = s->work[i];
     const int nc = pl.geom[i].n == N ? 1 : pl.geom[i].n;
     const int* act = stacked ? s->d_active : nullptr;
@@ -745,24 +755,14 @@ msld_status iterate_once(msld_solver* s, const float* d_Y, int64_t ldY, float* d
                              act, s->sst[i]);
     herr[i] = e;
   };
-  std::vector<std::thread> workers;
-  int first_waiting = no;
-  for (int oi = 0; oi < no; ++oi)
-    if (pl.use_lr[order[oi]]) {
-      first_waiting = oi;
-      break;
-    }
-  for (int oi = 0; oi < first_waiting; ++oi) issue(order[oi]);
-  for (int oi = first_waiting; oi + 1 < no; ++oi) {
+  for (int oi = 0; oi < no; ++oi) issue(order[oi]);
+  for (int oi = 0; oi < no; ++oi) {
     const int i = order[oi];
-    try {
-      workers.emplace_back(issue, i);
-    } catch (...) {
-      issue(i);   // no thread available: issue in order
-    }
+    if (herr[i] != hipSuccess || !deferred[i]) continue;
+    herr[i] = finish_fallback(pl.geom[i], s->work[i], d_Z + MN * i, Dn + MN * i,
+                              pl.tau_default[i], shs[i], s->sst[i]);
+    if (herr[i] == hipSuccess && ev) herr[i] = hipEventRecord(ev[4 + 5 * i + 4], s->sst[i]);
   }
-  if (first_waiting < no) issue(order[no - 1]);
-  for (auto& t : workers) t.join();
   for (int oi = 0; oi < no; ++oi) {
     const int i = order[oi];
     if (herr[i] != hipSuccess) return dev_err(s, herr[i]);
@@ -772,8 +772,8 @@ msld_status iterate_once(msld_solver* s, const float* d_Y, int64_t ldY, float* d
   }
   if (want_res) {
     double* part = reinterpret_cast<double*>(s->arena + pl.off_part);
-    MSLD_TRY(s, launch_resid(Dc, R, d_Z, M, N, L, IM, s->ninst, part, pl.resid_parts, dev_res(s),
-                             s->st));
+    MSLD_TRY(s, launch_resid(Dc, Dn, R, d_Z, M, N, L, IM, s->ninst, part, pl.resid_parts,
+                             dev_res(s), dev_res(s) + 2 * s->ninst, s->st));
   }
   if (stacked) MSLD_TRY(s, launch_inc_active(s->d_k, s->d_active, s->ninst, s->st));
   s->k += 1;
@@ -841,15 +841,31 @@ static msld_status reset_state(msld_solver* s, float* d_Z) {
   return zero_stats(s);
 }
 
-// residual of instance 0 after an iterate_once(..., want_res = true)
-static msld_status read_resid(msld_solver* s, const float* d_Y, int64_t ldY, double* out) {
+// residuals of instance 0 after an iterate_once(..., want_res = true): the primal
+// r_k = sqrt(sum_i ||X_i - Z_i'||^2) / ||Y||_F and the dual rho ||Z' - Z|| / ||Y||_F
+static msld_status read_resid(msld_solver* s, const float* d_Y, int64_t ldY, double* out,
+                              double* dual = nullptr) {
   msld_status st = launch_ynorms(s, d_Y, ldY);
   if (st != MSLD_OK) return st;
-  MSLD_TRY(s, hipMemcpyAsync(s->host_res, dev_res(s), 16, hipMemcpyDeviceToHost, s->st));
+  const int n = s->ninst;
+  MSLD_TRY(s, hipMemcpyAsync(s->host_res, dev_res(s), 24 * (size_t)n, hipMemcpyDeviceToHost,
+                             s->st));
   MSLD_TRY(s, hipStreamSynchronize(s->st));
-  const double ny2 = s->host_res[1] > 0 ? s->host_res[1] : 1.0;
+  const double ny2 = s->host_res[n] > 0 ? s->host_res[n] : 1.0;
   *out = std::sqrt(s->host_res[0] / ny2);
+  if (dual) *dual = (double)s->p.rho * std::sqrt(s->host_res[2 * n] / ny2);
   return std::isfinite(*out) ? MSLD_OK : MSLD_ENUMERIC;
+}
+
+// ||Y||_F^2 of instance 0 must be finite: a NaN or Inf in Y is reported before any
+// iteration runs (MSLD_ENUMERIC)
+static msld_status check_y_finite(msld_solver* s, const float* d_Y, int64_t ldY) {
+  msld_status st = launch_ynorms(s, d_Y, ldY);
+  if (st != MSLD_OK) return st;
+  MSLD_TRY(s, hipMemcpyAsync(s->host_res + s->ninst, dev_res(s) + s->ninst, 8,
+                             hipMemcpyDeviceToHost, s->st));
+  MSLD_TRY(s, hipStreamSynchronize(s->st));
+  return std::isfinite(s->host_res[s->ninst]) ? MSLD_OK : MSLD_ENUMERIC;
 }
 
 static msld_status fill_stats(msld_solver* s, msld_result* info) {
@@ -868,6 +884,7 @@ static msld_status fill_stats(msld_solver* s, msld_result* info) {
     info->fail_bound[i] = st8[5];
     info->polar[i] = (uint64_t)s->work[i].stats_host[0];
     info->polar_steps[i] = (uint64_t)(s->work[i].stats_host[1] + s->work[i].stats_host[2]);
+    info->undecided[i] = st8[6];
   }
   return MSLD_OK;
 }
@@ -954,9 +971,9 @@ msld_status msld_solve(msld_solver* s, const float* d_Y, int64_t ldY, float* d_Z
   if (ldY < p.N) return MSLD_EINVAL;
   msld_status st = reset_state(s, d_Z);
   if (st != MSLD_OK) return st;
-  double resid = -1.0;
-  msld_status result = MSLD_OK;
-  for (int k = 0; k < p.max_iters; ++k) {
+  double resid = -1.0, dual = -1.0;
+  msld_status result = check_y_finite(s, d_Y, ldY);
+  for (int k = 0; k < p.max_iters && result == MSLD_OK; ++k) {
     const int iters = k + 1;
     const bool check = p.tol > 0.f && (iters % p.check_every == 0);
     const bool last = iters == p.max_iters;
@@ -964,15 +981,17 @@ msld_status msld_solve(msld_solver* s, const float* d_Y, int64_t ldY, float* d_Z
     st = step_iteration(s, d_Y, ldY, d_Z, want);
     if (st != MSLD_OK) return st;
     if (want) {
-      result = read_resid(s, d_Y, ldY, &resid);
+      result = read_resid(s, d_Y, ldY, &resid, &dual);
       if (result != MSLD_OK) break;
       if (check && resid <= (double)p.tol) break;
     }
   }
+  if (result == MSLD_EDEVICE) return result;
   if (info) {
     st = fill_stats(s, info);
     if (st != MSLD_OK) return st;
     info->primal_resid = resid;
+    info->dual_resid = dual;
     info->status = result;
   }
   return result;

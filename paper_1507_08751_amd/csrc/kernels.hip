@@ -1313,12 +1313,22 @@ float stream_tau2lim(const ScaleGeom& g, float tau) {
   return (float)tl;
 }
 
+hipError_t finish_fallback(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout, float tau,
+                           const ShiftSpec& sh, hipStream_t st) {
+  hipError_t e;
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+  const int fallback = w.hostInts[1];
+  if (fallback > 0) return run_polar(g, w, Zout, Dout, tau, sh, fallback, st);
+  return hipSuccess;
+}
+
 hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, ScaleWork& w,
                         const float* Zin, const float* R, float* Zout, float* Dout, float tau,
                         const ShiftSpec& sh, float jtol, int max_sweeps, int panel_sweeps,
                         int num_cus, hipStream_t st, hipEvent_t* ev, int* round_launches,
-                        bool stream_done) {
+                        bool stream_done, int* deferred) {
   hipError_t e;
+  if (deferred) *deferred = 0;
   if (tier == TIER_FRO) {
     MSLD_EV(0); MSLD_EV(1); MSLD_EV(2);
     if ((e = launch_noise(g, w, Zin, R, Zout, Dout, tau, sh, st)) != hipSuccess) return e;
@@ -1397,12 +1407,8 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
     int G = 1;
     const int threads = lds_tier_threads(g.nb, g.mb, &G);
     const size_t ldsb = lds_tier_bytes(g.mb, g.nb);
-    int per_cu = (int)(160 * 1024 / (ldsb + 1024));
-    const int by_waves = 32 / ((threads + 63) / 64);
-    if (per_cu > by_waves) per_cu = by_waves;
-    if (per_cu > 2) per_cu = 2;   // failures are rare: a small persistent grid suffices
-    if (per_cu < 1) per_cu = 1;
-    int grid = num_cus * per_cu;
+    // failures are rare and counted on the device: a small grid walks the list
+    int grid = 64;
     if (grid > nblk) grid = nblk;
     ScaleWork fw = w;
     fw.live_count = w.lrCount + 1;
@@ -1445,76 +1451,66 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
     MSLD_EV(3); MSLD_EV(4);
     return hipSuccess;
   }
-  // panel tier
-  int slots_y = w.slots < 65535 ? w.slots : 65535;
-  int fallback = 1;
   if (w.use_lr) {
-    if ((e = hipMemcpyAsync(w.hostInts, w.live_count, sizeof(int), hipMemcpyDeviceToHost, st)) !=
-        hipSuccess)
-      return e;
-    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-    const int count = w.hostInts[0];
-    if (count <= 0) {
-      MSLD_EV(2); MSLD_EV(3); MSLD_EV(4);
+    // certified low-rank path: every launch walks the live count on the device
+    MSLD_EV(2);
+    if ((e = run_lowrank(g, w, Zout, Dout, tau, sh, st)) != hipSuccess) return e;
+    MSLD_EV(3);
+    if (w.lds_fallback) {
+      // blocks that failed the certificate and fit in LDS: one-sided Jacobi LDS tier
+      // over the fallback list (its count on the device; empty in the common case)
+      int G = 1;
+      const int threads = lds_tier_threads(g.nb, g.mb, &G);
+      const size_t ldsb = lds_tier_bytes(g.mb, g.nb);
+      // failures are rare and their count is only known on the device: a small grid
+      // that walks the list (a full-chip grid of LDS-hungry workgroups would wait for
+      // the concurrent scales' kernels to drain before it could even retire empty)
+      int grid = 32;
+      if (grid > nblk) grid = nblk;
+      ScaleWork fw = w;
+      fw.live_count = w.lrCount;
+      fw.live_list = w.lrFall;
+      switch (G) {
+        case 1: e = launch_lds_g<1>(grid, threads, ldsb, Zout, Dout, g, sh, tau, jtol, max_sweeps, fw, st); break;
+        case 2: e = launch_lds_g<2>(grid, threads, ldsb, Zout, Dout, g, sh, tau, jtol, max_sweeps, fw, st); break;
+        case 4: e = launch_lds_g<4>(grid, threads, ldsb, Zout, Dout, g, sh, tau, jtol, max_sweeps, fw, st); break;
+        case 8: e = launch_lds_g<8>(grid, threads, ldsb, Zout, Dout, g, sh, tau, jtol, max_sweeps, fw, st); break;
+        case 16: e = launch_lds_g<16>(grid, threads, ldsb, Zout, Dout, g, sh, tau, jtol, max_sweeps, fw, st); break;
+        default: e = launch_lds_g<32>(grid, threads, ldsb, Zout, Dout, g, sh, tau, jtol, max_sweeps, fw, st); break;
+      }
+      if (e != hipSuccess) return e;
+      MSLD_EV(4);
       return hipSuccess;
     }
-    slots_y = count < 65535 ? count : 65535;
+    // failed certificates of blocks beyond the LDS tier: exact polar-route SVT, whose
+    // step counts are chosen on the host: the one read-back of this path. With
+    // `deferred`, the count is only copied back here and finish_fallback (after the
+    // caller has issued its other work) waits for it and runs the polar route.
+    if ((e = hipMemcpyAsync(w.hostInts + 1, w.lrCount, sizeof(int), hipMemcpyDeviceToHost, st)) !=
+        hipSuccess)
+      return e;
+    if (deferred) {
+      *deferred = 1;
+      return hipSuccess;
+    }
+    if ((e = finish_fallback(g, w, Zout, Dout, tau, sh, st)) != hipSuccess) return e;
+    MSLD_EV(4);
+    return hipSuccess;
   }
+  // panel tier
+  const int slots_y = w.slots < 65535 ? w.slots : 65535;
   {
     const int tiles = ((g.m + 31) / 32) * ((g.n + 31) / 32);
     hipLaunchKernelGGL(k_panel_load, dim3(tiles, slots_y), dim3(256), 0, st, Dout, g, sh,
                        w.live_count, w.live_list, w.pA, w.nbp);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (!w.use_lr) {
-      // rotation accumulators and padding for the panel rounds (the low-rank path and
-      // its fallbacks use neither, and write every flag they read)
-      hipLaunchKernelGGL(k_panel_init, dim3(64, slots_y), dim3(256), 0, st, g, w.live_count,
-                         w.pA, w.pW, w.pflag, w.nbp);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
+    // rotation accumulators and padding for the panel rounds
+    hipLaunchKernelGGL(k_panel_init, dim3(64, slots_y), dim3(256), 0, st, g, w.live_count, w.pA,
+                       w.pW, w.pflag, w.nbp);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   MSLD_EV(2);
-  if (w.use_lr) {
-    if ((e = run_lowrank(g, w, Zout, Dout, tau, sh, jtol, w.hostInts[0], &fallback, st)) !=
-        hipSuccess)
-      return e;
-  }
   MSLD_EV(3);
-  if (fallback == 0) {
-    MSLD_EV(4);
-    return hipSuccess;
-  }
-  if (w.use_lr && !w.lds_fallback) {
-    // failed certificates of blocks beyond the LDS tier: exact polar-route SVT
-    if ((e = run_polar(g, w, Zout, Dout, tau, sh, fallback, st)) != hipSuccess) return e;
-    MSLD_EV(4);
-    return hipSuccess;
-  }
-  if (w.use_lr && w.lds_fallback) {
-    // blocks that failed the certificate and fit in LDS: one-sided Jacobi LDS tier
-    int G = 1;
-    const int threads = lds_tier_threads(g.nb, g.mb, &G);
-    const size_t ldsb = lds_tier_bytes(g.mb, g.nb);
-    int per_cu = (int)(160 * 1024 / (ldsb + 1024));
-    if (per_cu < 1) per_cu = 1;
-    if (per_cu > 8) per_cu = 8;
-    int grid = num_cus * per_cu;
-    if (grid > fallback) grid = fallback;
-    ScaleWork fw = w;
-    fw.live_count = w.lrCount;
-    fw.live_list = w.lrFall;
-    switch (G) {
-      case 1: e = launch_lds_g<1>(grid, threads, ldsb, Zout, Dout, g, sh, tau, jtol, max_sweeps, fw, st); break;
-      case 2: e = launch_lds_g<2>(grid, threads, ldsb, Zout, Dout, g, sh, tau, jtol, max_sweeps, fw, st); break;
-      case 4: e = launch_lds_g<4>(grid, threads, ldsb, Zout, Dout, g, sh, tau, jtol, max_sweeps, fw, st); break;
-      case 8: e = launch_lds_g<8>(grid, threads, ldsb, Zout, Dout, g, sh, tau, jtol, max_sweeps, fw, st); break;
-      case 16: e = launch_lds_g<16>(grid, threads, ldsb, Zout, Dout, g, sh, tau, jtol, max_sweeps, fw, st); break;
-      default: e = launch_lds_g<32>(grid, threads, ldsb, Zout, Dout, g, sh, tau, jtol, max_sweeps, fw, st); break;
-    }
-    if (e != hipSuccess) return e;
-    MSLD_EV(4);
-    return hipSuccess;
-  }
   const int npan = w.nbp / w.pw;
   const int G = 256 / w.pw;
   const size_t lds = (size_t)4 * 2 * w.pw * ((g.mb | 1) + (g.nb | 1));
@@ -1554,33 +1550,49 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
 // sum_i ||D_i + R - Z_i'||^2 (= sum_i ||X_i - Z_i'||^2) per instance, with
 // per-workgroup partials reduced in a fixed order (independent of scheduling).
 // Instance z owns rows [z IM, (z+1) IM) of every plane; grid = (parts, NI).
+// Per-instance sums of the primal residual sum_i ||X_i - Z_i'||^2 (X_i = D_i + R in D
+// form) and, into partial + NI * gridDim.x, of the dual residual sum_i ||Z_i' - Z_i||^2:
+// with V_i = Z_i + R and D_i' = 2 Z_i' - V_i, the previous iterate is
+// Z_i = 2 Z_i' - D_i' - R, so Z_i' - Z_i = D_i' + R - Z_i'.
 __global__ void __launch_bounds__(256) k_resid(const float* __restrict__ Dold,
+                                               const float* __restrict__ Dnew,
                                                const float* __restrict__ R,
                                                const float* __restrict__ Z, int64_t MN, int L,
                                                int64_t inst_elems, double* __restrict__ partial) {
-  __shared__ double red[256];
+  __shared__ double red[2][256];
   const int z = blockIdx.y;
-  double acc = 0.0;
+  double acc = 0.0, accd = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t base = (int64_t)z * inst_elems;
   for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e0 < inst_elems;
        e0 += stride) {
     const int64_t e = base + e0;
     const float r = R[e];
-    float s = 0.f;
+    float s = 0.f, sd = 0.f;
     for (int i = 0; i < L; ++i) {
-      const float d = Dold[i * MN + e] + r - Z[i * MN + e];
+      const float zi = Z[i * MN + e];
+      const float d = Dold[i * MN + e] + r - zi;
+      const float dd = Dnew[i * MN + e] + r - zi;
       s += d * d;
+      sd += dd * dd;
     }
     acc += (double)s;
+    accd += (double)sd;
   }
-  red[threadIdx.x] = acc;
+  red[0][threadIdx.x] = acc;
+  red[1][threadIdx.x] = accd;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    if (threadIdx.x < o) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + o];
+      red[1][threadIdx.x] += red[1][threadIdx.x + o];
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) partial[(int64_t)z * gridDim.x + blockIdx.x] = red[0];
+  if (threadIdx.x == 0) {
+    partial[(int64_t)z * gridDim.x + blockIdx.x] = red[0][0];
+    partial[((int64_t)gridDim.y + z) * gridDim.x + blockIdx.x] = red[1][0];
+  }
 }
 
 __global__ void __launch_bounds__(256) k_sumsq(const float* __restrict__ Y, int64_t ldY, int IM,
@@ -1615,13 +1627,17 @@ __global__ void k_final_sum(const double* partial, int nparts, int NI, double* o
   out[z] = s;
 }
 
-hipError_t launch_resid(const float* Dold, const float* R, const float* Z, int M, int N, int L,
-                        int IM, int NI, double* partial, int nparts, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_resid, dim3(nparts, NI), dim3(256), 0, st, Dold, R, Z, (int64_t)M * N, L,
-                     (int64_t)IM * N, partial);
+hipError_t launch_resid(const float* Dold, const float* Dnew, const float* R, const float* Z,
+                        int M, int N, int L, int IM, int NI, double* partial, int nparts,
+                        double* out, double* out_dual, hipStream_t st) {
+  hipLaunchKernelGGL(k_resid, dim3(nparts, NI), dim3(256), 0, st, Dold, Dnew, R, Z,
+                     (int64_t)M * N, L, (int64_t)IM * N, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_final_sum, dim3((NI + 63) / 64), dim3(64), 0, st, partial, nparts, NI, out);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_final_sum, dim3((NI + 63) / 64), dim3(64), 0, st,
+                     partial + (size_t)nparts * NI, nparts, NI, out_dual);
   return hipGetLastError();
 }
 

@@ -71,7 +71,6 @@ __device__ inline bool inst_active(const ShiftSpec& s, int z) {
 // ------------------------------------------------------------------ plans
 enum Tier { TIER_1X1 = 0, TIER_REG = 1, TIER_LDS = 2, TIER_PANEL = 3, TIER_LRS = 5,
             TIER_FRO = 6 };
-constexpr size_t kSplitFloats = (size_t)4 << 20;   // split-K partials of tall blocks
 constexpr int kFroParts = 512;   // partial sums per instance of the noise scale's norm
 
 // Geometry of one scale's partition. M counts the rows of all stacked instances
@@ -145,7 +144,6 @@ struct ScaleWork {
   int pw;               // panel width
   // certified low-rank path (lowrank.hip); per slot unless noted
   int use_lr;
-  void* blas;           // rocblas_handle
   float* lrG;           // [slots][nb*nb] Gram B^T B
   float* lrP;           // [slots][nb*nb] scratch for E^T E and its squarings
   float* lrQ;           // [slots][nb*nb]
@@ -159,11 +157,16 @@ struct ScaleWork {
   float* lrScal;        // [slots][8]
   float* lrRow;         // [slots][nb / 64 + 1][nb] row partials of |E^T E| and row sums
   float* lrOm;          // [nb*p] probe matrix
-  float* lrSplit;       // [kSplitFloats] split-K partials of tall blocks (null: none)
-  int* lrCount;         // [4] device counters: fallback, undecided, undecided by the trace bound
-  int* lrFall;          // [4 slots] block ids, then slot indices, of failed certificates;
+  float* lrSplit;       // [slots][chunks][nb*nb] split partials of tall blocks (null: none)
+  int lrChunks;         // split_chunks(mb, nb)
+  double* lrPart64;     // [slots][lrChunks64][256] float64 Gram partials of the reduced block
+  int lrChunks64;       // row chunks of that Gram
+  int* lrCount;         // [5] device counters: fallback, appends, undecided after the trace
+                        // bound, undecided after the stage-0 bounds, A_f list
+  int* lrFall;          // [5 slots] block ids, then slot indices, of failed certificates;
                         // then the slots left undecided by the stage-0 bound; then those
-                        // left undecided by the trace bound (stage -1)
+                        // left undecided by the trace bound (stage -1); then the slots
+                        // that need A_f (rebuild or fallback)
   int lds_fallback;     // 1: fallback blocks fit the LDS Jacobi tier
   int* hostInts;        // pinned host ints [2]
   // polar fallback (polar.hip) for failed certificates of blocks beyond the LDS tier;
@@ -234,32 +237,68 @@ hipError_t launch_consensus(const float* Y, int64_t ldY, const float* Dcur, floa
                             const uint8_t* mask, int64_t ldmask, hipStream_t st);
 // ev (optional, 5 events): recorded before the scale pass, after the stream pass,
 // before the panel rounds, after the panel rounds and after the whole pass.
+// deferred (optional): a low-rank scale whose fallback is the polar route only queues
+// the copy of its fallback count, sets *deferred = 1 and returns; the caller then calls
+// finish_fallback for it (on the same stream) once its other work is issued.
 hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, ScaleWork& w,
                         const float* Zin, const float* R, float* Zout, float* Dout,
                         float tau, const ShiftSpec& sh, float jtol, int max_sweeps,
                         int panel_sweeps, int num_cus, hipStream_t st, hipEvent_t* ev,
                         int* round_launches,
-                        bool stream_done);
+                        bool stream_done, int* deferred = nullptr);
+hipError_t finish_fallback(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout, float tau,
+                           const ShiftSpec& sh, hipStream_t st);
 int lr_small_shape(int mb, int nb, int* NB, int* MB, int* P);
 size_t lr_small_lds_bytes(int NB, int MB, int P);
 hipError_t launch_lr_small(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout,
                            float tau, const ShiftSpec& sh, int num_cus, int pass,
                            const int* count, const int* list, int* fcount, int* flist,
                            hipStream_t st);
-hipError_t batched_sgemm(void* blas, bool ta, bool tb, int m, int n, int k, const float* A,
-                         int lda, int64_t sa, const float* B, int ldb, int64_t sb, float* C,
-                         int ldc, int64_t sc, int batch);
+// Matrix-core kernels (mfma.hip). Slots walk up to a device count (dcount, or hcount
+// when dcount is null); `slots` is the most a launch can see, which sizes its grid.
+enum SkMode { SK_DENSE = 0, SK_B = 1, SK_BT = 2 };
+// Row chunks of the split contractions of tall blocks (1: no split); depends on the
+// block shape only. A split needs slots * chunks * nb * nb floats of partial sums.
+int split_chunks(int mb, int nb);
+// G = B^T B of the live blocks, B gathered from V = -Dout (tall blocks split their rows
+// over part when it is given).
+hipError_t launch_mf_gram(const ScaleGeom& g, const ShiftSpec& sh, const float* Dout,
+                          const int* live_count, const int* live_list, int slots, float* G,
+                          float* part, hipStream_t st);
+// C (M x 16) = A (M x K) X (K x 16): A dense column-major (SK_DENSE), the gathered
+// block B (SK_B) or B^T (SK_BT); C column-major or row-major (rowmaj).
+hipError_t launch_sk(int mode, bool rowmaj, const float* A, int64_t sA, int lda,
+                     const float* Dout, const ScaleGeom& g, const ShiftSpec& sh,
+                     const int* live_list, const float* X, int64_t sX, int M, int K, float* C,
+                     int64_t sC, const int* dcount, int hcount, int slots, const int* slot_list,
+                     float* part, int split, hipStream_t st);
+// Y = A X (M x 16) for symmetric A, barrier-free; needs M % 16 == 0 and lda % 4 == 0.
+hipError_t launch_sym_x(const float* A, int64_t sA, int lda, const float* X, int64_t sX, int M,
+                        float* Y, int64_t sY, const int* dcount, int slots, const int* slot_list,
+                        hipStream_t st);
+// C = op(A) B, column-major, batch entries c < count.
+hipError_t launch_gemm(bool ta, int M, int N, int K, const float* A, int lda, int64_t sa,
+                       const float* B, int ldb, int64_t sb, float* C, int ldc, int64_t sc,
+                       const int* dcount, int hcount, int max_count, hipStream_t st);
+// Z = A_f diag(gains) V_r^T of the certified slots among slot_list[0 .. *count) (all
+// slots < *count when the list is null), scattered with D' = 2 Z' - V.
+hipError_t launch_mf_rebuild(const ScaleGeom& g, const ShiftSpec& sh, float* Zout, float* Dout,
+                             const int* count, const int* slot_list, const int* live_list,
+                             int slots, const int* pflag, const float* Af, const float* Vr,
+                             const float* sig, const float* mask, float tau, hipStream_t st);
 hipError_t run_polar(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout, float tau,
                      const ShiftSpec& sh, int nfall, hipStream_t st);
+// Certified low-rank BlockSVT of the live blocks (count on the device); failed
+// certificates are listed for the exact fallback (w.lrCount[0], w.lrFall).
 hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout, float tau,
-                       const ShiftSpec& sh, float jtol, int count, int* fallback_host,
-                       hipStream_t st);
+                       const ShiftSpec& sh, hipStream_t st);
 __global__ void k_zero_ints(int* p, int n);
 __global__ void k_copy_count(const int* src, int* dst);
 // Per-instance sums (instance z = rows [z IM, (z+1) IM)): out[z].
-hipError_t launch_resid(const float* Dold, const float* R, const float* Z, int M, int N,
-                        int L, int IM, int NI, double* partial, int nparts, double* out,
-                        hipStream_t st);
+// Also the dual residual sums sum_i ||Z_i' - Z_i||^2 into out_dual[z].
+hipError_t launch_resid(const float* Dold, const float* Dnew, const float* R, const float* Z,
+                        int M, int N, int L, int IM, int NI, double* partial, int nparts,
+                        double* out, double* out_dual, hipStream_t st);
 hipError_t launch_sumsq(const float* Y, int64_t ldY, int IM, int N, int NI, const uint8_t* mask,
                         int64_t ldmask, double* partial, int nparts, double* out,
                         hipStream_t st);

@@ -14,7 +14,7 @@
 //  * an eigenvalue s of S with |s| <= alpha_S is mapped to s (1 + f_J(s / alpha_S)) / 2
 //    instead of (s)_+, an error of at most alpha_S max_x x (1 - f_J(x)) / 2; only
 //    singular values close to tau are affected, each by a fraction of its distance.
-// K and J are chosen on the host from these scalar recursions.
+// K and J are chosen on the host from these scalar recursions, per failed block.
 //
 // Deflation: when the coupling test of the low-rank path passed, its live directions
 // U_L (with singular values S_L, right vectors V_L) are split off first. With
@@ -33,7 +33,9 @@ namespace msld {
 // E' / alpha for each failed slot of the chunk, plus per-slot scalars
 // (alpha, alpha_S, deflated flag, ||B||_F).
 template <int P>
-__global__ void __launch_bounds__(256) k_pl_prepare(const float* __restrict__ pA, int64_t sB,
+__global__ void __launch_bounds__(256) k_pl_prepare(const float* __restrict__ Dout, ScaleGeom g,
+                                                    ShiftSpec sh,
+                                                    const int* __restrict__ live_list,
                                                     const float* __restrict__ Af,
                                                     const float* __restrict__ T,
                                                     const float* __restrict__ sig,
@@ -68,7 +70,11 @@ __global__ void __launch_bounds__(256) k_pl_prepare(const float* __restrict__ pA
   }
   __syncthreads();
   const int64_t elems = (int64_t)mb * nb;
-  const float* b = pA + (int64_t)slot * sB;
+  // the block is read from V = -D' at its shifted coordinates (logical B(r, col))
+  const int blk = live_list[slot];
+  const int p = blk / g.Q, q = blk - p * g.Q;
+  int sr, scol;
+  block_shift(sh, p / g.PI, g.m, g.n, &sr, &scol);
   const float* af = Af + (int64_t)slot * mb * P;
   const float* t = T + (int64_t)slot * P * nb;
   float* x = X0 + (int64_t)c * elems;
@@ -77,7 +83,8 @@ __global__ void __launch_bounds__(256) k_pl_prepare(const float* __restrict__ pA
        e += (int64_t)gridDim.x * blockDim.x) {
     const int col = (int)(e / mb);
     const int r = (int)(e - (int64_t)col * mb);
-    float v = b[e];
+    const int i = g.trans ? col : r, j = g.trans ? r : col;
+    float v = -Dout[(int64_t)grow(g, p, i, sr) * g.N + gcol(g, q, j, scol)];
     if (defl) {
 #pragma unroll
       for (int l = 0; l < P; ++l)
@@ -238,7 +245,6 @@ hipError_t run_polar(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout,
   constexpr int P = 16;
   hipError_t e;
   const int mb = g.mb, nb = g.nb;
-  const int64_t sB = (int64_t)w.nbp * mb;
   const int64_t sX = (int64_t)mb * nb;
   const int64_t sN = (int64_t)nb * nb;
   const int* fslot = w.lrFall + w.slots;
@@ -246,10 +252,13 @@ hipError_t run_polar(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout,
   const int tilesX = (int)std::min<int64_t>((sX + 1023) / 1024, 256);
   const int tilesN = (int)std::min<int64_t>((sN + 1023) / 1024, 256);
   const int tilesZ = ((g.m + 31) / 32) * ((g.n + 31) / 32);
-  for (int c0 = 0; c0 < nfall; c0 += w.plCap) {
-    const int cnt = std::min(w.plCap, nfall - c0);
-    hipLaunchKernelGGL(k_pl_prepare<P>, dim3(tilesX, cnt), dim3(256), 0, st, w.pA, sB, w.lrC,
-                       w.lrT, w.lrSig, mask, w.lrScal, fslot, c0, mb, nb, tau, w.plX0,
+  // one failed block at a time: its step counts K and J then depend on that block
+  // alone, so its result is the same whatever other blocks failed beside it (alone or
+  // in a batch); failures are rare
+  for (int c0 = 0; c0 < nfall; ++c0) {
+    const int cnt = 1;
+    hipLaunchKernelGGL(k_pl_prepare<P>, dim3(tilesX, cnt), dim3(256), 0, st, Dout, g, sh,
+                       w.live_list, w.lrC, w.lrT, w.lrSig, mask, w.lrScal, fslot, c0, mb, nb, tau, w.plX0,
                        w.plScal);
     if ((e = last()) != hipSuccess) return e;
     if ((e = hipMemcpyAsync(w.hostPl, w.plScal, sizeof(float) * 4 * cnt, hipMemcpyDeviceToHost,
@@ -272,21 +281,18 @@ hipError_t run_polar(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout,
     const float* X = w.plX0;
     float* Xn = w.plXa;
     for (int k = 0; k < K; ++k) {
-      if ((e = batched_sgemm(w.blas, true, false, nb, nb, mb, X, mb, sX, X, mb, sX, w.plT, nb,
-                             sN, cnt)) != hipSuccess)
+      if ((e = launch_gemm(true, nb, nb, mb, X, mb, sX, X, mb, sX, w.plT, nb, sN, nullptr, cnt, cnt, st)) != hipSuccess)
         return e;
       hipLaunchKernelGGL(k_pl_affine, dim3(tilesN, cnt), dim3(256), 0, st, w.plT, nb, 1.5f,
                          -0.5f);
       if ((e = last()) != hipSuccess) return e;
-      if ((e = batched_sgemm(w.blas, false, false, mb, nb, nb, X, mb, sX, w.plT, nb, sN, Xn, mb,
-                             sX, cnt)) != hipSuccess)
+      if ((e = launch_gemm(false, mb, nb, nb, X, mb, sX, w.plT, nb, sN, Xn, mb, sX, nullptr, cnt, cnt, st)) != hipSuccess)
         return e;
       X = Xn;
       Xn = (Xn == w.plXa) ? w.plXb : w.plXa;
     }
     // H = Q^T (E' / alpha); S = alpha sym(H) - tau I; Y0 = S / alpha_S
-    if ((e = batched_sgemm(w.blas, true, false, nb, nb, mb, X, mb, sX, w.plX0, mb, sX, w.plT, nb,
-                           sN, cnt)) != hipSuccess)
+    if ((e = launch_gemm(true, nb, nb, mb, X, mb, sX, w.plX0, mb, sX, w.plT, nb, sN, nullptr, cnt, cnt, st)) != hipSuccess)
       return e;
     hipLaunchKernelGGL(k_pl_shift, dim3(tilesN, cnt), dim3(256), 0, st, w.plT, w.plS, w.plY, nb,
                        tau, w.plScal);
@@ -295,25 +301,21 @@ hipError_t run_polar(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout,
     float* Y = w.plY;
     float* Yn = w.plT;
     for (int j = 0; j < J; ++j) {
-      if ((e = batched_sgemm(w.blas, false, false, nb, nb, nb, Y, nb, sN, Y, nb, sN, w.plW, nb,
-                             sN, cnt)) != hipSuccess)
+      if ((e = launch_gemm(false, nb, nb, nb, Y, nb, sN, Y, nb, sN, w.plW, nb, sN, nullptr, cnt, cnt, st)) != hipSuccess)
         return e;
       hipLaunchKernelGGL(k_pl_affine, dim3(tilesN, cnt), dim3(256), 0, st, w.plW, nb, 1.5f,
                          -0.5f);
       if ((e = last()) != hipSuccess) return e;
-      if ((e = batched_sgemm(w.blas, false, false, nb, nb, nb, Y, nb, sN, w.plW, nb, sN, Yn, nb,
-                             sN, cnt)) != hipSuccess)
+      if ((e = launch_gemm(false, nb, nb, nb, Y, nb, sN, w.plW, nb, sN, Yn, nb, sN, nullptr, cnt, cnt, st)) != hipSuccess)
         return e;
       std::swap(Y, Yn);
     }
     // (S)_+ = S (I + Y) / 2, then Ze = Q (S)_+ into the X0 buffer
     hipLaunchKernelGGL(k_pl_affine, dim3(tilesN, cnt), dim3(256), 0, st, Y, nb, 0.5f, 0.5f);
     if ((e = last()) != hipSuccess) return e;
-    if ((e = batched_sgemm(w.blas, false, false, nb, nb, nb, w.plS, nb, sN, Y, nb, sN, w.plW, nb,
-                           sN, cnt)) != hipSuccess)
+    if ((e = launch_gemm(false, nb, nb, nb, w.plS, nb, sN, Y, nb, sN, w.plW, nb, sN, nullptr, cnt, cnt, st)) != hipSuccess)
       return e;
-    if ((e = batched_sgemm(w.blas, false, false, mb, nb, nb, X, mb, sX, w.plW, nb, sN, Xn, mb,
-                           sX, cnt)) != hipSuccess)
+    if ((e = launch_gemm(false, mb, nb, nb, X, mb, sX, w.plW, nb, sN, Xn, mb, sX, nullptr, cnt, cnt, st)) != hipSuccess)
       return e;
     hipLaunchKernelGGL(k_pl_rebuild<P>, dim3(tilesZ, cnt), dim3(256), 0, st, Zout, Dout, g, sh,
                        w.live_list, fslot, c0, w.lrC, w.lrV, w.lrSig, mask, tau, Xn, w.plScal);

@@ -3,7 +3,6 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <cstddef>
 #include <cstdint>
@@ -43,7 +42,8 @@ struct Plan {
       off_pW[MSLD_MAX_SCALES], off_pflag[MSLD_MAX_SCALES], off_pg[MSLD_MAX_SCALES],
       off_lr[MSLD_MAX_SCALES], off_pl[MSLD_MAX_SCALES];
   int pl_cap[MSLD_MAX_SCALES];   // polar fallback chunk (0: none)
-  size_t off_split[MSLD_MAX_SCALES];   // split-K partials (tall low-rank blocks; 0: none)
+  size_t off_split[MSLD_MAX_SCALES];   // split partials (tall low-rank blocks; 0: none)
+  size_t off_part64[MSLD_MAX_SCALES];  // float64 Gram partials of the reduced block
   int lds_cap[MSLD_MAX_SCALES];    // LDS tier: workgroups per CU cap (0: as many as fit)
   int lrs_wide[MSLD_MAX_SCALES];   // fused low-rank kernel: first pass with 2p
   // averaged cycle spinning: shifts per iteration (0: one random shift), whether the
@@ -68,6 +68,9 @@ double lambda_default(int M, int N, int m, int n);
 msld_status validate_params(const msld_params* p);
 msld_status make_plan(const msld_params* p, int ninst, Plan* pl);
 bool same_class(const msld_params& a, const msld_params& b);
+// scale i's driver reads a count back from the device every iteration (a low-rank
+// scale whose blocks exceed the LDS tier: its polar fallback is sized on the host)
+bool host_waits(const Plan& pl, int i);
 
 }  // namespace msld
 
@@ -90,7 +93,6 @@ struct msld_solver {
   hipEvent_t ev_join[MSLD_MAX_SCALES];
   hipEvent_t ev_sfork[MSLD_MAX_SCALES];   // after scale i's stream pass (its own fork point)
   int early_fork;   // scales fork after their own stream pass (planes <= 2^24 elements)
-  rocblas_handle blas[MSLD_MAX_SCALES];   // one per low-rank scale, bound to its stream
   msld::ScaleWork work[MSLD_MAX_SCALES];
   msld::StreamAll sall;   // the stream pass of all decomposed scales (one launch)
   const uint8_t* mask;    // observed-entry mask (caller-owned, device) or null

@@ -1,9 +1,12 @@
 import os
 import sys
 
-# the oracle works on many tiny matrices: threaded BLAS only adds overhead there
-for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+# the oracle works on many tiny matrices: threaded BLAS only adds overhead there; its
+# Jacobi SVD spreads a batch of blocks over OpenMP threads (at most 16: the host share
+# of one GPU)
+for _v in ("OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
     os.environ.setdefault(_v, "1")
+os.environ.setdefault("OMP_NUM_THREADS", str(max(1, min(16, os.cpu_count() or 1))))
 # the hardware queue count the benchmark runs with: every scale stream (and batch class)
 # then runs on a queue of its own, so the tests see the same concurrency
 os.environ["GPU_MAX_HW_QUEUES"] = "16"

@@ -33,10 +33,13 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layout_matches_header():
     # int32 M,N,L; 16+16 int32; 16 float; rho,max_iters,tol,check_every,cycle_spin,lowrank_min;
     # 4 pad; u64 seed; 16 int32 kinds; int32 spin_count, image_w; 16 int32 patch_w
-    assert ctypes.sizeof(msld.Params) == 4 * 3 + 4 * 48 + 4 * 6 + 4 + 8 + 4 * 16 + 8 + 4 * 16
-    assert msld.Params.patch_w.offset == ctypes.sizeof(msld.Params) - 64
+    base = 4 * 3 + 4 * 48 + 4 * 6 + 4 + 8 + 4 * 16 + 8 + 4 * 16
+    assert ctypes.sizeof(msld.Params) == base + 8    # fork_mode, padded to 8 bytes
+    assert msld.Params.patch_w.offset == base - 64
+    assert msld.Params.fork_mode.offset == base
     assert msld.Params.shift_seed.offset % 8 == 0
-    assert ctypes.sizeof(msld.Result) == 4 + 4 + 8 + 8 * 8 * 16
+    assert ctypes.sizeof(msld.Result) == 4 + 4 + 8 + 8 + 9 * 8 * 16
+    assert msld.Result.dual_resid.offset == 16
 
 
 def test_status_strings():

@@ -39,7 +39,8 @@ def test_batch_matches_alone_and_oracle(lib):
         err = max(_rel(zb[i], za[i], ny) for i in range(len(inst.ladder)))
         worst = max(worst, err)
         assert infos[j]["iters"] == 30
-        assert err <= 1e-5, (j, inst.Y.shape, inst.ladder, err)
+        # every kernel treats a block the same way whatever else runs beside it
+        assert np.array_equal(zb, za), (j, inst.Y.shape, inst.ladder, err)
     print(f"batch vs alone: worst rel diff {worst:.2e}", flush=True)
     for j in (0, 5):
         inst = insts[j]

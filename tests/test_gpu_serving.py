@@ -49,13 +49,11 @@ def test_server_alone_equals_mix_and_oracle(lib):
         it_m, r_m, Z_m = mix[rid]
         print(f"request {rid} {inst.Y.shape} L={len(inst.ladder)}: alone {it_a} it r={r_a:.3e}; "
               f"mix {it_m} it r={r_m:.3e}", flush=True)
-        # the same iteration count, and Z equal up to the GEMM kernel rocBLAS picks for a
-        # different batch count (bitwise equal when no low-rank scale is involved)
-        assert abs(it_a - it_m) <= 1
-        scale = np.linalg.norm(inst.Y)
+        # the same iteration count and bitwise the same components: every kernel treats
+        # a block the same way whatever else runs beside it
+        assert it_a == it_m
         for i in range(len(inst.ladder)):
-            d = np.linalg.norm(Z_a[i] - Z_m[i]) / max(np.linalg.norm(Z_a[i]), 1e-3 * scale)
-            assert d <= 1e-5, (rid, i, d)
+            assert np.array_equal(Z_a[i], Z_m[i]), (rid, i)
     # against the oracle's tolerance-stopped ADMM, for two of the requests
     for rid, inst in reqs[:2]:
         ref = O.admm(inst.Y, inst.ladder, rho=1.0, iters=300, tol=1e-4, check_every=1)

@@ -297,6 +297,18 @@ def test_admm_grid_shift_equivariance():
     assert np.allclose(b["Z"], np.roll(a["Z"], d, axis=(1, 2)), atol=1e-12)
 
 
+def test_admm_dual_residual():
+    """The dual residual rho ||Z^k - Z^(k-1)|| / ||Y||: from Z^0 = 0 the first one is
+    rho ||Z^1|| / ||Y||; it vanishes at the fixed point and scales with rho."""
+    inst = make_instance(16, 16, [(1, 1), (4, 4), (16, 16)], 0.05, seed=0)
+    Y = inst.Y.astype(np.float64)
+    one = O.admm(Y, inst.ladder, rho=2.0, iters=1)
+    assert math.isclose(one["dual"], 2.0 * np.linalg.norm(one["Z"]) / np.linalg.norm(Y),
+                        rel_tol=1e-12)
+    assert O.admm(Y, inst.ladder, rho=2.0, iters=5)["dual"] > 1e-3
+    assert O.admm(Y, inst.ladder, rho=2.0, iters=1500)["dual"] < 1e-8
+
+
 def test_admm_kkt_and_duality_gap():
     """At convergence (no cycle spinning) the ADMM fixed point solves eq:cvx:
     consensus sum Z_i = Y, all U_i equal, rho*U is dual feasible with the dual norm
