@@ -43,7 +43,8 @@ typedef enum {
   MSLD_ENOMEM = -2,    /* device or host allocation failed */
   MSLD_EDEVICE = -3,   /* a HIP runtime call failed; the handle is now unusable */
   MSLD_ENUMERIC = -4,  /* the iterate became non-finite (NaN/Inf in Y or overflow) */
-  MSLD_EBUSY = -5      /* reserved for queue-full conditions */
+  MSLD_EBUSY = -5,     /* reserved for queue-full conditions */
+  MSLD_ETOOLARGE = -6  /* the problem exceeds a fixed capacity (msld_bsvt_noalloc) */
 } msld_status;
 
 /* Problem and solver parameters (Sec. 2 partition, Sec. 4 lambda, Sec. 7 ADMM,
@@ -296,6 +297,24 @@ msld_status msld_default_lambda(int32_t M, int32_t N, int32_t m, int32_t n, floa
  * 0 <= i < 16. */
 msld_status msld_cycle_shift(uint64_t seed, int32_t k, int32_t i, int32_t m, int32_t n,
                              int32_t *sr, int32_t *sc);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the block-wise SVT of msld_bsvt
+ * without a handle, d_Z = Shift_{-s}(BSVT_tau(Shift_s(d_V))) with m x n blocks, on the
+ * caller's stream (NULL = legacy default stream), enqueued and not waited for. It calls
+ * no allocating routine: its workspace (an M x N dual plane, the live-block list, bound
+ * partials, counters) is a fixed 32 MiB device array inside the library, held by every
+ * device the function runs on until the process ends, and every call on a device
+ * shares it, so calls that overlap on one device (concurrent streams or threads) race:
+ * serialise them. d_V and d_Z are M x N row-major device buffers of the current device
+ * and may alias; 0 <= sr < m, 0 <= sc < n, tau >= 0. Block shapes of the register and
+ * LDS tiers only (the blocks msld_bsvt decomposes with full one-sided Jacobi when its
+ * handle has lowrank_min < 0); 1 x 1 blocks and blocks too large for LDS return
+ * MSLD_EINVAL, a workspace beyond the 32 MiB (about M N <= 7 million elements, less for
+ * tall blocks) returns MSLD_ETOOLARGE, both before anything is enqueued. Results equal
+ * msld_bsvt's on a handle with lowrank_min < 0 bit for bit. */
+msld_status msld_bsvt_noalloc(int32_t M, int32_t N, int32_t m, int32_t n, const float *d_V,
+                              float *d_Z, float tau, int32_t sr, int32_t sc, void *hip_stream);
 
 /* The same shifts computed by device code (the code the kernels run), for
  * count consecutive iterations k0..k0+count-1 of every scale of the handle's

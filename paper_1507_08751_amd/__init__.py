@@ -80,6 +80,10 @@ EXPORTS = {
                                  ctypes.c_void_p, ctypes.c_float, ctypes.c_int32,
                                  ctypes.c_int32]),
     "msld_free": (None, [ctypes.c_void_p]),
+    "msld_bsvt_noalloc": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_float, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_void_p]),
     "msld_set_mask": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
     "msld_set_graph": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "msld_autotune": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
@@ -523,6 +527,25 @@ def bsvt(V, m, n, tau, shift=(0, 0), lowrank_min=0):
         return s.bsvt(0, V.contiguous(), tau, shift)
     finally:
         s.close()
+
+
+def bsvt_noalloc(V, m, n, tau, shift=(0, 0), out=None):
+    """msld_bsvt_noalloc: the same block-wise SVT without a handle and without any
+    device allocation by the library (its fixed device workspace is shared by every call
+    on a device: do not overlap calls). Enqueued on torch's current stream."""
+    import torch
+    lib = load()
+    if V.dtype != torch.float32 or not V.is_cuda or V.dim() != 2 or not V.is_contiguous():
+        raise ValueError("V must be a contiguous 2-D float32 CUDA tensor")
+    if out is None:
+        out = torch.empty_like(V)
+    with torch.cuda.device(V.device):
+        st = lib.msld_bsvt_noalloc(V.shape[0], V.shape[1], int(m), int(n),
+                                   ctypes.c_void_p(V.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                   float(tau), int(shift[0]), int(shift[1]),
+                                   _stream_ptr(torch, V.device))
+    _check(st, "msld_bsvt_noalloc")
+    return out
 
 
 def autotune(m, n, device=None):

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmsld.so")
 OBJ = os.path.join(os.path.dirname(HERE), "_build")
-SOURCES = ["kernels.hip", "lowrank.hip", "lowrank_small.hip", "mfma.hip", "polar.hip", "api.cpp",
+SOURCES = ["kernels.hip", "lowrank.hip", "lowrank_small.hip", "mfma.hip", "polar.hip", "noalloc.hip", "api.cpp",
            "server.cpp", "tune.cpp"]
 
 HIPCC_FLAGS = [

@@ -901,6 +901,7 @@ const char* msld_status_string(int32_t status) {
     case MSLD_EDEVICE: return "MSLD_EDEVICE: HIP runtime error";
     case MSLD_ENUMERIC: return "MSLD_ENUMERIC: non-finite iterate";
     case MSLD_EBUSY: return "MSLD_EBUSY: busy";
+    case MSLD_ETOOLARGE: return "MSLD_ETOOLARGE: beyond the fixed workspace of msld_bsvt_noalloc";
     default: return "MSLD_UNKNOWN";
   }
 }

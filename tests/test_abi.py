@@ -44,7 +44,7 @@ def test_struct_layout_matches_header():
 
 def test_status_strings():
     lib = msld.load()
-    for code in [0, -1, -2, -3, -4, -5]:
+    for code in [0, -1, -2, -3, -4, -5, -6]:
         assert lib.msld_status_string(code).startswith(b"MSLD_")
 
 
