@@ -557,7 +557,8 @@ def main():
             f"block-iters, sweeps {stats['sweeps'][i]}, rank {stats['rank'][i]}, "
             f"certified {stats['certified'][i]} (fail coupling {stats['fail_coupling'][i]}, "
             f"bound {stats['fail_bound'][i]}, polar {stats['polar'][i]}); undecided by the trace "
-            f"bound {stats['undecided'][i]}")
+            f"bound {stats['undecided'][i]}, certified by Collatz-Wielandt only "
+            f"{stats['cw_certified'][i]}")
     roof, extra = stream_roofline(prof, tiers, M, N, K)
     out = {"metric": METRIC, "value": round(ips, 4), "unit": "iters/s", "n_gpus": 1, "steps": K,
            "warmup": W, "ms_per_step": round(1e3 * sec / K, 3), "higher_is_better": True,

@@ -162,6 +162,8 @@ typedef struct msld_result {
   uint64_t undecided[MSLD_MAX_SCALES];    /* low-rank blocks whose certificate needed the
                                              remainder Gram E^T E (the trace bound left them
                                              undecided) */
+  uint64_t cw_certified[MSLD_MAX_SCALES]; /* of those, certified by the Collatz-Wielandt
+                                             bound where the Frobenius bound alone failed */
 } msld_result;
 
 typedef struct msld_solver msld_solver; /* opaque */

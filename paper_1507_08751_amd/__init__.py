@@ -68,7 +68,8 @@ class Result(ctypes.Structure):
                 ("fail_bound", ctypes.c_uint64 * MAX_SCALES),
                 ("polar", ctypes.c_uint64 * MAX_SCALES),
                 ("polar_steps", ctypes.c_uint64 * MAX_SCALES),
-                ("undecided", ctypes.c_uint64 * MAX_SCALES)]
+                ("undecided", ctypes.c_uint64 * MAX_SCALES),
+                ("cw_certified", ctypes.c_uint64 * MAX_SCALES)]
 
 
 EXPORTS = {
@@ -275,7 +276,8 @@ class Solver:
                      "fail_bound": list(res.fail_bound)[:self.L],
                 "polar": list(res.polar)[:self.L],
                 "polar_steps": list(res.polar_steps)[:self.L],
-                "undecided": list(res.undecided)[:self.L]}
+                "undecided": list(res.undecided)[:self.L],
+                "cw_certified": list(res.cw_certified)[:self.L]}
 
     def _check_yz(self, Y, Z):
         torch = self._torch
@@ -312,7 +314,8 @@ class Solver:
                 "fail_bound": list(res.fail_bound)[:self.L],
                 "polar": list(res.polar)[:self.L],
                 "polar_steps": list(res.polar_steps)[:self.L],
-                "undecided": list(res.undecided)[:self.L]}
+                "undecided": list(res.undecided)[:self.L],
+                "cw_certified": list(res.cw_certified)[:self.L]}
 
     def set_graph(self, enable=True):
         """Allow (default) or forbid replaying iterations from captured HIP graphs;

@@ -885,6 +885,7 @@ static msld_status fill_stats(msld_solver* s, msld_result* info) {
     info->polar[i] = (uint64_t)s->work[i].stats_host[0];
     info->polar_steps[i] = (uint64_t)(s->work[i].stats_host[1] + s->work[i].stats_host[2]);
     info->undecided[i] = st8[6];
+    info->cw_certified[i] = st8[7];
   }
   return MSLD_OK;
 }

@@ -351,17 +351,27 @@ __global__ void __launch_bounds__(256) k_lr_reduced(const float* X, const float*
     if (tid < P) sig[slot * P + tid] = (float)sqrt(fmax(K[tid][tid], 0.0));
     float* vr = Vr + (int64_t)slot * nb * P;
     float* tt = Tt + (int64_t)slot * nb * P;
-    // V_r = X W, T^T = W0 W: thread (row r, column l) pairs, 16 threads per row
-    for (int e = tid; e < nb * P; e += 256) {
-      const int r = e / P, l = e - (e / P) * P;
-      double o = 0.0, t = 0.0;
+    // V_r = X W, T^T = W0 W: one row per thread, its 2 P inputs read once (coalesced
+    // across the workgroup) and kept in registers
+    for (int r = tid; r < nb; r += 256) {
+      float xv[P], wv[P];
+#pragma unroll
       for (int j = 0; j < P; ++j) {
-        const double vjl = V[j][l];
-        o += (double)x[(int64_t)j * nb + r] * vjl;
-        t += (double)w0[(int64_t)j * nb + r] * vjl;
+        xv[j] = x[(int64_t)j * nb + r];
+        wv[j] = w0[(int64_t)j * nb + r];
       }
-      vr[(int64_t)l * nb + r] = (float)o;
-      tt[(int64_t)r * P + l] = (float)t;
+#pragma unroll 1
+      for (int l = 0; l < P; ++l) {
+        double o = 0.0, t = 0.0;
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+          const double vjl = V[j][l];
+          o += (double)xv[j] * vjl;
+          t += (double)wv[j] * vjl;
+        }
+        vr[(int64_t)l * nb + r] = (float)o;
+        tt[(int64_t)r * P + l] = (float)t;
+      }
     }
     __syncthreads();
   }
@@ -437,136 +447,61 @@ template <int P>
 __global__ void __launch_bounds__(256) k_lr_q(const float* Wg, const float* Vr, const float* mask,
                                               float* Qo, int nb, const int* list,
                                               const int* lcount) {
+  static_assert(P * P == 256, "one H entry per thread");
+  __shared__ float vs[kRC][P + 1], ws[kRC][P + 1];
   __shared__ float h[P * P];
   __shared__ float mk[P];
+  const int tid = threadIdx.x;
   const int cnt = *lcount;
   for (int c = blockIdx.x; c < cnt; c += gridDim.x) {
     const int slot = list[c];
-    const float* w = Wg + (int64_t)slot * nb * P;
-    const float* v = Vr + (int64_t)slot * nb * P;
+    const float* w = Wg + (int64_t)slot * nb * P;   // row-major: w[i P + k]
+    const float* v = Vr + (int64_t)slot * nb * P;   // column-major: v[l nb + i]
     float* q = Qo + (int64_t)slot * nb * P;
     __syncthreads();
-    if (threadIdx.x < P) mk[threadIdx.x] = mask[slot * P + threadIdx.x];
-    __syncthreads();
-    {
-      // H[k][l] = v_l . w_k over the masked pairs (one entry per thread)
-      const int k = threadIdx.x / P, l = threadIdx.x - (threadIdx.x / P) * P;
-      float sacc = 0.f;
-      if (mk[k] > 0.f && mk[l] > 0.f)
-        for (int i = 0; i < nb; ++i) sacc += v[l * nb + i] * w[(int64_t)i * P + k];
-      h[k * P + l] = sacc;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < nb * P; e += blockDim.x) {
-      const int k = e / nb, r = e - k * nb;
-      float sv = 0.f;
-      if (mk[k] > 0.f) {
-        float vh = 0.f;
-#pragma unroll
-        for (int l = 0; l < P; ++l)
-          if (mk[l] > 0.f) vh += v[l * nb + r] * h[k * P + l];
-        sv = w[(int64_t)r * P + k] - 0.5f * vh;
+    if (tid < P) mk[tid] = mask[slot * P + tid];
+    // H[k][l] = v_l . w_k over the masked pairs (thread (k, l), rows staged in LDS)
+    const int k = tid / P, l = tid - (tid / P) * P;
+    float hacc = 0.f;
+    for (int r0 = 0; r0 < nb; r0 += kRC) {
+      const int rows = min(kRC, nb - r0);
+      __syncthreads();
+      for (int e = tid; e < kRC * P; e += 256) {
+        const int j = e / kRC, r = e - j * kRC;   // column j, row r (column-major reads)
+        vs[r][j] = r < rows ? v[(int64_t)j * nb + r0 + r] : 0.f;
+        const int rr = e / P, jj = e - rr * P;     // row rr, column jj (row-major reads)
+        ws[rr][jj] = rr < rows ? w[(int64_t)(r0 + rr) * P + jj] : 0.f;
       }
-      q[e] = sv;
+      __syncthreads();
+#pragma unroll 8
+      for (int r = 0; r < kRC; ++r) hacc += vs[r][l] * ws[r][k];
     }
-  }
-}
-
-// E^T E = G - Q V^T - V Q^T (masked columns of V_r) on 64 x 64 tiles, to Pm, with
-// per-tile partial trace and squared Frobenius norm. Q and V rows of the tile's row
-// and column ranges are staged in LDS; each thread accumulates a 2 x 8 block (rows
-// i0 + il + 32 a, columns j0 + jg + 8 b), so one LDS value feeds several FMAs, and
-// each wave reads and writes 128-byte column segments of G and Pm.
-template <int P>
-__global__ void __launch_bounds__(256) k_lr_ge(const float* G, const float* Qm, const float* Vr,
-                                               const float* mask, float* Pm, int nb,
-                                               float* part, float* rowpart, const int* list,
-                                               const int* lcount) {
-  __shared__ float qi[64][P + 1], vi[64][P + 1], qj[64][P + 1], vj[64][P + 1];
-  __shared__ float mk[P];
-  __shared__ float red[8];
-  __shared__ float rs[8][64];
-  const int cnt = *lcount;
-  for (int cidx = blockIdx.y; cidx < cnt; cidx += gridDim.y) {
-  const int slot = list[cidx];
-  const int tn = (nb + 63) / 64;
-  const int ti = blockIdx.x % tn, tj = blockIdx.x / tn;
-  const int i0 = ti * 64, j0 = tj * 64;
-  const float* g = G + (int64_t)slot * nb * nb;
-  const float* q = Qm + (int64_t)slot * nb * P;
-  const float* v = Vr + (int64_t)slot * nb * P;
-  float* pm = Pm + (int64_t)slot * nb * nb;
-  const int tid = threadIdx.x;
-  __syncthreads();
-  if (tid < P) mk[tid] = mask[slot * P + tid];
-  __syncthreads();
-  for (int e = tid; e < 64 * P; e += 256) {
-    const int l = e / 64, r = e - l * 64;
-    const bool m = mk[l] > 0.f;
-    const int ri = i0 + r, rj = j0 + r;
-    qi[r][l] = ri < nb ? q[l * nb + ri] : 0.f;
-    vi[r][l] = (m && ri < nb) ? v[l * nb + ri] : 0.f;
-    qj[r][l] = rj < nb ? q[l * nb + rj] : 0.f;
-    vj[r][l] = (m && rj < nb) ? v[l * nb + rj] : 0.f;
-  }
-  __syncthreads();
-  const int il = tid & 31;
-  const int jg = tid >> 5;
-  float acc[2][8];
+    h[k * P + l] = (mk[k] > 0.f && mk[l] > 0.f) ? hacc : 0.f;
+    __syncthreads();
+    // Q[:, k] = W[:, k] - V H[k][:]^T / 2 on masked k (one row per thread)
+    for (int r = tid; r < nb; r += 256) {
+      float vv[P];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+      for (int j = 0; j < P; ++j) vv[j] = v[(int64_t)j * nb + r];
+#pragma unroll 1
+      for (int kk = 0; kk < P; ++kk) {
+        float sv = 0.f;
+        if (mk[kk] > 0.f) {
+          float vh = 0.f;
 #pragma unroll
-    for (int b = 0; b < 8; ++b) acc[a][b] = 0.f;
-#pragma unroll 4
-  for (int l = 0; l < P; ++l) {
-    const float qa0 = qi[il][l], qa1 = qi[il + 32][l];
-    const float va0 = vi[il][l], va1 = vi[il + 32][l];
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const float qb = qj[jg + 8 * b][l], vb = vj[jg + 8 * b][l];
-      acc[0][b] += qa0 * vb + va0 * qb;
-      acc[1][b] += qa1 * vb + va1 * qb;
-    }
-  }
-  float tr = 0.f, f2 = 0.f;
-  float ra[2] = {0.f, 0.f};
-#pragma unroll
-  for (int a = 0; a < 2; ++a) {
-    const int i = i0 + il + 32 * a;
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const int j = j0 + jg + 8 * b;
-      if (i < nb && j < nb) {
-        const float sv = g[(int64_t)j * nb + i] - acc[a][b];
-        pm[(int64_t)j * nb + i] = sv;
-        if (i == j) tr += sv;
-        f2 += sv * sv;
-        ra[a] += fabsf(sv);
+          for (int j = 0; j < P; ++j) vh += vv[j] * h[kk * P + j];
+          sv = w[(int64_t)r * P + kk] - 0.5f * vh;
+        }
+        q[(int64_t)kk * nb + r] = sv;
       }
     }
-  }
-  rs[jg][il] = ra[0];
-  rs[jg][il + 32] = ra[1];
-  tr = block_sum(tr, red);   // its barriers also order the rs writes before the reads
-  f2 = block_sum(f2, red);
-  if (tid == 0) {
-    part[((int64_t)slot * gridDim.x + blockIdx.x) * 2] = tr;
-    part[((int64_t)slot * gridDim.x + blockIdx.x) * 2 + 1] = f2;
-  }
-  // partial row |.| sums of this tile column (rows i0.., columns j0..j0+63)
-  if (tid < 64 && i0 + tid < nb) {
-    float r = 0.f;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) r += rs[k][tid];
-    rowpart[(int64_t)slot * nb * (tn + 1) + (int64_t)tj * nb + i0 + tid] = r;
-  }
   }
 }
 
 // Collatz-Wielandt bound for the symmetric M = E^T E (in Pm): with r = |M| 1 and
 // y = |M| r, lambda_max(M) <= rho(|M|) <= max_i y_i / r_i (a row with r_i = 0 is zero).
 // Three small steps on the tile partials, all in a fixed summation order:
-// k_lr_rsum: r_i = sum over tile columns of the row partials of k_lr_ge (slice tn);
+// k_lr_rsum: r_i = sum over tile columns of the row partials of E^T E (slice tn);
 // k_lr_cwy: per 64 x 64 tile, partial y_i over its columns (slices 0..tn-1);
 // k_lr_cwmax: y_i, the ratio, its maximum; scal[4] = min(||M||_F, bound) / tr(M).
 __global__ void __launch_bounds__(256) k_lr_rsum(float* rowpart, int nb, const int* list,
@@ -645,7 +580,7 @@ __global__ void __launch_bounds__(256) k_lr_cwmax(const float* rowpart, int nb, 
   }
 }
 
-// Reduce the per-tile partials of k_lr_ge in a fixed order: scal[2] = tr(E^T E),
+// Reduce the per-tile partials of E^T E in a fixed order: scal[2] = tr(E^T E),
 // scal[4] = ||E^T E||_F / tr(E^T E) (stage-0 bound factor).
 __global__ void k_lr_ge_reduce(const float* part, int tiles, float* scal, const int* list,
                                const int* lcount) {
@@ -660,6 +595,7 @@ __global__ void k_lr_ge_reduce(const float* part, int tiles, float* scal, const 
   }
   scal[slot * 8 + 2] = tr;
   scal[slot * 8 + 4] = tr > 0.f ? sqrtf(f2) / tr : 0.f;
+  scal[slot * 8 + 3] = scal[slot * 8 + 4];   // the Frobenius factor alone (statistics)
   }
 }
 
@@ -794,6 +730,9 @@ __global__ void k_lr_decide(const int* live, int slots, float* scal, const float
       const float b0 = fmaxf(sc[7], trE > 0.f ? trE * sc[4] : 0.f) + sqrtf(sc[6]);
       if (b0 <= lim && isfinite(b0)) {
         lr_certify(slot, sig, tau, pflag, stats);
+        // certified thanks to the Collatz-Wielandt bound (the Frobenius one alone fails)
+        const float bfro = fmaxf(sc[7], trE > 0.f ? trE * sc[3] : 0.f) + sqrtf(sc[6]);
+        if (!(bfro <= lim)) atomicAdd(&stats[7], 1ull);
       } else {
         pflag[4 * slot + 3] = 1;
         const int u = atomicAdd(&counts[1], 1);
@@ -927,9 +866,9 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
     hipLaunchKernelGGL(k_lr_q<P>, dim3(slot_grid(S)), dim3(256), 0, st, w.lrT, w.lrV, dmask, w.lrY,
                        nb, flist, fcount);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_lr_ge<P>, dim3(gtiles, slot_grid(S, 8192 / gtiles + 1)), dim3(256), 0, st,
-                       w.lrG, w.lrY, w.lrV, dmask, w.lrP, nb, w.lrQ, w.lrRow, flist, fcount);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_lr_ge(w.lrG, w.lrY, w.lrV, w.lrP, nb, w.lrQ, w.lrRow, flist, fcount, S, st)) !=
+        hipSuccess)
+      return e;
     // stage 0: Frobenius and Collatz-Wielandt bounds of E^T E
     hipLaunchKernelGGL(k_lr_ge_reduce, dim3(dgrid), dim3(256), 0, st, w.lrQ, gtiles, w.lrScal,
                        flist, fcount);

@@ -807,6 +807,105 @@ hipError_t launch_gemm(bool ta, int M, int N, int K, const float* A, int lda, in
   return hipGetLastError();
 }
 
+// E^T E = G - Q V^T - V Q^T for the undecided slots of the certificate (Q is zero outside
+// the masked columns, so V needs no mask), written to Pm with per-tile partial trace and
+// squared Frobenius norm (part) and per-row partial |.| sums of each 64-column tile
+// column (rowpart, slices 0 .. tn-1). 64 x 64 tiles, one 32 x 32 quadrant per wave on
+// v_mfma_f32_32x32x2f32 with K = 2P: A = [Q | V] at the quadrant's column indices j,
+// B = [V | Q] at its row indices i, so the accumulators hold D(j, i) with i = lane % 32
+// and each store of a column of Pm is a 128-byte segment. Q, V and the G tile are read
+// straight into registers in the accumulator layout.
+template <int P>
+__global__ void __launch_bounds__(256) k_mf_lr_ge(const float* G, const float* Qm,
+                                                  const float* Vr, float* Pm, int nb,
+                                                  float* part, float* rowpart, const int* list,
+                                                  const int* lcount) {
+  static_assert(P % 2 == 0, "K pairs");
+  __shared__ float red[2][4];
+  __shared__ float rs[2][64];
+  const int cnt = *lcount;
+  const int tn = (nb + 63) / 64;
+  const int ti = blockIdx.x % tn, tj = blockIdx.x / tn;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 31, lk = lane >> 5;
+  const int i = ti * 64 + (wv & 1) * 32 + li;   // B operand row, accumulator column
+  const int jb = tj * 64 + (wv >> 1) * 32;      // first D row of the quadrant
+  const int ja = jb + li;                       // A operand row
+  const bool iok = i < nb, jok = ja < nb;
+  for (int cidx = blockIdx.y; cidx < cnt; cidx += gridDim.y) {
+    const int slot = list[cidx];
+    const float* g = G + (int64_t)slot * nb * nb;
+    const float* q = Qm + (int64_t)slot * nb * P;
+    const float* v = Vr + (int64_t)slot * nb * P;
+    float* pm = Pm + (int64_t)slot * nb * nb;
+    float gv[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int j = jb + 8 * (r >> 2) + 4 * lk + (r & 3);
+      gv[r] = (iok && j < nb) ? g[(int64_t)j * nb + i] : 0.f;
+    }
+    float qa[P / 2], va[P / 2], qb[P / 2], vb[P / 2];
+#pragma unroll
+    for (int s = 0; s < P / 2; ++s) {
+      const int64_t l = 2 * s + lk;
+      qa[s] = jok ? q[l * nb + ja] : 0.f;
+      va[s] = jok ? v[l * nb + ja] : 0.f;
+      qb[s] = iok ? q[l * nb + i] : 0.f;
+      vb[s] = iok ? v[l * nb + i] : 0.f;
+    }
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+#pragma unroll
+    for (int s = 0; s < P / 2; ++s) acc = mfma32(qa[s], vb[s], acc);
+#pragma unroll
+    for (int s = 0; s < P / 2; ++s) acc = mfma32(va[s], qb[s], acc);
+    float tr = 0.f, f2 = 0.f, ra = 0.f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int j = jb + 8 * (r >> 2) + 4 * lk + (r & 3);
+      if (iok && j < nb) {
+        const float sv = gv[r] - acc[r];
+        pm[(int64_t)j * nb + i] = sv;
+        if (i == j) tr += sv;
+        f2 += sv * sv;
+        ra += fabsf(sv);
+      }
+    }
+    ra += __shfl_xor(ra, 32);   // the quadrant's other 16 columns
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      tr += __shfl_xor(tr, o);
+      f2 += __shfl_xor(f2, o);
+    }
+    __syncthreads();   // the previous slot's reads of rs and red are done
+    if (lk == 0) rs[wv >> 1][(wv & 1) * 32 + li] = ra;
+    if (lane == 0) {
+      red[0][wv] = tr;
+      red[1][wv] = f2;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      float* pp = part + ((int64_t)slot * gridDim.x + blockIdx.x) * 2;
+      pp[0] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+      pp[1] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+    }
+    if (tid < 64 && ti * 64 + tid < nb)
+      rowpart[(int64_t)slot * nb * (tn + 1) + (int64_t)tj * nb + ti * 64 + tid] =
+          rs[0][tid] + rs[1][tid];
+  }
+}
+
+hipError_t launch_lr_ge(const float* G, const float* Q, const float* V, float* Pm, int nb,
+                        float* part, float* rowpart, const int* list, const int* lcount,
+                        int slots, hipStream_t st) {
+  const int tn = (nb + 63) / 64;
+  const int tiles = tn * tn;
+  hipLaunchKernelGGL(k_mf_lr_ge<16>, dim3(tiles, grid_slots(slots, tiles)), dim3(256), 0, st, G,
+                     Q, V, Pm, nb, part, rowpart, list, lcount);
+  return hipGetLastError();
+}
+
 hipError_t launch_mf_rebuild(const ScaleGeom& g, const ShiftSpec& sh, float* Zout, float* Dout,
                              const int* count, const int* slot_list, const int* live_list,
                              int slots, const int* pflag, const float* Af, const float* Vr,

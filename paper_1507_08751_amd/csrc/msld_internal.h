@@ -286,6 +286,11 @@ hipError_t launch_mf_rebuild(const ScaleGeom& g, const ShiftSpec& sh, float* Zou
                              const int* count, const int* slot_list, const int* live_list,
                              int slots, const int* pflag, const float* Af, const float* Vr,
                              const float* sig, const float* mask, float tau, hipStream_t st);
+// E^T E = G - Q V^T - V Q^T (P = 16 columns) of the listed slots to Pm, with per-tile
+// partial trace and squared norm (part) and per-row partial |.| sums (rowpart).
+hipError_t launch_lr_ge(const float* G, const float* Q, const float* V, float* Pm, int nb,
+                        float* part, float* rowpart, const int* list, const int* lcount,
+                        int slots, hipStream_t st);
 hipError_t run_polar(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout, float tau,
                      const ShiftSpec& sh, int nfall, hipStream_t st);
 // Certified low-rank BlockSVT of the live blocks (count on the device); failed
