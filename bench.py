@@ -51,22 +51,34 @@ def consensus_bytes_per_elem(L, n1x1):
     return 4 * (1 + L + 1 + 3 * n1x1)
 
 
-def kernels_source_digest():
+STREAM_SRC_BEGIN = b"// ---------------------------------------------------------------- stream pass"
+STREAM_SRC_END = b"// ------------------------------------------------------ one-sided Jacobi core"
+
+
+def stream_source_digest():
+    """Digest of the stream pass's source text (its section of kernels.hip, from its
+    header comment to the next section's), so that the traffic counters stay valid
+    while that code is unchanged."""
     import hashlib
     with open(os.path.join(ROOT, "paper_1507_08751_amd", "csrc", "kernels.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+        src = f.read()
+    a = src.find(STREAM_SRC_BEGIN)
+    b = src.find(STREAM_SRC_END)
+    if a < 0 or b <= a:
+        return None
+    return hashlib.sha256(src[a:b]).hexdigest()[:16]
 
 
 def measured_traffic():
     """HBM bytes per k_stream_all launch from the committed rocprofv3 counter summary:
     FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the stream kernel, each scaled by
     what the same counter reads for a plain copy of known size. None when the summary
-    is missing or was taken on a different kernels.hip."""
+    is missing or was taken on a different stream pass source."""
     try:
         with open(TRAFFIC_PROFILE) as f:
             kv = dict(line.strip("- `\n").split(": ", 1) for line in f
                       if line.startswith("- `") and ": " in line)
-        if kv.get("kernels.hip digest") != kernels_source_digest():
+        if kv.get("stream pass source digest") != stream_source_digest():
             return None
         fr = float(kv["copy bytes read"]) / (1024.0 * float(kv["copy FETCH_SIZE KiB"]))
         fw = float(kv["copy bytes written"]) / (1024.0 * float(kv["copy WRITE_SIZE KiB"]))
@@ -452,6 +464,65 @@ def batch_bench(args):
         s.close()
 
 
+PEAK_FP32_TFLOPS = 157.3        # MI355X dense FP32, matrix cores and packed vector ALU alike
+LR_P = 16                       # subspace width of the low-rank chain (128 wide and up)
+LR_PRODUCTS = 8                 # G X products of its subspace iteration (7) and W = G V_r
+LRS_P, LRS_PRODUCTS = 4, 7      # the fused 32-wide kernel
+
+
+def svd_flops(tier, m, n, live, sweeps, rank):
+    """Algorithmic FP32 flops of one scale's BlockSVT over `live` block-iterations.
+
+    Jacobi tiers (register, LDS): per live m x n block (m >= n) and sweep,
+    3 n (n - 1) (2m + n) (the dot products and rotations of n (n - 1) / 2 column pairs,
+    with V), plus 2 m n k for the rebuild at output rank k; sweeps and ranks are the
+    device counters. Low-rank tiers: the matrix products per live block, the Gram
+    matrix's unique entries m n (n + 1), the subspace products 2 n^2 P each, the
+    projection B X and the rebuild 2 m n P each; the certificate's extra products for
+    undecided blocks are not counted. Skipped blocks count nothing."""
+    m, n = max(m, n), min(m, n)
+    if tier in ("register", "lds"):
+        return sweeps * 3.0 * n * (n - 1) * (2 * m + n) + 2.0 * m * n * rank
+    if tier == "lowrank":
+        P, k = LR_P, LR_PRODUCTS
+    elif tier == "lowrank_small":
+        P, k = LRS_P, LRS_PRODUCTS
+    else:
+        return 0.0
+    return live * (m * n * (n + 1.0) + k * 2.0 * n * n * P + 2 * 2.0 * m * n * P)
+
+
+def svd_rooflines(prof, stats, tiers, K):
+    """The Gram kernel B^T B of the low-rank scales (their dominant matrix-core kernel,
+    timed alone with HIP events on the scale's stream), and each scale's BlockSVT
+    (SVD and finish phases) against the FP32 peak."""
+    gflops, gms, launches = 0.0, 0.0, 0
+    per_scale = []
+    for i, (m, n) in enumerate(LADDER):
+        if tiers[i] == "1x1":
+            continue
+        live = stats["live"][i]
+        if tiers[i] == "lowrank":
+            mm, nn = max(m, n), min(m, n)
+            gflops += live * mm * nn * (nn + 1.0)
+            gms += prof["gram_ms"][i]
+            launches += K
+        fl = svd_flops(tiers[i], m, n, live, stats["sweeps"][i], stats["rank"][i])
+        ms = prof["scale_ms"][i][2] + prof["scale_ms"][i][3]
+        tf = fl / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+        per_scale.append({"scale": f"{m}x{n}", "tier": tiers[i],
+                          "flops_per_iter": round(fl / K), "ms_per_iter": round(ms / K, 4),
+                          "achieved_tflops": round(tf, 2),
+                          "frac": round(tf / PEAK_FP32_TFLOPS, 4)})
+    tf = gflops / (gms * 1e-3) / 1e12 if gms > 0 else 0.0
+    gram = {"bound": "mfma", "kernel": "k_mf_gram", "achieved": round(tf, 2),
+            "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(tf / PEAK_FP32_TFLOPS, 4),
+            "launches": launches, "avg_launch_ms": round(gms / max(1, launches), 4),
+            "algorithmic_flops_per_launch": round(gflops / max(1, launches)),
+            "flops_per_block": "m n (n + 1), the Gram matrix's unique entries"}
+    return gram, per_scale
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -473,7 +544,7 @@ def main():
     ap.add_argument("--hw-queues", type=int, default=None,
                     help="hardware queues per process (GPU_MAX_HW_QUEUES), 1..32; default 4 "
                          "for the 8192^2 run, 16 for the other modes")
-    ap.add_argument("--fork-mode", type=int, default=0, choices=[0, 1, 2],
+    ap.add_argument("--fork-mode", type=int, default=0, choices=[0, 1, 2, 3],
                     help="where the scales fork from the main stream (msld_params.fork_mode)")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the short serving measurement of the default run")
@@ -560,6 +631,35 @@ def main():
             f"bound {stats['undecided'][i]}, certified by Collatz-Wielandt only "
             f"{stats['cw_certified'][i]}")
     roof, extra = stream_roofline(prof, tiers, M, N, K)
+    if args.fork_mode == 3:
+        sprof, sstats, ssec = prof, stats, sec
+    else:
+        # the SVD figures come from the same K iterations with the scales run one after
+        # another on one stream (fork_mode 3), so that each phase's events time its own
+        # kernels rather than kernels sharing the chip with the other scales' chains
+        solver.close()
+        solver = msld.Solver(M, N, LADDER, rho=1.0, iters=K, cycle_spin=True, seed=0,
+                             device=dev, fork_mode=3)
+        solver.reset(Z)
+        torch.cuda.synchronize()
+        solver.profile_begin(K)
+        t0 = time.perf_counter()
+        solver.step(Y, Z, K)
+        torch.cuda.synchronize()
+        ssec = time.perf_counter() - t0
+        sprof = solver.profile_end()
+        sstats = solver.stats()
+        log(f"serial-scale run of the same {K} iterations: {K / ssec:.2f} iters/s")
+    gram_roof, svd_scales = svd_rooflines(sprof, sstats, tiers, K)
+    gram_roof["run"] = "scales one after another on one stream (fork_mode 3)"
+    gram_roof["serial_iters_per_s"] = round(K / ssec, 3)
+    # the whole iteration against HBM: every Z_i and U_i plane read and written once and
+    # Y read once, (4L + 1) 4 M N bytes
+    it_bytes = (4 * L + 1) * 4 * M * N
+    it_gbs = it_bytes / (sec / K) / 1e9
+    it_hbm = {"bound": "hbm", "algorithmic_bytes_per_iter": it_bytes,
+              "achieved": round(it_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+              "frac": round(it_gbs / PEAK_HBM_GBS, 4)}
     out = {"metric": METRIC, "value": round(ips, 4), "unit": "iters/s", "n_gpus": 1, "steps": K,
            "warmup": W, "ms_per_step": round(1e3 * sec / K, 3), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -567,8 +667,13 @@ def main():
                                   f"rank-1 blocks per scale + N(0,0.01^2) noise, default lambda, "
                                   f"rho=1, random cycle spinning, {K} iterations from zero",
                       "M": M, "N": N, "ladder": [list(b) for b in LADDER], "iters": K,
+                      "timed_window": f"iterations 1..{K} of a solve from zero (the warm-up "
+                                      f"is a separate {W}-iteration solve)",
                       "hw_queues": HW_QUEUES},
-           "roofline": roof, "roofline_consensus": extra,
+           "roofline": roof, "roofline_consensus": extra, "roofline_svd": gram_roof,
+           "blocksvt_fp32": svd_scales, "iteration_hbm": it_hbm,
+           "live_fraction": {f"{m}x{n}": round(stats["live"][i] / ((M // m) * (N // n) * K), 4)
+                             for i, (m, n) in enumerate(LADDER)},
            "phases_ms_per_iter": {
                "consensus": round(prof["consensus_ms"] / K, 4),
                "stream_all": round(prof["stream_ms"] / K, 4),

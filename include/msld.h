@@ -112,7 +112,10 @@ typedef enum {
  *                 scale right after its own stream pass on planes of at most 2^24
  *                 elements, one fork after every pass on larger planes); 1 = always
  *                 right after each scale's own pass; 2 = always one fork after every
- *                 pass. Other values: MSLD_EINVAL. */
+ *                 pass; 3 = no fork: every scale's BlockSVT runs on the handle's
+ *                 stream, one scale after another (no two kernels of an iteration
+ *                 overlap, so phase timings are each kernel's own). Other values:
+ *                 MSLD_EINVAL. */
 #define MSLD_KIND_BLOCK 0
 #define MSLD_KIND_NOISE 1
 #define MSLD_KIND_SPATIAL 2
@@ -260,12 +263,13 @@ msld_status msld_set_mask(msld_solver *s, const uint8_t *d_mask, int64_t ldmask)
  * creates events for the next n iterations (each iteration records them as it is
  * enqueued; later iterations are not recorded). msld_profile_end synchronises and
  * returns elapsed milliseconds summed over the recorded iterations in
- * ms[(L + 1) * 4]: ms[4L] the consensus pass, ms[4L + 1] the stream pass of all
+ * ms[(L + 1) * 4 + L]: ms[4L] the consensus pass, ms[4L + 1] the stream pass of all
  * decomposed scales (one launch: shifted gather, bound test, speculative write);
  * for scale i, ms[4i + 1] the rest of the set-up (bound reduction, panel load),
  * ms[4i + 2] the SVD kernels (register / LDS / fused low-rank kernel, the batched
  * low-rank path, or all panel-round launches), ms[4i + 3] the rest (fallbacks,
- * gains, rebuild); ms[4i + 0] stays 0 (the stream pass is shared). Scales run
+ * gains, rebuild); ms[4i + 0] stays 0 (the stream pass is shared); ms[4(L + 1) + i]
+ * the Gram kernel B^T B alone of a low-rank scale (inside ms[4i + 2]). Scales run
  * concurrently, so their times overlap. round_launches[L] receives the number of panel-round
  * kernel launches per scale, *iters_recorded the number of iterations covered. */
 msld_status msld_profile_begin(msld_solver *s, int32_t max_iters);

@@ -344,7 +344,7 @@ class Solver:
         _check(self._lib.msld_profile_begin(self._h, int(max_iters)), "msld_profile_begin")
 
     def profile_end(self):
-        ms = (ctypes.c_double * (4 * (self.L + 1)))()
+        ms = (ctypes.c_double * (4 * (self.L + 1) + self.L))()
         rl = (ctypes.c_int64 * self.L)()
         n = ctypes.c_int32()
         with self._torch.cuda.device(self.device):
@@ -352,7 +352,8 @@ class Solver:
                    "msld_profile_end")
         per = [list(ms[4 * i:4 * i + 4]) for i in range(self.L)]
         return {"scale_ms": per, "consensus_ms": ms[4 * self.L],
-                "stream_ms": ms[4 * self.L + 1], "round_launches": list(rl), "iters": n.value}
+                "stream_ms": ms[4 * self.L + 1], "round_launches": list(rl), "iters": n.value,
+                "gram_ms": list(ms[4 * (self.L + 1):4 * (self.L + 1) + self.L])}
 
     def bsvt(self, scale, V, tau, shift=(0, 0), out=None):
         """Z = Shift_{-s}(BSVT_tau(Shift_s(V))) with scale `scale`'s block shape."""

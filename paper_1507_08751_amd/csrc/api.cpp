@@ -18,6 +18,9 @@ namespace msld {
 namespace {
 
 constexpr int kResidPartsMax = 1024;
+// profiling events per scale and iteration: 0-4 bracket the phases, 5-6 the Gram kernel
+// of a low-rank tier
+constexpr int kEvPerScale = 7;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -53,7 +56,7 @@ msld_status validate_params(const msld_params* p) {
   if (p->check_every < 1) return MSLD_EINVAL;
   if (p->cycle_spin != 0 && p->cycle_spin != 1) return MSLD_EINVAL;
   if (p->spin_count < 0) return MSLD_EINVAL;
-  if (p->fork_mode < 0 || p->fork_mode > 2) return MSLD_EINVAL;
+  if (p->fork_mode < 0 || p->fork_mode > 3) return MSLD_EINVAL;
   if (p->image_w < 0 || (p->image_w > 0 && p->M % p->image_w)) return MSLD_EINVAL;
   for (int i = 0; i < p->L; ++i) {
     const int m = p->block_m[i], n = p->block_n[i];
@@ -324,7 +327,7 @@ static void destroy_solver(msld_solver* s) {
   (void)hipStreamSynchronize(s->st);
   drop_graphs(s);
   if (s->prof_ev) {
-    for (size_t e = 0; e < (4 + 5 * (size_t)s->p.L) * (size_t)s->prof_cap; ++e)
+    for (size_t e = 0; e < (4 + kEvPerScale * (size_t)s->p.L) * (size_t)s->prof_cap; ++e)
       (void)hipEventDestroy(s->prof_ev[e]);
     std::free(s->prof_ev);
   }
@@ -558,9 +561,10 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
   // are short: planes of up to 2^24 elements (video stand-in +5.7%, batches +3%). At
   // 8192^2 the iteration gained 1.3% but the HBM-bound passes ran 2.4x slower, so large
   // planes keep them uncontended. The caller can force either schedule (fork_mode).
-  s->early_fork = p->fork_mode == 1   ? 1
-                  : p->fork_mode == 2 ? 0
-                                      : (plane_elems(s) <= ((size_t)1 << 24) ? 1 : 0);
+  s->serial = p->fork_mode == 3;
+  s->early_fork = p->fork_mode == 1                        ? 1
+                  : (p->fork_mode == 2 || p->fork_mode == 3) ? 0
+                                                             : (plane_elems(s) <= ((size_t)1 << 24) ? 1 : 0);
   {
     StreamAll& a = s->sall;
     std::memset(&a, 0, sizeof(a));
@@ -623,6 +627,12 @@ static msld_status join_scale(msld_solver* s, int i) {
   return MSLD_OK;
 }
 
+// The stream scale i's BlockSVT runs on inside an iteration: its own, or the handle's
+// stream when the scales run one after another (fork_mode 3).
+static hipStream_t scale_stream(const msld_solver* s, int i) {
+  return s->serial ? s->st : s->sst[i];
+}
+
 static msld_status zero_stats(msld_solver* s) {
   for (int i = 0; i < s->p.L; ++i) {
     MSLD_TRY(s, hipMemsetAsync(s->work[i].stats, 0, 8 * 8, s->st));
@@ -655,7 +665,7 @@ msld_status iterate_once(msld_solver* s, const float* d_Y, int64_t ldY, float* d
     }
   hipEvent_t* ev = nullptr;
   if (s->prof_ev && s->prof_n < s->prof_cap) {
-    ev = s->prof_ev + (size_t)s->prof_n * (4 + 5 * L);
+    ev = s->prof_ev + (size_t)s->prof_n * (4 + kEvPerScale * L);
     ++s->prof_n;
     MSLD_TRY(s, hipEventRecord(ev[0], s->st));
   }
@@ -698,8 +708,10 @@ msld_status iterate_once(msld_solver* s, const float* d_Y, int64_t ldY, float* d
     if (s->early_fork)
       for (int k = 0; k < s->sall.n; ++k)
         if (s->sall.s[k].scale == i) own = true;
-    msld_status fs = fork_scale(s, i, own);
-    if (fs != MSLD_OK) return fs;
+    if (!s->serial) {
+      msld_status fs = fork_scale(s, i, own);
+      if (fs != MSLD_OK) return fs;
+    }
     ShiftSpec& sh = shs[i];
     sh.seed = p.shift_seed;
     sh.k = s->k;
@@ -720,7 +732,8 @@ msld_status iterate_once(msld_solver* s, const float* d_Y, int64_t ldY, float* d
     if (!pl.spin[i]) {
       herr[i] = launch_scale(pl.geom[i], pl.tier[i], pl.sp[i], s->work[i], Zi, R, Zi,
                              Dn + MN * i, pl.tau_default[i], shs[i], jacobi_tol(pl.geom[i].mb),
-                             40, 20, s->num_cus, s->sst[i], ev ? ev + 4 + 5 * i : nullptr,
+                             40, 20, s->num_cus, scale_stream(s, i),
+                             ev ? ev + 4 + kEvPerScale * i : nullptr,
                              &rls[i], true, &deferred[i]);
       return;
     }
@@ -745,14 +758,15 @@ msld_status iterate_once(msld_solver* s, const float* d_Y, int64_t ldY, float* d
       int rl = 0;
       e = launch_scale(pl.geom[i], pl.tier[i], pl.sp[i], s->work[i], Zi, R, out, Dn + MN * i,
                        pl.tau_default[i], sj, jacobi_tol(pl.geom[i].mb), 40, 20, s->num_cus,
-                       s->sst[i], (ev && j == 0) ? ev + 4 + 5 * i : nullptr, &rl, false);
+                       scale_stream(s, i), (ev && j == 0) ? ev + 4 + kEvPerScale * i : nullptr, &rl,
+                       false);
       rls[i] += rl;
       if (e == hipSuccess && j > 0)
-        e = launch_spin_acc(w.spinAcc, w.spinTmp, MN, inst, act, s->sst[i]);
+        e = launch_spin_acc(w.spinAcc, w.spinTmp, MN, inst, act, scale_stream(s, i));
     }
     if (e == hipSuccess)
       e = launch_spin_finish(Zi, Dn + MN * i, R, w.spinAcc, 1.0f / (float)pl.spin[i], MN, inst,
-                             act, s->sst[i]);
+                             act, scale_stream(s, i));
     herr[i] = e;
   };
   for (int oi = 0; oi < no; ++oi) issue(order[oi]);
@@ -760,13 +774,15 @@ msld_status iterate_once(msld_solver* s, const float* d_Y, int64_t ldY, float* d
     const int i = order[oi];
     if (herr[i] != hipSuccess || !deferred[i]) continue;
     herr[i] = finish_fallback(pl.geom[i], s->work[i], d_Z + MN * i, Dn + MN * i,
-                              pl.tau_default[i], shs[i], s->sst[i]);
-    if (herr[i] == hipSuccess && ev) herr[i] = hipEventRecord(ev[4 + 5 * i + 4], s->sst[i]);
+                              pl.tau_default[i], shs[i], scale_stream(s, i));
+    if (herr[i] == hipSuccess && ev)
+      herr[i] = hipEventRecord(ev[4 + kEvPerScale * i + 4], scale_stream(s, i));
   }
   for (int oi = 0; oi < no; ++oi) {
     const int i = order[oi];
     if (herr[i] != hipSuccess) return dev_err(s, herr[i]);
     if (ev) s->round_launches[i] += rls[i];
+    if (s->serial) continue;
     msld_status rs = join_scale(s, i);
     if (rs != MSLD_OK) return rs;
   }
@@ -1003,7 +1019,7 @@ msld_status msld_profile_begin(msld_solver* s, int32_t max_iters) {
   if (!s || max_iters < 1) return MSLD_EINVAL;
   if (s->failed) return MSLD_EDEVICE;
   if (s->prof_ev) return MSLD_EINVAL;
-  const size_t per = 4 + 5 * (size_t)s->p.L;
+  const size_t per = 4 + kEvPerScale * (size_t)s->p.L;
   const size_t n = per * (size_t)max_iters;
   s->prof_ev = static_cast<hipEvent_t*>(std::calloc(n, sizeof(hipEvent_t)));
   if (!s->prof_ev) return MSLD_ENOMEM;
@@ -1025,10 +1041,10 @@ msld_status msld_profile_end(msld_solver* s, double* ms, int64_t* round_launches
   if (!s || !ms || !round_launches || !iters_recorded) return MSLD_EINVAL;
   if (!s->prof_ev) return MSLD_EINVAL;
   const int L = s->p.L;
-  const size_t per = 4 + 5 * (size_t)L;
+  const size_t per = 4 + kEvPerScale * (size_t)L;
   msld_status result = MSLD_OK;
   if (hipStreamSynchronize(s->st) != hipSuccess) result = dev_err(s, hipErrorUnknown);
-  for (int i = 0; i < 4 * (L + 1); ++i) ms[i] = 0.0;
+  for (int i = 0; i < 4 * (L + 1) + L; ++i) ms[i] = 0.0;
   for (int it = 0; it < s->prof_n && result == MSLD_OK; ++it) {
     hipEvent_t* ev = s->prof_ev + (size_t)it * per;
     float t;
@@ -1036,9 +1052,12 @@ msld_status msld_profile_end(msld_solver* s, double* ms, int64_t* round_launches
     if (s->sall.n > 0 && hipEventElapsedTime(&t, ev[2], ev[3]) == hipSuccess) ms[4 * L + 1] += t;
     for (int i = 0; i < L; ++i) {
       if (s->plan.tier[i] == TIER_1X1) continue;
-      hipEvent_t* e5 = ev + 4 + 5 * i;
+      hipEvent_t* e5 = ev + 4 + kEvPerScale * i;
       for (int j = 0; j < 4; ++j)
         if (hipEventElapsedTime(&t, e5[j], e5[j + 1]) == hipSuccess) ms[4 * i + j] += t;
+      // the Gram kernel of a low-rank tier (events 5 and 6; never recorded otherwise)
+      if (s->work[i].use_lr && hipEventElapsedTime(&t, e5[5], e5[6]) == hipSuccess)
+        ms[4 * (L + 1) + i] += t;
     }
   }
   for (int i = 0; i < L; ++i) round_launches[i] = s->round_launches[i];

@@ -1454,7 +1454,8 @@ hipError_t launch_scale(const ScaleGeom& g, int tier, const StreamPlan& sp, Scal
   if (w.use_lr) {
     // certified low-rank path: every launch walks the live count on the device
     MSLD_EV(2);
-    if ((e = run_lowrank(g, w, Zout, Dout, tau, sh, st)) != hipSuccess) return e;
+    if ((e = run_lowrank(g, w, Zout, Dout, tau, sh, st, ev ? ev + 5 : nullptr)) != hipSuccess)
+      return e;
     MSLD_EV(3);
     if (w.lds_fallback) {
       // blocks that failed the certificate and fit in LDS: one-sided Jacobi LDS tier

@@ -266,6 +266,35 @@ __device__ __forceinline__ void lr_pair(int round, int k, int ncols, int* a, int
   *b = 1 + (ncols - 2 - k + round) % n1;
 }
 
+// Jacobi rotation annihilating the (p, q) entry of a symmetric matrix with diagonal
+// entries app, aqq: columns p' = c p - s q, q' = s p + c q. The angle only has to be
+// close to the annihilating one (the next sweep removes what is left), so tan is formed
+// with the hardware's approximate reciprocal and reciprocal square root; c = 1 /
+// sqrt(1 + t^2) then gets two Newton steps, so that c^2 + s^2 = 1 to float64 accuracy and
+// every rotation stays orthogonal. False (c = 1, s = 0) when |apq| <= 1e-14 sqrt(app aqq).
+__device__ __forceinline__ bool jacobi_rot64(double app, double aqq, double apq, double* c,
+                                             double* s) {
+  *c = 1.0;
+  *s = 0.0;
+  if (!(apq * apq > 1e-28 * fabs(app * aqq)) || apq == 0.0) return false;
+  const double th = (aqq - app) * __builtin_amdgcn_rcp(2.0 * apq);
+  double t;
+  if (fabs(th) > 1e150) {
+    t = 0.5 * __builtin_amdgcn_rcp(th);
+  } else {
+    const double h = th * th + 1.0;
+    const double den = fabs(th) + h * __builtin_amdgcn_rsq(h);
+    t = copysign(__builtin_amdgcn_rcp(den), th);
+  }
+  const double x = t * t + 1.0;
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * (1.5 - 0.5 * x * y * y);
+  y = y * (1.5 - 0.5 * x * y * y);
+  *c = y;
+  *s = t * y;
+  return true;
+}
+
 // SVD of the reduced block B X from the Gram matrix alone. With W0 = G X (nb x P),
 // K = X^T W0 = (B X)^T (B X) is the Gram of the reduced block (float64, symmetrised);
 // its eigen-decomposition K = W diag(lambda) W^T by cyclic two-sided Jacobi in float64
@@ -273,15 +302,20 @@ __device__ __forceinline__ void lr_pair(int round, int k, int ncols, int* a, int
 // V_r = X W (nb x P) and, since G is symmetric, T^T = G V_r = W0 W, the coupling
 // product A_f^T B with A_f = B V_r (T stored row-major, T[c P + l]). A_f itself is
 // formed later, only for the blocks whose rebuild or fallback needs it.
+// A Jacobi round: thread (u, w) of the first wave owns the 2 x 2 sub-block of K at
+// the rows of pair u and the columns of pair w; it forms both pairs' rotations from
+// the current K (every thread that needs a rotation computes it from the same
+// entries, so all copies agree bit for bit), writes its sub-block of J_u^T K J_w to the
+// other buffer and applies J_w to its sub-block of W; one barrier per round.
 template <int P>
 __global__ void __launch_bounds__(256) k_lr_reduced(const float* X, const float* W0, int nb,
                                                     float* Vr, float* Tt, float* sig,
                                                     const int* count) {
   static_assert(P * P == 256, "one Gram entry per thread");
+  static_assert((P / 2) * (P / 2) <= 64, "one wave of sub-blocks");
   __shared__ float ys[kRC][P + 1], zs[kRC][P + 1];
-  __shared__ double K[P][P + 1];
+  __shared__ double Kb[2][P][P + 1];
   __shared__ double V[P][P + 1];
-  __shared__ double cs[P / 2], sn[P / 2];
   __shared__ int s_rot;
   const int tid = threadIdx.x;
   const int cnt = *count;
@@ -289,65 +323,52 @@ __global__ void __launch_bounds__(256) k_lr_reduced(const float* X, const float*
     const float* x = X + (int64_t)slot * nb * P;
     const float* w0 = W0 + (int64_t)slot * nb * P;
     const double kv = gram64_pp<P>(x, w0, nb, ys, zs);
-    K[tid / P][tid % P] = kv;
+    Kb[1][tid / P][tid % P] = kv;
     __syncthreads();
     {
       const int a = tid / P, b = tid % P;
-      const double sym = 0.5 * (K[a][b] + K[b][a]);
-      __syncthreads();
-      K[a][b] = sym;
+      Kb[0][a][b] = 0.5 * (Kb[1][a][b] + Kb[1][b][a]);
       V[a][b] = a == b ? 1.0 : 0.0;
     }
-    __syncthreads();
+    int cur = 0;
     for (int sw = 0; sw < 40; ++sw) {
       if (tid == 0) s_rot = 0;
       __syncthreads();
       for (int rd = 0; rd < P - 1; ++rd) {
-        if (tid < P / 2) {
-          int p, q;
-          lr_pair(rd, tid, P, &p, &q);
-          const double app = K[p][p], aqq = K[q][q], apq = K[p][q];
-          double c = 1.0, s = 0.0;
-          if (apq != 0.0 && fabs(apq) > 1e-14 * sqrt(fabs(app) * fabs(aqq))) {
-            const double th = (aqq - app) / (2.0 * apq);
-            const double t = fabs(th) > 1e150 ? 0.5 / th
-                                              : copysign(1.0, th) / (fabs(th) + sqrt(th * th + 1.0));
-            c = 1.0 / sqrt(t * t + 1.0);
-            s = t * c;
-            s_rot = 1;
-          }
-          cs[tid] = c;
-          sn[tid] = s;
+        if (tid < (P / 2) * (P / 2)) {
+          const int u = tid / (P / 2), w = tid - (tid / (P / 2)) * (P / 2);
+          int pu, qu, pw, qw;
+          lr_pair(rd, u, P, &pu, &qu);
+          lr_pair(rd, w, P, &pw, &qw);
+          double (*K)[P + 1] = Kb[cur];
+          double cu, su, cw, sw2;
+          const bool ru = jacobi_rot64(K[pu][pu], K[qu][qu], K[pu][qu], &cu, &su);
+          jacobi_rot64(K[pw][pw], K[qw][qw], K[pw][qw], &cw, &sw2);
+          if (u == w && ru) s_rot = 1;
+          const double k00 = K[pu][pw], k01 = K[pu][qw], k10 = K[qu][pw], k11 = K[qu][qw];
+          // K J_w on rows pu, qu, then J_u^T on the left
+          const double t00 = cw * k00 - sw2 * k01, t01 = sw2 * k00 + cw * k01;
+          const double t10 = cw * k10 - sw2 * k11, t11 = sw2 * k10 + cw * k11;
+          double (*Kn)[P + 1] = Kb[cur ^ 1];
+          Kn[pu][pw] = cu * t00 - su * t10;
+          Kn[pu][qw] = cu * t01 - su * t11;
+          Kn[qu][pw] = su * t00 + cu * t10;
+          Kn[qu][qw] = su * t01 + cu * t11;
+          // W J_w on rows pu, qu (the rows of pair u cover every row once)
+          const double v00 = V[pu][pw], v01 = V[pu][qw], v10 = V[qu][pw], v11 = V[qu][qw];
+          V[pu][pw] = cw * v00 - sw2 * v01;
+          V[pu][qw] = sw2 * v00 + cw * v01;
+          V[qu][pw] = cw * v10 - sw2 * v11;
+          V[qu][qw] = sw2 * v10 + cw * v11;
         }
-        __syncthreads();
-        if (tid < (P / 2) * P) {   // K <- K J and V <- V J (columns p, q of every pair)
-          const int k = tid / P, r = tid - (tid / P) * P;
-          int p, q;
-          lr_pair(rd, k, P, &p, &q);
-          const double c = cs[k], s = sn[k];
-          const double kp = K[r][p], kq = K[r][q];
-          K[r][p] = c * kp - s * kq;
-          K[r][q] = s * kp + c * kq;
-          const double vp = V[r][p], vq = V[r][q];
-          V[r][p] = c * vp - s * vq;
-          V[r][q] = s * vp + c * vq;
-        }
-        __syncthreads();
-        if (tid < (P / 2) * P) {   // K <- J^T K (rows p, q)
-          const int k = tid / P, col = tid - (tid / P) * P;
-          int p, q;
-          lr_pair(rd, k, P, &p, &q);
-          const double c = cs[k], s = sn[k];
-          const double kp = K[p][col], kq = K[q][col];
-          K[p][col] = c * kp - s * kq;
-          K[q][col] = s * kp + c * kq;
-        }
+        cur ^= 1;
         __syncthreads();
       }
       const int rot = s_rot;
       __syncthreads();
       if (!rot) break;
     }
+    double (*K)[P + 1] = Kb[cur];
     if (tid < P) sig[slot * P + tid] = (float)sqrt(fmax(K[tid][tid], 0.0));
     float* vr = Vr + (int64_t)slot * nb * P;
     float* tt = Tt + (int64_t)slot * nb * P;
@@ -783,7 +804,7 @@ static int slot_grid(int slots, int per_cu_target = 4096) {
 }
 
 hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout, float tau,
-                       const ShiftSpec& sh, hipStream_t st) {
+                       const ShiftSpec& sh, hipStream_t st, hipEvent_t* gram_ev) {
   constexpr int P = 16;
   hipError_t e;
   const int mb = g.mb, nb = g.nb, S = w.slots;
@@ -798,8 +819,10 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
   hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, cnt, 5);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // G = B^T B, gathered straight from the iterate (matrix cores)
+  if (gram_ev && (e = hipEventRecord(gram_ev[0], st)) != hipSuccess) return e;
   if ((e = launch_mf_gram(g, sh, Dout, live, list, S, w.lrG, w.lrSplit, st)) != hipSuccess)
     return e;
+  if (gram_ev && (e = hipEventRecord(gram_ev[1], st)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_lr_trace, dim3(slot_grid(S)), dim3(256), 0, st, w.lrG, nb, sG, w.lrScal,
                      0, live);
   if ((e = hipGetLastError()) != hipSuccess) return e;

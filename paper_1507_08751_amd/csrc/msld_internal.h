@@ -296,7 +296,7 @@ hipError_t run_polar(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout,
 // Certified low-rank BlockSVT of the live blocks (count on the device); failed
 // certificates are listed for the exact fallback (w.lrCount[0], w.lrFall).
 hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout, float tau,
-                       const ShiftSpec& sh, hipStream_t st);
+                       const ShiftSpec& sh, hipStream_t st, hipEvent_t* gram_ev = nullptr);
 __global__ void k_zero_ints(int* p, int n);
 __global__ void k_copy_count(const int* src, int* dst);
 // Per-instance sums (instance z = rows [z IM, (z+1) IM)): out[z].

@@ -93,6 +93,7 @@ struct msld_solver {
   hipEvent_t ev_join[MSLD_MAX_SCALES];
   hipEvent_t ev_sfork[MSLD_MAX_SCALES];   // after scale i's stream pass (its own fork point)
   int early_fork;   // scales fork after their own stream pass (planes <= 2^24 elements)
+  int serial;       // every scale's BlockSVT on the handle's stream, one after another
   msld::ScaleWork work[MSLD_MAX_SCALES];
   msld::StreamAll sall;   // the stream pass of all decomposed scales (one launch)
   const uint8_t* mask;    // observed-entry mask (caller-owned, device) or null
