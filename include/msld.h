@@ -391,6 +391,11 @@ msld_status msld_server_step(msld_server *sv, int64_t *done_ids, int32_t *done_i
                              double *done_resid, int32_t *done_status, int32_t max_out,
                              int32_t *n_done, int32_t *n_active, int32_t *n_queued);
 
+/* HBM bytes a server with this max_active charges against its budget for the class
+ * of problem p (workspace plus stacked Y and Z planes of min(max_active, 8) slots),
+ * as used by admission. Host only. MSLD_EINVAL if p is invalid. */
+msld_status msld_server_class_bytes(const msld_params *p, int32_t max_active, size_t *out);
+
 /* Free the server, its streams and the workspace of requests still active. NULL-safe. */
 void msld_server_free(msld_server *sv);
 

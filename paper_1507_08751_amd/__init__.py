@@ -126,6 +126,8 @@ EXPORTS = {
                                         ctypes.POINTER(ctypes.c_int32),
                                         ctypes.POINTER(ctypes.c_int32)]),
     "msld_server_free": (None, [ctypes.c_void_p]),
+    "msld_server_class_bytes": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int32,
+                                               ctypes.POINTER(ctypes.c_size_t)]),
     "msld_profile_begin": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "msld_profile_end": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_int64),
@@ -498,6 +500,18 @@ class Server:
             out.append((rid, int(self._its[k]), float(self._res[k]), int(self._sts[k]), Z))
         self.active, self.queued = na.value, nq.value
         return out
+
+    @staticmethod
+    def class_bytes(M, N, ladder, max_active, lam=None, rho=1.0, iters=300, tol=1e-4,
+                    check_every=1, cycle_spin=False, seed=0, lowrank_min=0):
+        """HBM bytes a server with this max_active charges its budget for the class of
+        an M x N problem with this ladder (msld_server_class_bytes)."""
+        p = make_params(M, N, ladder, lam, rho, iters, tol, check_every, cycle_spin, seed,
+                        lowrank_min)
+        out = ctypes.c_size_t()
+        _check(load().msld_server_class_bytes(ctypes.byref(p), int(max_active),
+                                              ctypes.byref(out)), "msld_server_class_bytes")
+        return int(out.value)
 
     def close(self):
         if getattr(self, "_h", None):

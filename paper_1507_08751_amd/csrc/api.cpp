@@ -276,11 +276,10 @@ msld_status make_plan(const msld_params* p, int ninst, Plan* pl) {
         const size_t per = 3 * nb2 + 4 * (size_t)g.nb * kLRP + (size_t)g.mb * kLRP +
                            (size_t)kLRP * g.nb + 3 * kLRP + 8 + (size_t)g.nb * (tn + 1);
         pl->off_lr[i] = take(4 * ((size_t)nblk * per + (size_t)g.nb * kLRP + 64 + 5 * nblk));
-        // split partials of tall blocks and the float64 Gram partials of the reduced
-        // block, both sized by the block shape and the slot count
+        // split partials of the Gram matrix of tall or wide blocks, sized by the block
+        // shape and the slot count
         const int ch = split_chunks(g.mb, g.nb);
         if (ch > 1) pl->off_split[i] = take(4 * (size_t)nblk * ch * nb2);
-        pl->off_part64[i] = take(8 * (size_t)nblk * ((g.mb + 511) / 512) * 256);
         if (!lds_fits(g.mb, g.nb)) {
           // polar fallback buffers for a chunk of failed certificates (<= 256 MiB)
           const size_t pper = 3 * (size_t)g.mb * g.nb + 4 * nb2 + 4;
@@ -529,8 +528,6 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
         w.lrSplit = pl.off_split[i] ? reinterpret_cast<float*>(s->arena + pl.off_split[i])
                                     : nullptr;
         w.lrChunks = w.lrSplit ? split_chunks(g.mb, g.nb) : 1;
-        w.lrPart64 = reinterpret_cast<double*>(s->arena + pl.off_part64[i]);
-        w.lrChunks64 = (g.mb + 511) / 512;
         w.lrCount = reinterpret_cast<int*>(f);
         w.lrFall = w.lrCount + 64;
         w.lds_fallback = lds_fits(g.mb, g.nb) ? 1 : 0;
@@ -599,7 +596,7 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
   return MSLD_OK;
 }
 
-static float jacobi_tol(int mb) { return 4.0f * 5.9604645e-8f * std::sqrt((float)mb); }
+static float jacobi_tol(int mb) { return jacobi_tolerance(mb); }
 
 // Scale i's BlockSVT on its own stream; the caller forks it from s->st (after the
 // consensus) and joins it back.

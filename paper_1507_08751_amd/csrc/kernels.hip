@@ -342,12 +342,8 @@ __global__ void __launch_bounds__(256) k_tiny_live(
           }
           if (jacobi_rotates(ga, al, be, jtol)) {
             rot = true;
-            const float zeta = (be - al) / (2.f * ga);
-            const float t = (fabsf(zeta) > 1e18f)
-                                ? 0.5f / zeta
-                                : copysignf(1.f, zeta) / (fabsf(zeta) + sqrtf(1.f + zeta * zeta));
-            const float c = 1.f / sqrtf(1.f + t * t);
-            const float s = c * t;
+            float c, s;
+            jacobi_cs(ga, al, be, &c, &s);
 #pragma unroll
             for (int i = 0; i < LM; ++i) {
               const float x = a[i][pp], y = a[i][qq];
@@ -757,12 +753,8 @@ __device__ int jacobi_sweeps(float* A, int lda, int arows, float* W, int ldw, in
       }
       if (act && jacobi_rotates(ga, al, be, tol)) {
         rotated = 1;
-        const float zeta = (be - al) / (2.f * ga);
-        const float tt = (fabsf(zeta) > 1e18f)
-                             ? 0.5f / zeta
-                             : copysignf(1.f, zeta) / (fabsf(zeta) + sqrtf(1.f + zeta * zeta));
-        const float c = 1.f / sqrtf(1.f + tt * tt);
-        const float s = c * tt;
+        float c, s;
+        jacobi_cs(ga, al, be, &c, &s);
         float* ap = A + pa * lda;
         float* aq = A + pb * lda;
         float* wp = W + pa * ldw;
@@ -842,14 +834,25 @@ __global__ void __launch_bounds__(1024) k_svd_lds(
     const int q = blk - p * Q;
     int sr, sc;
     block_shift(sh, p / g.PI, m, n, &sr, &sc);
-    // gather V = -D' (written by the stream pass) into logical column-major B
-    for (int e = tid; valid && e < m * n; e += nt) {
-      const int i = e / n;
-      const int j = e - i * n;
-      const int64_t o = (int64_t)grow(g, p, i, sr) * N + gcol(g, q, j, sc);
-      const float v = -Dout[o];
-      if (!trans) A[j * lda + i] = v;
-      else A[i * lda + j] = v;
+    // gather V = -D' (written by the stream pass) into logical column-major B, four
+    // loads in flight per lane
+    const int tot = valid ? m * n : 0;
+    for (int e0 = tid; e0 < tot; e0 += 4 * nt) {
+      float v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + u * nt;
+        const int i = e / n, j = e - (e / n) * n;
+        v[u] = e < tot ? -Dout[(int64_t)grow(g, p, i, sr) * N + gcol(g, q, j, sc)] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + u * nt;
+        if (e >= tot) break;
+        const int i = e / n, j = e - (e / n) * n;
+        if (!trans) A[j * lda + i] = v[u];
+        else A[i * lda + j] = v[u];
+      }
     }
     if (valid && nbp > nb)
       for (int r = tid; r < mb; r += nt) A[nb * lda + r] = 0.f;
@@ -883,20 +886,32 @@ __global__ void __launch_bounds__(1024) k_svd_lds(
     const int k = valid ? s_k[sb] : 0;
     // rebuild B' = sum_j g_j (B w_j) w_j^T and scatter to the wrapped coordinates
     // (rank 0: the stream pass already wrote Z' = 0, D' = -V)
-    for (int e = tid; k > 0 && e < m * n; e += nt) {
-      const int i = e / n;
-      const int j = e - i * n;
-      const int r = trans ? j : i;
-      const int c = trans ? i : j;
-      float z = 0.f;
-      for (int t = 0; t < k; ++t) {
-        const int l = lcols[t];
-        z += gain[l] * A[l * lda + r] * W[l * ldw + c];
+    const int totr = k > 0 ? m * n : 0;
+    for (int e0 = tid; e0 < totr; e0 += 4 * nt) {
+      int64_t o[4];
+      float v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + u * nt;
+        const int i = e / n, j = e - (e / n) * n;
+        o[u] = e < totr ? (int64_t)grow(g, p, i, sr) * N + gcol(g, q, j, sc) : 0;
+        v[u] = e < totr ? -Dout[o[u]] : 0.f;
       }
-      const int64_t o = (int64_t)grow(g, p, i, sr) * N + gcol(g, q, j, sc);
-      const float v = -Dout[o];
-      Zout[o] = z;
-      Dout[o] = 2.f * z - v;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + u * nt;
+        if (e >= totr) break;
+        const int i = e / n, j = e - (e / n) * n;
+        const int r = trans ? j : i;
+        const int c = trans ? i : j;
+        float z = 0.f;
+        for (int t = 0; t < k; ++t) {
+          const int l = lcols[t];
+          z += gain[l] * A[l * lda + r] * W[l * ldw + c];
+        }
+        Zout[o[u]] = z;
+        Dout[o[u]] = 2.f * z - v[u];
+      }
     }
     __syncthreads();
   }

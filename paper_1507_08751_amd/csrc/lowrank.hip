@@ -102,79 +102,148 @@ __device__ __forceinline__ double gram64_pp(const float* y, const float* z, int 
   return acc;
 }
 
-// Orthonormalise the p columns of Y (nb x p, column-major) into X by classical
-// Gram-Schmidt with re-orthogonalisation until a pass keeps at least half the norm
-// (at most 4 passes); a column that stays numerically dependent is set to zero.
-template <int P>
-__global__ void __launch_bounds__(256) k_lr_orth(const float* Y, float* X, int nb,
-                                                 int64_t stride, const int* count) {
-  extern __shared__ float sy[];  // P x nb
-  __shared__ float red[4 * P];
-  __shared__ float coef[P];
-  const int cnt = *count;
-  for (int slot = blockIdx.x; slot < cnt; slot += gridDim.x) {
-  const float* y = Y + (int64_t)slot * stride;
-  float* x = X + (int64_t)slot * stride;
+// Float64 Gram K[a][b] = sum_r y[a nb + r] z[b nb + r] of two nb x P column-major panels
+// by NT threads (NT / P^2 interleaved row groups per entry): rows are staged through
+// LDS in chunks of kBC while the next chunk's loads are in flight (one load latency per
+// panel rather than per chunk); rows past nb are zero. Thread e < P^2 returns entry
+// (e / P, e % P), summed over the row groups in a fixed order; the others return 0.
+// With y == z only ys is used (zs may alias it) and K[a][b], K[b][a] come out equal.
+constexpr int kBC = 512;
+template <int P, int NT>
+__device__ double gram64_stream(const float* y, const float* z, int nb, float (*ys)[P + 1],
+                                float (*zs)[P + 1], double* red) {
+  constexpr int E = P * P, RG = NT / E, PER = kBC * P / NT;
+  static_assert(NT % E == 0 && (kBC * P) % NT == 0, "thread layout");
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wv = tid >> 6;
-  __syncthreads();
-  for (int e = tid; e < nb * P; e += blockDim.x) sy[e] = y[e];
-  __syncthreads();
-  for (int j = 0; j < P; ++j) {
-    float* yj = sy + j * nb;
-    // original norm
-    float n0 = 0.f;
-    for (int r = tid; r < nb; r += blockDim.x) n0 += yj[r] * yj[r];
-    n0 = block_sum(n0, red);
-    float nprev = n0;
-    bool dependent = true;
-    for (int pass = 0; pass < 4 && j > 0; ++pass) {
-      float part[P];
+  const int e = tid % E, rg = tid / E;
+  const int a = e / P, b = e - (e / P) * P;
+  const bool same = y == z;
+  float py[PER], pz[PER];
+  auto load = [&](int r0) {
 #pragma unroll
-      for (int i = 0; i < P; ++i) part[i] = 0.f;
-      for (int r = tid; r < nb; r += blockDim.x) {
-        const float v = yj[r];
-#pragma unroll
-        for (int i = 0; i < P; ++i)
-          if (i < j) part[i] += sy[i * nb + r] * v;
-      }
-#pragma unroll
-      for (int i = 0; i < P; ++i) {
-        float v = part[i];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-        part[i] = v;
-      }
-      __syncthreads();
-      if (lane == 0)
-        for (int i = 0; i < j; ++i) red[wv * P + i] = part[i];
-      __syncthreads();
-      if (tid < j) coef[tid] = red[tid] + red[P + tid] + red[2 * P + tid] + red[3 * P + tid];
-      __syncthreads();
-      for (int r = tid; r < nb; r += blockDim.x) {
-        float v = yj[r];
-        for (int i = 0; i < j; ++i) v -= coef[i] * sy[i * nb + r];
-        yj[r] = v;
-      }
-      __syncthreads();
-      float nn = 0.f;
-      for (int r = tid; r < nb; r += blockDim.x) nn += yj[r] * yj[r];
-      nn = block_sum(nn, red);
-      if (nn >= 0.25f * nprev) {   // norm kept above 1/2: orthogonal to working precision
-        dependent = false;
-        nprev = nn;
-        break;
-      }
-      nprev = nn;
+    for (int u = 0; u < PER; ++u) {
+      const int idx = tid + NT * u;
+      const int l = idx / kBC, r = idx - (idx / kBC) * kBC;
+      const bool in = r0 + r < nb;
+      py[u] = in ? y[(int64_t)l * nb + r0 + r] : 0.f;
+      pz[u] = (in && !same) ? z[(int64_t)l * nb + r0 + r] : 0.f;
     }
-    if (j == 0) dependent = false;
-    const float nrm = sqrtf(nprev);
-    const bool keep = !dependent && nrm > 1e-30f && nprev > 1e-12f * n0;
-    const float inv = keep ? 1.f / nrm : 0.f;
-    for (int r = tid; r < nb; r += blockDim.x) yj[r] = yj[r] * inv;
+  };
+  double acc = 0.0;
+  __syncthreads();   // earlier writes of the panels by this workgroup are visible
+  load(0);
+  for (int r0 = 0; r0 < nb; r0 += kBC) {
+    __syncthreads();   // the previous chunk (and any earlier use of ys, zs) is read
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int idx = tid + NT * u;
+      const int l = idx / kBC, r = idx - (idx / kBC) * kBC;
+      ys[r][l] = py[u];
+      if (!same) zs[r][l] = pz[u];
+    }
     __syncthreads();
+    if (r0 + kBC < nb) load(r0 + kBC);
+    const float (*zz)[P + 1] = same ? ys : zs;
+#pragma unroll 8
+    for (int r = rg; r < kBC; r += RG) acc += (double)ys[r][a] * (double)zz[r][b];
   }
-  for (int e = tid; e < nb * P; e += blockDim.x) x[e] = sy[e];
+  red[tid] = acc;
+  __syncthreads();
+  double k = 0.0;
+  if (tid < E)
+    for (int g2 = 0; g2 < RG; ++g2) k += red[g2 * E + tid];
+  __syncthreads();
+  return k;
+}
+
+// Orthonormalisation of large panels (nb > 512, one workgroup of 1024 threads per slot)
+// by Cholesky QR applied twice: the float64 Gram S = Z^T Z of the panel, its Cholesky
+// factor R, then Z <- Z R^-1 in float64 per row. A column whose remaining squared norm
+// is at most 1e-12 of its own (numerically dependent on the earlier ones) gets a zero
+// output column and no part in the later ones. The second pass removes what rounding
+// left of the first pass's departure from orthonormality.
+template <int P>
+__global__ void __launch_bounds__(1024) k_lr_orth_cq(const float* Y, float* X, int nb,
+                                                     int64_t stride, const int* count) {
+  constexpr int NT = 1024;
+  static_assert(P * P == 256, "the Gram entries fill a quarter of the workgroup");
+  __shared__ float zs[kBC][P + 1];
+  __shared__ double red[NT];
+  __shared__ double S[P][P + 1];
+  __shared__ double T[P][P + 1];
+  const int cnt = *count;
+  const int tid = threadIdx.x;
+  for (int slot = blockIdx.x; slot < cnt; slot += gridDim.x) {
+    const float* y = Y + (int64_t)slot * stride;
+    float* x = X + (int64_t)slot * stride;
+    for (int pass = 0; pass < 2; ++pass) {
+      const float* z = pass == 0 ? y : x;
+      // (its first barrier orders the previous pass's writes of x before the reads)
+      const double kv = gram64_stream<P, NT>(z, z, nb, zs, zs, red);
+      if (tid < P * P) S[tid / P][tid % P] = kv;
+      __syncthreads();
+      if (tid < 64) {
+        // Cholesky by wave 0 in LDS (right-looking: R's row j overwrites S's, then the
+        // trailing upper triangle is updated, one entry per lane and step), then lane k
+        // (< P) solves R t = e_k for column k of T = R^-1, bottom up. Wave-level fences
+        // order each step's LDS writes before the next step's reads.
+        const int lane = tid;
+        double d0 = 0.0;
+        if (lane < P) d0 = S[lane][lane];
+        unsigned dep = 0;
+        for (int j = 0; j < P; ++j) {
+          const double d = S[j][j];
+          const double s0 = __shfl(d0, j);
+          const bool dj = !(s0 > 0.0) || !(d > 1e-12 * s0);
+          if (dj) dep |= 1u << j;
+          const double rjj = dj ? 1.0 : sqrt(d);
+          __builtin_amdgcn_wave_barrier();
+          if (lane == j) S[j][j] = rjj;
+          if (lane > j && lane < P) S[j][lane] = dj ? 0.0 : S[j][lane] / rjj;
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          // trailing entries (i, k), j < i <= k < P, enumerated row by row
+          const int w = P - 1 - j;
+          for (int e = lane; e < w * (w + 1) / 2; e += 64) {
+            int i = 0, rem = e;
+            while (rem >= w - i) {
+              rem -= w - i;
+              ++i;
+            }
+            const int ii = j + 1 + i, kk = ii + rem;
+            S[ii][kk] -= S[j][ii] * S[j][kk];
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        if (lane < P) {
+          const int k = lane;
+          const bool dk = (dep >> k) & 1u;
+          for (int i = P - 1; i > k; --i) T[i][k] = 0.0;
+          T[k][k] = dk ? 0.0 : 1.0 / S[k][k];
+          for (int i = k - 1; i >= 0; --i) {
+            double v = 0.0;
+            for (int m = i + 1; m <= k; ++m) v += S[i][m] * T[m][k];
+            T[i][k] = dk ? 0.0 : -v / S[i][i];
+          }
+        }
+      }
+      __syncthreads();
+      for (int r = tid; r < nb; r += NT) {
+        float zv[P];
+#pragma unroll
+        for (int j = 0; j < P; ++j) zv[j] = z[(int64_t)j * nb + r];
+#pragma unroll 1
+        for (int l = 0; l < P; ++l) {
+          double o = 0.0;
+#pragma unroll
+          for (int j = 0; j < P; ++j) o += (double)zv[j] * T[j][l];
+          x[(int64_t)l * nb + r] = (float)o;
+        }
+      }
+    }
   }
 }
 
@@ -603,20 +672,37 @@ __global__ void __launch_bounds__(256) k_lr_cwmax(const float* rowpart, int nb, 
 
 // Reduce the per-tile partials of E^T E in a fixed order: scal[2] = tr(E^T E),
 // scal[4] = ||E^T E||_F / tr(E^T E) (stage-0 bound factor).
-__global__ void k_lr_ge_reduce(const float* part, int tiles, float* scal, const int* list,
-                               const int* lcount) {
-  const int cnt = *lcount;
-  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < cnt;
-       idx += gridDim.x * blockDim.x) {
-  const int slot = list[idx];
-  float tr = 0.f, f2 = 0.f;
-  for (int t = 0; t < tiles; ++t) {
-    tr += part[((int64_t)slot * tiles + t) * 2];
-    f2 += part[((int64_t)slot * tiles + t) * 2 + 1];
+// One workgroup per listed slot: thread t sums tiles t, t + 256, ... in order, then a
+// fixed tree over the threads.
+__device__ __forceinline__ float tree_sum256(float v, float* red) {
+  __syncthreads();
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
   }
-  scal[slot * 8 + 2] = tr;
-  scal[slot * 8 + 4] = tr > 0.f ? sqrtf(f2) / tr : 0.f;
-  scal[slot * 8 + 3] = scal[slot * 8 + 4];   // the Frobenius factor alone (statistics)
+  return red[0];
+}
+
+__global__ void __launch_bounds__(256) k_lr_ge_reduce(const float* part, int tiles, float* scal,
+                                                      const int* list, const int* lcount) {
+  __shared__ float red[256];
+  const int cnt = *lcount;
+  for (int idx = blockIdx.x; idx < cnt; idx += gridDim.x) {
+    const int slot = list[idx];
+    float tr = 0.f, f2 = 0.f;
+    for (int t = threadIdx.x; t < tiles; t += 256) {
+      tr += part[((int64_t)slot * tiles + t) * 2];
+      f2 += part[((int64_t)slot * tiles + t) * 2 + 1];
+    }
+    tr = tree_sum256(tr, red);
+    f2 = tree_sum256(f2, red);
+    if (threadIdx.x == 0) {
+      scal[slot * 8 + 2] = tr;
+      scal[slot * 8 + 4] = tr > 0.f ? sqrtf(f2) / tr : 0.f;
+      scal[slot * 8 + 3] = scal[slot * 8 + 4];   // the Frobenius factor alone (statistics)
+    }
   }
 }
 
@@ -655,14 +741,17 @@ __global__ void __launch_bounds__(256) k_lr_frob_part(const float* Pm, int nb, f
   }
 }
 
-// Compact entry c belongs to slot list[c].
-__global__ void k_lr_frob_reduce(const float* part, int tiles, const int* lcount,
-                                 const int* list, float* scal, int which) {
+// Compact entry c belongs to slot list[c]; one workgroup per entry (fixed order).
+__global__ void __launch_bounds__(256) k_lr_frob_reduce(const float* part, int tiles,
+                                                        const int* lcount, const int* list,
+                                                        float* scal, int which) {
+  __shared__ float red[256];
   const int cnt = *lcount;
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < cnt; c += gridDim.x * blockDim.x) {
+  for (int c = blockIdx.x; c < cnt; c += gridDim.x) {
     float f2 = 0.f;
-    for (int t = 0; t < tiles; ++t) f2 += part[(int64_t)c * tiles + t];
-    scal[list[c] * 8 + which] = sqrtf(f2);
+    for (int t = threadIdx.x; t < tiles; t += 256) f2 += part[(int64_t)c * tiles + t];
+    f2 = tree_sum256(f2, red);
+    if (threadIdx.x == 0) scal[list[c] * 8 + which] = sqrtf(f2);
   }
 }
 
@@ -835,14 +924,14 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
     else if (nb <= 512)
       hipLaunchKernelGGL((k_lr_orth_w<P, 8>), dim3(gw), dim3(256), 0, st, Yin, Xout, nb, sY, live);
     else
-      hipLaunchKernelGGL(k_lr_orth<P>, dim3(slot_grid(S)), dim3(256), (size_t)4 * nb * P, st, Yin,
-                         Xout, nb, sY, live);
+      hipLaunchKernelGGL(k_lr_orth_cq<P>, dim3(slot_grid(S)), dim3(1024), 0, st, Yin, Xout, nb,
+                         sY, live);
     return hipGetLastError();
   };
   // G X for the slots of a list (or all live slots): barrier-free when nb % 16 == 0
   const bool symx = nb % 16 == 0;
   auto gxl = [&](const float* X, int64_t sX, float* Y, const int* dcount, const int* sl) {
-    if (symx) return launch_sym_x(w.lrG, sG, nb, X, sX, nb, Y, sY, dcount, S, sl, st);
+    if (symx) return launch_sym_x(w.lrG, sG, nb, X, sX, nb, Y, sY, dcount, S, sl, w.lrSplit, st);
     return launch_sk(SK_DENSE, false, w.lrG, sG, nb, nullptr, g, sh, list, X, sX, nb, nb, Y, sY,
                      dcount, 0, S, sl, nullptr, 1, st);
   };
@@ -881,7 +970,10 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int* flist = w.lrFall + 3 * S;
   const int* fcount = cnt + 2;
-  const int tiles = (int)((sG + 255) / 256 < 64 ? (sG + 255) / 256 : 64);
+  // workgroups per slot of the elementwise passes over E^T E (at most 1024, and the frob
+  // partials of one slot must fit in its nb x P part of lrY)
+  const int tiles = (int)std::min<int64_t>(std::min<int64_t>((sG + 255) / 256, 1024),
+                                           (int64_t)nb * P);
   const int gtiles = ((nb + 63) / 64) * ((nb + 63) / 64);
   {
     // E^T E and its bounds: with W = G V_r (the coupling product, lrT), Q = W - V H / 2
@@ -893,8 +985,8 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
         hipSuccess)
       return e;
     // stage 0: Frobenius and Collatz-Wielandt bounds of E^T E
-    hipLaunchKernelGGL(k_lr_ge_reduce, dim3(dgrid), dim3(256), 0, st, w.lrQ, gtiles, w.lrScal,
-                       flist, fcount);
+    hipLaunchKernelGGL(k_lr_ge_reduce, dim3(slot_grid(S)), dim3(256), 0, st, w.lrQ, gtiles,
+                       w.lrScal, flist, fcount);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int rgx = (nb + 255) / 256;
     hipLaunchKernelGGL(k_lr_rsum, dim3(rgx, slot_grid(S, 8192 / rgx + 1)), dim3(256), 0, st,
@@ -927,8 +1019,9 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
     for (int stage = 1; stage <= 2; ++stage) {
       const int nsq = stage == 1 ? 1 : 2;
       for (int s2 = 0; s2 < nsq; ++s2) {
-        if ((e = launch_gemm(false, nb, nb, nb, a, nb, sG, a, nb, sG, b, nb, sG, ucount, 0, S,
-                             st)) != hipSuccess)
+        // the matrices are symmetric (E^T E / tr and its exactly symmetric powers), so
+        // the square is the Gram a^T a: half the tiles
+        if ((e = launch_syrk(nb, nb, a, nb, sG, b, nb, sG, ucount, 0, S, st)) != hipSuccess)
           return e;
         float* t = a;
         a = b;
@@ -939,8 +1032,8 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
       hipLaunchKernelGGL(k_lr_frob_part, dim3(tiles, slot_grid(S, 8192 / tiles + 1)), dim3(256), 0,
                          st, a, nb, w.lrY, ucount);
       if ((e = hipGetLastError()) != hipSuccess) return e;
-      hipLaunchKernelGGL(k_lr_frob_reduce, dim3(dgrid), dim3(256), 0, st, w.lrY, tiles, ucount,
-                         ulist, w.lrScal, 3);
+      hipLaunchKernelGGL(k_lr_frob_reduce, dim3(slot_grid(S)), dim3(256), 0, st, w.lrY, tiles,
+                         ucount, ulist, w.lrScal, 3);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, cnt + 1, 1);
       if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -956,8 +1049,11 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
   hipLaunchKernelGGL(k_lr_aflist<P>, dim3(dgrid), dim3(256), 0, st, live, w.pflag, w.lrSig, tau,
                      aflist, afcount);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  // (blocks 1024 wide or more split the contraction over the nb columns in 256-column
+  // chunks, a function of the shape alone)
+  const int afsplit = (w.lrSplit && nb >= 1024) ? (nb + 255) / 256 : 1;
   if ((e = launch_sk(SK_B, false, nullptr, 0, 0, Dout, g, sh, list, w.lrV, sY, mb, nb, w.lrC, sC,
-                     afcount, 0, S, aflist, nullptr, 1, st)) != hipSuccess)
+                     afcount, 0, S, aflist, w.lrSplit, afsplit, st)) != hipSuccess)
     return e;
   // Z = sum_{l in L} (1 - tau / sigma_l) a_l v_l^T for certified slots (matrix cores),
   // scattered to the shifted coordinates with D' = 2 Z' - V

@@ -298,12 +298,8 @@ __global__ void __launch_bounds__(NT) k_lr_small(float* __restrict__ Zout,
             ga = wsum(ga);
             if (jacobi_rotates(ga, al, be, rr_tol)) {
               rotated = 1;
-              const float zeta = (be - al) / (2.f * ga);
-              const float tt = (fabsf(zeta) > 1e18f)
-                                   ? 0.5f / zeta
-                                   : copysignf(1.f, zeta) / (fabsf(zeta) + sqrtf(1.f + zeta * zeta));
-              const float cs = 1.f / sqrtf(1.f + tt * tt);
-              const float sn = cs * tt;
+              float cs, sn;
+              jacobi_cs(ga, al, be, &cs, &sn);
               for (int r = t; r < MB; r += 64) {
                 const float u = ap[r], v = aq[r];
                 ap[r] = cs * u - sn * v;

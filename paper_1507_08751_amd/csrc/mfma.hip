@@ -73,8 +73,9 @@ __device__ __forceinline__ int dev_count(const int* dcount, int hcount) {
 constexpr int kGLd = 65;   // LDS row pitch of the staged slabs (conflict-free transposes)
 
 // Workgroup w of the launch is dispatched to XCD w mod 8 (the chip hands workgroups
-// to its eight XCDs in turn); every tile of one slot is given ids of one residue, so a
-// block's rows are fetched into one XCD's L2 once and shared by all its tiles.
+// to its eight XCDs in turn); every tile of one (slot, row chunk) unit is given ids of
+// one residue, so the unit's rows are fetched into one XCD's L2 once and shared by all
+// its tiles.
 // TM x TM tiles, four waves each owning a quarter as (TM / 64)^2 blocks of 32 x 32
 // accumulators (every operand value read from LDS feeds TM / 64 matrix instructions);
 // slabs of KS rows, the next one loaded into registers while the matrix cores work on
@@ -97,13 +98,13 @@ __global__ void __launch_bounds__(256) k_mf_gram(const float* __restrict__ Dout,
   const int tri = tn * (tn + 1) / 2;
   const int id = blockIdx.x;
   const int xcd = id & 7, kq = id >> 3;
-  const int per = tri * chunks;
-  const int slot = (kq / per) * 8 + xcd;
+  // unit = (slot, row chunk); every tile of a unit runs on one XCD, and consecutive
+  // units on consecutive XCDs (a single wide block's chunks spread over the chip)
+  const int unit = (kq / tri) * 8 + xcd;
+  const int slot = unit / chunks, ch = unit - (unit / chunks) * chunks;
   const int count = *live_count;
   if (slot >= count) return;
-  int t = kq % per;
-  const int ch = t / tri;
-  t -= ch * tri;
+  int t = kq % tri;
   int ti = 0;
   while (t >= tn - ti) {
     t -= tn - ti;
@@ -381,16 +382,22 @@ __global__ void __launch_bounds__(256) k_sk(const float* __restrict__ A, int64_t
 // A(i, k0 + 4 q + j) and X(k0 + 4 q + j, l % 16) for j < 4 as one 16-byte load each,
 // and matrix instruction j contracts over {k0 + 4 q + j : q < 4}; the four
 // instructions together cover the 16 indices once (a permutation of the sum).
-// Requires M % 16 == 0 and 16-byte aligned rows (lda % 4 == 0).
+// Requires M % 16 == 0 and 16-byte aligned rows (lda % 4 == 0). With gridDim.z > 1 the
+// contraction is split into chunks of KC (a multiple of 16) and chunk z writes its
+// partial product to part + (slot * chunks + z) * M * 16 (row-major), summed by k_sk_sum
+// (only without a slot list).
 __global__ void __launch_bounds__(256) k_sym_x(const float* __restrict__ A, int64_t sA, int lda,
                                                const float* __restrict__ X, int64_t sX, int M,
                                                float* __restrict__ Y, int64_t sY,
                                                const int* __restrict__ dcount,
-                                               const int* __restrict__ slot_list) {
+                                               const int* __restrict__ slot_list,
+                                               float* __restrict__ part, int KC) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int q = lane >> 4, c = lane & 15;
   const int count = *dcount;
   const int rows_per = gridDim.x * 64;
+  const int chunks = gridDim.z, ch = blockIdx.z;
+  const int kb = ch * KC, ke = min(M, kb + KC);
   for (int cidx = blockIdx.y; cidx < count; cidx += gridDim.y) {
     const int slot = slot_list ? slot_list[cidx] : cidx;
     for (int i0 = blockIdx.x * 64 + wv * 16; i0 < M; i0 += rows_per) {
@@ -398,7 +405,7 @@ __global__ void __launch_bounds__(256) k_sym_x(const float* __restrict__ A, int6
       const float* xcol = X + (int64_t)slot * sX + (int64_t)c * M + 4 * q;
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll 4
-      for (int k0 = 0; k0 < M; k0 += 16) {
+      for (int k0 = kb; k0 < ke; k0 += 16) {
         const float4 av = *reinterpret_cast<const float4*>(arow + k0);
         const float4 xv = *reinterpret_cast<const float4*>(xcol + k0);
         acc = mfma16(av.x, xv.x, acc);
@@ -406,9 +413,15 @@ __global__ void __launch_bounds__(256) k_sym_x(const float* __restrict__ A, int6
         acc = mfma16(av.z, xv.z, acc);
         acc = mfma16(av.w, xv.w, acc);
       }
-      float* y = Y + (int64_t)slot * sY + (int64_t)c * M + i0 + 4 * q;
+      if (chunks > 1) {
+        float* pp = part + ((int64_t)slot * chunks + ch) * M * 16;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) y[r] = acc[r];
+        for (int r = 0; r < 4; ++r) pp[(int64_t)(i0 + 4 * q + r) * 16 + c] = acc[r];
+      } else {
+        float* y = Y + (int64_t)slot * sY + (int64_t)c * M + i0 + 4 * q;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) y[r] = acc[r];
+      }
     }
   }
 }
@@ -494,10 +507,12 @@ __global__ void __launch_bounds__(256) k_skg(const float* __restrict__ Dout, Sca
 template <int ROWMAJ>
 __global__ void __launch_bounds__(256) k_sk_sum(const float* __restrict__ part, int chunks, int M,
                                                 float* __restrict__ C, int64_t sC,
-                                                const int* __restrict__ dcount, int hcount) {
+                                                const int* __restrict__ dcount, int hcount,
+                                                const int* __restrict__ slot_list) {
   const int count = dev_count(dcount, hcount);
   const int64_t n = (int64_t)M * 16;
-  for (int slot = blockIdx.y; slot < count; slot += gridDim.y)
+  for (int cidx = blockIdx.y; cidx < count; cidx += gridDim.y) {
+    const int slot = slot_list ? slot_list[cidx] : cidx;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
          e += (int64_t)gridDim.x * blockDim.x) {
       const float* p = part + (int64_t)slot * chunks * n + e;
@@ -507,13 +522,17 @@ __global__ void __launch_bounds__(256) k_sk_sum(const float* __restrict__ part, 
       if (ROWMAJ) C[(int64_t)slot * sC + e] = s;
       else C[(int64_t)slot * sC + (int64_t)l * M + i] = s;
     }
+  }
 }
 
 // ------------------------------------------------------------ general GEMM
 // C (M x N) = op(A) B, column-major, one problem per batch entry c < count (pointer
 // strides sa, sb, sc); op(A) = A (TA = 0, A[k lda + i]) or A^T (TA = 1, A[i lda + k]).
 // 64 x 64 tiles, slabs of 32 along K, four waves on v_mfma_f32_32x32x2f32.
-template <int TA>
+// SYM (with TA = 1, B = A, M = N): C = A^T A, only the tiles with i0 <= j0 are formed
+// (blockIdx.x enumerates the upper triangle) and each is also written mirrored, so C is
+// exactly symmetric.
+template <int TA, int SYM = 0>
 __global__ void __launch_bounds__(256) k_gemm(const float* __restrict__ A, int lda, int64_t sa,
                                               const float* __restrict__ B, int ldb, int64_t sb,
                                               float* __restrict__ C, int ldc, int64_t sc, int M,
@@ -523,7 +542,17 @@ __global__ void __launch_bounds__(256) k_gemm(const float* __restrict__ A, int l
   float* As = sm;
   float* Bs = sm + 32 * kGLd;
   const int tiles_m = (M + 63) / 64;
-  const int i0 = (blockIdx.x % tiles_m) * 64, j0 = (blockIdx.x / tiles_m) * 64;
+  int ti = blockIdx.x % tiles_m, tj = blockIdx.x / tiles_m;
+  if (SYM) {
+    int t = blockIdx.x;
+    ti = 0;
+    while (t >= tiles_m - ti) {
+      t -= tiles_m - ti;
+      ++ti;
+    }
+    tj = ti + t;
+  }
+  const int i0 = ti * 64, j0 = tj * 64;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wi = wv & 1, wj = wv >> 1;
   const int count = dev_count(dcount, hcount);
@@ -582,6 +611,11 @@ __global__ void __launch_bounds__(256) k_gemm(const float* __restrict__ A, int l
       const int jj = e >> 6, ii = e & 63;
       if (i0 + ii < M && j0 + jj < N) cc[(int64_t)(j0 + jj) * ldc + i0 + ii] = T[ii * kGLd + jj];
     }
+    if (SYM && i0 != j0)
+      for (int e = tid; e < 64 * 64; e += 256) {
+        const int ii = e >> 6, jj = e & 63;   // element (j0 + jj, i0 + ii), along jj
+        if (i0 + ii < M && j0 + jj < N) cc[(int64_t)(i0 + ii) * ldc + j0 + jj] = T[ii * kGLd + jj];
+      }
     __syncthreads();
   }
 }
@@ -676,10 +710,14 @@ static int grid_slots(int slots, int per_slot) {
 
 int split_chunks(int mb, int nb) {
   // tall blocks split their rows (the contraction of B^T B and B^T A_f) into chunks of
-  // about 512 rows, so that few blocks still fill the chip; a function of the block
-  // shape alone, so that a block's result does not depend on how many others run
-  if (mb < 4 * nb) return 1;
-  int c = (mb + 511) / 512;
+  // about 512 rows, and blocks 1024 wide or more into chunks of 256 rows, so that few
+  // blocks still fill the chip; a function of the block shape alone, so that a block's
+  // result does not depend on how many others run
+  int c = 1;
+  if (nb >= 1024)
+    c = (mb + 255) / 256;
+  else if (mb >= 4 * nb)
+    c = (mb + 511) / 512;
   return c > 64 ? 64 : c;
 }
 
@@ -706,9 +744,10 @@ hipError_t launch_mf_gram(const ScaleGeom& g, const ShiftSpec& sh, const float* 
   int KC = (mb + chunks - 1) / chunks;
   KC = (KC + KS - 1) / KS * KS;
   chunks = (mb + KC - 1) / KC;
-  // one workgroup per (slot, tile, chunk), ids grouped so that a slot stays on one XCD
-  const int64_t groups = (slots + 7) / 8;
-  const int64_t nwg = groups * 8 * tri * chunks;
+  // one workgroup per (slot, chunk, tile), ids grouped so that a (slot, chunk) unit
+  // stays on one XCD
+  const int64_t groups = ((int64_t)slots * chunks + 7) / 8;
+  const int64_t nwg = groups * 8 * tri;
   if (nwg > 0x7fffffff) return hipErrorInvalidValue;
   const int64_t sG = (int64_t)nb * nb;
   if (var == 0)
@@ -722,7 +761,7 @@ hipError_t launch_mf_gram(const ScaleGeom& g, const ShiftSpec& sh, const float* 
                        live_count, live_list, G, sG, part, KC, chunks);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || chunks == 1) return e;
-  const int gx = (int)std::min<int64_t>((sG + 255) / 256, 64);
+  const int gx = (int)std::min<int64_t>((sG + 255) / 256, 1024);
   hipLaunchKernelGGL(k_gram_sum, dim3(gx, grid_slots(slots, gx)), dim3(256), 0, st, part, chunks,
                      nb, live_count, G, sG);
   return hipGetLastError();
@@ -734,9 +773,8 @@ hipError_t launch_sk(int mode, bool rowmaj, const float* A, int64_t sA, int lda,
                      int64_t sC, const int* dcount, int hcount, int slots, const int* slot_list,
                      float* part, int split, hipStream_t st) {
   const int tm = (M + 63) / 64;
-  // split the contraction into `split` chunks (partial sums indexed by walk position,
-  // so never with a slot list)
-  int chunks = (part && !slot_list && split > 1) ? split : 1;
+  // split the contraction into `split` chunks (partial sums indexed by slot)
+  int chunks = (part && split > 1) ? split : 1;
   int KC = (K + chunks - 1) / chunks;
   KC = (KC + 63) / 64 * 64;
   chunks = (K + KC - 1) / KC;
@@ -776,19 +814,40 @@ hipError_t launch_sk(int mode, bool rowmaj, const float* A, int64_t sA, int lda,
   const int gx = (int)std::min<int64_t>((n + 255) / 256, 64);
   if (rowmaj)
     hipLaunchKernelGGL(k_sk_sum<1>, dim3(gx, grid_slots(slots, gx)), dim3(256), 0, st, part,
-                       chunks, M, C, sC, dcount, hcount);
+                       chunks, M, C, sC, dcount, hcount, slot_list);
   else
     hipLaunchKernelGGL(k_sk_sum<0>, dim3(gx, grid_slots(slots, gx)), dim3(256), 0, st, part,
-                       chunks, M, C, sC, dcount, hcount);
+                       chunks, M, C, sC, dcount, hcount, slot_list);
   return hipGetLastError();
 }
 
 hipError_t launch_sym_x(const float* A, int64_t sA, int lda, const float* X, int64_t sX, int M,
                         float* Y, int64_t sY, const int* dcount, int slots, const int* slot_list,
-                        hipStream_t st) {
+                        float* part, hipStream_t st) {
   const int gx = (M + 63) / 64;
-  hipLaunchKernelGGL(k_sym_x, dim3(gx, grid_slots(slots, gx)), dim3(256), 0, st, A, sA, lda, X,
-                     sX, M, Y, sY, dcount, slot_list);
+  // matrices 1024 wide or more split the contraction into 256-column chunks (a function
+  // of M alone, so a product's rounding does not depend on the slot count)
+  const int chunks = (part && !slot_list && M >= 1024) ? (M + 255) / 256 : 1;
+  const int KC = chunks > 1 ? 256 : M;
+  hipLaunchKernelGGL(k_sym_x, dim3(gx, grid_slots(slots, gx * chunks), chunks), dim3(256), 0, st,
+                     A, sA, lda, X, sX, M, Y, sY, dcount, slot_list, part, KC);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || chunks == 1) return e;
+  const int64_t n = (int64_t)M * 16;
+  const int sx = (int)std::min<int64_t>((n + 255) / 256, 64);
+  hipLaunchKernelGGL(k_sk_sum<0>, dim3(sx, grid_slots(slots, sx)), dim3(256), 0, st, part, chunks,
+                     M, Y, sY, dcount, 0, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_syrk(int M, int K, const float* A, int lda, int64_t sa, float* C, int ldc,
+                       int64_t sc, const int* dcount, int hcount, int max_count, hipStream_t st) {
+  if (max_count <= 0) return hipSuccess;
+  const int tm = (M + 63) / 64;
+  const int tiles = tm * (tm + 1) / 2;
+  const dim3 grid(tiles, grid_slots(max_count, tiles));
+  hipLaunchKernelGGL((k_gemm<1, 1>), grid, dim3(256), 0, st, A, lda, sa, A, lda, sa, C, ldc, sc, M,
+                     M, K, dcount, hcount);
   return hipGetLastError();
 }
 

@@ -64,6 +64,24 @@ __device__ inline bool jacobi_rotates(float ga, float al, float be, float tol) {
   return fabsf(ga) > tol * __builtin_amdgcn_sqrtf(al) * __builtin_amdgcn_sqrtf(be);
 }
 
+// One-sided Jacobi rotation of columns with squared norms al, be and inner product ga
+// (p' = c p - s q, q' = s p + c q): tan t of the smaller angle from zeta = (be - al) /
+// (2 ga), formed with the hardware reciprocal, square root and reciprocal square root
+// (about 1 ulp each). The angle need not be exact (the next sweep removes what is
+// left); c = 1 / sqrt(1 + t^2) and s = t c keep the rotation orthogonal to float32
+// rounding.
+__device__ inline void jacobi_cs(float ga, float al, float be, float* c, float* s) {
+  const float zeta = (be - al) * __builtin_amdgcn_rcpf(2.f * ga);
+  const float az = fabsf(zeta);
+  const float t = az > 1e18f ? 0.5f * __builtin_amdgcn_rcpf(zeta)
+                             : copysignf(__builtin_amdgcn_rcpf(
+                                             az + __builtin_amdgcn_sqrtf(1.f + zeta * zeta)),
+                                         zeta);
+  const float cc = __builtin_amdgcn_rsqf(1.f + t * t);
+  *c = cc;
+  *s = cc * t;
+}
+
 __device__ inline bool inst_active(const ShiftSpec& s, int z) {
   return s.iactive == nullptr || s.iactive[z] != 0;
 }
@@ -159,8 +177,6 @@ struct ScaleWork {
   float* lrOm;          // [nb*p] probe matrix
   float* lrSplit;       // [slots][chunks][nb*nb] split partials of tall blocks (null: none)
   int lrChunks;         // split_chunks(mb, nb)
-  double* lrPart64;     // [slots][lrChunks64][256] float64 Gram partials of the reduced block
-  int lrChunks64;       // row chunks of that Gram
   int* lrCount;         // [5] device counters: fallback, appends, undecided after the trace
                         // bound, undecided after the stage-0 bounds, A_f list
   int* lrFall;          // [5 slots] block ids, then slot indices, of failed certificates;
@@ -273,9 +289,14 @@ hipError_t launch_sk(int mode, bool rowmaj, const float* A, int64_t sA, int lda,
                      int64_t sC, const int* dcount, int hcount, int slots, const int* slot_list,
                      float* part, int split, hipStream_t st);
 // Y = A X (M x 16) for symmetric A, barrier-free; needs M % 16 == 0 and lda % 4 == 0.
+// With part (slots x ceil(M / 256) x M x 16 floats), M >= 1024 splits the contraction.
 hipError_t launch_sym_x(const float* A, int64_t sA, int lda, const float* X, int64_t sX, int M,
                         float* Y, int64_t sY, const int* dcount, int slots, const int* slot_list,
-                        hipStream_t st);
+                        float* part, hipStream_t st);
+// C = A^T A (M x M from the K x M column-major A), exactly symmetric (upper tiles formed
+// and mirrored), batch entries c < count.
+hipError_t launch_syrk(int M, int K, const float* A, int lda, int64_t sa, float* C, int ldc,
+                       int64_t sc, const int* dcount, int hcount, int max_count, hipStream_t st);
 // C = op(A) B, column-major, batch entries c < count.
 hipError_t launch_gemm(bool ta, int M, int N, int K, const float* A, int lda, int64_t sa,
                        const float* B, int ldb, int64_t sb, float* C, int ldc, int64_t sc,

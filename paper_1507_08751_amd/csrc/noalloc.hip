@@ -121,7 +121,7 @@ extern "C" msld_status msld_bsvt_noalloc(int32_t M, int32_t N, int32_t m, int32_
   sh.mode = 2;
   sh.sr = sr;
   sh.sc = sc;
-  const float jtol = 4.0f * 5.9604645e-8f * std::sqrt((float)g.mb);
+  const float jtol = jacobi_tolerance(g.mb);
   const hipError_t e = launch_scale(g, tier, sp, w, d_V, nullptr, d_Z, dual, tau, sh, jtol, 40, 20,
                                     num_cus, st, nullptr, nullptr, false);
   return e == hipSuccess ? MSLD_OK : MSLD_EDEVICE;

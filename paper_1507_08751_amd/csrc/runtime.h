@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstddef>
 #include <cstdint>
 
@@ -16,6 +17,16 @@ constexpr size_t kLdsTierMax = 150 * 1024;   // LDS budget of one workgroup (160
 constexpr int kStreamFloats = 16384;         // stream-pass tile budget (elements)
 constexpr int kLRP = 16;                     // subspace width of the certified low-rank path
 
+// Stopping threshold of the float32 one-sided Jacobi tiers: pair (p, q) is rotated while
+// |b_p . b_q| > tol ||b_p|| ||b_q||. Those inner products over mb rows carry rounding
+// noise of order mb 2^-24, and a threshold at that level lets a block keep rotating on
+// noise up to the sweep cap (the slowest block sets a launch's time), so small blocks
+// get 2 mb 2^-24 (at most 64 2^-24) and larger ones 4 sqrt(mb) 2^-24.
+inline float jacobi_tolerance(int mb) {
+  const float a = 4.0f * std::sqrt((float)mb);
+  const float b = std::fmin(2.0f * (float)mb, 64.0f);
+  return 5.9604645e-8f * std::fmax(a, b);
+}
 int lds_tier_threads(int nb, int mb, int* G);
 size_t lds_tier_bytes(int mb, int nb);
 size_t stream_lds_bytes(int m, const StreamPlan& sp);
@@ -43,7 +54,6 @@ struct Plan {
       off_lr[MSLD_MAX_SCALES], off_pl[MSLD_MAX_SCALES];
   int pl_cap[MSLD_MAX_SCALES];   // polar fallback chunk (0: none)
   size_t off_split[MSLD_MAX_SCALES];   // split partials (tall low-rank blocks; 0: none)
-  size_t off_part64[MSLD_MAX_SCALES];  // float64 Gram partials of the reduced block
   int lds_cap[MSLD_MAX_SCALES];    // LDS tier: workgroups per CU cap (0: as many as fit)
   int lrs_wide[MSLD_MAX_SCALES];   // fused low-rank kernel: first pass with 2p
   // averaged cycle spinning: shifts per iteration (0: one random shift), whether the

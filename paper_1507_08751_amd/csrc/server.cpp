@@ -360,6 +360,16 @@ msld_status msld_server_step(msld_server* sv, int64_t* done_ids, int32_t* done_i
   return MSLD_OK;
 }
 
+msld_status msld_server_class_bytes(const msld_params* p, int32_t max_active, size_t* out) {
+  if (!p || !out || max_active < 1) return MSLD_EINVAL;
+  *out = 0;
+  if (validate_params(p) != MSLD_OK) return MSLD_EINVAL;
+  const size_t fp = cls_footprint(*p, max_active < 8 ? max_active : 8);
+  if (fp == 0) return MSLD_EINVAL;
+  *out = fp;
+  return MSLD_OK;
+}
+
 void msld_server_free(msld_server* sv) {
   if (!sv) return;
   for (msld_server::Cls* c : sv->cls) cls_destroy(sv, c);

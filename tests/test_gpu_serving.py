@@ -72,3 +72,48 @@ def test_server_budget_admits_in_fifo_order(lib):
     # one request at a time (max_active = 1): completion follows submission order
     _, order = _run(lib, reqs, max_active=1, tol=1e-3, cap=50)
     assert order == [rid for rid, _ in reqs]
+
+
+def test_server_budget_defers_second_class(lib):
+    """Admission by HBM footprint: with a budget of 1.5x the larger class footprint two
+    shape classes never hold memory together. Requests A1, B1, A2 (A and B two shapes):
+    A1 runs alone; B1 waits at the queue head, and A2 behind it (first come, first
+    served), until A1 retires and its idle class is released; then B1 runs alone, then
+    A2. Each result equals its solo run bit for bit."""
+    lad_a = [(1, 1), (4, 4), (16, 16), (128, 128)]
+    lad_b = [(1, 1), (4, 4), (16, 16), (256, 64)]
+    reqs = [(0, make_instance(128, 128, lad_a, 0.02, rank=1, noise=0.01, seed=200)),
+            (1, make_instance(256, 64, lad_b, 0.02, rank=1, noise=0.01, seed=201)),
+            (2, make_instance(128, 128, lad_a, 0.02, rank=2, noise=0.01, seed=202))]
+    fa = lib.Server.class_bytes(128, 128, lad_a, max_active=4)
+    fb = lib.Server.class_bytes(256, 64, lad_b, max_active=4)
+    budget = int(1.5 * max(fa, fb))
+    print(f"class bytes A {fa} B {fb}, budget {budget}", flush=True)
+    assert fa + fb > budget >= max(fa, fb)
+    cap = 20
+    srv = lib.Server(max_active=4, hbm_budget=budget, num_streams=4)
+    ys, outs, order, trace = {}, {}, [], []
+    for rid, inst in reqs:
+        ys[rid] = torch.from_numpy(inst.Y).cuda()
+        srv.submit(rid, ys[rid], inst.ladder, iters=cap, tol=0.0)
+    for _ in range(10 * cap):
+        for (rid, iters, resid, status, Z) in srv.step():
+            assert status == 0
+            outs[rid] = (iters, Z.cpu().numpy().copy())
+            order.append(rid)
+        trace.append((srv.active, srv.queued))
+        if len(outs) == len(reqs):
+            break
+    srv.close()
+    print(f"completion order {order}; (active, queued) at steps 1, {cap}, {cap + 1}, "
+          f"{2 * cap + 1}: {trace[0]} {trace[cap - 1]} {trace[cap]} {trace[2 * cap]}", flush=True)
+    assert order == [0, 1, 2]
+    assert all(a <= 1 for a, _ in trace), "two classes were resident at once"
+    assert trace[0] == (1, 2)          # B1 and A2 wait while A1 runs
+    assert trace[cap] == (1, 1)        # A1 retired, its class released, B1 admitted
+    assert trace[2 * cap] == (1, 0)    # B1 retired, A2 admitted
+    for rid, inst in reqs:
+        solo, _ = _run(lib, [(rid, inst)], max_active=1, tol=0.0, cap=cap)
+        assert outs[rid][0] == solo[rid][0] == cap
+        for i in range(len(inst.ladder)):
+            assert np.array_equal(outs[rid][1][i], solo[rid][2][i]), (rid, i)
