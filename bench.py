@@ -302,7 +302,8 @@ def cpu_baseline(size, threads_env):
                       f"(same ladder/density/noise), {dt:.2f} s, scaled by {size}^2/8192^2"}
 
 
-def serving_measure(nreq, nwarm, max_active, hbm_budget_gib, baseline=True, nsat=None):
+def serving_measure(nreq, nwarm, max_active, hbm_budget_gib, baseline=True, nsat=None,
+                    rate=None, server=True):
     """Serving workload: a Poisson stream of decompositions of mixed sizes
     ({128^2, 512^2, 1024x256, 2048^2}, ratio-4 ladders of 4-6 scales ending in the
     full block, rank-1/rank-2 blocks at 2% + N(0, 0.01^2)), each retired at primal
@@ -310,8 +311,9 @@ def serving_measure(nreq, nwarm, max_active, hbm_budget_gib, baseline=True, nsat
     rate of the continuous-batching server is measured with the first nsat measured
     requests queued at once; then the trace is replayed at 0.7 x that rate, and
     (baseline) again with one request at a time (FIFO) at the same arrivals. Each
-    request's final residual and why it retired (tolerance or cap) are recorded.
-    Returns the figures as a dict."""
+    request's final residual and why it retired (tolerance or cap) are recorded. With
+    server=False only the baseline runs (after its own warm-up), at the given arrival
+    rate. Returns the figures as a dict."""
     import numpy as np
     import torch
     import paper_1507_08751_amd as msld
@@ -363,6 +365,15 @@ def serving_measure(nreq, nwarm, max_active, hbm_budget_gib, baseline=True, nsat
 
     warm = reqs[:nwarm]
     meas = reqs[nwarm:]
+    if not server:
+        if rate is None:
+            raise ValueError("the baseline alone needs the arrival rate")
+        run(1, None, warm)
+        span1, lat1, _, _ = run(1, rate, meas)
+        l1 = np.array([lat1[i] for i in range(len(meas))]) * 1e3
+        return {"baseline_one_at_a_time": {"solves_per_s": round(len(meas) / span1, 4),
+                                           "p50_ms": round(float(np.percentile(l1, 50)), 2),
+                                           "p99_ms": round(float(np.percentile(l1, 99)), 2)}}
     nsat = len(meas) if nsat is None else max(1, min(nsat, len(meas)))
     run(max_active, None, warm)
     span_sat, _, _, _ = run(max_active, None, meas[:nsat])
@@ -401,9 +412,24 @@ def serving_measure(nreq, nwarm, max_active, hbm_budget_gib, baseline=True, nsat
 
 def serve_bench(args):
     """The serving workload on its own (serving_measure with the one-at-a-time
-    baseline), printed as its own JSON line."""
+    baseline), printed as its own JSON line. A run too long for one session can be
+    split: --no-baseline prints the server's line, then --baseline-from FILE runs the
+    baseline alone on the same trace at FILE's arrival rate and prints FILE's line with
+    the baseline added."""
+    if args.baseline_from:
+        with open(args.baseline_from) as f:
+            out = json.loads(f.read().strip().splitlines()[-1])
+        cfg = out["config"]
+        if cfg["requests"] != args.requests or cfg["warmup_requests"] != args.warm_requests:
+            raise SystemExit("--requests / --warm-requests differ from the server run's")
+        b = serving_measure(args.requests, args.warm_requests, 1, args.hbm_budget, server=False,
+                            rate=cfg["arrival_rate"])
+        out["baseline_one_at_a_time"] = b["baseline_one_at_a_time"]
+        out["baseline_run"] = "separate process, same trace, warm-up and arrival rate"
+        print(json.dumps(out), flush=True)
+        return
     r = serving_measure(args.requests, args.warm_requests, args.max_active, args.hbm_budget,
-                        nsat=args.sat_requests)
+                        nsat=args.sat_requests, baseline=not args.no_baseline)
     out = {"metric": "served solves/s, p99 latency @ primal residual <= 1e-4 (cap 300)",
            "value": r["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
            "higher_is_better": True, "dtype": "f32", "data": "synthetic",
@@ -412,7 +438,7 @@ def serve_bench(args):
            **{k: r[k] for k in ("saturation_solves_per_s", "saturation_requests", "p50_ms",
                                 "p99_ms", "mean_iters", "retired_by_tolerance_frac",
                                 "retired_at_cap_frac", "final_resid_p50", "final_resid_max",
-                                "label", "baseline_one_at_a_time")}}
+                                "label", "baseline_one_at_a_time") if k in r}}
     out.setdefault("config", {})["hw_queues"] = HW_QUEUES
     print(json.dumps(out), flush=True)
 
@@ -558,9 +584,14 @@ def main():
     ap.add_argument("--instances", type=int, default=256)
     ap.add_argument("--requests", type=int, default=64)
     ap.add_argument("--warm-requests", type=int, default=8)
+    ap.add_argument("--no-baseline", action="store_true",
+                    help="--mode serve: skip the one-at-a-time baseline")
+    ap.add_argument("--baseline-from", default=None,
+                    help="--mode serve: run only the baseline, at the arrival rate of this "
+                         "earlier server line (a file), and print that line with it added")
     ap.add_argument("--sat-requests", type=int, default=200,
                     help="measured requests whose all-at-once run sets the saturation rate")
-    ap.add_argument("--max-active", type=int, default=16)
+    ap.add_argument("--max-active", type=int, default=32)
     ap.add_argument("--hbm-budget", type=int, default=64, help="GiB")
     ap.add_argument("--hw-queues", type=int, default=None,
                     help="hardware queues per process (GPU_MAX_HW_QUEUES), 1..32; default 4 "

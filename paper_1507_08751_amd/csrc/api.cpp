@@ -647,7 +647,7 @@ msld_status iterate_once(msld_solver* s, const float* d_Y, int64_t ldY, float* d
   const size_t MN = plane_elems(s);
   // per-instance device seeds, iteration counters and activity flags: stacked instances,
   // and single solves that may be captured into a graph
-  const bool stacked = s->ninst > 1 || s->graphable;
+  const bool stacked = s->ninst > 1 || s->graphable || s->per_instance;
   float* R = plane_R(s);
   float* Dc = plane_D(s, s->cur);
   float* Dn = plane_D(s, 1 - s->cur);

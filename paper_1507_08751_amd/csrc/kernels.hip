@@ -282,6 +282,33 @@ hipError_t launch_inc_active(int* k, const int* active, int n, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Retirement of stacked instances on the device, after an iteration's residual sums
+// (res[z], ||Y_z||^2 at res[n + z]) and iteration counters (ik[z], already advanced):
+// an active instance stops when r = sqrt(res / ||Y||^2) is not finite, when tol > 0,
+// ik % check_every == 0 and r <= tol, or when ik reaches max_iters. Its activity flag
+// drops, so later iterations leave its state untouched, and out_iters / out_resid keep
+// the count and residual it stopped with (the same as a check after every iteration).
+__global__ void k_retire(const double* res, int n, float tol, int check_every, int max_iters,
+                         const int* ik, int* active, int* out_iters, double* out_resid) {
+  const int z = blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= n || !active[z]) return;
+  const double ny2 = res[n + z] > 0.0 ? res[n + z] : 1.0;
+  const double r = sqrt(res[z] / ny2);
+  const int k = ik[z];
+  out_iters[z] = k;
+  out_resid[z] = r;
+  if (!isfinite(r) || (tol > 0.f && k % check_every == 0 && r <= (double)tol) || k >= max_iters)
+    active[z] = 0;
+}
+
+hipError_t launch_retire(const double* res, int n, float tol, int check_every, int max_iters,
+                         const int* ik, int* active, int* out_iters, double* out_resid,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_retire, dim3((n + 255) / 256), dim3(256), 0, st, res, n, tol, check_every,
+                     max_iters, ik, active, out_iters, out_resid);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------- register tier (small blocks)
 // Register tier, live blocks only: one lane per block of the live list built by the
 // stream pass. The block's V (SM x SN as stored) is read back from D' = -V (written by

@@ -33,6 +33,10 @@ size_t stream_lds_bytes(int m, const StreamPlan& sp);
 hipError_t launch_fill_ints(int* p, int v, size_t count, hipStream_t st);
 hipError_t launch_set_int(int* p, int idx, int v, hipStream_t st);
 hipError_t launch_inc_active(int* k, const int* active, int n, hipStream_t st);
+// Device-side retirement of stacked instances after an iteration (see kernels.hip).
+hipError_t launch_retire(const double* res, int n, float tol, int check_every, int max_iters,
+                         const int* ik, int* active, int* out_iters, double* out_resid,
+                         hipStream_t st);
 
 // Plan of one problem shape, for ninst instances stacked along the rows.
 struct Plan {
@@ -104,6 +108,9 @@ struct msld_solver {
   hipEvent_t ev_sfork[MSLD_MAX_SCALES];   // after scale i's stream pass (its own fork point)
   int early_fork;   // scales fork after their own stream pass (planes <= 2^24 elements)
   int serial;       // every scale's BlockSVT on the handle's stream, one after another
+  int per_instance; // per-instance seeds, counters and activity flags even for one
+                    // instance that is not replayed from graphs (the serving loop's
+                    // device-side retirement needs the flags)
   msld::ScaleWork work[MSLD_MAX_SCALES];
   msld::StreamAll sall;   // the stream pass of all decomposed scales (one launch)
   const uint8_t* mask;    // observed-entry mask (caller-owned, device) or null

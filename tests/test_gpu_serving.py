@@ -96,22 +96,22 @@ def test_server_budget_defers_second_class(lib):
     for rid, inst in reqs:
         ys[rid] = torch.from_numpy(inst.Y).cuda()
         srv.submit(rid, ys[rid], inst.ladder, iters=cap, tol=0.0)
-    for _ in range(10 * cap):
+    for _ in range(100000):
         for (rid, iters, resid, status, Z) in srv.step():
             assert status == 0
             outs[rid] = (iters, Z.cpu().numpy().copy())
             order.append(rid)
-        trace.append((srv.active, srv.queued))
+        trace.append((srv.active, srv.queued, len(order)))
         if len(outs) == len(reqs):
             break
     srv.close()
-    print(f"completion order {order}; (active, queued) at steps 1, {cap}, {cap + 1}, "
-          f"{2 * cap + 1}: {trace[0]} {trace[cap - 1]} {trace[cap]} {trace[2 * cap]}", flush=True)
+    print(f"completion order {order}; {len(trace)} steps; first {trace[0]}", flush=True)
     assert order == [0, 1, 2]
-    assert all(a <= 1 for a, _ in trace), "two classes were resident at once"
-    assert trace[0] == (1, 2)          # B1 and A2 wait while A1 runs
-    assert trace[cap] == (1, 1)        # A1 retired, its class released, B1 admitted
-    assert trace[2 * cap] == (1, 0)    # B1 retired, A2 admitted
+    assert all(a <= 1 for a, _, _ in trace), "two classes were resident at once"
+    assert trace[0] == (1, 2, 0)       # B1 and A2 wait while A1 runs
+    # B1 is admitted only after A1 retired (its idle class released), A2 only after B1
+    for a, q, d in trace:
+        assert q == 2 - d or (a == 0 and q == 3 - d), (a, q, d)
     for rid, inst in reqs:
         solo, _ = _run(lib, [(rid, inst)], max_active=1, tol=0.0, cap=cap)
         assert outs[rid][0] == solo[rid][0] == cap
