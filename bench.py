@@ -303,7 +303,7 @@ def cpu_baseline(size, threads_env):
 
 
 def serving_measure(nreq, nwarm, max_active, hbm_budget_gib, baseline=True, nsat=None,
-                    rate=None, server=True):
+                    rate=None, server=True, bwarm=None):
     """Serving workload: a Poisson stream of decompositions of mixed sizes
     ({128^2, 512^2, 1024x256, 2048^2}, ratio-4 ladders of 4-6 scales ending in the
     full block, rank-1/rank-2 blocks at 2% + N(0, 0.01^2)), each retired at primal
@@ -312,8 +312,8 @@ def serving_measure(nreq, nwarm, max_active, hbm_budget_gib, baseline=True, nsat
     requests queued at once; then the trace is replayed at 0.7 x that rate, and
     (baseline) again with one request at a time (FIFO) at the same arrivals. Each
     request's final residual and why it retired (tolerance or cap) are recorded. With
-    server=False only the baseline runs (after its own warm-up), at the given arrival
-    rate. Returns the figures as a dict."""
+    server=False only the baseline runs (after a warm-up on the first bwarm warm-up
+    requests, default all), at the given arrival rate. Returns the figures as a dict."""
     import numpy as np
     import torch
     import paper_1507_08751_amd as msld
@@ -366,9 +366,10 @@ def serving_measure(nreq, nwarm, max_active, hbm_budget_gib, baseline=True, nsat
     warm = reqs[:nwarm]
     meas = reqs[nwarm:]
     if not server:
+        bwarm = nwarm if bwarm is None else bwarm
         if rate is None:
             raise ValueError("the baseline alone needs the arrival rate")
-        run(1, None, warm)
+        run(1, None, warm[:bwarm])
         span1, lat1, _, _ = run(1, rate, meas)
         l1 = np.array([lat1[i] for i in range(len(meas))]) * 1e3
         return {"baseline_one_at_a_time": {"solves_per_s": round(len(meas) / span1, 4),
@@ -422,10 +423,12 @@ def serve_bench(args):
         cfg = out["config"]
         if cfg["requests"] != args.requests or cfg["warmup_requests"] != args.warm_requests:
             raise SystemExit("--requests / --warm-requests differ from the server run's")
+        bwarm = args.baseline_warm if args.baseline_warm is not None else args.warm_requests
         b = serving_measure(args.requests, args.warm_requests, 1, args.hbm_budget, server=False,
-                            rate=cfg["arrival_rate"])
+                            rate=cfg["arrival_rate"], bwarm=bwarm)
         out["baseline_one_at_a_time"] = b["baseline_one_at_a_time"]
-        out["baseline_run"] = "separate process, same trace, warm-up and arrival rate"
+        out["baseline_run"] = (f"separate process, the same {args.requests} measured requests at "
+                               f"the same arrival rate, after {bwarm} warm-up requests")
         print(json.dumps(out), flush=True)
         return
     r = serving_measure(args.requests, args.warm_requests, args.max_active, args.hbm_budget,
@@ -589,6 +592,8 @@ def main():
     ap.add_argument("--baseline-from", default=None,
                     help="--mode serve: run only the baseline, at the arrival rate of this "
                          "earlier server line (a file), and print that line with it added")
+    ap.add_argument("--baseline-warm", type=int, default=None,
+                    help="--baseline-from: warm-up requests run before the baseline")
     ap.add_argument("--sat-requests", type=int, default=200,
                     help="measured requests whose all-at-once run sets the saturation rate")
     ap.add_argument("--max-active", type=int, default=32)
