@@ -686,7 +686,8 @@ def main():
             f"certified {stats['certified'][i]} (fail coupling {stats['fail_coupling'][i]}, "
             f"bound {stats['fail_bound'][i]}, polar {stats['polar'][i]}); undecided by the trace "
             f"bound {stats['undecided'][i]}, certified by Collatz-Wielandt only "
-            f"{stats['cw_certified'][i]}")
+            f"{stats['cw_certified'][i]}, certified zero by the Gram bound "
+            f"{stats['gram_certified'][i]}")
     roof, extra = stream_roofline(prof, tiers, M, N, K)
     k50 = None
     if K != 50:

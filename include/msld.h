@@ -167,6 +167,10 @@ typedef struct msld_result {
                                              undecided) */
   uint64_t cw_certified[MSLD_MAX_SCALES]; /* of those, certified by the Collatz-Wielandt
                                              bound where the Frobenius bound alone failed */
+  uint64_t gram_certified[MSLD_MAX_SCALES]; /* low-rank blocks certified to have no singular
+                                               value above tau by the Collatz-Wielandt
+                                               bound of their Gram matrix, before any
+                                               subspace iteration (output zero) */
 } msld_result;
 
 typedef struct msld_solver msld_solver; /* opaque */

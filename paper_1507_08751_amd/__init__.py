@@ -69,7 +69,8 @@ class Result(ctypes.Structure):
                 ("polar", ctypes.c_uint64 * MAX_SCALES),
                 ("polar_steps", ctypes.c_uint64 * MAX_SCALES),
                 ("undecided", ctypes.c_uint64 * MAX_SCALES),
-                ("cw_certified", ctypes.c_uint64 * MAX_SCALES)]
+                ("cw_certified", ctypes.c_uint64 * MAX_SCALES),
+                ("gram_certified", ctypes.c_uint64 * MAX_SCALES)]
 
 
 EXPORTS = {
@@ -279,7 +280,8 @@ class Solver:
                 "polar": list(res.polar)[:self.L],
                 "polar_steps": list(res.polar_steps)[:self.L],
                 "undecided": list(res.undecided)[:self.L],
-                "cw_certified": list(res.cw_certified)[:self.L]}
+                "cw_certified": list(res.cw_certified)[:self.L],
+                "gram_certified": list(res.gram_certified)[:self.L]}
 
     def _check_yz(self, Y, Z):
         torch = self._torch
@@ -317,7 +319,8 @@ class Solver:
                 "polar": list(res.polar)[:self.L],
                 "polar_steps": list(res.polar_steps)[:self.L],
                 "undecided": list(res.undecided)[:self.L],
-                "cw_certified": list(res.cw_certified)[:self.L]}
+                "cw_certified": list(res.cw_certified)[:self.L],
+                "gram_certified": list(res.gram_certified)[:self.L]}
 
     def set_graph(self, enable=True):
         """Allow (default) or forbid replaying iterations from captured HIP graphs;

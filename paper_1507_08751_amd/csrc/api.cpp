@@ -145,7 +145,7 @@ msld_status make_plan(const msld_params* p, int ninst, Plan* pl) {
     if (noise) {
       // Frobenius prox: per-instance partial sums of squares and gains
       pl->tier[i] = TIER_FRO;
-      pl->off_stats[i] = take(8 * 8);
+      pl->off_stats[i] = take(8 * kStatsWords);
       pl->off_lr[i] = take(8 * (size_t)kFroParts * ninst + 4 * (size_t)ninst);
       continue;
     }
@@ -191,7 +191,7 @@ msld_status make_plan(const msld_params* p, int ninst, Plan* pl) {
     }
     pl->use_lr[i] = lr ? 1 : 0;
     pl->tier[i] = tier;
-    pl->off_stats[i] = take(8 * 8);
+    pl->off_stats[i] = take(8 * kStatsWords);
     if (tier == TIER_1X1) continue;
     // averaged cycle spinning: a cyclic shift along an axis the block spans whole
     // permutes rows (columns) inside each block, which its SVT follows exactly, so
@@ -275,7 +275,7 @@ msld_status make_plan(const msld_params* p, int ninst, Plan* pl) {
         const size_t tn = ((size_t)g.nb + 63) / 64;
         const size_t per = 3 * nb2 + 4 * (size_t)g.nb * kLRP + (size_t)g.mb * kLRP +
                            (size_t)kLRP * g.nb + 3 * kLRP + 8 + (size_t)g.nb * (tn + 1);
-        pl->off_lr[i] = take(4 * ((size_t)nblk * per + (size_t)g.nb * kLRP + 64 + 5 * nblk));
+        pl->off_lr[i] = take(4 * ((size_t)nblk * per + (size_t)g.nb * kLRP + 64 + 6 * nblk));
         // split partials of the Gram matrix of tall or wide blocks, sized by the block
         // shape and the slot count
         const int ch = split_chunks(g.mb, g.nb);
@@ -632,7 +632,7 @@ static hipStream_t scale_stream(const msld_solver* s, int i) {
 
 static msld_status zero_stats(msld_solver* s) {
   for (int i = 0; i < s->p.L; ++i) {
-    MSLD_TRY(s, hipMemsetAsync(s->work[i].stats, 0, 8 * 8, s->st));
+    MSLD_TRY(s, hipMemsetAsync(s->work[i].stats, 0, 8 * kStatsWords, s->st));
     for (long long& v : s->work[i].stats_host) v = 0;
   }
   return MSLD_OK;
@@ -886,7 +886,7 @@ static msld_status fill_stats(msld_solver* s, msld_result* info) {
   info->iters = s->k;
   info->primal_resid = -1.0;
   for (int i = 0; i < s->p.L; ++i) {
-    unsigned long long st8[8];
+    unsigned long long st8[kStatsWords];
     MSLD_TRY(s, hipMemcpyAsync(st8, s->work[i].stats, sizeof(st8), hipMemcpyDeviceToHost, s->st));
     MSLD_TRY(s, hipStreamSynchronize(s->st));
     info->live[i] = st8[0];
@@ -899,6 +899,7 @@ static msld_status fill_stats(msld_solver* s, msld_result* info) {
     info->polar_steps[i] = (uint64_t)(s->work[i].stats_host[1] + s->work[i].stats_host[2]);
     info->undecided[i] = st8[6];
     info->cw_certified[i] = st8[7];
+    info->gram_certified[i] = st8[8];
   }
   return MSLD_OK;
 }

@@ -164,7 +164,8 @@ __device__ double gram64_stream(const float* y, const float* z, int nb, float (*
 // left of the first pass's departure from orthonormality.
 template <int P>
 __global__ void __launch_bounds__(1024) k_lr_orth_cq(const float* Y, float* X, int nb,
-                                                     int64_t stride, const int* count) {
+                                                     int64_t stride, const int* count,
+                                                     const int* sl) {
   constexpr int NT = 1024;
   static_assert(P * P == 256, "the Gram entries fill a quarter of the workgroup");
   __shared__ float zs[kBC][P + 1];
@@ -173,7 +174,8 @@ __global__ void __launch_bounds__(1024) k_lr_orth_cq(const float* Y, float* X, i
   __shared__ double T[P][P + 1];
   const int cnt = *count;
   const int tid = threadIdx.x;
-  for (int slot = blockIdx.x; slot < cnt; slot += gridDim.x) {
+  for (int ci = blockIdx.x; ci < cnt; ci += gridDim.x) {
+    const int slot = sl ? sl[ci] : ci;
     const float* y = Y + (int64_t)slot * stride;
     float* x = X + (int64_t)slot * stride;
     for (int pass = 0; pass < 2; ++pass) {
@@ -260,10 +262,12 @@ __device__ __forceinline__ float wave_sum(float v) {
 // fixed pass count keeps every register index static.
 template <int P, int RPL>
 __global__ void __launch_bounds__(256) k_lr_orth_w(const float* Y, float* X, int nb,
-                                                   int64_t stride, const int* count) {
+                                                   int64_t stride, const int* count,
+                                                   const int* sl) {
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int cnt = *count;
-  for (int slot = blockIdx.x * 4 + wv; slot < cnt; slot += gridDim.x * 4) {
+  for (int ci = blockIdx.x * 4 + wv; ci < cnt; ci += gridDim.x * 4) {
+  const int slot = sl ? sl[ci] : ci;
   const float* y = Y + (int64_t)slot * stride;
   float* x = X + (int64_t)slot * stride;
   float v[P][RPL];
@@ -379,7 +383,7 @@ __device__ __forceinline__ bool jacobi_rot64(double app, double aqq, double apq,
 template <int P>
 __global__ void __launch_bounds__(256) k_lr_reduced(const float* X, const float* W0, int nb,
                                                     float* Vr, float* Tt, float* sig,
-                                                    const int* count) {
+                                                    const int* count, const int* sl) {
   static_assert(P * P == 256, "one Gram entry per thread");
   static_assert((P / 2) * (P / 2) <= 64, "one wave of sub-blocks");
   __shared__ float ys[kRC][P + 1], zs[kRC][P + 1];
@@ -388,7 +392,8 @@ __global__ void __launch_bounds__(256) k_lr_reduced(const float* X, const float*
   __shared__ int s_rot;
   const int tid = threadIdx.x;
   const int cnt = *count;
-  for (int slot = blockIdx.x; slot < cnt; slot += gridDim.x) {
+  for (int ci = blockIdx.x; ci < cnt; ci += gridDim.x) {
+    const int slot = sl ? sl[ci] : ci;
     const float* x = X + (int64_t)slot * nb * P;
     const float* w0 = W0 + (int64_t)slot * nb * P;
     const double kv = gram64_pp<P>(x, w0, nb, ys, zs);
@@ -478,11 +483,13 @@ template <int P>
 __global__ void __launch_bounds__(256) k_lr_coupling(const float* T, const float* sig,
                                                      const float* Vr, int nb, float tau,
                                                      float tol, float* scal, float* mask,
-                                                     float* dmask, const int* count) {
+                                                     float* dmask, const int* count,
+                                                     const int* sl) {
   __shared__ float red[8];
   __shared__ float cl[P];
   const int cnt = *count;
-  for (int slot = blockIdx.x; slot < cnt; slot += gridDim.x) {
+  for (int ci = blockIdx.x; ci < cnt; ci += gridDim.x) {
+  const int slot = sl ? sl[ci] : ci;
   __syncthreads();
   const float* t = T + (int64_t)slot * P * nb;
   const float* vr = Vr + (int64_t)slot * nb * P;
@@ -588,6 +595,60 @@ __global__ void __launch_bounds__(256) k_lr_q(const float* Wg, const float* Vr, 
   }
 }
 
+// Per 64 x 64 tile of the Gram matrix G of each live slot, the partial sums of |G_ij|
+// over the tile's columns for each of its rows (rowpart slice tj, the layout the
+// Collatz-Wielandt steps below read); fixed summation order.
+__global__ void __launch_bounds__(256) k_lr_gabs_rowpart(const float* G, int nb, float* rowpart,
+                                                         const int* count) {
+  __shared__ float ps[4][64];
+  const int cnt = *count;
+  const int tn = (nb + 63) / 64;
+  const int ti = blockIdx.x % tn, tj = blockIdx.x / tn;
+  const int i0 = ti * 64, j0 = tj * 64;
+  const int il = threadIdx.x & 63, jg = threadIdx.x >> 6;
+  const int i = i0 + il;
+  for (int slot = blockIdx.y; slot < cnt; slot += gridDim.y) {
+    const float* g = G + (int64_t)slot * nb * nb;
+    float a = 0.f;
+    if (i < nb)
+      for (int jl = jg; jl < 64 && j0 + jl < nb; jl += 4) a += fabsf(g[(int64_t)(j0 + jl) * nb + i]);
+    __syncthreads();
+    ps[jg][il] = a;
+    __syncthreads();
+    if (threadIdx.x < 64 && i < nb)
+      rowpart[(int64_t)slot * nb * (tn + 1) + (int64_t)tj * nb + i] =
+          (ps[0][il] + ps[1][il]) + (ps[2][il] + ps[3][il]);
+  }
+}
+
+// Zero-output certificate before the subspace iteration: sigma_max(B)^2 = lambda_max(G)
+// is at most the Collatz-Wielandt bound of |G| (scal[5]); below tau^2 (with the
+// certificate's margin) every singular value is thresholded to zero, which is the
+// output the stream pass already wrote (Z' = 0, D' = -V). Such slots are settled here
+// (no singular values, no rebuild); the others are listed for the subspace iteration
+// (fall[5 slots ..], counts[5]).
+__global__ void k_lr_gram_decide(const int* live, int slots, const float* scal, float* sig,
+                                 float tau, int* pflag, int* counts, int* fall,
+                                 unsigned long long* stats) {
+  const int count = *live;
+  const float lim = tau * tau * (1.f - kCertMargin);
+  for (int slot = blockIdx.x * blockDim.x + threadIdx.x; slot < count;
+       slot += gridDim.x * blockDim.x) {
+    const float b = scal[slot * 8 + 5];
+    if (b <= lim && isfinite(b)) {
+      for (int l = 0; l < 16; ++l) sig[slot * 16 + l] = 0.f;
+      pflag[4 * slot + 1] = 1;
+      pflag[4 * slot + 2] = 1;
+      pflag[4 * slot + 3] = 0;
+      atomicAdd(&stats[0], 1ull);
+      atomicAdd(&stats[3], 1ull);
+      atomicAdd(&stats[8], 1ull);
+    } else {
+      fall[5 * slots + atomicAdd(&counts[5], 1)] = slot;
+    }
+  }
+}
+
 // Collatz-Wielandt bound for the symmetric M = E^T E (in Pm): with r = |M| 1 and
 // y = |M| r, lambda_max(M) <= rho(|M|) <= max_i y_i / r_i (a row with r_i = 0 is zero).
 // Three small steps on the tile partials, all in a fixed summation order:
@@ -601,7 +662,7 @@ __global__ void __launch_bounds__(256) k_lr_rsum(float* rowpart, int nb, const i
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nb) return;
   for (int cidx = blockIdx.y; cidx < cnt; cidx += gridDim.y) {
-    const int slot = list[cidx];
+    const int slot = list ? list[cidx] : cidx;
     float* rp = rowpart + (int64_t)slot * nb * (tn + 1);
     float v = 0.f;
     for (int t = 0; t < tn; ++t) v += rp[(int64_t)t * nb + i];
@@ -615,7 +676,7 @@ __global__ void __launch_bounds__(256) k_lr_cwy(const float* Pm, float* rowpart,
   __shared__ float ys[4][64];
   const int cnt = *lcount;
   for (int cidx = blockIdx.y; cidx < cnt; cidx += gridDim.y) {
-  const int slot = list[cidx];
+  const int slot = list ? list[cidx] : cidx;
   const int tn = (nb + 63) / 64;
   const int ti = blockIdx.x % tn, tj = blockIdx.x / tn;
   const int i0 = ti * 64, j0 = tj * 64;
@@ -639,12 +700,14 @@ __global__ void __launch_bounds__(256) k_lr_cwy(const float* Pm, float* rowpart,
   }
 }
 
+// mode 0: scal[4] = min(scal[4], bound / tr(E^T E)); mode 1: scal[5] = the bound itself
+// (+inf when it cannot be formed).
 __global__ void __launch_bounds__(256) k_lr_cwmax(const float* rowpart, int nb, float* scal,
-                                                  const int* list, const int* lcount) {
+                                                  const int* list, const int* lcount, int mode) {
   __shared__ float red[8];
   const int cnt = *lcount;
   for (int cidx = blockIdx.x; cidx < cnt; cidx += gridDim.x) {
-  const int slot = list[cidx];
+  const int slot = list ? list[cidx] : cidx;
   const int tn = (nb + 63) / 64;
   const float* rp = rowpart + (int64_t)slot * nb * (tn + 1);
   float best = 0.f;
@@ -664,8 +727,12 @@ __global__ void __launch_bounds__(256) k_lr_cwmax(const float* rowpart, int nb, 
   if (threadIdx.x == 0) {
     float b = 0.f;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) b = fmaxf(b, red[w]);
-    const float tr = scal[slot * 8 + 2];
-    if (tr > 0.f && isfinite(b)) scal[slot * 8 + 4] = fminf(scal[slot * 8 + 4], b / tr);
+    if (mode == 1) {
+      scal[slot * 8 + 5] = isfinite(b) ? b : __int_as_float(0x7f800000);
+    } else {
+      const float tr = scal[slot * 8 + 2];
+      if (tr > 0.f && isfinite(b)) scal[slot * 8 + 4] = fminf(scal[slot * 8 + 4], b / tr);
+    }
   }
   }
 }
@@ -786,16 +853,19 @@ __device__ __forceinline__ void lr_fallback(int slot, int slots, int* pflag, int
 
 // Counters (counts[]): [0] fallback blocks, [1] appends of the stage being decided,
 // [2] slots left undecided by the trace bound (listed at fall[3 slots ..]), [3] slots
-// left undecided by the stage-0 bounds (listed at fall[2 slots ..]). Stage -1 walks the
-// live slots (count *live), stage 0 the first list, stages 1 and 2 the second.
+// left undecided by the stage-0 bounds (listed at fall[2 slots ..]), [4] the A_f list,
+// [5] slots the Gram bound left to the subspace iteration (fall[5 slots ..]). Stage -1
+// walks that list, stage 0 the trace bound's list, stages 1 and 2 stage 0's.
 __global__ void k_lr_decide(const int* live, int slots, float* scal, const float* sig,
                             const float* dmask, float tau, int* pflag, int* counts, int* fall,
                             const int* live_list, unsigned long long* stats, int stage,
                             int power) {
-  const int count = stage < 0 ? *live : stage == 0 ? counts[2] : counts[3];
+  (void)live;
+  const int count = stage < 0 ? counts[5] : stage == 0 ? counts[2] : counts[3];
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < count;
        idx += gridDim.x * blockDim.x) {
-    const int slot = stage < 0 ? idx : stage == 0 ? fall[3 * slots + idx] : fall[2 * slots + idx];
+    const int slot = stage < 0 ? fall[5 * slots + idx]
+                     : stage == 0 ? fall[3 * slots + idx] : fall[2 * slots + idx];
     const float* sc = scal + slot * 8;
     const float trG = sc[0], c2 = sc[1], trE = sc[2];
     const float lim = tau * tau * (1.f - kCertMargin);
@@ -905,7 +975,7 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
   int* cnt = w.lrCount;
   hipLaunchKernelGGL(k_lr_omega, dim3((nb * P + 255) / 256), dim3(256), 0, st, w.lrOm, nb, P);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, cnt, 5);
+  hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, cnt, 6);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // G = B^T B, gathered straight from the iterate (matrix cores)
   if (gram_ev && (e = hipEventRecord(gram_ev[0], st)) != hipSuccess) return e;
@@ -915,27 +985,56 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
   hipLaunchKernelGGL(k_lr_trace, dim3(slot_grid(S)), dim3(256), 0, st, w.lrG, nb, sG, w.lrScal,
                      0, live);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int tn = (nb + 63) / 64;
+  const int gtiles = tn * tn;
+  const int rgx = (nb + 255) / 256;
+  const int dgrid = (S + 255) / 256;
+  {
+    // zero-output certificate from the Gram matrix alone: the Collatz-Wielandt bound of
+    // |G| (r = |G| 1, bound max_i (|G| r)_i / r_i); the slots it cannot settle go on
+    // to the subspace iteration (fall[5 S ..], counts[5])
+    hipLaunchKernelGGL(k_lr_gabs_rowpart, dim3(gtiles, slot_grid(S, 8192 / gtiles + 1)),
+                       dim3(256), 0, st, w.lrG, nb, w.lrRow, live);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_lr_rsum, dim3(rgx, slot_grid(S, 8192 / rgx + 1)), dim3(256), 0, st,
+                       w.lrRow, nb, nullptr, live);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_lr_cwy, dim3(gtiles, slot_grid(S, 8192 / gtiles + 1)), dim3(256), 0, st,
+                       w.lrG, w.lrRow, nb, nullptr, live);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_lr_cwmax, dim3(slot_grid(S)), dim3(256), 0, st, w.lrRow, nb, w.lrScal,
+                       nullptr, live, 1);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_lr_gram_decide, dim3(dgrid), dim3(256), 0, st, live, S, w.lrScal,
+                       w.lrSig, tau, w.pflag, cnt, w.lrFall, w.stats);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  const int* slist = w.lrFall + 5 * S;
+  const int* scount = cnt + 5;
   auto orth = [&](const float* Yin, float* Xout) -> hipError_t {
     const int gw = slot_grid((S + 3) / 4);
     if (nb <= 128)
-      hipLaunchKernelGGL((k_lr_orth_w<P, 2>), dim3(gw), dim3(256), 0, st, Yin, Xout, nb, sY, live);
+      hipLaunchKernelGGL((k_lr_orth_w<P, 2>), dim3(gw), dim3(256), 0, st, Yin, Xout, nb, sY,
+                         scount, slist);
     else if (nb <= 256)
-      hipLaunchKernelGGL((k_lr_orth_w<P, 4>), dim3(gw), dim3(256), 0, st, Yin, Xout, nb, sY, live);
+      hipLaunchKernelGGL((k_lr_orth_w<P, 4>), dim3(gw), dim3(256), 0, st, Yin, Xout, nb, sY,
+                         scount, slist);
     else if (nb <= 512)
-      hipLaunchKernelGGL((k_lr_orth_w<P, 8>), dim3(gw), dim3(256), 0, st, Yin, Xout, nb, sY, live);
+      hipLaunchKernelGGL((k_lr_orth_w<P, 8>), dim3(gw), dim3(256), 0, st, Yin, Xout, nb, sY,
+                         scount, slist);
     else
       hipLaunchKernelGGL(k_lr_orth_cq<P>, dim3(slot_grid(S)), dim3(1024), 0, st, Yin, Xout, nb,
-                         sY, live);
+                         sY, scount, slist);
     return hipGetLastError();
   };
-  // G X for the slots of a list (or all live slots): barrier-free when nb % 16 == 0
+  // G X for the slots of a list: barrier-free when nb % 16 == 0
   const bool symx = nb % 16 == 0;
   auto gxl = [&](const float* X, int64_t sX, float* Y, const int* dcount, const int* sl) {
     if (symx) return launch_sym_x(w.lrG, sG, nb, X, sX, nb, Y, sY, dcount, S, sl, w.lrSplit, st);
     return launch_sk(SK_DENSE, false, w.lrG, sG, nb, nullptr, g, sh, list, X, sX, nb, nb, Y, sY,
                      dcount, 0, S, sl, nullptr, 1, st);
   };
-  auto gx = [&](const float* X, int64_t sX, float* Y) { return gxl(X, sX, Y, live, nullptr); };
+  auto gx = [&](const float* X, int64_t sX, float* Y) { return gxl(X, sX, Y, scount, slist); };
   // subspace iteration: X0 = orth(G Omega), then X <- orth(G (G X)) three times (seven
   // products by G in total; orthonormalising every second product keeps every
   // direction with sigma > tau / 2 representable while (2 sigma_1 / tau)^4 << 1/eps;
@@ -951,14 +1050,13 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
   // product T^T = G V_r (row-major, lrT), all without touching B again
   if ((e = gx(w.lrX, sY, w.lrW)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_lr_reduced<P>, dim3(slot_grid(S)), dim3(256), 0, st, w.lrX, w.lrW, nb,
-                     w.lrV, w.lrT, w.lrSig, live);
+                     w.lrV, w.lrT, w.lrSig, scount, slist);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   float* mask = w.lrSig + (size_t)S * P;       // second third of the sigma buffer
   float* dmask = w.lrSig + 2 * (size_t)S * P;  // last third
   hipLaunchKernelGGL(k_lr_coupling<P>, dim3(slot_grid(S)), dim3(256), 0, st, w.lrT, w.lrSig,
-                     w.lrV, nb, tau, kCouplingTol, w.lrScal, mask, dmask, live);
+                     w.lrV, nb, tau, kCouplingTol, w.lrScal, mask, dmask, scount, slist);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const int dgrid = (S + 255) / 256;
   // stage -1: the trace bound on lambda_max(E^T E) needs no E^T E; the slots it leaves
   // undecided (fall[3 S ..], counts[2]) get E^T E and its finer bounds
   hipLaunchKernelGGL(k_lr_decide, dim3(dgrid), dim3(256), 0, st, live, S, w.lrScal, w.lrSig,
@@ -974,7 +1072,6 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
   // partials of one slot must fit in its nb x P part of lrY)
   const int tiles = (int)std::min<int64_t>(std::min<int64_t>((sG + 255) / 256, 1024),
                                            (int64_t)nb * P);
-  const int gtiles = ((nb + 63) / 64) * ((nb + 63) / 64);
   {
     // E^T E and its bounds: with W = G V_r (the coupling product, lrT), Q = W - V H / 2
     // with H = V^T W (lrY), E^T E = G - Q V^T - V Q^T (lrP, tile partials in lrQ)
@@ -988,7 +1085,6 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
     hipLaunchKernelGGL(k_lr_ge_reduce, dim3(slot_grid(S)), dim3(256), 0, st, w.lrQ, gtiles,
                        w.lrScal, flist, fcount);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int rgx = (nb + 255) / 256;
     hipLaunchKernelGGL(k_lr_rsum, dim3(rgx, slot_grid(S, 8192 / rgx + 1)), dim3(256), 0, st,
                        w.lrRow, nb, flist, fcount);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -996,7 +1092,7 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
                        w.lrP, w.lrRow, nb, flist, fcount);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_lr_cwmax, dim3(slot_grid(S)), dim3(256), 0, st, w.lrRow, nb, w.lrScal,
-                       flist, fcount);
+                       flist, fcount, 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_lr_decide, dim3(dgrid), dim3(256), 0, st, live, S, w.lrScal, w.lrSig,
                        dmask, tau, w.pflag, cnt, w.lrFall, list, w.stats, 0, 1);

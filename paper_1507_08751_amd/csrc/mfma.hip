@@ -384,8 +384,8 @@ __global__ void __launch_bounds__(256) k_sk(const float* __restrict__ A, int64_t
 // instructions together cover the 16 indices once (a permutation of the sum).
 // Requires M % 16 == 0 and 16-byte aligned rows (lda % 4 == 0). With gridDim.z > 1 the
 // contraction is split into chunks of KC (a multiple of 16) and chunk z writes its
-// partial product to part + (slot * chunks + z) * M * 16 (row-major), summed by k_sk_sum
-// (only without a slot list).
+// partial product to part + (slot * chunks + z) * M * 16 (row-major), summed by
+// k_sk_sum.
 __global__ void __launch_bounds__(256) k_sym_x(const float* __restrict__ A, int64_t sA, int lda,
                                                const float* __restrict__ X, int64_t sX, int M,
                                                float* __restrict__ Y, int64_t sY,
@@ -827,7 +827,7 @@ hipError_t launch_sym_x(const float* A, int64_t sA, int lda, const float* X, int
   const int gx = (M + 63) / 64;
   // matrices 1024 wide or more split the contraction into 256-column chunks (a function
   // of M alone, so a product's rounding does not depend on the slot count)
-  const int chunks = (part && !slot_list && M >= 1024) ? (M + 255) / 256 : 1;
+  const int chunks = (part && M >= 1024) ? (M + 255) / 256 : 1;
   const int KC = chunks > 1 ? 256 : M;
   hipLaunchKernelGGL(k_sym_x, dim3(gx, grid_slots(slots, gx * chunks), chunks), dim3(256), 0, st,
                      A, sA, lda, X, sX, M, Y, sY, dcount, slot_list, part, KC);
@@ -836,7 +836,7 @@ hipError_t launch_sym_x(const float* A, int64_t sA, int lda, const float* X, int
   const int64_t n = (int64_t)M * 16;
   const int sx = (int)std::min<int64_t>((n + 255) / 256, 64);
   hipLaunchKernelGGL(k_sk_sum<0>, dim3(sx, grid_slots(slots, sx)), dim3(256), 0, st, part, chunks,
-                     M, Y, sY, dcount, 0, nullptr);
+                     M, Y, sY, dcount, 0, slot_list);
   return hipGetLastError();
 }
 

@@ -138,6 +138,12 @@ __device__ inline int gcol(const ScaleGeom& g, int q, int j, int sc) {
   return c;
 }
 
+// 64-bit device counters per scale: [0] live blocks, [1] sweeps, [2] output rank,
+// [3] certified, [4] coupling failures, [5] bound failures, [6] undecided by the trace
+// bound, [7] certified by the Collatz-Wielandt bound only, [8] certified zero by the
+// Gram matrix's Collatz-Wielandt bound before the subspace iteration.
+constexpr int kStatsWords = 16;
+
 // Per-scale device buffers and counters.
 struct ScaleWork {
   float* spinAcc;       // averaged cycle spinning: [plane] sum over the shift set
@@ -289,7 +295,8 @@ hipError_t launch_sk(int mode, bool rowmaj, const float* A, int64_t sA, int lda,
                      int64_t sC, const int* dcount, int hcount, int slots, const int* slot_list,
                      float* part, int split, hipStream_t st);
 // Y = A X (M x 16) for symmetric A, barrier-free; needs M % 16 == 0 and lda % 4 == 0.
-// With part (slots x ceil(M / 256) x M x 16 floats), M >= 1024 splits the contraction.
+// With part (slots x ceil(M / 256) x M x 16 floats), M >= 1024 splits the contraction
+// (partials indexed by slot, also under a slot list).
 hipError_t launch_sym_x(const float* A, int64_t sA, int lda, const float* X, int64_t sX, int M,
                         float* Y, int64_t sY, const int* dcount, int slots, const int* slot_list,
                         float* part, hipStream_t st);

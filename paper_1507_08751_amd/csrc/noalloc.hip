@@ -92,7 +92,7 @@ extern "C" msld_status msld_bsvt_noalloc(int32_t M, int32_t N, int32_t m, int32_
     off = up256(off + 4 * nblk * sp.spb);
   }
   const size_t o_stats = off;
-  off = up256(off + 8 * 8);
+  off = up256(off + 8 * kStatsWords);
   if (off > kNoAllocScratch) return MSLD_ETOOLARGE;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return MSLD_EDEVICE;
@@ -114,7 +114,7 @@ extern "C" msld_status msld_bsvt_noalloc(int32_t M, int32_t N, int32_t m, int32_
   float* dual = reinterpret_cast<float*>(base + o_dual);
   // the counters start at zero (a fill kernel; the live count is cleared by the stream
   // pass launch itself)
-  if (launch_fill_ints(reinterpret_cast<int*>(w.stats), 0, 16, st) != hipSuccess)
+  if (launch_fill_ints(reinterpret_cast<int*>(w.stats), 0, 2 * kStatsWords, st) != hipSuccess)
     return MSLD_EDEVICE;
   ShiftSpec sh;
   std::memset(&sh, 0, sizeof(sh));

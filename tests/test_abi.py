@@ -38,7 +38,7 @@ def test_struct_layout_matches_header():
     assert msld.Params.patch_w.offset == base - 64
     assert msld.Params.fork_mode.offset == base
     assert msld.Params.shift_seed.offset % 8 == 0
-    assert ctypes.sizeof(msld.Result) == 4 + 4 + 8 + 8 + 10 * 8 * 16
+    assert ctypes.sizeof(msld.Result) == 4 + 4 + 8 + 8 + 11 * 8 * 16
     assert msld.Result.dual_resid.offset == 16
 
 
