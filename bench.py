@@ -518,16 +518,17 @@ LR_PRODUCTS = 8                 # G X products of its subspace iteration (7) and
 LRS_P, LRS_PRODUCTS = 4, 7      # the fused 32-wide kernel
 
 
-def svd_flops(tier, m, n, live, sweeps, rank):
+def svd_flops(tier, m, n, live, sweeps, rank, gram_certified=0):
     """Algorithmic FP32 flops of one scale's BlockSVT over `live` block-iterations.
 
     Jacobi tiers (register, LDS): per live m x n block (m >= n) and sweep,
     3 n (n - 1) (2m + n) (the dot products and rotations of n (n - 1) / 2 column pairs,
     with V), plus 2 m n k for the rebuild at output rank k; sweeps and ranks are the
-    device counters. Low-rank tiers: the matrix products per live block, the Gram
-    matrix's unique entries m n (n + 1), the subspace products 2 n^2 P each, the
-    projection B X and the rebuild 2 m n P each; the certificate's extra products for
-    undecided blocks are not counted. Skipped blocks count nothing."""
+    device counters. Low-rank tiers: the Gram matrix's unique entries m n (n + 1) per
+    live block, and for the blocks its bound does not settle (live - gram_certified) the
+    subspace products 2 n^2 P each, the projection B X and the rebuild 2 m n P each; the
+    certificate's extra products for undecided blocks are not counted. Skipped blocks
+    count nothing."""
     m, n = max(m, n), min(m, n)
     if tier in ("register", "lds"):
         return sweeps * 3.0 * n * (n - 1) * (2 * m + n) + 2.0 * m * n * rank
@@ -537,7 +538,8 @@ def svd_flops(tier, m, n, live, sweeps, rank):
         P, k = LRS_P, LRS_PRODUCTS
     else:
         return 0.0
-    return live * (m * n * (n + 1.0) + k * 2.0 * n * n * P + 2 * 2.0 * m * n * P)
+    chain = live - gram_certified
+    return live * m * n * (n + 1.0) + chain * (k * 2.0 * n * n * P + 2 * 2.0 * m * n * P)
 
 
 def svd_rooflines(prof, stats, tiers, K):
@@ -555,7 +557,8 @@ def svd_rooflines(prof, stats, tiers, K):
             gflops += live * mm * nn * (nn + 1.0)
             gms += prof["gram_ms"][i]
             launches += K
-        fl = svd_flops(tiers[i], m, n, live, stats["sweeps"][i], stats["rank"][i])
+        fl = svd_flops(tiers[i], m, n, live, stats["sweeps"][i], stats["rank"][i],
+                       stats["gram_certified"][i])
         ms = prof["scale_ms"][i][2] + prof["scale_ms"][i][3]
         tf = fl / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
         per_scale.append({"scale": f"{m}x{n}", "tier": tiers[i],

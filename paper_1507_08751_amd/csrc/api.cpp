@@ -731,7 +731,7 @@ msld_status iterate_once(msld_solver* s, const float* d_Y, int64_t ldY, float* d
                              Dn + MN * i, pl.tau_default[i], shs[i], jacobi_tol(pl.geom[i].mb),
                              40, 20, s->num_cus, scale_stream(s, i),
                              ev ? ev + 4 + kEvPerScale * i : nullptr,
-                             &rls[i], true, &deferred[i]);
+                             &rls[i], true, s->serial ? nullptr : &deferred[i]);
       return;
     }
     // averaged cycle spinning: Z_i stays the input of every shift's Z-step until the
