@@ -979,7 +979,9 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // G = B^T B, gathered straight from the iterate (matrix cores)
   if (gram_ev && (e = hipEventRecord(gram_ev[0], st)) != hipSuccess) return e;
-  if ((e = launch_mf_gram(g, sh, Dout, live, list, S, w.lrG, w.lrSplit, st)) != hipSuccess)
+  bool rows_done = false;
+  if ((e = launch_mf_gram(g, sh, Dout, live, list, S, w.lrG, w.lrSplit, w.lrRow, &rows_done,
+                          st)) != hipSuccess)
     return e;
   if (gram_ev && (e = hipEventRecord(gram_ev[1], st)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_lr_trace, dim3(slot_grid(S)), dim3(256), 0, st, w.lrG, nb, sG, w.lrScal,
@@ -993,9 +995,11 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
     // zero-output certificate from the Gram matrix alone: the Collatz-Wielandt bound of
     // |G| (r = |G| 1, bound max_i (|G| r)_i / r_i); the slots it cannot settle go on
     // to the subspace iteration (fall[5 S ..], counts[5])
-    hipLaunchKernelGGL(k_lr_gabs_rowpart, dim3(gtiles, slot_grid(S, 8192 / gtiles + 1)),
-                       dim3(256), 0, st, w.lrG, nb, w.lrRow, live);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (!rows_done) {   // (else the Gram kernel wrote the per-tile |G| row sums)
+      hipLaunchKernelGGL(k_lr_gabs_rowpart, dim3(gtiles, slot_grid(S, 8192 / gtiles + 1)),
+                         dim3(256), 0, st, w.lrG, nb, w.lrRow, live);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_lr_rsum, dim3(rgx, slot_grid(S, 8192 / rgx + 1)), dim3(256), 0, st,
                        w.lrRow, nb, nullptr, live);
     if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -80,12 +80,15 @@ constexpr int kGLd = 65;   // LDS row pitch of the staged slabs (conflict-free t
 // accumulators (every operand value read from LDS feeds TM / 64 matrix instructions);
 // slabs of KS rows, the next one loaded into registers while the matrix cores work on
 // the current one.
-template <int TM, int KS>
+// TR: the block is stored transposed (g.trans), a template argument so that each
+// orientation's loader keeps only its own registers.
+template <int TM, int KS, int TR>
 __global__ void __launch_bounds__(256) k_mf_gram(const float* __restrict__ Dout, ScaleGeom g,
                                                  ShiftSpec sh, const int* __restrict__ live_count,
                                                  const int* __restrict__ live_list,
                                                  float* __restrict__ G, int64_t sG,
-                                                 float* __restrict__ part, int KC, int chunks) {
+                                                 float* __restrict__ part, int KC, int chunks,
+                                                 float* __restrict__ rowpart) {
   constexpr int LD = TM + 1;           // LDS pitch
   constexpr int QB = TM / 64;          // 32 x 32 blocks per wave and dimension
   constexpr int NL = KS * TM / 256;    // staged elements per thread and operand
@@ -141,7 +144,7 @@ __global__ void __launch_bounds__(256) k_mf_gram(const float* __restrict__ Dout,
         for (int y = 0; y < QB; ++y) acc[x][y] = mfma32(av[x], bv[y], acc[x][y]);
     }
   };
-  if (!g.trans) {
+  if constexpr (!TR) {
     // B(r, c) = stored (r, c): a slab row is contiguous along c; thread column
     // cc = tid % TM, rows tid / TM + (256 / TM) u
     constexpr int RS = 256 / TM;
@@ -232,6 +235,23 @@ __global__ void __launch_bounds__(256) k_mf_gram(const float* __restrict__ Dout,
     }
     __syncthreads();
     const int ib = i0 + h * 64;
+    if (rowpart && TM == 64) {
+      // |G| row sums of this tile (slice tj, rows ib..) and, for an off-diagonal tile, of
+      // its mirror (column sums: slice ti, rows j0..), for the Gram bound of the low-rank
+      // path; fixed summation order
+      const int tn = (nb + 63) / 64;
+      float* rp = rowpart + (int64_t)slot * nb * (tn + 1);
+      if (tid < 64 && ib + tid < nb) {
+        float a = 0.f;
+        for (int jj = 0; jj < 64; ++jj) a += fabsf(T[tid * LD + jj]);
+        rp[(int64_t)tj * nb + ib + tid] = a;
+      } else if (!diag && tid >= 64 && tid < 128 && j0 + tid - 64 < nb) {
+        const int cc = tid - 64;
+        float a = 0.f;
+        for (int ii = 0; ii < 64; ++ii) a += fabsf(T[ii * LD + cc]);
+        rp[(int64_t)ti * nb + j0 + cc] = a;
+      }
+    }
     for (int e = tid; e < 64 * TM; e += 256) {
       const int jj = e >> 6, ii = e & 63;   // element (ib + ii, j0 + jj)
       if (ib + ii < nb && j0 + jj < nb) dst[(int64_t)(j0 + jj) * nb + ib + ii] = T[ii * LD + jj];
@@ -531,13 +551,15 @@ __global__ void __launch_bounds__(256) k_sk_sum(const float* __restrict__ part, 
 // 64 x 64 tiles, slabs of 32 along K, four waves on v_mfma_f32_32x32x2f32.
 // SYM (with TA = 1, B = A, M = N): C = A^T A, only the tiles with i0 <= j0 are formed
 // (blockIdx.x enumerates the upper triangle) and each is also written mirrored, so C is
-// exactly symmetric.
+// exactly symmetric. With gridDim.z > 1 (never with SYM) the contraction is split into
+// chunks of KC and chunk z writes its partial product to part + (c chunks + z) M N
+// (column-major, ld M), summed by k_gemm_sum.
 template <int TA, int SYM = 0>
 __global__ void __launch_bounds__(256) k_gemm(const float* __restrict__ A, int lda, int64_t sa,
                                               const float* __restrict__ B, int ldb, int64_t sb,
                                               float* __restrict__ C, int ldc, int64_t sc, int M,
                                               int N, int K, const int* __restrict__ dcount,
-                                              int hcount) {
+                                              int hcount, float* __restrict__ part, int KC) {
   __shared__ float sm[64 * kGLd];   // As[k][i] then Bs[k][j]; the output tile at the end
   float* As = sm;
   float* Bs = sm + 32 * kGLd;
@@ -556,20 +578,22 @@ __global__ void __launch_bounds__(256) k_gemm(const float* __restrict__ A, int l
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wi = wv & 1, wj = wv >> 1;
   const int count = dev_count(dcount, hcount);
+  const int chunks = gridDim.z, ch = blockIdx.z;
+  const int k0 = ch * KC, k1 = min(K, k0 + KC);
   for (int c = blockIdx.y; c < count; c += gridDim.y) {
     const float* a = A + (int64_t)c * sa;
     const float* b = B + (int64_t)c * sb;
     f32x16 acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.f;
-    for (int kb = 0; kb < K; kb += 32) {
+    for (int kb = k0; kb < k1; kb += 32) {
       if (!TA) {
         const int ii = tid & 63;
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const int kk = (tid >> 6) + 4 * u;
           const int i = i0 + ii, k = kb + kk;
-          As[kk * kGLd + ii] = (i < M && k < K) ? a[(int64_t)k * lda + i] : 0.f;
+          As[kk * kGLd + ii] = (i < M && k < k1) ? a[(int64_t)k * lda + i] : 0.f;
         }
       } else {
         const int kk = tid & 31;
@@ -577,7 +601,7 @@ __global__ void __launch_bounds__(256) k_gemm(const float* __restrict__ A, int l
         for (int u = 0; u < 8; ++u) {
           const int ii = (tid >> 5) + 8 * u;
           const int i = i0 + ii, k = kb + kk;
-          As[kk * kGLd + ii] = (i < M && k < K) ? a[(int64_t)i * lda + k] : 0.f;
+          As[kk * kGLd + ii] = (i < M && k < k1) ? a[(int64_t)i * lda + k] : 0.f;
         }
       }
       {
@@ -586,7 +610,7 @@ __global__ void __launch_bounds__(256) k_gemm(const float* __restrict__ A, int l
         for (int u = 0; u < 8; ++u) {
           const int jj = (tid >> 5) + 8 * u;
           const int j = j0 + jj, k = kb + kk;
-          Bs[kk * kGLd + jj] = (j < N && k < K) ? b[(int64_t)j * ldb + k] : 0.f;
+          Bs[kk * kGLd + jj] = (j < N && k < k1) ? b[(int64_t)j * ldb + k] : 0.f;
         }
       }
       __syncthreads();
@@ -606,10 +630,11 @@ __global__ void __launch_bounds__(256) k_gemm(const float* __restrict__ A, int l
       T[ii * kGLd + jj] = acc[r];
     }
     __syncthreads();
-    float* cc = C + (int64_t)c * sc;
+    float* cc = chunks > 1 ? part + ((int64_t)c * chunks + ch) * M * N : C + (int64_t)c * sc;
+    const int ldo = chunks > 1 ? M : ldc;
     for (int e = tid; e < 64 * 64; e += 256) {
       const int jj = e >> 6, ii = e & 63;
-      if (i0 + ii < M && j0 + jj < N) cc[(int64_t)(j0 + jj) * ldc + i0 + ii] = T[ii * kGLd + jj];
+      if (i0 + ii < M && j0 + jj < N) cc[(int64_t)(j0 + jj) * ldo + i0 + ii] = T[ii * kGLd + jj];
     }
     if (SYM && i0 != j0)
       for (int e = tid; e < 64 * 64; e += 256) {
@@ -734,7 +759,7 @@ int gram_tile() {
 
 hipError_t launch_mf_gram(const ScaleGeom& g, const ShiftSpec& sh, const float* Dout,
                           const int* live_count, const int* live_list, int slots, float* G,
-                          float* part, hipStream_t st) {
+                          float* part, float* rowpart, bool* rows_done, hipStream_t st) {
   const int nb = g.nb, mb = g.mb;
   const int var = gram_tile();
   const int TM = var == 2 ? 128 : 64, KS = var == 1 ? 64 : 32;
@@ -750,15 +775,25 @@ hipError_t launch_mf_gram(const ScaleGeom& g, const ShiftSpec& sh, const float* 
   const int64_t nwg = groups * 8 * tri;
   if (nwg > 0x7fffffff) return hipErrorInvalidValue;
   const int64_t sG = (int64_t)nb * nb;
+  // the |G| row sums come with the tiles when the tiles are final (no split) and 64 wide
+  float* rp = (chunks == 1 && TM == 64) ? rowpart : nullptr;
+  if (rows_done) *rows_done = rp != nullptr;
+#define MSLD_GRAM(tm, ks, rpp)                                                                \
+  do {                                                                                        \
+    if (g.trans)                                                                              \
+      hipLaunchKernelGGL((k_mf_gram<tm, ks, 1>), dim3((unsigned)nwg), dim3(256), 0, st, Dout, \
+                         g, sh, live_count, live_list, G, sG, part, KC, chunks, rpp);         \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_mf_gram<tm, ks, 0>), dim3((unsigned)nwg), dim3(256), 0, st, Dout, \
+                         g, sh, live_count, live_list, G, sG, part, KC, chunks, rpp);         \
+  } while (0)
   if (var == 0)
-    hipLaunchKernelGGL((k_mf_gram<64, 32>), dim3((unsigned)nwg), dim3(256), 0, st, Dout, g, sh,
-                       live_count, live_list, G, sG, part, KC, chunks);
+    MSLD_GRAM(64, 32, rp);
   else if (var == 1)
-    hipLaunchKernelGGL((k_mf_gram<64, 64>), dim3((unsigned)nwg), dim3(256), 0, st, Dout, g, sh,
-                       live_count, live_list, G, sG, part, KC, chunks);
+    MSLD_GRAM(64, 64, rp);
   else
-    hipLaunchKernelGGL((k_mf_gram<128, 32>), dim3((unsigned)nwg), dim3(256), 0, st, Dout, g, sh,
-                       live_count, live_list, G, sG, part, KC, chunks);
+    MSLD_GRAM(128, 32, nullptr);
+#undef MSLD_GRAM
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || chunks == 1) return e;
   const int gx = (int)std::min<int64_t>((sG + 255) / 256, 1024);
@@ -847,22 +882,57 @@ hipError_t launch_syrk(int M, int K, const float* A, int lda, int64_t sa, float*
   const int tiles = tm * (tm + 1) / 2;
   const dim3 grid(tiles, grid_slots(max_count, tiles));
   hipLaunchKernelGGL((k_gemm<1, 1>), grid, dim3(256), 0, st, A, lda, sa, A, lda, sa, C, ldc, sc, M,
-                     M, K, dcount, hcount);
+                     M, K, dcount, hcount, nullptr, K);
   return hipGetLastError();
+}
+
+// C[c] (column-major, ldc) = sum over the chunks of k_gemm's partial products, in order.
+__global__ void __launch_bounds__(256) k_gemm_sum(const float* __restrict__ part, int chunks,
+                                                  int M, int N, float* __restrict__ C, int ldc,
+                                                  int64_t sc, const int* __restrict__ dcount,
+                                                  int hcount) {
+  const int count = dev_count(dcount, hcount);
+  const int64_t n = (int64_t)M * N;
+  for (int c = blockIdx.y; c < count; c += gridDim.y)
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+      const float* p = part + (int64_t)c * chunks * n + e;
+      float s = 0.f;
+      for (int ch = 0; ch < chunks; ++ch) s += p[(int64_t)ch * n];
+      const int64_t j = e / M, i = e - (e / M) * M;
+      C[(int64_t)c * sc + j * ldc + i] = s;
+    }
 }
 
 hipError_t launch_gemm(bool ta, int M, int N, int K, const float* A, int lda, int64_t sa,
                        const float* B, int ldb, int64_t sb, float* C, int ldc, int64_t sc,
-                       const int* dcount, int hcount, int max_count, hipStream_t st) {
+                       const int* dcount, int hcount, int max_count, hipStream_t st, float* part,
+                       int64_t part_floats) {
   if (max_count <= 0) return hipSuccess;
   const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
-  const dim3 grid(tiles, grid_slots(max_count, tiles));
+  // few output tiles and a long contraction: split it into chunks of 128 or more (a
+  // function of the shape alone), when the partial products fit in part
+  int chunks = 1;
+  if (part && tiles < 128 && K >= 256) {
+    chunks = std::min(K / 128, 8);
+    while (chunks > 1 && (int64_t)chunks * M * N * max_count > part_floats) --chunks;
+  }
+  int KC = (K + chunks - 1) / chunks;
+  KC = (KC + 31) / 32 * 32;
+  chunks = (K + KC - 1) / KC;
+  const dim3 grid(tiles, grid_slots(max_count, tiles * chunks), chunks);
   if (ta)
     hipLaunchKernelGGL(k_gemm<1>, grid, dim3(256), 0, st, A, lda, sa, B, ldb, sb, C, ldc, sc, M,
-                       N, K, dcount, hcount);
+                       N, K, dcount, hcount, part, KC);
   else
     hipLaunchKernelGGL(k_gemm<0>, grid, dim3(256), 0, st, A, lda, sa, B, ldb, sb, C, ldc, sc, M,
-                       N, K, dcount, hcount);
+                       N, K, dcount, hcount, part, KC);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || chunks == 1) return e;
+  const int64_t n = (int64_t)M * N;
+  const int gx = (int)std::min<int64_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_gemm_sum, dim3(gx, grid_slots(max_count, gx)), dim3(256), 0, st, part,
+                     chunks, M, N, C, ldc, sc, dcount, hcount);
   return hipGetLastError();
 }
 

@@ -282,11 +282,13 @@ enum SkMode { SK_DENSE = 0, SK_B = 1, SK_BT = 2 };
 // Row chunks of the split contractions of tall blocks (1: no split); depends on the
 // block shape only. A split needs slots * chunks * nb * nb floats of partial sums.
 int split_chunks(int mb, int nb);
-// G = B^T B of the live blocks, B gathered from V = -Dout (tall blocks split their rows
-// over part when it is given).
+// G = B^T B of the live blocks, B gathered from V = -Dout (tall and wide blocks split
+// their rows over part when it is given). With rowpart, unsplit 64-wide tiles also write
+// the per-tile |G| row sums (the layout of the Collatz-Wielandt steps); *rows_done says
+// whether they did.
 hipError_t launch_mf_gram(const ScaleGeom& g, const ShiftSpec& sh, const float* Dout,
                           const int* live_count, const int* live_list, int slots, float* G,
-                          float* part, hipStream_t st);
+                          float* part, float* rowpart, bool* rows_done, hipStream_t st);
 // C (M x 16) = A (M x K) X (K x 16): A dense column-major (SK_DENSE), the gathered
 // block B (SK_B) or B^T (SK_BT); C column-major or row-major (rowmaj).
 hipError_t launch_sk(int mode, bool rowmaj, const float* A, int64_t sA, int lda,
@@ -304,10 +306,12 @@ hipError_t launch_sym_x(const float* A, int64_t sA, int lda, const float* X, int
 // and mirrored), batch entries c < count.
 hipError_t launch_syrk(int M, int K, const float* A, int lda, int64_t sa, float* C, int ldc,
                        int64_t sc, const int* dcount, int hcount, int max_count, hipStream_t st);
-// C = op(A) B, column-major, batch entries c < count.
+// C = op(A) B, column-major, batch entries c < count. With part (part_floats floats), a
+// product with few output tiles splits its contraction (partials summed in order).
 hipError_t launch_gemm(bool ta, int M, int N, int K, const float* A, int lda, int64_t sa,
                        const float* B, int ldb, int64_t sb, float* C, int ldc, int64_t sc,
-                       const int* dcount, int hcount, int max_count, hipStream_t st);
+                       const int* dcount, int hcount, int max_count, hipStream_t st,
+                       float* part = nullptr, int64_t part_floats = 0);
 // Z = A_f diag(gains) V_r^T of the certified slots among slot_list[0 .. *count) (all
 // slots < *count when the list is null), scattered with D' = 2 Z' - V.
 hipError_t launch_mf_rebuild(const ScaleGeom& g, const ShiftSpec& sh, float* Zout, float* Dout,

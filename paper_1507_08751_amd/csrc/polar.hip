@@ -252,6 +252,10 @@ hipError_t run_polar(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout,
   const int tilesX = (int)std::min<int64_t>((sX + 1023) / 1024, 256);
   const int tilesN = (int)std::min<int64_t>((sN + 1023) / 1024, 256);
   const int tilesZ = ((g.m + 31) / 32) * ((g.n + 31) / 32);
+  // one block at a time uses slot 0 of the chunk buffers; the rest of the X0 buffer holds
+  // the split partial products of its GEMMs
+  float* part = w.plCap > 1 ? w.plX0 + sX : nullptr;
+  const int64_t pfl = w.plCap > 1 ? (int64_t)(w.plCap - 1) * sX : 0;
   // one failed block at a time: its step counts K and J then depend on that block
   // alone, so its result is the same whatever other blocks failed beside it (alone or
   // in a batch); failures are rare
@@ -281,18 +285,18 @@ hipError_t run_polar(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout,
     const float* X = w.plX0;
     float* Xn = w.plXa;
     for (int k = 0; k < K; ++k) {
-      if ((e = launch_gemm(true, nb, nb, mb, X, mb, sX, X, mb, sX, w.plT, nb, sN, nullptr, cnt, cnt, st)) != hipSuccess)
+      if ((e = launch_gemm(true, nb, nb, mb, X, mb, sX, X, mb, sX, w.plT, nb, sN, nullptr, cnt, cnt, st, part, pfl)) != hipSuccess)
         return e;
       hipLaunchKernelGGL(k_pl_affine, dim3(tilesN, cnt), dim3(256), 0, st, w.plT, nb, 1.5f,
                          -0.5f);
       if ((e = last()) != hipSuccess) return e;
-      if ((e = launch_gemm(false, mb, nb, nb, X, mb, sX, w.plT, nb, sN, Xn, mb, sX, nullptr, cnt, cnt, st)) != hipSuccess)
+      if ((e = launch_gemm(false, mb, nb, nb, X, mb, sX, w.plT, nb, sN, Xn, mb, sX, nullptr, cnt, cnt, st, part, pfl)) != hipSuccess)
         return e;
       X = Xn;
       Xn = (Xn == w.plXa) ? w.plXb : w.plXa;
     }
     // H = Q^T (E' / alpha); S = alpha sym(H) - tau I; Y0 = S / alpha_S
-    if ((e = launch_gemm(true, nb, nb, mb, X, mb, sX, w.plX0, mb, sX, w.plT, nb, sN, nullptr, cnt, cnt, st)) != hipSuccess)
+    if ((e = launch_gemm(true, nb, nb, mb, X, mb, sX, w.plX0, mb, sX, w.plT, nb, sN, nullptr, cnt, cnt, st, part, pfl)) != hipSuccess)
       return e;
     hipLaunchKernelGGL(k_pl_shift, dim3(tilesN, cnt), dim3(256), 0, st, w.plT, w.plS, w.plY, nb,
                        tau, w.plScal);
@@ -301,21 +305,21 @@ hipError_t run_polar(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout,
     float* Y = w.plY;
     float* Yn = w.plT;
     for (int j = 0; j < J; ++j) {
-      if ((e = launch_gemm(false, nb, nb, nb, Y, nb, sN, Y, nb, sN, w.plW, nb, sN, nullptr, cnt, cnt, st)) != hipSuccess)
+      if ((e = launch_gemm(false, nb, nb, nb, Y, nb, sN, Y, nb, sN, w.plW, nb, sN, nullptr, cnt, cnt, st, part, pfl)) != hipSuccess)
         return e;
       hipLaunchKernelGGL(k_pl_affine, dim3(tilesN, cnt), dim3(256), 0, st, w.plW, nb, 1.5f,
                          -0.5f);
       if ((e = last()) != hipSuccess) return e;
-      if ((e = launch_gemm(false, nb, nb, nb, Y, nb, sN, w.plW, nb, sN, Yn, nb, sN, nullptr, cnt, cnt, st)) != hipSuccess)
+      if ((e = launch_gemm(false, nb, nb, nb, Y, nb, sN, w.plW, nb, sN, Yn, nb, sN, nullptr, cnt, cnt, st, part, pfl)) != hipSuccess)
         return e;
       std::swap(Y, Yn);
     }
     // (S)_+ = S (I + Y) / 2, then Ze = Q (S)_+ into the X0 buffer
     hipLaunchKernelGGL(k_pl_affine, dim3(tilesN, cnt), dim3(256), 0, st, Y, nb, 0.5f, 0.5f);
     if ((e = last()) != hipSuccess) return e;
-    if ((e = launch_gemm(false, nb, nb, nb, w.plS, nb, sN, Y, nb, sN, w.plW, nb, sN, nullptr, cnt, cnt, st)) != hipSuccess)
+    if ((e = launch_gemm(false, nb, nb, nb, w.plS, nb, sN, Y, nb, sN, w.plW, nb, sN, nullptr, cnt, cnt, st, part, pfl)) != hipSuccess)
       return e;
-    if ((e = launch_gemm(false, mb, nb, nb, X, mb, sX, w.plW, nb, sN, Xn, mb, sX, nullptr, cnt, cnt, st)) != hipSuccess)
+    if ((e = launch_gemm(false, mb, nb, nb, X, mb, sX, w.plW, nb, sN, Xn, mb, sX, nullptr, cnt, cnt, st, part, pfl)) != hipSuccess)
       return e;
     hipLaunchKernelGGL(k_pl_rebuild<P>, dim3(tilesZ, cnt), dim3(256), 0, st, Zout, Dout, g, sh,
                        w.live_list, fslot, c0, w.lrC, w.lrV, w.lrSig, mask, tau, Xn, w.plScal);
