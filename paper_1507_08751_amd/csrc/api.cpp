@@ -287,7 +287,10 @@ msld_status make_plan(const msld_params* p, int ninst, Plan* pl) {
           if (cap < 1) cap = 1;
           if (cap > (size_t)nblk) cap = (size_t)nblk;
           pl->pl_cap[i] = (int)cap;
-          pl->off_pl[i] = take(4 * cap * pper);
+          // plus the split partial products of its GEMMs (one block at a time, at most 8
+          // chunks of an mb x nb product): sized by the block shape alone, so the split
+          // is the same whatever the slot count
+          pl->off_pl[i] = take(4 * (cap * pper + 8 * (size_t)g.mb * g.nb));
         }
       }
     }
@@ -543,7 +546,8 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
           w.plS = q; q += cap * nb2;
           w.plY = q; q += cap * nb2;
           w.plW = q; q += cap * nb2;
-          w.plScal = q;
+          w.plScal = q; q += 4 * cap;
+          w.plPart = q;
           size_t hoff = 0;
           for (int i2 = 0; i2 < i; ++i2) hoff += 4 * (size_t)pl.pl_cap[i2];
           w.hostPl = s->host_pl + hoff;

@@ -241,6 +241,35 @@ __global__ void __launch_bounds__(NT) k_lr_small(float* __restrict__ Zout,
       t = bsum<NT>(t, red);
       if (tid == 0) s_trG = t;
     }
+    {
+      // zero-output certificate from the Gram matrix alone: sigma_max(B)^2 is at most the
+      // Collatz-Wielandt bound of |G| (r = |G| 1, max_i (|G| r)_i / r_i); below tau^2
+      // (with the margin) the SVT is zero, which the stream pass already wrote. r goes
+      // to Xs, free until the probe is drawn.
+      for (int i = tid; i < NB; i += NT) {
+        float r = 0.f;
+        for (int j = 0; j < NB; ++j) r += fabsf(Gs[j * LDG + i]);
+        Xs[i] = r;
+      }
+      __syncthreads();
+      float best = 0.f;
+      for (int i = tid; i < NB; i += NT) {
+        float y = 0.f;
+        for (int j = 0; j < NB; ++j) y += fabsf(Gs[j * LDG + i]) * Xs[j];
+        const float ri = Xs[i];
+        if (ri > 0.f) best = fmaxf(best, y / ri);
+        else if (y > 0.f) best = __int_as_float(0x7f800000);
+      }
+      best = bmax<NT>(best, red);   // the same value in every thread
+      if (best <= lim && isfinite(best)) {
+        if (tid == 0) {
+          atomicAdd(&stats[0], 1ull);
+          atomicAdd(&stats[3], 1ull);
+          atomicAdd(&stats[8], 1ull);
+        }
+        continue;
+      }
+    }
     // X0 = orth(G Omega), Omega = fixed +-1 probe
     for (int o = tid; o < NB * P; o += NT) {
       const uint64_t z = mix64(0x243F6A8885A308D3ull + (uint64_t)o);

@@ -294,7 +294,7 @@ __global__ void __launch_bounds__(256) k_gram_sum(const float* __restrict__ part
 // product (row-major, M x 16) to part + (slot * chunks + c) * M * 16, summed by k_sk_sum.
 // Slot c of the walk is slot_list[c] when a list is given (slots of the undecided
 // list), else c.
-template <int MODE, int ROWMAJ>
+template <int MODE, int ROWMAJ, int TR>
 __global__ void __launch_bounds__(256) k_sk(const float* __restrict__ A, int64_t sA, int lda,
                                             const float* __restrict__ Dout, ScaleGeom g,
                                             ShiftSpec sh, const int* __restrict__ live_list,
@@ -311,7 +311,8 @@ __global__ void __launch_bounds__(256) k_sk(const float* __restrict__ A, int64_t
   const int k0 = ch * KC, k1 = min(K, k0 + KC);
   const int count = dev_count(dcount, hcount);
   // which index of the A tile runs along memory: "k-major" loads map lanes to k
-  const bool kmajor = MODE == SK_B ? !g.trans : MODE == SK_BT ? g.trans : false;
+  // (TR = g.trans, a template argument so that each orientation keeps its own registers)
+  constexpr bool kmajor = MODE == SK_B ? !TR : MODE == SK_BT ? (TR != 0) : false;
   for (int cidx = blockIdx.y; cidx < count; cidx += gridDim.y) {
     const int slot = slot_list ? slot_list[cidx] : cidx;
     BlockAt b;
@@ -324,7 +325,7 @@ __global__ void __launch_bounds__(256) k_sk(const float* __restrict__ A, int64_t
     int64_t ro[16];
     int cfix = 0;
     if (MODE != SK_DENSE) {
-      if (kmajor) {
+      if constexpr (kmajor) {
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
           const int i = i0 + (tid >> 6) + 4 * u;
@@ -339,7 +340,7 @@ __global__ void __launch_bounds__(256) k_sk(const float* __restrict__ A, int64_t
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[r] = 0.f;
     for (int kb = k0; kb < k1; kb += 64) {
-      if (MODE == SK_DENSE || !kmajor) {
+      if constexpr (MODE == SK_DENSE || !kmajor) {
         // lanes along i: column-major dense A, or gathers whose stored rows are k
         const int ii = tid & 63;
         const int i = i0 + ii;
@@ -653,7 +654,7 @@ __global__ void __launch_bounds__(256) k_gemm(const float* __restrict__ A, int l
 // v_mfma_f32_32x32x2f32 with K = P: D(i, j) = sum_l U(i, l) W(j, l) with U(i, l) the
 // factor of stored row i and W(j, l) that of stored column j; an accumulator's lanes
 // run along stored columns, so each write is a contiguous row segment.
-template <int P>
+template <int P, int TR>
 __global__ void __launch_bounds__(256) k_mf_rebuild(float* __restrict__ Zout,
                                                     float* __restrict__ Dout, ScaleGeom g,
                                                     ShiftSpec sh, const int* __restrict__ count_p,
@@ -700,8 +701,8 @@ __global__ void __launch_bounds__(256) k_mf_rebuild(float* __restrict__ Zout,
     for (int kk = 0; kk < P; kk += 2) {
       const int l = kk + (lane >> 5);
       float urow = 0.f, wcol = 0.f;
-      if (i < m) urow = g.trans ? vr[(int64_t)l * nb + i] : af[(int64_t)l * mb + i] * gl[l];
-      if (j < n) wcol = g.trans ? af[(int64_t)l * mb + j] * gl[l] : vr[(int64_t)l * nb + j];
+      if (i < m) urow = TR ? vr[(int64_t)l * nb + i] : af[(int64_t)l * mb + i] * gl[l];
+      if (j < n) wcol = TR ? af[(int64_t)l * mb + j] * gl[l] : vr[(int64_t)l * nb + j];
       acc = mfma32(urow, wcol, acc);
     }
     // accumulator r: stored row i0 + wi 32 + 8 (r / 4) + 4 (lane / 32) + r % 4, stored
@@ -831,9 +832,15 @@ hipError_t launch_sk(int mode, bool rowmaj, const float* A, int64_t sA, int lda,
     }
     chunks = ch16;
   } else {
-#define MSLD_SK(md, rm)                                                                          \
-  hipLaunchKernelGGL((k_sk<md, rm>), grid, dim3(256), 0, st, A, sA, lda, Dout, g, sh, live_list, \
-                     X, sX, M, K, C, sC, dcount, hcount, slot_list, part, KC)
+#define MSLD_SK(md, rm)                                                                         \
+  do {                                                                                          \
+    if (md != SK_DENSE && g.trans)                                                              \
+      hipLaunchKernelGGL((k_sk<md, rm, 1>), grid, dim3(256), 0, st, A, sA, lda, Dout, g, sh,     \
+                         live_list, X, sX, M, K, C, sC, dcount, hcount, slot_list, part, KC);   \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_sk<md, rm, 0>), grid, dim3(256), 0, st, A, sA, lda, Dout, g, sh,     \
+                         live_list, X, sX, M, K, C, sC, dcount, hcount, slot_list, part, KC);   \
+  } while (0)
   if (mode == SK_DENSE) {
     if (rowmaj) MSLD_SK(SK_DENSE, 1); else MSLD_SK(SK_DENSE, 0);
   } else if (mode == SK_B) {
@@ -911,11 +918,11 @@ hipError_t launch_gemm(bool ta, int M, int N, int K, const float* A, int lda, in
   if (max_count <= 0) return hipSuccess;
   const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
   // few output tiles and a long contraction: split it into chunks of 128 or more (a
-  // function of the shape alone), when the partial products fit in part
+  // function of the shape alone; a part too small for that split means no split)
   int chunks = 1;
   if (part && tiles < 128 && K >= 256) {
     chunks = std::min(K / 128, 8);
-    while (chunks > 1 && (int64_t)chunks * M * N * max_count > part_floats) --chunks;
+    if ((int64_t)chunks * M * N * max_count > part_floats) chunks = 1;
   }
   int KC = (K + chunks - 1) / chunks;
   KC = (KC + 31) / 32 * 32;
@@ -1040,9 +1047,14 @@ hipError_t launch_mf_rebuild(const ScaleGeom& g, const ShiftSpec& sh, float* Zou
                              int slots, const int* pflag, const float* Af, const float* Vr,
                              const float* sig, const float* mask, float tau, hipStream_t st) {
   const int tiles = ((g.m + 63) / 64) * ((g.n + 63) / 64);
-  hipLaunchKernelGGL(k_mf_rebuild<16>, dim3(tiles, grid_slots(slots, tiles)), dim3(256), 0, st,
-                     Zout, Dout, g, sh, count, slot_list, live_list, pflag, Af, Vr, sig, mask,
-                     tau);
+  if (g.trans)
+    hipLaunchKernelGGL((k_mf_rebuild<16, 1>), dim3(tiles, grid_slots(slots, tiles)), dim3(256), 0,
+                       st, Zout, Dout, g, sh, count, slot_list, live_list, pflag, Af, Vr, sig,
+                       mask, tau);
+  else
+    hipLaunchKernelGGL((k_mf_rebuild<16, 0>), dim3(tiles, grid_slots(slots, tiles)), dim3(256), 0,
+                       st, Zout, Dout, g, sh, count, slot_list, live_list, pflag, Af, Vr, sig,
+                       mask, tau);
   return hipGetLastError();
 }
 

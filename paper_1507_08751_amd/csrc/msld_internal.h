@@ -194,6 +194,7 @@ struct ScaleWork {
   // polar fallback (polar.hip) for failed certificates of blocks beyond the LDS tier;
   // buffers hold plCap compacted blocks
   int plCap;
+  float* plPart;        // [8][mb*nb] split partial products of the polar route's GEMMs
   float* plX0;          // [plCap][mb*nb] E' / alpha, later the thresholded block
   float* plXa;          // [plCap][mb*nb] Newton-Schulz iterates
   float* plXb;

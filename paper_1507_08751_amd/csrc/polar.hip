@@ -252,10 +252,10 @@ hipError_t run_polar(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout,
   const int tilesX = (int)std::min<int64_t>((sX + 1023) / 1024, 256);
   const int tilesN = (int)std::min<int64_t>((sN + 1023) / 1024, 256);
   const int tilesZ = ((g.m + 31) / 32) * ((g.n + 31) / 32);
-  // one block at a time uses slot 0 of the chunk buffers; the rest of the X0 buffer holds
-  // the split partial products of its GEMMs
-  float* part = w.plCap > 1 ? w.plX0 + sX : nullptr;
-  const int64_t pfl = w.plCap > 1 ? (int64_t)(w.plCap - 1) * sX : 0;
+  // split partial products of the GEMMs (8 mb nb floats: every split launch_gemm chooses
+  // for these shapes fits, so the split depends on the shapes alone)
+  float* part = w.plPart;
+  const int64_t pfl = 8 * sX;
   // one failed block at a time: its step counts K and J then depend on that block
   // alone, so its result is the same whatever other blocks failed beside it (alone or
   // in a batch); failures are rare
