@@ -249,11 +249,7 @@ __global__ void __launch_bounds__(1024) k_lr_orth_cq(const float* Y, float* X, i
   }
 }
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
+__device__ __forceinline__ float wave_sum(float v) { return wave_sum_dpp(v); }
 
 // Orthonormalisation with one wave per slot and the columns held in registers
 // (lane l owns rows l + 64 r, r < RPL): no LDS and no workgroup barriers. Classical

@@ -25,11 +25,7 @@ namespace {
 constexpr float kSmallCertMargin = 2e-3f;    // relative margin on tau^2
 constexpr float kSmallCouplingTol = 1e-5f;   // sum_L c_l^2 <= tol^2 ||B||_F^2
 
-__device__ __forceinline__ float wsum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
+__device__ __forceinline__ float wsum(float v) { return wave_sum_dpp(v); }
 
 template <int NT>
 __device__ __forceinline__ float bsum(float v, float* red) {

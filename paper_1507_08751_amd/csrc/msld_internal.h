@@ -64,6 +64,28 @@ __device__ inline bool jacobi_rotates(float ga, float al, float be, float tol) {
   return fabsf(ga) > tol * __builtin_amdgcn_sqrtf(al) * __builtin_amdgcn_sqrtf(be);
 }
 
+// Sum over the 64 lanes of a wave, returned to every lane, with DPP lane moves (register
+// to register) rather than LDS permutes: pairs, quads, 8-lane halves and 16-lane rows by
+// quad_perm / row_half_mirror / row_mirror (every lane of a row then holds the row's
+// sum), rows 1 and 3 add the preceding row's sum (row_bcast:15), rows 2 and 3 the sum of
+// rows 0-1 (row_bcast:31); lane 63 ends with the total, which readlane broadcasts.
+// Every lane of the wave must be active.
+__device__ inline float wave_sum_dpp(float v) {
+  int x = __float_as_int(v);
+  v = v + __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+  x = __float_as_int(v);
+  v = v + __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+  x = __float_as_int(v);
+  v = v + __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x141, 0xF, 0xF, false));  // row_half_mirror
+  x = __float_as_int(v);
+  v = v + __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x140, 0xF, 0xF, false));  // row_mirror
+  x = __float_as_int(v);
+  v = v + __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false));  // row_bcast:15
+  x = __float_as_int(v);
+  v = v + __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false));  // row_bcast:31
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 // One-sided Jacobi rotation of columns with squared norms al, be and inner product ga
 // (p' = c p - s q, q' = s p + c q): tan t of the smaller angle from zeta = (be - al) /
 // (2 ga), formed with the hardware reciprocal, square root and reciprocal square root
