@@ -25,9 +25,13 @@ if ROOT not in sys.path:
 # streams only run side by side on hardware queues of their own, and HIP's default of
 # 4 queues per process puts several of them on one. More queues also make every
 # HBM-bound launch about 10% slower here, so the 8192^2 run keeps HIP's 4 (same
-# iteration rate, faster stream pass) and the batch, serving, spinning, video and
-# completion runs take 16. HIP reads the count once, when it initialises, so main()
-# sets it (--hw-queues) before anything imports torch.
+# iteration rate, faster stream pass). The batch of 256 instances also runs fastest on 4
+# (492 solves/s, against 421 on 2, 321 on 8 and 337 on 16); serving, spinning, video and
+# completion take 16 (averaged spinning 308 against 202 iters/s on 4, serving saturates
+# at 2.72 against 2.35 solves/s). A batch-mode run with a single queue ended in a host
+# segmentation fault during start-up, so at least 2 are required. HIP reads the count
+# once, when it initialises, so main() sets it (--hw-queues) before anything imports
+# torch.
 HW_QUEUES = 4
 
 METRIC = "ADMM iters/s (8192², 5 scales) + served solves/s, p99 lat @ relerr≤1e-3"
@@ -602,8 +606,8 @@ def main():
     ap.add_argument("--max-active", type=int, default=32)
     ap.add_argument("--hbm-budget", type=int, default=64, help="GiB")
     ap.add_argument("--hw-queues", type=int, default=None,
-                    help="hardware queues per process (GPU_MAX_HW_QUEUES), 1..32; default 4 "
-                         "for the 8192^2 run, 16 for the other modes")
+                    help="hardware queues per process (GPU_MAX_HW_QUEUES), 2..32; default 4 "
+                         "for the 8192^2 run and the batch, 16 for the other modes")
     ap.add_argument("--fork-mode", type=int, default=0, choices=[0, 1, 2, 3],
                     help="where the scales fork from the main stream (msld_params.fork_mode)")
     ap.add_argument("--no-serving", action="store_true",
@@ -612,9 +616,9 @@ def main():
                     help="requests of the default run's serving measurement")
     args = ap.parse_args()
     if args.hw_queues is None:
-        args.hw_queues = 4 if args.mode == "iters" else 16
-    if not 1 <= args.hw_queues <= 32:
-        ap.error("--hw-queues must be in 1..32")
+        args.hw_queues = 4 if args.mode in ("iters", "batch") else 16
+    if not 2 <= args.hw_queues <= 32:
+        ap.error("--hw-queues must be in 2..32")
     global HW_QUEUES
     HW_QUEUES = args.hw_queues
     os.environ["GPU_MAX_HW_QUEUES"] = str(HW_QUEUES)

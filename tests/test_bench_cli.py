@@ -21,7 +21,7 @@ def test_more_than_one_gpu_exits_with_a_message():
 
 
 def test_hardware_queue_count_is_range_checked():
-    for bad in ("0", str(32 + 1)):
+    for bad in ("0", "1", str(32 + 1)):
         r = _run("--hw-queues", bad)
         assert r.returncode == 2
         assert "--hw-queues" in r.stderr
