@@ -281,16 +281,16 @@ msld_status make_plan(const msld_params* p, int ninst, Plan* pl) {
         const int ch = split_chunks(g.mb, g.nb);
         if (ch > 1) pl->off_split[i] = take(4 * (size_t)nblk * ch * nb2);
         if (!lds_fits(g.mb, g.nb)) {
-          // polar fallback buffers for a chunk of failed certificates (<= 256 MiB)
-          const size_t pper = 3 * (size_t)g.mb * g.nb + 4 * nb2 + 4;
+          // polar fallback buffers for a chunk of failed certificates (<= 256 MiB): per
+          // block its iterates, scalars and step counts, and the split partial products
+          // of its GEMMs at the split the shapes alone give
+          const size_t pper = 3 * (size_t)g.mb * g.nb + 4 * nb2 + 6 +
+                              (size_t)polar_part_floats(g.mb, g.nb);
           size_t cap = ((size_t)256 << 20) / (4 * pper);
           if (cap < 1) cap = 1;
           if (cap > (size_t)nblk) cap = (size_t)nblk;
           pl->pl_cap[i] = (int)cap;
-          // plus the split partial products of its GEMMs (one block at a time, at most 8
-          // chunks of an mb x nb product): sized by the block shape alone, so the split
-          // is the same whatever the slot count
-          pl->off_pl[i] = take(4 * (cap * pper + 8 * (size_t)g.mb * g.nb));
+          pl->off_pl[i] = take(4 * cap * pper);
         }
       }
     }
@@ -391,7 +391,7 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
     // scales run concurrently: each low-rank scale gets its own slice
     int cap = 0;
     for (int i = 0; i < p->L; ++i) cap += s->plan.pl_cap[i];
-    if (cap > 0 && hipHostMalloc(&s->host_pl, 4 * (size_t)cap * sizeof(float),
+    if (cap > 0 && hipHostMalloc(&s->host_pl, 6 * (size_t)cap * sizeof(float),
                                  hipHostMallocDefault) != hipSuccess) {
       destroy_solver(s);
       return MSLD_ENOMEM;
@@ -547,10 +547,13 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
           w.plY = q; q += cap * nb2;
           w.plW = q; q += cap * nb2;
           w.plScal = q; q += 4 * cap;
+          w.plSteps = reinterpret_cast<int*>(q); q += 2 * cap;
           w.plPart = q;
+          // pinned host slice: 4 scalars and 2 step counts per block
           size_t hoff = 0;
-          for (int i2 = 0; i2 < i; ++i2) hoff += 4 * (size_t)pl.pl_cap[i2];
+          for (int i2 = 0; i2 < i; ++i2) hoff += 6 * (size_t)pl.pl_cap[i2];
           w.hostPl = s->host_pl + hoff;
+          w.hostSteps = reinterpret_cast<int*>(w.hostPl + 4 * cap);
         }
       }
     }

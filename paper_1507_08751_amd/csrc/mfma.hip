@@ -911,22 +911,33 @@ __global__ void __launch_bounds__(256) k_gemm_sum(const float* __restrict__ part
     }
 }
 
+int gemm_split(int M, int N, int K, int* kc) {
+  // few output tiles and a long contraction: chunks of 128 or more, 32-aligned
+  const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
+  int chunks = (tiles < 128 && K >= 256) ? std::min(K / 128, 8) : 1;
+  int KC = (K + chunks - 1) / chunks;
+  KC = (KC + 31) / 32 * 32;
+  if (kc) *kc = KC;
+  return (K + KC - 1) / KC;
+}
+
 hipError_t launch_gemm(bool ta, int M, int N, int K, const float* A, int lda, int64_t sa,
                        const float* B, int ldb, int64_t sb, float* C, int ldc, int64_t sc,
                        const int* dcount, int hcount, int max_count, hipStream_t st, float* part,
                        int64_t part_floats) {
   if (max_count <= 0) return hipSuccess;
   const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
-  // few output tiles and a long contraction: split it into chunks of 128 or more (a
-  // function of the shape alone; a part too small for that split means no split)
-  int chunks = 1;
-  if (part && tiles < 128 && K >= 256) {
-    chunks = std::min(K / 128, 8);
-    if ((int64_t)chunks * M * N * max_count > part_floats) chunks = 1;
+  // the split is a function of the shape alone (gemm_split); a part too small for it
+  // means no split
+  int KC = (K + 31) / 32 * 32, chunks = 1;
+  if (part) {
+    int kc = 0;
+    const int c = gemm_split(M, N, K, &kc);
+    if (c > 1 && (int64_t)c * M * N * max_count <= part_floats) {
+      chunks = c;
+      KC = kc;
+    }
   }
-  int KC = (K + chunks - 1) / chunks;
-  KC = (KC + 31) / 32 * 32;
-  chunks = (K + KC - 1) / KC;
   const dim3 grid(tiles, grid_slots(max_count, tiles * chunks), chunks);
   if (ta)
     hipLaunchKernelGGL(k_gemm<1>, grid, dim3(256), 0, st, A, lda, sa, B, ldb, sb, C, ldc, sc, M,

@@ -216,7 +216,8 @@ struct ScaleWork {
   // polar fallback (polar.hip) for failed certificates of blocks beyond the LDS tier;
   // buffers hold plCap compacted blocks
   int plCap;
-  float* plPart;        // [8][mb*nb] split partial products of the polar route's GEMMs
+  float* plPart;        // [plCap][polar_part_floats(mb, nb)] split partial products of the
+                        // polar route's GEMMs
   float* plX0;          // [plCap][mb*nb] E' / alpha, later the thresholded block
   float* plXa;          // [plCap][mb*nb] Newton-Schulz iterates
   float* plXb;
@@ -225,7 +226,9 @@ struct ScaleWork {
   float* plY;
   float* plW;
   float* plScal;        // [plCap][4] alpha, alpha_S, deflated, ||B||_F
+  int* plSteps;         // [plCap][2] each block's polar and sign step counts
   float* hostPl;        // pinned host copy of plScal
+  int* hostSteps;       // pinned host staging of plSteps
   long long stats_host[3];   // polar blocks, polar steps, sign steps (host counters)
 };
 
@@ -329,8 +332,13 @@ hipError_t launch_sym_x(const float* A, int64_t sA, int lda, const float* X, int
 // and mirrored), batch entries c < count.
 hipError_t launch_syrk(int M, int K, const float* A, int lda, int64_t sa, float* C, int ldc,
                        int64_t sc, const int* dcount, int hcount, int max_count, hipStream_t st);
+// Contraction chunks of an M x N x K product (a function of the shape alone: few output
+// tiles and a long contraction split into chunks of at least 128, kc their 32-aligned
+// length); a split launch_gemm needs chunks x M x N floats of part per batch entry.
+int gemm_split(int M, int N, int K, int* kc);
 // C = op(A) B, column-major, batch entries c < count. With part (part_floats floats), a
-// product with few output tiles splits its contraction (partials summed in order).
+// product with few output tiles splits its contraction as gemm_split says (partials
+// summed in order), or not at all when part is too small for every entry.
 hipError_t launch_gemm(bool ta, int M, int N, int K, const float* A, int lda, int64_t sa,
                        const float* B, int ldb, int64_t sb, float* C, int ldc, int64_t sc,
                        const int* dcount, int hcount, int max_count, hipStream_t st,
@@ -346,6 +354,8 @@ hipError_t launch_mf_rebuild(const ScaleGeom& g, const ShiftSpec& sh, float* Zou
 hipError_t launch_lr_ge(const float* G, const float* Q, const float* V, float* Pm, int nb,
                         float* part, float* rowpart, const int* list, const int* lcount,
                         int slots, hipStream_t st);
+// Split partial floats per block of the polar route's products (mb x nb blocks).
+int64_t polar_part_floats(int mb, int nb);
 hipError_t run_polar(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout, float tau,
                      const ShiftSpec& sh, int nfall, hipStream_t st);
 // Certified low-rank BlockSVT of the live blocks (count on the device); failed

@@ -24,6 +24,7 @@
 // non-expansiveness. The remainder bound of the failed certificate bounds sigma_max(E'),
 // so alpha is within a small factor of tau and K is a handful of steps. Without a
 // passed coupling test the whole block goes through the polar route (L empty).
+#include <algorithm>
 #include <cmath>
 
 #include "msld_internal.h"
@@ -94,16 +95,20 @@ __global__ void __launch_bounds__(256) k_pl_prepare(const float* __restrict__ Do
   }
 }
 
-// M <- a I + b M for each nb x nb matrix of the chunk.
-__global__ void __launch_bounds__(256) k_pl_affine(float* M, int nb, float a, float b) {
+// M <- a I + b M for each nb x nb matrix of the chunk; with steps, a block whose own step
+// count steps[2 c] is reached (k >= steps[2 c]) gets M = I instead, so the product that
+// follows carries its iterate over unchanged (x 1 plus exact zeros).
+__global__ void __launch_bounds__(256) k_pl_affine(float* M, int nb, float a, float b,
+                                                   const int* __restrict__ steps, int k) {
   const int c = blockIdx.y;
+  const bool frozen = steps != nullptr && k >= steps[2 * c];
   const int64_t elems = (int64_t)nb * nb;
   float* m = M + (int64_t)c * elems;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < elems;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int j = (int)(e / nb);
     const int i = (int)(e - (int64_t)j * nb);
-    m[e] = b * m[e] + (i == j ? a : 0.f);
+    m[e] = frozen ? (i == j ? 1.f : 0.f) : b * m[e] + (i == j ? a : 0.f);
   }
 }
 
@@ -240,6 +245,16 @@ hipError_t last() { return hipGetLastError(); }
 
 }  // namespace
 
+int64_t polar_part_floats(int mb, int nb) {
+  // the route's products: X^T X and Q^T X0 (nb x nb, contraction mb), X T and Q W
+  // (mb x nb, contraction nb), Y Y, Y W and S Y (nb x nb, contraction nb)
+  auto need = [](int M, int N, int K) -> int64_t {
+    const int c = gemm_split(M, N, K, nullptr);
+    return c > 1 ? (int64_t)c * M * N : 0;
+  };
+  return std::max(need(nb, nb, mb), std::max(need(mb, nb, nb), need(nb, nb, nb)));
+}
+
 hipError_t run_polar(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout, float tau,
                      const ShiftSpec& sh, int nfall, hipStream_t st) {
   constexpr int P = 16;
@@ -252,15 +267,16 @@ hipError_t run_polar(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout,
   const int tilesX = (int)std::min<int64_t>((sX + 1023) / 1024, 256);
   const int tilesN = (int)std::min<int64_t>((sN + 1023) / 1024, 256);
   const int tilesZ = ((g.m + 31) / 32) * ((g.n + 31) / 32);
-  // split partial products of the GEMMs (8 mb nb floats: every split launch_gemm chooses
-  // for these shapes fits, so the split depends on the shapes alone)
+  // split partial products of the GEMMs: room for every block of a chunk at the split
+  // gemm_split gives each shape, so the split depends on the shapes alone
   float* part = w.plPart;
-  const int64_t pfl = 8 * sX;
-  // one failed block at a time: its step counts K and J then depend on that block
-  // alone, so its result is the same whatever other blocks failed beside it (alone or
-  // in a batch); failures are rare
-  for (int c0 = 0; c0 < nfall; ++c0) {
-    const int cnt = 1;
+  const int64_t pfl = (int64_t)w.plCap * polar_part_floats(mb, nb);
+  // Failed blocks in chunks of plCap. The step counts K and J are each block's own: the
+  // chunk runs the largest, and a block past its own count multiplies by an exact
+  // identity (k_pl_affine with steps), so its result is the one it gets alone, whatever
+  // other blocks fail beside it (alone or in a batch).
+  for (int c0 = 0; c0 < nfall; c0 += w.plCap) {
+    const int cnt = std::min(w.plCap, nfall - c0);
     hipLaunchKernelGGL(k_pl_prepare<P>, dim3(tilesX, cnt), dim3(256), 0, st, Dout, g, sh,
                        w.live_list, w.lrC, w.lrT, w.lrSig, mask, w.lrScal, fslot, c0, mb, nb, tau, w.plX0,
                        w.plScal);
@@ -275,12 +291,18 @@ hipError_t run_polar(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout,
       const int k = polar_steps((double)tau / alpha);
       const int j = sign_steps(alpha_s, w.hostPl[4 * c + 3]);
       if (k < 0 || !std::isfinite(alpha_s)) return hipErrorInvalidValue;
+      w.hostSteps[2 * c + 0] = k;
+      w.hostSteps[2 * c + 1] = j;
       K = std::max(K, k);
       J = std::max(J, j);
+      w.stats_host[1] += k;
+      w.stats_host[2] += j;
     }
     w.stats_host[0] += cnt;
-    w.stats_host[1] += K;
-    w.stats_host[2] += J;
+    // (the next chunk overwrites the staging only after its own stream synchronisation)
+    if ((e = hipMemcpyAsync(w.plSteps, w.hostSteps, sizeof(int) * 2 * cnt,
+                            hipMemcpyHostToDevice, st)) != hipSuccess)
+      return e;
     // polar factor of E' / alpha: X <- X (1.5 I - 0.5 X^T X)
     const float* X = w.plX0;
     float* Xn = w.plXa;
@@ -288,7 +310,7 @@ hipError_t run_polar(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout,
       if ((e = launch_gemm(true, nb, nb, mb, X, mb, sX, X, mb, sX, w.plT, nb, sN, nullptr, cnt, cnt, st, part, pfl)) != hipSuccess)
         return e;
       hipLaunchKernelGGL(k_pl_affine, dim3(tilesN, cnt), dim3(256), 0, st, w.plT, nb, 1.5f,
-                         -0.5f);
+                         -0.5f, (const int*)w.plSteps, k);
       if ((e = last()) != hipSuccess) return e;
       if ((e = launch_gemm(false, mb, nb, nb, X, mb, sX, w.plT, nb, sN, Xn, mb, sX, nullptr, cnt, cnt, st, part, pfl)) != hipSuccess)
         return e;
@@ -308,14 +330,15 @@ hipError_t run_polar(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout,
       if ((e = launch_gemm(false, nb, nb, nb, Y, nb, sN, Y, nb, sN, w.plW, nb, sN, nullptr, cnt, cnt, st, part, pfl)) != hipSuccess)
         return e;
       hipLaunchKernelGGL(k_pl_affine, dim3(tilesN, cnt), dim3(256), 0, st, w.plW, nb, 1.5f,
-                         -0.5f);
+                         -0.5f, (const int*)(w.plSteps + 1), j);
       if ((e = last()) != hipSuccess) return e;
       if ((e = launch_gemm(false, nb, nb, nb, Y, nb, sN, w.plW, nb, sN, Yn, nb, sN, nullptr, cnt, cnt, st, part, pfl)) != hipSuccess)
         return e;
       std::swap(Y, Yn);
     }
     // (S)_+ = S (I + Y) / 2, then Ze = Q (S)_+ into the X0 buffer
-    hipLaunchKernelGGL(k_pl_affine, dim3(tilesN, cnt), dim3(256), 0, st, Y, nb, 0.5f, 0.5f);
+    hipLaunchKernelGGL(k_pl_affine, dim3(tilesN, cnt), dim3(256), 0, st, Y, nb, 0.5f, 0.5f,
+                       (const int*)nullptr, 0);
     if ((e = last()) != hipSuccess) return e;
     if ((e = launch_gemm(false, nb, nb, nb, w.plS, nb, sN, Y, nb, sN, w.plW, nb, sN, nullptr, cnt, cnt, st, part, pfl)) != hipSuccess)
       return e;

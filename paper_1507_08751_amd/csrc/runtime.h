@@ -99,7 +99,7 @@ struct msld_solver {
   char* arena;
   double* host_res;   // pinned: [0, ninst) residual sums, [ninst, 2 ninst) ||Y||^2
   int* host_ints;     // pinned, 2 per scale
-  float* host_pl;     // pinned, 4 floats per polar chunk slot, one slice per scale
+  float* host_pl;     // pinned, per polar chunk slot 4 scalars and 2 step counts, one slice per scale
   // scales are independent between two consensus passes: each runs on its own
   // stream (forked from st after the consensus, joined before the residual)
   hipStream_t sst[MSLD_MAX_SCALES];
