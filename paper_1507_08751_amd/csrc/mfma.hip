@@ -550,11 +550,12 @@ __global__ void __launch_bounds__(256) k_sk_sum(const float* __restrict__ part, 
 // C (M x N) = op(A) B, column-major, one problem per batch entry c < count (pointer
 // strides sa, sb, sc); op(A) = A (TA = 0, A[k lda + i]) or A^T (TA = 1, A[i lda + k]).
 // 64 x 64 tiles, slabs of 32 along K, four waves on v_mfma_f32_32x32x2f32.
-// SYM (with TA = 1, B = A, M = N): C = A^T A, only the tiles with i0 <= j0 are formed
-// (blockIdx.x enumerates the upper triangle) and each is also written mirrored, so C is
-// exactly symmetric. With gridDim.z > 1 (never with SYM) the contraction is split into
-// chunks of KC and chunk z writes its partial product to part + (c chunks + z) M N
-// (column-major, ld M), summed by k_gemm_sum.
+// SYM (with TA = 1, M = N, for products A^T B known to be symmetric: A^T A, or A^T B with
+// A and B symmetric and commuting): only the tiles with i0 <= j0 are formed (blockIdx.x
+// enumerates the upper triangle), each also written mirrored and the diagonal tiles from
+// their upper triangle, so C is exactly symmetric. With gridDim.z > 1 the contraction is
+// split into chunks of KC and chunk z writes its partial product to part + (c chunks + z)
+// M N (column-major, ld M), summed by k_gemm_sum.
 template <int TA, int SYM = 0>
 __global__ void __launch_bounds__(256) k_gemm(const float* __restrict__ A, int lda, int64_t sa,
                                               const float* __restrict__ B, int ldb, int64_t sb,
@@ -587,14 +588,18 @@ __global__ void __launch_bounds__(256) k_gemm(const float* __restrict__ A, int l
     f32x16 acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.f;
-    for (int kb = k0; kb < k1; kb += 32) {
+    // 32-deep slabs of A and B staged through LDS; the next slab's global loads are
+    // issued into registers before the current slab's products, so they are in flight
+    // while the matrix cores run
+    float ra[8], rb[8];
+    auto load = [&](int kb) {
       if (!TA) {
         const int ii = tid & 63;
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const int kk = (tid >> 6) + 4 * u;
           const int i = i0 + ii, k = kb + kk;
-          As[kk * kGLd + ii] = (i < M && k < k1) ? a[(int64_t)k * lda + i] : 0.f;
+          ra[u] = (i < M && k < k1) ? a[(int64_t)k * lda + i] : 0.f;
         }
       } else {
         const int kk = tid & 31;
@@ -602,19 +607,30 @@ __global__ void __launch_bounds__(256) k_gemm(const float* __restrict__ A, int l
         for (int u = 0; u < 8; ++u) {
           const int ii = (tid >> 5) + 8 * u;
           const int i = i0 + ii, k = kb + kk;
-          As[kk * kGLd + ii] = (i < M && k < k1) ? a[(int64_t)i * lda + k] : 0.f;
+          ra[u] = (i < M && k < k1) ? a[(int64_t)i * lda + k] : 0.f;
         }
       }
-      {
-        const int kk = tid & 31;
+      const int kk = tid & 31;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int jj = (tid >> 5) + 8 * u;
-          const int j = j0 + jj, k = kb + kk;
-          Bs[kk * kGLd + jj] = (j < N && k < k1) ? b[(int64_t)j * ldb + k] : 0.f;
-        }
+      for (int u = 0; u < 8; ++u) {
+        const int jj = (tid >> 5) + 8 * u;
+        const int j = j0 + jj, k = kb + kk;
+        rb[u] = (j < N && k < k1) ? b[(int64_t)j * ldb + k] : 0.f;
       }
+    };
+    if (k0 < k1) load(k0);
+    for (int kb = k0; kb < k1; kb += 32) {
+      if (!TA) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) As[((tid >> 6) + 4 * u) * kGLd + (tid & 63)] = ra[u];
+      } else {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) As[(tid & 31) * kGLd + (tid >> 5) + 8 * u] = ra[u];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) Bs[(tid & 31) * kGLd + (tid >> 5) + 8 * u] = rb[u];
       __syncthreads();
+      if (kb + 32 < k1) load(kb + 32);
 #pragma unroll
       for (int kk = 0; kk < 32; kk += 2) {
         const float av = As[(kk + (lane >> 5)) * kGLd + wi * 32 + (lane & 31)];
@@ -635,12 +651,14 @@ __global__ void __launch_bounds__(256) k_gemm(const float* __restrict__ A, int l
     const int ldo = chunks > 1 ? M : ldc;
     for (int e = tid; e < 64 * 64; e += 256) {
       const int jj = e >> 6, ii = e & 63;
-      if (i0 + ii < M && j0 + jj < N) cc[(int64_t)(j0 + jj) * ldo + i0 + ii] = T[ii * kGLd + jj];
+      // (a diagonal tile of a symmetric product takes its upper triangle on both sides)
+      const float v = (SYM && i0 == j0 && ii > jj) ? T[jj * kGLd + ii] : T[ii * kGLd + jj];
+      if (i0 + ii < M && j0 + jj < N) cc[(int64_t)(j0 + jj) * ldo + i0 + ii] = v;
     }
     if (SYM && i0 != j0)
       for (int e = tid; e < 64 * 64; e += 256) {
         const int ii = e >> 6, jj = e & 63;   // element (j0 + jj, i0 + ii), along jj
-        if (i0 + ii < M && j0 + jj < N) cc[(int64_t)(i0 + ii) * ldc + j0 + jj] = T[ii * kGLd + jj];
+        if (i0 + ii < M && j0 + jj < N) cc[(int64_t)(i0 + ii) * ldo + j0 + jj] = T[ii * kGLd + jj];
       }
     __syncthreads();
   }
@@ -913,8 +931,9 @@ __global__ void __launch_bounds__(256) k_gemm_sum(const float* __restrict__ part
 
 int gemm_split(int M, int N, int K, int* kc) {
   // few output tiles and a long contraction: chunks of 128 or more, 32-aligned
+  // (about 1024 workgroups: the chip's 256 compute units each run several)
   const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
-  int chunks = (tiles < 128 && K >= 256) ? std::min(K / 128, 8) : 1;
+  int chunks = (tiles < 512 && K >= 256) ? std::max(1, std::min(1024 / tiles, std::min(K / 128, 8))) : 1;
   int KC = (K + chunks - 1) / chunks;
   KC = (KC + 31) / 32 * 32;
   if (kc) *kc = KC;
@@ -951,6 +970,39 @@ hipError_t launch_gemm(bool ta, int M, int N, int K, const float* A, int lda, in
   const int gx = (int)std::min<int64_t>((n + 255) / 256, 1024);
   hipLaunchKernelGGL(k_gemm_sum, dim3(gx, grid_slots(max_count, gx)), dim3(256), 0, st, part,
                      chunks, M, N, C, ldc, sc, dcount, hcount);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_sym(int M, int K, const float* A, int lda, int64_t sa, const float* B,
+                           int ldb, int64_t sb, float* C, int ldc, int64_t sc, int count,
+                           hipStream_t st, float* part, int64_t part_floats, int* unsummed) {
+  if (unsummed) *unsummed = 0;
+  if (count <= 0) return hipSuccess;
+  const int tm = (M + 63) / 64;
+  const int tiles = tm * (tm + 1) / 2;
+  // the split of the full M x M product (gemm_split), so that part is sized alike
+  int KC = (K + 31) / 32 * 32, chunks = 1;
+  if (part) {
+    int kc = 0;
+    const int c = gemm_split(M, M, K, &kc);
+    if (c > 1 && (int64_t)c * M * M * count <= part_floats) {
+      chunks = c;
+      KC = kc;
+    }
+  }
+  const dim3 grid(tiles, grid_slots(count, tiles * chunks), chunks);
+  hipLaunchKernelGGL((k_gemm<1, 1>), grid, dim3(256), 0, st, A, lda, sa, B, ldb, sb, C, ldc, sc,
+                     M, M, K, nullptr, count, part, KC);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || chunks == 1) return e;
+  if (unsummed) {
+    *unsummed = chunks;   // the caller's next kernel sums the partials
+    return hipSuccess;
+  }
+  const int64_t n = (int64_t)M * M;
+  const int gx = (int)std::min<int64_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_gemm_sum, dim3(gx, grid_slots(count, gx)), dim3(256), 0, st, part, chunks,
+                     M, M, C, ldc, sc, nullptr, count);
   return hipGetLastError();
 }
 

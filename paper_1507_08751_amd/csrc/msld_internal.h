@@ -332,9 +332,10 @@ hipError_t launch_sym_x(const float* A, int64_t sA, int lda, const float* X, int
 // and mirrored), batch entries c < count.
 hipError_t launch_syrk(int M, int K, const float* A, int lda, int64_t sa, float* C, int ldc,
                        int64_t sc, const int* dcount, int hcount, int max_count, hipStream_t st);
-// Contraction chunks of an M x N x K product (a function of the shape alone: few output
-// tiles and a long contraction split into chunks of at least 128, kc their 32-aligned
-// length); a split launch_gemm needs chunks x M x N floats of part per batch entry.
+// Contraction chunks of an M x N x K product (a function of the shape alone: fewer than
+// 512 output tiles of 64 x 64 and a contraction of 256 or more split into up to 8 chunks
+// of at least 128, about 1024 workgroups in all; kc their 32-aligned length); a split
+// launch_gemm needs chunks x M x N floats of part per batch entry.
 int gemm_split(int M, int N, int K, int* kc);
 // C = op(A) B, column-major, batch entries c < count. With part (part_floats floats), a
 // product with few output tiles splits its contraction as gemm_split says (partials
@@ -343,6 +344,16 @@ hipError_t launch_gemm(bool ta, int M, int N, int K, const float* A, int lda, in
                        const float* B, int ldb, int64_t sb, float* C, int ldc, int64_t sc,
                        const int* dcount, int hcount, int max_count, hipStream_t st,
                        float* part = nullptr, int64_t part_floats = 0);
+// C = A^T B for products known to be symmetric (M x M, contraction K, count batch
+// entries): the upper 64 x 64 tiles, each mirrored below the diagonal, so C is exactly
+// symmetric; part as for launch_gemm, at the split of the full product. With unsummed,
+// a split product is left as its chunks in part (column-major M x M each, chunk z of
+// entry c at (c chunks + z) M M) and *unsummed = chunks, for the caller to sum in order;
+// otherwise (and with no split) *unsummed = 0 and C holds the product.
+hipError_t launch_gemm_sym(int M, int K, const float* A, int lda, int64_t sa, const float* B,
+                           int ldb, int64_t sb, float* C, int ldc, int64_t sc, int count,
+                           hipStream_t st, float* part, int64_t part_floats,
+                           int* unsummed = nullptr);
 // Z = A_f diag(gains) V_r^T of the certified slots among slot_list[0 .. *count) (all
 // slots < *count when the list is null), scattered with D' = 2 Z' - V.
 hipError_t launch_mf_rebuild(const ScaleGeom& g, const ShiftSpec& sh, float* Zout, float* Dout,

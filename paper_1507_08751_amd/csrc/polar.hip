@@ -112,6 +112,28 @@ __global__ void __launch_bounds__(256) k_pl_affine(float* M, int nb, float a, fl
   }
 }
 
+// The same, with M the in-order sum of the chunks partials left by a split product
+// (chunk z of matrix c at part + (c chunks + z) nb^2), written to M.
+__global__ void __launch_bounds__(256) k_pl_affine_part(const float* __restrict__ part,
+                                                        int chunks, float* M, int nb, float a,
+                                                        float b, const int* __restrict__ steps,
+                                                        int k) {
+  const int c = blockIdx.y;
+  const bool frozen = steps != nullptr && k >= steps[2 * c];
+  const int64_t elems = (int64_t)nb * nb;
+  const float* p = part + (int64_t)c * chunks * elems;
+  float* m = M + (int64_t)c * elems;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < elems;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(e / nb);
+    const int i = (int)(e - (int64_t)j * nb);
+    float v = 0.f;
+    if (!frozen)
+      for (int z = 0; z < chunks; ++z) v += p[(int64_t)z * elems + e];
+    m[e] = frozen ? (i == j ? 1.f : 0.f) : b * v + (i == j ? a : 0.f);
+  }
+}
+
 // S = alpha (H + H^T) / 2 - tau I and Y0 = S / alpha_S, with H = Q^T X0.
 __global__ void __launch_bounds__(256) k_pl_shift(const float* __restrict__ H,
                                                   float* __restrict__ S, float* __restrict__ Y,
@@ -266,6 +288,7 @@ hipError_t run_polar(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout,
   const float* mask = w.lrSig + (size_t)w.slots * P;
   const int tilesX = (int)std::min<int64_t>((sX + 1023) / 1024, 256);
   const int tilesN = (int)std::min<int64_t>((sN + 1023) / 1024, 256);
+  const int tilesP = (int)std::min<int64_t>((sN + 255) / 256, 4096);
   const int tilesZ = ((g.m + 31) / 32) * ((g.n + 31) / 32);
   // split partial products of the GEMMs: room for every block of a chunk at the split
   // gemm_split gives each shape, so the split depends on the shapes alone
@@ -303,15 +326,24 @@ hipError_t run_polar(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout,
     if ((e = hipMemcpyAsync(w.plSteps, w.hostSteps, sizeof(int) * 2 * cnt,
                             hipMemcpyHostToDevice, st)) != hipSuccess)
       return e;
+    // M <- a I + b (product), from its unsummed split partials when ch > 1
+    auto affine = [&](float* Mm, int ch, float a, float b, const int* steps, int step) {
+      if (ch > 1)   // (one element per thread: the chunk reads are the latency)
+        hipLaunchKernelGGL(k_pl_affine_part, dim3(tilesP, cnt), dim3(256), 0, st, part, ch, Mm,
+                           nb, a, b, steps, step);
+      else
+        hipLaunchKernelGGL(k_pl_affine, dim3(tilesN, cnt), dim3(256), 0, st, Mm, nb, a, b,
+                           steps, step);
+      return last();
+    };
     // polar factor of E' / alpha: X <- X (1.5 I - 0.5 X^T X)
     const float* X = w.plX0;
     float* Xn = w.plXa;
     for (int k = 0; k < K; ++k) {
-      if ((e = launch_gemm(true, nb, nb, mb, X, mb, sX, X, mb, sX, w.plT, nb, sN, nullptr, cnt, cnt, st, part, pfl)) != hipSuccess)
+      int ch = 0;
+      if ((e = launch_gemm_sym(nb, mb, X, mb, sX, X, mb, sX, w.plT, nb, sN, cnt, st, part, pfl, &ch)) != hipSuccess)
         return e;
-      hipLaunchKernelGGL(k_pl_affine, dim3(tilesN, cnt), dim3(256), 0, st, w.plT, nb, 1.5f,
-                         -0.5f, (const int*)w.plSteps, k);
-      if ((e = last()) != hipSuccess) return e;
+      if ((e = affine(w.plT, ch, 1.5f, -0.5f, w.plSteps, k)) != hipSuccess) return e;
       if ((e = launch_gemm(false, mb, nb, nb, X, mb, sX, w.plT, nb, sN, Xn, mb, sX, nullptr, cnt, cnt, st, part, pfl)) != hipSuccess)
         return e;
       X = Xn;
@@ -327,12 +359,11 @@ hipError_t run_polar(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout,
     float* Y = w.plY;
     float* Yn = w.plT;
     for (int j = 0; j < J; ++j) {
-      if ((e = launch_gemm(false, nb, nb, nb, Y, nb, sN, Y, nb, sN, w.plW, nb, sN, nullptr, cnt, cnt, st, part, pfl)) != hipSuccess)
+      int ch = 0;
+      if ((e = launch_gemm_sym(nb, nb, Y, nb, sN, Y, nb, sN, w.plW, nb, sN, cnt, st, part, pfl, &ch)) != hipSuccess)
         return e;
-      hipLaunchKernelGGL(k_pl_affine, dim3(tilesN, cnt), dim3(256), 0, st, w.plW, nb, 1.5f,
-                         -0.5f, (const int*)(w.plSteps + 1), j);
-      if ((e = last()) != hipSuccess) return e;
-      if ((e = launch_gemm(false, nb, nb, nb, Y, nb, sN, w.plW, nb, sN, Yn, nb, sN, nullptr, cnt, cnt, st, part, pfl)) != hipSuccess)
+      if ((e = affine(w.plW, ch, 1.5f, -0.5f, w.plSteps + 1, j)) != hipSuccess) return e;
+      if ((e = launch_gemm_sym(nb, nb, Y, nb, sN, w.plW, nb, sN, Yn, nb, sN, cnt, st, part, pfl)) != hipSuccess)
         return e;
       std::swap(Y, Yn);
     }
@@ -340,7 +371,7 @@ hipError_t run_polar(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dout,
     hipLaunchKernelGGL(k_pl_affine, dim3(tilesN, cnt), dim3(256), 0, st, Y, nb, 0.5f, 0.5f,
                        (const int*)nullptr, 0);
     if ((e = last()) != hipSuccess) return e;
-    if ((e = launch_gemm(false, nb, nb, nb, w.plS, nb, sN, Y, nb, sN, w.plW, nb, sN, nullptr, cnt, cnt, st, part, pfl)) != hipSuccess)
+    if ((e = launch_gemm_sym(nb, nb, w.plS, nb, sN, Y, nb, sN, w.plW, nb, sN, cnt, st, part, pfl)) != hipSuccess)
       return e;
     if ((e = launch_gemm(false, mb, nb, nb, X, mb, sX, w.plW, nb, sN, Xn, mb, sX, nullptr, cnt, cnt, st, part, pfl)) != hipSuccess)
       return e;
