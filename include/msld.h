@@ -240,8 +240,9 @@ msld_status msld_autotune(int32_t m, int32_t n, void* hip_stream, msld_tune_resu
 void msld_autotune_clear(void);
 
 /* Iterations as HIP graphs (not a step of the paper: launch overhead). When no scale
- * of the plan takes the batched low-rank path (whose driver reads live and fallback
- * counts on the host), msld_step, msld_solve and msld_batch_solve capture one ADMM
+ * of the plan takes the low-rank path with blocks beyond the LDS Jacobi tier (its polar
+ * fallback reads the failure count and per-block scalars on the host to size its step
+ * counts), msld_step, msld_solve and msld_batch_solve capture one ADMM
  * iteration per D-buffer parity into a HIP graph on first use and replay it for every
  * iteration whose residual is not read; the shift seed and iteration counter then live
  * on the device. Graphs are keyed by the Y and Z buffers and the mask; new buffers are
