@@ -230,6 +230,41 @@ def test_polar_fallback_parity(lib, M, N, m, n, kind):
     solver.close()
 
 
+def test_polar_blocks_independent_of_batch(lib):
+    """Failed blocks go through the polar route together, each with its own polar and
+    sign step counts: every block's result equals, bit for bit, the one it gets when it
+    is the only block of the call, and matches the oracle."""
+    rng = np.random.default_rng(77)
+    m = n = 256
+    tau = 2.0
+    kinds = ["dense", "bulk", "bulk_below", "dense"]
+    blocks = [_clustered_block(rng, m, n, tau, k) for k in kinds]
+    blocks[3] = 0.4 * blocks[3]   # fewer values above tau: other step counts
+    V64 = np.zeros((2 * m, 2 * n))
+    for b, blk in enumerate(blocks):
+        p, q = divmod(b, 2)
+        V64[p * m:(p + 1) * m, q * n:(q + 1) * n] = blk
+    V = V64.astype(np.float32)
+    solver = lib.Solver(2 * m, 2 * n, [(m, n)], iters=1, lowrank_min=64)
+    assert lib.TIERS[solver.tier(0)] == "lowrank"
+    Z = solver.bsvt(0, torch.from_numpy(V).cuda(), tau, (0, 0)).cpu()
+    torch.cuda.synchronize()
+    st = solver.stats()
+    solver.close()
+    print(f"polar blocks {st['polar']} steps {st['polar_steps']}", flush=True)
+    assert st["polar"][0] >= 3
+    ref = O.cycle_spun_bsvt(V.astype(np.float64), m, n, tau, (0, 0))
+    assert rel_err(Z.numpy(), ref, np.linalg.norm(V)) <= 1e-4
+    for b in range(4):
+        p, q = divmod(b, 2)
+        one = lib.Solver(m, n, [(m, n)], iters=1, lowrank_min=64)
+        vb = torch.from_numpy(np.ascontiguousarray(V[p * m:(p + 1) * m, q * n:(q + 1) * n]))
+        zb = one.bsvt(0, vb.cuda(), tau, (0, 0)).cpu()
+        torch.cuda.synchronize()
+        one.close()
+        assert torch.equal(zb, Z[p * m:(p + 1) * m, q * n:(q + 1) * n]), f"block {b}"
+
+
 @pytest.mark.parametrize("M,N,m,n,kind", [(256, 256, 64, 64, "dense"),
                                           (256, 256, 64, 64, "bulk_below"),
                                           (128, 128, 32, 32, "bulk"),
