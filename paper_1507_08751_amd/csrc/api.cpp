@@ -280,6 +280,11 @@ msld_status make_plan(const msld_params* p, int ninst, Plan* pl) {
         // shape and the slot count
         const int ch = split_chunks(g.mb, g.nb);
         if (ch > 1) pl->off_split[i] = take(4 * (size_t)nblk * ch * nb2);
+        // a single wide block otherwise leaves its skinny products to a handful of
+        // workgroups: their contractions split too
+        if (ch <= 1 && g.nb >= 768)
+          pl->off_skpart[i] = take(4 * (size_t)nblk * sk_chunks(g.nb) *
+                                   (size_t)std::max(g.mb, g.nb) * kLRP);
         if (!lds_fits(g.mb, g.nb)) {
           // polar fallback buffers for a chunk of failed certificates (<= 256 MiB): per
           // block its iterates, scalars and step counts, and the split partial products
@@ -531,6 +536,9 @@ msld_status create_solver(const msld_params* p, int ninst, hipStream_t stream,
         w.lrSplit = pl.off_split[i] ? reinterpret_cast<float*>(s->arena + pl.off_split[i])
                                     : nullptr;
         w.lrChunks = w.lrSplit ? split_chunks(g.mb, g.nb) : 1;
+        w.lrSkPart = pl.off_skpart[i] ? reinterpret_cast<float*>(s->arena + pl.off_skpart[i])
+                                      : nullptr;
+        w.lrSkChunks = w.lrSkPart ? sk_chunks(g.nb) : 1;
         w.lrCount = reinterpret_cast<int*>(f);
         w.lrFall = w.lrCount + 64;
         w.lds_fallback = lds_fits(g.mb, g.nb) ? 1 : 0;

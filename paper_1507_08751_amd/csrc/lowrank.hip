@@ -1032,7 +1032,7 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
   auto gxl = [&](const float* X, int64_t sX, float* Y, const int* dcount, const int* sl) {
     if (symx) return launch_sym_x(w.lrG, sG, nb, X, sX, nb, Y, sY, dcount, S, sl, w.lrSplit, st);
     return launch_sk(SK_DENSE, false, w.lrG, sG, nb, nullptr, g, sh, list, X, sX, nb, nb, Y, sY,
-                     dcount, 0, S, sl, nullptr, 1, st);
+                     dcount, 0, S, sl, w.lrSkPart, w.lrSkChunks, st);
   };
   auto gx = [&](const float* X, int64_t sX, float* Y) { return gxl(X, sX, Y, scount, slist); };
   // subspace iteration: X0 = orth(G Omega), then X <- orth(G (G X)) three times (seven
@@ -1145,11 +1145,14 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
   hipLaunchKernelGGL(k_lr_aflist<P>, dim3(dgrid), dim3(256), 0, st, live, w.pflag, w.lrSig, tau,
                      aflist, afcount);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  // (blocks 1024 wide or more split the contraction over the nb columns in 256-column
-  // chunks, a function of the shape alone)
-  const int afsplit = (w.lrSplit && nb >= 1024) ? (nb + 255) / 256 : 1;
+  // (blocks 1024 wide or more with a split Gram split the contraction over the nb columns
+  // in 256-column chunks, other blocks 768 or more wide in 128-column chunks: functions
+  // of the shape alone)
+  const bool gsplit = w.lrSplit && nb >= 1024;
+  const int afsplit = gsplit ? (nb + 255) / 256 : w.lrSkChunks;
+  float* afpart = gsplit ? w.lrSplit : w.lrSkPart;
   if ((e = launch_sk(SK_B, false, nullptr, 0, 0, Dout, g, sh, list, w.lrV, sY, mb, nb, w.lrC, sC,
-                     afcount, 0, S, aflist, w.lrSplit, afsplit, st)) != hipSuccess)
+                     afcount, 0, S, aflist, afpart, afsplit, st)) != hipSuccess)
     return e;
   // Z = sum_{l in L} (1 - tau / sigma_l) a_l v_l^T for certified slots (matrix cores),
   // scattered to the shifted coordinates with D' = 2 Z' - V

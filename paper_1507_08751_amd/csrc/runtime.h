@@ -58,6 +58,7 @@ struct Plan {
       off_lr[MSLD_MAX_SCALES], off_pl[MSLD_MAX_SCALES];
   int pl_cap[MSLD_MAX_SCALES];   // polar fallback chunk (0: none)
   size_t off_split[MSLD_MAX_SCALES];   // split partials (tall low-rank blocks; 0: none)
+  size_t off_skpart[MSLD_MAX_SCALES];  // skinny-product split partials (wide blocks; 0: none)
   int lds_cap[MSLD_MAX_SCALES];    // LDS tier: workgroups per CU cap (0: as many as fit)
   int lrs_wide[MSLD_MAX_SCALES];   // fused low-rank kernel: first pass with 2p
   // averaged cycle spinning: shifts per iteration (0: one random shift), whether the
