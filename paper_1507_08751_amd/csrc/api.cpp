@@ -280,9 +280,9 @@ msld_status make_plan(const msld_params* p, int ninst, Plan* pl) {
         // shape and the slot count
         const int ch = split_chunks(g.mb, g.nb);
         if (ch > 1) pl->off_split[i] = take(4 * (size_t)nblk * ch * nb2);
-        // a single wide block otherwise leaves its skinny products to a handful of
+        // a single wide block would leave its skinny products to a handful of
         // workgroups: their contractions split too
-        if (ch <= 1 && g.nb >= 768)
+        if (g.nb >= 768)
           pl->off_skpart[i] = take(4 * (size_t)nblk * sk_chunks(g.nb) *
                                    (size_t)std::max(g.mb, g.nb) * kLRP);
         if (!lds_fits(g.mb, g.nb)) {

@@ -1145,9 +1145,8 @@ hipError_t run_lowrank(const ScaleGeom& g, ScaleWork& w, float* Zout, float* Dou
   hipLaunchKernelGGL(k_lr_aflist<P>, dim3(dgrid), dim3(256), 0, st, live, w.pflag, w.lrSig, tau,
                      aflist, afcount);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  // (blocks 1024 wide or more with a split Gram split the contraction over the nb columns
-  // in 256-column chunks, other blocks 768 or more wide in 128-column chunks: functions
-  // of the shape alone)
+  // (blocks 1024 wide or more split the contraction over the nb columns in 256-column
+  // chunks, blocks 768 to 1023 wide in 128-column chunks: functions of the shape alone)
   const bool gsplit = w.lrSplit && nb >= 1024;
   const int afsplit = gsplit ? (nb + 255) / 256 : w.lrSkChunks;
   float* afpart = gsplit ? w.lrSplit : w.lrSkPart;

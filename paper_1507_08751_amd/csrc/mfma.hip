@@ -754,11 +754,11 @@ static int grid_slots(int slots, int per_slot) {
 
 int split_chunks(int mb, int nb) {
   // tall blocks split their rows (the contraction of B^T B and B^T A_f) into chunks of
-  // about 512 rows, and blocks 1024 wide or more into chunks of 256 rows, so that few
+  // about 512 rows, and blocks 768 wide or more into chunks of 256 rows, so that few
   // blocks still fill the chip; a function of the block shape alone, so that a block's
   // result does not depend on how many others run
   int c = 1;
-  if (nb >= 1024)
+  if (nb >= 768)
     c = (mb + 255) / 256;
   else if (mb >= 4 * nb)
     c = (mb + 511) / 512;

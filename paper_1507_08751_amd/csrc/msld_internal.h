@@ -206,8 +206,7 @@ struct ScaleWork {
   float* lrSplit;       // [slots][chunks][nb*nb] split partials of tall blocks (null: none)
   int lrChunks;         // split_chunks(mb, nb)
   float* lrSkPart;      // [slots][sk_chunks(nb)][max(mb, nb)*p] split partials of the skinny
-                        // products G X and B V_r of wide blocks without a Gram split (null:
-                        // none)
+                        // products G X and B V_r of blocks 768 or more wide (null: none)
   int lrSkChunks;
   int* lrCount;         // [5] device counters: fallback, appends, undecided after the trace
                         // bound, undecided after the stage-0 bounds, A_f list
@@ -369,8 +368,9 @@ hipError_t launch_mf_rebuild(const ScaleGeom& g, const ShiftSpec& sh, float* Zou
 hipError_t launch_lr_ge(const float* G, const float* Q, const float* V, float* Pm, int nb,
                         float* part, float* rowpart, const int* list, const int* lcount,
                         int slots, hipStream_t st);
-// Contraction chunks of the skinny products (G X, B V_r) of blocks 768 or more wide whose
-// Gram is not split: 128 columns each, a function of nb alone.
+// Contraction chunks of the skinny products (G X, B V_r) of blocks 768 or more wide: 128
+// columns each, a function of nb alone (B V_r of blocks 1024 or more wide uses the Gram's
+// split buffer and 256-column chunks instead).
 inline int sk_chunks(int nb) { return (nb + 127) / 128; }
 // Split partial floats per block of the polar route's products (mb x nb blocks).
 int64_t polar_part_floats(int mb, int nb);
