@@ -156,6 +156,12 @@ __device__ double gram64_stream(const float* y, const float* z, int nb, float (*
   return k;
 }
 
+// Lane l's double, broadcast to the whole wave (l uniform).
+__device__ __forceinline__ double bcast64(double v, int l) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_readlane(hi, l), __builtin_amdgcn_readlane(lo, l));
+}
+
 // Orthonormalisation of large panels (nb > 512, one workgroup of 1024 threads per slot)
 // by Cholesky QR applied twice: the float64 Gram S = Z^T Z of the panel, its Cholesky
 // factor R, then Z <- Z R^-1 in float64 per row. A column whose remaining squared norm
@@ -185,51 +191,55 @@ __global__ void __launch_bounds__(1024) k_lr_orth_cq(const float* Y, float* X, i
       if (tid < P * P) S[tid / P][tid % P] = kv;
       __syncthreads();
       if (tid < 64) {
-        // Cholesky by wave 0 in LDS (right-looking: R's row j overwrites S's, then the
-        // trailing upper triangle is updated, one entry per lane and step), then lane k
-        // (< P) solves R t = e_k for column k of T = R^-1, bottom up. Wave-level fences
-        // order each step's LDS writes before the next step's reads.
+        // Cholesky by wave 0 in registers: lane k (< P) holds column k of S, which
+        // becomes column k of R (right-looking: row j of R, then the trailing upper
+        // triangle, entry (i, k) by lane k); every other entry a lane needs is broadcast
+        // from its owner with readlane. Then lane k solves R t = e_k for column k of
+        // T = R^-1, bottom up, and writes it to LDS.
         const int lane = tid;
-        double d0 = 0.0;
-        if (lane < P) d0 = S[lane][lane];
+        double c[P];
+#pragma unroll
+        for (int i = 0; i < P; ++i) c[i] = lane < P ? S[i][lane] : 0.0;
+        const double d0 = lane < P ? S[lane][lane] : 0.0;
         unsigned dep = 0;
+#pragma unroll
         for (int j = 0; j < P; ++j) {
-          const double d = S[j][j];
-          const double s0 = __shfl(d0, j);
+          const double d = bcast64(c[j], j);
+          const double s0 = bcast64(d0, j);
           const bool dj = !(s0 > 0.0) || !(d > 1e-12 * s0);
           if (dj) dep |= 1u << j;
           const double rjj = dj ? 1.0 : sqrt(d);
-          __builtin_amdgcn_wave_barrier();
-          if (lane == j) S[j][j] = rjj;
-          if (lane > j && lane < P) S[j][lane] = dj ? 0.0 : S[j][lane] / rjj;
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-          // trailing entries (i, k), j < i <= k < P, enumerated row by row
-          const int w = P - 1 - j;
-          for (int e = lane; e < w * (w + 1) / 2; e += 64) {
-            int i = 0, rem = e;
-            while (rem >= w - i) {
-              rem -= w - i;
-              ++i;
-            }
-            const int ii = j + 1 + i, kk = ii + rem;
-            S[ii][kk] -= S[j][ii] * S[j][kk];
+          if (lane == j) c[j] = rjj;
+          else if (lane > j) c[j] = dj ? 0.0 : c[j] / rjj;
+          const double rjk = c[j];
+#pragma unroll
+          for (int i = j + 1; i < P; ++i) {
+            const double rji = bcast64(c[j], i);
+            if (lane >= i) c[i] -= rji * rjk;
           }
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        const bool dk = lane < P && ((dep >> lane) & 1u);
+        double t[P];
+#pragma unroll
+        for (int i = P - 1; i >= 0; --i) {
+          const double rii = bcast64(c[i], i);
+          if (i > lane) {
+            t[i] = 0.0;
+          } else if (i == lane) {
+            t[i] = dk ? 0.0 : 1.0 / rii;
+          } else {
+            double v = 0.0;
+#pragma unroll
+            for (int m = i + 1; m < P; ++m) {
+              const double rim = bcast64(c[i], m);
+              if (m <= lane) v += rim * t[m];
+            }
+            t[i] = dk ? 0.0 : -v / rii;
+          }
         }
         if (lane < P) {
-          const int k = lane;
-          const bool dk = (dep >> k) & 1u;
-          for (int i = P - 1; i > k; --i) T[i][k] = 0.0;
-          T[k][k] = dk ? 0.0 : 1.0 / S[k][k];
-          for (int i = k - 1; i >= 0; --i) {
-            double v = 0.0;
-            for (int m = i + 1; m <= k; ++m) v += S[i][m] * T[m][k];
-            T[i][k] = dk ? 0.0 : -v / S[i][i];
-          }
+#pragma unroll
+          for (int i = 0; i < P; ++i) T[i][lane] = t[i];
         }
       }
       __syncthreads();
