@@ -846,7 +846,13 @@ __device__ __forceinline__ void lr_certify(int slot, const float* sig, float tau
 
 // A slot whose certificate failed: its block id goes to fall[] (LDS Jacobi fallback) and
 // its slot index to fall[slots + f] (polar fallback); scal[5] keeps the remainder bound
-// on lambda_max(E^T E), or -1 when the coupling test failed (no deflation possible).
+// on lambda_max(E^T E), or, when the coupling test failed (no deflation possible), minus
+// the Collatz-Wielandt bound on sigma_max(B)^2 that the Gram bound left there (-inf when
+// it is not a positive finite number).
+__device__ __forceinline__ float undeflated(float cw) {
+  return (cw > 0.f && isfinite(cw)) ? -cw : -__int_as_float(0x7f800000);
+}
+
 __device__ __forceinline__ void lr_fallback(int slot, int slots, int* pflag, int* counts,
                                             int* fall, const int* live_list, float* scal,
                                             float bound) {
@@ -879,7 +885,7 @@ __global__ void k_lr_decide(const int* live, int slots, float* scal, const float
       pflag[4 * slot + 3] = 0;
       const bool c_ok = c2 <= kCouplingTol * kCouplingTol * trG && isfinite(c2) && isfinite(trG);
       if (!c_ok) {
-        lr_fallback(slot, slots, pflag, counts, fall, live_list, scal, -1.f);
+        lr_fallback(slot, slots, pflag, counts, fall, live_list, scal, undeflated(scal[slot * 8 + 5]));
         atomicAdd(&stats[4], 1ull);
         continue;
       }
@@ -906,7 +912,7 @@ __global__ void k_lr_decide(const int* live, int slots, float* scal, const float
       pflag[4 * slot + 3] = 0;
       const bool c_ok = c2 <= kCouplingTol * kCouplingTol * trG && isfinite(c2) && isfinite(trE);
       if (!c_ok) {
-        lr_fallback(slot, slots, pflag, counts, fall, live_list, scal, -1.f);
+        lr_fallback(slot, slots, pflag, counts, fall, live_list, scal, undeflated(scal[slot * 8 + 5]));
         atomicAdd(&stats[4], 1ull);
         continue;
       }

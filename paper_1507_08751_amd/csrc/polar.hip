@@ -23,7 +23,9 @@
 // SVT(B0) = Z_L + SVT(E') and ||SVT(B) - SVT(B0)||_F <= ||U_L^T E||_F by
 // non-expansiveness. The remainder bound of the failed certificate bounds sigma_max(E'),
 // so alpha is within a small factor of tau and K is a handful of steps. Without a
-// passed coupling test the whole block goes through the polar route (L empty).
+// passed coupling test the whole block goes through the polar route (L empty), with
+// alpha the smaller of ||B||_F and the square root of the Collatz-Wielandt bound of
+// |B^T B| that the zero-output certificate computed (both bound sigma_max(B)).
 #include <algorithm>
 #include <cmath>
 
@@ -59,7 +61,10 @@ __global__ void __launch_bounds__(256) k_pl_prepare(const float* __restrict__ Do
   }
   if (threadIdx.x == 0) {
     const float fro = sqrtf(fmaxf(sc[0], 0.f));
+    // without deflation alpha bounds sigma_max(B): the smaller of ||B||_F and the
+    // Collatz-Wielandt bound of the Gram matrix (stored negated), with a margin
     float alpha = defl ? 1.02f * sqrtf(bound) : 1.001f * fro;
+    if (!defl && bound < 0.f && isfinite(bound)) alpha = fminf(alpha, 1.02f * sqrtf(-bound));
     if (!(alpha > 1e-30f)) alpha = 1e-30f;
     inv_alpha = 1.f / alpha;
     if (blockIdx.x == 0) {
