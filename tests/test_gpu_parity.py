@@ -857,10 +857,12 @@ def test_full_size_bsvt_sampled_parity(lib, m):
 
 
 @pytest.mark.parametrize("M,N,m,n", [(2048, 2048, 2048, 2048), (2048, 2048, 1024, 1024),
-                                     (1024, 2048, 1024, 2048)])
+                                     (1024, 2048, 1024, 2048), (1536, 1536, 768, 768),
+                                     (1800, 900, 900, 900)])
 def test_wide_block_closed_form(lib, M, N, m, n):
-    """Blocks 1024 wide and more (split Gram and skinny products, Cholesky-QR
-    orthonormalisation) against the closed form of eq:svt: each block is built as
+    """Blocks 768 wide and more (split Gram and skinny products, Cholesky-QR
+    orthonormalisation; 900 columns take the dense skinny product, not a multiple of 16)
+    against the closed form of eq:svt: each block is built as
     U diag(s) W^T with orthonormal U, W, so its SVT is U diag(max(s - tau, 0)) W^T.
     Per block: 6 values above tau and 100 below it (0.4 tau .. 0.6 tau), more than the
     16-wide subspace holds, so the remainder is certified by the Collatz-Wielandt or
