@@ -33,7 +33,7 @@ def gpu_available():
 
 @pytest.fixture(scope="session")
 def lib():
-    """The product binding; on a GPU machine a missing library is an error, not a skip."""
+    """The product binding; on a machine with a GPU a missing library is an error, not a skip."""
     import paper_1507_08751_amd as msld
     msld.load()
     return msld
