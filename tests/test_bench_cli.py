@@ -25,3 +25,15 @@ def test_hardware_queue_count_is_range_checked():
         r = _run("--hw-queues", bad)
         assert r.returncode == 2
         assert "--hw-queues" in r.stderr
+
+
+def test_traffic_is_reported_only_for_the_profiled_stream_source(monkeypatch):
+    """bench.py reports the counter-measured HBM bytes of the stream pass only while the
+    stream pass's source still has the digest the committed summary was taken with; the
+    bytes are FETCH_SIZE and WRITE_SIZE scaled by the copy calibration."""
+    sys.path.insert(0, ROOT)
+    import bench
+    t = bench.measured_traffic()
+    assert t is not None and 1.0 < t / bench.STREAM_BYTES_PER_ELEM / 8192 ** 2 < 1.2
+    monkeypatch.setattr(bench, "stream_source_digest", lambda: "0000000000000000")
+    assert bench.measured_traffic() is None
